@@ -1,0 +1,261 @@
+"""Oracle for the Embedded IPC contact stage: TEST INFRASTRUCTURE ONLY.
+
+A plain FP64 CPU implementation (``eipc_oracle.c``) of what the contact
+stage computes, written from the paper's definitions, plus this ctypes
+wrapper.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark may use it; the product path never does.  It shares no code with
+the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+ENERGY, GRAD, HESS, PROJECT, MOLLIFY = 1, 2, 4, 8, 16
+OK, INACTIVE, ERR_CAPACITY, ERR_INTERSECTING, ERR_NONFINITE = 0, 1, -2, -3, -5
+PT_TYPES = ["P-T0", "P-T1", "P-T2", "P-E0", "P-E1", "P-E2", "P-T"]
+EE_TYPES = ["EA0-EB0", "EA0-EB1", "EA1-EB0", "EA1-EB1", "EA-EB0", "EA-EB1",
+            "EA0-EB", "EA1-EB", "EA-EB"]
+
+_P = C.c_void_p
+_D = C.c_double
+_I64 = C.c_int64
+_I32 = C.c_int32
+
+
+class OrScene(C.Structure):
+    _fields_ = [("n_vert", _I32), ("n_node", _I32), ("n_face", _I32), ("n_edge", _I32),
+                ("faces", _P), ("edges", _P), ("rowptr", _P), ("col", _P), ("val", _P),
+                ("x_off", _P), ("x_rest", _P)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        sig = {
+            "or_embed": (None, [_P, _P, _P, _P]),
+            "or_pt_query": (_I64, [_P, _P, _P, _D, _I32, _P, _I64]),
+            "or_ee_query": (_I64, [_P, _P, _P, _D, _I32, _P, _I64]),
+            "or_candidates": (C.c_int, [_P, _P, _P, _D, _P, _I64, _P, _P, _I64, _P]),
+            "or_pt_type": (C.c_int, [_P, _P, _P, _P]),
+            "or_ee_type": (C.c_int, [_P, _P, _P, _P]),
+            "or_pair_dist2": (_D, [C.c_int, C.c_int, _P]),
+            "or_pair_dist2_derivs": (None, [C.c_int, C.c_int, _P, _P, _P, _P]),
+            "or_barrier": (None, [_D, _D, _P, _P, _P]),
+            "or_mollifier": (None, [_D, _D, _P, _P, _P]),
+            "or_pair_eval": (C.c_int, [C.c_int, _P, _P, _D, _D, _P, _P, _P, _P, _P]),
+            "or_project_psd": (C.c_int, [C.c_int, _P, _P]),
+            "or_barrier_reduce": (C.c_int, [_P, _P, _P, _I64, _P, _I64, _D, _D, C.c_uint32,
+                                            _P, _P, _P, _P]),
+            "or_barrier_hvp": (C.c_int, [_P, _P, _P, _I64, _P, _I64, _D, _D, C.c_uint32,
+                                         _P, _P, _P, _P]),
+            "or_accd_pair": (_D, [C.c_int, _P, _P, _D, _D, _I64, _P]),
+            "or_ccd_toi": (C.c_int, [_P, _P, _P, C.c_int, _P, _I64, _D, _D, _I64, _P, _P]),
+            "or_ccd_max_step": (C.c_int, [_P, _P, _P, _P, _D, _D, _D, _I64, _P, _P, _P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+class _Sc:
+    """ctypes view of a scenes.Scene (keeps the arrays alive)."""
+
+    def __init__(self, sc):
+        self.keep = [_i32(sc.faces), _i32(sc.edges), _i32(sc.W_rowptr), _i32(sc.W_col),
+                     _f64(sc.W_val), _f64(sc.x_off), _f64(sc.x_rest)]
+        f, e, rp, col, val, xo, xr = self.keep
+        self.s = OrScene(sc.n_vert, sc.n_node, sc.n_face, sc.n_edge, _ptr(f), _ptr(e),
+                         _ptr(rp), _ptr(col), _ptr(val), _ptr(xo), _ptr(xr))
+        self.n_vert, self.n_node = sc.n_vert, sc.n_node
+        self.n_face, self.n_edge = sc.n_face, sc.n_edge
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def scene(sc) -> _Sc:
+    return sc if isinstance(sc, _Sc) else _Sc(sc)
+
+
+def embed(sc, q, off="scene"):
+    """x = W q + off (AoS [n_vert, 3]); off defaults to the scene's x_off."""
+    s = scene(sc)
+    q = _f64(q)
+    if isinstance(off, str):
+        off = s.keep[5]
+    off = _f64(off)
+    x = np.empty((s.n_vert, 3))
+    lib().or_embed(s.ref, _ptr(q), _ptr(off), _ptr(x))
+    return x
+
+
+def candidates(sc, x, dhat, x1=None):
+    s = scene(sc)
+    x = _f64(x)
+    x1 = _f64(x1)
+    npt, nee = _I64(), _I64()
+    lib().or_candidates(s.ref, _ptr(x), _ptr(x1), dhat, None, 0, C.byref(npt), None, 0, C.byref(nee))
+    pt = np.empty((max(npt.value, 1), 2), dtype=np.int32)
+    ee = np.empty((max(nee.value, 1), 2), dtype=np.int32)
+    st = lib().or_candidates(s.ref, _ptr(x), _ptr(x1), dhat, _ptr(pt), npt.value, C.byref(npt),
+                             _ptr(ee), nee.value, C.byref(nee))
+    assert st == OK
+    return pt[:npt.value].copy(), ee[:nee.value].copy()
+
+
+def pt_query(sc, x, dhat, v, x1=None):
+    s = scene(sc)
+    x, x1 = _f64(x), _f64(x1)
+    out = np.empty(max(s.n_face, 1), dtype=np.int32)
+    n = lib().or_pt_query(s.ref, _ptr(x), _ptr(x1), dhat, int(v), _ptr(out), len(out))
+    return out[:n].copy()
+
+
+def ee_query(sc, x, dhat, ea, x1=None):
+    s = scene(sc)
+    x, x1 = _f64(x), _f64(x1)
+    out = np.empty(max(s.n_edge, 1), dtype=np.int32)
+    n = lib().or_ee_query(s.ref, _ptr(x), _ptr(x1), dhat, int(ea), _ptr(out), len(out))
+    return out[:n].copy()
+
+
+def pt_type(p, t0, t1, t2) -> int:
+    a = [_f64(v) for v in (p, t0, t1, t2)]
+    return lib().or_pt_type(*[_ptr(v) for v in a])
+
+
+def ee_type(a0, a1, b0, b1) -> int:
+    a = [_f64(v) for v in (a0, a1, b0, b1)]
+    return lib().or_ee_type(*[_ptr(v) for v in a])
+
+
+def pair_dist2(kind: int, type_: int, x12) -> float:
+    x12 = _f64(x12).reshape(12)
+    return lib().or_pair_dist2(kind, type_, _ptr(x12))
+
+
+def pair_dist2_derivs(kind: int, type_: int, x12):
+    x12 = _f64(x12).reshape(12)
+    s = np.zeros(1)
+    g = np.zeros(12)
+    H = np.zeros((12, 12))
+    lib().or_pair_dist2_derivs(kind, type_, _ptr(x12), _ptr(s), _ptr(g), _ptr(H))
+    return s[0], g, H
+
+
+def barrier(d, dhat):
+    out = np.zeros(3)
+    lib().or_barrier(d, dhat, _ptr(out[0:]), _ptr(out[1:]), _ptr(out[2:]))
+    return out[0], out[1], out[2]
+
+
+def mollifier(c, eps):
+    out = np.zeros(3)
+    lib().or_mollifier(c, eps, _ptr(out[0:]), _ptr(out[1:]), _ptr(out[2:]))
+    return out[0], out[1], out[2]
+
+
+def pair_eval(kind, x12, dhat, kappa, rest12=None):
+    """Returns (status, type, s, e, g[12], H[12,12]) with the true Hessian."""
+    x12 = _f64(x12).reshape(12)
+    r12 = None if rest12 is None else _f64(rest12).reshape(12)
+    t = C.c_int()
+    s = np.zeros(1)
+    e = np.zeros(1)
+    g = np.zeros(12)
+    H = np.zeros((12, 12))
+    st = lib().or_pair_eval(kind, _ptr(x12), _ptr(r12), dhat, kappa, C.byref(t), _ptr(s),
+                            _ptr(e), _ptr(g), _ptr(H))
+    return st, t.value, s[0], e[0], g, H
+
+
+def project_psd(A):
+    A = _f64(A)
+    n = A.shape[0]
+    P = np.zeros((n, n))
+    sweeps = lib().or_project_psd(n, _ptr(A), _ptr(P))
+    return P, sweeps
+
+
+def barrier_reduce(sc, q, pt, ee, dhat, kappa, flags, hess=True):
+    """Returns dict(status, energy, grad, hess (dense or None), n_active)."""
+    s = scene(sc)
+    q = _f64(q)
+    pt = _i32(pt).reshape(-1, 2) if pt is not None else np.zeros((0, 2), np.int32)
+    ee = _i32(ee).reshape(-1, 2) if ee is not None else np.zeros((0, 2), np.int32)
+    nd = 3 * s.n_node
+    e = np.zeros(1)
+    g = np.zeros(nd)
+    H = np.zeros((nd, nd)) if hess else None
+    na = _I64()
+    st = lib().or_barrier_reduce(s.ref, _ptr(q), _ptr(pt), len(pt), _ptr(ee), len(ee), dhat, kappa,
+                                 int(flags), _ptr(e), _ptr(g), _ptr(H), C.byref(na))
+    return {"status": st, "energy": e[0], "grad": g, "hess": H, "n_active": na.value}
+
+
+def barrier_hvp(sc, q, pt, ee, dhat, kappa, flags, v, v_off=None, want_off=False):
+    s = scene(sc)
+    q, v, v_off = _f64(q), _f64(v), _f64(v_off)
+    pt = _i32(pt).reshape(-1, 2)
+    ee = _i32(ee).reshape(-1, 2)
+    out = np.zeros(3 * s.n_node)
+    out_off = np.zeros((s.n_vert, 3)) if want_off else None
+    st = lib().or_barrier_hvp(s.ref, _ptr(q), _ptr(pt), len(pt), _ptr(ee), len(ee), dhat, kappa,
+                              int(flags), _ptr(v), _ptr(v_off), _ptr(out), _ptr(out_off))
+    return st, out, out_off
+
+
+def accd_pair(kind, x12, p12, s=0.1, t_c=1.0, max_iter=100000):
+    x12 = _f64(x12).reshape(12)
+    p12 = _f64(p12).reshape(12)
+    it = _I64()
+    t = lib().or_accd_pair(kind, _ptr(x12), _ptr(p12), s, t_c, max_iter, C.byref(it))
+    return t, it.value
+
+
+def ccd_toi(sc, x, p, kind, pairs, s=0.1, t_c=1.0, max_iter=100000):
+    sc_ = scene(sc)
+    x, p = _f64(x), _f64(p)
+    pairs = _i32(pairs).reshape(-1, 2)
+    t = np.zeros(len(pairs))
+    it = np.zeros(len(pairs), dtype=np.int64)
+    lib().or_ccd_toi(sc_.ref, _ptr(x), _ptr(p), kind, _ptr(pairs), len(pairs), s, t_c, max_iter,
+                     _ptr(t), _ptr(it))
+    return t, it
+
+
+def ccd_max_step(sc, q, dq, dhat, dx_off=None, s=0.1, t_max=1.0, max_iter=100000):
+    sc_ = scene(sc)
+    q, dq, dx_off = _f64(q), _f64(dq), _f64(dx_off)
+    a = np.zeros(1)
+    nc, ncap = _I64(), _I64()
+    lib().or_ccd_max_step(sc_.ref, _ptr(q), _ptr(dq), _ptr(dx_off), dhat, s, t_max, max_iter,
+                          _ptr(a), C.byref(nc), C.byref(ncap))
+    return a[0], nc.value, ncap.value

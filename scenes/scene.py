@@ -1,0 +1,492 @@
+"""Scene container and the seeded scene recipes.
+
+Recipes (sizes and value distributions follow the paper's experiments and
+the workloads the contact stage is measured on):
+
+* ``config1``: icosphere of frequency 16 (2,562 v / 5,120 f, r = 0.05 m)
+  embedded in a 5x5x5-node Kuhn-split grid, on a static 2-triangle ground.
+* ``config2``: soft-bubble grasp: a spherical-harmonic blob (frequency 71,
+  100,820 f) between two conformed ellipsoidal membranes (frequency 32,
+  20,480 f each).
+* ``config3``: thin disc plate (about 60k f) over a static rack of 40
+  cylinders (4,992 f each), near-parallel edges.
+* ``tiny_scene``: two small convex bodies separated by a plane, for exact
+  comparisons on inputs small enough for brute force.
+* ``batch_scenes``: many grasp scenes of uneven size.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from .meshes import (CoarseGrid, assemble_csr, cylinder_mesh, disc_plate_mesh,
+                     geodesic_sphere, near_cubic_dims, padded_grid, unique_edges)
+
+
+def rng_for(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([int(seed), int(stream)]))
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    n_node: int
+    faces: np.ndarray            # int32 [n_face, 3]
+    edges: np.ndarray            # int32 [n_edge, 2], a < b, sorted
+    W_rowptr: np.ndarray         # int32 [n_vert + 1]
+    W_col: np.ndarray            # int32 [nnz]
+    W_val: np.ndarray            # f64 [nnz]
+    x_off: np.ndarray | None     # f64 [n_vert, 3] or None
+    x_rest: np.ndarray | None    # f64 [n_vert, 3] or None
+    q: np.ndarray                # f64 [3 n_node]
+    dq: np.ndarray               # f64 [3 n_node]
+    dx_off: np.ndarray | None    # f64 [n_vert, 3] or None
+    dhat: float
+    kappa: float
+    seed: int = 0
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n_vert(self) -> int:
+        return len(self.W_rowptr) - 1
+
+    @property
+    def n_face(self) -> int:
+        return len(self.faces)
+
+    @property
+    def n_edge(self) -> int:
+        return len(self.edges)
+
+    def summary(self) -> str:
+        return (f"{self.name}: n_vert={self.n_vert} n_face={self.n_face} "
+                f"n_edge={self.n_edge} n_node={self.n_node} nnz={len(self.W_col)} "
+                f"dhat={self.dhat:g} kappa={self.kappa:g} seed={self.seed}")
+
+
+def _wq(rowptr, col, val, q):
+    """Plain W q used only to place bodies while generating inputs."""
+    q3 = q.reshape(-1, 3)
+    n = len(rowptr) - 1
+    x = np.zeros((n, 3))
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    np.add.at(x, rows, val[:, None] * q3[col])
+    return x
+
+
+@dataclasses.dataclass
+class Body:
+    verts: np.ndarray            # rest positions [n, 3]
+    faces: np.ndarray            # local indices [m, 3]
+    grid: CoarseGrid | None      # None: static / kinematic (empty W rows)
+    full_space: bool = False     # W = I rows (one node per vertex)
+
+
+def _assemble(bodies: list[Body]):
+    """Concatenate bodies into one scene: vertex, face and node numbering in
+    body order.  Returns faces, edges, W pieces, q0, x_off, x_rest."""
+    v_off = 0
+    n_off = 0
+    faces = []
+    entries = []
+    q_parts = []
+    x_off_parts = []
+    any_static = False
+    for b in bodies:
+        n = len(b.verts)
+        faces.append(b.faces.astype(np.int64) + v_off)
+        rows = np.arange(v_off, v_off + n)
+        if b.full_space:
+            entries.append((rows, (np.arange(n) + n_off)[:, None], np.ones((n, 1))))
+            q_parts.append(b.verts.reshape(-1))
+            n_off += n
+            x_off_parts.append(np.zeros((n, 3)))
+        elif b.grid is not None:
+            tn, w = b.grid.embed(b.verts)
+            entries.append((rows, tn.astype(np.int64) + n_off, w))
+            q_parts.append(b.grid.nodes.reshape(-1))
+            n_off += b.grid.n_node
+            x_off_parts.append(np.zeros((n, 3)))
+        else:
+            any_static = True
+            x_off_parts.append(b.verts.copy())
+        v_off += n
+    n_vert = v_off
+    faces = np.concatenate(faces).astype(np.int32)
+    edges = unique_edges(faces)
+    rowptr, col, val = assemble_csr(n_vert, entries)
+    q0 = np.concatenate(q_parts) if q_parts else np.zeros(0)
+    x_off = np.concatenate(x_off_parts) if any_static else None
+    x_rest = np.concatenate([b.verts for b in bodies])
+    return faces, edges, rowptr, col, val, q0, n_off, x_off, x_rest
+
+
+def _make(name, bodies, q, dq, dhat, kappa, seed, dx_off=None, meta=None,
+          assembled=None):
+    faces, edges, rowptr, col, val, q0, n_node, x_off, x_rest = assembled or _assemble(bodies)
+    return Scene(name=name, n_node=n_node, faces=faces, edges=edges,
+                 W_rowptr=rowptr, W_col=col, W_val=val, x_off=x_off,
+                 x_rest=x_rest, q=np.ascontiguousarray(q, dtype=np.float64),
+                 dq=np.ascontiguousarray(dq, dtype=np.float64), dx_off=dx_off,
+                 dhat=float(dhat), kappa=float(kappa), seed=seed, meta=meta or {})
+
+
+# ---------------------------------------------------------------------------
+# Config 1: icosphere on a ground plane
+# ---------------------------------------------------------------------------
+
+def config1(seed: int = 0, literal: bool = False, grid_dims=(5, 5, 5),
+            noise: float = 1e-4) -> Scene:
+    """Icosphere (frequency 16, r = 0.05 m) in a padded 5x5x5 Kuhn grid over
+    a static ground made of 2 triangles spanning [-0.2, 0.2]^2 at z = 0.
+
+    The bottom node layer is moved toward the next layer by sigma = 0.077
+    (an exact vertical compression of the bottom cell layer) so that about
+    300 vertices end within dhat of the ground; ``literal=True`` skips it.
+    q gets N(0, noise) per coordinate, then the body is shifted in z so the
+    lowest vertex sits at 1e-4 m.  dq ~ N(0, 5e-3 m) from a second stream.
+    dhat = 1e-3 m, kappa = 1e3."""
+    r = 0.05
+    v_unit, f = geodesic_sphere(16)
+    v = r * v_unit
+    grid = padded_grid(v, grid_dims)
+    ground_v = np.array([[-0.2, -0.2, 0.0], [0.2, -0.2, 0.0],
+                         [0.2, 0.2, 0.0], [-0.2, 0.2, 0.0]])
+    ground_f = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    bodies = [Body(v, f, grid), Body(ground_v, ground_f, None)]
+    asm = _assemble(bodies)
+    faces, edges, rowptr, col, val, q0, n_node, x_off, x_rest = asm
+    q = q0.reshape(-1, 3).copy()
+    nz = grid.dims[2]
+    k = np.arange(grid.n_node) % nz
+    if not literal:
+        z0 = q[k == 0, 2]
+        z1 = q[k == 1, 2]
+        q[k == 0, 2] = z1 + 0.077 * (z0 - z1)
+    rng = rng_for(seed, 0)
+    q += rng.normal(0.0, noise, q.shape)
+    x = _wq(rowptr, col, val, q.reshape(-1))
+    zmin = x[:len(v), 2].min()
+    q[:, 2] += 1e-4 - zmin
+    dq = rng_for(seed, 1).normal(0.0, 5e-3, q.size)
+    return _make("config1" + ("_literal" if literal else ""), bodies, q.reshape(-1), dq,
+                 1e-3, 1e3, seed, assembled=asm,
+                 meta={"grid_dims": grid_dims, "squash": not literal})
+
+
+# ---------------------------------------------------------------------------
+# Tiny two-body scenes (brute-force sized)
+# ---------------------------------------------------------------------------
+
+def _random_rotation(rng: np.random.Generator) -> np.ndarray:
+    qv = rng.normal(size=4)
+    qv /= np.linalg.norm(qv)
+    w, x, y, z = qv
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+class SingleTet:
+    """One tetrahedron enclosing a point set (the paper's affine-body special
+    case): a regular tetrahedron around the points' bounding sphere."""
+
+    def __init__(self, points: np.ndarray, margin: float = 1.5):
+        c = points.mean(axis=0)
+        r = np.linalg.norm(points - c, axis=1).max() * margin
+        # regular tetrahedron with insphere radius r: vertices at distance 3r
+        d = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        self.nodes = c + 3.0 * r * d
+        self.tets = np.array([[0, 1, 2, 3]], dtype=np.int32)
+
+    @property
+    def n_node(self) -> int:
+        return 4
+
+    def embed(self, x: np.ndarray):
+        p0 = self.nodes[0]
+        D = np.stack([self.nodes[1] - p0, self.nodes[2] - p0, self.nodes[3] - p0], axis=1)
+        lam = np.linalg.solve(D, (x - p0).T).T
+        w = np.concatenate([1.0 - lam.sum(axis=1, keepdims=True), lam], axis=1)
+        if w.min() < -1e-12:
+            raise ValueError("point outside the enclosing tetrahedron")
+        return np.repeat(self.tets, len(x), axis=0), w
+
+
+def tiny_scene(seed: int, dhat: float | None = None, mode: str = "grid") -> Scene:
+    """Two small convex bodies (geodesic spheres of frequency 1-3 with random
+    anisotropic scale and rotation) on opposite sides of a random plane,
+    separated by a gap g (so they cannot intersect), with dhat = g U(2, 12).
+
+    ``mode``: 'grid' (both embedded in small Kuhn grids), 'static' (body B
+    static), 'full' (body B full-space, W = I rows), 'full_both' (both
+    full-space: the paper's full-space IPC special case), 'tet' (body A in
+    one enclosing tetrahedron: the affine-body special case; B static)."""
+    rng = rng_for(seed, 0)
+    bodies = []
+    nrm = rng.normal(size=3)
+    nrm /= np.linalg.norm(nrm)
+    gap = 10 ** rng.uniform(-4.0, -3.0)
+    for side in (-1.0, 1.0):
+        nu = int(rng.integers(1, 4))
+        v, f = geodesic_sphere(nu)
+        v = v * (0.01 * rng.uniform(0.6, 1.6, size=3))
+        v = v @ _random_rotation(rng).T
+        # put the body on its side of the plane n.x = 0 at distance gap/2
+        h = v @ nrm
+        if side < 0:
+            v = v - nrm * (h.max() + gap / 2)
+        else:
+            v = v - nrm * (h.min() - gap / 2)
+        bodies.append((v, f))
+    # slide B along the plane so its extreme vertex faces A's extreme vertex:
+    # the closest distance is then exactly the gap
+    va, vb = bodies[0][0], bodies[1][0]
+    pa = va[np.argmax(va @ nrm)]
+    pb = vb[np.argmin(vb @ nrm)]
+    t = pa - pb
+    t = t - nrm * (t @ nrm)
+    bodies[1] = (vb + t, bodies[1][1])
+    dhat_v = float(dhat) if dhat is not None else gap * rng.uniform(2.0, 12.0)
+    blist = []
+    for i, (v, f) in enumerate(bodies):
+        if mode == "full_both" or (i == 1 and mode == "full"):
+            blist.append(Body(v, f, None, full_space=True))
+        elif i == 1 and mode in ("static", "tet"):
+            blist.append(Body(v, f, None))
+        elif i == 0 and mode == "tet":
+            blist.append(Body(v, f, SingleTet(v)))
+        else:
+            dims = tuple(int(d) for d in rng.integers(2, 4, size=3))
+            blist.append(Body(v, f, padded_grid(v, dims)))
+    asm = _assemble(blist)
+    q0 = asm[5]
+    # small perturbation of the nodes, far below the gap
+    q = q0 + rng.normal(0.0, gap * 0.02, q0.shape)
+    dq = rng_for(seed, 1).normal(0.0, 5e-3, q0.shape)
+    return _make(f"tiny{seed}_{mode}", blist, q, dq, dhat_v, 1e3, seed, assembled=asm,
+                 meta={"gap": gap, "normal": nrm.tolist(), "mode": mode,
+                       "n_vert_a": len(bodies[0][0])})
+
+
+def full_space_scene(seed: int = 0) -> Scene:
+    """The paper's full-space special case: every vertex is its own node."""
+    return tiny_scene(seed, mode="full_both")
+
+
+def single_tet_scene(seed: int = 0) -> Scene:
+    """The paper's affine-body special case: body A in one tetrahedron."""
+    return tiny_scene(seed, mode="tet")
+
+
+# ---------------------------------------------------------------------------
+# Config 3: plate over a rack of cylinders
+# ---------------------------------------------------------------------------
+
+def config3(seed: int = 0, n_cyl: int = 40, spacing: float = 1.75e-3) -> Scene:
+    """Disc plate (R = 0.12 m, 4 mm thick, about 60k triangles) in a
+    ~300-node grid, face down over 40 static cylinders (r = 3 mm, L = 0.15 m,
+    32 x 77 facets + fan caps = 4,992 triangles each) whose axes run along x
+    with an 8 mm pitch in y and whose tops are at z = 0.  Seeded pose: yaw
+    U(-1, 1) degrees, tilt giving a height change across the plate of
+    U(0, 2 mm), lowest point at a gap dhat U(0.1, 0.9) above z = 0.
+    dhat = 2e-4 m, kappa = 1e3."""
+    rng = rng_for(seed, 0)
+    dhat = 2e-4
+    pv, pf = disc_plate_mesh(0.12, 4e-3, spacing)
+    yaw = math.radians(rng.uniform(-1.0, 1.0))
+    drop = rng.uniform(0.0, 2e-3)
+    tilt = math.atan2(drop, 0.24)
+    tdir = rng.uniform(0, 2 * math.pi)
+    ax = np.array([math.cos(tdir), math.sin(tdir), 0.0])
+    # Rodrigues rotation about a horizontal axis, then yaw about z
+    K = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    Rt = np.eye(3) + math.sin(tilt) * K + (1 - math.cos(tilt)) * K @ K
+    Rz = np.array([[math.cos(yaw), -math.sin(yaw), 0], [math.sin(yaw), math.cos(yaw), 0], [0, 0, 1]])
+    pv = pv @ (Rz @ Rt).T
+    gap = dhat * rng.uniform(0.1, 0.9)
+    pv[:, 2] += gap - pv[:, 2].min()
+    grid = padded_grid(pv, near_cubic_dims(pv.max(0) - pv.min(0), 300))
+    bodies = [Body(pv, pf, grid)]
+    cv, cf = cylinder_mesh(3e-3, 0.15, 32, 77)
+    for i in range(n_cyl):
+        y = (i - (n_cyl - 1) / 2.0) * 8e-3
+        v = cv + np.array([-0.075, y, -3e-3])
+        bodies.append(Body(v, cf, None))
+    asm = _assemble(bodies)
+    q0 = asm[5]
+    dq = rng_for(seed, 1).normal(0.0, 2e-4, q0.shape)
+    return _make("config3", bodies, q0.copy(), dq, dhat, 1e3, seed, assembled=asm,
+                 meta={"yaw_deg": math.degrees(yaw), "drop": drop, "gap": gap,
+                       "grid_dims": grid.dims})
+
+
+# ---------------------------------------------------------------------------
+# Config 2 / batch: conformed bubble grasp
+# ---------------------------------------------------------------------------
+
+def _real_sh_basis(lmax: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    """Real spherical harmonics up to lmax (l >= 1) at polar angle theta and
+    azimuth phi, one column per (l, m)."""
+    from scipy.special import sph_harm_y
+    cols = []
+    for l in range(1, lmax + 1):
+        for m in range(-l, l + 1):
+            y = sph_harm_y(l, abs(m), theta, phi)
+            if m < 0:
+                cols.append(math.sqrt(2) * (-1) ** m * y.imag)
+            elif m == 0:
+                cols.append(y.real)
+            else:
+                cols.append(math.sqrt(2) * (-1) ** m * y.real)
+    return np.stack(cols, axis=1)
+
+
+class Blob:
+    """Star-shaped body r(dir) = R0 (1 + sum a_lm Y_lm(dir)), perturbation
+    rescaled to a maximum magnitude ``amp`` over a dense direction sample."""
+
+    def __init__(self, rng, r0=0.04, lmax=8, amp=0.10):
+        self.r0 = r0
+        self.lmax = lmax
+        n = sum(2 * l + 1 for l in range(1, lmax + 1))
+        self.a = rng.normal(size=n)
+        d, _ = geodesic_sphere(24)
+        p = self._pert(d)
+        self.a *= amp / np.abs(p).max()
+
+    def _pert(self, d):
+        th = np.arccos(np.clip(d[:, 2], -1, 1))
+        ph = np.arctan2(d[:, 1], d[:, 0])
+        return _real_sh_basis(self.lmax, th, ph) @ self.a
+
+    def radius(self, d):
+        return self.r0 * (1.0 + self._pert(d))
+
+    def first_hit(self, origin: np.ndarray, direction: np.ndarray, t_hi: float):
+        """Smallest t in [0, t_hi] where origin + t dir enters the body
+        (bisection on a coarse march), or nan if the ray misses."""
+        n = len(origin)
+        ts = np.linspace(0.0, t_hi, 400)
+        hit = np.full(n, np.nan)
+        prev_in = np.zeros(n, dtype=bool)
+        prev_t = np.zeros(n)
+        for t in ts:
+            p = origin + t * direction
+            r = np.linalg.norm(p, axis=1)
+            inside = r < self.radius(p / np.maximum(r, 1e-300)[:, None])
+            new = inside & ~prev_in & np.isnan(hit)
+            if new.any():
+                lo = prev_t[new].copy()
+                hi = np.full(new.sum(), t)
+                o = origin[new]
+                for _ in range(60):
+                    mid = 0.5 * (lo + hi)
+                    pm = o + mid[:, None] * direction
+                    rm = np.linalg.norm(pm, axis=1)
+                    ins = rm < self.radius(pm / rm[:, None])
+                    hi = np.where(ins, mid, hi)
+                    lo = np.where(ins, lo, mid)
+                hit[new] = lo
+            prev_in = inside
+            prev_t[:] = t
+        return hit
+
+
+def _conformed_finger(blob: Blob, obj_v: np.ndarray, nu: int, semi, side: float,
+                      frac: float, dhat: float, rng) -> np.ndarray:
+    """Ellipsoidal membrane (semi-axes semi = (a_x, a_y, a_z), x the grasp
+    axis) on the ``side`` (-1 or +1) of the object along x.  Vertices on the
+    object-facing half whose (y, z) lie within ``frac`` of the semi-axes are
+    pressed onto the object: moved along x to the object's first-hit surface
+    minus a gap dhat U(0.1, 0.9).  Returns the conformed vertex positions."""
+    v_unit, _ = geodesic_sphere(nu)
+    v = v_unit * np.asarray(semi)
+    facing = (v[:, 0] * -side) > 0  # half pointing at the object
+    ell = (v[:, 1] / semi[1]) ** 2 + (v[:, 2] / semi[2]) ** 2
+    sel = facing & (ell < frac ** 2)
+    # place the finger so its facing apex touches the object's extreme
+    ext = obj_v[:, 0].max() if side > 0 else -obj_v[:, 0].min()
+    v[:, 0] += side * (ext + semi[0])
+    # pressed region: cast rays from the finger toward the object
+    o = v[sel].copy()
+    o[:, 0] = side * (ext + 0.02)
+    direction = np.array([-side, 0.0, 0.0])
+    t = blob.first_hit(o, direction, ext + 0.02)
+    ok = ~np.isnan(t)
+    gap = dhat * rng.uniform(0.1, 0.9, size=ok.sum())
+    surf_x = o[ok, 0] - side * t[ok]
+    idx = np.nonzero(sel)[0][ok]
+    v[idx, 0] = surf_x + side * gap
+    # smooth the transition: vertices on the facing half but outside the
+    # pressed set must stay outside; push any that crossed back out
+    rest = np.nonzero(facing & ~np.isin(np.arange(len(v)), idx))[0]
+    if len(rest):
+        o2 = v[rest].copy()
+        o2[:, 0] = side * (ext + 0.02)
+        t2 = blob.first_hit(o2, direction, ext + 0.02)
+        hit = ~np.isnan(t2)
+        lim = o2[hit, 0] - side * t2[hit] + side * dhat * 2.0
+        cur = v[rest[hit], 0]
+        bad = (cur - lim) * side < 0
+        v[rest[hit][bad], 0] = lim[bad]
+    return v
+
+
+def grasp_scene(seed: int, obj_nu: int, obj_nodes: int, finger_nu: int,
+                finger_semi=(0.015, 0.04, 0.06), finger_dims=(5, 10, 10),
+                frac: float = 0.8, dhat: float = 5e-4, kappa: float = 1e3,
+                rotate: bool = False, dq_sigma: float = 1e-3, name="grasp",
+                r0: float = 0.04) -> Scene:
+    rng = rng_for(seed, 0)
+    blob = Blob(rng, r0=r0)
+    v_unit, of = geodesic_sphere(obj_nu)
+    ov = v_unit * blob.radius(v_unit)[:, None]
+    f1 = _conformed_finger(blob, ov, finger_nu, finger_semi, -1.0, frac, dhat, rng)
+    f2 = _conformed_finger(blob, ov, finger_nu, finger_semi, +1.0, frac, dhat, rng)
+    _, ff = geodesic_sphere(finger_nu)
+    if rotate:
+        R = _random_rotation(rng)
+        ov, f1, f2 = ov @ R.T, f1 @ R.T, f2 @ R.T
+    og = padded_grid(ov, near_cubic_dims(ov.max(0) - ov.min(0), obj_nodes))
+    g1 = padded_grid(f1, finger_dims)
+    g2 = padded_grid(f2, finger_dims)
+    bodies = [Body(ov, of, og), Body(f1, ff, g1), Body(f2, ff, g2)]
+    asm = _assemble(bodies)
+    q0 = asm[5]
+    dq = rng_for(seed, 1).normal(0.0, dq_sigma, q0.shape)
+    return _make(name, bodies, q0.copy(), dq, dhat, kappa, seed, assembled=asm,
+                 meta={"obj_nu": obj_nu, "finger_nu": finger_nu, "frac": frac,
+                       "obj_grid": og.dims, "finger_grid": finger_dims})
+
+
+def config2(seed: int = 0, frac: float = 0.8) -> Scene:
+    """Bubble-gripper grasp: blob of frequency 71 (100,820 f, r0 = 0.04 m,
+    SH order 8, 10 % amplitude) in a ~2,000-node grid, two ellipsoidal
+    membranes (semi-axes 0.015 x 0.04 x 0.06 m, x the grasp axis, frequency
+    32, 20,480 f each) in 5x10x10-node grids, pressed onto the object over
+    ``frac`` of their semi-axes with gaps dhat U(0.1, 0.9).  dhat = 5e-4 m,
+    kappa = 1e3, dq ~ N(0, 1e-3 m)."""
+    return grasp_scene(seed, 71, 2000, 32, frac=frac, name="config2")
+
+
+def batch_scenes(n: int = 256, seed0: int = 0) -> list[Scene]:
+    """Ragged grasp batch: object triangle count log-uniform in [2e3, 5e4]
+    (frequency round(sqrt(F / 20))), object nodes log-uniform in
+    [100, 2000], fingers of frequency 16, random SE(3) orientation, pressed
+    fraction log-uniform in [0.1, 0.8] so contact counts spread over orders
+    of magnitude."""
+    out = []
+    for i in range(n):
+        rng = rng_for(seed0 + i, 7)
+        F = math.exp(rng.uniform(math.log(2e3), math.log(5e4)))
+        nu = max(2, int(round(math.sqrt(F / 20.0))))
+        nodes = int(round(math.exp(rng.uniform(math.log(100), math.log(2000)))))
+        frac = math.exp(rng.uniform(math.log(0.1), math.log(0.8)))
+        out.append(grasp_scene(seed0 + i, nu, nodes, 16, frac=frac, rotate=True,
+                               name=f"batch{seed0 + i}"))
+    return out
