@@ -1,0 +1,205 @@
+/* eipc.h -- C ABI of the MI355X (gfx950) contact-stage library for
+ * Embedded IPC (arXiv 2409.16385).
+ *
+ * The library computes, for one Newton iteration, the contact terms of the
+ * embedded IPC objective on a high-resolution surface whose vertices are
+ * interpolated from coarse nodes, x = W q + x_off (Sec. III-D, Eq. 13-14):
+ * candidate point-triangle (PT) and edge-edge (EE) pairs, the log-barrier
+ * energy kappa * sum b(d_k) (Sec. III-B, Eq. 7, 10-11), its gradient and
+ * PSD-projected Hessian reduced through the embedding (Eq. 17), Hessian-
+ * vector products, and a conservative continuous-collision step bound that
+ * clamps the line search (Sec. III-C).
+ *
+ * Conventions (every entry point):
+ *  - Array arguments are DEVICE pointers on the context's GPU, caller
+ *    owned, contiguous, unless a comment says "host".  The library never
+ *    frees or retains caller memory past a call.
+ *  - FP64 for all real data, int32 indices, int64 sizes.
+ *  - q and every reduced vector are double[3*n_node], node-major xyz.
+ *    Positions are double[3*n_vert] AoS.
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
+ *    Calls that return a count or a scalar to a host pointer synchronize
+ *    that stream before returning.
+ *  - Argument errors are returned synchronously and nothing is enqueued.
+ *    Data-dependent errors (an intersecting pair, a non-finite value) are
+ *    raised by the kernels into a device status word; calls that
+ *    synchronize return it, eipc_sync_status() reads it otherwise.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef EIPC_H
+#define EIPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t eipc_status;
+enum {
+  EIPC_OK = 0,
+  EIPC_ERR_ARG = -1,          /* invalid argument (nothing enqueued) */
+  EIPC_ERR_CAPACITY = -2,     /* an output buffer is too small; the required size is returned */
+  EIPC_ERR_INTERSECTING = -3, /* a candidate pair has distance 0: the input is not intersection-free */
+  EIPC_ERR_DEGENERATE = -4,   /* reserved */
+  EIPC_ERR_NONFINITE = -5,    /* NaN or Inf in positions or pair quantities */
+  EIPC_ERR_HIP = -6,          /* a HIP runtime call failed; see eipc_last_error */
+  EIPC_WARN_CCD_CAPPED = 1    /* CCD hit its per-pair iteration cap (the bound is still safe) */
+};
+
+/* flags for eipc_barrier_reduce / eipc_barrier_hvp */
+enum {
+  EIPC_ENERGY = 1,  /* total barrier energy */
+  EIPC_GRAD = 2,    /* reduced gradient W^T g */
+  EIPC_HESS = 4,    /* reduced Hessian W^T H W */
+  EIPC_PROJECT = 8, /* use the per-pair PSD projection of H (projected Newton, Sec. III-C) */
+  EIPC_MOLLIFY = 16 /* EE mollifier for near-parallel edges (needs x_rest) */
+};
+
+typedef struct eipc_ctx eipc_ctx;
+typedef void *eipc_stream; /* hipStream_t */
+
+/* One scene: a collision surface M_col = (X, S) and its embedding
+ * (Sec. III-D).  Row k of W holds the barycentric weights of surface
+ * vertex k in its coarse tetrahedron (Eq. 13); an empty row marks a vertex
+ * with no DoF (static, or kinematic: prescribed through x_off, as in the
+ * position-controlled grippers of Sec. IV-A).  A row with a single weight
+ * 1 is a full-space vertex (W = I is full-space IPC, Sec. III-D). */
+typedef struct {
+  int32_t n_vert, n_node, n_face, n_edge;
+  const int32_t *faces;    /* [n_face*3] vertex indices */
+  const int32_t *edges;    /* [n_edge*2] unique undirected edges, a < b */
+  const int32_t *W_rowptr; /* [n_vert+1] CSR row pointers */
+  const int32_t *W_col;    /* [nnz] node index in [0, n_node) */
+  const double *W_val;     /* [nnz] weights */
+  const double *x_off;     /* [n_vert*3] added to W q (static / kinematic positions), or NULL */
+  const double *x_rest;    /* [n_vert*3] rest positions for the EE mollifier, or NULL */
+} eipc_scene;
+
+/* Reduced Hessian in 3x3 block-sparse rows (both triangles stored, columns
+ * sorted).  All pointers are device memory owned by the context, valid
+ * until the next call on that context. */
+typedef struct {
+  int32_t n_rows;         /* = n_node */
+  int64_t nnzb;           /* number of stored 3x3 blocks */
+  const int32_t *rowptr;  /* [n_rows+1] */
+  const int32_t *col;     /* [nnzb] */
+  const double *blocks;   /* [nnzb*9] row-major 3x3 */
+} eipc_bsr;
+
+/* Context on GPU `device`.  Owns scratch memory (grown on demand, kept
+ * until eipc_destroy) and the device status word. */
+eipc_status eipc_create(eipc_ctx **ctx, int32_t device);
+void eipc_destroy(eipc_ctx *ctx);
+const char *eipc_last_error(const eipc_ctx *ctx);
+const char *eipc_status_string(eipc_status s);
+/* Synchronizes `stream`, returns and clears the device status word. */
+eipc_status eipc_sync_status(eipc_ctx *ctx, eipc_stream stream);
+
+/* Embedding map x = W q + off (Eq. 14), written AoS to x[n_vert*3].
+ * Each coordinate is accumulated in CSR order from 0.0 (one rounded
+ * multiply and one rounded add per term) and off is added last, so x is
+ * reproducible bit for bit.  off may be NULL. */
+eipc_status eipc_embed(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const double *off, double *x,
+                       eipc_stream stream);
+
+/* Candidate pairs of the pair set B (Sec. III-B) at positions W q + x_off:
+ * PT pairs (vertex v, face f) with v not in f and EE pairs (edge a, edge b)
+ * with a < b and no shared vertex, whose boxes overlap.  The box of a
+ * primitive spans its vertices, widened by dhat/2 on every side (closed
+ * intervals).  Pairs whose four vertices all have empty W rows are
+ * excluded.  Outputs pt[2*k] = v, pt[2*k+1] = f and ee[2*k] = a,
+ * ee[2*k+1] = b, sorted by (first, second).
+ * *n_pt, *n_ee (host) always receive the required counts; if either
+ * exceeds cap_pt / cap_ee the call returns EIPC_ERR_CAPACITY and the
+ * lists are not written.  Synchronizes. */
+eipc_status eipc_build_candidates(eipc_ctx *ctx, const eipc_scene *sc, const double *q, double dhat, int32_t *pt,
+                                  int64_t cap_pt, int32_t *ee, int64_t cap_ee, int64_t *n_pt, int64_t *n_ee,
+                                  eipc_stream stream);
+
+/* Barrier terms over the given pairs (Sec. III-B, Eq. 7, 10-11; reduction
+ * Eq. 17).  A pair is active when 0 < d < dhat with d the Euclidean
+ * distance between the closed primitives; its energy is kappa * b(d)
+ * (times the mollifier m(|ea x eb|^2) for EE pairs with EIPC_MOLLIFY).
+ * Pass kappa * h^2 to obtain the h^2-scaled barrier term of E_IPC.
+ *   energy    device double[1] or NULL: total energy (overwritten)
+ *   grad_q    device double[3*n_node] or NULL: W^T g (overwritten)
+ *   hess_dense device double[(3*n_node)^2] or NULL: W^T H W, row-major
+ *   hess_bsr  host struct or NULL: filled with a context-owned BSR view
+ * H is the per-pair PSD projection when EIPC_PROJECT is set, else the true
+ * pair Hessian.  n_active (host) or NULL receives the number of active
+ * pairs.  Synchronizes when n_active or hess_bsr is requested.
+ * An active pair with d == 0 raises EIPC_ERR_INTERSECTING. */
+eipc_status eipc_barrier_reduce(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
+                                int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
+                                uint32_t flags, double *energy, double *grad_q, double *hess_dense,
+                                eipc_bsr *hess_bsr, int64_t *n_active, eipc_stream stream);
+
+/* Conservative step bound for the line search (Sec. III-C): the largest
+ * alpha <= t_max such that moving x by alpha * p, p = W dq + dx_off, is
+ * guaranteed free of new intersections, computed per swept candidate pair
+ * by additive conservative advancement with gap factor s (0 < s < 1) and
+ * the minimum taken over all pairs whose swept boxes (start and end
+ * positions, widened by dhat/2) overlap.  dx_off may be NULL.
+ * alpha (host), n_cand (host, or NULL) receives the number of swept
+ * candidates.  Returns EIPC_WARN_CCD_CAPPED if some pair reached max_iter
+ * iterations (alpha is still safe).  Synchronizes. */
+eipc_status eipc_ccd_max_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const double *dq,
+                              const double *dx_off, double dhat, double s, double t_max, int64_t max_iter,
+                              double *alpha, int64_t *n_cand, eipc_stream stream);
+
+/* Hessian-vector product through the embedding (Eq. 17), recomputing the
+ * pair Hessians (nothing is stored per pair):
+ *   out = sum_k W_k^T H_k (W_k v + v_off_k)
+ * with H_k the true pair Hessian, or its PSD projection with EIPC_PROJECT.
+ * v: device double[3*n_node]; v_off: device double[3*n_vert] or NULL.
+ * out: device double[3*n_node] (overwritten).  out_off: device
+ * double[3*n_vert] or NULL, receives the unreduced per-vertex sums
+ * sum_k H_k z_k (the rows of kinematic vertices). */
+eipc_status eipc_barrier_hvp(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
+                             int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
+                             uint32_t flags, const double *v, const double *v_off, double *out, double *out_off,
+                             eipc_stream stream);
+
+/* ---- inspection entry points (same kernels as above, for tests) ---- */
+
+/* Active subset of the given pairs (0 < d < dhat).  act_pt / act_ee
+ * (device int32[n_pt] / [n_ee]) receive indices into pt / ee, type_pt /
+ * type_ee (device int32, same sizes) the distance type, in unspecified
+ * order; counts go to the host.  Synchronizes. */
+eipc_status eipc_narrow_phase(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
+                              int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, int32_t *act_pt,
+                              int32_t *type_pt, int64_t *n_act_pt, int32_t *act_ee, int32_t *type_ee,
+                              int64_t *n_act_ee, eipc_stream stream);
+
+/* Per-pair quantities for `n` pairs of one kind (0 = PT, 1 = EE): distance
+ * type, squared distance, energy, 12-gradient and the 12x12 Hessian
+ * (projected with EIPC_PROJECT).  Inactive pairs get e = 0, g = 0, H = 0.
+ * Outputs are device arrays int32[n], double[n], double[n], double[n*12],
+ * double[n*144]; any may be NULL. */
+eipc_status eipc_pair_eval(eipc_ctx *ctx, const eipc_scene *sc, const double *q, int32_t kind,
+                           const int32_t *pairs, int64_t n, double dhat, double kappa, uint32_t flags,
+                           int32_t *type, double *s, double *e, double *g, double *H, eipc_stream stream);
+
+/* Swept candidates of eipc_ccd_max_step (same layout and capacity rules as
+ * eipc_build_candidates).  Synchronizes. */
+eipc_status eipc_ccd_candidates(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const double *dq,
+                                const double *dx_off, double dhat, int32_t *pt, int64_t cap_pt, int32_t *ee,
+                                int64_t cap_ee, int64_t *n_pt, int64_t *n_ee, eipc_stream stream);
+
+/* Per-pair step bound of eipc_ccd_max_step for `n` given pairs of one
+ * kind; t (device double[n]) and iters (device int64[n] or NULL). */
+eipc_status eipc_ccd_toi(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const double *dq,
+                         const double *dx_off, int32_t kind, const int32_t *pairs, int64_t n, double s,
+                         double t_max, int64_t max_iter, double *t, int64_t *iters, eipc_stream stream);
+
+/* Device FP64 square root and division on n inputs (sqrt(a), a / b), to
+ * check that the device rounds them like the host. */
+eipc_status eipc_fp64_selftest(eipc_ctx *ctx, const double *a, const double *b, double *sqrt_a, double *a_div_b,
+                               int64_t n, eipc_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EIPC_H */

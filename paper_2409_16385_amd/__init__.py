@@ -1,0 +1,14 @@
+"""MI355X (gfx950) contact stage of Embedded IPC (arXiv 2409.16385).
+
+Thin Python binding over the C ABI of ``libeipc.so`` (declared in
+``include/eipc.h``): argument marshalling only.  Every step of the contact
+stage runs in the library's HIP kernels; PyTorch supplies device memory
+and streams.  There is no CPU fallback: importing works without a GPU, but
+every compute call needs the built library and a ROCm device and raises
+otherwise.
+"""
+from .binding import (  # noqa: F401
+    ENERGY, GRAD, HESS, PROJECT, MOLLIFY, EipcError, Context, Scene, lib_path,
+    embed, build_candidates, barrier_reduce, ccd_max_step, barrier_hvp,
+    narrow_phase, pair_eval, ccd_candidates, ccd_toi, fp64_selftest, bsr_to_dense,
+)

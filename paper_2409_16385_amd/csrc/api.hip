@@ -1,0 +1,426 @@
+// C-ABI entry points (see include/eipc.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace eipc {
+
+eipc_status set_err(eipc_ctx *c, eipc_status st, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return st;
+}
+
+eipc_status ensure(eipc_ctx *c, BufId id, size_t bytes, void **out) {
+  DevBuf &b = c->buf[id];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      EIPC_HIP(c, hipDeviceSynchronize());
+      EIPC_HIP(c, hipFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    size_t nb = std::max(bytes, (size_t)4096);
+    nb = (nb + 4095) & ~(size_t)4095;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess)
+      return set_err(c, EIPC_ERR_HIP, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
+    b.p = p;
+    b.bytes = nb;
+  }
+  *out = b.p;
+  return EIPC_OK;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+
+static eipc_status fill_i32(eipc_ctx *c, int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  k_fill_i32<<<(int)std::min<int64_t>(grid_for(n, 256), 4096), 256, 0, s>>>(p, n, v);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+static eipc_status check_scene(eipc_ctx *c, const eipc_scene *sc) {
+  if (!c) return EIPC_ERR_ARG;
+  if (!sc) return set_err(c, EIPC_ERR_ARG, "scene is NULL");
+  if (sc->n_vert < 0 || sc->n_node < 0 || sc->n_face < 0 || sc->n_edge < 0)
+    return set_err(c, EIPC_ERR_ARG, "negative scene size");
+  if (!sc->W_rowptr || (sc->n_vert > 0 && (!sc->W_col || !sc->W_val)))
+    return set_err(c, EIPC_ERR_ARG, "W is NULL");
+  if (sc->n_face > 0 && !sc->faces) return set_err(c, EIPC_ERR_ARG, "faces is NULL");
+  if (sc->n_edge > 0 && !sc->edges) return set_err(c, EIPC_ERR_ARG, "edges is NULL");
+  return EIPC_OK;
+}
+
+static eipc_status check_dhat(eipc_ctx *c, double dhat) {
+  if (!(dhat > 0.0) || !std::isfinite(dhat)) return set_err(c, EIPC_ERR_ARG, "dhat must be positive and finite");
+  return EIPC_OK;
+}
+
+// device status -> API status; clears the word
+static eipc_status read_status(eipc_ctx *c, hipStream_t s, bool clear = true) {
+  uint32_t st = 0;
+  EIPC_HIP(c, hipMemcpyAsync(&st, c->status, 4, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  if (clear && st) EIPC_HIP(c, hipMemsetAsync(c->status, 0, 4, s));
+  if (st & ST_INTERSECTING) return set_err(c, EIPC_ERR_INTERSECTING, "a candidate pair has zero distance");
+  if (st & ST_NONFINITE) return set_err(c, EIPC_ERR_NONFINITE, "non-finite position or pair quantity");
+  if (st & ST_CCD_CAPPED) return EIPC_WARN_CCD_CAPPED;
+  return EIPC_OK;
+}
+
+static uint32_t pow2_at_least(int64_t v) {
+  uint64_t p = 1;
+  while ((int64_t)p < v) p <<= 1;
+  return (uint32_t)std::min<uint64_t>(p, 1ull << 30);
+}
+
+static eipc_status narrow_both(eipc_ctx *c, const eipc_scene *sc, const double *xs, const int32_t *pt, int64_t n_pt,
+                               const int32_t *ee, int64_t n_ee, double dhat, int32_t **act_pt, int32_t **typ_pt,
+                               int32_t **act_ee, int32_t **typ_ee, hipStream_t s) {
+  EIPC_TRY(ensure_t(c, B_ACT_PT, (size_t)std::max<int64_t>(n_pt, 1), act_pt));
+  EIPC_TRY(ensure_t(c, B_TYP_PT, (size_t)std::max<int64_t>(n_pt, 1), typ_pt));
+  EIPC_TRY(ensure_t(c, B_ACT_EE, (size_t)std::max<int64_t>(n_ee, 1), act_ee));
+  EIPC_TRY(ensure_t(c, B_TYP_EE, (size_t)std::max<int64_t>(n_ee, 1), typ_ee));
+  EIPC_TRY(launch_zero(c, c->counters + 2, 2 * sizeof(int64_t), s));
+  EIPC_TRY(launch_narrow(c, sc, 0, xs, pt, n_pt, dhat, *act_pt, *typ_pt, c->counters + 2, s));
+  EIPC_TRY(launch_narrow(c, sc, 1, xs, ee, n_ee, dhat, *act_ee, *typ_ee, c->counters + 3, s));
+  return EIPC_OK;
+}
+
+}  // namespace eipc
+
+using namespace eipc;
+
+extern "C" {
+
+const char *eipc_status_string(eipc_status s) {
+  switch (s) {
+    case EIPC_OK: return "ok";
+    case EIPC_ERR_ARG: return "invalid argument";
+    case EIPC_ERR_CAPACITY: return "output capacity too small";
+    case EIPC_ERR_INTERSECTING: return "intersecting input (zero distance pair)";
+    case EIPC_ERR_DEGENERATE: return "degenerate primitive";
+    case EIPC_ERR_NONFINITE: return "non-finite value";
+    case EIPC_ERR_HIP: return "HIP runtime error";
+    case EIPC_WARN_CCD_CAPPED: return "CCD iteration cap reached (bound still conservative)";
+    default: return "unknown status";
+  }
+}
+
+eipc_status eipc_create(eipc_ctx **out, int32_t device) {
+  if (!out) return EIPC_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EIPC_ERR_ARG;
+  eipc_ctx *c = new (std::nothrow) eipc_ctx();
+  if (!c) return EIPC_ERR_HIP;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&c->status, 256) != hipSuccess ||
+      hipMalloc(&c->stats, 32 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->counters, 16 * sizeof(int64_t)) != hipSuccess ||
+      hipMemset(c->status, 0, 256) != hipSuccess || hipMemset(c->counters, 0, 16 * sizeof(int64_t)) != hipSuccess) {
+    eipc_destroy(c);
+    return EIPC_ERR_HIP;
+  }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    c->num_cu = ncu;
+  *out = c;
+  return EIPC_OK;
+}
+
+void eipc_destroy(eipc_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (auto &b : c->buf)
+    if (b.p) hipFree(b.p);
+  if (c->status) hipFree(c->status);
+  if (c->stats) hipFree(c->stats);
+  if (c->counters) hipFree(c->counters);
+  delete c;
+}
+
+const char *eipc_last_error(const eipc_ctx *c) { return c ? c->err : "no context"; }
+
+eipc_status eipc_sync_status(eipc_ctx *c, eipc_stream stream) {
+  if (!c) return EIPC_ERR_ARG;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  return read_status(c, (hipStream_t)stream);
+}
+
+eipc_status eipc_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *off, double *x,
+                       eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  if ((!q && sc->n_node > 0) || (!x && sc->n_vert > 0)) return set_err(c, EIPC_ERR_ARG, "q or x is NULL");
+  EIPC_HIP(c, hipSetDevice(c->device));
+  return launch_embed(c, sc, q, off, nullptr, x, (hipStream_t)stream);
+}
+
+eipc_status eipc_build_candidates(eipc_ctx *c, const eipc_scene *sc, const double *q, double dhat, int32_t *pt,
+                                  int64_t cap_pt, int32_t *ee, int64_t cap_ee, int64_t *n_pt, int64_t *n_ee,
+                                  eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (!n_pt || !n_ee || (!q && sc->n_node > 0) || cap_pt < 0 || cap_ee < 0)
+    return set_err(c, EIPC_ERR_ARG, "bad candidate arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  eipc_status s1 = broad_phase(c, sc, 0, xs, nullptr, dhat, pt, cap_pt, n_pt, 1, s);
+  if (s1 != EIPC_OK && s1 != EIPC_ERR_CAPACITY) return s1;
+  eipc_status s2 = broad_phase(c, sc, 1, xs, nullptr, dhat, ee, cap_ee, n_ee, 1, s);
+  if (s2 != EIPC_OK && s2 != EIPC_ERR_CAPACITY) return s2;
+  eipc_status st = read_status(c, s);
+  if (st != EIPC_OK && st != EIPC_WARN_CCD_CAPPED) return st;
+  if (s1 == EIPC_ERR_CAPACITY || s2 == EIPC_ERR_CAPACITY)
+    return set_err(c, EIPC_ERR_CAPACITY, "candidates need %lld PT / %lld EE slots", (long long)*n_pt,
+                   (long long)*n_ee);
+  return EIPC_OK;
+}
+
+eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
+                                const int32_t *ee, int64_t n_ee, double dhat, double kappa, uint32_t flags,
+                                double *energy, double *grad_q, double *hess_dense, eipc_bsr *hess_bsr,
+                                int64_t *n_active, eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && !pt) || (n_ee > 0 && !ee) || (!q && sc->n_node > 0) ||
+      !std::isfinite(kappa))
+    return set_err(c, EIPC_ERR_ARG, "bad pair or parameter arguments");
+  const bool want_h = (flags & EIPC_HESS) && (hess_dense || hess_bsr);
+  if (want_h && (int64_t)sc->n_node * sc->n_node >= (int64_t)INT32_MAX)
+    return set_err(c, EIPC_ERR_ARG, "reduced Hessian output supports n_node <= 46340");
+  if (hess_dense && hess_bsr) return set_err(c, EIPC_ERR_ARG, "ask for one Hessian layout");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  int32_t *act_pt, *typ_pt, *act_ee, *typ_ee;
+  EIPC_TRY(narrow_both(c, sc, xs, pt, n_pt, ee, n_ee, dhat, &act_pt, &typ_pt, &act_ee, &typ_ee, s));
+  const int64_t n3 = 3 * (int64_t)sc->n_node;
+  for (int attempt = 0;; ++attempt) {
+    if (energy) EIPC_TRY(launch_zero(c, energy, sizeof(double), s));
+    if (grad_q && (flags & EIPC_GRAD)) EIPC_TRY(launch_zero(c, grad_q, sizeof(double) * n3, s));
+    HessOut h{0, nullptr, nullptr, nullptr, 0};
+    if (want_h && hess_dense) {
+      EIPC_TRY(launch_zero(c, hess_dense, sizeof(double) * n3 * n3, s));
+      h.kind = 1;
+      h.dense = hess_dense;
+    } else if (want_h) {
+      int64_t cap = std::max<int64_t>(c->hash_cap, pow2_at_least(16 * (int64_t)sc->n_node));
+      c->hash_cap = cap;
+      EIPC_TRY(ensure_t(c, B_HKEY, (size_t)cap, &h.hkey));
+      EIPC_TRY(ensure_t(c, B_HVAL, (size_t)cap * 9, &h.hval));
+      EIPC_TRY(fill_i32(c, h.hkey, cap, -1, s));
+      EIPC_TRY(launch_zero(c, h.hval, sizeof(double) * 9 * cap, s));
+      h.kind = 2;
+      h.hmask = (uint32_t)(cap - 1);
+    }
+    const uint32_t f = flags & (want_h ? ~0u : ~(uint32_t)EIPC_HESS);
+    double *g = (flags & EIPC_GRAD) ? grad_q : nullptr;
+    EIPC_TRY(launch_barrier(c, sc, 0, xs, pt, act_pt, typ_pt, c->counters + 2, n_pt, dhat, kappa, f, energy, g, h, s));
+    EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, c->counters + 3, n_ee, dhat, kappa, f, energy, g, h, s));
+    if (h.kind == 1) EIPC_TRY(launch_dense_mirror(c, sc->n_node, hess_dense, s));
+    if (h.kind == 2) {
+      uint32_t st = 0;
+      EIPC_HIP(c, hipMemcpyAsync(&st, c->status, 4, hipMemcpyDeviceToHost, s));
+      EIPC_HIP(c, hipStreamSynchronize(s));
+      if ((st & ST_HASH_OVERFLOW) && attempt < 8) {
+        st &= ~ST_HASH_OVERFLOW;
+        EIPC_HIP(c, hipMemcpyAsync(c->status, &st, 4, hipMemcpyHostToDevice, s));
+        c->hash_cap *= 4;
+        continue;
+      }
+      if (st & ST_HASH_OVERFLOW) return set_err(c, EIPC_ERR_CAPACITY, "reduced Hessian hash overflow");
+      EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s));
+    }
+    break;
+  }
+  if (n_active) {
+    int64_t cnt[2];
+    EIPC_HIP(c, hipMemcpyAsync(cnt, c->counters + 2, 16, hipMemcpyDeviceToHost, s));
+    EIPC_HIP(c, hipStreamSynchronize(s));
+    *n_active = cnt[0] + cnt[1];
+  }
+  if (n_active || hess_bsr) {
+    eipc_status st = read_status(c, s);
+    if (st != EIPC_OK && st != EIPC_WARN_CCD_CAPPED) return st;
+  }
+  return EIPC_OK;
+}
+
+eipc_status eipc_ccd_max_step(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq,
+                              const double *dx_off, double dhat, double sfac, double t_max, int64_t max_iter,
+                              double *alpha, int64_t *n_cand, eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (!alpha || (sc->n_node > 0 && (!q || !dq)) || !(sfac > 0.0 && sfac < 1.0) || !(t_max > 0.0) ||
+      !std::isfinite(t_max) || max_iter < 1)
+    return set_err(c, EIPC_ERR_ARG, "bad CCD arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  double *xs, *ps, *x1s;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_P, (size_t)n3 + 1, &ps));
+  EIPC_TRY(ensure_t(c, B_X1, (size_t)n3 + 1, &x1s));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
+  EIPC_TRY(launch_add_soa(c, n3, xs, ps, x1s, s));
+  int64_t npt = 0, nee = 0;
+  int32_t *cpt = nullptr, *cee = nullptr;
+  EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, nullptr, 0, &npt, 0, s, B_CAND_PT, &cpt));
+  EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, nullptr, 0, &nee, 0, s, B_CAND_EE, &cee));
+  uint64_t *abits = (uint64_t *)(c->counters + 4);
+  uint64_t tb;
+  std::memcpy(&tb, &t_max, 8);
+  k_set_u64<<<1, 1, 0, s>>>(abits, tb);
+  EIPC_HIP(c, hipGetLastError());
+  EIPC_TRY(launch_ccd(c, sc, 0, xs, ps, cpt, npt, sfac, t_max, max_iter, abits, nullptr, nullptr, s));
+  EIPC_TRY(launch_ccd(c, sc, 1, xs, ps, cee, nee, sfac, t_max, max_iter, abits, nullptr, nullptr, s));
+  uint64_t ab = 0;
+  EIPC_HIP(c, hipMemcpyAsync(&ab, abits, 8, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  std::memcpy(alpha, &ab, 8);
+  if (n_cand) *n_cand = npt + nee;
+  return read_status(c, s);
+}
+
+eipc_status eipc_barrier_hvp(eipc_ctx *c, const eipc_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
+                             const int32_t *ee, int64_t n_ee, double dhat, double kappa, uint32_t flags,
+                             const double *v, const double *v_off, double *out, double *out_off,
+                             eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && !pt) || (n_ee > 0 && !ee) || (sc->n_node > 0 && (!q || !v || !out)))
+    return set_err(c, EIPC_ERR_ARG, "bad HVP arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  double *xs, *xvs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_XV, (size_t)n3 + 1, &xvs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_embed(c, sc, v, v_off, xvs, nullptr, s));
+  int32_t *act_pt, *typ_pt, *act_ee, *typ_ee;
+  EIPC_TRY(narrow_both(c, sc, xs, pt, n_pt, ee, n_ee, dhat, &act_pt, &typ_pt, &act_ee, &typ_ee, s));
+  EIPC_TRY(launch_zero(c, out, sizeof(double) * 3 * (size_t)sc->n_node, s));
+  if (out_off) EIPC_TRY(launch_zero(c, out_off, sizeof(double) * (size_t)n3, s));
+  EIPC_TRY(launch_hvp(c, sc, 0, xs, xvs, pt, act_pt, typ_pt, c->counters + 2, n_pt, dhat, kappa, flags, out, out_off,
+                      s));
+  EIPC_TRY(launch_hvp(c, sc, 1, xs, xvs, ee, act_ee, typ_ee, c->counters + 3, n_ee, dhat, kappa, flags, out, out_off,
+                      s));
+  return EIPC_OK;
+}
+
+eipc_status eipc_narrow_phase(eipc_ctx *c, const eipc_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
+                              const int32_t *ee, int64_t n_ee, double dhat, int32_t *act_pt, int32_t *type_pt,
+                              int64_t *n_act_pt, int32_t *act_ee, int32_t *type_ee, int64_t *n_act_ee,
+                              eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && (!pt || !act_pt || !type_pt)) || (n_ee > 0 && (!ee || !act_ee || !type_ee)) ||
+      !n_act_pt || !n_act_ee)
+    return set_err(c, EIPC_ERR_ARG, "bad narrow-phase arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_zero(c, c->counters + 2, 2 * sizeof(int64_t), s));
+  EIPC_TRY(launch_narrow(c, sc, 0, xs, pt, n_pt, dhat, act_pt, type_pt, c->counters + 2, s));
+  EIPC_TRY(launch_narrow(c, sc, 1, xs, ee, n_ee, dhat, act_ee, type_ee, c->counters + 3, s));
+  int64_t cnt[2];
+  EIPC_HIP(c, hipMemcpyAsync(cnt, c->counters + 2, 16, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  *n_act_pt = cnt[0];
+  *n_act_ee = cnt[1];
+  eipc_status st = read_status(c, s);
+  return st == EIPC_WARN_CCD_CAPPED ? EIPC_OK : st;
+}
+
+eipc_status eipc_pair_eval(eipc_ctx *c, const eipc_scene *sc, const double *q, int32_t kind, const int32_t *pairs,
+                           int64_t n, double dhat, double kappa, uint32_t flags, int32_t *type, double *sq, double *e,
+                           double *g, double *H, eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if ((kind != 0 && kind != 1) || n < 0 || (n > 0 && !pairs)) return set_err(c, EIPC_ERR_ARG, "bad pair arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  return launch_pair_eval(c, sc, kind, xs, pairs, n, dhat, kappa, flags, type, sq, e, g, H, s);
+}
+
+eipc_status eipc_ccd_candidates(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq,
+                                const double *dx_off, double dhat, int32_t *pt, int64_t cap_pt, int32_t *ee,
+                                int64_t cap_ee, int64_t *n_pt, int64_t *n_ee, eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (!n_pt || !n_ee || (sc->n_node > 0 && (!q || !dq))) return set_err(c, EIPC_ERR_ARG, "bad CCD arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  double *xs, *ps, *x1s;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_P, (size_t)n3 + 1, &ps));
+  EIPC_TRY(ensure_t(c, B_X1, (size_t)n3 + 1, &x1s));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
+  EIPC_TRY(launch_add_soa(c, n3, xs, ps, x1s, s));
+  eipc_status s1 = broad_phase(c, sc, 0, xs, x1s, dhat, pt, cap_pt, n_pt, 1, s);
+  if (s1 != EIPC_OK && s1 != EIPC_ERR_CAPACITY) return s1;
+  eipc_status s2 = broad_phase(c, sc, 1, xs, x1s, dhat, ee, cap_ee, n_ee, 1, s);
+  if (s2 != EIPC_OK && s2 != EIPC_ERR_CAPACITY) return s2;
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  if (s1 == EIPC_ERR_CAPACITY || s2 == EIPC_ERR_CAPACITY)
+    return set_err(c, EIPC_ERR_CAPACITY, "swept candidates need %lld PT / %lld EE slots", (long long)*n_pt,
+                   (long long)*n_ee);
+  return EIPC_OK;
+}
+
+eipc_status eipc_ccd_toi(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq, const double *dx_off,
+                         int32_t kind, const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
+                         double *t, int64_t *iters, eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  if ((kind != 0 && kind != 1) || n < 0 || (n > 0 && (!pairs || !t)) || !(sfac > 0.0 && sfac < 1.0) ||
+      !(t_max > 0.0) || max_iter < 1)
+    return set_err(c, EIPC_ERR_ARG, "bad CCD arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  double *xs, *ps;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_P, (size_t)n3 + 1, &ps));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
+  return launch_ccd(c, sc, kind, xs, ps, pairs, n, sfac, t_max, max_iter, nullptr, t, iters, s);
+}
+
+eipc_status eipc_fp64_selftest(eipc_ctx *c, const double *a, const double *b, double *sq, double *dv, int64_t n,
+                               eipc_stream stream) {
+  if (!c || n < 0 || (n > 0 && (!a || !b || !sq || !dv))) return EIPC_ERR_ARG;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  return launch_fp64_selftest(c, a, b, sq, dv, n, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,587 @@
+// Per-pair barrier energy, gradient and (projected) Hessian, reduced through
+// the embedding (Eq. 17) with LDS-staged accumulation; Hessian-vector
+// products; BSR compaction of the reduced Hessian.
+#include <algorithm>
+
+#include "common.h"
+#include "pair_math.h"
+
+namespace eipc {
+
+constexpr int BR_THREADS = 256;
+constexpr int LTBL = 512;  // LDS 3x3-block table entries (36 KiB)
+constexpr int LGT = 256;   // LDS node-vector table entries (6 KiB)
+constexpr int MAX_PROBE = 32;
+
+__device__ __forceinline__ uint32_t mix32(uint32_t k) {
+  k ^= k >> 16;
+  k *= 0x7feb352dU;
+  k ^= k >> 15;
+  k *= 0x846ca68bU;
+  k ^= k >> 16;
+  return k;
+}
+
+// find-or-insert in an open-addressing table of int keys (-1 = empty)
+__device__ __forceinline__ int table_slot(int *keys, uint32_t mask, int key) {
+  uint32_t h = mix32((uint32_t)key) & mask;
+  for (int p = 0; p < MAX_PROBE; ++p) {
+    int k = ((volatile int *)keys)[h];
+    if (k == key) return (int)h;
+    if (k == -1) {
+      int old = atomicCAS(&keys[h], -1, key);
+      if (old == -1 || old == key) return (int)h;
+    }
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
+template <int KIND>
+__device__ __forceinline__ void pair_vertices(const int32_t *pairs, int64_t k, const int32_t *faces,
+                                              const int32_t *edges, int *vid) {
+  const int a = pairs[2 * k], b = pairs[2 * k + 1];
+  if (KIND == 0) {
+    vid[0] = a;
+    vid[1] = faces[3 * (int64_t)b];
+    vid[2] = faces[3 * (int64_t)b + 1];
+    vid[3] = faces[3 * (int64_t)b + 2];
+  } else {
+    vid[0] = edges[2 * (int64_t)a];
+    vid[1] = edges[2 * (int64_t)a + 1];
+    vid[2] = edges[2 * (int64_t)b];
+    vid[3] = edges[2 * (int64_t)b + 1];
+  }
+}
+
+__device__ __forceinline__ V3 load3(const double *xs, int n, int v) {
+  return V3{xs[v], xs[n + v], xs[2 * (int64_t)n + v]};
+}
+
+// global destination of a 3x3 block (I <= J)
+__device__ __forceinline__ void global_block_add(const HessOut &h, int n_node, int I, int J, const double *B,
+                                                 uint32_t *status) {
+  if (h.kind == 1) {
+    const int64_t n3 = 3 * (int64_t)n_node;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) atomicAdd(&h.dense[(3 * (int64_t)I + i) * n3 + 3 * J + j], B[3 * i + j]);
+  } else if (h.kind == 2) {
+    int slot = table_slot(h.hkey, h.hmask, I * n_node + J);
+    if (slot < 0) {
+      atomicOr(status, ST_HASH_OVERFLOW);
+      return;
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) atomicAdd(&h.hval[9 * (int64_t)slot + t], B[t]);
+  }
+}
+
+struct LdsTables {
+  int *bkey;
+  double *bval;
+  int *gkey;
+  double *gval;
+};
+
+__device__ __forceinline__ void lds_block_add(const LdsTables &T, const HessOut &h, int n_node, int I, int J,
+                                              const double *B, uint32_t *status) {
+  int slot = table_slot(T.bkey, LTBL - 1, I * n_node + J);
+  if (slot < 0) {
+    global_block_add(h, n_node, I, J, B, status);
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) atomicAdd(&T.bval[9 * slot + t], B[t]);
+}
+
+__device__ __forceinline__ void lds_vec_add(const LdsTables &T, double *grad, int I, double g0, double g1,
+                                            double g2) {
+  int slot = table_slot(T.gkey, LGT - 1, I);
+  if (slot < 0) {
+    atomicAdd(&grad[3 * (int64_t)I], g0);
+    atomicAdd(&grad[3 * (int64_t)I + 1], g1);
+    atomicAdd(&grad[3 * (int64_t)I + 2], g2);
+    return;
+  }
+  atomicAdd(&T.gval[3 * slot], g0);
+  atomicAdd(&T.gval[3 * slot + 1], g1);
+  atomicAdd(&T.gval[3 * slot + 2], g2);
+}
+
+// Expansion through W: for slot pairs (a,k) <= (b,l) the block
+// w_ak w_bl P_x[a][b] goes to node block (I, J); only blocks with I <= J
+// are accumulated (transposing when I > J, adding both orders when the
+// two slots share a node).
+__device__ __forceinline__ void expand_hessian(const double *X, const int *vid, const int32_t *rowptr,
+                                               const int32_t *col, const double *val, const LdsTables &T,
+                                               const HessOut &h, int n_node, uint32_t *status) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int ka0 = rowptr[vid[a]], ka1 = rowptr[vid[a] + 1];
+    if (ka0 == ka1) continue;
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      const int kb0 = rowptr[vid[b]], kb1 = rowptr[vid[b] + 1];
+      if (kb0 == kb1) continue;
+      double P[9];
+      x_block(X, a, b, P);
+      for (int ka = ka0; ka < ka1; ++ka) {
+        const int I = col[ka];
+        const double wa = val[ka];
+        for (int kb = (a == b ? ka : kb0); kb < kb1; ++kb) {
+          const int J = col[kb];
+          const double w = wa * val[kb];
+          double C[9];
+          if (a == b && ka == kb) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) C[t] = w * P[t];
+            lds_block_add(T, h, n_node, I, I, C, status);
+          } else if (I < J) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) C[t] = w * P[t];
+            lds_block_add(T, h, n_node, I, J, C, status);
+          } else if (I > J) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) C[3 * i + j] = w * P[3 * j + i];
+            lds_block_add(T, h, n_node, J, I, C, status);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) C[3 * i + j] = w * (P[3 * i + j] + P[3 * j + i]);
+            lds_block_add(T, h, n_node, I, I, C, status);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(BR_THREADS) void k_barrier(
+    const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
+    const int64_t *__restrict__ d_count, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ xs, const double *__restrict__ x_rest, int n_vert, int n_node, double dhat,
+    double kappa, uint32_t flags, double *energy, double *grad, HessOut h, uint32_t *status) {
+  __shared__ int s_bkey[LTBL];
+  __shared__ double s_bval[LTBL * 9];
+  __shared__ int s_gkey[LGT];
+  __shared__ double s_gval[LGT * 3];
+  __shared__ double s_e[BR_THREADS / 64];
+  LdsTables T{s_bkey, s_bval, s_gkey, s_gval};
+  const bool want_g = (flags & EIPC_GRAD) && grad;
+  const bool want_h = (flags & EIPC_HESS) && h.kind != 0;
+  const bool project = flags & EIPC_PROJECT;
+  const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
+  for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) s_bkey[t] = -1;
+  for (int t = threadIdx.x; t < LTBL * 9; t += BR_THREADS) s_bval[t] = 0.0;
+  for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = -1;
+  for (int t = threadIdx.x; t < LGT * 3; t += BR_THREADS) s_gval[t] = 0.0;
+  __syncthreads();
+  const int64_t n = *d_count;
+  double e_acc = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * BR_THREADS; base < n; base += (int64_t)gridDim.x * BR_THREADS) {
+    const int64_t i = base + threadIdx.x;
+    if (i < n) {
+      const int64_t k = act[i];
+      const int ty = typ[i];
+      int vid[4];
+      pair_vertices<KIND>(pairs, k, faces, edges, vid);
+      V3 x[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = load3(xs, n_vert, vid[a]);
+      const double s2 = type_value<KIND>(ty, x);
+      double eps = 0.0;
+      if (moll) {
+        V3 r[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
+        eps = mollifier_eps(r);
+      }
+      V3 Y[3];
+      y_basis<KIND>(x, Y);
+      double gE[9], HE[45];
+      e_acc += energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, want_h);
+      if (want_g) {
+        double gx[12];
+        slot_grad<KIND>(gE, gx);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int k0 = rowptr[vid[a]], k1 = rowptr[vid[a] + 1];
+          for (int kk = k0; kk < k1; ++kk) {
+            const double w = val[kk];
+            lds_vec_add(T, grad, col[kk], w * gx[3 * a], w * gx[3 * a + 1], w * gx[3 * a + 2]);
+          }
+        }
+      }
+      if (want_h) {
+        double M[45];
+        to_q_basis<KIND>(HE, M);
+        if (project) project_psd9(M);
+        expand_hessian(M, vid, rowptr, col, val, T, h, n_node, status);
+      }
+    }
+    __syncthreads();
+    // flush the LDS tables to global memory and reset them
+    for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) {
+      const int key = s_bkey[t];
+      if (key != -1) {
+        global_block_add(h, n_node, key / n_node, key % n_node, &s_bval[9 * t], status);
+        s_bkey[t] = -1;
+#pragma unroll
+        for (int u = 0; u < 9; ++u) s_bval[9 * t + u] = 0.0;
+      }
+    }
+    for (int t = threadIdx.x; t < LGT; t += BR_THREADS) {
+      const int key = s_gkey[t];
+      if (key != -1) {
+        atomicAdd(&grad[3 * (int64_t)key], s_gval[3 * t]);
+        atomicAdd(&grad[3 * (int64_t)key + 1], s_gval[3 * t + 1]);
+        atomicAdd(&grad[3 * (int64_t)key + 2], s_gval[3 * t + 2]);
+        s_gkey[t] = -1;
+        s_gval[3 * t] = s_gval[3 * t + 1] = s_gval[3 * t + 2] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (energy) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e_acc += __shfl_xor(e_acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s_e[threadIdx.x >> 6] = e_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < BR_THREADS / 64; ++w) t += s_e[w];
+      if (t != 0.0) atomicAdd(energy, t);
+    }
+  }
+}
+
+eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                           const int32_t *act, const int32_t *typ, const int64_t *d_count, int64_t max_count,
+                           double dhat, double kappa, uint32_t flags, double *energy, double *grad,
+                           const HessOut &h, hipStream_t s) {
+  if (max_count == 0) return EIPC_OK;
+  int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 4 * (int64_t)c->num_cu);
+  if (kind == 0)
+    k_barrier<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr,
+                                                sc->W_col, sc->W_val, xs, sc->x_rest, sc->n_vert, sc->n_node, dhat,
+                                                kappa, flags, energy, grad, h, c->status);
+  else
+    k_barrier<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr,
+                                                sc->W_col, sc->W_val, xs, sc->x_rest, sc->n_vert, sc->n_node, dhat,
+                                                kappa, flags, energy, grad, h, c->status);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+// lower 3x3 blocks of the dense reduced Hessian from the upper ones
+__global__ void k_dense_mirror(int n_node, double *d) {
+  const int64_t n3 = 3 * (int64_t)n_node;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n3 * n3) return;
+  const int64_t r = idx / n3, cc = idx % n3;
+  if (r / 3 > cc / 3) d[idx] = d[cc * n3 + r];
+}
+
+eipc_status launch_dense_mirror(eipc_ctx *c, int n_node, double *dense, hipStream_t s) {
+  int64_t n3 = 3 * (int64_t)n_node;
+  if (n3 == 0) return EIPC_OK;
+  k_dense_mirror<<<grid_for(n3 * n3, 256), 256, 0, s>>>(n_node, dense);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BSR from the global hash of upper blocks: count per row (both
+// triangles), scan, fill, sort each row by column, gather values.
+// ---------------------------------------------------------------------------
+__global__ void k_hash_rowcount(int64_t cap, const int32_t *hkey, int n_node, int32_t *rowcnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cap) return;
+  const int key = hkey[t];
+  if (key < 0) return;
+  const int I = key / n_node, J = key % n_node;
+  atomicAdd(&rowcnt[I], 1);
+  if (I != J) atomicAdd(&rowcnt[J], 1);
+}
+
+__global__ void k_hash_rowfill(int64_t cap, const int32_t *hkey, int n_node, const int64_t *rowptr,
+                               int32_t *rowfill, int32_t *bcol, int64_t *bsrc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cap) return;
+  const int key = hkey[t];
+  if (key < 0) return;
+  const int I = key / n_node, J = key % n_node;
+  int64_t p = rowptr[I] + atomicAdd(&rowfill[I], 1);
+  bcol[p] = J;
+  bsrc[p] = 2 * t;  // even: as stored
+  if (I != J) {
+    p = rowptr[J] + atomicAdd(&rowfill[J], 1);
+    bcol[p] = I;
+    bsrc[p] = 2 * t + 1;  // odd: transposed
+  }
+}
+
+__global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int64_t *bsrc, int32_t *rowptr32) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > n_node) return;
+  rowptr32[r] = (int32_t)rowptr[r];
+  if (r == n_node) return;
+  const int64_t b = rowptr[r], e = rowptr[r + 1];
+  for (int64_t i = b + 1; i < e; ++i) {
+    const int32_t cv = bcol[i];
+    const int64_t sv = bsrc[i];
+    int64_t j = i - 1;
+    while (j >= b && bcol[j] > cv) {
+      bcol[j + 1] = bcol[j];
+      bsrc[j + 1] = bsrc[j];
+      --j;
+    }
+    bcol[j + 1] = cv;
+    bsrc[j + 1] = sv;
+  }
+}
+
+__global__ void k_bsr_gather(int64_t nnzb, const int64_t *bsrc, const double *hval, double *blocks) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnzb) return;
+  const int64_t src = bsrc[p];
+  const double *v = hval + 9 * (src >> 1);
+  if ((src & 1) == 0) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) blocks[9 * p + t] = v[t];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) blocks[9 * p + 3 * i + j] = v[3 * j + i];
+  }
+}
+
+eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out, hipStream_t s) {
+  const int64_t cap = (int64_t)h.hmask + 1;
+  int32_t *rowcnt, *rowfill, *bcol, *rowptr32;
+  int64_t *rowptr, *bsrc;
+  double *blocks;
+  EIPC_TRY(ensure_t(c, B_ROWCNT, (size_t)n_node + 1, &rowcnt));
+  EIPC_TRY(ensure_t(c, B_ROWFILL, (size_t)n_node + 1, &rowfill));
+  EIPC_TRY(ensure_t(c, B_ROWPTR, (size_t)n_node + 1, &rowptr));
+  EIPC_TRY(launch_zero(c, rowcnt, sizeof(int32_t) * (n_node + 1), s));
+  EIPC_TRY(launch_zero(c, rowfill, sizeof(int32_t) * (n_node + 1), s));
+  k_hash_rowcount<<<grid_for(cap, 256), 256, 0, s>>>(cap, h.hkey, n_node, rowcnt);
+  EIPC_HIP(c, hipGetLastError());
+  EIPC_TRY(exclusive_scan(c, rowcnt, n_node, rowptr, s));
+  int64_t nnzb = 0;
+  EIPC_HIP(c, hipMemcpyAsync(&nnzb, rowptr + n_node, 8, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  EIPC_TRY(ensure_t(c, B_BCOL, (size_t)std::max<int64_t>(nnzb, 1), &bcol));
+  EIPC_TRY(ensure_t(c, B_BSRC, (size_t)std::max<int64_t>(nnzb, 1), &bsrc));
+  EIPC_TRY(ensure_t(c, B_BBLK, (size_t)std::max<int64_t>(nnzb, 1) * 9, &blocks));
+  int32_t *rp32;
+  EIPC_TRY(ensure_t(c, B_ROWCNT, (size_t)n_node + 1, &rp32));  // reuse: counts no longer needed
+  k_hash_rowfill<<<grid_for(cap, 256), 256, 0, s>>>(cap, h.hkey, n_node, rowptr, rowfill, bcol, bsrc);
+  EIPC_HIP(c, hipGetLastError());
+  k_row_sort<<<grid_for(n_node + 1, 128), 128, 0, s>>>(n_node, rowptr, bcol, bsrc, rp32);
+  EIPC_HIP(c, hipGetLastError());
+  if (nnzb) {
+    k_bsr_gather<<<grid_for(nnzb, 256), 256, 0, s>>>(nnzb, bsrc, h.hval, blocks);
+    EIPC_HIP(c, hipGetLastError());
+  }
+  out->n_rows = n_node;
+  out->nnzb = nnzb;
+  out->rowptr = rp32;
+  out->col = bcol;
+  out->blocks = blocks;
+  (void)rowcnt;
+  return EIPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Hessian-vector product: y = H_x z per pair, z = (W v + v_off) on the
+// pair's vertices, scattered through W^T (and unreduced into out_off).
+// H_x = Q X Q^T:  zeta = Q^T z, eta = X zeta, y = Q eta.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(BR_THREADS) void k_hvp(
+    const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
+    const int64_t *__restrict__ d_count, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ xs, const double *__restrict__ xvs, const double *__restrict__ x_rest, int n_vert,
+    double dhat, double kappa, uint32_t flags, double *out, double *out_off) {
+  const int64_t n = *d_count;
+  const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
+  for (int64_t i = (int64_t)blockIdx.x * BR_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BR_THREADS) {
+    const int64_t k = act[i];
+    const int ty = typ[i];
+    int vid[4];
+    pair_vertices<KIND>(pairs, k, faces, edges, vid);
+    V3 x[4], z[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      x[a] = load3(xs, n_vert, vid[a]);
+      z[a] = load3(xvs, n_vert, vid[a]);
+    }
+    const double s2 = type_value<KIND>(ty, x);
+    double eps = 0.0;
+    if (moll) {
+      V3 r[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
+      eps = mollifier_eps(r);
+    }
+    V3 Y[3];
+    y_basis<KIND>(x, Y);
+    double gE[9], HE[45], M[45];
+    energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, true);
+    to_q_basis<KIND>(HE, M);
+    if (flags & EIPC_PROJECT) project_psd9(M);
+    double zeta[9], eta[9];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      double zx = 0, zy = 0, zz = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double sg = 0.5 * kS[a][al];
+        zx += sg * z[a].x;
+        zy += sg * z[a].y;
+        zz += sg * z[a].z;
+      }
+      zeta[3 * al] = zx;
+      zeta[3 * al + 1] = zy;
+      zeta[3 * al + 2] = zz;
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < 9; ++cc) acc += M[pidx(r, cc)] * zeta[cc];
+      eta[r] = acc;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      double y0 = 0, y1 = 0, y2 = 0;
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        const double sg = 0.5 * kS[a][al];
+        y0 += sg * eta[3 * al];
+        y1 += sg * eta[3 * al + 1];
+        y2 += sg * eta[3 * al + 2];
+      }
+      if (out_off) {
+        atomicAdd(&out_off[3 * (int64_t)vid[a]], y0);
+        atomicAdd(&out_off[3 * (int64_t)vid[a] + 1], y1);
+        atomicAdd(&out_off[3 * (int64_t)vid[a] + 2], y2);
+      }
+      const int k0 = rowptr[vid[a]], k1 = rowptr[vid[a] + 1];
+      for (int kk = k0; kk < k1; ++kk) {
+        const double w = val[kk];
+        const int64_t I = col[kk];
+        atomicAdd(&out[3 * I], w * y0);
+        atomicAdd(&out[3 * I + 1], w * y1);
+        atomicAdd(&out[3 * I + 2], w * y2);
+      }
+    }
+  }
+}
+
+eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *xvs,
+                       const int32_t *pairs, const int32_t *act, const int32_t *typ, const int64_t *d_count,
+                       int64_t max_count, double dhat, double kappa, uint32_t flags, double *out,
+                       double *out_off, hipStream_t s) {
+  if (max_count == 0) return EIPC_OK;
+  int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 4 * (int64_t)c->num_cu);
+  if (kind == 0)
+    k_hvp<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                            sc->W_val, xs, xvs, sc->x_rest, sc->n_vert, dhat, kappa, flags, out,
+                                            out_off);
+  else
+    k_hvp<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                            sc->W_val, xs, xvs, sc->x_rest, sc->n_vert, dhat, kappa, flags, out,
+                                            out_off);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-pair inspection: type, s, e, g (12), H (12x12)
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ void k_pair_eval(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
+                            const int32_t *__restrict__ edges, const double *__restrict__ xs,
+                            const double *__restrict__ x_rest, int n_vert, double dhat, double kappa,
+                            uint32_t flags, int32_t *type, double *sq, double *e, double *g, double *H) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int vid[4];
+  pair_vertices<KIND>(pairs, i, faces, edges, vid);
+  V3 x[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) x[a] = load3(xs, n_vert, vid[a]);
+  int ty;
+  const double s2 = pair_dist2<KIND>(x, &ty);
+  if (type) type[i] = ty;
+  if (sq) sq[i] = s2;
+  const bool active = s2 > 0.0 && s2 < dhat * dhat;
+  double eps = 0.0;
+  if (KIND == 1 && (flags & EIPC_MOLLIFY) && x_rest) {
+    V3 r[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
+    eps = mollifier_eps(r);
+  }
+  double gE[9], HE[45], M[45];
+  double ev = 0.0;
+  if (active) {
+    V3 Y[3];
+    y_basis<KIND>(x, Y);
+    ev = energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, true);
+    to_q_basis<KIND>(HE, M);
+    if (flags & EIPC_PROJECT) project_psd9(M);
+  }
+  if (e) e[i] = ev;
+  if (g) {
+    double gx[12];
+    if (active)
+      slot_grad<KIND>(gE, gx);
+    else
+      for (int t = 0; t < 12; ++t) gx[t] = 0.0;
+    for (int t = 0; t < 12; ++t) g[12 * i + t] = gx[t];
+  }
+  if (H) {
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        double B[9];
+        if (active)
+          x_block(M, a, b, B);
+        else
+          for (int t = 0; t < 9; ++t) B[t] = 0.0;
+        for (int ii = 0; ii < 3; ++ii)
+          for (int jj = 0; jj < 3; ++jj) H[144 * i + (3 * a + ii) * 12 + 3 * b + jj] = B[3 * ii + jj];
+      }
+  }
+}
+
+eipc_status launch_pair_eval(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                             int64_t n, double dhat, double kappa, uint32_t flags, int32_t *type, double *sq,
+                             double *e, double *g, double *H, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  if (kind == 0)
+    k_pair_eval<0><<<grid_for(n, 64), 64, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->x_rest, sc->n_vert, dhat,
+                                                   kappa, flags, type, sq, e, g, H);
+  else
+    k_pair_eval<1><<<grid_for(n, 64), 64, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->x_rest, sc->n_vert, dhat,
+                                                   kappa, flags, type, sq, e, g, H);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+}  // namespace eipc

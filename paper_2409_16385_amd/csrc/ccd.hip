@@ -1,0 +1,84 @@
+// Conservative CCD step bound: additive conservative advancement per swept
+// candidate pair, minimum over pairs by wavefront reduction and one atomic.
+#include <algorithm>
+
+#include "common.h"
+#include "pair_math.h"
+
+namespace eipc {
+
+template <int KIND>
+__global__ void k_ccd(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
+                      const int32_t *__restrict__ edges, const double *__restrict__ xs, const double *__restrict__ ps,
+                      int n_vert, double sfac, double t_max, int64_t max_iter, unsigned long long *alpha_bits,
+                      double *t_out, int64_t *it_out, uint32_t *status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double t = t_max;
+  bool capped = false;
+  if (i < n) {
+    const int a = pairs[2 * i], b = pairs[2 * i + 1];
+    int vid[4];
+    if (KIND == 0) {
+      vid[0] = a;
+      vid[1] = faces[3 * (int64_t)b];
+      vid[2] = faces[3 * (int64_t)b + 1];
+      vid[3] = faces[3 * (int64_t)b + 2];
+    } else {
+      vid[0] = edges[2 * (int64_t)a];
+      vid[1] = edges[2 * (int64_t)a + 1];
+      vid[2] = edges[2 * (int64_t)b];
+      vid[3] = edges[2 * (int64_t)b + 1];
+    }
+    V3 x[4], p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[k] = V3{xs[vid[k]], xs[n_vert + vid[k]], xs[2 * (int64_t)n_vert + vid[k]]};
+      p[k] = V3{ps[vid[k]], ps[n_vert + vid[k]], ps[2 * (int64_t)n_vert + vid[k]]};
+    }
+    int64_t it = 0;
+    t = accd<KIND>(x, p, sfac, t_max, max_iter, &it);
+    capped = it >= max_iter;
+    if (t_out) t_out[i] = t;
+    if (it_out) it_out[i] = it;
+  }
+  if (alpha_bits) {
+    // t >= 0, so the IEEE bit pattern orders like the value
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMin(alpha_bits, (unsigned long long)__double_as_longlong(t));
+  }
+  if (__any(capped) && (threadIdx.x & 63) == 0) atomicOr(status, ST_CCD_CAPPED);
+}
+
+eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
+                       const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
+                       uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  if (kind == 0)
+    k_ccd<0><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                               max_iter, (unsigned long long *)d_alpha_bits, t_out, it_out,
+                                               c->status);
+  else
+    k_ccd<1><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                               max_iter, (unsigned long long *)d_alpha_bits, t_out, it_out,
+                                               c->status);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+__global__ void k_fp64_selftest(int64_t n, const double *a, const double *b, double *sq, double *dv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sq[i] = sqrt(a[i]);
+  dv[i] = a[i] / b[i];
+}
+
+eipc_status launch_fp64_selftest(eipc_ctx *c, const double *a, const double *b, double *sq, double *dv, int64_t n,
+                                 hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  k_fp64_selftest<<<grid_for(n, 256), 256, 0, s>>>(n, a, b, sq, dv);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+}  // namespace eipc

@@ -1,0 +1,138 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+
+#include "eipc.h"
+
+namespace eipc {
+
+// status bits raised by kernels into the device status word
+enum : uint32_t { ST_INTERSECTING = 1u, ST_NONFINITE = 2u, ST_CCD_CAPPED = 4u, ST_HASH_OVERFLOW = 8u };
+
+// scratch buffers owned by the context
+enum BufId {
+  B_X = 0,       // positions, SoA [3][n_vert]
+  B_P,           // CCD displacement, SoA
+  B_X1,          // CCD end positions, SoA
+  B_XV,          // HVP input mapped to vertices, SoA
+  B_QBOX,        // query boxes lo[3][n], hi[3][n]
+  B_IBOX,        // item boxes
+  B_CELLCNT,     // int32 per item
+  B_CELLOFF,     // int64 per item + 1
+  B_BCNT,        // int32 per bucket
+  B_BSTART,      // int64 per bucket + 1
+  B_BFILL,       // int32 per bucket
+  B_ENTCELL,     // uint64 per entry
+  B_ENTITEM,     // int32 per entry
+  B_LARGE,       // int32 large items
+  B_QCNT,        // int32 per query
+  B_QOFF,        // int64 per query + 1
+  B_SCANTMP,     // int64 block sums
+  B_ACT_PT, B_TYP_PT, B_ACT_EE, B_TYP_EE,
+  B_CAND_PT, B_CAND_EE,  // swept candidates (CCD)
+  B_HKEY, B_HVAL,        // global block hash
+  B_ROWCNT, B_ROWFILL, B_ROWPTR, B_BCOL, B_BSRC, B_BBLK,
+  B_NUM
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace eipc
+
+struct eipc_ctx {
+  int device = 0;
+  char err[512] = {0};
+  eipc::DevBuf buf[eipc::B_NUM];
+  uint32_t *status = nullptr;   // device status word
+  double *stats = nullptr;      // device [32] reduction scratch
+  int64_t *counters = nullptr;  // device [16] counters
+  int64_t *host = nullptr;      // pinned host staging [64]
+  int64_t hash_cap = 1 << 16;   // global block hash capacity (power of 2, grows)
+  int num_cu = 256;
+};
+
+namespace eipc {
+
+eipc_status set_err(eipc_ctx *c, eipc_status st, const char *fmt, ...);
+
+#define EIPC_HIP(ctx, expr)                                                                      \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return ::eipc::set_err((ctx), EIPC_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define EIPC_TRY(expr)            \
+  do {                            \
+    eipc_status s_ = (expr);      \
+    if (s_ != EIPC_OK) return s_; \
+  } while (0)
+
+// grow-only scratch allocation
+eipc_status ensure(eipc_ctx *c, BufId id, size_t bytes, void **out);
+template <class T>
+inline eipc_status ensure_t(eipc_ctx *c, BufId id, size_t count, T **out) {
+  void *p = nullptr;
+  eipc_status st = ensure(c, id, count * sizeof(T) + 64, &p);
+  *out = (T *)p;
+  return st;
+}
+
+inline int grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  return (int)(g < 1 ? 1 : g);
+}
+
+// ---- geometry.hip ----
+eipc_status launch_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *off, double *xs,
+                         double *x_aos, hipStream_t s);
+eipc_status launch_add_soa(eipc_ctx *c, int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+eipc_status exclusive_scan(eipc_ctx *c, const int32_t *in, int64_t n, int64_t *out, hipStream_t s);
+eipc_status launch_zero(eipc_ctx *c, void *p, size_t bytes, hipStream_t s);
+// Candidate pairs of one kind; swept when x1s != nullptr.  Writes
+// required count to *n_out; writes pairs when it fits (and sorts per
+// query when sort != 0).
+eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *x1s,
+                        double dhat, int32_t *out, int64_t cap, int64_t *n_out, int sort, hipStream_t s,
+                        int grow_id = -1, int32_t **grown = nullptr);
+eipc_status launch_narrow(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                          int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s);
+
+// ---- barrier.hip ----
+struct HessOut {
+  int kind;  // 0 none, 1 dense, 2 global hash
+  double *dense;
+  int32_t *hkey;
+  double *hval;
+  uint32_t hmask;
+};
+eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                           const int32_t *act, const int32_t *typ, const int64_t *d_count, int64_t max_count,
+                           double dhat, double kappa, uint32_t flags, double *energy, double *grad,
+                           const HessOut &h, hipStream_t s);
+eipc_status launch_dense_mirror(eipc_ctx *c, int n_node, double *dense, hipStream_t s);
+eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out, hipStream_t s);
+eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *xvs,
+                       const int32_t *pairs, const int32_t *act, const int32_t *typ, const int64_t *d_count,
+                       int64_t max_count, double dhat, double kappa, uint32_t flags, double *out,
+                       double *out_off, hipStream_t s);
+eipc_status launch_pair_eval(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                             int64_t n, double dhat, double kappa, uint32_t flags, int32_t *type, double *sq,
+                             double *e, double *g, double *H, hipStream_t s);
+
+// ---- ccd.hip ----
+eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
+                       const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
+                       uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s);
+eipc_status launch_fp64_selftest(eipc_ctx *c, const double *a, const double *b, double *sq, double *dv, int64_t n,
+                                 hipStream_t s);
+
+}  // namespace eipc

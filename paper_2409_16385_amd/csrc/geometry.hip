@@ -1,0 +1,678 @@
+// Embedding, scans, the spatial-hash broad phase and the narrow phase.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "pair_math.h"
+
+namespace eipc {
+
+// ---------------------------------------------------------------------------
+// embedding x = W q + off (Eq. 14): CSR order from 0.0, one rounded multiply
+// and one rounded add per term, off added last.  Output SoA (and AoS).
+// ---------------------------------------------------------------------------
+__global__ void k_embed(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                        const double *__restrict__ val, const double *__restrict__ q,
+                        const double *__restrict__ off, double *__restrict__ xs, double *__restrict__ x_aos,
+                        uint32_t *status) {
+#pragma clang fp contract(off)
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  const int k0 = rowptr[v], k1 = rowptr[v + 1];
+  for (int k = k0; k < k1; ++k) {
+    const double w = val[k];
+    const int64_t c = 3 * (int64_t)col[k];
+    a0 = a0 + w * q[c];
+    a1 = a1 + w * q[c + 1];
+    a2 = a2 + w * q[c + 2];
+  }
+  if (off) {
+    a0 = a0 + off[3 * (int64_t)v];
+    a1 = a1 + off[3 * (int64_t)v + 1];
+    a2 = a2 + off[3 * (int64_t)v + 2];
+  }
+  if (xs) {
+    xs[v] = a0;
+    xs[n + v] = a1;
+    xs[2 * (int64_t)n + v] = a2;
+  }
+  if (x_aos) {
+    x_aos[3 * (int64_t)v] = a0;
+    x_aos[3 * (int64_t)v + 1] = a1;
+    x_aos[3 * (int64_t)v + 2] = a2;
+  }
+  if (!(isfinite(a0) && isfinite(a1) && isfinite(a2))) atomicOr(status, ST_NONFINITE);
+}
+
+eipc_status launch_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *off, double *xs,
+                         double *x_aos, hipStream_t s) {
+  if (sc->n_vert == 0) return EIPC_OK;
+  k_embed<<<grid_for(sc->n_vert, 256), 256, 0, s>>>(sc->n_vert, sc->W_rowptr, sc->W_col, sc->W_val, q, off, xs,
+                                                     x_aos, c->status);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+__global__ void k_add(int64_t n, const double *a, const double *b, double *out) {
+#pragma clang fp contract(off)
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+eipc_status launch_add_soa(eipc_ctx *c, int64_t n, const double *a, const double *b, double *out, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  k_add<<<grid_for(n, 256), 256, 0, s>>>(n, a, b, out);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+__global__ void k_zero(uint64_t *p, int64_t n64) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n64; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+__global__ void k_zero_bytes(uint8_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Fill kernel (used instead of hipMemsetAsync so the sequence can be
+// captured into a graph).
+eipc_status launch_zero(eipc_ctx *c, void *p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return EIPC_OK;
+  int64_t n64 = (int64_t)(bytes / 8);
+  if (((uintptr_t)p & 7) == 0 && n64 > 0) {
+    int g = (int)std::min<int64_t>(grid_for(n64, 256), 4096);
+    k_zero<<<g, 256, 0, s>>>((uint64_t *)p, n64);
+    EIPC_HIP(c, hipGetLastError());
+    size_t rem = bytes - (size_t)n64 * 8;
+    if (rem) {
+      k_zero_bytes<<<1, 64, 0, s>>>((uint8_t *)p + n64 * 8, (int64_t)rem);
+      EIPC_HIP(c, hipGetLastError());
+    }
+  } else {
+    k_zero_bytes<<<grid_for((int64_t)bytes, 256), 256, 0, s>>>((uint8_t *)p, (int64_t)bytes);
+    EIPC_HIP(c, hipGetLastError());
+  }
+  return EIPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan: int32 counts[n] -> int64 offsets[n+1] (offsets[n] = total)
+// tiles of 2048 elements (256 threads x 8), block sums scanned by one block
+// ---------------------------------------------------------------------------
+constexpr int SCAN_T = 256, SCAN_E = 8, SCAN_TILE = SCAN_T * SCAN_E;
+
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *smem, int64_t *total) {
+  // inclusive wave scan
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) smem[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      int64_t t = smem[w];
+      smem[w] = acc;
+      acc += t;
+    }
+    smem[16] = acc;
+  }
+  __syncthreads();
+  int64_t r = x - v + smem[wid];
+  *total = smem[16];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_scan_partial(const int32_t *in, int64_t n, int64_t *bsum) {
+  __shared__ int64_t sm[17];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_E;
+  int64_t acc = 0;
+#pragma unroll
+  for (int e = 0; e < SCAN_E; ++e)
+    if (base + e < n) acc += in[base + e];
+  int64_t tot;
+  block_excl_scan(acc, sm, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(int64_t *bsum, int64_t nb) {
+  __shared__ int64_t sm[17];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += blockDim.x) {
+    int64_t i = base + threadIdx.x;
+    int64_t v = i < nb ? bsum[i] : 0;
+    int64_t tot;
+    int64_t ex = block_excl_scan(v, sm, &tot);
+    if (i < nb) bsum[i] = ex + carry;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ void k_scan_final(const int32_t *in, int64_t n, const int64_t *bsum, int64_t nb, int64_t *out) {
+  __shared__ int64_t sm[17];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_E;
+  int64_t vals[SCAN_E];
+  int64_t acc = 0;
+#pragma unroll
+  for (int e = 0; e < SCAN_E; ++e) {
+    vals[e] = (base + e < n) ? in[base + e] : 0;
+    acc += vals[e];
+  }
+  int64_t tot;
+  int64_t ex = block_excl_scan(acc, sm, &tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (int e = 0; e < SCAN_E; ++e) {
+    if (base + e < n) out[base + e] = ex;
+    ex += vals[e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[nb];
+}
+
+eipc_status exclusive_scan(eipc_ctx *c, const int32_t *in, int64_t n, int64_t *out, hipStream_t s) {
+  int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb < 1) nb = 1;
+  int64_t *bsum;
+  EIPC_TRY(ensure_t(c, B_SCANTMP, (size_t)nb + 1, &bsum));
+  k_scan_partial<<<(unsigned)nb, SCAN_T, 0, s>>>(in, n, bsum);
+  EIPC_HIP(c, hipGetLastError());
+  k_scan_top<<<1, 1024, 0, s>>>(bsum, nb);
+  EIPC_HIP(c, hipGetLastError());
+  k_scan_final<<<(unsigned)nb, SCAN_T, 0, s>>>(in, n, bsum, nb, out);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// boxes: per primitive, lo = min over vertices (start and end) - dhat/2,
+// hi = max + dhat/2.  SoA lo[3][n] then hi[3][n].
+// ---------------------------------------------------------------------------
+template <int NV>
+__global__ void k_boxes(int n, const int32_t *__restrict__ idx, const double *__restrict__ xs,
+                        const double *__restrict__ x1s, int n_vert, double h, double *__restrict__ box) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int vid[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) vid[a] = (NV == 1) ? i : idx[(int64_t)NV * i + a];
+#pragma unroll
+  for (int cax = 0; cax < 3; ++cax) {
+    const double *xc = xs + (int64_t)cax * n_vert;
+    double mn = xc[vid[0]], mx = mn;
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+      double v = xc[vid[a]];
+      mn = fmin(mn, v);
+      mx = fmax(mx, v);
+      if (x1s) {
+        double w = x1s[(int64_t)cax * n_vert + vid[a]];
+        mn = fmin(mn, w);
+        mx = fmax(mx, w);
+      }
+    }
+    box[(int64_t)cax * n + i] = mn - h;
+    box[(int64_t)(3 + cax) * n + i] = mx + h;
+  }
+}
+
+__device__ __forceinline__ uint64_t ord_key(double v) {
+  uint64_t b = __double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __forceinline__ double ord_dec(uint64_t k) {
+  uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  double v;
+  std::memcpy(&v, &b, 8);
+  return v;
+}
+
+// stats layout (uint64 view): [0..2] min lo (ordered), [3..5] max hi
+// (ordered); double view [6..8] sum of extents
+__global__ void k_box_stats(int n, const double *__restrict__ box, uint64_t *st, int with_ext) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double lo[3], hi[3], ex[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = i < n ? box[(int64_t)a * n + i] : INFINITY;
+    hi[a] = i < n ? box[(int64_t)(3 + a) * n + i] : -INFINITY;
+    ex[a] = i < n ? hi[a] - lo[a] : 0.0;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fmin(lo[a], __shfl_xor(lo[a], o, 64));
+      hi[a] = fmax(hi[a], __shfl_xor(hi[a], o, 64));
+      ex[a] += __shfl_xor(ex[a], o, 64);
+    }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      atomicMin((unsigned long long *)&st[a], (unsigned long long)ord_key(lo[a]));
+      atomicMax((unsigned long long *)&st[3 + a], (unsigned long long)ord_key(hi[a]));
+      if (with_ext) atomicAdd((double *)&st[6 + a], ex[a]);
+    }
+  }
+}
+
+__global__ void k_stats_init(uint64_t *st) {
+  int t = threadIdx.x;
+  if (t < 3) {
+    st[t] = ~0ull;
+    st[3 + t] = 0ull;
+    ((double *)st)[6 + t] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// spatial hash over a uniform grid
+// ---------------------------------------------------------------------------
+struct GridDev {
+  double o[3];
+  double inv_h;
+  int dim[3];
+  uint32_t bmask;
+  const int64_t *bstart;
+  const uint64_t *ent_cell;
+  const int32_t *ent_item;
+  const int32_t *large;
+  int n_large;
+};
+
+constexpr int MAX_ITEM_CELLS = 64;
+
+__device__ __forceinline__ int cell_of(double v, double o, double inv_h, int dim) {
+#pragma clang fp contract(off)
+  double t = floor((v - o) * inv_h);
+  int c = t < 0.0 ? 0 : (t > (double)(dim - 1) ? dim - 1 : (int)t);
+  return c;
+}
+__device__ __forceinline__ uint64_t cell_key(int x, int y, int z) {
+  return (uint64_t)x | ((uint64_t)y << 21) | ((uint64_t)z << 42);
+}
+__device__ __forceinline__ uint32_t cell_hash(int x, int y, int z) {
+  return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u);
+}
+
+__device__ __forceinline__ void cell_range(const GridDev &g, const double *box, int64_t n, int64_t i, int *c0,
+                                           int *c1) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    c0[a] = cell_of(box[a * n + i], g.o[a], g.inv_h, g.dim[a]);
+    c1[a] = cell_of(box[(3 + a) * n + i], g.o[a], g.inv_h, g.dim[a]);
+  }
+}
+
+__global__ void k_item_cells(int n, const double *__restrict__ box, GridDev g, int32_t *cnt, int32_t *large,
+                             int64_t *counters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c0[3], c1[3];
+  cell_range(g, box, n, i, c0, c1);
+  int64_t nc = (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+  if (nc > MAX_ITEM_CELLS) {
+    int slot = (int)atomicAdd((unsigned long long *)&counters[0], 1ull);
+    large[slot] = i;
+    cnt[i] = 0;
+  } else {
+    cnt[i] = (int32_t)nc;
+  }
+}
+
+__global__ void k_item_hist(int n, const double *__restrict__ box, GridDev g, const int32_t *cnt, int32_t *bcnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || cnt[i] == 0) return;
+  int c0[3], c1[3];
+  cell_range(g, box, n, i, c0, c1);
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&bcnt[cell_hash(x, y, z) & g.bmask], 1);
+}
+
+__global__ void k_item_fill(int n, const double *__restrict__ box, GridDev g, const int32_t *cnt, int32_t *bfill,
+                            uint64_t *ent_cell, int32_t *ent_item) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || cnt[i] == 0) return;
+  int c0[3], c1[3];
+  cell_range(g, box, n, i, c0, c1);
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) {
+        uint32_t b = cell_hash(x, y, z) & g.bmask;
+        int64_t slot = g.bstart[b] + atomicAdd(&bfill[b], 1);
+        ent_cell[slot] = cell_key(x, y, z);
+        ent_item[slot] = i;
+      }
+}
+
+__device__ __forceinline__ bool has_dof(const int32_t *rowptr, int v) { return rowptr[v + 1] > rowptr[v]; }
+
+__device__ __forceinline__ bool overlap(const double *qb, int64_t nq, int64_t q, const double *ib, int64_t ni,
+                                        int64_t i) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!(qb[a * nq + q] <= ib[(3 + a) * ni + i] && ib[a * ni + i] <= qb[(3 + a) * nq + q])) return false;
+  }
+  return true;
+}
+
+// Candidate query.  KIND 0: query = vertex v, item = face f.  KIND 1: query
+// = edge a, item = edge b > a.  A pair overlapping in several cells is
+// reported only in the cell of the lower corner of the box intersection.
+template <int KIND>
+__global__ void k_query(int nq, const double *__restrict__ qbox, int ni, const double *__restrict__ ibox, GridDev g,
+                        const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
+                        const int32_t *__restrict__ rowptr, int32_t *__restrict__ cnt,
+                        const int64_t *__restrict__ off, int32_t *__restrict__ out, int write, int sort) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int qa, qb = -1;
+  if (KIND == 0) {
+    qa = q;
+  } else {
+    qa = edges[2 * (int64_t)q];
+    qb = edges[2 * (int64_t)q + 1];
+  }
+  const bool qdof = has_dof(rowptr, qa) || (KIND == 1 && has_dof(rowptr, qb));
+  int c0[3], c1[3];
+  cell_range(g, qbox, nq, q, c0, c1);
+  const int64_t base = write ? off[q] : 0;
+  int64_t k = 0;
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) {
+        const uint64_t key = cell_key(x, y, z);
+        const uint32_t b = cell_hash(x, y, z) & g.bmask;
+        const int64_t e1 = g.bstart[b + 1];
+        for (int64_t e = g.bstart[b]; e < e1; ++e) {
+          if (g.ent_cell[e] != key) continue;
+          const int it = g.ent_item[e];
+          if (KIND == 1 && it <= q) continue;
+          int iv0, iv1, iv2 = -1;
+          if (KIND == 0) {
+            iv0 = faces[3 * (int64_t)it];
+            iv1 = faces[3 * (int64_t)it + 1];
+            iv2 = faces[3 * (int64_t)it + 2];
+            if (qa == iv0 || qa == iv1 || qa == iv2) continue;
+            if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1) && !has_dof(rowptr, iv2)) continue;
+          } else {
+            iv0 = edges[2 * (int64_t)it];
+            iv1 = edges[2 * (int64_t)it + 1];
+            if (qa == iv0 || qa == iv1 || qb == iv0 || qb == iv1) continue;
+            if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1)) continue;
+          }
+          if (!overlap(qbox, nq, q, ibox, ni, it)) continue;
+          // dedup: lower corner of the intersection
+          bool home = true;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            int ic = cell_of(ibox[(int64_t)a * ni + it], g.o[a], g.inv_h, g.dim[a]);
+            int cs = ic > c0[a] ? ic : c0[a];
+            int cur = a == 0 ? x : (a == 1 ? y : z);
+            home = home && (cs == cur);
+          }
+          if (!home) continue;
+          if (write) {
+            out[2 * (base + k)] = q;
+            out[2 * (base + k) + 1] = it;
+          }
+          ++k;
+        }
+      }
+  for (int j = 0; j < g.n_large; ++j) {
+    const int it = g.large[j];
+    if (KIND == 1 && it <= q) continue;
+    int iv0, iv1, iv2 = -1;
+    if (KIND == 0) {
+      iv0 = faces[3 * (int64_t)it];
+      iv1 = faces[3 * (int64_t)it + 1];
+      iv2 = faces[3 * (int64_t)it + 2];
+      if (qa == iv0 || qa == iv1 || qa == iv2) continue;
+      if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1) && !has_dof(rowptr, iv2)) continue;
+    } else {
+      iv0 = edges[2 * (int64_t)it];
+      iv1 = edges[2 * (int64_t)it + 1];
+      if (qa == iv0 || qa == iv1 || qb == iv0 || qb == iv1) continue;
+      if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1)) continue;
+    }
+    if (!overlap(qbox, nq, q, ibox, ni, it)) continue;
+    if (write) {
+      out[2 * (base + k)] = q;
+      out[2 * (base + k) + 1] = it;
+    }
+    ++k;
+  }
+  if (!write) {
+    cnt[q] = (int32_t)k;
+  } else if (sort && k > 1) {
+    int32_t *seg = out + 2 * base;
+    for (int64_t i = 1; i < k; ++i) {
+      int32_t v = seg[2 * i + 1];
+      int64_t j = i - 1;
+      while (j >= 0 && seg[2 * j + 1] > v) {
+        seg[2 * (j + 1) + 1] = seg[2 * j + 1];
+        --j;
+      }
+      seg[2 * (j + 1) + 1] = v;
+    }
+  }
+}
+
+static uint32_t next_pow2(uint64_t v) {
+  uint64_t p = 1;
+  while (p < v) p <<= 1;
+  return (uint32_t)p;
+}
+
+eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *x1s,
+                        double dhat, int32_t *out, int64_t cap, int64_t *n_out, int sort, hipStream_t s,
+                        int grow_id, int32_t **grown) {
+  const int nq = kind == 0 ? sc->n_vert : sc->n_edge;
+  const int ni = kind == 0 ? sc->n_face : sc->n_edge;
+  *n_out = 0;
+  if (nq == 0 || ni == 0) return EIPC_OK;
+  const double h = 0.5 * dhat;
+  double *qbox, *ibox;
+  EIPC_TRY(ensure_t(c, B_QBOX, (size_t)6 * nq, &qbox));
+  if (kind == 0) {
+    EIPC_TRY(ensure_t(c, B_IBOX, (size_t)6 * ni, &ibox));
+    k_boxes<1><<<grid_for(nq, 256), 256, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, qbox);
+    k_boxes<3><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->faces, xs, x1s, sc->n_vert, h, ibox);
+  } else {
+    ibox = qbox;
+    k_boxes<2><<<grid_for(nq, 256), 256, 0, s>>>(nq, sc->edges, xs, x1s, sc->n_vert, h, qbox);
+  }
+  EIPC_HIP(c, hipGetLastError());
+  uint64_t *st = (uint64_t *)c->stats;
+  k_stats_init<<<1, 64, 0, s>>>(st);
+  k_box_stats<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, st, 1);
+  if (kind == 0) k_box_stats<<<grid_for(nq, 256), 256, 0, s>>>(nq, qbox, st, 0);
+  EIPC_HIP(c, hipGetLastError());
+  uint64_t hs[9];
+  EIPC_HIP(c, hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  double lo[3], hi[3], ext[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ord_dec(hs[a]);
+    hi[a] = ord_dec(hs[3 + a]);
+    std::memcpy(&ext[a], &hs[6 + a], 8);
+  }
+  if (!(std::isfinite(lo[0]) && std::isfinite(lo[1]) && std::isfinite(lo[2]) && std::isfinite(hi[0]) &&
+        std::isfinite(hi[1]) && std::isfinite(hi[2])))
+    return set_err(c, EIPC_ERR_NONFINITE, "non-finite primitive boxes");
+  // cell edge: the mean item box extent (largest axis of the mean)
+  double cell = std::max(ext[0], std::max(ext[1], ext[2])) / ni;
+  double span = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+  cell = std::max(cell, span * 1e-6);
+  if (!(cell > 0)) cell = 1.0;
+  GridDev g;
+  for (int a = 0; a < 3; ++a) g.o[a] = lo[a];
+  for (;;) {
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      double d = std::floor((hi[a] - lo[a]) / cell) + 1.0;
+      if (d > (double)(1 << 20)) ok = false;
+      g.dim[a] = (int)std::min(d, (double)(1 << 20));
+    }
+    if (ok) break;
+    cell *= 2.0;
+  }
+  g.inv_h = 1.0 / cell;
+  // item cell counts
+  int32_t *cnt, *large;
+  int64_t *cell_off;
+  EIPC_TRY(ensure_t(c, B_CELLCNT, (size_t)ni, &cnt));
+  EIPC_TRY(ensure_t(c, B_LARGE, (size_t)ni, &large));
+  EIPC_TRY(ensure_t(c, B_CELLOFF, (size_t)ni + 1, &cell_off));
+  EIPC_TRY(launch_zero(c, c->counters, 16 * sizeof(int64_t), s));
+  g.bmask = 0;
+  g.bstart = nullptr;
+  g.ent_cell = nullptr;
+  g.ent_item = nullptr;
+  g.large = large;
+  g.n_large = 0;
+  k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, g, cnt, large, c->counters);
+  EIPC_HIP(c, hipGetLastError());
+  EIPC_TRY(exclusive_scan(c, cnt, ni, cell_off, s));
+  int64_t hv[2];
+  EIPC_HIP(c, hipMemcpyAsync(&hv[0], cell_off + ni, 8, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipMemcpyAsync(&hv[1], c->counters, 8, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  const int64_t n_ent = hv[0];
+  g.n_large = (int)hv[1];
+  const uint32_t nb = next_pow2((uint64_t)std::max<int64_t>(2 * n_ent, 1024));
+  g.bmask = nb - 1;
+  int32_t *bcnt, *bfill;
+  int64_t *bstart;
+  uint64_t *ent_cell;
+  int32_t *ent_item;
+  EIPC_TRY(ensure_t(c, B_BCNT, nb, &bcnt));
+  EIPC_TRY(ensure_t(c, B_BFILL, nb, &bfill));
+  EIPC_TRY(ensure_t(c, B_BSTART, (size_t)nb + 1, &bstart));
+  EIPC_TRY(ensure_t(c, B_ENTCELL, (size_t)std::max<int64_t>(n_ent, 1), &ent_cell));
+  EIPC_TRY(ensure_t(c, B_ENTITEM, (size_t)std::max<int64_t>(n_ent, 1), &ent_item));
+  EIPC_TRY(launch_zero(c, bcnt, sizeof(int32_t) * nb, s));
+  EIPC_TRY(launch_zero(c, bfill, sizeof(int32_t) * nb, s));
+  k_item_hist<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, g, cnt, bcnt);
+  EIPC_HIP(c, hipGetLastError());
+  EIPC_TRY(exclusive_scan(c, bcnt, nb, bstart, s));
+  g.bstart = bstart;
+  k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, g, cnt, bfill, ent_cell, ent_item);
+  EIPC_HIP(c, hipGetLastError());
+  g.ent_cell = ent_cell;
+  g.ent_item = ent_item;
+  // query: count, scan, write
+  int32_t *qcnt;
+  int64_t *qoff;
+  EIPC_TRY(ensure_t(c, B_QCNT, (size_t)nq, &qcnt));
+  EIPC_TRY(ensure_t(c, B_QOFF, (size_t)nq + 1, &qoff));
+  if (kind == 0)
+    k_query<0><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
+                                                  nullptr, nullptr, 0, 0);
+  else
+    k_query<1><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
+                                                  nullptr, nullptr, 0, 0);
+  EIPC_HIP(c, hipGetLastError());
+  EIPC_TRY(exclusive_scan(c, qcnt, nq, qoff, s));
+  int64_t total = 0;
+  EIPC_HIP(c, hipMemcpyAsync(&total, qoff + nq, 8, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  *n_out = total;
+  if (grow_id >= 0) {
+    EIPC_TRY(ensure_t(c, (BufId)grow_id, (size_t)std::max<int64_t>(2 * total, 2), &out));
+    cap = total;
+    *grown = out;
+  }
+  if (total > cap || out == nullptr) return total > cap ? EIPC_ERR_CAPACITY : EIPC_OK;
+  if (total == 0) return EIPC_OK;
+  if (kind == 0)
+    k_query<0><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
+                                                  qoff, out, 1, sort);
+  else
+    k_query<1><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
+                                                  qoff, out, 1, sort);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// narrow phase: distance type and d^2 per candidate; active (0 < d < dhat)
+// pairs compacted with a wavefront ballot and one atomic per wavefront.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ void pair_vids(const int32_t *pairs, int64_t k, const int32_t *faces,
+                                          const int32_t *edges, int *vid) {
+  const int a = pairs[2 * k], b = pairs[2 * k + 1];
+  if (KIND == 0) {
+    vid[0] = a;
+    vid[1] = faces[3 * (int64_t)b];
+    vid[2] = faces[3 * (int64_t)b + 1];
+    vid[3] = faces[3 * (int64_t)b + 2];
+  } else {
+    vid[0] = edges[2 * (int64_t)a];
+    vid[1] = edges[2 * (int64_t)a + 1];
+    vid[2] = edges[2 * (int64_t)b];
+    vid[3] = edges[2 * (int64_t)b + 1];
+  }
+}
+
+template <int KIND>
+__global__ void k_narrow(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
+                         const int32_t *__restrict__ edges, const double *__restrict__ xs, int n_vert, double dhat2,
+                         int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t *count, uint32_t *status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool active = false;
+  int ty = 0;
+  if (i < n) {
+    int vid[4];
+    pair_vids<KIND>(pairs, i, faces, edges, vid);
+    V3 x[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] = V3{xs[vid[a]], xs[n_vert + vid[a]], xs[2 * (int64_t)n_vert + vid[a]]};
+    double s2 = pair_dist2<KIND>(x, &ty);
+    if (!isfinite(s2)) {
+      atomicOr(status, ST_NONFINITE);
+    } else if (s2 < dhat2) {
+      if (s2 <= 0.0)
+        atomicOr(status, ST_INTERSECTING);
+      else
+        active = true;
+    }
+  }
+  const uint64_t mask = __ballot(active);
+  const int lane = threadIdx.x & 63;
+  int64_t base = 0;
+  if (lane == 0 && mask) base = (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(mask));
+  base = __shfl(base, 0, 64);
+  if (active) {
+    const int64_t pos = base + __popcll(mask & ((1ull << lane) - 1ull));
+    act[pos] = (int32_t)i;
+    typ[pos] = ty;
+  }
+}
+
+eipc_status launch_narrow(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                          int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  const double d2 = dhat * dhat;
+  if (kind == 0)
+    k_narrow<0><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ,
+                                                  d_count, c->status);
+  else
+    k_narrow<1><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ,
+                                                  d_count, c->status);
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
+}  // namespace eipc

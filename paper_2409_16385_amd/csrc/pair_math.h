@@ -1,0 +1,723 @@
+// Per-pair device math for the contact stage (gfx950, FP64).
+//
+// Two kinds of code live here:
+//  * exact code (embedding sums, boxes, distance classification and the
+//    squared-distance value, the CCD advancement loop) is compiled with
+//    contraction off so each expression is one rounded operation per
+//    operator, evaluated as written;
+//  * derivative code (distance derivatives, barrier chain rule, mollifier,
+//    the 9x9 eigen-projection) lets the compiler fuse multiply-adds.
+//
+// A pair has four vertex slots: PT (p, t0, t1, t2), EE (a0, a1, b0, b1).
+// All pair quantities are translation invariant, so derivatives are taken in
+// a 9-dimensional basis of difference vectors
+//   PT: Y = (p - t0, t1 - t0, t2 - t0),   EE: Y = (a0 - b0, a1 - a0, b1 - b0)
+// and the 12x12 Hessian is H_x = T^T H_Y T with T the fixed 9x12 difference
+// map.  Its PSD projection is taken in an orthonormal basis Q (12x9, entries
+// +-1/2, Hadamard columns orthogonal to translations):
+//   P_x = Q proj(Q^T H_x Q) Q^T,   Q^T H_x Q = G^T H_Y G,  G = T Q.
+// Since H_x vanishes on translations this equals the projection of the full
+// 12x12 matrix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eipc {
+
+struct V3 {
+  double x, y, z;
+};
+
+// ---------------------------------------------------------------------------
+// exact helpers (contraction off)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ V3 xsub(V3 a, V3 b) {
+#pragma clang fp contract(off)
+  return V3{a.x - b.x, a.y - b.y, a.z - b.z};
+}
+__device__ __forceinline__ double xdot(V3 a, V3 b) {
+#pragma clang fp contract(off)
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+__device__ __forceinline__ V3 xcross(V3 a, V3 b) {
+#pragma clang fp contract(off)
+  return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// ---------------------------------------------------------------------------
+// distance types and their canonical squared-distance formulas
+//   PP      s = r.r                r = x[plus0] - x[minus0]
+//   PL      s = |r x e|^2 / e.e    r = x[plus0]-x[minus0], e = x[plus1]-x[minus1]
+//   TRIPLE  s = (y0.(y1 x y2))^2 / |y1 x y2|^2,  y_j = x[plus_j] - x[minus_j]
+// ---------------------------------------------------------------------------
+enum { PT_T0 = 0, PT_T1, PT_T2, PT_E0, PT_E1, PT_E2, PT_T };
+enum { EE_A0B0 = 0, EE_A0B1, EE_A1B0, EE_A1B1, EE_AB0, EE_AB1, EE_A0B, EE_A1B, EE_AB };
+enum { FN_PP = 0, FN_PL = 1, FN_TRI = 2 };
+
+struct TypeDef {
+  int fn, m;
+  int plus[3], minus[3];
+  int c[3][3];  // local vector j as an integer combination of the Y basis
+};
+
+// PT slots p=0, t0=1, t1=2, t2=3;  Y = (p-t0, t1-t0, t2-t0)
+constexpr TypeDef kPT[7] = {
+    {FN_PP, 1, {0, 0, 0}, {1, 0, 0}, {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}}},       // p - t0
+    {FN_PP, 1, {0, 0, 0}, {2, 0, 0}, {{1, -1, 0}, {0, 0, 0}, {0, 0, 0}}},      // p - t1
+    {FN_PP, 1, {0, 0, 0}, {3, 0, 0}, {{1, 0, -1}, {0, 0, 0}, {0, 0, 0}}},      // p - t2
+    {FN_PL, 2, {0, 2, 0}, {1, 1, 0}, {{1, 0, 0}, {0, 1, 0}, {0, 0, 0}}},       // p on t0t1
+    {FN_PL, 2, {0, 3, 0}, {2, 2, 0}, {{1, -1, 0}, {0, -1, 1}, {0, 0, 0}}},     // p on t1t2
+    {FN_PL, 2, {0, 1, 0}, {3, 3, 0}, {{1, 0, -1}, {0, 0, -1}, {0, 0, 0}}},     // p on t2t0
+    {FN_TRI, 3, {0, 2, 3}, {1, 1, 1}, {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}},      // interior
+};
+// EE slots a0=0, a1=1, b0=2, b1=3;  Y = (a0-b0, a1-a0, b1-b0)
+constexpr TypeDef kEE[9] = {
+    {FN_PP, 1, {0, 0, 0}, {2, 0, 0}, {{1, 0, 0}, {0, 0, 0}, {0, 0, 0}}},       // a0 - b0
+    {FN_PP, 1, {0, 0, 0}, {3, 0, 0}, {{1, 0, -1}, {0, 0, 0}, {0, 0, 0}}},      // a0 - b1
+    {FN_PP, 1, {1, 0, 0}, {2, 0, 0}, {{1, 1, 0}, {0, 0, 0}, {0, 0, 0}}},       // a1 - b0
+    {FN_PP, 1, {1, 0, 0}, {3, 0, 0}, {{1, 1, -1}, {0, 0, 0}, {0, 0, 0}}},      // a1 - b1
+    {FN_PL, 2, {2, 1, 0}, {0, 0, 0}, {{-1, 0, 0}, {0, 1, 0}, {0, 0, 0}}},      // b0 on a
+    {FN_PL, 2, {3, 1, 0}, {0, 0, 0}, {{-1, 0, 1}, {0, 1, 0}, {0, 0, 0}}},      // b1 on a
+    {FN_PL, 2, {0, 3, 0}, {2, 2, 0}, {{1, 0, 0}, {0, 0, 1}, {0, 0, 0}}},       // a0 on b
+    {FN_PL, 2, {1, 3, 0}, {2, 2, 0}, {{1, 1, 0}, {0, 0, 1}, {0, 0, 0}}},       // a1 on b
+    {FN_TRI, 3, {0, 1, 3}, {2, 0, 2}, {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}},      // interior
+};
+
+// T: rows of the Y basis over the 4 slots; S: 2*Q (Hadamard signs), Q = S/2
+constexpr int kT[2][3][4] = {{{1, -1, 0, 0}, {0, -1, 1, 0}, {0, -1, 0, 1}},
+                                        {{1, 0, -1, 0}, {-1, 1, 0, 0}, {0, 0, -1, 1}}};
+constexpr int kS[4][3] = {{1, 1, 1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
+// G = T Q: G[J][alpha] = (1/2) sum_a T[J][a] S[a][alpha] (integers)
+__host__ __device__ constexpr int gcoef(int kind, int J, int al) {
+  return (kT[kind][J][0] * kS[0][al] + kT[kind][J][1] * kS[1][al] + kT[kind][J][2] * kS[2][al] +
+          kT[kind][J][3] * kS[3][al]) /
+         2;
+}
+
+template <int KIND, int TYPE>
+__host__ __device__ constexpr TypeDef type_def() {
+  if constexpr (KIND == 0)
+    return kPT[TYPE];
+  else
+    return kEE[TYPE];
+}
+
+template <int KIND, int TYPE>
+__device__ __forceinline__ double type_value_t(const V3 *x) {
+#pragma clang fp contract(off)
+  constexpr TypeDef t = type_def<KIND, TYPE>();
+  V3 y0 = xsub(x[t.plus[0]], x[t.minus[0]]);
+  if constexpr (t.fn == FN_PP) {
+    return xdot(y0, y0);
+  } else if constexpr (t.fn == FN_PL) {
+    V3 y1 = xsub(x[t.plus[1]], x[t.minus[1]]);
+    V3 c = xcross(y0, y1);
+    return xdot(c, c) / xdot(y1, y1);
+  } else {
+    V3 y1 = xsub(x[t.plus[1]], x[t.minus[1]]);
+    V3 y2 = xsub(x[t.plus[2]], x[t.minus[2]]);
+    V3 n = xcross(y1, y2);
+    double N = xdot(y0, n);
+    return (N * N) / xdot(n, n);
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ double type_value(int type, const V3 *x) {
+  if constexpr (KIND == 0) {
+    switch (type) {
+      case 0: return type_value_t<0, 0>(x);
+      case 1: return type_value_t<0, 1>(x);
+      case 2: return type_value_t<0, 2>(x);
+      case 3: return type_value_t<0, 3>(x);
+      case 4: return type_value_t<0, 4>(x);
+      case 5: return type_value_t<0, 5>(x);
+      default: return type_value_t<0, 6>(x);
+    }
+  } else {
+    switch (type) {
+      case 0: return type_value_t<1, 0>(x);
+      case 1: return type_value_t<1, 1>(x);
+      case 2: return type_value_t<1, 2>(x);
+      case 3: return type_value_t<1, 3>(x);
+      case 4: return type_value_t<1, 4>(x);
+      case 5: return type_value_t<1, 5>(x);
+      case 6: return type_value_t<1, 6>(x);
+      case 7: return type_value_t<1, 7>(x);
+      default: return type_value_t<1, 8>(x);
+    }
+  }
+}
+
+// point-segment sub-feature: 0 endpoint a, 1 endpoint b, 2 interior
+__device__ __forceinline__ int point_segment(V3 p, V3 a, V3 b) {
+#pragma clang fp contract(off)
+  V3 r = xsub(p, a);
+  V3 e = xsub(b, a);
+  double t = xdot(r, e);
+  if (t <= 0.0) return 0;
+  double ee = xdot(e, e);
+  if (t >= ee) return 1;
+  return 2;
+}
+
+// PT: interior when the plane projection is strictly inside (Cramer
+// numerators against det = |n|^2); else the closest point-segment feature
+// over edges t0t1, t1t2, t2t0 (first strict minimum wins).
+__device__ __forceinline__ int pt_type(const V3 *x) {
+#pragma clang fp contract(off)
+  V3 e0 = xsub(x[2], x[1]);
+  V3 e1 = xsub(x[3], x[1]);
+  V3 r = xsub(x[0], x[1]);
+  V3 n = xcross(e0, e1);
+  double det = xdot(n, n);
+  if (det > 0.0) {
+    double a = xdot(e0, e0), b = xdot(e0, e1), c = xdot(e1, e1);
+    double d0 = xdot(e0, r), d1 = xdot(e1, r);
+    double un = c * d0 - b * d1;
+    double vn = a * d1 - b * d0;
+    if (un > 0.0 && vn > 0.0 && un + vn < det) return PT_T;
+  }
+  int best = 0;
+  double bs = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int ia = 1 + k, ib = 1 + (k + 1) % 3;
+    int sub = point_segment(x[0], x[ia], x[ib]);
+    int ty = sub == 0 ? (ia - 1) : (sub == 1 ? (ib - 1) : PT_E0 + k);
+    double s = type_value<0>(ty, x);
+    if (k == 0 || s < bs) {
+      best = ty;
+      bs = s;
+    }
+  }
+  return best;
+}
+
+// EE: interior-interior when not near-parallel (|u x v|^2 > 1e-20 |u|^2
+// |v|^2) and both line parameters lie strictly inside (0, 1); else the
+// closest endpoint-segment feature in order a0|b, a1|b, b0|a, b1|a.
+__device__ __forceinline__ int ee_type(const V3 *x) {
+#pragma clang fp contract(off)
+  V3 u = xsub(x[1], x[0]);
+  V3 v = xsub(x[3], x[2]);
+  V3 w = xsub(x[0], x[2]);
+  V3 n = xcross(u, v);
+  double D = xdot(n, n);
+  double a = xdot(u, u), c = xdot(v, v);
+  if (D > 1e-20 * a * c) {
+    double b = xdot(u, v), d = xdot(u, w), e = xdot(v, w);
+    double sn = b * e - c * d;
+    double tn = a * e - b * d;
+    if (sn > 0.0 && sn < D && tn > 0.0 && tn < D) return EE_AB;
+  }
+  constexpr int pslot[4] = {0, 1, 2, 3};
+  constexpr int sa[4] = {2, 2, 0, 0};
+  constexpr int sb[4] = {3, 3, 1, 1};
+  constexpr int ty[4][3] = {{EE_A0B0, EE_A0B1, EE_A0B},
+                            {EE_A1B0, EE_A1B1, EE_A1B},
+                            {EE_A0B0, EE_A1B0, EE_AB0},
+                            {EE_A0B1, EE_A1B1, EE_AB1}};
+  int best = 0;
+  double bs = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int sub = point_segment(x[pslot[k]], x[sa[k]], x[sb[k]]);
+    int t = ty[k][sub];
+    double s = type_value<1>(t, x);
+    if (k == 0 || s < bs) {
+      best = t;
+      bs = s;
+    }
+  }
+  return best;
+}
+
+template <int KIND>
+__device__ __forceinline__ int classify(const V3 *x) {
+  if constexpr (KIND == 0)
+    return pt_type(x);
+  else
+    return ee_type(x);
+}
+
+template <int KIND>
+__device__ __forceinline__ double pair_dist2(const V3 *x, int *type_out) {
+  int t = classify<KIND>(x);
+  *type_out = t;
+  return type_value<KIND>(t, x);
+}
+
+// ---------------------------------------------------------------------------
+// symmetric 9x9 in packed upper storage
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int pidx(int i, int j) {
+  return i <= j ? i * 9 - (i * (i - 1)) / 2 + (j - i) : j * 9 - (j * (j - 1)) / 2 + (i - j);
+}
+
+__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ double comp(V3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+__device__ __forceinline__ V3 lin(int c0, V3 a, int c1, V3 b, int c2, V3 c) {
+  V3 r{0.0, 0.0, 0.0};
+  if (c0) { r.x += c0 * a.x; r.y += c0 * a.y; r.z += c0 * a.z; }
+  if (c1) { r.x += c1 * b.x; r.y += c1 * b.y; r.z += c1 * b.z; }
+  if (c2) { r.x += c2 * c.x; r.y += c2 * c.y; r.z += c2 * c.z; }
+  return r;
+}
+
+// Local derivatives of s for a type in its own local vectors y_0..y_{m-1}:
+// gl[3m], Hl[3m][3m] (full, row-major, stride 9).
+//   PP:  s = y.y
+//   PL:  s = N/D, N = |r x e|^2, D = e.e
+//   TRI: s = N^2/D, N = y0.(y1 x y2), D = |y1 x y2|^2
+// via  grad s = fN gN + fD gD,
+//      hess s = fNN gN gN^T + fND (gN gD^T + gD gN^T) + fDD gD gD^T + fN HN + fD HD.
+struct Local {
+  double g[9];
+  double H[81];
+};
+
+__device__ __forceinline__ void skew_into(double *H, int r0, int c0, V3 a, double sgn) {
+  // H[r0+i][c0+j] += sgn * [a]_x[i][j]
+  H[(r0 + 0) * 9 + c0 + 1] += -sgn * a.z;
+  H[(r0 + 0) * 9 + c0 + 2] += sgn * a.y;
+  H[(r0 + 1) * 9 + c0 + 0] += sgn * a.z;
+  H[(r0 + 1) * 9 + c0 + 2] += -sgn * a.x;
+  H[(r0 + 2) * 9 + c0 + 0] += -sgn * a.y;
+  H[(r0 + 2) * 9 + c0 + 1] += sgn * a.x;
+}
+
+// |y1 x y2|^2: gradient into g[o1..], g[o2..] and Hessian blocks into H.
+__device__ __forceinline__ double crossnorm2(V3 y1, V3 y2, int o1, int o2, double *g, double *H) {
+  V3 n = cross(y1, y2);
+  V3 t1 = cross(y2, n), t2 = cross(n, y1);
+  g[o1 + 0] = 2.0 * t1.x; g[o1 + 1] = 2.0 * t1.y; g[o1 + 2] = 2.0 * t1.z;
+  g[o2 + 0] = 2.0 * t2.x; g[o2 + 1] = 2.0 * t2.y; g[o2 + 2] = 2.0 * t2.z;
+  double a11 = dot(y1, y1), a22 = dot(y2, y2), a12 = dot(y1, y2);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double id = (i == j) ? 1.0 : 0.0;
+      H[(o1 + i) * 9 + o1 + j] = 2.0 * (a22 * id - comp(y2, i) * comp(y2, j));
+      H[(o2 + i) * 9 + o2 + j] = 2.0 * (a11 * id - comp(y1, i) * comp(y1, j));
+      double c = 4.0 * comp(y1, i) * comp(y2, j) - 2.0 * comp(y2, i) * comp(y1, j) - 2.0 * a12 * id;
+      H[(o1 + i) * 9 + o2 + j] = c;
+      H[(o2 + j) * 9 + o1 + i] = c;
+    }
+  return dot(n, n);
+}
+
+template <int FN>
+__device__ __forceinline__ void local_derivs(const V3 *y, Local &L) {
+#pragma unroll
+  for (int i = 0; i < 81; ++i) L.H[i] = 0.0;
+  if constexpr (FN == FN_PP) {
+    L.g[0] = 2.0 * y[0].x; L.g[1] = 2.0 * y[0].y; L.g[2] = 2.0 * y[0].z;
+    L.H[0] = 2.0; L.H[10] = 2.0; L.H[20] = 2.0;
+    return;
+  } else {
+    constexpr int nl = FN == FN_PL ? 6 : 9;
+    double gN[9] = {0}, gD[9] = {0}, HN[81], HD[81];
+#pragma unroll
+    for (int i = 0; i < 81; ++i) { HN[i] = 0.0; HD[i] = 0.0; }
+    double N, D, fN, fD, fNN, fND, fDD;
+    if constexpr (FN == FN_PL) {
+      N = crossnorm2(y[0], y[1], 0, 3, gN, HN);
+      D = dot(y[1], y[1]);
+      gD[3] = 2.0 * y[1].x; gD[4] = 2.0 * y[1].y; gD[5] = 2.0 * y[1].z;
+      HD[3 * 9 + 3] = 2.0; HD[4 * 9 + 4] = 2.0; HD[5 * 9 + 5] = 2.0;
+      double iD = 1.0 / D;
+      fN = iD;
+      fD = -N * iD * iD;
+      fNN = 0.0;
+      fND = -iD * iD;
+      fDD = 2.0 * N * iD * iD * iD;
+    } else {
+      V3 n = cross(y[1], y[2]);
+      V3 c20 = cross(y[2], y[0]), c01 = cross(y[0], y[1]);
+      N = dot(y[0], n);
+      gN[0] = n.x; gN[1] = n.y; gN[2] = n.z;
+      gN[3] = c20.x; gN[4] = c20.y; gN[5] = c20.z;
+      gN[6] = c01.x; gN[7] = c01.y; gN[8] = c01.z;
+      skew_into(HN, 0, 3, y[2], -1.0);
+      skew_into(HN, 0, 6, y[1], 1.0);
+      skew_into(HN, 3, 6, y[0], -1.0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = 0; j < i; ++j) HN[i * 9 + j] = HN[j * 9 + i];
+      D = crossnorm2(y[1], y[2], 3, 6, gD, HD);
+      double iD = 1.0 / D;
+      fN = 2.0 * N * iD;
+      fD = -(N * N) * iD * iD;
+      fNN = 2.0 * iD;
+      fND = -2.0 * N * iD * iD;
+      fDD = 2.0 * (N * N) * iD * iD * iD;
+    }
+#pragma unroll
+    for (int i = 0; i < nl; ++i) L.g[i] = fN * gN[i] + fD * gD[i];
+#pragma unroll
+    for (int i = 0; i < nl; ++i)
+#pragma unroll
+      for (int j = 0; j < nl; ++j)
+        L.H[i * 9 + j] = fNN * gN[i] * gN[j] + fND * (gN[i] * gD[j] + gD[i] * gN[j]) + fDD * gD[i] * gD[j] +
+                         fN * HN[i * 9 + j] + fD * HD[i * 9 + j];
+  }
+}
+
+// s-derivatives of one type mapped to the Y basis: gY[9], HY packed[45].
+template <int KIND, int TYPE>
+__device__ __forceinline__ void s_derivs_typed(const V3 *Y, double *gY, double *HY) {
+  constexpr TypeDef t = type_def<KIND, TYPE>();
+  V3 y[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) y[j] = (j < t.m) ? lin(t.c[j][0], Y[0], t.c[j][1], Y[1], t.c[j][2], Y[2]) : V3{0, 0, 0};
+  Local L;
+  local_derivs<t.fn>(y, L);
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < t.m; ++j)
+        if (t.c[j][J] != 0) acc += t.c[j][J] * L.g[3 * j + i];
+      gY[3 * J + i] = acc;
+    }
+#pragma unroll
+  for (int J = 0; J < 3; ++J)
+#pragma unroll
+    for (int K = J; K < 3; ++K)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          if (J == K && l < i) continue;
+          double acc = 0.0;
+#pragma unroll
+          for (int j = 0; j < t.m; ++j)
+#pragma unroll
+            for (int k = 0; k < t.m; ++k)
+              if (t.c[j][J] != 0 && t.c[k][K] != 0) acc += (t.c[j][J] * t.c[k][K]) * L.H[(3 * j + i) * 9 + 3 * k + l];
+          HY[pidx(3 * J + i, 3 * K + l)] = acc;
+        }
+}
+
+template <int KIND>
+__device__ __noinline__ void s_derivs(int type, const V3 *Y, double *gY, double *HY) {
+  if constexpr (KIND == 0) {
+    switch (type) {
+      case 0: s_derivs_typed<0, 0>(Y, gY, HY); break;
+      case 1: s_derivs_typed<0, 1>(Y, gY, HY); break;
+      case 2: s_derivs_typed<0, 2>(Y, gY, HY); break;
+      case 3: s_derivs_typed<0, 3>(Y, gY, HY); break;
+      case 4: s_derivs_typed<0, 4>(Y, gY, HY); break;
+      case 5: s_derivs_typed<0, 5>(Y, gY, HY); break;
+      default: s_derivs_typed<0, 6>(Y, gY, HY); break;
+    }
+  } else {
+    switch (type) {
+      case 0: s_derivs_typed<1, 0>(Y, gY, HY); break;
+      case 1: s_derivs_typed<1, 1>(Y, gY, HY); break;
+      case 2: s_derivs_typed<1, 2>(Y, gY, HY); break;
+      case 3: s_derivs_typed<1, 3>(Y, gY, HY); break;
+      case 4: s_derivs_typed<1, 4>(Y, gY, HY); break;
+      case 5: s_derivs_typed<1, 5>(Y, gY, HY); break;
+      case 6: s_derivs_typed<1, 6>(Y, gY, HY); break;
+      case 7: s_derivs_typed<1, 7>(Y, gY, HY); break;
+      default: s_derivs_typed<1, 8>(Y, gY, HY); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// barrier (Eq. 7) as a function of s = d^2:  bt(s) = b(sqrt(s))
+//   b   = -(d - dhat)^2 ln(d/dhat)
+//   b'  = -2 (d - dhat) ln(d/dhat) - (d - dhat)^2 / d
+//   b'' = -2 ln(d/dhat) - 4 (d - dhat)/d + (d - dhat)^2/d^2
+//   bt' = b'/(2d),  bt'' = (b'' - b'/d) / (4 s)
+// ---------------------------------------------------------------------------
+struct Barrier {
+  double b, bs1, bs2;
+};
+__device__ __forceinline__ Barrier barrier_s(double s, double dhat) {
+  double d = sqrt(s);
+  double lr = log(d / dhat);
+  double dm = d - dhat;
+  double id = 1.0 / d;
+  double b = -(dm * dm) * lr;
+  double b1 = -2.0 * dm * lr - (dm * dm) * id;
+  double b2 = -2.0 * lr - 4.0 * dm * id + (dm * dm) * id * id;
+  Barrier r;
+  r.b = b;
+  r.bs1 = 0.5 * b1 * id;
+  r.bs2 = (b2 - b1 * id) * (0.25 / s);
+  return r;
+}
+
+// Energy derivatives in the Y basis: e = kappa m(c) bt(s) (m = 1 without
+// mollifier).  gE[9], HE packed [45].  eps_x <= 0 disables the mollifier.
+// Returns the energy.
+template <int KIND>
+__device__ __forceinline__ double energy_derivs(int type, const V3 *Y, double s, double dhat, double kappa,
+                                                double eps_x, double *gE, double *HE, bool want_h) {
+  double gs[9], Hs[45];
+  s_derivs<KIND>(type, Y, gs, Hs);
+  Barrier br = barrier_s(s, dhat);
+  double m = 1.0, m1 = 0.0, m2 = 0.0;
+  double gc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double Hc[81];
+  bool moll = false;
+  if constexpr (KIND == 1) {
+    if (eps_x > 0.0) {
+      V3 n = cross(Y[1], Y[2]);
+      double c = dot(n, n);
+      if (c < eps_x) {
+        moll = true;
+        double r = c / eps_x;
+        m = (2.0 - r) * r;
+        m1 = (2.0 - 2.0 * r) / eps_x;
+        m2 = -2.0 / (eps_x * eps_x);
+#pragma unroll
+        for (int i = 0; i < 81; ++i) Hc[i] = 0.0;
+        crossnorm2(Y[1], Y[2], 3, 6, gc, Hc);
+      }
+    }
+  }
+  double e = kappa * (m * br.b);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    double gb = br.bs1 * gs[i];
+    gE[i] = kappa * (moll ? (m * gb + br.b * m1 * gc[i]) : gb);
+  }
+  if (want_h) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+      for (int j = i; j < 9; ++j) {
+        double hb = br.bs2 * gs[i] * gs[j] + br.bs1 * Hs[pidx(i, j)];
+        double h = hb;
+        if (moll) {
+          double gbi = br.bs1 * gs[i], gbj = br.bs1 * gs[j];
+          h = m * hb + m1 * (gbi * gc[j] + gc[i] * gbj) + br.b * (m2 * gc[i] * gc[j] + m1 * Hc[i * 9 + j]);
+        }
+        HE[pidx(i, j)] = kappa * h;
+      }
+  }
+  return e;
+}
+
+// M = G^T H G (packed), G = (T Q) (x) I3 with integer entries gcoef.
+template <int KIND>
+__device__ __forceinline__ void to_q_basis(const double *H, double *M) {
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int be = al; be < 3; ++be)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (al == be && j < i) continue;
+          double acc = 0.0;
+#pragma unroll
+          for (int J = 0; J < 3; ++J)
+#pragma unroll
+            for (int K = 0; K < 3; ++K) {
+              const int c = gcoef(KIND, J, al) * gcoef(KIND, K, be);
+              if (c != 0) acc += c * H[pidx(3 * J + i, 3 * K + j)];
+            }
+          M[pidx(3 * al + i, 3 * be + j)] = acc;
+        }
+}
+
+// One Jacobi rotation zeroing a[p][q]; V accumulates the rotations.
+template <int P, int Q>
+__device__ __forceinline__ void jacobi_rot(double *a, double *v) {
+  const double apq = a[pidx(P, Q)];
+  const double app = a[pidx(P, P)];
+  const double aqq = a[pidx(Q, Q)];
+  const double h = 0.5 * (aqq - app);
+  const double r = sqrt(h * h + apq * apq);
+  const double den = h >= 0.0 ? h + r : h - r;
+  const double t = (apq == 0.0) ? 0.0 : apq / den;
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = t * c;
+  a[pidx(P, P)] = app - t * apq;
+  a[pidx(Q, Q)] = aqq + t * apq;
+  a[pidx(P, Q)] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k == P || k == Q) continue;
+    const double akp = a[pidx(k, P)], akq = a[pidx(k, Q)];
+    a[pidx(k, P)] = c * akp - s * akq;
+    a[pidx(k, Q)] = s * akp + c * akq;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double vkp = v[k * 9 + P], vkq = v[k * 9 + Q];
+    v[k * 9 + P] = c * vkp - s * vkq;
+    v[k * 9 + Q] = s * vkp + c * vkq;
+  }
+}
+
+template <int P, int Q>
+__device__ __forceinline__ void jacobi_sweep_from(double *a, double *v) {
+  if constexpr (P < 8) {
+    jacobi_rot<P, Q>(a, v);
+    if constexpr (Q + 1 < 9)
+      jacobi_sweep_from<P, Q + 1>(a, v);
+    else if constexpr (P + 2 < 9)
+      jacobi_sweep_from<P + 1, P + 2>(a, v);
+  }
+}
+
+// In place: a <- V max(L, 0) V^T, cyclic Jacobi until the off-diagonal mass
+// is below 1e-30 of the total (relative off-norm 1e-15), at most 16 sweeps.
+// The loop count is uniform over the wavefront.
+__device__ __forceinline__ void project_psd9(double *a) {
+  double v[81];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) v[i * 9 + j] = (i == j) ? 1.0 : 0.0;
+  double fro2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = i; j < 9; ++j) fro2 += (i == j ? 1.0 : 2.0) * a[pidx(i, j)] * a[pidx(i, j)];
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    double off = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 9; ++j) off += a[pidx(i, j)] * a[pidx(i, j)];
+    const bool done = !(off > 1e-30 * fro2);
+    if (__all(done)) break;
+    jacobi_sweep_from<0, 1>(a, v);
+  }
+  double lam[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) lam[k] = fmax(a[pidx(k, k)], 0.0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = i; j < 9; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc += v[i * 9 + k] * lam[k] * v[j * 9 + k];
+      a[pidx(i, j)] = acc;
+    }
+}
+
+// 3x3 block (a, b) of H_x = Q X Q^T from X packed in the Q basis.
+__device__ __forceinline__ void x_block(const double *X, int a, int b, double *B) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int be = 0; be < 3; ++be) {
+          const double x = X[pidx(3 * al + i, 3 * be + j)];
+          acc += (kS[a][al] * kS[b][be] > 0) ? x : -x;
+        }
+      B[i * 3 + j] = 0.25 * acc;
+    }
+}
+
+// gradient over the 4 slots from the Y basis: g_x[a] = sum_J T[J][a] gY[J]
+template <int KIND>
+__device__ __forceinline__ void slot_grad(const double *gY, double *gx) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int J = 0; J < 3; ++J)
+        if (kT[KIND][J][a] != 0) acc += kT[KIND][J][a] * gY[3 * J + i];
+      gx[3 * a + i] = acc;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void y_basis(const V3 *x, V3 *Y) {
+  if constexpr (KIND == 0) {
+    Y[0] = V3{x[0].x - x[1].x, x[0].y - x[1].y, x[0].z - x[1].z};
+    Y[1] = V3{x[2].x - x[1].x, x[2].y - x[1].y, x[2].z - x[1].z};
+    Y[2] = V3{x[3].x - x[1].x, x[3].y - x[1].y, x[3].z - x[1].z};
+  } else {
+    Y[0] = V3{x[0].x - x[2].x, x[0].y - x[2].y, x[0].z - x[2].z};
+    Y[1] = V3{x[1].x - x[0].x, x[1].y - x[0].y, x[1].z - x[0].z};
+    Y[2] = V3{x[3].x - x[2].x, x[3].y - x[2].y, x[3].z - x[2].z};
+  }
+}
+
+// mollifier threshold eps_x = 1e-3 |ea_rest|^2 |eb_rest|^2
+__device__ __forceinline__ double mollifier_eps(const V3 *r) {
+#pragma clang fp contract(off)
+  V3 u = xsub(r[1], r[0]);
+  V3 v = xsub(r[3], r[2]);
+  return 1e-3 * xdot(u, u) * xdot(v, v);
+}
+
+// ---------------------------------------------------------------------------
+// CCD: additive conservative advancement for one pair (exact arithmetic,
+// same operation sequence as the CPU reference reading):
+//   p_i -= mean(p);  l_p = |p0| + max(|p1|,|p2|,|p3|)  (PT)
+//                     l_p = max(|p0|,|p1|) + max(|p2|,|p3|) (EE)
+//   d = dist(x); g = s d; t = 0; tl = (1 - s) d / l_p
+//   loop: x += tl p; d = dist(x); if t > 0 and d < g stop;
+//         t += tl; if t > t_c return t_c; tl = 0.9 d / l_p
+// ---------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ double accd(V3 *x, V3 *p, double s, double t_c, int64_t max_iter, int64_t *iters) {
+#pragma clang fp contract(off)
+  V3 mean;
+  mean.x = (((p[0].x + p[1].x) + p[2].x) + p[3].x) * 0.25;
+  mean.y = (((p[0].y + p[1].y) + p[2].y) + p[3].y) * 0.25;
+  mean.z = (((p[0].z + p[1].z) + p[2].z) + p[3].z) * 0.25;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) p[a] = xsub(p[a], mean);
+  double n0 = sqrt(xdot(p[0], p[0])), n1 = sqrt(xdot(p[1], p[1]));
+  double n2 = sqrt(xdot(p[2], p[2])), n3 = sqrt(xdot(p[3], p[3]));
+  double lp = KIND == 0 ? n0 + fmax(n1, fmax(n2, n3)) : fmax(n0, n1) + fmax(n2, n3);
+  *iters = 0;
+  if (lp == 0.0) return t_c;
+  int ty;
+  double d = sqrt(pair_dist2<KIND>(x, &ty));
+  const double g = s * d;
+  double t = 0.0;
+  double tl = (1.0 - s) * d / lp;
+  int64_t it = 0;
+  for (;;) {
+    if (it >= max_iter) break;
+    ++it;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      x[a].x = x[a].x + tl * p[a].x;
+      x[a].y = x[a].y + tl * p[a].y;
+      x[a].z = x[a].z + tl * p[a].z;
+    }
+    d = sqrt(pair_dist2<KIND>(x, &ty));
+    if (t > 0.0 && d < g) break;
+    t = t + tl;
+    if (t > t_c) {
+      t = t_c;
+      break;
+    }
+    tl = 0.9 * d / lp;
+  }
+  *iters = it;
+  return t;
+}
+
+}  // namespace eipc
