@@ -65,7 +65,9 @@ typedef void *eipc_stream; /* hipStream_t */
  * vertex k in its coarse tetrahedron (Eq. 13); an empty row marks a vertex
  * with no DoF (static, or kinematic: prescribed through x_off, as in the
  * position-controlled grippers of Sec. IV-A).  A row with a single weight
- * 1 is a full-space vertex (W = I is full-space IPC, Sec. III-D). */
+ * 1 is a full-space vertex (W = I is full-space IPC, Sec. III-D).  A row
+ * holds at most 4 weights (the nodes of one tetrahedron); a longer row is
+ * reported as EIPC_ERR_ARG by the next call that synchronizes. */
 typedef struct {
   int32_t n_vert, n_node, n_face, n_edge;
   const int32_t *faces;    /* [n_face*3] vertex indices */
@@ -161,6 +163,21 @@ eipc_status eipc_barrier_hvp(eipc_ctx *ctx, const eipc_scene *sc, const double *
                              int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
                              uint32_t flags, const double *v, const double *v_off, double *out, double *out_off,
                              eipc_stream stream);
+
+/* ---- optional kernel timing (benchmarks) ---- */
+
+/* Turn per-kernel timing on or off.  While on, the library brackets each
+ * launch of its main kernels with HIP events on the launch stream. */
+eipc_status eipc_profile(eipc_ctx *ctx, int32_t enable);
+
+/* Synchronizes on the recorded events and returns, for the kernel `name`
+ * ("embed", "query_count_pt", "query_count_ee", "query_write_pt",
+ * "query_write_ee", "narrow_pt", "narrow_ee", "barrier_pt", "barrier_ee",
+ * "expand_pt", "expand_ee", "ccd_pt", "ccd_ee", "hvp_pt", "hvp_ee"), the
+ * summed milliseconds and the
+ * number of timed launches since the last reset.  reset != 0 clears all
+ * totals after reading.  ms and launches are host pointers. */
+eipc_status eipc_profile_read(eipc_ctx *ctx, const char *name, double *ms, int64_t *launches, int32_t reset);
 
 /* ---- inspection entry points (same kernels as above, for tests) ---- */
 

@@ -69,6 +69,8 @@ def _load():
         "eipc_ccd_candidates": (_I32, [_P, _P, _P, _P, _P, _D, _P, _I64, _P, _I64, _P, _P, _P]),
         "eipc_ccd_toi": (_I32, [_P, _P, _P, _P, _P, _I32, _P, _I64, _D, _D, _I64, _P, _P, _P]),
         "eipc_fp64_selftest": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
+        "eipc_profile": (_I32, [_P, _I32]),
+        "eipc_profile_read": (_I32, [_P, C.c_char_p, _P, _P, _I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -136,6 +138,24 @@ class Context:
 
     def sync_status(self) -> int:
         return _load().eipc_sync_status(self._h, self.stream())
+
+    KERNELS = ("embed", "query_count_pt", "query_count_ee", "query_write_pt", "query_write_ee", "narrow_pt",
+               "narrow_ee", "barrier_pt", "barrier_ee", "ccd_pt", "ccd_ee", "hvp_pt", "hvp_ee", "expand_pt",
+               "expand_ee")
+
+    def profile(self, enable: bool = True):
+        """Per-kernel HIP-event timing inside the library (on the launch stream)."""
+        self.check(_load().eipc_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{kernel: (total_ms, launches)} since the last reset."""
+        out = {}
+        for i, k in enumerate(self.KERNELS):
+            ms, n = _D(), _I64()
+            last = reset and i == len(self.KERNELS) - 1
+            self.check(_load().eipc_profile_read(self._h, k.encode(), C.byref(ms), C.byref(n), 1 if last else 0))
+            out[k] = (ms.value, n.value)
+        return out
 
 
 def _f64(t, dev):

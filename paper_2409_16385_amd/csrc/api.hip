@@ -18,6 +18,48 @@ eipc_status set_err(eipc_ctx *c, eipc_status st, const char *fmt, ...) {
   return st;
 }
 
+const char *const kKernelNames[K_NUM] = {"embed",        "query_count_pt", "query_count_ee", "query_write_pt",
+                                         "query_write_ee", "narrow_pt",     "narrow_ee",      "barrier_pt",
+                                         "barrier_ee",     "ccd_pt",        "ccd_ee",         "hvp_pt",
+                                         "hvp_ee",         "expand_pt",     "expand_ee"};
+
+static hipEvent_t take_event(eipc_ctx *c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(eipc_ctx *c_, int id_, hipStream_t s_) : c(c_), id(id_), s(s_) {
+  if (!c->prof) return;
+  a = take_event(c);
+  b = take_event(c);
+  if (a && b) hipEventRecord(a, s);
+}
+
+ProfScope::~ProfScope() {
+  if (!c->prof || !a || !b) return;
+  hipEventRecord(b, s);
+  c->prof_pending.push_back(ProfRec{id, a, b});
+}
+
+static void prof_collect(eipc_ctx *c) {
+  for (auto &r : c->prof_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      c->prof_ms[r.id] += ms;
+      c->prof_n[r.id] += 1;
+    }
+    c->prof_pool.push_back(r.start);
+    c->prof_pool.push_back(r.stop);
+  }
+  c->prof_pending.clear();
+}
+
 eipc_status ensure(eipc_ctx *c, BufId id, size_t bytes, void **out) {
   DevBuf &b = c->buf[id];
   if (b.bytes < bytes) {
@@ -76,6 +118,7 @@ static eipc_status read_status(eipc_ctx *c, hipStream_t s, bool clear = true) {
   EIPC_HIP(c, hipMemcpyAsync(&st, c->status, 4, hipMemcpyDeviceToHost, s));
   EIPC_HIP(c, hipStreamSynchronize(s));
   if (clear && st) EIPC_HIP(c, hipMemsetAsync(c->status, 0, 4, s));
+  if (st & ST_BAD_W) return set_err(c, EIPC_ERR_ARG, "a row of W has more than 4 weights");
   if (st & ST_INTERSECTING) return set_err(c, EIPC_ERR_INTERSECTING, "a candidate pair has zero distance");
   if (st & ST_NONFINITE) return set_err(c, EIPC_ERR_NONFINITE, "non-finite position or pair quantity");
   if (st & ST_CCD_CAPPED) return EIPC_WARN_CCD_CAPPED;
@@ -147,6 +190,8 @@ void eipc_destroy(eipc_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
+  prof_collect(c);
+  for (auto e : c->prof_pool) hipEventDestroy(e);
   for (auto &b : c->buf)
     if (b.p) hipFree(b.p);
   if (c->status) hipFree(c->status);
@@ -156,6 +201,30 @@ void eipc_destroy(eipc_ctx *c) {
 }
 
 const char *eipc_last_error(const eipc_ctx *c) { return c ? c->err : "no context"; }
+
+eipc_status eipc_profile(eipc_ctx *c, int32_t enable) {
+  if (!c) return EIPC_ERR_ARG;
+  c->prof = enable != 0;
+  return EIPC_OK;
+}
+
+eipc_status eipc_profile_read(eipc_ctx *c, const char *name, double *ms, int64_t *launches, int32_t reset) {
+  if (!c || !name || !ms || !launches) return EIPC_ERR_ARG;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  prof_collect(c);
+  int id = -1;
+  for (int k = 0; k < K_NUM; ++k)
+    if (std::strcmp(name, kKernelNames[k]) == 0) id = k;
+  if (id < 0) return set_err(c, EIPC_ERR_ARG, "unknown kernel name %s", name);
+  *ms = c->prof_ms[id];
+  *launches = c->prof_n[id];
+  if (reset)
+    for (int k = 0; k < K_NUM; ++k) {
+      c->prof_ms[k] = 0.0;
+      c->prof_n[k] = 0;
+    }
+  return EIPC_OK;
+}
 
 eipc_status eipc_sync_status(eipc_ctx *c, eipc_stream stream) {
   if (!c) return EIPC_ERR_ARG;

@@ -9,8 +9,8 @@
 namespace eipc {
 
 constexpr int BR_THREADS = 256;
-constexpr int LTBL = 512;  // LDS 3x3-block table entries (36 KiB)
-constexpr int LGT = 256;   // LDS node-vector table entries (6 KiB)
+constexpr int LTBL = 1024;  // LDS 3x3-block table entries (76 KiB)
+constexpr int LGT = 512;    // LDS node-vector table entries (14 KiB)
 constexpr int MAX_PROBE = 32;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t k) {
@@ -110,145 +110,201 @@ __device__ __forceinline__ void lds_vec_add(const LdsTables &T, double *grad, in
   atomicAdd(&T.gval[3 * slot + 2], g2);
 }
 
-// Expansion through W: for slot pairs (a,k) <= (b,l) the block
-// w_ak w_bl P_x[a][b] goes to node block (I, J); only blocks with I <= J
-// are accumulated (transposing when I > J, adding both orders when the
-// two slots share a node).
-__device__ __forceinline__ void expand_hessian(const double *X, const int *vid, const int32_t *rowptr,
-                                               const int32_t *col, const double *val, const LdsTables &T,
-                                               const HessOut &h, int n_node, uint32_t *status) {
+// ---------------------------------------------------------------------------
+// Merged expansion.  The 16 (node, weight) slots of a pair (4 vertices x up
+// to 4 weights) are taken to the Q basis, z_s = w_s Q[a(s)] (3 numbers),
+// sorted by node with a bitonic network, equal nodes merged, and sorted
+// again to compact.  Then, for distinct nodes I <= J,
+//   block(I, J) = sum_{alpha, beta} z_I[alpha] z_J[beta] X[alpha][beta]
+// and the gradient of node I is sum_alpha z_I[alpha] gamma_alpha with
+// gamma = G^T gY.  Each block is summed across the wavefront when every
+// lane holding one targets the same block, else added per lane.
+// ---------------------------------------------------------------------------
+constexpr int NO_NODE = 0x7fffffff;
+
+struct NodeSet {
+  int node[16];
+  double z[16][3];
+};
+
+__device__ __forceinline__ void cswap(NodeSet &S, int a, int b, bool up) {
+  const bool sw = up ? (S.node[a] > S.node[b]) : (S.node[a] < S.node[b]);
+  const int na = S.node[a], nb = S.node[b];
+  S.node[a] = sw ? nb : na;
+  S.node[b] = sw ? na : nb;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int ka0 = rowptr[vid[a]], ka1 = rowptr[vid[a] + 1];
-    if (ka0 == ka1) continue;
-#pragma unroll
-    for (int b = a; b < 4; ++b) {
-      const int kb0 = rowptr[vid[b]], kb1 = rowptr[vid[b] + 1];
-      if (kb0 == kb1) continue;
-      double P[9];
-      x_block(X, a, b, P);
-      for (int ka = ka0; ka < ka1; ++ka) {
-        const int I = col[ka];
-        const double wa = val[ka];
-        for (int kb = (a == b ? ka : kb0); kb < kb1; ++kb) {
-          const int J = col[kb];
-          const double w = wa * val[kb];
-          double C[9];
-          if (a == b && ka == kb) {
-#pragma unroll
-            for (int t = 0; t < 9; ++t) C[t] = w * P[t];
-            lds_block_add(T, h, n_node, I, I, C, status);
-          } else if (I < J) {
-#pragma unroll
-            for (int t = 0; t < 9; ++t) C[t] = w * P[t];
-            lds_block_add(T, h, n_node, I, J, C, status);
-          } else if (I > J) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int j = 0; j < 3; ++j) C[3 * i + j] = w * P[3 * j + i];
-            lds_block_add(T, h, n_node, J, I, C, status);
-          } else {
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int j = 0; j < 3; ++j) C[3 * i + j] = w * (P[3 * i + j] + P[3 * j + i]);
-            lds_block_add(T, h, n_node, I, I, C, status);
-          }
-        }
-      }
-    }
+  for (int c = 0; c < 3; ++c) {
+    const double za = S.z[a][c], zb = S.z[b][c];
+    S.z[a][c] = sw ? zb : za;
+    S.z[b][c] = sw ? za : zb;
   }
 }
 
+__device__ __forceinline__ void sort16(NodeSet &S) {
+#pragma unroll
+  for (int k = 2; k <= 16; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int l = i ^ j;
+        if (l > i) cswap(S, i, l, (i & k) == 0);
+      }
+}
+
+// Rows hold at most 4 weights (checked when positions are embedded).
 template <int KIND>
-__global__ __launch_bounds__(BR_THREADS) void k_barrier(
+__device__ __forceinline__ bool gather_nodes(const int *vid, const int32_t *rowptr, const int32_t *col,
+                                             const double *val, NodeSet &S, int &m) {
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int k0 = rowptr[vid[a]];
+    const int cnt = rowptr[vid[a] + 1] - k0;
+    ok = ok && cnt <= 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool v = k < cnt;
+      const double w = v ? val[k0 + k] : 0.0;
+      S.node[4 * a + k] = v ? col[k0 + k] : NO_NODE;
+#pragma unroll
+      for (int al = 0; al < 3; ++al) S.z[4 * a + k][al] = 0.5 * kS[a][al] * w;
+    }
+  }
+  sort16(S);
+#pragma unroll
+  for (int s = 0; s < 15; ++s) {
+    if (S.node[s] == S.node[s + 1] && S.node[s] != NO_NODE) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        S.z[s + 1][c] += S.z[s][c];
+        S.z[s][c] = 0.0;
+      }
+      S.node[s] = NO_NODE;
+    }
+  }
+  sort16(S);
+  m = 0;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) m += S.node[s] != NO_NODE;
+  return ok;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+struct Acc {
+  LdsTables T;
+  HessOut h;
+  int n_node;
+  double *grad;
+  uint32_t *status;
+};
+
+__device__ __forceinline__ void lds_block_add_n(const Acc &A, int key, const double *B) {
+  int slot = table_slot(A.T.bkey, LTBL - 1, key);
+  if (slot < 0) {
+    global_block_add(A.h, A.n_node, key / A.n_node, key % A.n_node, B, A.status);
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) atomicAdd(&A.T.bval[9 * slot + t], B[t]);
+}
+
+// wavefront-aggregated add of a 3x3 block (all lanes must call)
+__device__ __forceinline__ void agg_block(const Acc &A, bool valid, int key, const double *B) {
+  const uint64_t vm = __ballot(valid);
+  if (vm == 0) return;
+  const int first = __ffsll((unsigned long long)vm) - 1;
+  const int k0 = __shfl(key, first, 64);
+  const bool uniform = __ballot(valid && key != k0) == 0;
+  if (uniform) {
+    double S[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) S[t] = wave_sum(valid ? B[t] : 0.0);
+    if ((int)(threadIdx.x & 63) == first) lds_block_add_n(A, key, S);
+  } else if (valid) {
+    lds_block_add_n(A, key, B);
+  }
+}
+
+__device__ __forceinline__ void agg_vec(const Acc &A, bool valid, int node, double g0, double g1, double g2) {
+  const uint64_t vm = __ballot(valid);
+  if (vm == 0) return;
+  const int first = __ffsll((unsigned long long)vm) - 1;
+  const int k0 = __shfl(node, first, 64);
+  const bool uniform = __ballot(valid && node != k0) == 0;
+  if (uniform) {
+    g0 = wave_sum(valid ? g0 : 0.0);
+    g1 = wave_sum(valid ? g1 : 0.0);
+    g2 = wave_sum(valid ? g2 : 0.0);
+    if ((int)(threadIdx.x & 63) == first) lds_vec_add(A.T, A.grad, node, g0, g1, g2);
+  } else if (valid) {
+    lds_vec_add(A.T, A.grad, node, g0, g1, g2);
+  }
+}
+
+// Phase 1: per active pair, energy (block-reduced into *energy), the
+// gradient in the Q basis gamma = G^T gY (9) and the Hessian X in the Q
+// basis (45, PSD-projected with EIPC_PROJECT), stored SoA: out[e*cap + i].
+template <int KIND>
+__global__ __launch_bounds__(BR_THREADS) void k_pair_terms(
     const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
     const int64_t *__restrict__ d_count, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
-    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, const double *__restrict__ val,
-    const double *__restrict__ xs, const double *__restrict__ x_rest, int n_vert, int n_node, double dhat,
-    double kappa, uint32_t flags, double *energy, double *grad, HessOut h, uint32_t *status) {
-  __shared__ int s_bkey[LTBL];
-  __shared__ double s_bval[LTBL * 9];
-  __shared__ int s_gkey[LGT];
-  __shared__ double s_gval[LGT * 3];
+    const double *__restrict__ xs, const double *__restrict__ x_rest, int n_vert, double dhat, double kappa,
+    uint32_t flags, double *energy, double *__restrict__ gq, double *__restrict__ Xq, int64_t cap) {
   __shared__ double s_e[BR_THREADS / 64];
-  LdsTables T{s_bkey, s_bval, s_gkey, s_gval};
-  const bool want_g = (flags & EIPC_GRAD) && grad;
-  const bool want_h = (flags & EIPC_HESS) && h.kind != 0;
+  const bool want_g = gq != nullptr;
+  const bool want_h = Xq != nullptr;
   const bool project = flags & EIPC_PROJECT;
   const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
-  for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) s_bkey[t] = -1;
-  for (int t = threadIdx.x; t < LTBL * 9; t += BR_THREADS) s_bval[t] = 0.0;
-  for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = -1;
-  for (int t = threadIdx.x; t < LGT * 3; t += BR_THREADS) s_gval[t] = 0.0;
-  __syncthreads();
   const int64_t n = *d_count;
   double e_acc = 0.0;
-  for (int64_t base = (int64_t)blockIdx.x * BR_THREADS; base < n; base += (int64_t)gridDim.x * BR_THREADS) {
-    const int64_t i = base + threadIdx.x;
-    if (i < n) {
-      const int64_t k = act[i];
-      const int ty = typ[i];
-      int vid[4];
-      pair_vertices<KIND>(pairs, k, faces, edges, vid);
-      V3 x[4];
+  for (int64_t i = (int64_t)blockIdx.x * BR_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BR_THREADS) {
+    const int64_t k = act[i];
+    const int ty = typ[i];
+    int vid[4];
+    pair_vertices<KIND>(pairs, k, faces, edges, vid);
+    V3 x[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) x[a] = load3(xs, n_vert, vid[a]);
-      const double s2 = type_value<KIND>(ty, x);
-      double eps = 0.0;
-      if (moll) {
-        V3 r[4];
+    for (int a = 0; a < 4; ++a) x[a] = load3(xs, n_vert, vid[a]);
+    const double s2 = type_value<KIND>(ty, x);
+    double eps = 0.0;
+    if (moll) {
+      V3 r[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-          r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
-        eps = mollifier_eps(r);
-      }
-      V3 Y[3];
-      y_basis<KIND>(x, Y);
-      double gE[9], HE[45];
-      e_acc += energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, want_h);
-      if (want_g) {
-        double gx[12];
-        slot_grad<KIND>(gE, gx);
+      for (int a = 0; a < 4; ++a)
+        r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
+      eps = mollifier_eps(r);
+    }
+    V3 Y[3];
+    y_basis<KIND>(x, Y);
+    double gE[9], HE[45];
+    e_acc += energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, want_h);
+    if (want_g) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int k0 = rowptr[vid[a]], k1 = rowptr[vid[a] + 1];
-          for (int kk = k0; kk < k1; ++kk) {
-            const double w = val[kk];
-            lds_vec_add(T, grad, col[kk], w * gx[3 * a], w * gx[3 * a + 1], w * gx[3 * a + 2]);
+      for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int J = 0; J < 3; ++J) {
+            const int g = gcoef(KIND, J, al);
+            if (g != 0) acc += g * gE[3 * J + c];
           }
+          gq[(3 * al + c) * cap + i] = acc;
         }
-      }
-      if (want_h) {
-        double M[45];
-        to_q_basis<KIND>(HE, M);
-        if (project) project_psd9(M);
-        expand_hessian(M, vid, rowptr, col, val, T, h, n_node, status);
-      }
     }
-    __syncthreads();
-    // flush the LDS tables to global memory and reset them
-    for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) {
-      const int key = s_bkey[t];
-      if (key != -1) {
-        global_block_add(h, n_node, key / n_node, key % n_node, &s_bval[9 * t], status);
-        s_bkey[t] = -1;
+    if (want_h) {
+      double M[45];
+      to_q_basis<KIND>(HE, M);
+      if (project) project_psd9(M);
 #pragma unroll
-        for (int u = 0; u < 9; ++u) s_bval[9 * t + u] = 0.0;
-      }
+      for (int e = 0; e < 45; ++e) Xq[e * cap + i] = M[e];
     }
-    for (int t = threadIdx.x; t < LGT; t += BR_THREADS) {
-      const int key = s_gkey[t];
-      if (key != -1) {
-        atomicAdd(&grad[3 * (int64_t)key], s_gval[3 * t]);
-        atomicAdd(&grad[3 * (int64_t)key + 1], s_gval[3 * t + 1]);
-        atomicAdd(&grad[3 * (int64_t)key + 2], s_gval[3 * t + 2]);
-        s_gkey[t] = -1;
-        s_gval[3 * t] = s_gval[3 * t + 1] = s_gval[3 * t + 2] = 0.0;
-      }
-    }
-    __syncthreads();
   }
   if (energy) {
 #pragma unroll
@@ -263,21 +319,156 @@ __global__ __launch_bounds__(BR_THREADS) void k_barrier(
   }
 }
 
+// Phase 2: reduction through W of gamma and X (merged node sets, wavefront
+// aggregation, LDS tables flushed to the global target).
+template <int KIND>
+__global__ __launch_bounds__(BR_THREADS) void k_expand(
+    const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int64_t *__restrict__ d_count,
+    const int32_t *__restrict__ faces, const int32_t *__restrict__ edges, const int32_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const double *__restrict__ val, int n_node, const double *__restrict__ gq,
+    const double *__restrict__ Xq, int64_t cap, double *grad, HessOut h, uint32_t *status) {
+  __shared__ int s_bkey[LTBL];
+  __shared__ double s_bval[LTBL * 9];
+  __shared__ int s_gkey[LGT];
+  __shared__ double s_gval[LGT * 3];
+  __shared__ int s_used;
+  LdsTables T{s_bkey, s_bval, s_gkey, s_gval};
+  Acc A{T, h, n_node, grad, status};
+  const bool want_g = gq != nullptr && grad != nullptr;
+  const bool want_h = Xq != nullptr && h.kind != 0;
+  for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) s_bkey[t] = -1;
+  for (int t = threadIdx.x; t < LTBL * 9; t += BR_THREADS) s_bval[t] = 0.0;
+  for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = -1;
+  for (int t = threadIdx.x; t < LGT * 3; t += BR_THREADS) s_gval[t] = 0.0;
+  __syncthreads();
+  const int64_t n = *d_count;
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + BR_THREADS - 1) / BR_THREADS * BR_THREADS;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  for (int64_t base = r0; base < r1; base += BR_THREADS) {
+    const int64_t i = base + threadIdx.x;
+    const bool active = i < r1;
+    int vid[4] = {0, 0, 0, 0};
+    NodeSet S;
+    int m = 0;
+    bool fast = true;
+    if (active) {
+      pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
+      fast = gather_nodes<KIND>(vid, rowptr, col, val, S, m);
+    }
+    const bool use_fast = active && fast;
+    if (want_g) {
+      double gam[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) gam[e] = active ? gq[e * cap + i] : 0.0;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const bool v = use_fast && s < m;
+        if (__any(v)) {
+          double g[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) g[c] = S.z[s][0] * gam[c] + S.z[s][1] * gam[3 + c] + S.z[s][2] * gam[6 + c];
+          agg_vec(A, v, v ? S.node[s] : -1, g[0], g[1], g[2]);
+        }
+      }
+    }
+    if (want_h) {
+      double X[45];
+#pragma unroll
+      for (int e = 0; e < 45; ++e) X[e] = active ? Xq[e * cap + i] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (!__any(use_fast && j < m)) continue;
+        double Rt[3][9];
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              Rt[al][3 * r + c] = S.z[j][0] * X[pidx(3 * al + r, c)] + S.z[j][1] * X[pidx(3 * al + r, 3 + c)] +
+                                  S.z[j][2] * X[pidx(3 * al + r, 6 + c)];
+#pragma unroll
+        for (int ii = 0; ii <= j; ++ii) {
+          const bool v = use_fast && j < m;
+          double B[9];
+#pragma unroll
+          for (int t = 0; t < 9; ++t) B[t] = S.z[ii][0] * Rt[0][t] + S.z[ii][1] * Rt[1][t] + S.z[ii][2] * Rt[2][t];
+          const int key = v ? S.node[ii] * n_node + S.node[j] : -1;
+          agg_block(A, v, key, B);
+        }
+      }
+    }
+    __syncthreads();
+    const bool last = base + BR_THREADS >= r1;
+    if (!last) {
+      if (threadIdx.x == 0) s_used = 0;
+      __syncthreads();
+      int cnt = 0;
+      for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) cnt += s_bkey[t] != -1;
+      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) cnt += 2 * (s_gkey[t] != -1);
+      if (cnt) atomicAdd(&s_used, cnt);
+      __syncthreads();
+    }
+    if (last || s_used > LTBL / 2) {
+      for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) {
+        const int key = s_bkey[t];
+        if (key != -1) {
+          global_block_add(h, n_node, key / n_node, key % n_node, &s_bval[9 * t], status);
+          s_bkey[t] = -1;
+#pragma unroll
+          for (int u = 0; u < 9; ++u) s_bval[9 * t + u] = 0.0;
+        }
+      }
+      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) {
+        const int key = s_gkey[t];
+        if (key != -1) {
+          atomicAdd(&grad[3 * (int64_t)key], s_gval[3 * t]);
+          atomicAdd(&grad[3 * (int64_t)key + 1], s_gval[3 * t + 1]);
+          atomicAdd(&grad[3 * (int64_t)key + 2], s_gval[3 * t + 2]);
+          s_gkey[t] = -1;
+          s_gval[3 * t] = s_gval[3 * t + 1] = s_gval[3 * t + 2] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                            const int32_t *act, const int32_t *typ, const int64_t *d_count, int64_t max_count,
                            double dhat, double kappa, uint32_t flags, double *energy, double *grad,
                            const HessOut &h, hipStream_t s) {
   if (max_count == 0) return EIPC_OK;
-  int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 4 * (int64_t)c->num_cu);
-  if (kind == 0)
-    k_barrier<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr,
-                                                sc->W_col, sc->W_val, xs, sc->x_rest, sc->n_vert, sc->n_node, dhat,
-                                                kappa, flags, energy, grad, h, c->status);
-  else
-    k_barrier<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr,
-                                                sc->W_col, sc->W_val, xs, sc->x_rest, sc->n_vert, sc->n_node, dhat,
-                                                kappa, flags, energy, grad, h, c->status);
-  EIPC_HIP(c, hipGetLastError());
+  const bool want_g = (flags & EIPC_GRAD) && grad;
+  const bool want_h = (flags & EIPC_HESS) && h.kind != 0;
+  double *gq = nullptr, *Xq = nullptr;
+  const int64_t cap = max_count;
+  if (want_g) EIPC_TRY(ensure_t(c, kind == 0 ? B_PG_PT : B_PG_EE, (size_t)9 * cap, &gq));
+  if (want_h) EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)45 * cap, &Xq));
+  {
+    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 8 * (int64_t)c->num_cu);
+    ProfScope ps(c, kind == 0 ? K_BARRIER_PT : K_BARRIER_EE, s);
+    if (kind == 0)
+      k_pair_terms<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
+                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap);
+    else
+      k_pair_terms<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
+                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap);
+    EIPC_HIP(c, hipGetLastError());
+  }
+  if (!want_g && !want_h) return EIPC_OK;
+  {
+    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 2 * (int64_t)c->num_cu);
+    ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
+    if (kind == 0)
+      k_expand<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                                 sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
+    else
+      k_expand<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                                 sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
+    EIPC_HIP(c, hipGetLastError());
+  }
   return EIPC_OK;
 }
 
@@ -498,6 +689,7 @@ eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double
                        double *out_off, hipStream_t s) {
   if (max_count == 0) return EIPC_OK;
   int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 4 * (int64_t)c->num_cu);
+  ProfScope ps(c, kind == 0 ? K_HVP_PT : K_HVP_EE, s);
   if (kind == 0)
     k_hvp<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
                                             sc->W_val, xs, xvs, sc->x_rest, sc->n_vert, dhat, kappa, flags, out,

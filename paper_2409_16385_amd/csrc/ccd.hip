@@ -54,6 +54,7 @@ eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double
                        const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
                        uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s) {
   if (n == 0) return EIPC_OK;
+  ProfScope prof(c, kind == 0 ? K_CCD_PT : K_CCD_EE, s);
   if (kind == 0)
     k_ccd<0><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
                                                max_iter, (unsigned long long *)d_alpha_bits, t_out, it_out,

@@ -6,13 +6,20 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <vector>
 
 #include "eipc.h"
 
 namespace eipc {
 
 // status bits raised by kernels into the device status word
-enum : uint32_t { ST_INTERSECTING = 1u, ST_NONFINITE = 2u, ST_CCD_CAPPED = 4u, ST_HASH_OVERFLOW = 8u };
+enum : uint32_t {
+  ST_INTERSECTING = 1u,
+  ST_NONFINITE = 2u,
+  ST_CCD_CAPPED = 4u,
+  ST_HASH_OVERFLOW = 8u,
+  ST_BAD_W = 16u  // a W row with more than 4 weights
+};
 
 // scratch buffers owned by the context
 enum BufId {
@@ -37,12 +44,25 @@ enum BufId {
   B_CAND_PT, B_CAND_EE,  // swept candidates (CCD)
   B_HKEY, B_HVAL,        // global block hash
   B_ROWCNT, B_ROWFILL, B_ROWPTR, B_BCOL, B_BSRC, B_BBLK,
+  B_PG_PT, B_PG_EE, B_PX_PT, B_PX_EE,  // per-pair gradient / Hessian in the Q basis
   B_NUM
 };
 
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+};
+
+// kernels timed by the optional event profiler
+enum KernelId {
+  K_EMBED = 0, K_QUERY_COUNT_PT, K_QUERY_COUNT_EE, K_QUERY_WRITE_PT, K_QUERY_WRITE_EE, K_NARROW_PT, K_NARROW_EE,
+  K_BARRIER_PT, K_BARRIER_EE, K_CCD_PT, K_CCD_EE, K_HVP_PT, K_HVP_EE, K_EXPAND_PT, K_EXPAND_EE, K_NUM
+};
+extern const char *const kKernelNames[K_NUM];
+
+struct ProfRec {
+  int id;
+  hipEvent_t start, stop;
 };
 
 }  // namespace eipc
@@ -57,6 +77,11 @@ struct eipc_ctx {
   int64_t *host = nullptr;      // pinned host staging [64]
   int64_t hash_cap = 1 << 16;   // global block hash capacity (power of 2, grows)
   int num_cu = 256;
+  bool prof = false;                        // record per-kernel events
+  std::vector<eipc::ProfRec> prof_pending;  // recorded, not yet read
+  std::vector<hipEvent_t> prof_pool;        // reusable events
+  double prof_ms[eipc::K_NUM] = {0};
+  int64_t prof_n[eipc::K_NUM] = {0};
 };
 
 namespace eipc {
@@ -85,6 +110,16 @@ inline eipc_status ensure_t(eipc_ctx *c, BufId id, size_t count, T **out) {
   *out = (T *)p;
   return st;
 }
+
+// event bracket around one kernel launch when profiling is on
+struct ProfScope {
+  eipc_ctx *c;
+  int id;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(eipc_ctx *c_, int id_, hipStream_t s_);
+  ~ProfScope();
+};
 
 inline int grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;

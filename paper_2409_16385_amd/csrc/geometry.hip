@@ -22,6 +22,7 @@ __global__ void k_embed(int n, const int32_t *__restrict__ rowptr, const int32_t
   if (v >= n) return;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const int k0 = rowptr[v], k1 = rowptr[v + 1];
+  if (k1 - k0 > 4 || k1 < k0) atomicOr(status, ST_BAD_W);
   for (int k = k0; k < k1; ++k) {
     const double w = val[k];
     const int64_t c = 3 * (int64_t)col[k];
@@ -50,6 +51,7 @@ __global__ void k_embed(int n, const int32_t *__restrict__ rowptr, const int32_t
 eipc_status launch_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *off, double *xs,
                          double *x_aos, hipStream_t s) {
   if (sc->n_vert == 0) return EIPC_OK;
+  ProfScope ps(c, K_EMBED, s);
   k_embed<<<grid_for(sc->n_vert, 256), 256, 0, s>>>(sc->n_vert, sc->W_rowptr, sc->W_col, sc->W_val, q, off, xs,
                                                      x_aos, c->status);
   EIPC_HIP(c, hipGetLastError());
@@ -576,12 +578,15 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   int64_t *qoff;
   EIPC_TRY(ensure_t(c, B_QCNT, (size_t)nq, &qcnt));
   EIPC_TRY(ensure_t(c, B_QOFF, (size_t)nq + 1, &qoff));
-  if (kind == 0)
-    k_query<0><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
-                                                  nullptr, nullptr, 0, 0);
-  else
-    k_query<1><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
-                                                  nullptr, nullptr, 0, 0);
+  {
+    ProfScope ps(c, kind == 0 ? K_QUERY_COUNT_PT : K_QUERY_COUNT_EE, s);
+    if (kind == 0)
+      k_query<0><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr,
+                                                    qcnt, nullptr, nullptr, 0, 0);
+    else
+      k_query<1><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr,
+                                                    qcnt, nullptr, nullptr, 0, 0);
+  }
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, qcnt, nq, qoff, s));
   int64_t total = 0;
@@ -595,6 +600,7 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   }
   if (total > cap || out == nullptr) return total > cap ? EIPC_ERR_CAPACITY : EIPC_OK;
   if (total == 0) return EIPC_OK;
+  ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
   if (kind == 0)
     k_query<0><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
                                                   qoff, out, 1, sort);
@@ -665,6 +671,7 @@ eipc_status launch_narrow(eipc_ctx *c, const eipc_scene *sc, int kind, const dou
                           int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s) {
   if (n == 0) return EIPC_OK;
   const double d2 = dhat * dhat;
+  ProfScope ps(c, kind == 0 ? K_NARROW_PT : K_NARROW_EE, s);
   if (kind == 0)
     k_narrow<0><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ,
                                                   d_count, c->status);

@@ -409,7 +409,7 @@ __device__ __forceinline__ void s_derivs_typed(const V3 *Y, double *gY, double *
 }
 
 template <int KIND>
-__device__ __noinline__ void s_derivs(int type, const V3 *Y, double *gY, double *HY) {
+__device__ __forceinline__ void s_derivs(int type, const V3 *Y, double *gY, double *HY) {
   if constexpr (KIND == 0) {
     switch (type) {
       case 0: s_derivs_typed<0, 0>(Y, gY, HY); break;

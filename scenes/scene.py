@@ -330,19 +330,32 @@ def config3(seed: int = 0, n_cyl: int = 40, spacing: float = 1.75e-3) -> Scene:
 # ---------------------------------------------------------------------------
 
 def _real_sh_basis(lmax: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
-    """Real spherical harmonics up to lmax (l >= 1) at polar angle theta and
-    azimuth phi, one column per (l, m)."""
-    from scipy.special import sph_harm_y
+    """Real spherical harmonics for 1 <= l <= lmax at polar angle theta and
+    azimuth phi, one column per (l, m), m = -l..l.  Associated Legendre
+    functions by the standard three-term recurrence in l."""
+    x = np.cos(theta)
+    sx = np.sqrt(np.maximum(1.0 - x * x, 0.0))
+    P = {}
+    pmm = np.ones_like(x)
+    for m in range(lmax + 1):
+        if m > 0:
+            pmm = -pmm * (2 * m - 1) * sx
+        P[m, m] = pmm
+        if m + 1 <= lmax:
+            P[m + 1, m] = x * (2 * m + 1) * pmm
+        for l in range(m + 2, lmax + 1):
+            P[l, m] = ((2 * l - 1) * x * P[l - 1, m] - (l + m - 1) * P[l - 2, m]) / (l - m)
     cols = []
     for l in range(1, lmax + 1):
         for m in range(-l, l + 1):
-            y = sph_harm_y(l, abs(m), theta, phi)
+            am = abs(m)
+            norm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
             if m < 0:
-                cols.append(math.sqrt(2) * (-1) ** m * y.imag)
+                cols.append(math.sqrt(2) * norm * P[l, am] * np.sin(am * phi))
             elif m == 0:
-                cols.append(y.real)
+                cols.append(norm * P[l, 0])
             else:
-                cols.append(math.sqrt(2) * (-1) ** m * y.real)
+                cols.append(math.sqrt(2) * norm * P[l, am] * np.cos(am * phi))
     return np.stack(cols, axis=1)
 
 
@@ -371,7 +384,7 @@ class Blob:
         """Smallest t in [0, t_hi] where origin + t dir enters the body
         (bisection on a coarse march), or nan if the ray misses."""
         n = len(origin)
-        ts = np.linspace(0.0, t_hi, 400)
+        ts = np.linspace(0.0, t_hi, 160)
         hit = np.full(n, np.nan)
         prev_in = np.zeros(n, dtype=bool)
         prev_t = np.zeros(n)
