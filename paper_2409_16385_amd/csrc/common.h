@@ -27,15 +27,15 @@ enum BufId {
   B_P,           // CCD displacement, SoA
   B_X1,          // CCD end positions, SoA
   B_XV,          // HVP input mapped to vertices, SoA
-  B_QBOX,        // query boxes lo[3][n], hi[3][n]
-  B_IBOX,        // item boxes
+  B_QBOX,        // (unused)
+  B_IBOX,        // item records (box, vertices, DoF flag)
   B_CELLCNT,     // int32 per item
   B_CELLOFF,     // int64 per item + 1
   B_BCNT,        // int32 per bucket
   B_BSTART,      // int64 per bucket + 1
   B_BFILL,       // int32 per bucket
-  B_ENTCELL,     // uint64 per entry
-  B_ENTITEM,     // int32 per entry
+  B_ENTCELL,     // hash entries {cell, item}
+  B_ENTITEM,     // (unused)
   B_LARGE,       // int32 large items
   B_QCNT,        // int32 per query
   B_QOFF,        // int64 per query + 1

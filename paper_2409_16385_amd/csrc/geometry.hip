@@ -195,18 +195,28 @@ eipc_status exclusive_scan(eipc_ctx *c, const int32_t *in, int64_t n, int64_t *o
 }
 
 // ---------------------------------------------------------------------------
-// boxes: per primitive, lo = min over vertices (start and end) - dhat/2,
-// hi = max + dhat/2.  SoA lo[3][n] then hi[3][n].
+// Broad phase.  Boxes: per primitive, lo = min over its vertices (start and
+// end positions when swept) - dhat/2, hi = max + dhat/2.  Items (faces for
+// PT, edges for EE) are stored as 64-byte records; the uniform grid is a
+// hash from cell to the items whose boxes touch it.
 // ---------------------------------------------------------------------------
+struct ItemRec {
+  double lo[3], hi[3];
+  int32_t v[3];
+  int32_t dof;  // 1 if any vertex has a DoF
+};
+struct Entry {
+  uint64_t cell;
+  int32_t item;
+  int32_t dlo;  // cell minus the item's lower cell, 6 bits per axis
+};
+
+__device__ __forceinline__ bool has_dof(const int32_t *rowptr, int v) { return rowptr[v + 1] > rowptr[v]; }
+
 template <int NV>
-__global__ void k_boxes(int n, const int32_t *__restrict__ idx, const double *__restrict__ xs,
-                        const double *__restrict__ x1s, int n_vert, double h, double *__restrict__ box) {
+__device__ __forceinline__ void prim_box(const int *vid, const double *xs, const double *x1s, int n_vert, double h,
+                                         double *lo, double *hi) {
 #pragma clang fp contract(off)
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int vid[NV];
-#pragma unroll
-  for (int a = 0; a < NV; ++a) vid[a] = (NV == 1) ? i : idx[(int64_t)NV * i + a];
 #pragma unroll
   for (int cax = 0; cax < 3; ++cax) {
     const double *xc = xs + (int64_t)cax * n_vert;
@@ -222,9 +232,30 @@ __global__ void k_boxes(int n, const int32_t *__restrict__ idx, const double *__
         mx = fmax(mx, w);
       }
     }
-    box[(int64_t)cax * n + i] = mn - h;
-    box[(int64_t)(3 + cax) * n + i] = mx + h;
+    lo[cax] = mn - h;
+    hi[cax] = mx + h;
   }
+}
+
+template <int NV>
+__global__ void k_items(int n, const int32_t *__restrict__ idx, const double *__restrict__ xs,
+                        const double *__restrict__ x1s, int n_vert, double h, const int32_t *__restrict__ rowptr,
+                        ItemRec *__restrict__ rec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int vid[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) vid[a] = idx[(int64_t)NV * i + a];
+  ItemRec r;
+  prim_box<NV>(vid, xs, x1s, n_vert, h, r.lo, r.hi);
+  int dof = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r.v[a] = a < NV ? vid[a] : -1;
+    if (a < NV) dof |= has_dof(rowptr, vid[a]);
+  }
+  r.dof = dof;
+  rec[i] = r;
 }
 
 __device__ __forceinline__ uint64_t ord_key(double v) {
@@ -238,16 +269,33 @@ __host__ __forceinline__ double ord_dec(uint64_t k) {
   return v;
 }
 
-// stats layout (uint64 view): [0..2] min lo (ordered), [3..5] max hi
-// (ordered); double view [6..8] sum of extents
-__global__ void k_box_stats(int n, const double *__restrict__ box, uint64_t *st, int with_ext) {
+// stats (uint64 view): [0..2] min lo (ordered), [3..5] max hi (ordered);
+// double view [6..8] sum of item extents.  Items from records, or vertex
+// (point) boxes when rec == nullptr.
+__global__ void k_box_stats(int n, const ItemRec *__restrict__ rec, const double *__restrict__ xs,
+                            const double *__restrict__ x1s, int n_vert, double h, uint64_t *st, int with_ext) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double lo[3], hi[3], ex[3];
+  if (i < n) {
+    if (rec) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = i < n ? box[(int64_t)a * n + i] : INFINITY;
-    hi[a] = i < n ? box[(int64_t)(3 + a) * n + i] : -INFINITY;
-    ex[a] = i < n ? hi[a] - lo[a] : 0.0;
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = rec[i].lo[a];
+        hi[a] = rec[i].hi[a];
+      }
+    } else {
+      int v = i;
+      prim_box<1>(&v, xs, x1s, n_vert, h, lo, hi);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ex[a] = hi[a] - lo[a];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = INFINITY;
+      hi[a] = -INFINITY;
+      ex[a] = 0.0;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1)
@@ -276,17 +324,13 @@ __global__ void k_stats_init(uint64_t *st) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// spatial hash over a uniform grid
-// ---------------------------------------------------------------------------
 struct GridDev {
   double o[3];
   double inv_h;
   int dim[3];
   uint32_t bmask;
   const int64_t *bstart;
-  const uint64_t *ent_cell;
-  const int32_t *ent_item;
+  const Entry *ent;
   const int32_t *large;
   int n_large;
 };
@@ -305,22 +349,20 @@ __device__ __forceinline__ uint64_t cell_key(int x, int y, int z) {
 __device__ __forceinline__ uint32_t cell_hash(int x, int y, int z) {
   return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u);
 }
-
-__device__ __forceinline__ void cell_range(const GridDev &g, const double *box, int64_t n, int64_t i, int *c0,
-                                           int *c1) {
+__device__ __forceinline__ void cell_range(const GridDev &g, const double *lo, const double *hi, int *c0, int *c1) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    c0[a] = cell_of(box[a * n + i], g.o[a], g.inv_h, g.dim[a]);
-    c1[a] = cell_of(box[(3 + a) * n + i], g.o[a], g.inv_h, g.dim[a]);
+    c0[a] = cell_of(lo[a], g.o[a], g.inv_h, g.dim[a]);
+    c1[a] = cell_of(hi[a], g.o[a], g.inv_h, g.dim[a]);
   }
 }
 
-__global__ void k_item_cells(int n, const double *__restrict__ box, GridDev g, int32_t *cnt, int32_t *large,
+__global__ void k_item_cells(int n, const ItemRec *__restrict__ rec, GridDev g, int32_t *cnt, int32_t *large,
                              int64_t *counters) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int c0[3], c1[3];
-  cell_range(g, box, n, i, c0, c1);
+  cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
   int64_t nc = (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
   if (nc > MAX_ITEM_CELLS) {
     int slot = (int)atomicAdd((unsigned long long *)&counters[0], 1ull);
@@ -331,64 +373,104 @@ __global__ void k_item_cells(int n, const double *__restrict__ box, GridDev g, i
   }
 }
 
-__global__ void k_item_hist(int n, const double *__restrict__ box, GridDev g, const int32_t *cnt, int32_t *bcnt) {
+__global__ void k_item_hist(int n, const ItemRec *__restrict__ rec, GridDev g, const int32_t *cnt, int32_t *bcnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || cnt[i] == 0) return;
   int c0[3], c1[3];
-  cell_range(g, box, n, i, c0, c1);
+  cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&bcnt[cell_hash(x, y, z) & g.bmask], 1);
 }
 
-__global__ void k_item_fill(int n, const double *__restrict__ box, GridDev g, const int32_t *cnt, int32_t *bfill,
-                            uint64_t *ent_cell, int32_t *ent_item) {
+__global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, GridDev g, const int32_t *cnt, int32_t *bfill,
+                            Entry *ent) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || cnt[i] == 0) return;
   int c0[3], c1[3];
-  cell_range(g, box, n, i, c0, c1);
+  cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) {
         uint32_t b = cell_hash(x, y, z) & g.bmask;
         int64_t slot = g.bstart[b] + atomicAdd(&bfill[b], 1);
-        ent_cell[slot] = cell_key(x, y, z);
-        ent_item[slot] = i;
+        ent[slot] = Entry{cell_key(x, y, z), i, (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12)};
       }
 }
 
-__device__ __forceinline__ bool has_dof(const int32_t *rowptr, int v) { return rowptr[v + 1] > rowptr[v]; }
-
-__device__ __forceinline__ bool overlap(const double *qb, int64_t nq, int64_t q, const double *ib, int64_t ni,
-                                        int64_t i) {
+__device__ __forceinline__ bool overlap(const double *qlo, const double *qhi, const ItemRec &r) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (!(qb[a * nq + q] <= ib[(3 + a) * ni + i] && ib[a * ni + i] <= qb[(3 + a) * nq + q])) return false;
-  }
+  for (int a = 0; a < 3; ++a)
+    if (!(qlo[a] <= r.hi[a] && r.lo[a] <= qhi[a])) return false;
   return true;
 }
 
-// Candidate query.  KIND 0: query = vertex v, item = face f.  KIND 1: query
-// = edge a, item = edge b > a.  A pair overlapping in several cells is
-// reported only in the cell of the lower corner of the box intersection.
+// modes: 0 count, 1 write (offset per query, sorted per query), 2 append
+// (wavefront-aggregated atomic append, unsorted; *total receives the count)
 template <int KIND>
-__global__ void k_query(int nq, const double *__restrict__ qbox, int ni, const double *__restrict__ ibox, GridDev g,
-                        const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
-                        const int32_t *__restrict__ rowptr, int32_t *__restrict__ cnt,
-                        const int64_t *__restrict__ off, int32_t *__restrict__ out, int write, int sort) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  int qa, qb = -1;
+__device__ __forceinline__ bool pair_ok(int q, int qa, int qb, bool qdof, int it, const ItemRec &r) {
+  if (KIND == 1 && it <= q) return false;
   if (KIND == 0) {
-    qa = q;
+    if (qa == r.v[0] || qa == r.v[1] || qa == r.v[2]) return false;
   } else {
-    qa = edges[2 * (int64_t)q];
-    qb = edges[2 * (int64_t)q + 1];
+    if (qa == r.v[0] || qa == r.v[1] || qb == r.v[0] || qb == r.v[1]) return false;
   }
-  const bool qdof = has_dof(rowptr, qa) || (KIND == 1 && has_dof(rowptr, qb));
-  int c0[3], c1[3];
-  cell_range(g, qbox, nq, q, c0, c1);
-  const int64_t base = write ? off[q] : 0;
+  return qdof || r.dof;
+}
+
+constexpr int QT = 128;      // query threads per block
+constexpr int APPEND_BUF = 16;  // per-thread LDS staging for append mode
+
+// append mode: stage a candidate in the thread's LDS slots; flush a full
+// buffer with one atomic
+__device__ __forceinline__ void stage_pair(int2 *buf, int &nb, int q, int it, unsigned long long *total,
+                                           int32_t *out, int64_t cap) {
+  buf[nb] = make_int2(q, it);
+  if (++nb == APPEND_BUF) {
+    const int64_t p = (int64_t)atomicAdd(total, (unsigned long long)APPEND_BUF);
+    for (int j = 0; j < APPEND_BUF; ++j)
+      if (p + j < cap) {
+        out[2 * (p + j)] = buf[j].x;
+        out[2 * (p + j) + 1] = buf[j].y;
+      }
+    nb = 0;
+  }
+}
+
+template <int KIND, int MODE>
+__global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__ xs, const double *__restrict__ x1s,
+                                              int n_vert, double h, const int32_t *__restrict__ rowptr,
+                                              const ItemRec *__restrict__ items, GridDev g,
+                                              int32_t *__restrict__ cnt, const int64_t *__restrict__ off,
+                                              int32_t *__restrict__ out, int64_t cap, unsigned long long *total) {
+  __shared__ int2 s_buf[MODE == 2 ? QT * APPEND_BUF : 1];
+  int2 *buf = s_buf + (MODE == 2 ? threadIdx.x * APPEND_BUF : 0);
+  int nbuf = 0;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = q < nq;
+  int qa = 0, qb = -1;
+  bool qdof = false;
+  double qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+  if (live) {
+    if (KIND == 0) {
+      qa = q;
+      prim_box<1>(&qa, xs, x1s, n_vert, h, qlo, qhi);
+      qdof = has_dof(rowptr, qa);
+    } else {
+      const ItemRec r = items[q];
+      qa = r.v[0];
+      qb = r.v[1];
+      qdof = r.dof;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        qlo[a] = r.lo[a];
+        qhi[a] = r.hi[a];
+      }
+    }
+  }
+  int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
+  if (live) cell_range(g, qlo, qhi, c0, c1);
+  const int64_t base = (MODE == 1 && live) ? off[q] : 0;
   int64_t k = 0;
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
@@ -397,66 +479,67 @@ __global__ void k_query(int nq, const double *__restrict__ qbox, int ni, const d
         const uint32_t b = cell_hash(x, y, z) & g.bmask;
         const int64_t e1 = g.bstart[b + 1];
         for (int64_t e = g.bstart[b]; e < e1; ++e) {
-          if (g.ent_cell[e] != key) continue;
-          const int it = g.ent_item[e];
+          const Entry en = g.ent[e];
+          if (en.cell != key) continue;
+          const int it = en.item;
           if (KIND == 1 && it <= q) continue;
-          int iv0, iv1, iv2 = -1;
-          if (KIND == 0) {
-            iv0 = faces[3 * (int64_t)it];
-            iv1 = faces[3 * (int64_t)it + 1];
-            iv2 = faces[3 * (int64_t)it + 2];
-            if (qa == iv0 || qa == iv1 || qa == iv2) continue;
-            if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1) && !has_dof(rowptr, iv2)) continue;
-          } else {
-            iv0 = edges[2 * (int64_t)it];
-            iv1 = edges[2 * (int64_t)it + 1];
-            if (qa == iv0 || qa == iv1 || qb == iv0 || qb == iv1) continue;
-            if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1)) continue;
+          // report only in the cell holding the lower corner of the overlap:
+          // max(query low cell, item low cell) == this cell on every axis
+          {
+            const int ix = x - (en.dlo & 63), iy = y - ((en.dlo >> 6) & 63), iz = z - ((en.dlo >> 12) & 63);
+            const bool home = (ix > c0[0] ? ix : c0[0]) == x && (iy > c0[1] ? iy : c0[1]) == y &&
+                              (iz > c0[2] ? iz : c0[2]) == z;
+            if (!home) continue;
           }
-          if (!overlap(qbox, nq, q, ibox, ni, it)) continue;
-          // dedup: lower corner of the intersection
-          bool home = true;
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            int ic = cell_of(ibox[(int64_t)a * ni + it], g.o[a], g.inv_h, g.dim[a]);
-            int cs = ic > c0[a] ? ic : c0[a];
-            int cur = a == 0 ? x : (a == 1 ? y : z);
-            home = home && (cs == cur);
-          }
-          if (!home) continue;
-          if (write) {
+          const ItemRec r = items[it];
+          if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
+          if (!overlap(qlo, qhi, r)) continue;
+          if (MODE == 1) {
             out[2 * (base + k)] = q;
             out[2 * (base + k) + 1] = it;
+          } else if (MODE == 2) {
+            stage_pair(buf, nbuf, q, it, total, out, cap);
           }
           ++k;
         }
       }
-  for (int j = 0; j < g.n_large; ++j) {
-    const int it = g.large[j];
-    if (KIND == 1 && it <= q) continue;
-    int iv0, iv1, iv2 = -1;
-    if (KIND == 0) {
-      iv0 = faces[3 * (int64_t)it];
-      iv1 = faces[3 * (int64_t)it + 1];
-      iv2 = faces[3 * (int64_t)it + 2];
-      if (qa == iv0 || qa == iv1 || qa == iv2) continue;
-      if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1) && !has_dof(rowptr, iv2)) continue;
-    } else {
-      iv0 = edges[2 * (int64_t)it];
-      iv1 = edges[2 * (int64_t)it + 1];
-      if (qa == iv0 || qa == iv1 || qb == iv0 || qb == iv1) continue;
-      if (!qdof && !has_dof(rowptr, iv0) && !has_dof(rowptr, iv1)) continue;
+  if (live) {
+    for (int j = 0; j < g.n_large; ++j) {
+      const int it = g.large[j];
+      const ItemRec r = items[it];
+      if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
+      if (!overlap(qlo, qhi, r)) continue;
+      if (MODE == 1) {
+        out[2 * (base + k)] = q;
+        out[2 * (base + k) + 1] = it;
+      } else if (MODE == 2) {
+        stage_pair(buf, nbuf, q, it, total, out, cap);
+      }
+      ++k;
     }
-    if (!overlap(qbox, nq, q, ibox, ni, it)) continue;
-    if (write) {
-      out[2 * (base + k)] = q;
-      out[2 * (base + k) + 1] = it;
-    }
-    ++k;
   }
-  if (!write) {
-    cnt[q] = (int32_t)k;
-  } else if (sort && k > 1) {
+  if (MODE == 2) {
+    // flush what is left: one atomic per wavefront
+    int64_t ex = nbuf;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int64_t y = __shfl_up(ex, o, 64);
+      if (lane >= o) ex += y;
+    }
+    const int64_t wsum = __shfl(ex, 63, 64);
+    int64_t p0 = 0;
+    if (lane == 63 && wsum) p0 = (int64_t)atomicAdd(total, (unsigned long long)wsum);
+    p0 = __shfl(p0, 63, 64);
+    const int64_t p = p0 + ex - nbuf;
+    for (int j = 0; j < nbuf; ++j)
+      if (p + j < cap) {
+        out[2 * (p + j)] = buf[j].x;
+        out[2 * (p + j) + 1] = buf[j].y;
+      }
+  }
+  if (MODE == 0 && live) cnt[q] = (int32_t)k;
+  if (MODE == 1 && live && k > 1) {
     int32_t *seg = out + 2 * base;
     for (int64_t i = 1; i < k; ++i) {
       int32_t v = seg[2 * i + 1];
@@ -476,6 +559,14 @@ static uint32_t next_pow2(uint64_t v) {
   return (uint32_t)p;
 }
 
+template <int KIND, int MODE>
+static void launch_query(int nq, const double *xs, const double *x1s, int n_vert, double h, const int32_t *rowptr,
+                         const ItemRec *items, const GridDev &g, int32_t *cnt, const int64_t *off, int32_t *out,
+                         int64_t cap, unsigned long long *total, hipStream_t s) {
+  k_query<KIND, MODE><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, rowptr, items, g, cnt, off, out, cap,
+                                                       total);
+}
+
 eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *x1s,
                         double dhat, int32_t *out, int64_t cap, int64_t *n_out, int sort, hipStream_t s,
                         int grow_id, int32_t **grown) {
@@ -484,21 +575,17 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   *n_out = 0;
   if (nq == 0 || ni == 0) return EIPC_OK;
   const double h = 0.5 * dhat;
-  double *qbox, *ibox;
-  EIPC_TRY(ensure_t(c, B_QBOX, (size_t)6 * nq, &qbox));
-  if (kind == 0) {
-    EIPC_TRY(ensure_t(c, B_IBOX, (size_t)6 * ni, &ibox));
-    k_boxes<1><<<grid_for(nq, 256), 256, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, qbox);
-    k_boxes<3><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->faces, xs, x1s, sc->n_vert, h, ibox);
-  } else {
-    ibox = qbox;
-    k_boxes<2><<<grid_for(nq, 256), 256, 0, s>>>(nq, sc->edges, xs, x1s, sc->n_vert, h, qbox);
-  }
+  ItemRec *items;
+  EIPC_TRY(ensure_t(c, B_IBOX, (size_t)ni, &items));
+  if (kind == 0)
+    k_items<3><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->faces, xs, x1s, sc->n_vert, h, sc->W_rowptr, items);
+  else
+    k_items<2><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->edges, xs, x1s, sc->n_vert, h, sc->W_rowptr, items);
   EIPC_HIP(c, hipGetLastError());
   uint64_t *st = (uint64_t *)c->stats;
   k_stats_init<<<1, 64, 0, s>>>(st);
-  k_box_stats<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, st, 1);
-  if (kind == 0) k_box_stats<<<grid_for(nq, 256), 256, 0, s>>>(nq, qbox, st, 0);
+  k_box_stats<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, nullptr, nullptr, 0, h, st, 1);
+  if (kind == 0) k_box_stats<<<grid_for(nq, 256), 256, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, st, 0);
   EIPC_HIP(c, hipGetLastError());
   uint64_t hs[9];
   EIPC_HIP(c, hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -530,7 +617,6 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
     cell *= 2.0;
   }
   g.inv_h = 1.0 / cell;
-  // item cell counts
   int32_t *cnt, *large;
   int64_t *cell_off;
   EIPC_TRY(ensure_t(c, B_CELLCNT, (size_t)ni, &cnt));
@@ -539,11 +625,10 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   EIPC_TRY(launch_zero(c, c->counters, 16 * sizeof(int64_t), s));
   g.bmask = 0;
   g.bstart = nullptr;
-  g.ent_cell = nullptr;
-  g.ent_item = nullptr;
+  g.ent = nullptr;
   g.large = large;
   g.n_large = 0;
-  k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, g, cnt, large, c->counters);
+  k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, g, cnt, large, c->counters);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, cnt, ni, cell_off, s));
   int64_t hv[2];
@@ -556,24 +641,55 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   g.bmask = nb - 1;
   int32_t *bcnt, *bfill;
   int64_t *bstart;
-  uint64_t *ent_cell;
-  int32_t *ent_item;
+  Entry *ent;
   EIPC_TRY(ensure_t(c, B_BCNT, nb, &bcnt));
   EIPC_TRY(ensure_t(c, B_BFILL, nb, &bfill));
   EIPC_TRY(ensure_t(c, B_BSTART, (size_t)nb + 1, &bstart));
-  EIPC_TRY(ensure_t(c, B_ENTCELL, (size_t)std::max<int64_t>(n_ent, 1), &ent_cell));
-  EIPC_TRY(ensure_t(c, B_ENTITEM, (size_t)std::max<int64_t>(n_ent, 1), &ent_item));
+  EIPC_TRY(ensure_t(c, B_ENTCELL, (size_t)std::max<int64_t>(n_ent, 1), &ent));
   EIPC_TRY(launch_zero(c, bcnt, sizeof(int32_t) * nb, s));
   EIPC_TRY(launch_zero(c, bfill, sizeof(int32_t) * nb, s));
-  k_item_hist<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, g, cnt, bcnt);
+  k_item_hist<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, g, cnt, bcnt);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, bcnt, nb, bstart, s));
   g.bstart = bstart;
-  k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, ibox, g, cnt, bfill, ent_cell, ent_item);
+  k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, g, cnt, bfill, ent);
   EIPC_HIP(c, hipGetLastError());
-  g.ent_cell = ent_cell;
-  g.ent_item = ent_item;
-  // query: count, scan, write
+  g.ent = ent;
+  const int n_vert = sc->n_vert;
+  const int32_t *rp = sc->W_rowptr;
+  if (!sort) {
+    // single pass, unsorted append into a buffer grown to the required size
+    unsigned long long *tot = (unsigned long long *)(c->counters + 8);
+    int64_t capa = cap;
+    if (grow_id >= 0) {
+      capa = (int64_t)(c->buf[grow_id].bytes / 8);
+      if (capa > 64) capa -= 16;
+      EIPC_TRY(ensure_t(c, (BufId)grow_id, (size_t)std::max<int64_t>(2 * capa, 2), &out));
+    }
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      EIPC_TRY(launch_zero(c, tot, 8, s));
+      {
+        ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
+        if (kind == 0)
+          launch_query<0, 2>(nq, xs, x1s, n_vert, h, rp, items, g, nullptr, nullptr, out, capa, tot, s);
+        else
+          launch_query<1, 2>(nq, xs, x1s, n_vert, h, rp, items, g, nullptr, nullptr, out, capa, tot, s);
+      }
+      EIPC_HIP(c, hipGetLastError());
+      int64_t total = 0;
+      EIPC_HIP(c, hipMemcpyAsync(&total, tot, 8, hipMemcpyDeviceToHost, s));
+      EIPC_HIP(c, hipStreamSynchronize(s));
+      *n_out = total;
+      if (total <= capa) {
+        if (grown) *grown = out;
+        return EIPC_OK;
+      }
+      if (grow_id < 0) return EIPC_ERR_CAPACITY;
+      capa = total + total / 4 + 1024;
+      EIPC_TRY(ensure_t(c, (BufId)grow_id, (size_t)2 * capa, &out));
+    }
+    return set_err(c, EIPC_ERR_CAPACITY, "candidate append did not converge");
+  }
   int32_t *qcnt;
   int64_t *qoff;
   EIPC_TRY(ensure_t(c, B_QCNT, (size_t)nq, &qcnt));
@@ -581,11 +697,9 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   {
     ProfScope ps(c, kind == 0 ? K_QUERY_COUNT_PT : K_QUERY_COUNT_EE, s);
     if (kind == 0)
-      k_query<0><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr,
-                                                    qcnt, nullptr, nullptr, 0, 0);
+      launch_query<0, 0>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, nullptr, nullptr, 0, nullptr, s);
     else
-      k_query<1><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr,
-                                                    qcnt, nullptr, nullptr, 0, 0);
+      launch_query<1, 0>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, nullptr, nullptr, 0, nullptr, s);
   }
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, qcnt, nq, qoff, s));
@@ -602,11 +716,9 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   if (total == 0) return EIPC_OK;
   ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
   if (kind == 0)
-    k_query<0><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
-                                                  qoff, out, 1, sort);
+    launch_query<0, 1>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, qoff, out, cap, nullptr, s);
   else
-    k_query<1><<<grid_for(nq, 128), 128, 0, s>>>(nq, qbox, ni, ibox, g, sc->faces, sc->edges, sc->W_rowptr, qcnt,
-                                                  qoff, out, 1, sort);
+    launch_query<1, 1>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, qoff, out, cap, nullptr, s);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }
