@@ -49,6 +49,8 @@ def _args():
                     help="oracle CPU baseline: number of sampled query primitives per kind")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -157,6 +159,13 @@ def main():
         alpha, ncand, capped = E.ccd_max_step(ctx, dsc, q, dq, sc.dhat)
         info.update(pt=pt, ee=ee, r=r, alpha=alpha, ncand=ncand, capped=capped)
 
+    if a.copy_calibration_mib:
+        src = torch.ones(a.copy_calibration_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()

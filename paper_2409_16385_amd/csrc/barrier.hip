@@ -520,23 +520,39 @@ __global__ void k_hash_rowfill(int64_t cap, const int32_t *hkey, int n_node, con
   }
 }
 
+// Sort each BSR row by column: one wavefront per row; rows of at most 64
+// blocks by rank (columns of a row are distinct), longer rows by insertion.
 __global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int64_t *bsrc, int32_t *rowptr32) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (r > n_node) return;
-  rowptr32[r] = (int32_t)rowptr[r];
+  if (lane == 0) rowptr32[r] = (int32_t)rowptr[r];
   if (r == n_node) return;
   const int64_t b = rowptr[r], e = rowptr[r + 1];
-  for (int64_t i = b + 1; i < e; ++i) {
-    const int32_t cv = bcol[i];
-    const int64_t sv = bsrc[i];
-    int64_t j = i - 1;
-    while (j >= b && bcol[j] > cv) {
-      bcol[j + 1] = bcol[j];
-      bsrc[j + 1] = bsrc[j];
-      --j;
+  const int64_t len = e - b;
+  if (len <= 64) {
+    const bool v = lane < len;
+    const int32_t cv = v ? bcol[b + lane] : 0x7fffffff;
+    const int64_t sv = v ? bsrc[b + lane] : 0;
+    int rank = 0;
+    for (int j = 0; j < len; ++j) rank += __shfl(cv, j, 64) < cv;
+    if (v) {
+      bcol[b + rank] = cv;
+      bsrc[b + rank] = sv;
     }
-    bcol[j + 1] = cv;
-    bsrc[j + 1] = sv;
+  } else if (lane == 0) {
+    for (int64_t i = b + 1; i < e; ++i) {
+      const int32_t cv = bcol[i];
+      const int64_t sv = bsrc[i];
+      int64_t j = i - 1;
+      while (j >= b && bcol[j] > cv) {
+        bcol[j + 1] = bcol[j];
+        bsrc[j + 1] = bsrc[j];
+        --j;
+      }
+      bcol[j + 1] = cv;
+      bsrc[j + 1] = sv;
+    }
   }
 }
 
@@ -579,7 +595,7 @@ eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out
   EIPC_TRY(ensure_t(c, B_ROWCNT, (size_t)n_node + 1, &rp32));  // reuse: counts no longer needed
   k_hash_rowfill<<<grid_for(cap, 256), 256, 0, s>>>(cap, h.hkey, n_node, rowptr, rowfill, bcol, bsrc);
   EIPC_HIP(c, hipGetLastError());
-  k_row_sort<<<grid_for(n_node + 1, 128), 128, 0, s>>>(n_node, rowptr, bcol, bsrc, rp32);
+  k_row_sort<<<grid_for((int64_t)(n_node + 1) * 64, 256), 256, 0, s>>>(n_node, rowptr, bcol, bsrc, rp32);
   EIPC_HIP(c, hipGetLastError());
   if (nnzb) {
     k_bsr_gather<<<grid_for(nnzb, 256), 256, 0, s>>>(nnzb, bsrc, h.hval, blocks);
@@ -605,81 +621,129 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
     const int64_t *__restrict__ d_count, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ xs, const double *__restrict__ xvs, const double *__restrict__ x_rest, int n_vert,
-    double dhat, double kappa, uint32_t flags, double *out, double *out_off) {
-  const int64_t n = *d_count;
+    int n_node, double dhat, double kappa, uint32_t flags, double *out, double *out_off, uint32_t *status) {
+  __shared__ int s_gkey[LGT];
+  __shared__ double s_gval[LGT * 3];
+  __shared__ int s_used;
+  LdsTables T{nullptr, nullptr, s_gkey, s_gval};
+  HessOut none{0, nullptr, nullptr, nullptr, 0};
+  Acc A{T, none, n_node, out, status};
   const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
-  for (int64_t i = (int64_t)blockIdx.x * BR_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BR_THREADS) {
-    const int64_t k = act[i];
-    const int ty = typ[i];
-    int vid[4];
-    pair_vertices<KIND>(pairs, k, faces, edges, vid);
-    V3 x[4], z[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      x[a] = load3(xs, n_vert, vid[a]);
-      z[a] = load3(xvs, n_vert, vid[a]);
-    }
-    const double s2 = type_value<KIND>(ty, x);
-    double eps = 0.0;
-    if (moll) {
-      V3 r[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
-      eps = mollifier_eps(r);
-    }
-    V3 Y[3];
-    y_basis<KIND>(x, Y);
-    double gE[9], HE[45], M[45];
-    energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, true);
-    to_q_basis<KIND>(HE, M);
-    if (flags & EIPC_PROJECT) project_psd9(M);
-    double zeta[9], eta[9];
-#pragma unroll
-    for (int al = 0; al < 3; ++al) {
-      double zx = 0, zy = 0, zz = 0;
+  for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = -1;
+  for (int t = threadIdx.x; t < LGT * 3; t += BR_THREADS) s_gval[t] = 0.0;
+  __syncthreads();
+  const int64_t n = *d_count;
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + BR_THREADS - 1) / BR_THREADS * BR_THREADS;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  for (int64_t base = r0; base < r1; base += BR_THREADS) {
+    const int64_t i = base + threadIdx.x;
+    const bool active = i < r1;
+    double eta[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int vid[4] = {0, 0, 0, 0};
+    if (active) {
+      const int64_t k = act[i];
+      const int ty = typ[i];
+      pair_vertices<KIND>(pairs, k, faces, edges, vid);
+      V3 x[4], z[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const double sg = 0.5 * kS[a][al];
-        zx += sg * z[a].x;
-        zy += sg * z[a].y;
-        zz += sg * z[a].z;
+        x[a] = load3(xs, n_vert, vid[a]);
+        z[a] = load3(xvs, n_vert, vid[a]);
       }
-      zeta[3 * al] = zx;
-      zeta[3 * al + 1] = zy;
-      zeta[3 * al + 2] = zz;
-    }
+      const double s2 = type_value<KIND>(ty, x);
+      double eps = 0.0;
+      if (moll) {
+        V3 r[4];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      double acc = 0.0;
-#pragma unroll
-      for (int cc = 0; cc < 9; ++cc) acc += M[pidx(r, cc)] * zeta[cc];
-      eta[r] = acc;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      double y0 = 0, y1 = 0, y2 = 0;
+        for (int a = 0; a < 4; ++a)
+          r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
+        eps = mollifier_eps(r);
+      }
+      V3 Y[3];
+      y_basis<KIND>(x, Y);
+      double gE[9], HE[45], M[45];
+      energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, true);
+      to_q_basis<KIND>(HE, M);
+      if (flags & EIPC_PROJECT) project_psd9(M);
+      // zeta = Q^T z, eta = X zeta
+      double zeta[9];
 #pragma unroll
       for (int al = 0; al < 3; ++al) {
-        const double sg = 0.5 * kS[a][al];
-        y0 += sg * eta[3 * al];
-        y1 += sg * eta[3 * al + 1];
-        y2 += sg * eta[3 * al + 2];
+        double zx = 0, zy = 0, zz = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double sg = 0.5 * kS[a][al];
+          zx += sg * z[a].x;
+          zy += sg * z[a].y;
+          zz += sg * z[a].z;
+        }
+        zeta[3 * al] = zx;
+        zeta[3 * al + 1] = zy;
+        zeta[3 * al + 2] = zz;
+      }
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        double acc = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 9; ++cc) acc += M[pidx(r, cc)] * zeta[cc];
+        eta[r] = acc;
       }
       if (out_off) {
-        atomicAdd(&out_off[3 * (int64_t)vid[a]], y0);
-        atomicAdd(&out_off[3 * (int64_t)vid[a] + 1], y1);
-        atomicAdd(&out_off[3 * (int64_t)vid[a] + 2], y2);
-      }
-      const int k0 = rowptr[vid[a]], k1 = rowptr[vid[a] + 1];
-      for (int kk = k0; kk < k1; ++kk) {
-        const double w = val[kk];
-        const int64_t I = col[kk];
-        atomicAdd(&out[3 * I], w * y0);
-        atomicAdd(&out[3 * I + 1], w * y1);
-        atomicAdd(&out[3 * I + 2], w * y2);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          double y0 = 0, y1 = 0, y2 = 0;
+#pragma unroll
+          for (int al = 0; al < 3; ++al) {
+            const double sg = 0.5 * kS[a][al];
+            y0 += sg * eta[3 * al];
+            y1 += sg * eta[3 * al + 1];
+            y2 += sg * eta[3 * al + 2];
+          }
+          atomicAdd(&out_off[3 * (int64_t)vid[a]], y0);
+          atomicAdd(&out_off[3 * (int64_t)vid[a] + 1], y1);
+          atomicAdd(&out_off[3 * (int64_t)vid[a] + 2], y2);
+        }
       }
     }
+    // reduced product through the merged node set: out[I] += z_I^T eta
+    NodeSet S;
+    int m = 0;
+    if (active) gather_nodes<KIND>(vid, rowptr, col, val, S, m);
+#pragma unroll
+    for (int sl = 0; sl < 16; ++sl) {
+      const bool v = active && sl < m;
+      if (__any(v)) {
+        double g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          g[c] = S.z[sl][0] * eta[c] + S.z[sl][1] * eta[3 + c] + S.z[sl][2] * eta[6 + c];
+        agg_vec(A, v, v ? S.node[sl] : -1, g[0], g[1], g[2]);
+      }
+    }
+    __syncthreads();
+    const bool last = base + BR_THREADS >= r1;
+    if (!last) {
+      if (threadIdx.x == 0) s_used = 0;
+      __syncthreads();
+      int cnt = 0;
+      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) cnt += s_gkey[t] != -1;
+      if (cnt) atomicAdd(&s_used, cnt);
+      __syncthreads();
+    }
+    if (last || s_used > LGT / 2) {
+      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) {
+        const int key = s_gkey[t];
+        if (key != -1) {
+          atomicAdd(&out[3 * (int64_t)key], s_gval[3 * t]);
+          atomicAdd(&out[3 * (int64_t)key + 1], s_gval[3 * t + 1]);
+          atomicAdd(&out[3 * (int64_t)key + 2], s_gval[3 * t + 2]);
+          s_gkey[t] = -1;
+          s_gval[3 * t] = s_gval[3 * t + 1] = s_gval[3 * t + 2] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -692,12 +756,12 @@ eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double
   ProfScope ps(c, kind == 0 ? K_HVP_PT : K_HVP_EE, s);
   if (kind == 0)
     k_hvp<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                            sc->W_val, xs, xvs, sc->x_rest, sc->n_vert, dhat, kappa, flags, out,
-                                            out_off);
+                                            sc->W_val, xs, xvs, sc->x_rest, sc->n_vert, sc->n_node, dhat, kappa,
+                                            flags, out, out_off, c->status);
   else
     k_hvp<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                            sc->W_val, xs, xvs, sc->x_rest, sc->n_vert, dhat, kappa, flags, out,
-                                            out_off);
+                                            sc->W_val, xs, xvs, sc->x_rest, sc->n_vert, sc->n_node, dhat, kappa,
+                                            flags, out, out_off, c->status);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }

@@ -271,30 +271,31 @@ __host__ __forceinline__ double ord_dec(uint64_t k) {
 
 // stats (uint64 view): [0..2] min lo (ordered), [3..5] max hi (ordered);
 // double view [6..8] sum of item extents.  Items from records, or vertex
-// (point) boxes when rec == nullptr.
-__global__ void k_box_stats(int n, const ItemRec *__restrict__ rec, const double *__restrict__ xs,
-                            const double *__restrict__ x1s, int n_vert, double h, uint64_t *st, int with_ext) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double lo[3], hi[3], ex[3];
-  if (i < n) {
+// (point) boxes when rec == nullptr.  Grid-stride, reduced per workgroup,
+// one atomic per workgroup and value.
+constexpr int STAT_T = 256;
+__global__ __launch_bounds__(STAT_T) void k_box_stats(int n, const ItemRec *__restrict__ rec,
+                                                      const double *__restrict__ xs, const double *__restrict__ x1s,
+                                                      int n_vert, double h, uint64_t *st, int with_ext) {
+  __shared__ double s_red[STAT_T / 64][9];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, ex[3] = {0, 0, 0};
+  for (int i = blockIdx.x * STAT_T + threadIdx.x; i < n; i += gridDim.x * STAT_T) {
+    double l[3], u[3];
     if (rec) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        lo[a] = rec[i].lo[a];
-        hi[a] = rec[i].hi[a];
+        l[a] = rec[i].lo[a];
+        u[a] = rec[i].hi[a];
       }
     } else {
       int v = i;
-      prim_box<1>(&v, xs, x1s, n_vert, h, lo, hi);
+      prim_box<1>(&v, xs, x1s, n_vert, h, l, u);
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) ex[a] = hi[a] - lo[a];
-  } else {
-#pragma unroll
     for (int a = 0; a < 3; ++a) {
-      lo[a] = INFINITY;
-      hi[a] = -INFINITY;
-      ex[a] = 0.0;
+      lo[a] = fmin(lo[a], l[a]);
+      hi[a] = fmax(hi[a], u[a]);
+      ex[a] += u[a] - l[a];
     }
   }
 #pragma unroll
@@ -305,7 +306,24 @@ __global__ void k_box_stats(int n, const ItemRec *__restrict__ rec, const double
       hi[a] = fmax(hi[a], __shfl_xor(hi[a], o, 64));
       ex[a] += __shfl_xor(ex[a], o, 64);
     }
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      s_red[w][a] = lo[a];
+      s_red[w][3 + a] = hi[a];
+      s_red[w][6 + a] = ex[a];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < STAT_T / 64; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fmin(lo[a], s_red[k][a]);
+        hi[a] = fmax(hi[a], s_red[k][3 + a]);
+        ex[a] += s_red[k][6 + a];
+      }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       atomicMin((unsigned long long *)&st[a], (unsigned long long)ord_key(lo[a]));
@@ -314,6 +332,8 @@ __global__ void k_box_stats(int n, const ItemRec *__restrict__ rec, const double
     }
   }
 }
+
+static int stat_blocks(int n) { return std::max(1, std::min(grid_for(n, STAT_T), 512)); }
 
 __global__ void k_stats_init(uint64_t *st) {
   int t = threadIdx.x;
@@ -584,8 +604,8 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   EIPC_HIP(c, hipGetLastError());
   uint64_t *st = (uint64_t *)c->stats;
   k_stats_init<<<1, 64, 0, s>>>(st);
-  k_box_stats<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, nullptr, nullptr, 0, h, st, 1);
-  if (kind == 0) k_box_stats<<<grid_for(nq, 256), 256, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, st, 0);
+  k_box_stats<<<stat_blocks(ni), STAT_T, 0, s>>>(ni, items, nullptr, nullptr, 0, h, st, 1);
+  if (kind == 0) k_box_stats<<<stat_blocks(nq), STAT_T, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, st, 0);
   EIPC_HIP(c, hipGetLastError());
   uint64_t hs[9];
   EIPC_HIP(c, hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));

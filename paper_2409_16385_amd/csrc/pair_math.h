@@ -537,15 +537,18 @@ __device__ __forceinline__ void to_q_basis(const double *H, double *M) {
 }
 
 // One Jacobi rotation zeroing a[p][q]; V accumulates the rotations.
+// Entries below thr (1e-20 of the matrix norm) are left alone: lanes keep
+// sweeping until the whole wavefront has converged, and rotating such
+// entries would square values that underflow.
 template <int P, int Q>
-__device__ __forceinline__ void jacobi_rot(double *a, double *v) {
+__device__ __forceinline__ void jacobi_rot(double *a, double *v, double thr) {
   const double apq = a[pidx(P, Q)];
   const double app = a[pidx(P, P)];
   const double aqq = a[pidx(Q, Q)];
   const double h = 0.5 * (aqq - app);
   const double r = sqrt(h * h + apq * apq);
   const double den = h >= 0.0 ? h + r : h - r;
-  const double t = (apq == 0.0) ? 0.0 : apq / den;
+  const double t = (fabs(apq) > thr && den != 0.0) ? apq / den : 0.0;
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = t * c;
   a[pidx(P, P)] = app - t * apq;
@@ -567,13 +570,13 @@ __device__ __forceinline__ void jacobi_rot(double *a, double *v) {
 }
 
 template <int P, int Q>
-__device__ __forceinline__ void jacobi_sweep_from(double *a, double *v) {
+__device__ __forceinline__ void jacobi_sweep_from(double *a, double *v, double thr) {
   if constexpr (P < 8) {
-    jacobi_rot<P, Q>(a, v);
+    jacobi_rot<P, Q>(a, v, thr);
     if constexpr (Q + 1 < 9)
-      jacobi_sweep_from<P, Q + 1>(a, v);
+      jacobi_sweep_from<P, Q + 1>(a, v, thr);
     else if constexpr (P + 2 < 9)
-      jacobi_sweep_from<P + 1, P + 2>(a, v);
+      jacobi_sweep_from<P + 1, P + 2>(a, v, thr);
   }
 }
 
@@ -591,6 +594,7 @@ __device__ __forceinline__ void project_psd9(double *a) {
   for (int i = 0; i < 9; ++i)
 #pragma unroll
     for (int j = i; j < 9; ++j) fro2 += (i == j ? 1.0 : 2.0) * a[pidx(i, j)] * a[pidx(i, j)];
+  const double thr = 1e-20 * sqrt(fro2);
   for (int sweep = 0; sweep < 16; ++sweep) {
     double off = 0.0;
 #pragma unroll
@@ -599,7 +603,7 @@ __device__ __forceinline__ void project_psd9(double *a) {
       for (int j = i + 1; j < 9; ++j) off += a[pidx(i, j)] * a[pidx(i, j)];
     const bool done = !(off > 1e-30 * fro2);
     if (__all(done)) break;
-    jacobi_sweep_from<0, 1>(a, v);
+    jacobi_sweep_from<0, 1>(a, v, thr);
   }
   double lam[9];
 #pragma unroll
