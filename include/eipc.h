@@ -164,6 +164,24 @@ eipc_status eipc_barrier_hvp(eipc_ctx *ctx, const eipc_scene *sc, const double *
                              uint32_t flags, const double *v, const double *v_off, double *out, double *out_off,
                              eipc_stream stream);
 
+/* ---- dense reduced Newton system (adjoint of a converged step) ---- */
+
+/* In-place dense FP64 Cholesky factorization A = L L^T of the reduced
+ * Newton matrix of one implicit step, H = M^q + h^2 (Hessian of the step's
+ * potentials) (Sec. III-A, Eq. 5-6; Sec. III-B, Eq. 10-12), which is
+ * symmetric positive definite at a strict minimum.  A is row-major, leading
+ * dimension lda >= n, device memory; only the lower triangle is read and L
+ * overwrites it (the strict upper triangle is left unchanged).  *info
+ * (host) receives 0 on success, or j+1 when the leading minor of order j+1
+ * is not positive definite (the factor is then not usable).
+ * Synchronizes. */
+eipc_status eipc_cholesky(eipc_ctx *ctx, double *A, int64_t n, int64_t lda, int64_t *info, eipc_stream stream);
+
+/* Solves A X = B with the factor written by eipc_cholesky.  B is row-major
+ * [n][nrhs] device memory and is overwritten by X. */
+eipc_status eipc_cholesky_solve(eipc_ctx *ctx, const double *L, int64_t n, int64_t lda, double *B, int64_t nrhs,
+                                eipc_stream stream);
+
 /* ---- optional kernel timing (benchmarks) ---- */
 
 /* Turn per-kernel timing on or off.  While on, the library brackets each

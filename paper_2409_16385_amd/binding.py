@@ -70,6 +70,8 @@ def _load():
         "eipc_ccd_toi": (_I32, [_P, _P, _P, _P, _P, _I32, _P, _I64, _D, _D, _I64, _P, _P, _P]),
         "eipc_fp64_selftest": (_I32, [_P, _P, _P, _P, _P, _I64, _P]),
         "eipc_profile": (_I32, [_P, _I32]),
+        "eipc_cholesky": (_I32, [_P, _P, _I64, _I64, _P, _P]),
+        "eipc_cholesky_solve": (_I32, [_P, _P, _I64, _I64, _P, _I64, _P]),
         "eipc_profile_read": (_I32, [_P, C.c_char_p, _P, _P, _I32]),
     }
     for name, (res, args) in sig.items():
@@ -384,6 +386,26 @@ def ccd_toi(ctx: Context, sc: Scene, q, dq, kind: int, pairs, dx_off=None, s: fl
                               float(s), float(t_max), int(max_iter), _ptr(t), _ptr(it), ctx.stream())
     ctx.check(st)
     return t[:n], it[:n]
+
+
+def cholesky(ctx: Context, A: torch.Tensor):
+    """In-place Cholesky of a square float64 device matrix (lower factor
+    overwrites the lower triangle).  Returns info (0 = success)."""
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[0] != A.shape[1] or not A.is_contiguous():
+        raise ValueError("A must be a contiguous square float64 tensor")
+    info = _I64()
+    ctx.check(_load().eipc_cholesky(ctx.handle, _ptr(A), A.shape[0], A.shape[1], C.byref(info), ctx.stream()))
+    return info.value
+
+
+def cholesky_solve(ctx: Context, L: torch.Tensor, B: torch.Tensor):
+    """Solve (L L^T) X = B in place; B is [n] or [n, nrhs] float64 (contiguous)."""
+    n = L.shape[0]
+    Bm = B.reshape(n, -1)
+    if not Bm.is_contiguous():
+        raise ValueError("B must be contiguous")
+    ctx.check(_load().eipc_cholesky_solve(ctx.handle, _ptr(L), n, L.shape[1], _ptr(Bm), Bm.shape[1], ctx.stream()))
+    return B
 
 
 def fp64_selftest(ctx: Context, a, b):
