@@ -1,13 +1,18 @@
 """Benchmark of the contact stage on one MI355X.
 
-One step = one full pass of the contact stage over a resident scene:
-candidate pairs (broad phase), barrier energy + reduced gradient + reduced
-PSD-projected Hessian (BSR) over all candidates (narrow phase inside), and
-the CCD step bound for a displacement dq.  Prints one JSON line.
+One step = one full pass of the contact stage over resident inputs:
+candidate pairs (broad phase), narrow phase, barrier energy + reduced
+gradient + reduced PSD-projected Hessian (BSR), and the conservative step
+bound for the search direction dq (swept broad phase + CCD).  The timed
+step is the planned, synchronization-free entry point replayed from a
+captured HIP graph; the plain per-call entry points are timed beside it.
+``--config batch`` runs 256 ragged grasp scenes as one batch and compares
+with 256 sequential single-scene calls.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -22,20 +27,23 @@ METRIC = "contact pairs/s (barrier+reduce) & CCD pairs/s, FP64, % HBM roofline"
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops per active pair (ENERGY|GRAD|HESS|PROJECT), by the
-# feature function of its distance type (point-point / point-line /
-# triple-product), in the 9-dimensional translation-free basis:
-#   distance derivatives          30 / 350 / 700
-#   barrier chain rule            220
-#   basis change G^T H G          200
-#   9x9 eigen-projection          9 n^3 + 2 n^2 (n+1)/2 = 6561 + 810
-#   12x12 blocks Q X Q^T          810
-#   W expansion (16 weights)      136 block pairs x 19 = 2584
-#   gradient expansion            132
-FLOPS_COMMON = 220 + 200 + 6561 + 810 + 810 + 2584 + 132
+# Algorithmic FP64 flops per active pair, split by kernel.  Pair terms
+# (distance type fixed): derivatives of the feature function in the
+# 9-dimensional translation-free basis (point-point / point-line /
+# triple-product) + barrier chain rule + basis change + 9x9 Jacobi
+# eigen-projection (9 n^3) + reconstruction (2 n^2 (n+1) / 2).  Expansion:
+# blocks z_I^T X z_J over the merged nodes of the pair (16 weights, 136
+# block pairs) and the gradient expansion.
+FLOPS_TERMS = 220 + 200 + 6561 + 810
 FLOPS_DIST = {"PP": 30, "PL": 350, "TRI": 700}
+FLOPS_EXPAND = 810 + 2584 + 132
 PT_FN = ["PP", "PP", "PP", "PL", "PL", "PL", "TRI"]
 EE_FN = ["PP", "PP", "PP", "PP", "PL", "PL", "PL", "PL", "TRI"]
+FAMILIES = {
+    "query": ("query_count_pt", "query_count_ee", "query_write_pt", "query_write_ee"),
+    "pair_terms": ("barrier_pt", "barrier_ee"), "expand": ("expand_pt", "expand_ee"),
+    "narrow": ("narrow_pt", "narrow_ee"), "ccd": ("ccd_pt", "ccd_ee"), "embed": ("embed",),
+}
 
 
 def _args():
@@ -43,12 +51,15 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3"])
+    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "batch"])
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n-scene", type=int, default=256, help="scenes in the batch config")
     ap.add_argument("--cpu-queries", type=int, default=2000,
                     help="oracle CPU baseline: number of sampled query primitives per kind")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--no-graph", action="store_true", help="time eager planned steps instead of graph replays")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -57,6 +68,49 @@ def _args():
 def make_scene(name, seed):
     import scenes
     return {"config1": scenes.config1, "config2": scenes.config2, "config3": scenes.config3}[name](seed)
+
+
+def _batch_one(i):
+    from scenes import scene as S
+    return S.batch_scenes(1, seed0=i)[0]
+
+
+def make_batch(n, seed0, log):
+    """The ragged grasp batch, generated in worker processes (spawned
+    before the GPU is touched)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        out = list(ex.map(_batch_one, range(seed0, seed0 + n), chunksize=4))
+    log(f"generated {n} batch scenes with {workers} processes in {time.perf_counter() - t0:.1f} s")
+    return out
+
+
+def source_digest():
+    """Digest of the library sources (traffic counters are valid only for
+    the sources they were taken with)."""
+    h = hashlib.sha256()
+    for d in ("paper_2409_16385_amd/csrc", "include"):
+        for f in sorted(os.listdir(os.path.join(ROOT, d))):
+            with open(os.path.join(ROOT, d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from committed counter summaries, when taken
+    with the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    e = t.get(f"{workload}:{kernel}")
+    if not e or e.get("sources") != source_digest():
+        return None
+    return e.get("bytes_per_launch")
 
 
 def cpu_baseline(sc, n_queries, log):
@@ -69,9 +123,6 @@ def cpu_baseline(sc, n_queries, log):
     dof = np.diff(sc.W_rowptr) > 0
     x = O.embed(sc, sc.q)
     rng = np.random.default_rng(sc.seed + 99)
-    # sample queries among vertices/edges that have a DoF and lie near the
-    # other bodies' boxes: use every vertex/edge whose own dhat box meets
-    # another body's vertex within 2 dhat (cheap numpy filter on a grid)
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import connected_components
     e = sc.edges.astype(np.int64)
@@ -87,19 +138,17 @@ def cpu_baseline(sc, n_queries, log):
     base = code(keys + 1)
     order = np.argsort(base)
     sb = base[order]
+    bl = body[order]
     for dx in (-1, 0, 1):
         for dy in (-1, 0, 1):
             for dz in (-1, 0, 1):
                 c = code(keys + 1 + np.array([dx, dy, dz]))
                 lo = np.searchsorted(sb, c, side="left")
                 hi = np.searchsorted(sb, c, side="right")
-                has = hi > lo
-                # another body present in that cell?  compare with min/max body label in the cell
-                idx = np.nonzero(has)[0]
+                idx = np.nonzero(hi > lo)[0]
                 if len(idx) == 0:
                     continue
-                bl = body[order]
-                mn = np.minimum.reduceat(bl, lo[idx]) if len(idx) else None
+                mn = np.minimum.reduceat(bl, lo[idx])
                 mx = np.maximum.reduceat(bl, lo[idx])
                 other = (mn != body[idx]) | (mx != body[idx])
                 near[idx[other]] = True
@@ -126,134 +175,240 @@ def cpu_baseline(sc, n_queries, log):
                        f"or_barrier_reduce energy+grad+projected dense Hessian, 1 thread, {t_red:.2f} s")}
 
 
+def _timed(fn, reps, sync):
+    fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    sync()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def _rooflines(prof, n_steps, work, workload):
+    """Per-family averages and the roofline entry of the dominant family.
+    work: active pairs per type, candidate and query counts of one step."""
+    fam_ms = {f: sum(prof.get(k, (0.0, 0))[0] for k in ks) / n_steps for f, ks in FAMILIES.items()}
+    launches = {k: v[1] for k, v in prof.items() if v[1]}
+    dom = max(fam_ms, key=fam_ms.get)
+    kernels = [k for k in FAMILIES[dom] if prof.get(k, (0, 0))[1]]
+    # dominant single kernel of that family
+    kdom = max(kernels, key=lambda k: prof[k][0])
+    ms, n = prof[kdom]
+    avg_s = ms / n / 1e3
+    ent = {"kernel": kdom, "family": dom, "avg_launch_us": avg_s * 1e6, "traffic": None}
+    if dom in ("pair_terms", "expand"):
+        kind = 0 if kdom.endswith("_pt") else 1
+        per = work["terms_flops"][kind] if dom == "pair_terms" else FLOPS_EXPAND * work["active"][kind]
+        ach = per / avg_s / 1e12
+        ent.update(bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s", frac=ach / PEAK_FP64_TFLOPS,
+                   per_unit=(f"{FLOPS_TERMS}+distance flop per active pair" if dom == "pair_terms"
+                             else f"{FLOPS_EXPAND} flop per active pair"))
+    else:
+        # compulsory bytes: query = query records + item table + pairs out;
+        # narrow = pair ids + 4 gathered vertices + type/index out;
+        # ccd = pair ids + 4 vertices x (x, p)
+        kind = 0 if kdom.endswith("_pt") else 1
+        if dom == "query":
+            swept = kdom.startswith("query_write") and work.get("swept_query", False)
+            nq, ni = work["n_query"][kind], work["n_item"][kind]
+            qb = (24 if kind == 0 else 64)
+            ncand = work["cand"][kind]
+            nbytes = nq * qb + ni * 64 + 8 * ncand
+            per_unit = f"{qb} B per query + 64 B per item + 8 B per candidate"
+        elif dom == "narrow":
+            nbytes = work["cand"][kind] * (8 + 4 * 24) + 8 * work["active"][kind]
+            per_unit = "104 B per candidate + 8 B per active pair"
+        elif dom == "ccd":
+            nbytes = work["swept"][kind] * (8 + 4 * 48)
+            per_unit = "200 B per swept candidate"
+        else:
+            nbytes = work["n_vert"] * (24 + 24 + 16 * 4)
+            per_unit = "112 B per vertex"
+        ach = nbytes / avg_s / 1e9
+        ent.update(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS,
+                   per_unit=per_unit)
+        tb = load_traffic(kdom, workload)
+        if tb is not None:
+            ent["traffic"] = tb
+    ent["family_ms_per_step"] = {f: round(v, 4) for f, v in fam_ms.items()}
+    ent["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1]}
+    for k, kind in (("barrier_pt", 0), ("barrier_ee", 1)):
+        if prof.get(k, (0, 0))[1]:
+            s_ = prof[k][0] / prof[k][1] / 1e3
+            ent[f"{k}_tflops"] = work["terms_flops"][kind] / s_ / 1e12
+    ent["launches"] = launches
+    return ent
+
+
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
+                                   "(a multi-GPU run would shard scenes or pairs, see the design notes)",
                           "n_gpus": a.gpus}), flush=True)
         sys.exit(2)
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    batch_scenes = make_batch(a.n_scene, a.seed, log) if a.config == "batch" else None
+
     import numpy as np
     import torch
 
     import paper_2409_16385_amd as E
+    from paper_2409_16385_amd import batch as BT
 
+    dev = torch.device("cuda", 0)
+    sync = lambda: torch.cuda.synchronize(dev)  # noqa: E731
     t0 = time.perf_counter()
-    sc = make_scene(a.config, a.seed)
-    log(f"{sc.summary()} (generated in {time.perf_counter() - t0:.1f} s)")
+    if batch_scenes is None:
+        sc = make_scene(a.config, a.seed)
+        log(f"{sc.summary()} (generated in {time.perf_counter() - t0:.1f} s)")
+        scenes_list = [sc]
+    else:
+        scenes_list = batch_scenes
     ctx = E.Context(0)
-    dev = ctx.torch_device
-    dsc = E.Scene.from_host(ctx, sc)
-    q = torch.as_tensor(sc.q, device=dev)
-    dq = torch.as_tensor(sc.dq, device=dev)
     flags = E.ENERGY | E.GRAD | E.HESS | E.PROJECT | (E.MOLLIFY if a.config == "config3" else 0)
-
-    info = {}
-
-    def step():
-        pt, ee = E.build_candidates(ctx, dsc, q, sc.dhat)
-        r = E.barrier_reduce(ctx, dsc, q, pt, ee, sc.dhat, sc.kappa, flags, hess="bsr", count=False)
-        alpha, ncand, capped = E.ccd_max_step(ctx, dsc, q, dq, sc.dhat)
-        info.update(pt=pt, ee=ee, r=r, alpha=alpha, ncand=ncand, capped=capped)
-
+    hb = BT.concat(scenes_list)
+    bt = BT.Batch(ctx, hb, flags=flags)
     if a.copy_calibration_mib:
         src = torch.ones(a.copy_calibration_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
-        torch.cuda.synchronize()
+        sync()
         del src, dst
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    # workload counts (outside the timed region)
-    pt, ee = info["pt"], info["ee"]
-    ap, tp, ae, te = E.narrow_phase(ctx, dsc, q, pt, ee, sc.dhat)
-    n_act_pt, n_act_ee = int(ap.numel()), int(ae.numel())
-    n_active = n_act_pt + n_act_ee
-    tpc = np.bincount(tp.cpu().numpy(), minlength=7)
-    tec = np.bincount(te.cpu().numpy(), minlength=9)
-    flops_pt = sum(int(tpc[i]) * (FLOPS_COMMON + FLOPS_DIST[PT_FN[i]]) for i in range(7))
-    flops_ee = sum(int(tec[i]) * (FLOPS_COMMON + FLOPS_DIST[EE_FN[i]]) for i in range(9))
-    log(f"candidates pt={pt.shape[0]} ee={ee.shape[0]} active pt={n_act_pt} ee={n_act_ee} "
-        f"ccd candidates={info['ncand']} alpha={info['alpha']:.6g} nnzb={info['r']['hess'][1].numel()}")
-    log(f"PT types {tpc.tolist()} EE types {tec.tolist()}")
+    tuning = None
+    if not a.no_autotune:
+        t1 = time.perf_counter()
+        tuning = bt.autotune(reps=2)
+        log(f"autotune: cell_scale={tuning['cell_scale']} wg_per_cu={tuning['wg_per_cu']} "
+            f"({time.perf_counter() - t1:.1f} s)")
+    else:
+        bt.make_plan(1.5)
+    plan = bt.plan.as_dict()
+    log(f"plan: {plan}")
 
+    # workload (outside the timed region): counts and active pairs per type
+    bt.step()
+    st = bt.status()
+    if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):
+        raise RuntimeError(f"planned step failed with status {st}")
+    cnt = bt.counts()
+    n_active = cnt["active"]
+    swept = cnt["swept_pt"] + cnt["swept_ee"]
+    tpc = np.zeros(7, dtype=np.int64)
+    tec = np.zeros(9, dtype=np.int64)
+    dsc = bt.scene
+    q = bt.q
+    pt, ee = E.build_candidates(ctx, dsc, q, hb.dhat)
+    ap, tp, ae, te = E.narrow_phase(ctx, dsc, q, pt, ee, hb.dhat)
+    tpc += np.bincount(tp.cpu().numpy(), minlength=7)
+    tec += np.bincount(te.cpu().numpy(), minlength=9)
+    assert int(ap.numel() + ae.numel()) == n_active and pt.shape[0] == cnt["cand_pt"] and ee.shape[0] == cnt["cand_ee"]
+    terms_pt = sum(int(tpc[i]) * (FLOPS_TERMS + FLOPS_DIST[PT_FN[i]]) for i in range(7))
+    terms_ee = sum(int(tec[i]) * (FLOPS_TERMS + FLOPS_DIST[EE_FN[i]]) for i in range(9))
+    work = {"active": (int(ap.numel()), int(ae.numel())), "cand": (cnt["cand_pt"], cnt["cand_ee"]),
+            "swept": (cnt["swept_pt"], cnt["swept_ee"]), "terms_flops": (terms_pt, terms_ee),
+            "n_query": (hb.W_rowptr.size - 1, hb.edges.shape[0]), "n_item": (hb.faces.shape[0], hb.edges.shape[0]),
+            "n_vert": hb.W_rowptr.size - 1}
+    log(f"candidates pt={cnt['cand_pt']} ee={cnt['cand_ee']} active pt={work['active'][0]} "
+        f"ee={work['active'][1]} swept={swept} PT types {tpc.tolist()} EE types {tec.tolist()}")
+    del pt, ee, ap, tp, ae, te
+
+    # timed region: graph replays (or eager planned steps)
+    use_graph = not a.no_graph
+    if use_graph:
+        bt.capture()
+    run = bt.replay if use_graph else bt.step
+    for _ in range(a.warmup):
+        run()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        run()
+    sync()
+    elapsed = time.perf_counter() - t0
+    st = bt.status()
+    if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):
+        raise RuntimeError(f"timed steps reported status {st}")
+    ms_per_step = 1e3 * elapsed / a.steps
+
+    # per-kernel event profile of eager planned steps (same kernels)
+    prof = {}
     if not a.no_profile:
         ctx.profile(True)
         ctx.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / a.steps
-    prof = ctx.profile_read(reset=True) if not a.no_profile else {}
-    ctx.profile(False)
-    for k, (ms, n) in prof.items():
-        if n:
-            log(f"kernel {k:16s} {ms / n * 1e3:10.1f} us/launch x {n}")
+        n_prof = max(3, min(a.steps, 10))
+        for _ in range(n_prof):
+            bt.step()
+        prof = ctx.profile_read(reset=True)
+        ctx.profile(False)
+        for k, (ms, n) in prof.items():
+            if n:
+                log(f"kernel {k:16s} {ms / n * 1e3:10.1f} us/launch x {n}")
+    workload = a.config
+    roofline = _rooflines(prof, max(3, min(a.steps, 10)), work, workload) if prof else None
 
-    # call-level breakdown with events (separate short run)
-    ev = {}
-    for name, fn in (("candidates", lambda: E.build_candidates(ctx, dsc, q, sc.dhat)),
-                     ("barrier_reduce", lambda: E.barrier_reduce(ctx, dsc, q, pt, ee, sc.dhat, sc.kappa, flags,
-                                                                 hess="bsr", count=False)),
-                     ("ccd", lambda: E.ccd_max_step(ctx, dsc, q, dq, sc.dhat))):
-        fn()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(5):
-            fn()
-        torch.cuda.synchronize()
-        ev[name] = 1e3 * (time.perf_counter() - t1) / 5
-
-    # dominant kernel and its roofline
-    roofline = None
-    if prof:
-        dom = max(prof, key=lambda k: prof[k][0])
-        ms, n = prof[dom]
-        avg_s = ms / n / 1e3
-        if dom in ("barrier_pt", "barrier_ee"):
-            fl = flops_pt if dom == "barrier_pt" else flops_ee
-            ach = fl / avg_s / 1e12
-            roofline = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                        "frac": ach / PEAK_FP64_TFLOPS, "traffic": None, "kernel": dom,
-                        "avg_launch_us": avg_s * 1e6,
-                        "per_unit": f"{FLOPS_COMMON}+dist flop per active pair"}
-        else:
-            roofline = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                        "frac": None, "traffic": None, "kernel": dom, "avg_launch_us": avg_s * 1e6}
-        roofline["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1]}
-        # the barrier kernels' own roofline is reported too
-        for k, fl in (("barrier_pt", flops_pt), ("barrier_ee", flops_ee)):
-            if prof.get(k, (0, 0))[1]:
-                s_ = prof[k][0] / prof[k][1] / 1e3
-                roofline[f"{k}_tflops"] = fl / s_ / 1e12
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(sc, a.cpu_queries, log)
-
-    value = n_active / (ms_per_step / 1e3)
     out = {
-        "metric": METRIC, "value": value, "unit": "contact pairs/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{a.config} ({sc.name}): n_vert={sc.n_vert} n_face={sc.n_face} "
-                               f"n_edge={sc.n_edge} n_node={sc.n_node} dhat={sc.dhat:g}",
-                   "active_pairs": n_active, "candidates": int(pt.shape[0] + ee.shape[0]),
-                   "ccd_candidates": info["ncand"], "seed": a.seed},
-        "barrier_reduce_pairs_per_s": n_active / (ev["barrier_reduce"] / 1e3),
-        "ccd_pairs_per_s": info["ncand"] / (ev["ccd"] / 1e3),
-        "call_ms": ev, "alpha": info["alpha"],
-        "roofline": roofline, "cpu_baseline": cpu,
+        "metric": METRIC, "value": n_active / (ms_per_step / 1e3), "unit": "contact pairs/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
     }
+    if a.config == "batch":
+        # 256 sequential single-scene calls on the same scenes
+        dscs = [E.Scene.from_host(ctx, s) for s in scenes_list]
+        BT.sequential_reference(ctx, scenes_list[:4], dscs[:4])
+        _, t_seq = BT.sequential_reference(ctx, scenes_list, dscs)
+        nv = np.diff(hb.vert_off)
+        out["config"] = {"workload": (f"batch of {hb.n_scene} ragged grasp scenes (objects 2e3-5e4 triangles, "
+                                      f"100-2000 coarse nodes, fingers 2x5120 triangles, random SE(3)): "
+                                      f"n_vert={int(hb.vert_off[-1])} n_face={hb.faces.shape[0]} "
+                                      f"n_node={hb.n_node} dhat={hb.dhat:g}"),
+                         "n_scene": hb.n_scene, "active_pairs": n_active,
+                         "candidates": cnt["cand_pt"] + cnt["cand_ee"], "ccd_candidates": swept,
+                         "verts_per_scene_min_max": [int(nv.min()), int(nv.max())], "seed0": a.seed}
+        out["scenes_per_s"] = hb.n_scene / (ms_per_step / 1e3)
+        out["sequential_ms"] = 1e3 * t_seq
+        out["sequential_scenes_per_s"] = hb.n_scene / t_seq
+        out["sequential_pairs_per_s"] = n_active / t_seq
+        out["batch_speedup"] = (t_seq * 1e3) / ms_per_step
+    else:
+        sc = scenes_list[0]
+        out["config"] = {"workload": f"{a.config} ({sc.name}): n_vert={sc.n_vert} n_face={sc.n_face} "
+                                     f"n_edge={sc.n_edge} n_node={sc.n_node} dhat={sc.dhat:g}",
+                         "active_pairs": n_active, "candidates": cnt["cand_pt"] + cnt["cand_ee"],
+                         "ccd_candidates": swept, "seed": a.seed}
+        # plain per-call entry points, for comparison
+        q0 = torch.as_tensor(sc.q, device=dev)
+        dq0 = torch.as_tensor(sc.dq, device=dev)
+        dsc0 = E.Scene.from_host(ctx, sc)
+        pt, ee = E.build_candidates(ctx, dsc0, q0, sc.dhat)
+        ev = {"candidates": _timed(lambda: E.build_candidates(ctx, dsc0, q0, sc.dhat), 5, sync),
+              "barrier_reduce": _timed(lambda: E.barrier_reduce(ctx, dsc0, q0, pt, ee, sc.dhat, sc.kappa, flags,
+                                                                hess="bsr", count=False), 5, sync),
+              "ccd": _timed(lambda: E.ccd_max_step(ctx, dsc0, q0, dq0, sc.dhat), 5, sync)}
+        out["call_ms"] = ev
+        out["plain_calls_ms_per_step"] = sum(ev.values())
+        out["barrier_reduce_pairs_per_s"] = n_active / (ev["barrier_reduce"] / 1e3)
+        out["ccd_pairs_per_s"] = swept / (ev["ccd"] / 1e3)
+    out["timed"] = "graph replay of the planned step" if use_graph else "eager planned step"
+    out["alpha_min"] = float(bt.out.alpha.min().item())
+    out["tuning"] = None if tuning is None else {"cell_scale": tuning["cell_scale"],
+                                                 "wg_per_cu": tuning["wg_per_cu"]}
+    out["roofline"] = roofline
+    out["cpu_baseline"] = None
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scenes_list[0] if a.config != "batch" else _largest(scenes_list),
+                                           a.cpu_queries, log)
+    out["sources"] = source_digest()
     print(json.dumps(out), flush=True)
+
+
+def _largest(scenes_list):
+    return max(scenes_list, key=lambda s: s.n_face)
 
 
 if __name__ == "__main__":

@@ -47,6 +47,9 @@ enum {
   EIPC_ERR_HIP = -6,          /* a HIP runtime call failed; see eipc_last_error */
   EIPC_WARN_CCD_CAPPED = 1    /* CCD hit its per-pair iteration cap (the bound is still safe) */
 };
+/* A planned call that exceeded a capacity of its plan reports
+ * EIPC_ERR_CAPACITY through eipc_sync_status; its outputs are then not
+ * valid and the caller plans again with a larger margin. */
 
 /* flags for eipc_barrier_reduce / eipc_barrier_hvp */
 enum {
@@ -67,7 +70,16 @@ typedef void *eipc_stream; /* hipStream_t */
  * position-controlled grippers of Sec. IV-A).  A row with a single weight
  * 1 is a full-space vertex (W = I is full-space IPC, Sec. III-D).  A row
  * holds at most 4 weights (the nodes of one tetrahedron); a longer row is
- * reported as EIPC_ERR_ARG by the next call that synchronizes. */
+ * reported as EIPC_ERR_ARG by the next call that synchronizes.
+ *
+ * A batch of independent scenes is one eipc_scene whose arrays are the
+ * concatenations of the scenes' arrays, with indices already offset to the
+ * concatenation (global vertex and node numbers), plus n_scene > 1 and
+ * vert_scene[v] = the scene of vertex v.  Every face, edge and W row must
+ * stay within one scene.  Pairs never join two scenes, outputs per scene
+ * (energy, step bound) are arrays of n_scene, and the reduced vectors are
+ * the concatenated per-scene vectors.  n_scene <= 65536.  n_scene = 0 or 1
+ * is one scene and vert_scene is then ignored. */
 typedef struct {
   int32_t n_vert, n_node, n_face, n_edge;
   const int32_t *faces;    /* [n_face*3] vertex indices */
@@ -77,6 +89,8 @@ typedef struct {
   const double *W_val;     /* [nnz] weights */
   const double *x_off;     /* [n_vert*3] added to W q (static / kinematic positions), or NULL */
   const double *x_rest;    /* [n_vert*3] rest positions for the EE mollifier, or NULL */
+  int32_t n_scene;         /* scenes in a batch (0 or 1: a single scene) */
+  const int32_t *vert_scene; /* [n_vert] scene id per vertex when n_scene > 1 */
 } eipc_scene;
 
 /* Reduced Hessian in 3x3 block-sparse rows (both triangles stored, columns
@@ -84,7 +98,7 @@ typedef struct {
  * until the next call on that context. */
 typedef struct {
   int32_t n_rows;         /* = n_node */
-  int64_t nnzb;           /* number of stored 3x3 blocks */
+  int64_t nnzb;           /* number of stored 3x3 blocks (-1: only on the device, as rowptr[n_rows]) */
   const int32_t *rowptr;  /* [n_rows+1] */
   const int32_t *col;     /* [nnzb] */
   const double *blocks;   /* [nnzb*9] row-major 3x3 */
@@ -125,14 +139,15 @@ eipc_status eipc_build_candidates(eipc_ctx *ctx, const eipc_scene *sc, const dou
  * distance between the closed primitives; its energy is kappa * b(d)
  * (times the mollifier m(|ea x eb|^2) for EE pairs with EIPC_MOLLIFY).
  * Pass kappa * h^2 to obtain the h^2-scaled barrier term of E_IPC.
- *   energy    device double[1] or NULL: total energy (overwritten)
+ *   energy    device double[n_scene] or NULL: energy per scene (overwritten)
  *   grad_q    device double[3*n_node] or NULL: W^T g (overwritten)
  *   hess_dense device double[(3*n_node)^2] or NULL: W^T H W, row-major
  *   hess_bsr  host struct or NULL: filled with a context-owned BSR view
  * H is the per-pair PSD projection when EIPC_PROJECT is set, else the true
  * pair Hessian.  n_active (host) or NULL receives the number of active
  * pairs.  Synchronizes when n_active or hess_bsr is requested.
- * An active pair with d == 0 raises EIPC_ERR_INTERSECTING. */
+ * An active pair with d == 0 raises EIPC_ERR_INTERSECTING.  The reduced
+ * Hessian needs n_node < 2^31 / 3 rows. */
 eipc_status eipc_barrier_reduce(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
                                 int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
                                 uint32_t flags, double *energy, double *grad_q, double *hess_dense,
@@ -144,7 +159,8 @@ eipc_status eipc_barrier_reduce(eipc_ctx *ctx, const eipc_scene *sc, const doubl
  * by additive conservative advancement with gap factor s (0 < s < 1) and
  * the minimum taken over all pairs whose swept boxes (start and end
  * positions, widened by dhat/2) overlap.  dx_off may be NULL.
- * alpha (host), n_cand (host, or NULL) receives the number of swept
+ * alpha (host double[n_scene]): the bound per scene; n_cand (host, or
+ * NULL) receives the number of swept
  * candidates.  Returns EIPC_WARN_CCD_CAPPED if some pair reached max_iter
  * iterations (alpha is still safe).  Synchronizes. */
 eipc_status eipc_ccd_max_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const double *dq,
@@ -163,6 +179,55 @@ eipc_status eipc_barrier_hvp(eipc_ctx *ctx, const eipc_scene *sc, const double *
                              int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
                              uint32_t flags, const double *v, const double *v_off, double *out, double *out_off,
                              eipc_stream stream);
+
+/* ---- planned contact step: one Newton iteration's contact stage with no
+ * host synchronization and no allocation (capturable in a HIP graph) ---- */
+
+/* Capacities of a planned step (element counts). */
+typedef struct {
+  int64_t cand_pt, cand_ee;   /* proximity candidates */
+  int64_t swept_pt, swept_ee; /* swept candidates for the step bound */
+  int64_t ent[4];             /* broad-phase hash entries: PT, EE, swept PT, swept EE */
+  int64_t buckets[4];         /* broad-phase hash buckets (powers of 2) */
+  int64_t hess_blocks;        /* reduced-Hessian block table (power of 2); 0: no Hessian */
+  int64_t nnzb;               /* BSR blocks */
+} eipc_plan;
+
+/* Measures a step at (q, dq, dx_off) with the synchronizing entry points
+ * and returns capacities of `margin` (>= 1) times what it needed, then
+ * reserves the context's scratch for them, so that eipc_contact_step
+ * allocates nothing while the plan holds.  with_hess != 0 plans the
+ * reduced-Hessian output.  Synchronizes. */
+eipc_status eipc_plan_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const double *dq,
+                           const double *dx_off, double dhat, double margin, int32_t with_hess, eipc_plan *plan,
+                           eipc_stream stream);
+
+/* One contact stage (Sec. III-B, III-C; Eq. 7, 10-11, 17): candidates at
+ * q (unsorted), active pairs, energy per scene, reduced gradient and
+ * (projected with EIPC_PROJECT) reduced Hessian, and the conservative step
+ * bound alpha per scene for the search direction dq (+ dx_off), with the
+ * semantics of eipc_build_candidates, eipc_barrier_reduce and
+ * eipc_ccd_max_step.  Enqueues work only: no synchronization, no
+ * allocation, no host-side reads of device data, so it can be captured in
+ * a HIP graph and replayed with new contents of q and dq.
+ *   energy   device double[n_scene] or NULL     grad_q  device double[3*n_node] or NULL
+ *   hess_bsr host struct or NULL (needs EIPC_HESS and plan->hess_blocks > 0): context-owned
+ *            BSR view with nnzb = -1 (the count is rowptr[n_rows] on the device)
+ *   alpha    device double[n_scene] or NULL: step bound per scene (dq may be NULL when NULL)
+ *   counts   device int64[5] or NULL: PT and EE candidates, active pairs, swept PT and EE
+ * Capacity overflow and data errors are reported by eipc_sync_status. */
+eipc_status eipc_contact_step(eipc_ctx *ctx, const eipc_scene *sc, const eipc_plan *plan, const double *q,
+                              const double *dq, const double *dx_off, double dhat, double kappa, uint32_t flags,
+                              double s, double t_max, int64_t max_iter, double *energy, double *grad_q,
+                              eipc_bsr *hess_bsr, double *alpha, int64_t *counts, eipc_stream stream);
+
+/* Launch shape of the library's kernels for this context: the broad-phase
+ * cell edge as a multiple of the mean primitive box extent (> 0), and the
+ * workgroups per compute unit of the grid-stride kernels (pair terms,
+ * expansion, narrow phase, CCD; each 1..64, 0 keeps the current value).
+ * Used by the batch autotuner; results do not depend on them except for
+ * the rounding order of sums. */
+eipc_status eipc_set_tuning(eipc_ctx *ctx, double cell_scale, const int32_t wg_per_cu[4]);
 
 /* ---- dense reduced Newton system (adjoint of a converged step) ---- */
 

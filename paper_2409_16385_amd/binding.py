@@ -34,11 +34,22 @@ class EipcError(RuntimeError):
 class _Scene(C.Structure):
     _fields_ = [("n_vert", _I32), ("n_node", _I32), ("n_face", _I32), ("n_edge", _I32),
                 ("faces", _P), ("edges", _P), ("W_rowptr", _P), ("W_col", _P), ("W_val", _P),
-                ("x_off", _P), ("x_rest", _P)]
+                ("x_off", _P), ("x_rest", _P), ("n_scene", _I32), ("vert_scene", _P)]
 
 
 class _Bsr(C.Structure):
     _fields_ = [("n_rows", _I32), ("nnzb", _I64), ("rowptr", _P), ("col", _P), ("blocks", _P)]
+
+
+class Plan(C.Structure):
+    """Capacities of a planned contact step (eipc_plan)."""
+    _fields_ = [("cand_pt", _I64), ("cand_ee", _I64), ("swept_pt", _I64), ("swept_ee", _I64),
+                ("ent", _I64 * 4), ("buckets", _I64 * 4), ("hess_blocks", _I64), ("nnzb", _I64)]
+
+    def as_dict(self) -> dict:
+        return {"cand_pt": self.cand_pt, "cand_ee": self.cand_ee, "swept_pt": self.swept_pt,
+                "swept_ee": self.swept_ee, "ent": list(self.ent), "buckets": list(self.buckets),
+                "hess_blocks": self.hess_blocks, "nnzb": self.nnzb}
 
 
 _lib = None
@@ -73,6 +84,9 @@ def _load():
         "eipc_cholesky": (_I32, [_P, _P, _I64, _I64, _P, _P]),
         "eipc_cholesky_solve": (_I32, [_P, _P, _I64, _I64, _P, _I64, _P]),
         "eipc_profile_read": (_I32, [_P, C.c_char_p, _P, _P, _I32]),
+        "eipc_plan_step": (_I32, [_P, _P, _P, _P, _P, _D, _D, _I32, _P, _P]),
+        "eipc_contact_step": (_I32, [_P, _P, _P, _P, _P, _P, _D, _D, _U32, _D, _D, _I64, _P, _P, _P, _P, _P, _P]),
+        "eipc_set_tuning": (_I32, [_P, _D, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -169,9 +183,11 @@ def _i32(t, dev):
 
 
 class Scene:
-    """Device copy of a scene: faces, edges, W (CSR), x_off, x_rest."""
+    """Device copy of a scene: faces, edges, W (CSR), x_off, x_rest; for a
+    batch also n_scene and the scene id of every vertex."""
 
-    def __init__(self, ctx: Context, faces, edges, W_rowptr, W_col, W_val, n_node, x_off=None, x_rest=None):
+    def __init__(self, ctx: Context, faces, edges, W_rowptr, W_col, W_val, n_node, x_off=None, x_rest=None,
+                 n_scene: int = 1, vert_scene=None):
         dev = ctx.torch_device
         self.ctx = ctx
         self.faces = _i32(faces, dev).reshape(-1, 3)
@@ -185,9 +201,11 @@ class Scene:
         self.n_node = int(n_node)
         self.n_face = self.faces.shape[0]
         self.n_edge = self.edges.shape[0]
+        self.n_scene = int(n_scene)
+        self.vert_scene = None if vert_scene is None else _i32(vert_scene, dev)
         self._s = _Scene(self.n_vert, self.n_node, self.n_face, self.n_edge, _ptr(self.faces), _ptr(self.edges),
                          _ptr(self.W_rowptr), _ptr(self.W_col), _ptr(self.W_val), _ptr(self.x_off),
-                         _ptr(self.x_rest))
+                         _ptr(self.x_rest), self.n_scene, _ptr(self.vert_scene))
 
     @classmethod
     def from_host(cls, ctx: Context, sc):
@@ -248,14 +266,14 @@ def barrier_reduce(ctx: Context, sc: Scene, q, pt, ee, dhat: float, kappa: float
                    count: bool = True):
     """Energy, reduced gradient and reduced Hessian ('bsr', 'dense' or None).
 
-    Returns a dict: energy (tensor [1]), grad (tensor [3 n_node] or None),
+    Returns a dict: energy (tensor [n_scene]), grad (tensor [3 n_node] or None),
     hess (dense tensor, or (rowptr, col, blocks) tensors for BSR, or None),
     n_active (int or None)."""
     dev = ctx.torch_device
     q = _f64(q, dev)
     pt = _i32(pt, dev).reshape(-1, 2)
     ee = _i32(ee, dev).reshape(-1, 2)
-    energy = torch.empty(1, dtype=torch.float64, device=dev) if flags & ENERGY else None
+    energy = torch.empty(max(sc.n_scene, 1), dtype=torch.float64, device=dev) if flags & ENERGY else None
     grad = torch.empty(3 * sc.n_node, dtype=torch.float64, device=dev) if flags & GRAD else None
     dense = None
     bsr = None
@@ -293,15 +311,17 @@ def _copy_bsr(ctx: Context, b: _Bsr):
 
 def ccd_max_step(ctx: Context, sc: Scene, q, dq, dhat: float, dx_off=None, s: float = 0.1, t_max: float = 1.0,
                  max_iter: int = 100000):
-    """Returns (alpha, n_candidates, capped)."""
+    """Returns (alpha, n_candidates, capped); alpha is a float for one
+    scene and a float64 array of n_scene values for a batch."""
     dev = ctx.torch_device
     q, dq, dx_off = _f64(q, dev), _f64(dq, dev), _f64(dx_off, dev)
-    a = _D()
+    a = (_D * max(sc.n_scene, 1))()
     nc = _I64()
     st = _load().eipc_ccd_max_step(ctx.handle, sc.ref, _ptr(q), _ptr(dq), _ptr(dx_off), float(dhat), float(s),
-                                   float(t_max), int(max_iter), C.byref(a), C.byref(nc), ctx.stream())
+                                   float(t_max), int(max_iter), a, C.byref(nc), ctx.stream())
     ctx.check(st, allow=(OK, WARN_CCD_CAPPED))
-    return a.value, nc.value, st == WARN_CCD_CAPPED
+    alpha = a[0] if sc.n_scene <= 1 else np.array(a[:], dtype=np.float64)
+    return alpha, nc.value, st == WARN_CCD_CAPPED
 
 
 def barrier_hvp(ctx: Context, sc: Scene, q, pt, ee, dhat: float, kappa: float, flags: int, v, v_off=None,
@@ -415,3 +435,62 @@ def fp64_selftest(ctx: Context, a, b):
     dv = torch.empty_like(a)
     ctx.check(_load().eipc_fp64_selftest(ctx.handle, _ptr(a), _ptr(b), _ptr(sq), _ptr(dv), a.numel(), ctx.stream()))
     return sq, dv
+
+
+def set_tuning(ctx: Context, cell_scale: float, wg_per_cu=(0, 0, 0, 0)):
+    """Broad-phase cell scale and workgroups per CU of the grid-stride
+    kernels (pair terms, expansion, narrow phase, CCD; 0 keeps a value)."""
+    w = (_I32 * 4)(*[int(v) for v in wg_per_cu])
+    ctx.check(_load().eipc_set_tuning(ctx.handle, float(cell_scale), w))
+
+
+def plan_step(ctx: Context, sc: Scene, q, dhat: float, dq=None, dx_off=None, margin: float = 1.5,
+              with_hess: bool = True) -> Plan:
+    """Capacities for contact_step measured at (q, dq) times `margin`;
+    reserves the context's scratch (synchronizes)."""
+    dev = ctx.torch_device
+    q, dq, dx_off = _f64(q, dev), _f64(dq, dev), _f64(dx_off, dev)
+    p = Plan()
+    ctx.check(_load().eipc_plan_step(ctx.handle, sc.ref, _ptr(q), _ptr(dq), _ptr(dx_off), float(dhat),
+                                     float(margin), 1 if with_hess else 0, C.byref(p), ctx.stream()))
+    return p
+
+
+class StepOut:
+    """Output tensors of contact_step (allocated once, reused by replays)."""
+
+    def __init__(self, ctx: Context, sc: Scene, plan: Plan, flags: int, with_alpha: bool = True):
+        dev = ctx.torch_device
+        ns = max(sc.n_scene, 1)
+        self.energy = torch.zeros(ns, dtype=torch.float64, device=dev) if flags & ENERGY else None
+        self.grad = torch.zeros(3 * sc.n_node, dtype=torch.float64, device=dev) if flags & GRAD else None
+        self.alpha = torch.zeros(ns, dtype=torch.float64, device=dev) if with_alpha else None
+        self.counts = torch.zeros(5, dtype=torch.int64, device=dev)
+        self.bsr = _Bsr() if (flags & HESS and plan.hess_blocks > 0) else None
+
+    def hess(self, ctx: Context):
+        """BSR of the last step as (rowptr, col, blocks) copies (synchronizes)."""
+        if self.bsr is None or not self.bsr.rowptr:
+            return None
+        b = _Bsr(self.bsr.n_rows, 0, self.bsr.rowptr, self.bsr.col, self.bsr.blocks)
+        rp = torch.empty(b.n_rows + 1, dtype=torch.int32, device=ctx.torch_device)
+        err = _hiprt().hipMemcpyAsync(_P(rp.data_ptr()), _P(b.rowptr), 4 * (b.n_rows + 1), 3, ctx.stream())
+        if err != 0:
+            raise EipcError(ERR_HIP, f"hipMemcpyAsync failed ({err})")
+        b.nnzb = int(rp[-1].item())
+        return _copy_bsr(ctx, b)
+
+
+def contact_step(ctx: Context, sc: Scene, plan: Plan, q, dhat: float, kappa: float, out: StepOut, dq=None,
+                 dx_off=None, flags: int = ENERGY | GRAD | HESS | PROJECT, s: float = 0.1, t_max: float = 1.0,
+                 max_iter: int = 100000):
+    """Enqueue one planned contact step (no synchronization, no allocation:
+    capturable in a graph).  q, dq, dx_off must be float64 device tensors
+    whose storage stays fixed across replays.  Errors are read later with
+    ctx.sync_status()."""
+    st = _load().eipc_contact_step(ctx.handle, sc.ref, C.byref(plan), _ptr(q), _ptr(dq), _ptr(dx_off),
+                                   float(dhat), float(kappa), int(flags), float(s), float(t_max), int(max_iter),
+                                   _ptr(out.energy), _ptr(out.grad),
+                                   None if out.bsr is None else C.byref(out.bsr), _ptr(out.alpha),
+                                   _ptr(out.counts), ctx.stream())
+    ctx.check(st)

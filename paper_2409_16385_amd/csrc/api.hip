@@ -86,7 +86,10 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
-__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
 
 static eipc_status fill_i32(eipc_ctx *c, int32_t *p, int64_t n, int32_t v, hipStream_t s) {
   if (n == 0) return EIPC_OK;
@@ -104,6 +107,16 @@ static eipc_status check_scene(eipc_ctx *c, const eipc_scene *sc) {
     return set_err(c, EIPC_ERR_ARG, "W is NULL");
   if (sc->n_face > 0 && !sc->faces) return set_err(c, EIPC_ERR_ARG, "faces is NULL");
   if (sc->n_edge > 0 && !sc->edges) return set_err(c, EIPC_ERR_ARG, "edges is NULL");
+  if (sc->n_scene < 0 || sc->n_scene > 65536) return set_err(c, EIPC_ERR_ARG, "n_scene must be in [0, 65536]");
+  if (sc->n_scene > 1 && sc->n_vert > 0 && !sc->vert_scene)
+    return set_err(c, EIPC_ERR_ARG, "vert_scene is NULL for a batch");
+  return EIPC_OK;
+}
+
+static eipc_status fill_u64(eipc_ctx *c, uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  k_fill_u64<<<(int)std::min<int64_t>(grid_for(n, 256), 4096), 256, 0, s>>>(p, n, v);
+  EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }
 
@@ -119,16 +132,29 @@ static eipc_status read_status(eipc_ctx *c, hipStream_t s, bool clear = true) {
   EIPC_HIP(c, hipStreamSynchronize(s));
   if (clear && st) EIPC_HIP(c, hipMemsetAsync(c->status, 0, 4, s));
   if (st & ST_BAD_W) return set_err(c, EIPC_ERR_ARG, "a row of W has more than 4 weights");
+  if (st & ST_BAD_SCENE) return set_err(c, EIPC_ERR_ARG, "a vertex scene id is out of range");
+  if (st & ST_PLAN_OVERFLOW) return set_err(c, EIPC_ERR_CAPACITY, "a capacity of the step plan was exceeded");
   if (st & ST_INTERSECTING) return set_err(c, EIPC_ERR_INTERSECTING, "a candidate pair has zero distance");
   if (st & ST_NONFINITE) return set_err(c, EIPC_ERR_NONFINITE, "non-finite position or pair quantity");
   if (st & ST_CCD_CAPPED) return EIPC_WARN_CCD_CAPPED;
   return EIPC_OK;
 }
 
-static uint32_t pow2_at_least(int64_t v) {
+static int64_t pow2_at_least(int64_t v) {
   uint64_t p = 1;
   while ((int64_t)p < v) p <<= 1;
-  return (uint32_t)std::min<uint64_t>(p, 1ull << 30);
+  return (int64_t)std::min<uint64_t>(p, 1ull << 34);
+}
+
+// global block hash of the reduced Hessian, cleared (int64 keys, -1 empty)
+static eipc_status hess_table(eipc_ctx *c, int64_t cap, HessOut &h, hipStream_t s) {
+  EIPC_TRY(ensure_t(c, B_HKEY, (size_t)cap, &h.hkey));
+  EIPC_TRY(ensure_t(c, B_HVAL, (size_t)cap * 9, &h.hval));
+  EIPC_TRY(fill_u64(c, (uint64_t *)h.hkey, cap, ~0ull, s));
+  EIPC_TRY(launch_zero(c, h.hval, sizeof(double) * 9 * cap, s));
+  h.kind = 2;
+  h.hmask = (uint64_t)(cap - 1);
+  return EIPC_OK;
 }
 
 static eipc_status narrow_both(eipc_ctx *c, const eipc_scene *sc, const double *xs, const int32_t *pt, int64_t n_pt,
@@ -274,8 +300,8 @@ eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double 
       !std::isfinite(kappa))
     return set_err(c, EIPC_ERR_ARG, "bad pair or parameter arguments");
   const bool want_h = (flags & EIPC_HESS) && (hess_dense || hess_bsr);
-  if (want_h && (int64_t)sc->n_node * sc->n_node >= (int64_t)INT32_MAX)
-    return set_err(c, EIPC_ERR_ARG, "reduced Hessian output supports n_node <= 46340");
+  if (want_h && 3 * (int64_t)sc->n_node >= (int64_t)INT32_MAX)
+    return set_err(c, EIPC_ERR_ARG, "reduced Hessian output needs 3 * n_node < 2^31");
   if (hess_dense && hess_bsr) return set_err(c, EIPC_ERR_ARG, "ask for one Hessian layout");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
@@ -286,7 +312,7 @@ eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double 
   EIPC_TRY(narrow_both(c, sc, xs, pt, n_pt, ee, n_ee, dhat, &act_pt, &typ_pt, &act_ee, &typ_ee, s));
   const int64_t n3 = 3 * (int64_t)sc->n_node;
   for (int attempt = 0;; ++attempt) {
-    if (energy) EIPC_TRY(launch_zero(c, energy, sizeof(double), s));
+    if (energy) EIPC_TRY(launch_zero(c, energy, sizeof(double) * n_scene_of(sc), s));
     if (grad_q && (flags & EIPC_GRAD)) EIPC_TRY(launch_zero(c, grad_q, sizeof(double) * n3, s));
     HessOut h{0, nullptr, nullptr, nullptr, 0};
     if (want_h && hess_dense) {
@@ -296,12 +322,7 @@ eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double 
     } else if (want_h) {
       int64_t cap = std::max<int64_t>(c->hash_cap, pow2_at_least(16 * (int64_t)sc->n_node));
       c->hash_cap = cap;
-      EIPC_TRY(ensure_t(c, B_HKEY, (size_t)cap, &h.hkey));
-      EIPC_TRY(ensure_t(c, B_HVAL, (size_t)cap * 9, &h.hval));
-      EIPC_TRY(fill_i32(c, h.hkey, cap, -1, s));
-      EIPC_TRY(launch_zero(c, h.hval, sizeof(double) * 9 * cap, s));
-      h.kind = 2;
-      h.hmask = (uint32_t)(cap - 1);
+      EIPC_TRY(hess_table(c, cap, h, s));
     }
     const uint32_t f = flags & (want_h ? ~0u : ~(uint32_t)EIPC_HESS);
     double *g = (flags & EIPC_GRAD) ? grad_q : nullptr;
@@ -358,17 +379,16 @@ eipc_status eipc_ccd_max_step(eipc_ctx *c, const eipc_scene *sc, const double *q
   int32_t *cpt = nullptr, *cee = nullptr;
   EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, nullptr, 0, &npt, 0, s, B_CAND_PT, &cpt));
   EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, nullptr, 0, &nee, 0, s, B_CAND_EE, &cee));
-  uint64_t *abits = (uint64_t *)(c->counters + 4);
+  const int nsc = n_scene_of(sc);
+  uint64_t *abits;
+  EIPC_TRY(ensure_t(c, B_ALPHA, (size_t)nsc, &abits));
   uint64_t tb;
   std::memcpy(&tb, &t_max, 8);
-  k_set_u64<<<1, 1, 0, s>>>(abits, tb);
-  EIPC_HIP(c, hipGetLastError());
+  EIPC_TRY(fill_u64(c, abits, nsc, tb, s));
   EIPC_TRY(launch_ccd(c, sc, 0, xs, ps, cpt, npt, sfac, t_max, max_iter, abits, nullptr, nullptr, s));
   EIPC_TRY(launch_ccd(c, sc, 1, xs, ps, cee, nee, sfac, t_max, max_iter, abits, nullptr, nullptr, s));
-  uint64_t ab = 0;
-  EIPC_HIP(c, hipMemcpyAsync(&ab, abits, 8, hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipMemcpyAsync(alpha, abits, 8 * (size_t)nsc, hipMemcpyDeviceToHost, s));
   EIPC_HIP(c, hipStreamSynchronize(s));
-  std::memcpy(alpha, &ab, 8);
   if (n_cand) *n_cand = npt + nee;
   return read_status(c, s);
 }
@@ -490,6 +510,201 @@ eipc_status eipc_fp64_selftest(eipc_ctx *c, const double *a, const double *b, do
   if (!c || n < 0 || (n > 0 && (!a || !b || !sq || !dv))) return EIPC_ERR_ARG;
   EIPC_HIP(c, hipSetDevice(c->device));
   return launch_fp64_selftest(c, a, b, sq, dv, n, (hipStream_t)stream);
+}
+
+
+eipc_status eipc_set_tuning(eipc_ctx *c, double cell_scale, const int32_t wg_per_cu[4]) {
+  if (!c) return EIPC_ERR_ARG;
+  if (!(cell_scale > 0.0) || !std::isfinite(cell_scale)) return set_err(c, EIPC_ERR_ARG, "cell_scale must be > 0");
+  if (wg_per_cu)
+    for (int k = 0; k < 4; ++k)
+      if (wg_per_cu[k] < 0 || wg_per_cu[k] > 64) return set_err(c, EIPC_ERR_ARG, "wg_per_cu must be in [0, 64]");
+  c->cell_scale = cell_scale;
+  if (wg_per_cu)
+    for (int k = 0; k < 4; ++k)
+      if (wg_per_cu[k] > 0) c->wg_per_cu[k] = wg_per_cu[k];
+  return EIPC_OK;
+}
+
+}  // extern "C"
+
+namespace eipc {
+
+__global__ void k_step_counts(const int64_t *cn, int64_t *out) {
+  if (threadIdx.x == 0) {
+    out[0] = cn[5];
+    out[1] = cn[6];
+    out[2] = cn[2] + cn[3];
+    out[3] = cn[7];
+    out[4] = cn[8];
+  }
+}
+
+static eipc_status check_plan(eipc_ctx *c, const eipc_plan *p) {
+  if (!p) return set_err(c, EIPC_ERR_ARG, "plan is NULL");
+  if (p->cand_pt < 0 || p->cand_ee < 0 || p->swept_pt < 0 || p->swept_ee < 0 || p->hess_blocks < 0 || p->nnzb < 0)
+    return set_err(c, EIPC_ERR_ARG, "negative plan capacity");
+  for (int k = 0; k < 4; ++k) {
+    const int64_t b = p->buckets[k];
+    if (b < 1 || (b & (b - 1)) || b > (1ll << 31) || p->ent[k] < 1)
+      return set_err(c, EIPC_ERR_ARG, "plan buckets must be powers of 2 and entries >= 1");
+  }
+  if (p->hess_blocks & (p->hess_blocks - 1)) return set_err(c, EIPC_ERR_ARG, "plan hess_blocks must be a power of 2");
+  return EIPC_OK;
+}
+
+}  // namespace eipc
+
+extern "C" {
+
+eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan *plan, const double *q,
+                              const double *dq, const double *dx_off, double dhat, double kappa, uint32_t flags,
+                              double sfac, double t_max, int64_t max_iter, double *energy, double *grad_q,
+                              eipc_bsr *hess_bsr, double *alpha, int64_t *counts, eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  EIPC_TRY(check_plan(c, plan));
+  if ((!q && sc->n_node > 0) || !std::isfinite(kappa)) return set_err(c, EIPC_ERR_ARG, "bad step arguments");
+  if (alpha && ((!dq && sc->n_node > 0) || !(sfac > 0.0 && sfac < 1.0) || !(t_max > 0.0) || !std::isfinite(t_max) ||
+                max_iter < 1))
+    return set_err(c, EIPC_ERR_ARG, "bad step-bound arguments");
+  const bool want_h = (flags & EIPC_HESS) && hess_bsr;
+  if (want_h && (plan->hess_blocks == 0 || 3 * (int64_t)sc->n_node >= (int64_t)INT32_MAX))
+    return set_err(c, EIPC_ERR_ARG, "the plan has no Hessian capacity");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  const int64_t n3v = 3 * (int64_t)sc->n_vert;
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)n3v + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  // proximity candidates (unsorted), counts on the device
+  int32_t *pt, *ee;
+  EIPC_TRY(ensure_t(c, B_STEP_PT, (size_t)2 * std::max<int64_t>(plan->cand_pt, 1), &pt));
+  EIPC_TRY(ensure_t(c, B_STEP_EE, (size_t)2 * std::max<int64_t>(plan->cand_ee, 1), &ee));
+  int64_t *cn = c->counters;
+  const BPPlan bp[4] = {{(uint32_t)plan->buckets[0], plan->ent[0], plan->cand_pt},
+                        {(uint32_t)plan->buckets[1], plan->ent[1], plan->cand_ee},
+                        {(uint32_t)plan->buckets[2], plan->ent[2], plan->swept_pt},
+                        {(uint32_t)plan->buckets[3], plan->ent[3], plan->swept_ee}};
+  EIPC_TRY(launch_zero(c, cn + 2, 7 * sizeof(int64_t), s));  // active PT/EE, (4), candidates, swept
+  EIPC_TRY(broad_phase(c, sc, 0, xs, nullptr, dhat, pt, plan->cand_pt, nullptr, 0, s, -1, nullptr, &bp[0], cn + 5));
+  EIPC_TRY(broad_phase(c, sc, 1, xs, nullptr, dhat, ee, plan->cand_ee, nullptr, 0, s, -1, nullptr, &bp[1], cn + 6));
+  // narrow phase
+  int32_t *act_pt, *typ_pt, *act_ee, *typ_ee;
+  EIPC_TRY(ensure_t(c, B_ACT_PT, (size_t)std::max<int64_t>(plan->cand_pt, 1), &act_pt));
+  EIPC_TRY(ensure_t(c, B_TYP_PT, (size_t)std::max<int64_t>(plan->cand_pt, 1), &typ_pt));
+  EIPC_TRY(ensure_t(c, B_ACT_EE, (size_t)std::max<int64_t>(plan->cand_ee, 1), &act_ee));
+  EIPC_TRY(ensure_t(c, B_TYP_EE, (size_t)std::max<int64_t>(plan->cand_ee, 1), &typ_ee));
+  EIPC_TRY(launch_narrow(c, sc, 0, xs, pt, plan->cand_pt, dhat, act_pt, typ_pt, cn + 2, s, cn + 5));
+  EIPC_TRY(launch_narrow(c, sc, 1, xs, ee, plan->cand_ee, dhat, act_ee, typ_ee, cn + 3, s, cn + 6));
+  // barrier terms and reduction
+  const int64_t n3 = 3 * (int64_t)sc->n_node;
+  if (energy) EIPC_TRY(launch_zero(c, energy, sizeof(double) * n_scene_of(sc), s));
+  double *g = (flags & EIPC_GRAD) ? grad_q : nullptr;
+  if (g) EIPC_TRY(launch_zero(c, g, sizeof(double) * n3, s));
+  HessOut h{0, nullptr, nullptr, nullptr, 0};
+  if (want_h) EIPC_TRY(hess_table(c, plan->hess_blocks, h, s));
+  const uint32_t f = flags & (want_h ? ~0u : ~(uint32_t)EIPC_HESS);
+  if (energy || g || want_h) {
+    EIPC_TRY(launch_barrier(c, sc, 0, xs, pt, act_pt, typ_pt, cn + 2, plan->cand_pt, dhat, kappa, f, energy, g, h, s));
+    EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, cn + 3, plan->cand_ee, dhat, kappa, f, energy, g, h, s));
+  }
+  if (want_h) EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s, plan->nnzb));
+  // step bound over swept candidates
+  if (alpha) {
+    double *ps, *x1s;
+    EIPC_TRY(ensure_t(c, B_P, (size_t)n3v + 1, &ps));
+    EIPC_TRY(ensure_t(c, B_X1, (size_t)n3v + 1, &x1s));
+    EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
+    EIPC_TRY(launch_add_soa(c, n3v, xs, ps, x1s, s));
+    int32_t *cpt, *cee;
+    EIPC_TRY(ensure_t(c, B_CAND_PT, (size_t)2 * std::max<int64_t>(plan->swept_pt, 1), &cpt));
+    EIPC_TRY(ensure_t(c, B_CAND_EE, (size_t)2 * std::max<int64_t>(plan->swept_ee, 1), &cee));
+    EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, cpt, plan->swept_pt, nullptr, 0, s, -1, nullptr, &bp[2], cn + 7));
+    EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, cee, plan->swept_ee, nullptr, 0, s, -1, nullptr, &bp[3], cn + 8));
+    uint64_t tb;
+    std::memcpy(&tb, &t_max, 8);
+    EIPC_TRY(fill_u64(c, (uint64_t *)alpha, n_scene_of(sc), tb, s));
+    EIPC_TRY(launch_ccd(c, sc, 0, xs, ps, cpt, plan->swept_pt, sfac, t_max, max_iter, (uint64_t *)alpha, nullptr,
+                        nullptr, s, cn + 7));
+    EIPC_TRY(launch_ccd(c, sc, 1, xs, ps, cee, plan->swept_ee, sfac, t_max, max_iter, (uint64_t *)alpha, nullptr,
+                        nullptr, s, cn + 8));
+  }
+  if (counts) {
+    k_step_counts<<<1, 64, 0, s>>>(cn, counts);
+    EIPC_HIP(c, hipGetLastError());
+  }
+  return EIPC_OK;
+}
+
+eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq,
+                           const double *dx_off, double dhat, double margin, int32_t with_hess, eipc_plan *plan,
+                           eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (!plan || (!q && sc->n_node > 0) || !(margin >= 1.0) || !std::isfinite(margin))
+    return set_err(c, EIPC_ERR_ARG, "bad plan arguments");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  const int64_t n3v = 3 * (int64_t)sc->n_vert;
+  auto grow = [margin](int64_t v) { return (int64_t)std::ceil(margin * (double)v) + 1024; };
+  eipc_plan p{};
+  // measure: unplanned broad phases (append mode, buffers grown to fit)
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)n3v + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  int64_t npt = 0, nee = 0;
+  int32_t *pt = nullptr, *ee = nullptr;
+  EIPC_TRY(broad_phase(c, sc, 0, xs, nullptr, dhat, nullptr, 0, &npt, 0, s, B_STEP_PT, &pt));
+  EIPC_TRY(broad_phase(c, sc, 1, xs, nullptr, dhat, nullptr, 0, &nee, 0, s, B_STEP_EE, &ee));
+  p.cand_pt = grow(npt);
+  p.cand_ee = grow(nee);
+  for (int k = 0; k < 2; ++k) p.ent[k] = grow(c->last_plan[k].ent_cap);
+  if (with_hess && sc->n_node > 0) {
+    eipc_bsr tmp;
+    EIPC_TRY(eipc_barrier_reduce(c, sc, q, pt, npt, ee, nee, dhat, 1.0, EIPC_HESS, nullptr, nullptr, nullptr, &tmp,
+                                 nullptr, stream));
+    // keys (upper blocks) <= nnzb; table at most half full
+    p.nnzb = grow(tmp.nnzb);
+    p.hess_blocks = pow2_at_least(2 * p.nnzb);
+  }
+  if (dq) {
+    double *ps, *x1s;
+    EIPC_TRY(ensure_t(c, B_P, (size_t)n3v + 1, &ps));
+    EIPC_TRY(ensure_t(c, B_X1, (size_t)n3v + 1, &x1s));
+    EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
+    EIPC_TRY(launch_add_soa(c, n3v, xs, ps, x1s, s));
+    int64_t spt = 0, see = 0;
+    int32_t *cpt = nullptr, *cee = nullptr;
+    EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, nullptr, 0, &spt, 0, s, B_CAND_PT, &cpt));
+    EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, nullptr, 0, &see, 0, s, B_CAND_EE, &cee));
+    p.swept_pt = grow(spt);
+    p.swept_ee = grow(see);
+    for (int k = 2; k < 4; ++k) p.ent[k] = grow(c->last_plan[k].ent_cap);
+  } else {
+    p.ent[2] = p.ent[3] = 1;
+  }
+  for (int k = 0; k < 4; ++k) p.buckets[k] = std::max<int64_t>(pow2_at_least(2 * p.ent[k]), 1024);
+  {
+    const eipc_status st0 = read_status(c, s);
+    if (st0 != EIPC_OK && st0 != EIPC_WARN_CCD_CAPPED) return st0;
+  }
+  // reserve: one planned step at these sizes performs every allocation
+  double *e1, *g1, *a1;
+  int64_t *cnt;
+  const int nsc = n_scene_of(sc);
+  EIPC_TRY(ensure_t(c, B_PLAN_OUT, (size_t)(3 * sc->n_node + 2 * nsc + 8), &e1));
+  g1 = e1 + nsc;
+  a1 = g1 + 3 * (int64_t)sc->n_node;
+  cnt = (int64_t *)(a1 + nsc);
+  eipc_bsr hb;
+  const uint32_t fl = EIPC_ENERGY | EIPC_GRAD | (p.hess_blocks ? (EIPC_HESS | EIPC_PROJECT) : 0);
+  EIPC_TRY(eipc_contact_step(c, sc, &p, q, dq, dx_off, dhat, 1.0, fl, 0.5, 1.0, 1, e1, g1,
+                             p.hess_blocks ? &hb : nullptr, dq ? a1 : nullptr, cnt, stream));
+  eipc_status st = read_status(c, s);
+  if (st != EIPC_OK && st != EIPC_WARN_CCD_CAPPED) return st;
+  *plan = p;
+  return EIPC_OK;
 }
 
 }  // extern "C"

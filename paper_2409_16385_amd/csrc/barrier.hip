@@ -22,6 +22,29 @@ __device__ __forceinline__ uint32_t mix32(uint32_t k) {
   return k;
 }
 
+__device__ __forceinline__ uint32_t mix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  return (uint32_t)k;
+}
+
+// find-or-insert in an open-addressing table of 64-bit keys (-1 = empty)
+__device__ __forceinline__ int64_t table_slot64(long long *keys, uint64_t mask, long long key) {
+  uint64_t h = mix64((uint64_t)key) & mask;
+  for (int p = 0; p < MAX_PROBE; ++p) {
+    long long k = ((volatile long long *)keys)[h];
+    if (k == key) return (int64_t)h;
+    if (k == -1) {
+      long long old = (long long)atomicCAS((unsigned long long *)&keys[h], (unsigned long long)-1ll,
+                                           (unsigned long long)key);
+      if (old == -1 || old == key) return (int64_t)h;
+    }
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
 // find-or-insert in an open-addressing table of int keys (-1 = empty)
 __device__ __forceinline__ int table_slot(int *keys, uint32_t mask, int key) {
   uint32_t h = mix32((uint32_t)key) & mask;
@@ -59,8 +82,8 @@ __device__ __forceinline__ V3 load3(const double *xs, int n, int v) {
 }
 
 // global destination of a 3x3 block (I <= J)
-__device__ __forceinline__ void global_block_add(const HessOut &h, int n_node, int I, int J, const double *B,
-                                                 uint32_t *status) {
+__device__ __forceinline__ void global_block_add(const HessOut &h, int n_node, int64_t I, int64_t J,
+                                                 const double *B, uint32_t *status) {
   if (h.kind == 1) {
     const int64_t n3 = 3 * (int64_t)n_node;
 #pragma unroll
@@ -68,7 +91,7 @@ __device__ __forceinline__ void global_block_add(const HessOut &h, int n_node, i
 #pragma unroll
       for (int j = 0; j < 3; ++j) atomicAdd(&h.dense[(3 * (int64_t)I + i) * n3 + 3 * J + j], B[3 * i + j]);
   } else if (h.kind == 2) {
-    int slot = table_slot(h.hkey, h.hmask, I * n_node + J);
+    const int64_t slot = table_slot64((long long *)h.hkey, h.hmask, (long long)(I * n_node + J));
     if (slot < 0) {
       atomicOr(status, ST_HASH_OVERFLOW);
       return;
@@ -79,22 +102,11 @@ __device__ __forceinline__ void global_block_add(const HessOut &h, int n_node, i
 }
 
 struct LdsTables {
-  int *bkey;
+  long long *bkey;
   double *bval;
   int *gkey;
   double *gval;
 };
-
-__device__ __forceinline__ void lds_block_add(const LdsTables &T, const HessOut &h, int n_node, int I, int J,
-                                              const double *B, uint32_t *status) {
-  int slot = table_slot(T.bkey, LTBL - 1, I * n_node + J);
-  if (slot < 0) {
-    global_block_add(h, n_node, I, J, B, status);
-    return;
-  }
-#pragma unroll
-  for (int t = 0; t < 9; ++t) atomicAdd(&T.bval[9 * slot + t], B[t]);
-}
 
 __device__ __forceinline__ void lds_vec_add(const LdsTables &T, double *grad, int I, double g0, double g1,
                                             double g2) {
@@ -204,8 +216,8 @@ struct Acc {
   uint32_t *status;
 };
 
-__device__ __forceinline__ void lds_block_add_n(const Acc &A, int key, const double *B) {
-  int slot = table_slot(A.T.bkey, LTBL - 1, key);
+__device__ __forceinline__ void lds_block_add_n(const Acc &A, long long key, const double *B) {
+  int slot = (int)table_slot64(A.T.bkey, LTBL - 1, key);
   if (slot < 0) {
     global_block_add(A.h, A.n_node, key / A.n_node, key % A.n_node, B, A.status);
     return;
@@ -215,11 +227,11 @@ __device__ __forceinline__ void lds_block_add_n(const Acc &A, int key, const dou
 }
 
 // wavefront-aggregated add of a 3x3 block (all lanes must call)
-__device__ __forceinline__ void agg_block(const Acc &A, bool valid, int key, const double *B) {
+__device__ __forceinline__ void agg_block(const Acc &A, bool valid, long long key, const double *B) {
   const uint64_t vm = __ballot(valid);
   if (vm == 0) return;
   const int first = __ffsll((unsigned long long)vm) - 1;
-  const int k0 = __shfl(key, first, 64);
+  const long long k0 = __shfl(key, first, 64);
   const bool uniform = __ballot(valid && key != k0) == 0;
   if (uniform) {
     double S[9];
@@ -247,68 +259,95 @@ __device__ __forceinline__ void agg_vec(const Acc &A, bool valid, int node, doub
   }
 }
 
-// Phase 1: per active pair, energy (block-reduced into *energy), the
-// gradient in the Q basis gamma = G^T gY (9) and the Hessian X in the Q
-// basis (45, PSD-projected with EIPC_PROJECT), stored SoA: out[e*cap + i].
+// Add a per-lane value into out[scene] (all lanes of the wavefront call):
+// one atomic per wavefront when the contributing lanes share a scene.
+__device__ __forceinline__ void agg_scene_add(double *out, bool valid, int scene, int n_scene, double v,
+                                              uint32_t *status) {
+  const bool ok = valid && (unsigned)scene < (unsigned)n_scene;
+  if (valid && !ok) atomicOr(status, ST_BAD_SCENE);
+  const uint64_t vm = __ballot(ok);
+  if (vm == 0) return;
+  const int first = __ffsll((unsigned long long)vm) - 1;
+  const int s0 = __shfl(scene, first, 64);
+  if (__ballot(ok && scene != s0) == 0) {
+    const double t = wave_sum(ok ? v : 0.0);
+    if ((int)(threadIdx.x & 63) == first && t != 0.0) atomicAdd(&out[s0], t);
+  } else if (ok && v != 0.0) {
+    atomicAdd(&out[scene], v);
+  }
+}
+
+// Phase 1: per active pair, energy (reduced per scene), the gradient in
+// the Q basis gamma = G^T gY (9) and the Hessian X in the Q basis (45,
+// PSD-projected with EIPC_PROJECT), stored SoA: out[e*cap + i].
 template <int KIND>
 __global__ __launch_bounds__(BR_THREADS) void k_pair_terms(
     const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
     const int64_t *__restrict__ d_count, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
     const double *__restrict__ xs, const double *__restrict__ x_rest, int n_vert, double dhat, double kappa,
-    uint32_t flags, double *energy, double *__restrict__ gq, double *__restrict__ Xq, int64_t cap) {
+    uint32_t flags, double *energy, double *__restrict__ gq, double *__restrict__ Xq, int64_t cap,
+    const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
   __shared__ double s_e[BR_THREADS / 64];
   const bool want_g = gq != nullptr;
   const bool want_h = Xq != nullptr;
   const bool project = flags & EIPC_PROJECT;
   const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
-  const int64_t n = *d_count;
+  const int64_t n = *d_count < cap ? *d_count : cap;
   double e_acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * BR_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BR_THREADS) {
-    const int64_t k = act[i];
-    const int ty = typ[i];
-    int vid[4];
-    pair_vertices<KIND>(pairs, k, faces, edges, vid);
-    V3 x[4];
+  for (int64_t base = (int64_t)blockIdx.x * BR_THREADS; base < n; base += (int64_t)gridDim.x * BR_THREADS) {
+    const int64_t i = base + threadIdx.x;
+    const bool live = i < n;
+    double e_pair = 0.0;
+    int scene = 0;
+    if (live) {
+      const int64_t k = act[i];
+      const int ty = typ[i];
+      int vid[4];
+      pair_vertices<KIND>(pairs, k, faces, edges, vid);
+      if (vscene) scene = vscene[vid[0]];
+      V3 x[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) x[a] = load3(xs, n_vert, vid[a]);
-    const double s2 = type_value<KIND>(ty, x);
-    double eps = 0.0;
-    if (moll) {
-      V3 r[4];
+      for (int a = 0; a < 4; ++a) x[a] = load3(xs, n_vert, vid[a]);
+      const double s2 = type_value<KIND>(ty, x);
+      double eps = 0.0;
+      if (moll) {
+        V3 r[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-        r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
-      eps = mollifier_eps(r);
-    }
-    V3 Y[3];
-    y_basis<KIND>(x, Y);
-    double gE[9], HE[45];
-    e_acc += energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, want_h);
-    if (want_g) {
+        for (int a = 0; a < 4; ++a)
+          r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
+        eps = mollifier_eps(r);
+      }
+      V3 Y[3];
+      y_basis<KIND>(x, Y);
+      double gE[9], HE[45];
+      e_pair = energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, want_h);
+      if (want_g) {
 #pragma unroll
-      for (int al = 0; al < 3; ++al)
+        for (int al = 0; al < 3; ++al)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          double acc = 0.0;
+          for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
 #pragma unroll
-          for (int J = 0; J < 3; ++J) {
-            const int g = gcoef(KIND, J, al);
-            if (g != 0) acc += g * gE[3 * J + c];
+            for (int J = 0; J < 3; ++J) {
+              const int g = gcoef(KIND, J, al);
+              if (g != 0) acc += g * gE[3 * J + c];
+            }
+            gq[(3 * al + c) * cap + i] = acc;
           }
-          gq[(3 * al + c) * cap + i] = acc;
-        }
-    }
-    if (want_h) {
-      double M[45];
-      to_q_basis<KIND>(HE, M);
-      if (project) project_psd9(M);
+      }
+      if (want_h) {
+        double M[45];
+        to_q_basis<KIND>(HE, M);
+        if (project) project_psd9(M);
 #pragma unroll
-      for (int e = 0; e < 45; ++e) Xq[e * cap + i] = M[e];
+        for (int e = 0; e < 45; ++e) Xq[e * cap + i] = M[e];
+      }
     }
+    if (energy && vscene) agg_scene_add(energy, live, scene, n_scene, e_pair, status);
+    e_acc += e_pair;
   }
-  if (energy) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) e_acc += __shfl_xor(e_acc, o, 64);
+  if (energy && !vscene) {
+    e_acc = wave_sum(e_acc);
     if ((threadIdx.x & 63) == 0) s_e[threadIdx.x >> 6] = e_acc;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -327,7 +366,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
     const int32_t *__restrict__ faces, const int32_t *__restrict__ edges, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const double *__restrict__ val, int n_node, const double *__restrict__ gq,
     const double *__restrict__ Xq, int64_t cap, double *grad, HessOut h, uint32_t *status) {
-  __shared__ int s_bkey[LTBL];
+  __shared__ long long s_bkey[LTBL];
   __shared__ double s_bval[LTBL * 9];
   __shared__ int s_gkey[LGT];
   __shared__ double s_gval[LGT * 3];
@@ -341,7 +380,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
   for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = -1;
   for (int t = threadIdx.x; t < LGT * 3; t += BR_THREADS) s_gval[t] = 0.0;
   __syncthreads();
-  const int64_t n = *d_count;
+  const int64_t n = *d_count < cap ? *d_count : cap;
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + BR_THREADS - 1) / BR_THREADS * BR_THREADS;
   const int64_t r0 = (int64_t)blockIdx.x * per;
   const int64_t r1 = r0 + per < n ? r0 + per : n;
@@ -394,7 +433,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
           double B[9];
 #pragma unroll
           for (int t = 0; t < 9; ++t) B[t] = S.z[ii][0] * Rt[0][t] + S.z[ii][1] * Rt[1][t] + S.z[ii][2] * Rt[2][t];
-          const int key = v ? S.node[ii] * n_node + S.node[j] : -1;
+          const long long key = v ? (long long)S.node[ii] * n_node + S.node[j] : -1ll;
           agg_block(A, v, key, B);
         }
       }
@@ -412,7 +451,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
     }
     if (last || s_used > LTBL / 2) {
       for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) {
-        const int key = s_bkey[t];
+        const long long key = s_bkey[t];
         if (key != -1) {
           global_block_add(h, n_node, key / n_node, key % n_node, &s_bval[9 * t], status);
           s_bkey[t] = -1;
@@ -447,19 +486,23 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
   if (want_g) EIPC_TRY(ensure_t(c, kind == 0 ? B_PG_PT : B_PG_EE, (size_t)9 * cap, &gq));
   if (want_h) EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)45 * cap, &Xq));
   {
-    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 8 * (int64_t)c->num_cu);
+    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), (int64_t)c->wg_per_cu[0] * c->num_cu);
     ProfScope ps(c, kind == 0 ? K_BARRIER_PT : K_BARRIER_EE, s);
+    const int32_t *vsc = vscene_of(sc);
+    const int nsc = n_scene_of(sc);
     if (kind == 0)
       k_pair_terms<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
-                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap);
+                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap, vsc, nsc,
+                                                     c->status);
     else
       k_pair_terms<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
-                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap);
+                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap, vsc, nsc,
+                                                     c->status);
     EIPC_HIP(c, hipGetLastError());
   }
   if (!want_g && !want_h) return EIPC_OK;
   {
-    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 2 * (int64_t)c->num_cu);
+    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), (int64_t)c->wg_per_cu[1] * c->num_cu);
     ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
     if (kind == 0)
       k_expand<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
@@ -493,42 +536,56 @@ eipc_status launch_dense_mirror(eipc_ctx *c, int n_node, double *dense, hipStrea
 // BSR from the global hash of upper blocks: count per row (both
 // triangles), scan, fill, sort each row by column, gather values.
 // ---------------------------------------------------------------------------
-__global__ void k_hash_rowcount(int64_t cap, const int32_t *hkey, int n_node, int32_t *rowcnt) {
+__global__ void k_hash_rowcount(int64_t cap, const int64_t *hkey, int n_node, int32_t *rowcnt) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cap) return;
-  const int key = hkey[t];
+  const int64_t key = hkey[t];
   if (key < 0) return;
-  const int I = key / n_node, J = key % n_node;
+  const int I = (int)(key / n_node), J = (int)(key % n_node);
   atomicAdd(&rowcnt[I], 1);
   if (I != J) atomicAdd(&rowcnt[J], 1);
 }
 
-__global__ void k_hash_rowfill(int64_t cap, const int32_t *hkey, int n_node, const int64_t *rowptr,
-                               int32_t *rowfill, int32_t *bcol, int64_t *bsrc) {
+__global__ void k_hash_rowfill(int64_t cap, const int64_t *hkey, int n_node, const int64_t *rowptr,
+                               int32_t *rowfill, int32_t *bcol, int64_t *bsrc, int64_t nnzb_cap) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= cap) return;
-  const int key = hkey[t];
+  const int64_t key = hkey[t];
   if (key < 0) return;
-  const int I = key / n_node, J = key % n_node;
+  const int I = (int)(key / n_node), J = (int)(key % n_node);
   int64_t p = rowptr[I] + atomicAdd(&rowfill[I], 1);
-  bcol[p] = J;
-  bsrc[p] = 2 * t;  // even: as stored
+  if (p < nnzb_cap) {
+    bcol[p] = J;
+    bsrc[p] = 2 * t;  // even: as stored
+  }
   if (I != J) {
     p = rowptr[J] + atomicAdd(&rowfill[J], 1);
-    bcol[p] = I;
-    bsrc[p] = 2 * t + 1;  // odd: transposed
+    if (p < nnzb_cap) {
+      bcol[p] = I;
+      bsrc[p] = 2 * t + 1;  // odd: transposed
+    }
   }
 }
 
 // Sort each BSR row by column: one wavefront per row; rows of at most 64
 // blocks by rank (columns of a row are distinct), longer rows by insertion.
-__global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int64_t *bsrc, int32_t *rowptr32) {
+// Rows that end beyond the capacity are left alone (overflow is raised).
+__global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int64_t *bsrc, int32_t *rowptr32,
+                           int64_t nnzb_cap, uint32_t *status) {
   const int lane = threadIdx.x & 63;
   const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (r > n_node) return;
-  if (lane == 0) rowptr32[r] = (int32_t)rowptr[r];
-  if (r == n_node) return;
+  if (r == n_node) {
+    if (lane == 0) {
+      const int64_t tot = rowptr[r];
+      rowptr32[r] = (int32_t)(tot < nnzb_cap ? tot : nnzb_cap);
+      if (tot > nnzb_cap) atomicOr(status, ST_PLAN_OVERFLOW);
+    }
+    return;
+  }
   const int64_t b = rowptr[r], e = rowptr[r + 1];
+  if (lane == 0) rowptr32[r] = (int32_t)(b < nnzb_cap ? b : nnzb_cap);
+  if (e > nnzb_cap) return;
   const int64_t len = e - b;
   if (len <= 64) {
     const bool v = lane < len;
@@ -556,23 +613,27 @@ __global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int
   }
 }
 
-__global__ void k_bsr_gather(int64_t nnzb, const int64_t *bsrc, const double *hval, double *blocks) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nnzb) return;
-  const int64_t src = bsrc[p];
-  const double *v = hval + 9 * (src >> 1);
-  if ((src & 1) == 0) {
+// blocks in BSR order; the count is read from the device (capped)
+__global__ void k_bsr_gather(int64_t cap, const int32_t *rowptr32, int n_node, const int64_t *bsrc,
+                             const double *hval, double *blocks) {
+  const int64_t nnzb = rowptr32[n_node];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnzb && p < cap;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t src = bsrc[p];
+    const double *v = hval + 9 * (src >> 1);
+    if ((src & 1) == 0) {
 #pragma unroll
-    for (int t = 0; t < 9; ++t) blocks[9 * p + t] = v[t];
-  } else {
+      for (int t = 0; t < 9; ++t) blocks[9 * p + t] = v[t];
+    } else {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) blocks[9 * p + 3 * i + j] = v[3 * j + i];
+        for (int j = 0; j < 3; ++j) blocks[9 * p + 3 * i + j] = v[3 * j + i];
+    }
   }
 }
 
-eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out, hipStream_t s) {
+eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out, hipStream_t s, int64_t nnzb_cap) {
   const int64_t cap = (int64_t)h.hmask + 1;
   int32_t *rowcnt, *rowfill, *bcol, *rowptr32;
   int64_t *rowptr, *bsrc;
@@ -585,28 +646,32 @@ eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out
   k_hash_rowcount<<<grid_for(cap, 256), 256, 0, s>>>(cap, h.hkey, n_node, rowcnt);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, rowcnt, n_node, rowptr, s));
+  const bool planned = nnzb_cap >= 0;
   int64_t nnzb = 0;
-  EIPC_HIP(c, hipMemcpyAsync(&nnzb, rowptr + n_node, 8, hipMemcpyDeviceToHost, s));
-  EIPC_HIP(c, hipStreamSynchronize(s));
-  EIPC_TRY(ensure_t(c, B_BCOL, (size_t)std::max<int64_t>(nnzb, 1), &bcol));
-  EIPC_TRY(ensure_t(c, B_BSRC, (size_t)std::max<int64_t>(nnzb, 1), &bsrc));
-  EIPC_TRY(ensure_t(c, B_BBLK, (size_t)std::max<int64_t>(nnzb, 1) * 9, &blocks));
-  int32_t *rp32;
-  EIPC_TRY(ensure_t(c, B_ROWCNT, (size_t)n_node + 1, &rp32));  // reuse: counts no longer needed
-  k_hash_rowfill<<<grid_for(cap, 256), 256, 0, s>>>(cap, h.hkey, n_node, rowptr, rowfill, bcol, bsrc);
+  if (!planned) {
+    EIPC_HIP(c, hipMemcpyAsync(&nnzb, rowptr + n_node, 8, hipMemcpyDeviceToHost, s));
+    EIPC_HIP(c, hipStreamSynchronize(s));
+    nnzb_cap = nnzb;
+  }
+  EIPC_TRY(ensure_t(c, B_BCOL, (size_t)std::max<int64_t>(nnzb_cap, 1), &bcol));
+  EIPC_TRY(ensure_t(c, B_BSRC, (size_t)std::max<int64_t>(nnzb_cap, 1), &bsrc));
+  EIPC_TRY(ensure_t(c, B_BBLK, (size_t)std::max<int64_t>(nnzb_cap, 1) * 9, &blocks));
+  rowptr32 = rowcnt;  // counts are no longer needed once scanned
+  k_hash_rowfill<<<grid_for(cap, 256), 256, 0, s>>>(cap, h.hkey, n_node, rowptr, rowfill, bcol, bsrc, nnzb_cap);
   EIPC_HIP(c, hipGetLastError());
-  k_row_sort<<<grid_for((int64_t)(n_node + 1) * 64, 256), 256, 0, s>>>(n_node, rowptr, bcol, bsrc, rp32);
+  k_row_sort<<<grid_for((int64_t)(n_node + 1) * 64, 256), 256, 0, s>>>(n_node, rowptr, bcol, bsrc, rowptr32,
+                                                                        nnzb_cap, c->status);
   EIPC_HIP(c, hipGetLastError());
-  if (nnzb) {
-    k_bsr_gather<<<grid_for(nnzb, 256), 256, 0, s>>>(nnzb, bsrc, h.hval, blocks);
+  if (nnzb_cap > 0) {
+    k_bsr_gather<<<std::min(grid_for(nnzb_cap, 256), 16 * c->num_cu), 256, 0, s>>>(nnzb_cap, rowptr32, n_node, bsrc,
+                                                                                   h.hval, blocks);
     EIPC_HIP(c, hipGetLastError());
   }
   out->n_rows = n_node;
-  out->nnzb = nnzb;
-  out->rowptr = rp32;
+  out->nnzb = planned ? -1 : nnzb;
+  out->rowptr = rowptr32;
   out->col = bcol;
   out->blocks = blocks;
-  (void)rowcnt;
   return EIPC_OK;
 }
 

@@ -7,62 +7,86 @@
 
 namespace eipc {
 
-template <int KIND>
-__global__ void k_ccd(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
-                      const int32_t *__restrict__ edges, const double *__restrict__ xs, const double *__restrict__ ps,
-                      int n_vert, double sfac, double t_max, int64_t max_iter, unsigned long long *alpha_bits,
-                      double *t_out, int64_t *it_out, uint32_t *status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double t = t_max;
-  bool capped = false;
-  if (i < n) {
-    const int a = pairs[2 * i], b = pairs[2 * i + 1];
-    int vid[4];
-    if (KIND == 0) {
-      vid[0] = a;
-      vid[1] = faces[3 * (int64_t)b];
-      vid[2] = faces[3 * (int64_t)b + 1];
-      vid[3] = faces[3 * (int64_t)b + 2];
-    } else {
-      vid[0] = edges[2 * (int64_t)a];
-      vid[1] = edges[2 * (int64_t)a + 1];
-      vid[2] = edges[2 * (int64_t)b];
-      vid[3] = edges[2 * (int64_t)b + 1];
-    }
-    V3 x[4], p[4];
+// Min of a per-lane value into bits[scene] (all lanes of the wavefront
+// call): one atomic per wavefront when the contributing lanes share a scene.
+// Values are >= 0, so their IEEE bit patterns order like the values.
+__device__ __forceinline__ void agg_scene_min(unsigned long long *bits, bool valid, int scene, int n_scene, double t,
+                                              uint32_t *status) {
+  const bool ok = valid && (unsigned)scene < (unsigned)n_scene;
+  if (valid && !ok) atomicOr(status, ST_BAD_SCENE);
+  const uint64_t vm = __ballot(ok);
+  if (vm == 0) return;
+  const int first = __ffsll((unsigned long long)vm) - 1;
+  const int s0 = __shfl(scene, first, 64);
+  if (__ballot(ok && scene != s0) == 0) {
+    double m = ok ? t : INFINITY;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x[k] = V3{xs[vid[k]], xs[n_vert + vid[k]], xs[2 * (int64_t)n_vert + vid[k]]};
-      p[k] = V3{ps[vid[k]], ps[n_vert + vid[k]], ps[2 * (int64_t)n_vert + vid[k]]};
-    }
-    int64_t it = 0;
-    t = accd<KIND>(x, p, sfac, t_max, max_iter, &it);
-    capped = it >= max_iter;
-    if (t_out) t_out[i] = t;
-    if (it_out) it_out[i] = it;
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    if ((int)(threadIdx.x & 63) == first) atomicMin(&bits[s0], (unsigned long long)__double_as_longlong(m));
+  } else if (ok) {
+    atomicMin(&bits[scene], (unsigned long long)__double_as_longlong(t));
   }
-  if (alpha_bits) {
-    // t >= 0, so the IEEE bit pattern orders like the value
+}
+
+template <int KIND>
+__global__ void k_ccd(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
+                      const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
+                      const double *__restrict__ xs, const double *__restrict__ ps, int n_vert, double sfac,
+                      double t_max, int64_t max_iter, unsigned long long *alpha_bits, double *t_out, int64_t *it_out,
+                      const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
+  const int64_t n = d_n ? (*d_n < cap ? *d_n : cap) : cap;
+  bool capped = false;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool live = i < n;
+    double t = t_max;
+    int scene = 0;
+    if (live) {
+      const int a = pairs[2 * i], b = pairs[2 * i + 1];
+      int vid[4];
+      if (KIND == 0) {
+        vid[0] = a;
+        vid[1] = faces[3 * (int64_t)b];
+        vid[2] = faces[3 * (int64_t)b + 1];
+        vid[3] = faces[3 * (int64_t)b + 2];
+      } else {
+        vid[0] = edges[2 * (int64_t)a];
+        vid[1] = edges[2 * (int64_t)a + 1];
+        vid[2] = edges[2 * (int64_t)b];
+        vid[3] = edges[2 * (int64_t)b + 1];
+      }
+      if (vscene) scene = vscene[vid[0]];
+      V3 x[4], p[4];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMin(alpha_bits, (unsigned long long)__double_as_longlong(t));
+      for (int k = 0; k < 4; ++k) {
+        x[k] = V3{xs[vid[k]], xs[n_vert + vid[k]], xs[2 * (int64_t)n_vert + vid[k]]};
+        p[k] = V3{ps[vid[k]], ps[n_vert + vid[k]], ps[2 * (int64_t)n_vert + vid[k]]};
+      }
+      int64_t it = 0;
+      t = accd<KIND>(x, p, sfac, t_max, max_iter, &it);
+      capped = capped || it >= max_iter;
+      if (t_out) t_out[i] = t;
+      if (it_out) it_out[i] = it;
+    }
+    if (alpha_bits) agg_scene_min(alpha_bits, live, scene, n_scene, t, status);
   }
   if (__any(capped) && (threadIdx.x & 63) == 0) atomicOr(status, ST_CCD_CAPPED);
 }
 
 eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
                        const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
-                       uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s) {
+                       uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s, const int64_t *d_n) {
   if (n == 0) return EIPC_OK;
   ProfScope prof(c, kind == 0 ? K_CCD_PT : K_CCD_EE, s);
+  const int blocks = (int)std::min<int64_t>(grid_for(n, 256), (int64_t)c->wg_per_cu[3] * c->num_cu);
+  const int32_t *vsc = vscene_of(sc);
+  const int nsc = n_scene_of(sc);
   if (kind == 0)
-    k_ccd<0><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                               max_iter, (unsigned long long *)d_alpha_bits, t_out, it_out,
-                                               c->status);
+    k_ccd<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max, max_iter,
+                                     (unsigned long long *)d_alpha_bits, t_out, it_out, vsc, nsc, c->status);
   else
-    k_ccd<1><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                               max_iter, (unsigned long long *)d_alpha_bits, t_out, it_out,
-                                               c->status);
+    k_ccd<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max, max_iter,
+                                     (unsigned long long *)d_alpha_bits, t_out, it_out, vsc, nsc, c->status);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }

@@ -18,7 +18,9 @@ enum : uint32_t {
   ST_NONFINITE = 2u,
   ST_CCD_CAPPED = 4u,
   ST_HASH_OVERFLOW = 8u,
-  ST_BAD_W = 16u  // a W row with more than 4 weights
+  ST_BAD_W = 16u,         // a W row with more than 4 weights
+  ST_PLAN_OVERFLOW = 32u,  // a planned capacity was exceeded
+  ST_BAD_SCENE = 64u       // a vertex scene id out of range
 };
 
 // scratch buffers owned by the context
@@ -27,25 +29,25 @@ enum BufId {
   B_P,           // CCD displacement, SoA
   B_X1,          // CCD end positions, SoA
   B_XV,          // HVP input mapped to vertices, SoA
-  B_QBOX,        // (unused)
-  B_IBOX,        // item records (box, vertices, DoF flag)
-  B_CELLCNT,     // int32 per item
-  B_CELLOFF,     // int64 per item + 1
-  B_BCNT,        // int32 per bucket
-  B_BSTART,      // int64 per bucket + 1
-  B_BFILL,       // int32 per bucket
-  B_ENTCELL,     // hash entries {cell, item}
-  B_ENTITEM,     // (unused)
-  B_LARGE,       // int32 large items
-  B_QCNT,        // int32 per query
-  B_QOFF,        // int64 per query + 1
   B_SCANTMP,     // int64 block sums
   B_ACT_PT, B_TYP_PT, B_ACT_EE, B_TYP_EE,
   B_CAND_PT, B_CAND_EE,  // swept candidates (CCD)
   B_HKEY, B_HVAL,        // global block hash
   B_ROWCNT, B_ROWFILL, B_ROWPTR, B_BCOL, B_BSRC, B_BBLK,
   B_PG_PT, B_PG_EE, B_PX_PT, B_PX_EE,  // per-pair gradient / Hessian in the Q basis
-  B_NUM
+  B_STEP_PT, B_STEP_EE,                // candidates of a planned step
+  B_ALPHA,                             // per-scene step bound bits
+  B_PLAN_OUT,                          // outputs of the reserving step of a plan
+  B_BP0,                               // broad-phase scratch: 4 slots (kind, swept) x BP_NBUF
+  B_NUM = B_BP0 + 4 * 11
+};
+constexpr int BP_NBUF = 11;
+
+// capacities of one broad phase in a planned (synchronization-free) call
+struct BPPlan {
+  uint32_t nb;       // hash buckets (power of 2)
+  int64_t ent_cap;   // hash entries
+  int64_t cand_cap;  // candidate pairs
 };
 
 struct DevBuf {
@@ -77,6 +79,9 @@ struct eipc_ctx {
   int64_t *host = nullptr;      // pinned host staging [64]
   int64_t hash_cap = 1 << 16;   // global block hash capacity (power of 2, grows)
   int num_cu = 256;
+  double cell_scale = 2.0;       // broad-phase cell edge / mean item extent
+  int wg_per_cu[4] = {8, 2, 4, 4};  // grid sizes: pair terms, expansion, narrow, CCD
+  eipc::BPPlan last_plan[4] = {};   // sizes seen by the last unplanned broad phases
   bool prof = false;                        // record per-kernel events
   std::vector<eipc::ProfRec> prof_pending;  // recorded, not yet read
   std::vector<hipEvent_t> prof_pool;        // reusable events
@@ -132,29 +137,41 @@ eipc_status launch_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, con
 eipc_status launch_add_soa(eipc_ctx *c, int64_t n, const double *a, const double *b, double *out, hipStream_t s);
 eipc_status exclusive_scan(eipc_ctx *c, const int32_t *in, int64_t n, int64_t *out, hipStream_t s);
 eipc_status launch_zero(eipc_ctx *c, void *p, size_t bytes, hipStream_t s);
-// Candidate pairs of one kind; swept when x1s != nullptr.  Writes
-// required count to *n_out; writes pairs when it fits (and sorts per
-// query when sort != 0).
+// Candidate pairs of one kind; swept when x1s != nullptr.  Unplanned
+// (plan == nullptr): synchronizes, writes the required count to *n_out and
+// the pairs when they fit (sorted per query when sort != 0), growing buffer
+// grow_id when given.  Planned: no synchronization and no allocation beyond
+// the plan's sizes; the count goes to device *d_total and an overflow
+// raises ST_PLAN_OVERFLOW.
 eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *x1s,
                         double dhat, int32_t *out, int64_t cap, int64_t *n_out, int sort, hipStream_t s,
-                        int grow_id = -1, int32_t **grown = nullptr);
+                        int grow_id = -1, int32_t **grown = nullptr, const BPPlan *plan = nullptr,
+                        int64_t *d_total = nullptr);
+// Active subset of `n` pairs (at most `n`; min(n, *d_n) when d_n is given).
 eipc_status launch_narrow(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
-                          int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s);
+                          int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s,
+                          const int64_t *d_n = nullptr);
+inline int n_scene_of(const eipc_scene *sc) { return sc->n_scene > 1 ? sc->n_scene : 1; }
+inline const int32_t *vscene_of(const eipc_scene *sc) { return sc->n_scene > 1 ? sc->vert_scene : nullptr; }
 
 // ---- barrier.hip ----
 struct HessOut {
   int kind;  // 0 none, 1 dense, 2 global hash
   double *dense;
-  int32_t *hkey;
+  int64_t *hkey;  // I * n_node + J, -1 empty
   double *hval;
-  uint32_t hmask;
+  uint64_t hmask;
 };
 eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                            const int32_t *act, const int32_t *typ, const int64_t *d_count, int64_t max_count,
                            double dhat, double kappa, uint32_t flags, double *energy, double *grad,
                            const HessOut &h, hipStream_t s);
 eipc_status launch_dense_mirror(eipc_ctx *c, int n_node, double *dense, hipStream_t s);
-eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out, hipStream_t s);
+// BSR view of the hashed blocks.  nnzb_cap < 0: sized on the host
+// (synchronizes); else fixed capacity, the count only on the device
+// (rowptr[n_node]) and out->nnzb = -1.
+eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out, hipStream_t s,
+                        int64_t nnzb_cap = -1);
 eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *xvs,
                        const int32_t *pairs, const int32_t *act, const int32_t *typ, const int64_t *d_count,
                        int64_t max_count, double dhat, double kappa, uint32_t flags, double *out,
@@ -164,9 +181,12 @@ eipc_status launch_pair_eval(eipc_ctx *c, const eipc_scene *sc, int kind, const 
                              double *e, double *g, double *H, hipStream_t s);
 
 // ---- ccd.hip ----
+// Per-pair bound; min into d_alpha_bits[scene] when given.  n pairs at
+// most (min(n, *d_n) when d_n is given).
 eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
                        const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
-                       uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s);
+                       uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s,
+                       const int64_t *d_n = nullptr);
 eipc_status launch_fp64_selftest(eipc_ctx *c, const double *a, const double *b, double *sq, double *dv, int64_t n,
                                  hipStream_t s);
 

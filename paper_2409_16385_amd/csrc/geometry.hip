@@ -16,13 +16,14 @@ namespace eipc {
 __global__ void k_embed(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                         const double *__restrict__ val, const double *__restrict__ q,
                         const double *__restrict__ off, double *__restrict__ xs, double *__restrict__ x_aos,
-                        uint32_t *status) {
+                        const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
 #pragma clang fp contract(off)
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const int k0 = rowptr[v], k1 = rowptr[v + 1];
   if (k1 - k0 > 4 || k1 < k0) atomicOr(status, ST_BAD_W);
+  if (vscene && (unsigned)vscene[v] >= (unsigned)n_scene) atomicOr(status, ST_BAD_SCENE);
   for (int k = k0; k < k1; ++k) {
     const double w = val[k];
     const int64_t c = 3 * (int64_t)col[k];
@@ -53,7 +54,7 @@ eipc_status launch_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, con
   if (sc->n_vert == 0) return EIPC_OK;
   ProfScope ps(c, K_EMBED, s);
   k_embed<<<grid_for(sc->n_vert, 256), 256, 0, s>>>(sc->n_vert, sc->W_rowptr, sc->W_col, sc->W_val, q, off, xs,
-                                                     x_aos, c->status);
+                                                     x_aos, vscene_of(sc), n_scene_of(sc), c->status);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }
@@ -194,24 +195,30 @@ eipc_status exclusive_scan(eipc_ctx *c, const int32_t *in, int64_t n, int64_t *o
   return EIPC_OK;
 }
 
+// device-side candidate count for the next stage, clamped to the capacity
+// (an overflow is raised for the caller to re-plan)
+__global__ void k_copy_count(const int64_t *src, int64_t *dst, int64_t cap, uint32_t *status) {
+  const int64_t v = *src;
+  if (v > cap) atomicOr(status, ST_PLAN_OVERFLOW);
+  *dst = v < cap ? v : cap;
+}
+
 // ---------------------------------------------------------------------------
 // Broad phase.  Boxes: per primitive, lo = min over its vertices (start and
 // end positions when swept) - dhat/2, hi = max + dhat/2.  Items (faces for
 // PT, edges for EE) are stored as 64-byte records; the uniform grid is a
-// hash from cell to the items whose boxes touch it.
+// hash from (scene, cell) to the items whose boxes touch the cell.  Grid
+// parameters are computed on the device, so the sequence can run without
+// host synchronization once capacities are known.
 // ---------------------------------------------------------------------------
 struct ItemRec {
   double lo[3], hi[3];
   int32_t v[3];
-  int32_t dof;  // 1 if any vertex has a DoF
-};
-struct Entry {
-  uint64_t cell;
-  int32_t item;
-  int32_t dlo;  // cell minus the item's lower cell, 6 bits per axis
+  int32_t tag;  // bit 0: some vertex has a DoF; bits 1..: scene id
 };
 
 __device__ __forceinline__ bool has_dof(const int32_t *rowptr, int v) { return rowptr[v + 1] > rowptr[v]; }
+__device__ __forceinline__ int scene_of(const int32_t *vscene, int v) { return vscene ? vscene[v] : 0; }
 
 template <int NV>
 __device__ __forceinline__ void prim_box(const int *vid, const double *xs, const double *x1s, int n_vert, double h,
@@ -240,7 +247,7 @@ __device__ __forceinline__ void prim_box(const int *vid, const double *xs, const
 template <int NV>
 __global__ void k_items(int n, const int32_t *__restrict__ idx, const double *__restrict__ xs,
                         const double *__restrict__ x1s, int n_vert, double h, const int32_t *__restrict__ rowptr,
-                        ItemRec *__restrict__ rec) {
+                        const int32_t *__restrict__ vscene, ItemRec *__restrict__ rec) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int vid[NV];
@@ -254,7 +261,7 @@ __global__ void k_items(int n, const int32_t *__restrict__ idx, const double *__
     r.v[a] = a < NV ? vid[a] : -1;
     if (a < NV) dof |= has_dof(rowptr, vid[a]);
   }
-  r.dof = dof;
+  r.tag = dof | (scene_of(vscene, vid[0]) << 1);
   rec[i] = r;
 }
 
@@ -262,11 +269,9 @@ __device__ __forceinline__ uint64_t ord_key(double v) {
   uint64_t b = __double_as_longlong(v);
   return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
-__host__ __forceinline__ double ord_dec(uint64_t k) {
+__device__ __forceinline__ double ord_dec(uint64_t k) {
   uint64_t b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
-  double v;
-  std::memcpy(&v, &b, 8);
-  return v;
+  return __longlong_as_double(b);
 }
 
 // stats (uint64 view): [0..2] min lo (ordered), [3..5] max hi (ordered);
@@ -348,14 +353,53 @@ struct GridDev {
   double o[3];
   double inv_h;
   int dim[3];
-  uint32_t bmask;
-  const int64_t *bstart;
-  const Entry *ent;
-  const int32_t *large;
-  int n_large;
+  int bad;  // non-finite boxes
 };
 
 constexpr int MAX_ITEM_CELLS = 64;
+constexpr int GRID_AXIS_MAX = 1 << 16;
+
+// cell edge: cell_scale times the mean item box extent (largest axis of the
+// mean), at least 1e-6 of the scene span, grown until every axis has at
+// most 2^16 cells
+__global__ void k_grid_params(const uint64_t *st, int n_items, double cell_scale, GridDev *g, uint32_t *status) {
+  if (threadIdx.x != 0) return;
+  double lo[3], hi[3], ext[3];
+  bool ok = true;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ord_dec(st[a]);
+    hi[a] = ord_dec(st[3 + a]);
+    ext[a] = ((const double *)st)[6 + a];
+    ok = ok && isfinite(lo[a]) && isfinite(hi[a]);
+  }
+  GridDev r;
+  r.bad = ok ? 0 : 1;
+  if (!ok) {
+    atomicOr(status, ST_NONFINITE);
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = 0.0;
+      hi[a] = 0.0;
+    }
+  }
+  double cell = cell_scale * fmax(ext[0], fmax(ext[1], ext[2])) / (double)(n_items > 0 ? n_items : 1);
+  double span = fmax(hi[0] - lo[0], fmax(hi[1] - lo[1], hi[2] - lo[2]));
+  cell = fmax(cell, span * 1e-6);
+  if (!(cell > 0.0) || !isfinite(cell)) cell = 1.0;
+  for (int it = 0; it < 64; ++it) {
+    bool fits = true;
+    for (int a = 0; a < 3; ++a)
+      if (floor((hi[a] - lo[a]) / cell) + 1.0 > (double)GRID_AXIS_MAX) fits = false;
+    if (fits) break;
+    cell *= 2.0;
+  }
+  for (int a = 0; a < 3; ++a) {
+    r.o[a] = lo[a];
+    double d = floor((hi[a] - lo[a]) / cell) + 1.0;
+    r.dim[a] = (int)fmin(d, (double)GRID_AXIS_MAX);
+  }
+  r.inv_h = 1.0 / cell;
+  *g = r;
+}
 
 __device__ __forceinline__ int cell_of(double v, double o, double inv_h, int dim) {
 #pragma clang fp contract(off)
@@ -363,11 +407,12 @@ __device__ __forceinline__ int cell_of(double v, double o, double inv_h, int dim
   int c = t < 0.0 ? 0 : (t > (double)(dim - 1) ? dim - 1 : (int)t);
   return c;
 }
-__device__ __forceinline__ uint64_t cell_key(int x, int y, int z) {
-  return (uint64_t)x | ((uint64_t)y << 21) | ((uint64_t)z << 42);
+__device__ __forceinline__ uint64_t cell_key(int x, int y, int z, int scene) {
+  return (uint64_t)x | ((uint64_t)y << 16) | ((uint64_t)z << 32) | ((uint64_t)scene << 48);
 }
-__device__ __forceinline__ uint32_t cell_hash(int x, int y, int z) {
-  return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u);
+__device__ __forceinline__ uint32_t cell_hash(int x, int y, int z, int scene) {
+  return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u) ^
+         ((uint32_t)scene * 2654435761u);
 }
 __device__ __forceinline__ void cell_range(const GridDev &g, const double *lo, const double *hi, int *c0, int *c1) {
 #pragma unroll
@@ -377,15 +422,16 @@ __device__ __forceinline__ void cell_range(const GridDev &g, const double *lo, c
   }
 }
 
-__global__ void k_item_cells(int n, const ItemRec *__restrict__ rec, GridDev g, int32_t *cnt, int32_t *large,
-                             int64_t *counters) {
+__global__ void k_item_cells(int n, const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, int32_t *cnt,
+                             int32_t *large, int64_t *n_large) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const GridDev g = *gp;
   int c0[3], c1[3];
   cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
   int64_t nc = (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
   if (nc > MAX_ITEM_CELLS) {
-    int slot = (int)atomicAdd((unsigned long long *)&counters[0], 1ull);
+    int slot = (int)atomicAdd((unsigned long long *)n_large, 1ull);
     large[slot] = i;
     cnt[i] = 0;
   } else {
@@ -393,28 +439,43 @@ __global__ void k_item_cells(int n, const ItemRec *__restrict__ rec, GridDev g, 
   }
 }
 
-__global__ void k_item_hist(int n, const ItemRec *__restrict__ rec, GridDev g, const int32_t *cnt, int32_t *bcnt) {
+__global__ void k_item_hist(int n, const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, uint32_t bmask,
+                            const int32_t *cnt, int32_t *bcnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || cnt[i] == 0) return;
+  const GridDev g = *gp;
+  const int sc = rec[i].tag >> 1;
   int c0[3], c1[3];
   cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
-      for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&bcnt[cell_hash(x, y, z) & g.bmask], 1);
+      for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&bcnt[cell_hash(x, y, z, sc) & bmask], 1);
 }
 
-__global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, GridDev g, const int32_t *cnt, int32_t *bfill,
-                            Entry *ent) {
+struct Entry {
+  uint64_t cell;
+  int32_t item;
+  int32_t dlo;  // cell minus the item's lower cell, 6 bits per axis
+};
+
+__global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, uint32_t bmask,
+                            const int32_t *cnt, const int64_t *bstart, int32_t *bfill, Entry *ent, int64_t ent_cap,
+                            uint32_t *status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || cnt[i] == 0) return;
+  const GridDev g = *gp;
+  const int sc = rec[i].tag >> 1;
   int c0[3], c1[3];
   cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) {
-        uint32_t b = cell_hash(x, y, z) & g.bmask;
-        int64_t slot = g.bstart[b] + atomicAdd(&bfill[b], 1);
-        ent[slot] = Entry{cell_key(x, y, z), i, (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12)};
+        uint32_t b = cell_hash(x, y, z, sc) & bmask;
+        int64_t slot = bstart[b] + atomicAdd(&bfill[b], 1);
+        if (slot < ent_cap)
+          ent[slot] = Entry{cell_key(x, y, z, sc), i, (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12)};
+        else
+          atomicOr(status, ST_PLAN_OVERFLOW);
       }
 }
 
@@ -425,8 +486,6 @@ __device__ __forceinline__ bool overlap(const double *qlo, const double *qhi, co
   return true;
 }
 
-// modes: 0 count, 1 write (offset per query, sorted per query), 2 append
-// (wavefront-aggregated atomic append, unsorted; *total receives the count)
 template <int KIND>
 __device__ __forceinline__ bool pair_ok(int q, int qa, int qb, bool qdof, int it, const ItemRec &r) {
   if (KIND == 1 && it <= q) return false;
@@ -435,10 +494,10 @@ __device__ __forceinline__ bool pair_ok(int q, int qa, int qb, bool qdof, int it
   } else {
     if (qa == r.v[0] || qa == r.v[1] || qb == r.v[0] || qb == r.v[1]) return false;
   }
-  return qdof || r.dof;
+  return qdof || (r.tag & 1);
 }
 
-constexpr int QT = 128;      // query threads per block
+constexpr int QT = 128;         // query threads per block
 constexpr int APPEND_BUF = 16;  // per-thread LDS staging for append mode
 
 // append mode: stage a candidate in the thread's LDS slots; flush a full
@@ -457,30 +516,48 @@ __device__ __forceinline__ void stage_pair(int2 *buf, int &nb, int q, int it, un
   }
 }
 
+struct QueryArgs {
+  const GridDev *g;
+  uint32_t bmask;
+  const int64_t *bstart;
+  const Entry *ent;
+  int64_t ent_cap;
+  const int32_t *large;
+  const int64_t *n_large;
+  const ItemRec *items;
+  const int32_t *rowptr;
+  const int32_t *vscene;
+};
+
+// modes: 0 count, 1 write (offset per query, sorted per query, capacity
+// guarded), 2 append (LDS-staged, unsorted; *total receives the count)
 template <int KIND, int MODE>
 __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__ xs, const double *__restrict__ x1s,
-                                              int n_vert, double h, const int32_t *__restrict__ rowptr,
-                                              const ItemRec *__restrict__ items, GridDev g,
-                                              int32_t *__restrict__ cnt, const int64_t *__restrict__ off,
-                                              int32_t *__restrict__ out, int64_t cap, unsigned long long *total) {
+                                              int n_vert, double h, QueryArgs qa_, int32_t *__restrict__ cnt,
+                                              const int64_t *__restrict__ off, int32_t *__restrict__ out, int64_t cap,
+                                              unsigned long long *total, uint32_t *status) {
   __shared__ int2 s_buf[MODE == 2 ? QT * APPEND_BUF : 1];
   int2 *buf = s_buf + (MODE == 2 ? threadIdx.x * APPEND_BUF : 0);
   int nbuf = 0;
+  const GridDev g = *qa_.g;
+  const ItemRec *items = qa_.items;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = q < nq;
-  int qa = 0, qb = -1;
+  int qa = 0, qb = -1, qsc = 0;
   bool qdof = false;
   double qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
   if (live) {
     if (KIND == 0) {
       qa = q;
       prim_box<1>(&qa, xs, x1s, n_vert, h, qlo, qhi);
-      qdof = has_dof(rowptr, qa);
+      qdof = has_dof(qa_.rowptr, qa);
+      qsc = scene_of(qa_.vscene, qa);
     } else {
       const ItemRec r = items[q];
       qa = r.v[0];
       qb = r.v[1];
-      qdof = r.dof;
+      qdof = r.tag & 1;
+      qsc = r.tag >> 1;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         qlo[a] = r.lo[a];
@@ -495,11 +572,11 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) {
-        const uint64_t key = cell_key(x, y, z);
-        const uint32_t b = cell_hash(x, y, z) & g.bmask;
-        const int64_t e1 = g.bstart[b + 1];
-        for (int64_t e = g.bstart[b]; e < e1; ++e) {
-          const Entry en = g.ent[e];
+        const uint64_t key = cell_key(x, y, z, qsc);
+        const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
+        const int64_t e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
+        for (int64_t e = qa_.bstart[b]; e < e1; ++e) {
+          const Entry en = qa_.ent[e];
           if (en.cell != key) continue;
           const int it = en.item;
           if (KIND == 1 && it <= q) continue;
@@ -515,8 +592,10 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
           if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
           if (!overlap(qlo, qhi, r)) continue;
           if (MODE == 1) {
-            out[2 * (base + k)] = q;
-            out[2 * (base + k) + 1] = it;
+            if (base + k < cap) {
+              out[2 * (base + k)] = q;
+              out[2 * (base + k) + 1] = it;
+            }
           } else if (MODE == 2) {
             stage_pair(buf, nbuf, q, it, total, out, cap);
           }
@@ -524,14 +603,18 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
         }
       }
   if (live) {
-    for (int j = 0; j < g.n_large; ++j) {
-      const int it = g.large[j];
+    const int nl = (int)*qa_.n_large;
+    for (int j = 0; j < nl; ++j) {
+      const int it = qa_.large[j];
       const ItemRec r = items[it];
+      if ((r.tag >> 1) != qsc) continue;
       if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
       if (!overlap(qlo, qhi, r)) continue;
       if (MODE == 1) {
-        out[2 * (base + k)] = q;
-        out[2 * (base + k) + 1] = it;
+        if (base + k < cap) {
+          out[2 * (base + k)] = q;
+          out[2 * (base + k) + 1] = it;
+        }
       } else if (MODE == 2) {
         stage_pair(buf, nbuf, q, it, total, out, cap);
       }
@@ -559,16 +642,20 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
       }
   }
   if (MODE == 0 && live) cnt[q] = (int32_t)k;
-  if (MODE == 1 && live && k > 1) {
-    int32_t *seg = out + 2 * base;
-    for (int64_t i = 1; i < k; ++i) {
-      int32_t v = seg[2 * i + 1];
-      int64_t j = i - 1;
-      while (j >= 0 && seg[2 * j + 1] > v) {
-        seg[2 * (j + 1) + 1] = seg[2 * j + 1];
-        --j;
+  if (MODE == 1 && live) {
+    if (base + k > cap) {
+      atomicOr(status, ST_PLAN_OVERFLOW);
+    } else if (k > 1) {
+      int32_t *seg = out + 2 * base;
+      for (int64_t i = 1; i < k; ++i) {
+        int32_t v = seg[2 * i + 1];
+        int64_t j = i - 1;
+        while (j >= 0 && seg[2 * j + 1] > v) {
+          seg[2 * (j + 1) + 1] = seg[2 * j + 1];
+          --j;
+        }
+        seg[2 * (j + 1) + 1] = v;
       }
-      seg[2 * (j + 1) + 1] = v;
     }
   }
 }
@@ -580,128 +667,138 @@ static uint32_t next_pow2(uint64_t v) {
 }
 
 template <int KIND, int MODE>
-static void launch_query(int nq, const double *xs, const double *x1s, int n_vert, double h, const int32_t *rowptr,
-                         const ItemRec *items, const GridDev &g, int32_t *cnt, const int64_t *off, int32_t *out,
-                         int64_t cap, unsigned long long *total, hipStream_t s) {
-  k_query<KIND, MODE><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, rowptr, items, g, cnt, off, out, cap,
-                                                       total);
+static void launch_query(int nq, const double *xs, const double *x1s, int n_vert, double h, const QueryArgs &qa,
+                         int32_t *cnt, const int64_t *off, int32_t *out, int64_t cap, unsigned long long *total,
+                         uint32_t *status, hipStream_t s) {
+  k_query<KIND, MODE><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qa, cnt, off, out, cap, total,
+                                                       status);
+}
+
+// Scratch of one broad phase (kind, swept) kept in the context's buffers.
+struct BPScratch {
+  ItemRec *items;
+  int32_t *cnt, *large, *bcnt, *bfill, *qcnt;
+  int64_t *cell_off, *bstart, *qoff, *n_large;
+  Entry *ent;
+  GridDev *g;
+  uint64_t *st;
+  unsigned long long *total;
+};
+
+static eipc_status bp_scratch(eipc_ctx *c, int nq, int ni, uint32_t nb, int64_t ent_cap, int slot, BPScratch &b) {
+  const int base = slot * BP_NBUF;
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 0), (size_t)ni, &b.items));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 1), (size_t)ni, &b.cnt));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 2), (size_t)ni, &b.large));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 3), (size_t)ni + 1, &b.cell_off));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 4), (size_t)nb, &b.bcnt));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 5), (size_t)nb, &b.bfill));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 6), (size_t)nb + 1, &b.bstart));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 7), (size_t)std::max<int64_t>(ent_cap, 1), &b.ent));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 8), (size_t)nq, &b.qcnt));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 9), (size_t)nq + 1, &b.qoff));
+  char *small;
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 10), 512, &small));
+  b.g = (GridDev *)small;
+  b.st = (uint64_t *)(small + 128);
+  b.n_large = (int64_t *)(small + 256);
+  b.total = (unsigned long long *)(small + 264);
+  return EIPC_OK;
 }
 
 eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *x1s,
                         double dhat, int32_t *out, int64_t cap, int64_t *n_out, int sort, hipStream_t s,
-                        int grow_id, int32_t **grown) {
+                        int grow_id, int32_t **grown, const BPPlan *plan, int64_t *d_total) {
   const int nq = kind == 0 ? sc->n_vert : sc->n_edge;
   const int ni = kind == 0 ? sc->n_face : sc->n_edge;
-  *n_out = 0;
-  if (nq == 0 || ni == 0) return EIPC_OK;
+  const int slot = kind + 2 * (x1s != nullptr);
+  if (n_out) *n_out = 0;
+  if (nq == 0 || ni == 0) {
+    if (d_total) EIPC_TRY(launch_zero(c, d_total, 8, s));
+    if (!plan) c->last_plan[slot] = BPPlan{1024, 1, 0};
+    return EIPC_OK;
+  }
   const double h = 0.5 * dhat;
-  ItemRec *items;
-  EIPC_TRY(ensure_t(c, B_IBOX, (size_t)ni, &items));
+  const int32_t *vsc = sc->n_scene > 1 ? sc->vert_scene : nullptr;
+  // phase 1: items, statistics, grid parameters, cell counts (always)
+  BPScratch b;
+  uint32_t nb = plan ? plan->nb : 1024;
+  int64_t ent_cap = plan ? plan->ent_cap : 1;
+  EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b));
   if (kind == 0)
-    k_items<3><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->faces, xs, x1s, sc->n_vert, h, sc->W_rowptr, items);
+    k_items<3><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->faces, xs, x1s, sc->n_vert, h, sc->W_rowptr, vsc, b.items);
   else
-    k_items<2><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->edges, xs, x1s, sc->n_vert, h, sc->W_rowptr, items);
+    k_items<2><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->edges, xs, x1s, sc->n_vert, h, sc->W_rowptr, vsc, b.items);
   EIPC_HIP(c, hipGetLastError());
-  uint64_t *st = (uint64_t *)c->stats;
-  k_stats_init<<<1, 64, 0, s>>>(st);
-  k_box_stats<<<stat_blocks(ni), STAT_T, 0, s>>>(ni, items, nullptr, nullptr, 0, h, st, 1);
-  if (kind == 0) k_box_stats<<<stat_blocks(nq), STAT_T, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, st, 0);
+  k_stats_init<<<1, 64, 0, s>>>(b.st);
+  k_box_stats<<<stat_blocks(ni), STAT_T, 0, s>>>(ni, b.items, nullptr, nullptr, 0, h, b.st, 1);
+  if (kind == 0) k_box_stats<<<stat_blocks(nq), STAT_T, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, b.st, 0);
+  k_grid_params<<<1, 64, 0, s>>>(b.st, ni, c->cell_scale, b.g, c->status);
+  EIPC_TRY(launch_zero(c, b.n_large, 16, s));
+  k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, b.cnt, b.large, b.n_large);
   EIPC_HIP(c, hipGetLastError());
-  uint64_t hs[9];
-  EIPC_HIP(c, hipMemcpyAsync(hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-  EIPC_HIP(c, hipStreamSynchronize(s));
-  double lo[3], hi[3], ext[3];
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = ord_dec(hs[a]);
-    hi[a] = ord_dec(hs[3 + a]);
-    std::memcpy(&ext[a], &hs[6 + a], 8);
-  }
-  if (!(std::isfinite(lo[0]) && std::isfinite(lo[1]) && std::isfinite(lo[2]) && std::isfinite(hi[0]) &&
-        std::isfinite(hi[1]) && std::isfinite(hi[2])))
-    return set_err(c, EIPC_ERR_NONFINITE, "non-finite primitive boxes");
-  // cell edge: the mean item box extent (largest axis of the mean)
-  double cell = std::max(ext[0], std::max(ext[1], ext[2])) / ni;
-  double span = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
-  cell = std::max(cell, span * 1e-6);
-  if (!(cell > 0)) cell = 1.0;
-  GridDev g;
-  for (int a = 0; a < 3; ++a) g.o[a] = lo[a];
-  for (;;) {
-    bool ok = true;
-    for (int a = 0; a < 3; ++a) {
-      double d = std::floor((hi[a] - lo[a]) / cell) + 1.0;
-      if (d > (double)(1 << 20)) ok = false;
-      g.dim[a] = (int)std::min(d, (double)(1 << 20));
+  EIPC_TRY(exclusive_scan(c, b.cnt, ni, b.cell_off, s));
+  if (!plan) {
+    // size the hash from the entry count (synchronizes)
+    int64_t hv[2];
+    GridDev gh;
+    EIPC_HIP(c, hipMemcpyAsync(&hv[0], b.cell_off + ni, 8, hipMemcpyDeviceToHost, s));
+    EIPC_HIP(c, hipMemcpyAsync(&gh, b.g, sizeof(GridDev), hipMemcpyDeviceToHost, s));
+    EIPC_HIP(c, hipStreamSynchronize(s));
+    if (gh.bad) {
+      EIPC_TRY(launch_zero(c, c->status, 4, s));  // reported here instead
+      return set_err(c, EIPC_ERR_NONFINITE, "non-finite primitive boxes");
     }
-    if (ok) break;
-    cell *= 2.0;
+    ent_cap = std::max<int64_t>(hv[0], 1);
+    nb = next_pow2((uint64_t)std::max<int64_t>(2 * hv[0], 1024));
+    EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b));
+    c->last_plan[slot].nb = nb;
+    c->last_plan[slot].ent_cap = ent_cap;
   }
-  g.inv_h = 1.0 / cell;
-  int32_t *cnt, *large;
-  int64_t *cell_off;
-  EIPC_TRY(ensure_t(c, B_CELLCNT, (size_t)ni, &cnt));
-  EIPC_TRY(ensure_t(c, B_LARGE, (size_t)ni, &large));
-  EIPC_TRY(ensure_t(c, B_CELLOFF, (size_t)ni + 1, &cell_off));
-  EIPC_TRY(launch_zero(c, c->counters, 16 * sizeof(int64_t), s));
-  g.bmask = 0;
-  g.bstart = nullptr;
-  g.ent = nullptr;
-  g.large = large;
-  g.n_large = 0;
-  k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, g, cnt, large, c->counters);
+  const uint32_t bmask = nb - 1;
+  EIPC_TRY(launch_zero(c, b.bcnt, sizeof(int32_t) * nb, s));
+  EIPC_TRY(launch_zero(c, b.bfill, sizeof(int32_t) * nb, s));
+  k_item_hist<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bcnt);
   EIPC_HIP(c, hipGetLastError());
-  EIPC_TRY(exclusive_scan(c, cnt, ni, cell_off, s));
-  int64_t hv[2];
-  EIPC_HIP(c, hipMemcpyAsync(&hv[0], cell_off + ni, 8, hipMemcpyDeviceToHost, s));
-  EIPC_HIP(c, hipMemcpyAsync(&hv[1], c->counters, 8, hipMemcpyDeviceToHost, s));
-  EIPC_HIP(c, hipStreamSynchronize(s));
-  const int64_t n_ent = hv[0];
-  g.n_large = (int)hv[1];
-  const uint32_t nb = next_pow2((uint64_t)std::max<int64_t>(2 * n_ent, 1024));
-  g.bmask = nb - 1;
-  int32_t *bcnt, *bfill;
-  int64_t *bstart;
-  Entry *ent;
-  EIPC_TRY(ensure_t(c, B_BCNT, nb, &bcnt));
-  EIPC_TRY(ensure_t(c, B_BFILL, nb, &bfill));
-  EIPC_TRY(ensure_t(c, B_BSTART, (size_t)nb + 1, &bstart));
-  EIPC_TRY(ensure_t(c, B_ENTCELL, (size_t)std::max<int64_t>(n_ent, 1), &ent));
-  EIPC_TRY(launch_zero(c, bcnt, sizeof(int32_t) * nb, s));
-  EIPC_TRY(launch_zero(c, bfill, sizeof(int32_t) * nb, s));
-  k_item_hist<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, g, cnt, bcnt);
+  EIPC_TRY(exclusive_scan(c, b.bcnt, nb, b.bstart, s));
+  k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bstart, b.bfill, b.ent, ent_cap,
+                                                 c->status);
   EIPC_HIP(c, hipGetLastError());
-  EIPC_TRY(exclusive_scan(c, bcnt, nb, bstart, s));
-  g.bstart = bstart;
-  k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, items, g, cnt, bfill, ent);
-  EIPC_HIP(c, hipGetLastError());
-  g.ent = ent;
+  QueryArgs qa{b.g, bmask, b.bstart, b.ent, ent_cap, b.large, b.n_large, b.items, sc->W_rowptr, vsc};
   const int n_vert = sc->n_vert;
-  const int32_t *rp = sc->W_rowptr;
   if (!sort) {
-    // single pass, unsorted append into a buffer grown to the required size
-    unsigned long long *tot = (unsigned long long *)(c->counters + 8);
+    // single pass, unsorted append
     int64_t capa = cap;
-    if (grow_id >= 0) {
+    if (plan) {
+      capa = plan->cand_cap;
+    } else if (grow_id >= 0) {
       capa = (int64_t)(c->buf[grow_id].bytes / 8);
       if (capa > 64) capa -= 16;
       EIPC_TRY(ensure_t(c, (BufId)grow_id, (size_t)std::max<int64_t>(2 * capa, 2), &out));
     }
     for (int attempt = 0; attempt < 2; ++attempt) {
-      EIPC_TRY(launch_zero(c, tot, 8, s));
+      EIPC_TRY(launch_zero(c, b.total, 8, s));
       {
         ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
         if (kind == 0)
-          launch_query<0, 2>(nq, xs, x1s, n_vert, h, rp, items, g, nullptr, nullptr, out, capa, tot, s);
+          launch_query<0, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
         else
-          launch_query<1, 2>(nq, xs, x1s, n_vert, h, rp, items, g, nullptr, nullptr, out, capa, tot, s);
+          launch_query<1, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
       }
       EIPC_HIP(c, hipGetLastError());
+      if (plan) {
+        // device-side count for the consumer; overflow is detected there
+        k_copy_count<<<1, 1, 0, s>>>((const int64_t *)b.total, d_total, capa, c->status);
+        EIPC_HIP(c, hipGetLastError());
+        return EIPC_OK;
+      }
       int64_t total = 0;
-      EIPC_HIP(c, hipMemcpyAsync(&total, tot, 8, hipMemcpyDeviceToHost, s));
+      EIPC_HIP(c, hipMemcpyAsync(&total, b.total, 8, hipMemcpyDeviceToHost, s));
       EIPC_HIP(c, hipStreamSynchronize(s));
-      *n_out = total;
+      if (n_out) *n_out = total;
       if (total <= capa) {
         if (grown) *grown = out;
+        c->last_plan[slot].cand_cap = total;
         return EIPC_OK;
       }
       if (grow_id < 0) return EIPC_ERR_CAPACITY;
@@ -710,36 +807,43 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
     }
     return set_err(c, EIPC_ERR_CAPACITY, "candidate append did not converge");
   }
-  int32_t *qcnt;
-  int64_t *qoff;
-  EIPC_TRY(ensure_t(c, B_QCNT, (size_t)nq, &qcnt));
-  EIPC_TRY(ensure_t(c, B_QOFF, (size_t)nq + 1, &qoff));
   {
     ProfScope ps(c, kind == 0 ? K_QUERY_COUNT_PT : K_QUERY_COUNT_EE, s);
     if (kind == 0)
-      launch_query<0, 0>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, nullptr, nullptr, 0, nullptr, s);
+      launch_query<0, 0>(nq, xs, x1s, n_vert, h, qa, b.qcnt, nullptr, nullptr, 0, nullptr, c->status, s);
     else
-      launch_query<1, 0>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, nullptr, nullptr, 0, nullptr, s);
+      launch_query<1, 0>(nq, xs, x1s, n_vert, h, qa, b.qcnt, nullptr, nullptr, 0, nullptr, c->status, s);
   }
   EIPC_HIP(c, hipGetLastError());
-  EIPC_TRY(exclusive_scan(c, qcnt, nq, qoff, s));
-  int64_t total = 0;
-  EIPC_HIP(c, hipMemcpyAsync(&total, qoff + nq, 8, hipMemcpyDeviceToHost, s));
-  EIPC_HIP(c, hipStreamSynchronize(s));
-  *n_out = total;
-  if (grow_id >= 0) {
-    EIPC_TRY(ensure_t(c, (BufId)grow_id, (size_t)std::max<int64_t>(2 * total, 2), &out));
-    cap = total;
-    *grown = out;
+  EIPC_TRY(exclusive_scan(c, b.qcnt, nq, b.qoff, s));
+  if (plan) {
+    cap = plan->cand_cap;
+  } else {
+    int64_t total = 0;
+    EIPC_HIP(c, hipMemcpyAsync(&total, b.qoff + nq, 8, hipMemcpyDeviceToHost, s));
+    EIPC_HIP(c, hipStreamSynchronize(s));
+    if (n_out) *n_out = total;
+    c->last_plan[slot].cand_cap = total;
+    if (grow_id >= 0) {
+      EIPC_TRY(ensure_t(c, (BufId)grow_id, (size_t)std::max<int64_t>(2 * total, 2), &out));
+      cap = total;
+      *grown = out;
+    }
+    if (total > cap || out == nullptr) return total > cap ? EIPC_ERR_CAPACITY : EIPC_OK;
+    if (total == 0) return EIPC_OK;
   }
-  if (total > cap || out == nullptr) return total > cap ? EIPC_ERR_CAPACITY : EIPC_OK;
-  if (total == 0) return EIPC_OK;
-  ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
-  if (kind == 0)
-    launch_query<0, 1>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, qoff, out, cap, nullptr, s);
-  else
-    launch_query<1, 1>(nq, xs, x1s, n_vert, h, rp, items, g, qcnt, qoff, out, cap, nullptr, s);
+  {
+    ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
+    if (kind == 0)
+      launch_query<0, 1>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qoff, out, cap, nullptr, c->status, s);
+    else
+      launch_query<1, 1>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qoff, out, cap, nullptr, c->status, s);
+  }
   EIPC_HIP(c, hipGetLastError());
+  if (plan) {
+    k_copy_count<<<1, 1, 0, s>>>(b.qoff + nq, d_total, cap, c->status);
+    EIPC_HIP(c, hipGetLastError());
+  }
   return EIPC_OK;
 }
 
@@ -765,51 +869,57 @@ __device__ __forceinline__ void pair_vids(const int32_t *pairs, int64_t k, const
 }
 
 template <int KIND>
-__global__ void k_narrow(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
-                         const int32_t *__restrict__ edges, const double *__restrict__ xs, int n_vert, double dhat2,
-                         int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t *count, uint32_t *status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool active = false;
-  int ty = 0;
-  if (i < n) {
-    int vid[4];
-    pair_vids<KIND>(pairs, i, faces, edges, vid);
-    V3 x[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) x[a] = V3{xs[vid[a]], xs[n_vert + vid[a]], xs[2 * (int64_t)n_vert + vid[a]]};
-    double s2 = pair_dist2<KIND>(x, &ty);
-    if (!isfinite(s2)) {
-      atomicOr(status, ST_NONFINITE);
-    } else if (s2 < dhat2) {
-      if (s2 <= 0.0)
-        atomicOr(status, ST_INTERSECTING);
-      else
-        active = true;
-    }
-  }
-  const uint64_t mask = __ballot(active);
+__global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
+                         const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
+                         const double *__restrict__ xs, int n_vert, double dhat2, int32_t *__restrict__ act,
+                         int32_t *__restrict__ typ, int64_t *count, uint32_t *status) {
+  const int64_t n = d_n ? (*d_n < cap ? *d_n : cap) : cap;
   const int lane = threadIdx.x & 63;
-  int64_t base = 0;
-  if (lane == 0 && mask) base = (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(mask));
-  base = __shfl(base, 0, 64);
-  if (active) {
-    const int64_t pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-    act[pos] = (int32_t)i;
-    typ[pos] = ty;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    bool active = false;
+    int ty = 0;
+    if (i < n) {
+      int vid[4];
+      pair_vids<KIND>(pairs, i, faces, edges, vid);
+      V3 x[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) x[a] = V3{xs[vid[a]], xs[n_vert + vid[a]], xs[2 * (int64_t)n_vert + vid[a]]};
+      double s2 = pair_dist2<KIND>(x, &ty);
+      if (!isfinite(s2)) {
+        atomicOr(status, ST_NONFINITE);
+      } else if (s2 < dhat2) {
+        if (s2 <= 0.0)
+          atomicOr(status, ST_INTERSECTING);
+        else
+          active = true;
+      }
+    }
+    const uint64_t mask = __ballot(active);
+    int64_t pos0 = 0;
+    if (lane == 0 && mask) pos0 = (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(mask));
+    pos0 = __shfl(pos0, 0, 64);
+    if (active) {
+      const int64_t pos = pos0 + __popcll(mask & ((1ull << lane) - 1ull));
+      act[pos] = (int32_t)i;
+      typ[pos] = ty;
+    }
   }
 }
 
 eipc_status launch_narrow(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
-                          int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s) {
+                          int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s,
+                          const int64_t *d_n) {
   if (n == 0) return EIPC_OK;
   const double d2 = dhat * dhat;
+  const int blocks = (int)std::min<int64_t>(grid_for(n, 256), (int64_t)c->wg_per_cu[2] * c->num_cu);
   ProfScope ps(c, kind == 0 ? K_NARROW_PT : K_NARROW_EE, s);
   if (kind == 0)
-    k_narrow<0><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ,
-                                                  d_count, c->status);
+    k_narrow<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ, d_count,
+                                        c->status);
   else
-    k_narrow<1><<<grid_for(n, 256), 256, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ,
-                                                  d_count, c->status);
+    k_narrow<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ, d_count,
+                                        c->status);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }

@@ -329,10 +329,10 @@ def config3(seed: int = 0, n_cyl: int = 40, spacing: float = 1.75e-3) -> Scene:
 # Config 2 / batch: conformed bubble grasp
 # ---------------------------------------------------------------------------
 
-def _real_sh_basis(lmax: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
-    """Real spherical harmonics for 1 <= l <= lmax at polar angle theta and
-    azimuth phi, one column per (l, m), m = -l..l.  Associated Legendre
-    functions by the standard three-term recurrence in l."""
+def _real_sh_sum(lmax: int, theta: np.ndarray, phi: np.ndarray, coef: np.ndarray) -> np.ndarray:
+    """sum over 1 <= l <= lmax, -l <= m <= l of coef[(l, m)] Y_lm(theta, phi)
+    for real spherical harmonics (coefficients in (l, m) order).  Associated
+    Legendre functions by the standard three-term recurrence in l."""
     x = np.cos(theta)
     sx = np.sqrt(np.maximum(1.0 - x * x, 0.0))
     P = {}
@@ -345,18 +345,22 @@ def _real_sh_basis(lmax: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
             P[m + 1, m] = x * (2 * m + 1) * pmm
         for l in range(m + 2, lmax + 1):
             P[l, m] = ((2 * l - 1) * x * P[l - 1, m] - (l + m - 1) * P[l - 2, m]) / (l - m)
-    cols = []
+    cosm = [np.cos(m * phi) for m in range(lmax + 1)]
+    sinm = [np.sin(m * phi) for m in range(lmax + 1)]
+    out = np.zeros_like(x)
+    k = 0
     for l in range(1, lmax + 1):
         for m in range(-l, l + 1):
             am = abs(m)
             norm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
             if m < 0:
-                cols.append(math.sqrt(2) * norm * P[l, am] * np.sin(am * phi))
+                out += (coef[k] * math.sqrt(2) * norm) * P[l, am] * sinm[am]
             elif m == 0:
-                cols.append(norm * P[l, 0])
+                out += (coef[k] * norm) * P[l, 0]
             else:
-                cols.append(math.sqrt(2) * norm * P[l, am] * np.cos(am * phi))
-    return np.stack(cols, axis=1)
+                out += (coef[k] * math.sqrt(2) * norm) * P[l, am] * cosm[am]
+            k += 1
+    return out
 
 
 class Blob:
@@ -375,39 +379,38 @@ class Blob:
     def _pert(self, d):
         th = np.arccos(np.clip(d[:, 2], -1, 1))
         ph = np.arctan2(d[:, 1], d[:, 0])
-        return _real_sh_basis(self.lmax, th, ph) @ self.a
+        return _real_sh_sum(self.lmax, th, ph, self.a)
 
     def radius(self, d):
         return self.r0 * (1.0 + self._pert(d))
 
-    def first_hit(self, origin: np.ndarray, direction: np.ndarray, t_hi: float):
-        """Smallest t in [0, t_hi] where origin + t dir enters the body
-        (bisection on a coarse march), or nan if the ray misses."""
+    def inside(self, p: np.ndarray) -> np.ndarray:
+        r = np.linalg.norm(p, axis=-1)
+        d = p / np.maximum(r, 1e-300)[..., None]
+        return r < self.radius(d.reshape(-1, 3)).reshape(r.shape)
+
+    def first_hit(self, origin: np.ndarray, direction: np.ndarray, t_hi: float, n_march: int = 96):
+        """Smallest t in [0, t_hi] where origin + t dir enters the body:
+        a march over all rays at once, then a joint bisection on the first
+        bracketing interval (nan where a ray misses)."""
         n = len(origin)
-        ts = np.linspace(0.0, t_hi, 160)
-        hit = np.full(n, np.nan)
-        prev_in = np.zeros(n, dtype=bool)
-        prev_t = np.zeros(n)
-        for t in ts:
-            p = origin + t * direction
-            r = np.linalg.norm(p, axis=1)
-            inside = r < self.radius(p / np.maximum(r, 1e-300)[:, None])
-            new = inside & ~prev_in & np.isnan(hit)
-            if new.any():
-                lo = prev_t[new].copy()
-                hi = np.full(new.sum(), t)
-                o = origin[new]
-                for _ in range(60):
-                    mid = 0.5 * (lo + hi)
-                    pm = o + mid[:, None] * direction
-                    rm = np.linalg.norm(pm, axis=1)
-                    ins = rm < self.radius(pm / rm[:, None])
-                    hi = np.where(ins, mid, hi)
-                    lo = np.where(ins, lo, mid)
-                hit[new] = lo
-            prev_in = inside
-            prev_t[:] = t
-        return hit
+        if n == 0:
+            return np.zeros(0)
+        ts = np.linspace(0.0, t_hi, n_march)
+        P = origin[:, None, :] + ts[None, :, None] * direction[None, None, :]
+        ins = self.inside(P)
+        first = np.argmax(ins, axis=1)
+        hit = ins[np.arange(n), first]
+        hit &= first > 0
+        lo = np.where(hit, ts[np.maximum(first - 1, 0)], 0.0)
+        hi = np.where(hit, ts[first], 0.0)
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            pm = origin + mid[:, None] * direction
+            ins_m = self.inside(pm)
+            hi = np.where(ins_m, mid, hi)
+            lo = np.where(ins_m, lo, mid)
+        return np.where(hit, lo, np.nan)
 
 
 def _conformed_finger(blob: Blob, obj_v: np.ndarray, nu: int, semi, side: float,

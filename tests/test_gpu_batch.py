@@ -1,0 +1,188 @@
+"""Batched form: ragged grasp scenes concatenated into one planned contact
+step, eager and replayed from a captured HIP graph.  Per scene the batch
+must reproduce the single-scene calls (candidate and active counts exactly,
+energy, reduced gradient and Hessian to rounding, the step bound bit for
+bit) and, on sampled scenes, the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import paper_2409_16385_amd as E  # noqa: E402
+from paper_2409_16385_amd import batch as BT  # noqa: E402
+from scenes import scene as S  # noqa: E402
+
+TOL = 1e-10
+
+
+def _small_scenes(n=7):
+    """Ragged small grasps (object frequency 6..17, 60..400 nodes, fingers
+    of frequency 8, random orientation); the last scene has its fingers
+    moved 1 m away so it has no proximity pairs."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(500 + i)
+        sc = S.grasp_scene(500 + i, int(rng.integers(6, 18)), int(rng.integers(60, 400)), 8,
+                           frac=float(rng.uniform(0.2, 0.8)), rotate=True, name=f"small{i}")
+        out.append(sc)
+    last = out[-1]
+    n_obj = int(np.prod(last.meta["obj_grid"]))
+    q = last.q.reshape(-1, 3).copy()
+    q[n_obj:, 0] += 1.0
+    last.q = q.reshape(-1)
+    return out
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return E.Context(0)
+
+
+@pytest.fixture(scope="module")
+def scenes():
+    return _small_scenes()
+
+
+@pytest.fixture(scope="module")
+def seq(ctx, scenes):
+    res, _ = BT.sequential_reference(ctx, scenes)
+    return res
+
+
+@pytest.fixture(scope="module")
+def batch(ctx, scenes):
+    b = BT.Batch(ctx, BT.concat(scenes))
+    b.make_plan(1.5)
+    return b
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    d = np.linalg.norm(a - b)
+    n = np.linalg.norm(b)
+    return d / n if n > 0 else d
+
+
+def _scene_hess(bsr, hb, i):
+    rp, col, blk = (t.cpu().numpy() for t in bsr)
+    n0, n1 = hb.node_off[i], hb.node_off[i + 1]
+    m = n1 - n0
+    H = np.zeros((3 * m, 3 * m))
+    for r in range(n0, n1):
+        for p in range(rp[r], rp[r + 1]):
+            c = col[p]
+            assert n0 <= c < n1, "a block joins two scenes"
+            H[3 * (r - n0):3 * (r - n0) + 3, 3 * (c - n0):3 * (c - n0) + 3] = blk[p]
+    return H
+
+
+def _check_against_sequential(b, seq, scenes):
+    cnt = b.counts()
+    assert cnt["cand_pt"] == sum(r["n_pt"] for r in seq)
+    assert cnt["cand_ee"] == sum(r["n_ee"] for r in seq)
+    assert cnt["active"] == sum(r["n_active"] for r in seq)
+    assert cnt["swept_pt"] + cnt["swept_ee"] == sum(r["n_swept"] for r in seq)
+    energy = b.out.energy.cpu().numpy()
+    alpha = b.out.alpha.cpu().numpy()
+    bsr = b.out.hess(b.ctx)
+    for i, (r, sc) in enumerate(zip(seq, scenes)):
+        e_ref = float(r["energy"][0])
+        assert energy[i] == pytest.approx(e_ref, rel=1e-12, abs=0.0)
+        assert _rel(b.per_scene_grad(i).cpu().numpy(), r["grad"].cpu().numpy()) <= 1e-12
+        H_ref = E.bsr_to_dense(*r["hess"], sc.n_node)
+        assert _rel(_scene_hess(bsr, b.hb, i), H_ref) <= 1e-12
+        assert alpha[i] == r["alpha"]
+
+
+def test_batch_layout(batch, scenes):
+    hb = batch.hb
+    assert hb.n_scene == len(scenes)
+    assert hb.vert_off[-1] == sum(s.n_vert for s in scenes)
+    assert batch.plan.cand_pt > 0 and batch.plan.hess_blocks > 0
+
+
+def test_eager_step_matches_sequential(batch, seq, scenes):
+    batch.step()
+    assert batch.status() == E.binding.OK
+    _check_against_sequential(batch, seq, scenes)
+    assert seq[-1]["n_active"] == 0 and batch.out.energy[-1].item() == 0.0
+
+
+@pytest.mark.parametrize("i", [0, 3])
+def test_batch_scene_against_oracle(batch, scenes, i):
+    batch.step()
+    assert batch.status() == E.binding.OK
+    sc = scenes[i]
+    x = O.embed(sc, sc.q)
+    opt, oee = O.candidates(sc, x, sc.dhat)
+    ref = O.barrier_reduce(sc, sc.q, opt, oee, sc.dhat, sc.kappa, O.ENERGY | O.GRAD | O.HESS | O.PROJECT)
+    assert batch.out.energy[i].item() == pytest.approx(ref["energy"], rel=TOL)
+    assert _rel(batch.per_scene_grad(i).cpu().numpy(), ref["grad"]) <= TOL
+    H = _scene_hess(batch.out.hess(batch.ctx), batch.hb, i)
+    assert _rel(H, ref["hess"]) <= TOL
+    a_ref, _, _ = O.ccd_max_step(sc, sc.q, sc.dq, sc.dhat)
+    a = batch.out.alpha[i].item()
+    assert a <= a_ref and a == a_ref
+
+
+def test_graph_replays_match_eager(batch, scenes):
+    """Capture once; replay on three different q (written into the
+    captured input) with eager work in between; each replay equals an eager
+    step on the same q."""
+    batch.capture()
+    q0 = batch.q.clone()
+    rng = np.random.default_rng(3)
+    for k in range(3):
+        dq = torch.as_tensor(rng.normal(0.0, 2e-6, q0.shape), device=q0.device)
+        batch.q.copy_(q0 + dq)
+        _ = (batch.q * 2.0).sum().item()  # unrelated eager work between replays
+        batch.replay()
+        assert batch.status() == E.binding.OK
+        g_e = batch.out.energy.clone()
+        g_g = batch.out.grad.clone()
+        g_a = batch.out.alpha.clone()
+        g_c = batch.out.counts.clone()
+        batch.step()
+        assert batch.status() == E.binding.OK
+        assert torch.equal(g_c, batch.out.counts)
+        assert torch.equal(g_a, batch.out.alpha)
+        assert _rel(g_e.cpu().numpy(), batch.out.energy.cpu().numpy()) <= 1e-12
+        assert _rel(g_g.cpu().numpy(), batch.out.grad.cpu().numpy()) <= 1e-12
+    batch.q.copy_(q0)
+
+
+def test_plan_overflow_is_reported(batch):
+    """A plan with too few candidate slots reports a capacity error (the
+    kernels stay within the planned buffers) and the next good step is
+    clean."""
+    small = E.Plan.from_buffer_copy(batch.plan)
+    small.cand_pt = 16
+    small.cand_ee = 16
+    E.contact_step(batch.ctx, batch.scene, small, batch.q, batch.hb.dhat, batch.hb.kappa, batch.out, batch.dq,
+                   None, BT.DEFAULT_FLAGS)
+    assert batch.status() == E.binding.ERR_CAPACITY
+    batch.step()
+    assert batch.status() == E.binding.OK
+
+
+def test_autotune_keeps_results(ctx, scenes, seq):
+    b = BT.Batch(ctx, BT.concat(scenes))
+    t = b.autotune(cell_scales=(1.0, 2.0), wg_values=(2, 8), reps=1)
+    assert t["cell_scale"] in (1.0, 2.0) and all(v in (2, 8) for v in t["wg_per_cu"])
+    b.step()
+    assert b.status() == E.binding.OK
+    _check_against_sequential(b, seq, scenes)
+    E.set_tuning(ctx, 2.0, [8, 2, 4, 4])
+
+
+def test_bad_scene_id_is_an_argument_error(ctx, scenes):
+    hb = BT.concat(scenes[:2])
+    hb.vert_scene = hb.vert_scene.copy()
+    hb.vert_scene[-5:] = 2  # == n_scene: out of range
+    b = BT.Batch(ctx, hb)
+    with pytest.raises(E.EipcError):
+        b.make_plan(1.5)
+    ctx.sync_status()
