@@ -60,6 +60,8 @@ def _args():
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--no-graph", action="store_true", help="time eager planned steps instead of graph replays")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed tuning 'cell_scale,wg_terms,wg_expand,wg_narrow,wg_ccd' (skips the autotuner)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -281,7 +283,12 @@ def main():
         sync()
         del src, dst
     tuning = None
-    if not a.no_autotune:
+    if a.tuning:
+        v = [float(t) for t in a.tuning.split(",")]
+        tuning = {"cell_scale": v[0], "wg_per_cu": [int(t) for t in v[1:5]]}
+        E.set_tuning(ctx, tuning["cell_scale"], tuning["wg_per_cu"])
+        bt.make_plan(1.5)
+    elif not a.no_autotune:
         t1 = time.perf_counter()
         tuning = bt.autotune(reps=2)
         log(f"autotune: cell_scale={tuning['cell_scale']} wg_per_cu={tuning['wg_per_cu']} "

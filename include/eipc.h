@@ -185,8 +185,9 @@ eipc_status eipc_barrier_hvp(eipc_ctx *ctx, const eipc_scene *sc, const double *
 
 /* Capacities of a planned step (element counts). */
 typedef struct {
-  int64_t cand_pt, cand_ee;   /* proximity candidates */
+  int64_t cand_pt, cand_ee;   /* proximity candidates (only used when the step bound is not asked for) */
   int64_t swept_pt, swept_ee; /* swept candidates for the step bound */
+  int64_t act_pt, act_ee;     /* active pairs */
   int64_t ent[4];             /* broad-phase hash entries: PT, EE, swept PT, swept EE */
   int64_t buckets[4];         /* broad-phase hash buckets (powers of 2) */
   int64_t hess_blocks;        /* reduced-Hessian block table (power of 2); 0: no Hessian */
@@ -207,7 +208,11 @@ eipc_status eipc_plan_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q,
  * (projected with EIPC_PROJECT) reduced Hessian, and the conservative step
  * bound alpha per scene for the search direction dq (+ dx_off), with the
  * semantics of eipc_build_candidates, eipc_barrier_reduce and
- * eipc_ccd_max_step.  Enqueues work only: no synchronization, no
+ * eipc_ccd_max_step.  When alpha is asked for, one swept broad phase serves
+ * both: every candidate at q is a swept candidate (the swept boxes contain
+ * the boxes at q), so the candidates at q are the swept candidates that
+ * pass the candidate predicate at q, tested pair by pair before the
+ * distance.  Enqueues work only: no synchronization, no
  * allocation, no host-side reads of device data, so it can be captured in
  * a HIP graph and replayed with new contents of q and dq.
  *   energy   device double[n_scene] or NULL     grad_q  device double[3*n_node] or NULL
@@ -215,7 +220,11 @@ eipc_status eipc_plan_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q,
  *            BSR view with nnzb = -1 (the count is rowptr[n_rows] on the device)
  *   alpha    device double[n_scene] or NULL: step bound per scene (dq may be NULL when NULL)
  *   counts   device int64[5] or NULL: PT and EE candidates, active pairs, swept PT and EE
- * Capacity overflow and data errors are reported by eipc_sync_status. */
+ * Capacity overflow and data errors are reported by eipc_sync_status.
+ * A graph captured from this call keeps the context's scratch addresses:
+ * it stays valid while only planned steps of the same (or a smaller) plan
+ * run on the context; any other entry point or a larger plan may move
+ * that scratch, after which the graph must be captured again. */
 eipc_status eipc_contact_step(eipc_ctx *ctx, const eipc_scene *sc, const eipc_plan *plan, const double *q,
                               const double *dq, const double *dx_off, double dhat, double kappa, uint32_t flags,
                               double s, double t_max, int64_t max_iter, double *energy, double *grad_q,

@@ -194,7 +194,8 @@ def gradient_hessian(prob: StepProblem, q, project: bool):
 def solve_step(prob: StepProblem, tol: float = 1e-12, max_iter: int = 100, verbose: bool = False):
     """Projected Newton with CCD-clamped backtracking (Armijo); switches to
     the true Hessian when it is positive definite.  Converged when
-    |grad E| <= tol |M qt| (or the step no longer changes q)."""
+    |grad E| <= tol |M qt|, when the Newton decrement falls below the
+    energy's rounding level, or when the step no longer changes q."""
     q = prob.q_n.clone()
     qt = prob.q_n + prob.h * prob.v_n
     scale = float(torch.linalg.vector_norm(prob.M @ qt))
@@ -216,10 +217,14 @@ def solve_step(prob: StepProblem, tol: float = 1e-12, max_iter: int = 100, verbo
         info["true_hessian_steps"] += int(used_true)
         dq = -g.clone()
         B.cholesky_solve(prob.ctx, L, dq)
-        alpha, _, _ = B.ccd_max_step(prob.ctx, prob.scene, q, dq, prob.dhat)
-        alpha = min(1.0, alpha)
         e0 = energy(prob, q)
         slope = float(g @ dq)
+        # the predicted decrease (half the Newton decrement) is below the
+        # rounding level of the energy: nothing left to gain
+        if -0.5 * slope <= 1e-15 * abs(e0):
+            break
+        alpha, _, _ = B.ccd_max_step(prob.ctx, prob.scene, q, dq, prob.dhat)
+        alpha = min(1.0, alpha)
         while True:
             q1 = q + alpha * dq
             if energy(prob, q1) <= e0 + 1e-4 * alpha * slope or alpha < 1e-12:

@@ -99,13 +99,16 @@ class Batch:
     """Device batch with a planned, graph-captured contact step.
 
     ``q``, ``dq`` (and ``dx_off``) are device tensors with fixed storage:
-    write new values into them (``copy_``) and call ``replay()``.
+    write new values into them (``copy_``) and call ``replay()``.  The batch
+    owns a library context of its own on the device of ``ctx``: a captured
+    graph holds that context's scratch addresses, which stay fixed as long
+    as only planned steps run on it.
     """
 
     def __init__(self, ctx: B.Context, hb: HostBatch, flags: int = DEFAULT_FLAGS, s: float = 0.1,
                  t_max: float = 1.0, max_iter: int = 100000):
         dev = ctx.torch_device
-        self.ctx, self.hb = ctx, hb
+        self.ctx, self.hb = B.Context(ctx.device), hb
         self.scene = B.Scene(ctx, hb.faces, hb.edges, hb.W_rowptr, hb.W_col, hb.W_val, hb.n_node, hb.x_off,
                              hb.x_rest, n_scene=hb.n_scene, vert_scene=hb.vert_scene)
         self.q = torch.as_tensor(hb.q, dtype=torch.float64, device=dev).clone()

@@ -44,11 +44,13 @@ class _Bsr(C.Structure):
 class Plan(C.Structure):
     """Capacities of a planned contact step (eipc_plan)."""
     _fields_ = [("cand_pt", _I64), ("cand_ee", _I64), ("swept_pt", _I64), ("swept_ee", _I64),
+                ("act_pt", _I64), ("act_ee", _I64),
                 ("ent", _I64 * 4), ("buckets", _I64 * 4), ("hess_blocks", _I64), ("nnzb", _I64)]
 
     def as_dict(self) -> dict:
         return {"cand_pt": self.cand_pt, "cand_ee": self.cand_ee, "swept_pt": self.swept_pt,
-                "swept_ee": self.swept_ee, "ent": list(self.ent), "buckets": list(self.buckets),
+                "swept_ee": self.swept_ee, "act_pt": self.act_pt, "act_ee": self.act_ee,
+                "ent": list(self.ent), "buckets": list(self.buckets),
                 "hess_blocks": self.hess_blocks, "nnzb": self.nnzb}
 
 

@@ -542,7 +542,8 @@ __global__ void k_step_counts(const int64_t *cn, int64_t *out) {
 
 static eipc_status check_plan(eipc_ctx *c, const eipc_plan *p) {
   if (!p) return set_err(c, EIPC_ERR_ARG, "plan is NULL");
-  if (p->cand_pt < 0 || p->cand_ee < 0 || p->swept_pt < 0 || p->swept_ee < 0 || p->hess_blocks < 0 || p->nnzb < 0)
+  if (p->cand_pt < 0 || p->cand_ee < 0 || p->swept_pt < 0 || p->swept_ee < 0 || p->act_pt < 0 || p->act_ee < 0 ||
+      p->hess_blocks < 0 || p->nnzb < 0)
     return set_err(c, EIPC_ERR_ARG, "negative plan capacity");
   for (int k = 0; k < 4; ++k) {
     const int64_t b = p->buckets[k];
@@ -574,29 +575,51 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   const int64_t n3v = 3 * (int64_t)sc->n_vert;
-  double *xs;
-  EIPC_TRY(ensure_t(c, B_X, (size_t)n3v + 1, &xs));
-  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
-  // proximity candidates (unsorted), counts on the device
-  int32_t *pt, *ee;
-  EIPC_TRY(ensure_t(c, B_STEP_PT, (size_t)2 * std::max<int64_t>(plan->cand_pt, 1), &pt));
-  EIPC_TRY(ensure_t(c, B_STEP_EE, (size_t)2 * std::max<int64_t>(plan->cand_ee, 1), &ee));
-  int64_t *cn = c->counters;
+  int64_t *cn = c->counters;  // [2,3] active, [5,6] candidates, [7,8] swept candidates
   const BPPlan bp[4] = {{(uint32_t)plan->buckets[0], plan->ent[0], plan->cand_pt},
                         {(uint32_t)plan->buckets[1], plan->ent[1], plan->cand_ee},
                         {(uint32_t)plan->buckets[2], plan->ent[2], plan->swept_pt},
                         {(uint32_t)plan->buckets[3], plan->ent[3], plan->swept_ee}};
-  EIPC_TRY(launch_zero(c, cn + 2, 7 * sizeof(int64_t), s));  // active PT/EE, (4), candidates, swept
-  EIPC_TRY(broad_phase(c, sc, 0, xs, nullptr, dhat, pt, plan->cand_pt, nullptr, 0, s, -1, nullptr, &bp[0], cn + 5));
-  EIPC_TRY(broad_phase(c, sc, 1, xs, nullptr, dhat, ee, plan->cand_ee, nullptr, 0, s, -1, nullptr, &bp[1], cn + 6));
-  // narrow phase
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)n3v + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_zero(c, cn + 2, 7 * sizeof(int64_t), s));
   int32_t *act_pt, *typ_pt, *act_ee, *typ_ee;
-  EIPC_TRY(ensure_t(c, B_ACT_PT, (size_t)std::max<int64_t>(plan->cand_pt, 1), &act_pt));
-  EIPC_TRY(ensure_t(c, B_TYP_PT, (size_t)std::max<int64_t>(plan->cand_pt, 1), &typ_pt));
-  EIPC_TRY(ensure_t(c, B_ACT_EE, (size_t)std::max<int64_t>(plan->cand_ee, 1), &act_ee));
-  EIPC_TRY(ensure_t(c, B_TYP_EE, (size_t)std::max<int64_t>(plan->cand_ee, 1), &typ_ee));
-  EIPC_TRY(launch_narrow(c, sc, 0, xs, pt, plan->cand_pt, dhat, act_pt, typ_pt, cn + 2, s, cn + 5));
-  EIPC_TRY(launch_narrow(c, sc, 1, xs, ee, plan->cand_ee, dhat, act_ee, typ_ee, cn + 3, s, cn + 6));
+  EIPC_TRY(ensure_t(c, B_ACT_PT, (size_t)std::max<int64_t>(plan->act_pt, 1), &act_pt));
+  EIPC_TRY(ensure_t(c, B_TYP_PT, (size_t)std::max<int64_t>(plan->act_pt, 1), &typ_pt));
+  EIPC_TRY(ensure_t(c, B_ACT_EE, (size_t)std::max<int64_t>(plan->act_ee, 1), &act_ee));
+  EIPC_TRY(ensure_t(c, B_TYP_EE, (size_t)std::max<int64_t>(plan->act_ee, 1), &typ_ee));
+  const int32_t *pt, *ee;
+  double *ps = nullptr;
+  int32_t *cpt = nullptr, *cee = nullptr;
+  if (alpha) {
+    // one swept broad phase; candidates at q filtered from it pair by pair
+    double *x1s;
+    EIPC_TRY(ensure_t(c, B_P, (size_t)n3v + 1, &ps));
+    EIPC_TRY(ensure_t(c, B_X1, (size_t)n3v + 1, &x1s));
+    EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
+    EIPC_TRY(launch_add_soa(c, n3v, xs, ps, x1s, s));
+    EIPC_TRY(ensure_t(c, B_CAND_PT, (size_t)2 * std::max<int64_t>(plan->swept_pt, 1), &cpt));
+    EIPC_TRY(ensure_t(c, B_CAND_EE, (size_t)2 * std::max<int64_t>(plan->swept_ee, 1), &cee));
+    EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, cpt, plan->swept_pt, nullptr, 0, s, -1, nullptr, &bp[2], cn + 7));
+    EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, cee, plan->swept_ee, nullptr, 0, s, -1, nullptr, &bp[3], cn + 8));
+    EIPC_TRY(launch_narrow(c, sc, 0, xs, cpt, plan->swept_pt, dhat, act_pt, typ_pt, cn + 2, s, cn + 7, plan->act_pt,
+                           cn + 5));
+    EIPC_TRY(launch_narrow(c, sc, 1, xs, cee, plan->swept_ee, dhat, act_ee, typ_ee, cn + 3, s, cn + 8, plan->act_ee,
+                           cn + 6));
+    pt = cpt;
+    ee = cee;
+  } else {
+    int32_t *ppt, *pee;
+    EIPC_TRY(ensure_t(c, B_STEP_PT, (size_t)2 * std::max<int64_t>(plan->cand_pt, 1), &ppt));
+    EIPC_TRY(ensure_t(c, B_STEP_EE, (size_t)2 * std::max<int64_t>(plan->cand_ee, 1), &pee));
+    EIPC_TRY(broad_phase(c, sc, 0, xs, nullptr, dhat, ppt, plan->cand_pt, nullptr, 0, s, -1, nullptr, &bp[0], cn + 5));
+    EIPC_TRY(broad_phase(c, sc, 1, xs, nullptr, dhat, pee, plan->cand_ee, nullptr, 0, s, -1, nullptr, &bp[1], cn + 6));
+    EIPC_TRY(launch_narrow(c, sc, 0, xs, ppt, plan->cand_pt, dhat, act_pt, typ_pt, cn + 2, s, cn + 5, plan->act_pt));
+    EIPC_TRY(launch_narrow(c, sc, 1, xs, pee, plan->cand_ee, dhat, act_ee, typ_ee, cn + 3, s, cn + 6, plan->act_ee));
+    pt = ppt;
+    ee = pee;
+  }
   // barrier terms and reduction
   const int64_t n3 = 3 * (int64_t)sc->n_node;
   if (energy) EIPC_TRY(launch_zero(c, energy, sizeof(double) * n_scene_of(sc), s));
@@ -606,22 +629,12 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
   if (want_h) EIPC_TRY(hess_table(c, plan->hess_blocks, h, s));
   const uint32_t f = flags & (want_h ? ~0u : ~(uint32_t)EIPC_HESS);
   if (energy || g || want_h) {
-    EIPC_TRY(launch_barrier(c, sc, 0, xs, pt, act_pt, typ_pt, cn + 2, plan->cand_pt, dhat, kappa, f, energy, g, h, s));
-    EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, cn + 3, plan->cand_ee, dhat, kappa, f, energy, g, h, s));
+    EIPC_TRY(launch_barrier(c, sc, 0, xs, pt, act_pt, typ_pt, cn + 2, plan->act_pt, dhat, kappa, f, energy, g, h, s));
+    EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, cn + 3, plan->act_ee, dhat, kappa, f, energy, g, h, s));
   }
   if (want_h) EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s, plan->nnzb));
-  // step bound over swept candidates
+  // step bound over the swept candidates
   if (alpha) {
-    double *ps, *x1s;
-    EIPC_TRY(ensure_t(c, B_P, (size_t)n3v + 1, &ps));
-    EIPC_TRY(ensure_t(c, B_X1, (size_t)n3v + 1, &x1s));
-    EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
-    EIPC_TRY(launch_add_soa(c, n3v, xs, ps, x1s, s));
-    int32_t *cpt, *cee;
-    EIPC_TRY(ensure_t(c, B_CAND_PT, (size_t)2 * std::max<int64_t>(plan->swept_pt, 1), &cpt));
-    EIPC_TRY(ensure_t(c, B_CAND_EE, (size_t)2 * std::max<int64_t>(plan->swept_ee, 1), &cee));
-    EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, cpt, plan->swept_pt, nullptr, 0, s, -1, nullptr, &bp[2], cn + 7));
-    EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, cee, plan->swept_ee, nullptr, 0, s, -1, nullptr, &bp[3], cn + 8));
     uint64_t tb;
     std::memcpy(&tb, &t_max, 8);
     EIPC_TRY(fill_u64(c, (uint64_t *)alpha, n_scene_of(sc), tb, s));
@@ -660,13 +673,21 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
   p.cand_pt = grow(npt);
   p.cand_ee = grow(nee);
   for (int k = 0; k < 2; ++k) p.ent[k] = grow(c->last_plan[k].ent_cap);
-  if (with_hess && sc->n_node > 0) {
+  {
     eipc_bsr tmp;
-    EIPC_TRY(eipc_barrier_reduce(c, sc, q, pt, npt, ee, nee, dhat, 1.0, EIPC_HESS, nullptr, nullptr, nullptr, &tmp,
-                                 nullptr, stream));
-    // keys (upper blocks) <= nnzb; table at most half full
-    p.nnzb = grow(tmp.nnzb);
-    p.hess_blocks = pow2_at_least(2 * p.nnzb);
+    int64_t n_act = 0;
+    const bool h = with_hess && sc->n_node > 0;
+    EIPC_TRY(eipc_barrier_reduce(c, sc, q, pt, npt, ee, nee, dhat, 1.0, h ? EIPC_HESS : 0, nullptr, nullptr, nullptr,
+                                 h ? &tmp : nullptr, &n_act, stream));
+    int64_t na[2];
+    EIPC_HIP(c, hipMemcpy(na, c->counters + 2, 16, hipMemcpyDeviceToHost));
+    p.act_pt = grow(na[0]);
+    p.act_ee = grow(na[1]);
+    if (h) {
+      // keys (upper blocks) <= nnzb; table at most half full
+      p.nnzb = grow(tmp.nnzb);
+      p.hess_blocks = pow2_at_least(2 * p.nnzb);
+    }
   }
   if (dq) {
     double *ps, *x1s;
@@ -689,7 +710,8 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
     const eipc_status st0 = read_status(c, s);
     if (st0 != EIPC_OK && st0 != EIPC_WARN_CCD_CAPPED) return st0;
   }
-  // reserve: one planned step at these sizes performs every allocation
+  // reserve: planned steps at these sizes (with and without the step
+  // bound) perform every allocation
   double *e1, *g1, *a1;
   int64_t *cnt;
   const int nsc = n_scene_of(sc);
@@ -700,7 +722,10 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
   eipc_bsr hb;
   const uint32_t fl = EIPC_ENERGY | EIPC_GRAD | (p.hess_blocks ? (EIPC_HESS | EIPC_PROJECT) : 0);
   EIPC_TRY(eipc_contact_step(c, sc, &p, q, dq, dx_off, dhat, 1.0, fl, 0.5, 1.0, 1, e1, g1,
-                             p.hess_blocks ? &hb : nullptr, dq ? a1 : nullptr, cnt, stream));
+                             p.hess_blocks ? &hb : nullptr, nullptr, cnt, stream));
+  if (dq)
+    EIPC_TRY(eipc_contact_step(c, sc, &p, q, dq, dx_off, dhat, 1.0, fl, 0.5, 1.0, 1, e1, g1,
+                               p.hess_blocks ? &hb : nullptr, a1, cnt, stream));
   eipc_status st = read_status(c, s);
   if (st != EIPC_OK && st != EIPC_WARN_CCD_CAPPED) return st;
   *plan = p;

@@ -147,10 +147,13 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
                         double dhat, int32_t *out, int64_t cap, int64_t *n_out, int sort, hipStream_t s,
                         int grow_id = -1, int32_t **grown = nullptr, const BPPlan *plan = nullptr,
                         int64_t *d_total = nullptr);
-// Active subset of `n` pairs (at most `n`; min(n, *d_n) when d_n is given).
+// Active subset of `n` pairs (at most `n`; min(n, *d_n) when d_n is given)
+// into act/typ of capacity act_cap (< 0: n).  With cand_count, the pairs
+// are swept candidates filtered by the candidate predicate at xs first and
+// the number passing is added to *cand_count.
 eipc_status launch_narrow(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                           int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s,
-                          const int64_t *d_n = nullptr);
+                          const int64_t *d_n = nullptr, int64_t act_cap = -1, int64_t *cand_count = nullptr);
 inline int n_scene_of(const eipc_scene *sc) { return sc->n_scene > 1 ? sc->n_scene : 1; }
 inline const int32_t *vscene_of(const eipc_scene *sc) { return sc->n_scene > 1 ? sc->vert_scene : nullptr; }
 

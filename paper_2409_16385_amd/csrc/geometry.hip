@@ -868,13 +868,49 @@ __device__ __forceinline__ void pair_vids(const int32_t *pairs, int64_t k, const
   }
 }
 
+// The candidate predicate on the pair's own vertices: the box of the
+// query primitive (PT: the vertex, EE: the first edge) against the box of
+// the item (the face, the second edge), each spanning its vertices widened
+// by h on every side, closed intervals -- the same arithmetic as the broad
+// phase's boxes.
 template <int KIND>
+__device__ __forceinline__ bool static_boxes_overlap(const V3 *x, double h) {
+#pragma clang fp contract(off)
+  const int nq = KIND == 0 ? 1 : 2;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double qmn = INFINITY, qmx = -INFINITY, imn = INFINITY, imx = -INFINITY;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double v = c == 0 ? x[a].x : (c == 1 ? x[a].y : x[a].z);
+      if (a < nq) {
+        qmn = fmin(qmn, v);
+        qmx = fmax(qmx, v);
+      } else {
+        imn = fmin(imn, v);
+        imx = fmax(imx, v);
+      }
+    }
+    ok = ok && (qmn - h <= imx + h) && (imn - h <= qmx + h);
+  }
+  return ok;
+}
+
+// Narrow phase: distance type and d^2 per pair, active iff 0 < d^2 <
+// dhat^2, wavefront-ballot compaction into act/typ (capacity act_cap).
+// FILTER: the pairs are swept candidates; only those that pass the
+// candidate predicate at the start positions are considered, and their
+// number is added to *cand_count.
+template <int KIND, bool FILTER>
 __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
                          const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
-                         const double *__restrict__ xs, int n_vert, double dhat2, int32_t *__restrict__ act,
-                         int32_t *__restrict__ typ, int64_t *count, uint32_t *status) {
+                         const double *__restrict__ xs, int n_vert, double dhat2, double h,
+                         int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t act_cap, int64_t *count,
+                         int64_t *cand_count, uint32_t *status) {
   const int64_t n = d_n ? (*d_n < cap ? *d_n : cap) : cap;
   const int lane = threadIdx.x & 63;
+  int64_t n_cand = 0;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = base + threadIdx.x;
     bool active = false;
@@ -885,14 +921,18 @@ __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restr
       V3 x[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) x[a] = V3{xs[vid[a]], xs[n_vert + vid[a]], xs[2 * (int64_t)n_vert + vid[a]]};
-      double s2 = pair_dist2<KIND>(x, &ty);
-      if (!isfinite(s2)) {
-        atomicOr(status, ST_NONFINITE);
-      } else if (s2 < dhat2) {
-        if (s2 <= 0.0)
-          atomicOr(status, ST_INTERSECTING);
-        else
-          active = true;
+      const bool cand = !FILTER || static_boxes_overlap<KIND>(x, h);
+      if (cand) {
+        ++n_cand;
+        double s2 = pair_dist2<KIND>(x, &ty);
+        if (!isfinite(s2)) {
+          atomicOr(status, ST_NONFINITE);
+        } else if (s2 < dhat2) {
+          if (s2 <= 0.0)
+            atomicOr(status, ST_INTERSECTING);
+          else
+            active = true;
+        }
       }
     }
     const uint64_t mask = __ballot(active);
@@ -901,25 +941,45 @@ __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restr
     pos0 = __shfl(pos0, 0, 64);
     if (active) {
       const int64_t pos = pos0 + __popcll(mask & ((1ull << lane) - 1ull));
-      act[pos] = (int32_t)i;
-      typ[pos] = ty;
+      if (pos < act_cap) {
+        act[pos] = (int32_t)i;
+        typ[pos] = ty;
+      } else {
+        atomicOr(status, ST_PLAN_OVERFLOW);
+      }
     }
+  }
+  if (FILTER) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n_cand += __shfl_xor(n_cand, o, 64);
+    if (lane == 0 && n_cand) atomicAdd((unsigned long long *)cand_count, (unsigned long long)n_cand);
   }
 }
 
 eipc_status launch_narrow(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                           int64_t n, double dhat, int32_t *act, int32_t *typ, int64_t *d_count, hipStream_t s,
-                          const int64_t *d_n) {
+                          const int64_t *d_n, int64_t act_cap, int64_t *cand_count) {
   if (n == 0) return EIPC_OK;
   const double d2 = dhat * dhat;
+  const double h = 0.5 * dhat;
+  if (act_cap < 0) act_cap = n;
   const int blocks = (int)std::min<int64_t>(grid_for(n, 256), (int64_t)c->wg_per_cu[2] * c->num_cu);
   ProfScope ps(c, kind == 0 ? K_NARROW_PT : K_NARROW_EE, s);
-  if (kind == 0)
-    k_narrow<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ, d_count,
-                                        c->status);
-  else
-    k_narrow<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, act, typ, d_count,
-                                        c->status);
+  if (cand_count) {
+    if (kind == 0)
+      k_narrow<0, true><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, h, act, typ,
+                                               act_cap, d_count, cand_count, c->status);
+    else
+      k_narrow<1, true><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, h, act, typ,
+                                               act_cap, d_count, cand_count, c->status);
+  } else {
+    if (kind == 0)
+      k_narrow<0, false><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, h, act,
+                                                typ, act_cap, d_count, nullptr, c->status);
+    else
+      k_narrow<1, false><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, sc->n_vert, d2, h, act,
+                                                typ, act_cap, d_count, nullptr, c->status);
+  }
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }

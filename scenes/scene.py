@@ -389,7 +389,8 @@ class Blob:
         d = p / np.maximum(r, 1e-300)[..., None]
         return r < self.radius(d.reshape(-1, 3)).reshape(r.shape)
 
-    def first_hit(self, origin: np.ndarray, direction: np.ndarray, t_hi: float, n_march: int = 96):
+    def first_hit(self, origin: np.ndarray, direction: np.ndarray, t_hi: float, n_march: int = 96,
+                  n_bisect: int = 60):
         """Smallest t in [0, t_hi] where origin + t dir enters the body:
         a march over all rays at once, then a joint bisection on the first
         bracketing interval (nan where a ray misses)."""
@@ -404,7 +405,7 @@ class Blob:
         hit &= first > 0
         lo = np.where(hit, ts[np.maximum(first - 1, 0)], 0.0)
         hi = np.where(hit, ts[first], 0.0)
-        for _ in range(60):
+        for _ in range(n_bisect):
             mid = 0.5 * (lo + hi)
             pm = origin + mid[:, None] * direction
             ins_m = self.inside(pm)
@@ -413,14 +414,31 @@ class Blob:
         return np.where(hit, lo, np.nan)
 
 
+# barycentric sample points of a triangle (centroid, edge midpoints, inner points)
+_FACE_SAMPLES = np.array([[1 / 3, 1 / 3, 1 / 3], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5],
+                          [2 / 3, 1 / 6, 1 / 6], [1 / 6, 2 / 3, 1 / 6], [1 / 6, 1 / 6, 2 / 3]])
+
+
+def mesh_bulge(blob: Blob, v: np.ndarray, f: np.ndarray) -> float:
+    """Largest radial distance by which the flat faces of the object mesh
+    stand outside the smooth surface (where the surface is concave)."""
+    P = np.einsum("sk,fkc->fsc", _FACE_SAMPLES, v[f]).reshape(-1, 3)
+    r = np.linalg.norm(P, axis=1)
+    return max(0.0, float((r - blob.radius(P / r[:, None])).max()))
+
+
 def _conformed_finger(blob: Blob, obj_v: np.ndarray, nu: int, semi, side: float,
-                      frac: float, dhat: float, rng) -> np.ndarray:
+                      frac: float, dhat: float, rng, clearance: float = 0.0) -> np.ndarray:
     """Ellipsoidal membrane (semi-axes semi = (a_x, a_y, a_z), x the grasp
     axis) on the ``side`` (-1 or +1) of the object along x.  Vertices on the
     object-facing half whose (y, z) lie within ``frac`` of the semi-axes are
     pressed onto the object: moved along x to the object's first-hit surface
-    minus a gap dhat U(0.1, 0.9).  Returns the conformed vertex positions."""
-    v_unit, _ = geodesic_sphere(nu)
+    minus a gap dhat U(0.1, 0.9).  Then, so that the flat finger faces do
+    not dip into the object, sample points of every facing face must keep
+    ``clearance`` above the smooth surface along x: faces short of it push
+    their vertices out (repeated until none is).  Returns the conformed
+    vertex positions."""
+    v_unit, ff = geodesic_sphere(nu)
     v = v_unit * np.asarray(semi)
     facing = (v[:, 0] * -side) > 0  # half pointing at the object
     ell = (v[:, 1] / semi[1]) ** 2 + (v[:, 2] / semi[2]) ** 2
@@ -450,6 +468,30 @@ def _conformed_finger(blob: Blob, obj_v: np.ndarray, nu: int, semi, side: float,
         cur = v[rest[hit], 0]
         bad = (cur - lim) * side < 0
         v[rest[hit][bad], 0] = lim[bad]
+    # keep the flat faces outside the object (chords of the conformed
+    # surface sag toward it)
+    # faces with a pressed vertex (the others stay >= 2 dhat away)
+    fsel = ff[np.isin(ff, idx).any(axis=1)]
+    need = clearance + 0.05 * dhat
+    for _ in range(6):
+        if len(fsel) == 0:
+            break
+        P = np.einsum("sk,fkc->fsc", _FACE_SAMPLES, v[fsel])
+        # short rays through each sample point: from 2 mm outside, 6 mm long
+        o = P.reshape(-1, 3).copy()
+        o[:, 0] += side * 2e-3
+        t = blob.first_hit(o, direction, 6e-3, n_march=25, n_bisect=34)
+        surf = o[:, 0] - side * t
+        clear = ((P.reshape(-1, 3)[:, 0] - surf) * side).reshape(len(fsel), -1)
+        short = np.nan_to_num(need - clear, nan=-1.0).max(axis=1)
+        if short.max() <= 0.0:
+            break
+        push = np.zeros(len(v))
+        for k in range(3):
+            np.maximum.at(push, fsel[:, k], np.maximum(short, 0.0) * 1.05)
+        v[:, 0] += side * push
+        # only faces touching a moved vertex can have changed
+        fsel = ff[(push[ff] > 0).any(axis=1)]
     return v
 
 
@@ -462,8 +504,9 @@ def grasp_scene(seed: int, obj_nu: int, obj_nodes: int, finger_nu: int,
     blob = Blob(rng, r0=r0)
     v_unit, of = geodesic_sphere(obj_nu)
     ov = v_unit * blob.radius(v_unit)[:, None]
-    f1 = _conformed_finger(blob, ov, finger_nu, finger_semi, -1.0, frac, dhat, rng)
-    f2 = _conformed_finger(blob, ov, finger_nu, finger_semi, +1.0, frac, dhat, rng)
+    clr = 2.0 * mesh_bulge(blob, ov, of)
+    f1 = _conformed_finger(blob, ov, finger_nu, finger_semi, -1.0, frac, dhat, rng, clr)
+    f2 = _conformed_finger(blob, ov, finger_nu, finger_semi, +1.0, frac, dhat, rng, clr)
     _, ff = geodesic_sphere(finger_nu)
     if rotate:
         R = _random_rotation(rng)
