@@ -293,6 +293,7 @@ def main():
         tuning = bt.autotune(reps=2)
         log(f"autotune: cell_scale={tuning['cell_scale']} wg_per_cu={tuning['wg_per_cu']} "
             f"({time.perf_counter() - t1:.1f} s)")
+        log("autotune trace (what, value, ms): " + " ".join(f"{w}={v}:{t:.3f}" for w, v, t in tuning["trace"]))
     else:
         bt.make_plan(1.5)
     plan = bt.plan.as_dict()
@@ -346,13 +347,13 @@ def main():
     # per-kernel event profile of eager planned steps (same kernels)
     prof = {}
     if not a.no_profile:
-        ctx.profile(True)
-        ctx.profile_read(reset=True)
+        bt.ctx.profile(True)
+        bt.ctx.profile_read(reset=True)
         n_prof = max(3, min(a.steps, 10))
         for _ in range(n_prof):
             bt.step()
-        prof = ctx.profile_read(reset=True)
-        ctx.profile(False)
+        prof = bt.ctx.profile_read(reset=True)
+        bt.ctx.profile(False)
         for k, (ms, n) in prof.items():
             if n:
                 log(f"kernel {k:16s} {ms / n * 1e3:10.1f} us/launch x {n}")

@@ -474,6 +474,76 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Locality order of the active pairs: a counting sort by the first coarse
+// node of the pair's first vertex with a DoF, so that a workgroup's range
+// of pairs touches few distinct node blocks (its LDS tables then absorb
+// most of the accumulation).
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ void k_pair_keys(const int32_t *__restrict__ pairs, const int32_t *__restrict__ act,
+                            const int64_t *__restrict__ d_count, int64_t cap, const int32_t *__restrict__ faces,
+                            const int32_t *__restrict__ edges, const int32_t *__restrict__ rowptr,
+                            const int32_t *__restrict__ col, int n_node, int32_t *__restrict__ key, int32_t *hist) {
+  const int64_t n = *d_count < cap ? *d_count : cap;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int vid[4];
+    pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
+    int k = -1;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r0 = rowptr[vid[a]];
+      if (k < 0 && rowptr[vid[a] + 1] > r0) k = col[r0];
+    }
+    if ((unsigned)k >= (unsigned)n_node) k = 0;
+    key[i] = k;
+    atomicAdd(&hist[k], 1);
+  }
+}
+
+__global__ void k_pair_scatter(const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
+                               const int64_t *__restrict__ d_count, int64_t cap, const int32_t *__restrict__ key,
+                               const int64_t *__restrict__ start, int32_t *fill, int32_t *__restrict__ act2,
+                               int32_t *__restrict__ typ2) {
+  const int64_t n = *d_count < cap ? *d_count : cap;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = key[i];
+    const int64_t pos = start[k] + atomicAdd(&fill[k], 1);
+    act2[pos] = act[i];
+    typ2[pos] = typ[i];
+  }
+}
+
+static eipc_status sort_active(eipc_ctx *c, const eipc_scene *sc, int kind, const int32_t *pairs, const int32_t *act,
+                               const int32_t *typ, const int64_t *d_count, int64_t cap, const int32_t **act2,
+                               const int32_t **typ2, hipStream_t s) {
+  const int nn = std::max(sc->n_node, 1);
+  int32_t *key, *hist, *fill, *a2, *t2;
+  int64_t *start;
+  EIPC_TRY(ensure_t(c, B_SKEY, (size_t)cap, &key));
+  EIPC_TRY(ensure_t(c, B_SHIST, (size_t)nn + 1, &hist));
+  EIPC_TRY(ensure_t(c, B_SFILL, (size_t)nn + 1, &fill));
+  EIPC_TRY(ensure_t(c, B_SSTART, (size_t)nn + 1, &start));
+  EIPC_TRY(ensure_t(c, B_SACT, (size_t)cap, &a2));
+  EIPC_TRY(ensure_t(c, B_STYP, (size_t)cap, &t2));
+  EIPC_TRY(launch_zero(c, hist, sizeof(int32_t) * (nn + 1), s));
+  EIPC_TRY(launch_zero(c, fill, sizeof(int32_t) * (nn + 1), s));
+  const int blocks = (int)std::min<int64_t>(grid_for(cap, 256), 8 * (int64_t)c->num_cu);
+  if (kind == 0)
+    k_pair_keys<0><<<blocks, 256, 0, s>>>(pairs, act, d_count, cap, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                          nn, key, hist);
+  else
+    k_pair_keys<1><<<blocks, 256, 0, s>>>(pairs, act, d_count, cap, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                          nn, key, hist);
+  EIPC_HIP(c, hipGetLastError());
+  EIPC_TRY(exclusive_scan(c, hist, nn, start, s));
+  k_pair_scatter<<<blocks, 256, 0, s>>>(act, typ, d_count, cap, key, start, fill, a2, t2);
+  EIPC_HIP(c, hipGetLastError());
+  *act2 = a2;
+  *typ2 = t2;
+  return EIPC_OK;
+}
+
 eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                            const int32_t *act, const int32_t *typ, const int64_t *d_count, int64_t max_count,
                            double dhat, double kappa, uint32_t flags, double *energy, double *grad,
@@ -485,6 +555,7 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
   const int64_t cap = max_count;
   if (want_g) EIPC_TRY(ensure_t(c, kind == 0 ? B_PG_PT : B_PG_EE, (size_t)9 * cap, &gq));
   if (want_h) EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)45 * cap, &Xq));
+  if (want_g || want_h) EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, cap, &act, &typ, s));
   {
     int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), (int64_t)c->wg_per_cu[0] * c->num_cu);
     ProfScope ps(c, kind == 0 ? K_BARRIER_PT : K_BARRIER_EE, s);
@@ -567,8 +638,10 @@ __global__ void k_hash_rowfill(int64_t cap, const int64_t *hkey, int n_node, con
   }
 }
 
-// Sort each BSR row by column: one wavefront per row; rows of at most 64
-// blocks by rank (columns of a row are distinct), longer rows by insertion.
+// Sort each BSR row by column: one wavefront per row, by rank (columns of
+// a row are distinct); rows longer than 64 x ROW_PER_LANE blocks by
+// insertion.
+constexpr int ROW_PER_LANE = 16;
 // Rows that end beyond the capacity are left alone (overflow is raised).
 __global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int64_t *bsrc, int32_t *rowptr32,
                            int64_t nnzb_cap, uint32_t *status) {
@@ -597,6 +670,31 @@ __global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int
       bcol[b + rank] = cv;
       bsrc[b + rank] = sv;
     }
+  } else if (len <= 64 * ROW_PER_LANE) {
+    // rank sort: each lane ranks up to ROW_PER_LANE entries against the
+    // whole row (broadcast reads), then scatters them; every read of the
+    // row happens before the first write in the wavefront's stream
+    int32_t cv[ROW_PER_LANE];
+    int64_t sv[ROW_PER_LANE];
+    int rk[ROW_PER_LANE];
+#pragma unroll
+    for (int u = 0; u < ROW_PER_LANE; ++u) {
+      const int64_t idx = lane + 64 * u;
+      cv[u] = idx < len ? bcol[b + idx] : 0x7fffffff;
+      sv[u] = idx < len ? bsrc[b + idx] : 0;
+      rk[u] = 0;
+    }
+    for (int64_t j = 0; j < len; ++j) {
+      const int32_t cj = bcol[b + j];
+#pragma unroll
+      for (int u = 0; u < ROW_PER_LANE; ++u) rk[u] += cj < cv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < ROW_PER_LANE; ++u)
+      if (lane + 64 * u < len) {
+        bcol[b + rk[u]] = cv[u];
+        bsrc[b + rk[u]] = sv[u];
+      }
   } else if (lane == 0) {
     for (int64_t i = b + 1; i < e; ++i) {
       const int32_t cv = bcol[i];
@@ -817,6 +915,7 @@ eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double
                        int64_t max_count, double dhat, double kappa, uint32_t flags, double *out,
                        double *out_off, hipStream_t s) {
   if (max_count == 0) return EIPC_OK;
+  EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, max_count, &act, &typ, s));
   int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 4 * (int64_t)c->num_cu);
   ProfScope ps(c, kind == 0 ? K_HVP_PT : K_HVP_EE, s);
   if (kind == 0)

@@ -452,11 +452,22 @@ __global__ void k_item_hist(int n, const ItemRec *__restrict__ rec, const GridDe
       for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&bcnt[cell_hash(x, y, z, sc) & bmask], 1);
 }
 
+// Hash entry: the item's box rounded outward to float, so that most
+// non-overlapping items are rejected without reading their record.
 struct Entry {
   uint64_t cell;
   int32_t item;
   int32_t dlo;  // cell minus the item's lower cell, 6 bits per axis
+  float lo[3], hi[3];
 };
+
+__device__ __forceinline__ void box_f32(const double *lo, const double *hi, float *flo, float *fhi) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    flo[a] = __double2float_rd(lo[a]);
+    fhi[a] = __double2float_ru(hi[a]);
+  }
+}
 
 __global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, uint32_t bmask,
                             const int32_t *cnt, const int64_t *bstart, int32_t *bfill, Entry *ent, int64_t ent_cap,
@@ -472,9 +483,14 @@ __global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, const GridDe
       for (int x = c0[0]; x <= c1[0]; ++x) {
         uint32_t b = cell_hash(x, y, z, sc) & bmask;
         int64_t slot = bstart[b] + atomicAdd(&bfill[b], 1);
-        if (slot < ent_cap)
-          ent[slot] = Entry{cell_key(x, y, z, sc), i, (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12)};
-        else
+        if (slot < ent_cap) {
+          Entry en;
+          en.cell = cell_key(x, y, z, sc);
+          en.item = i;
+          en.dlo = (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12);
+          box_f32(rec[i].lo, rec[i].hi, en.lo, en.hi);
+          ent[slot] = en;
+        } else
           atomicOr(status, ST_PLAN_OVERFLOW);
       }
 }
@@ -498,7 +514,7 @@ __device__ __forceinline__ bool pair_ok(int q, int qa, int qb, bool qdof, int it
 }
 
 constexpr int QT = 128;         // query threads per block
-constexpr int APPEND_BUF = 16;  // per-thread LDS staging for append mode
+constexpr int APPEND_BUF = 8;   // per-thread LDS staging for append mode
 
 // append mode: stage a candidate in the thread's LDS slots; flush a full
 // buffer with one atomic
@@ -567,6 +583,8 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
   }
   int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
   if (live) cell_range(g, qlo, qhi, c0, c1);
+  float fqlo[3], fqhi[3];
+  box_f32(qlo, qhi, fqlo, fqhi);
   const int64_t base = (MODE == 1 && live) ? off[q] : 0;
   int64_t k = 0;
   for (int z = c0[2]; z <= c1[2]; ++z)
@@ -588,6 +606,10 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
                               (iz > c0[2] ? iz : c0[2]) == z;
             if (!home) continue;
           }
+          // conservative float test first (no false rejections)
+          if (!(fqlo[0] <= en.hi[0] && en.lo[0] <= fqhi[0] && fqlo[1] <= en.hi[1] && en.lo[1] <= fqhi[1] &&
+                fqlo[2] <= en.hi[2] && en.lo[2] <= fqhi[2]))
+            continue;
           const ItemRec r = items[it];
           if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
           if (!overlap(qlo, qhi, r)) continue;

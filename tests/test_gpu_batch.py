@@ -158,14 +158,14 @@ def test_plan_overflow_is_reported(batch):
     """A plan with too few candidate slots reports a capacity error (the
     kernels stay within the planned buffers) and the next good step is
     clean."""
-    small = E.Plan.from_buffer_copy(batch.plan)
-    small.cand_pt = 16
-    small.cand_ee = 16
-    E.contact_step(batch.ctx, batch.scene, small, batch.q, batch.hb.dhat, batch.hb.kappa, batch.out, batch.dq,
-                   None, BT.DEFAULT_FLAGS)
-    assert batch.status() == E.binding.ERR_CAPACITY
-    batch.step()
-    assert batch.status() == E.binding.OK
+    for field in ("swept_pt", "swept_ee", "act_pt", "act_ee", "nnzb"):
+        small = E.Plan.from_buffer_copy(batch.plan)
+        setattr(small, field, 16)
+        E.contact_step(batch.ctx, batch.scene, small, batch.q, batch.hb.dhat, batch.hb.kappa, batch.out, batch.dq,
+                       None, BT.DEFAULT_FLAGS)
+        assert batch.status() == E.binding.ERR_CAPACITY, field
+        batch.step()
+        assert batch.status() == E.binding.OK
 
 
 def test_autotune_keeps_results(ctx, scenes, seq):
