@@ -61,7 +61,8 @@ def _args():
     ap.add_argument("--no-graph", action="store_true", help="time eager planned steps instead of graph replays")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", default=None,
-                    help="fixed tuning 'cell_scale,wg_terms,wg_expand,wg_narrow,wg_ccd' (skips the autotuner)")
+                    help="fixed tuning 'cell_scale,wg_terms,wg_expand,wg_narrow,wg_ccd,query_cells' "
+                         "(skips the autotuner)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -285,8 +286,9 @@ def main():
     tuning = None
     if a.tuning:
         v = [float(t) for t in a.tuning.split(",")]
-        tuning = {"cell_scale": v[0], "wg_per_cu": [int(t) for t in v[1:5]]}
-        E.set_tuning(ctx, tuning["cell_scale"], tuning["wg_per_cu"])
+        tuning = {"cell_scale": v[0], "wg_per_cu": [int(t) for t in v[1:5]],
+                  "query_cells": int(v[5]) if len(v) > 5 else -1}
+        E.set_tuning(bt.ctx, tuning["cell_scale"], tuning["wg_per_cu"], tuning["query_cells"])
         bt.make_plan(1.5)
     elif not a.no_autotune:
         t1 = time.perf_counter()
@@ -405,7 +407,8 @@ def main():
     out["timed"] = "graph replay of the planned step" if use_graph else "eager planned step"
     out["alpha_min"] = float(bt.out.alpha.min().item())
     out["tuning"] = None if tuning is None else {"cell_scale": tuning["cell_scale"],
-                                                 "wg_per_cu": tuning["wg_per_cu"]}
+                                                 "wg_per_cu": tuning["wg_per_cu"],
+                                                 "query_cells": tuning.get("query_cells", -1)}
     out["roofline"] = roofline
     out["cpu_baseline"] = None
     if not a.no_cpu_baseline:

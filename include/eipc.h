@@ -188,7 +188,8 @@ typedef struct {
   int64_t cand_pt, cand_ee;   /* proximity candidates (only used when the step bound is not asked for) */
   int64_t swept_pt, swept_ee; /* swept candidates for the step bound */
   int64_t act_pt, act_ee;     /* active pairs */
-  int64_t ent[4];             /* broad-phase hash entries: PT, EE, swept PT, swept EE */
+  int64_t ent[4];             /* broad-phase item cell entries: PT, EE, swept PT, swept EE */
+  int64_t qent[4];            /* broad-phase query cell entries, same order */
   int64_t buckets[4];         /* broad-phase hash buckets (powers of 2) */
   int64_t hess_blocks;        /* reduced-Hessian block table (power of 2); 0: no Hessian */
   int64_t nnzb;               /* BSR blocks */
@@ -231,12 +232,17 @@ eipc_status eipc_contact_step(eipc_ctx *ctx, const eipc_scene *sc, const eipc_pl
                               eipc_bsr *hess_bsr, double *alpha, int64_t *counts, eipc_stream stream);
 
 /* Launch shape of the library's kernels for this context: the broad-phase
- * cell edge as a multiple of the mean primitive box extent (> 0), and the
+ * cell edge as a multiple of the mean primitive box extent (> 0); the
  * workgroups per compute unit of the grid-stride kernels (pair terms,
- * expansion, narrow phase, CCD; each 1..64, 0 keeps the current value).
- * Used by the batch autotuner; results do not depend on them except for
- * the rounding order of sums. */
-eipc_status eipc_set_tuning(eipc_ctx *ctx, double cell_scale, const int32_t wg_per_cu[4]);
+ * expansion, narrow phase, CCD; each 1..64, 0 keeps the current value; the
+ * array may be NULL); and how the unsorted (planned-step and step-bound)
+ * broad phases split their work: bit 0 for PT, bit 1 for EE, set = one
+ * thread per (query, cell of its box), clear = one thread per query
+ * (-1 keeps the current choice; default 1).  Used by the batch autotuner;
+ * results do not depend on them except for the order of unsorted
+ * candidate lists and the rounding order of sums.  A plan must be made
+ * again after changing them. */
+eipc_status eipc_set_tuning(eipc_ctx *ctx, double cell_scale, const int32_t wg_per_cu[4], int32_t query_cells);
 
 /* ---- dense reduced Newton system (adjoint of a converged step) ---- */
 

@@ -118,7 +118,7 @@ class Batch:
         self.plan: B.Plan | None = None
         self.out: B.StepOut | None = None
         self.graph: torch.cuda.CUDAGraph | None = None
-        self.tuning = {"cell_scale": 2.0, "wg_per_cu": [8, 2, 4, 4]}
+        self.tuning = {"cell_scale": 2.0, "wg_per_cu": [8, 2, 4, 4], "query_cells": 1}
 
     # -- planning ---------------------------------------------------------
     def make_plan(self, margin: float = 1.5):
@@ -196,31 +196,33 @@ class Batch:
         ev1.synchronize()
         return ev0.elapsed_time(ev1) / reps
 
-    def autotune(self, cell_scales=(1.0, 1.5, 2.0, 3.0, 4.0), wg_values=(1, 2, 4, 8, 16), reps: int = 3,
-                 margin: float = 1.5, verbose: bool = False) -> dict:
-        """Pick the broad-phase cell scale (whole-step time, re-planning for
-        each value), then for each grid-stride kernel family the workgroups
-        per CU with the smallest kernel time (per-kernel event timing)."""
+    def autotune(self, cell_scales=(1.5, 2.0, 3.0, 4.0), query_modes=(0, 1, 2, 3), wg_values=(1, 2, 4, 8, 16),
+                 reps: int = 3, margin: float = 1.5, verbose: bool = False) -> dict:
+        """Pick the broad-phase cell scale and work split per query kind
+        (whole-step time, re-planning for each pair of values), then for
+        each grid-stride kernel family the workgroups per CU with the
+        smallest kernel time (per-kernel event timing)."""
         wg = list(self.tuning["wg_per_cu"])
         best = None
         trace = []
         for cs in cell_scales:
-            B.set_tuning(self.ctx, cs, wg)
-            self.make_plan(margin)
-            ms = self._time_steps(reps)
-            if self.status() not in (B.OK, B.WARN_CCD_CAPPED):
-                continue
-            trace.append(("cell_scale", cs, ms))
-            if best is None or ms < best[1]:
-                best = (cs, ms)
-        cs = best[0]
-        B.set_tuning(self.ctx, cs, wg)
+            for qm in query_modes:
+                B.set_tuning(self.ctx, cs, wg, qm)
+                self.make_plan(margin)
+                ms = self._time_steps(reps)
+                if self.status() not in (B.OK, B.WARN_CCD_CAPPED):
+                    continue
+                trace.append((f"cell_scale/query_cells {qm}", cs, ms))
+                if best is None or ms < best[2]:
+                    best = (cs, qm, ms)
+        cs, qm = best[0], best[1]
+        B.set_tuning(self.ctx, cs, wg, qm)
         self.make_plan(margin)
         families = (("barrier_pt", "barrier_ee"), ("expand_pt", "expand_ee"), ("narrow_pt", "narrow_ee"),
                     ("ccd_pt", "ccd_ee"))
         kbest = [None] * 4
         for v in wg_values:
-            B.set_tuning(self.ctx, cs, [v] * 4)
+            B.set_tuning(self.ctx, cs, [v] * 4, qm)
             self.step()
             torch.cuda.synchronize(self.ctx.torch_device)
             self.ctx.profile(True)
@@ -235,8 +237,8 @@ class Batch:
                 if kbest[k] is None or t < kbest[k][1]:
                     kbest[k] = (v, t)
         wg = [kb[0] for kb in kbest]
-        B.set_tuning(self.ctx, cs, wg)
-        self.tuning = {"cell_scale": cs, "wg_per_cu": wg, "trace": trace}
+        B.set_tuning(self.ctx, cs, wg, qm)
+        self.tuning = {"cell_scale": cs, "wg_per_cu": wg, "query_cells": qm, "trace": trace}
         self.make_plan(margin)
         if verbose:
             print("autotune:", {k: v for k, v in self.tuning.items() if k != "trace"})

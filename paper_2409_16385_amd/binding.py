@@ -17,7 +17,7 @@ OK, ERR_ARG, ERR_CAPACITY, ERR_INTERSECTING, ERR_DEGENERATE, ERR_NONFINITE, ERR_
 WARN_CCD_CAPPED = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libeipc.so")
+_LIB_PATH = os.environ.get("EIPC_LIBRARY", os.path.join(_HERE, "libeipc.so"))
 _P, _D, _I32, _I64, _U32 = C.c_void_p, C.c_double, C.c_int32, C.c_int64, C.c_uint32
 
 
@@ -45,12 +45,13 @@ class Plan(C.Structure):
     """Capacities of a planned contact step (eipc_plan)."""
     _fields_ = [("cand_pt", _I64), ("cand_ee", _I64), ("swept_pt", _I64), ("swept_ee", _I64),
                 ("act_pt", _I64), ("act_ee", _I64),
-                ("ent", _I64 * 4), ("buckets", _I64 * 4), ("hess_blocks", _I64), ("nnzb", _I64)]
+                ("ent", _I64 * 4), ("qent", _I64 * 4), ("buckets", _I64 * 4), ("hess_blocks", _I64),
+                ("nnzb", _I64)]
 
     def as_dict(self) -> dict:
         return {"cand_pt": self.cand_pt, "cand_ee": self.cand_ee, "swept_pt": self.swept_pt,
                 "swept_ee": self.swept_ee, "act_pt": self.act_pt, "act_ee": self.act_ee,
-                "ent": list(self.ent), "buckets": list(self.buckets),
+                "ent": list(self.ent), "qent": list(self.qent), "buckets": list(self.buckets),
                 "hess_blocks": self.hess_blocks, "nnzb": self.nnzb}
 
 
@@ -88,7 +89,7 @@ def _load():
         "eipc_profile_read": (_I32, [_P, C.c_char_p, _P, _P, _I32]),
         "eipc_plan_step": (_I32, [_P, _P, _P, _P, _P, _D, _D, _I32, _P, _P]),
         "eipc_contact_step": (_I32, [_P, _P, _P, _P, _P, _P, _D, _D, _U32, _D, _D, _I64, _P, _P, _P, _P, _P, _P]),
-        "eipc_set_tuning": (_I32, [_P, _D, _P]),
+        "eipc_set_tuning": (_I32, [_P, _D, _P, _I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -439,11 +440,13 @@ def fp64_selftest(ctx: Context, a, b):
     return sq, dv
 
 
-def set_tuning(ctx: Context, cell_scale: float, wg_per_cu=(0, 0, 0, 0)):
-    """Broad-phase cell scale and workgroups per CU of the grid-stride
-    kernels (pair terms, expansion, narrow phase, CCD; 0 keeps a value)."""
+def set_tuning(ctx: Context, cell_scale: float, wg_per_cu=(0, 0, 0, 0), query_cells: int = -1):
+    """Broad-phase cell scale, workgroups per CU of the grid-stride kernels
+    (pair terms, expansion, narrow phase, CCD; 0 keeps a value) and the
+    unsorted broad phase's work split (bit 0 PT, bit 1 EE: per query cell;
+    -1 keeps it)."""
     w = (_I32 * 4)(*[int(v) for v in wg_per_cu])
-    ctx.check(_load().eipc_set_tuning(ctx.handle, float(cell_scale), w))
+    ctx.check(_load().eipc_set_tuning(ctx.handle, float(cell_scale), w, int(query_cells)))
 
 
 def plan_step(ctx: Context, sc: Scene, q, dhat: float, dq=None, dx_off=None, margin: float = 1.5,

@@ -513,8 +513,9 @@ eipc_status eipc_fp64_selftest(eipc_ctx *c, const double *a, const double *b, do
 }
 
 
-eipc_status eipc_set_tuning(eipc_ctx *c, double cell_scale, const int32_t wg_per_cu[4]) {
+eipc_status eipc_set_tuning(eipc_ctx *c, double cell_scale, const int32_t wg_per_cu[4], int32_t query_cells) {
   if (!c) return EIPC_ERR_ARG;
+  if (query_cells < -1 || query_cells > 3) return set_err(c, EIPC_ERR_ARG, "query_cells must be -1 or in [0, 3]");
   if (!(cell_scale > 0.0) || !std::isfinite(cell_scale)) return set_err(c, EIPC_ERR_ARG, "cell_scale must be > 0");
   if (wg_per_cu)
     for (int k = 0; k < 4; ++k)
@@ -523,6 +524,10 @@ eipc_status eipc_set_tuning(eipc_ctx *c, double cell_scale, const int32_t wg_per
   if (wg_per_cu)
     for (int k = 0; k < 4; ++k)
       if (wg_per_cu[k] > 0) c->wg_per_cu[k] = wg_per_cu[k];
+  if (query_cells >= 0) {
+    c->query_cells[0] = (query_cells & 1) != 0;
+    c->query_cells[1] = (query_cells & 2) != 0;
+  }
   return EIPC_OK;
 }
 
@@ -547,7 +552,7 @@ static eipc_status check_plan(eipc_ctx *c, const eipc_plan *p) {
     return set_err(c, EIPC_ERR_ARG, "negative plan capacity");
   for (int k = 0; k < 4; ++k) {
     const int64_t b = p->buckets[k];
-    if (b < 1 || (b & (b - 1)) || b > (1ll << 31) || p->ent[k] < 1)
+    if (b < 1 || (b & (b - 1)) || b > (1ll << 31) || p->ent[k] < 1 || p->qent[k] < 1)
       return set_err(c, EIPC_ERR_ARG, "plan buckets must be powers of 2 and entries >= 1");
   }
   if (p->hess_blocks & (p->hess_blocks - 1)) return set_err(c, EIPC_ERR_ARG, "plan hess_blocks must be a power of 2");
@@ -576,10 +581,10 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
   EIPC_HIP(c, hipSetDevice(c->device));
   const int64_t n3v = 3 * (int64_t)sc->n_vert;
   int64_t *cn = c->counters;  // [2,3] active, [5,6] candidates, [7,8] swept candidates
-  const BPPlan bp[4] = {{(uint32_t)plan->buckets[0], plan->ent[0], plan->cand_pt},
-                        {(uint32_t)plan->buckets[1], plan->ent[1], plan->cand_ee},
-                        {(uint32_t)plan->buckets[2], plan->ent[2], plan->swept_pt},
-                        {(uint32_t)plan->buckets[3], plan->ent[3], plan->swept_ee}};
+  const BPPlan bp[4] = {{(uint32_t)plan->buckets[0], plan->ent[0], plan->cand_pt, plan->qent[0]},
+                        {(uint32_t)plan->buckets[1], plan->ent[1], plan->cand_ee, plan->qent[1]},
+                        {(uint32_t)plan->buckets[2], plan->ent[2], plan->swept_pt, plan->qent[2]},
+                        {(uint32_t)plan->buckets[3], plan->ent[3], plan->swept_ee, plan->qent[3]}};
   double *xs;
   EIPC_TRY(ensure_t(c, B_X, (size_t)n3v + 1, &xs));
   EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
@@ -672,7 +677,10 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
   EIPC_TRY(broad_phase(c, sc, 1, xs, nullptr, dhat, nullptr, 0, &nee, 0, s, B_STEP_EE, &ee));
   p.cand_pt = grow(npt);
   p.cand_ee = grow(nee);
-  for (int k = 0; k < 2; ++k) p.ent[k] = grow(c->last_plan[k].ent_cap);
+  for (int k = 0; k < 2; ++k) {
+    p.ent[k] = grow(c->last_plan[k].ent_cap);
+    p.qent[k] = grow(c->last_plan[k].qent_cap);
+  }
   {
     eipc_bsr tmp;
     int64_t n_act = 0;
@@ -701,9 +709,13 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
     EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, nullptr, 0, &see, 0, s, B_CAND_EE, &cee));
     p.swept_pt = grow(spt);
     p.swept_ee = grow(see);
-    for (int k = 2; k < 4; ++k) p.ent[k] = grow(c->last_plan[k].ent_cap);
+    for (int k = 2; k < 4; ++k) {
+      p.ent[k] = grow(c->last_plan[k].ent_cap);
+      p.qent[k] = grow(c->last_plan[k].qent_cap);
+    }
   } else {
     p.ent[2] = p.ent[3] = 1;
+    p.qent[2] = p.qent[3] = 1;
   }
   for (int k = 0; k < 4; ++k) p.buckets[k] = std::max<int64_t>(pow2_at_least(2 * p.ent[k]), 1024);
   {

@@ -40,15 +40,16 @@ enum BufId {
   B_PLAN_OUT,                          // outputs of the reserving step of a plan
   B_SKEY, B_SHIST, B_SFILL, B_SSTART, B_SACT, B_STYP,  // locality sort of active pairs
   B_BP0,                               // broad-phase scratch: 4 slots (kind, swept) x BP_NBUF
-  B_NUM = B_BP0 + 4 * 11
+  B_NUM = B_BP0 + 4 * 13
 };
-constexpr int BP_NBUF = 11;
+constexpr int BP_NBUF = 13;
 
 // capacities of one broad phase in a planned (synchronization-free) call
 struct BPPlan {
-  uint32_t nb;       // hash buckets (power of 2)
-  int64_t ent_cap;   // hash entries
-  int64_t cand_cap;  // candidate pairs
+  uint32_t nb;        // hash buckets (power of 2)
+  int64_t ent_cap;    // item hash entries
+  int64_t cand_cap;   // candidate pairs
+  int64_t qent_cap;   // query cell entries (append mode)
 };
 
 struct DevBuf {
@@ -82,6 +83,7 @@ struct eipc_ctx {
   int num_cu = 256;
   double cell_scale = 2.0;       // broad-phase cell edge / mean item extent
   int wg_per_cu[4] = {8, 2, 4, 4};  // grid sizes: pair terms, expansion, narrow, CCD
+  bool query_cells[2] = {true, false};  // append-mode query per (query, cell) [PT, EE], else per query
   eipc::BPPlan last_plan[4] = {};   // sizes seen by the last unplanned broad phases
   bool prof = false;                        // record per-kernel events
   std::vector<eipc::ProfRec> prof_pending;  // recorded, not yet read

@@ -458,7 +458,6 @@ struct Entry {
   uint64_t cell;
   int32_t item;
   int32_t dlo;  // cell minus the item's lower cell, 6 bits per axis
-  float lo[3], hi[3];
 };
 
 __device__ __forceinline__ void box_f32(const double *lo, const double *hi, float *flo, float *fhi) {
@@ -488,7 +487,6 @@ __global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, const GridDe
           en.cell = cell_key(x, y, z, sc);
           en.item = i;
           en.dlo = (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12);
-          box_f32(rec[i].lo, rec[i].hi, en.lo, en.hi);
           ent[slot] = en;
         } else
           atomicOr(status, ST_PLAN_OVERFLOW);
@@ -514,7 +512,7 @@ __device__ __forceinline__ bool pair_ok(int q, int qa, int qb, bool qdof, int it
 }
 
 constexpr int QT = 128;         // query threads per block
-constexpr int APPEND_BUF = 8;   // per-thread LDS staging for append mode
+constexpr int APPEND_BUF = 16;  // per-thread LDS staging for append mode
 
 // append mode: stage a candidate in the thread's LDS slots; flush a full
 // buffer with one atomic
@@ -543,7 +541,35 @@ struct QueryArgs {
   const ItemRec *items;
   const int32_t *rowptr;
   const int32_t *vscene;
+  const int32_t *qlist;    // when set: the queries to run, *n_qlist of them
+  const int64_t *n_qlist;
 };
+
+// box, vertices, DoF flag and scene of query q (a vertex for PT, an edge
+// record for EE)
+template <int KIND>
+__device__ __forceinline__ void query_data(int q, const double *xs, const double *x1s, int n_vert, double h,
+                                           const QueryArgs &qa_, double *qlo, double *qhi, int &qa, int &qb,
+                                           bool &qdof, int &qsc) {
+  if (KIND == 0) {
+    qa = q;
+    qb = -1;
+    prim_box<1>(&qa, xs, x1s, n_vert, h, qlo, qhi);
+    qdof = has_dof(qa_.rowptr, qa);
+    qsc = scene_of(qa_.vscene, qa);
+  } else {
+    const ItemRec r = qa_.items[q];
+    qa = r.v[0];
+    qb = r.v[1];
+    qdof = r.tag & 1;
+    qsc = r.tag >> 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      qlo[a] = r.lo[a];
+      qhi[a] = r.hi[a];
+    }
+  }
+}
 
 // modes: 0 count, 1 write (offset per query, sorted per query, capacity
 // guarded), 2 append (LDS-staged, unsorted; *total receives the count)
@@ -557,30 +583,13 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
   int nbuf = 0;
   const GridDev g = *qa_.g;
   const ItemRec *items = qa_.items;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = q < nq;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = qa_.qlist ? (t < *qa_.n_qlist ? qa_.qlist[t] : -1) : t;
+  const bool live = q >= 0 && q < nq;
   int qa = 0, qb = -1, qsc = 0;
   bool qdof = false;
   double qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
-  if (live) {
-    if (KIND == 0) {
-      qa = q;
-      prim_box<1>(&qa, xs, x1s, n_vert, h, qlo, qhi);
-      qdof = has_dof(qa_.rowptr, qa);
-      qsc = scene_of(qa_.vscene, qa);
-    } else {
-      const ItemRec r = items[q];
-      qa = r.v[0];
-      qb = r.v[1];
-      qdof = r.tag & 1;
-      qsc = r.tag >> 1;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        qlo[a] = r.lo[a];
-        qhi[a] = r.hi[a];
-      }
-    }
-  }
+  if (live) query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
   int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
   if (live) cell_range(g, qlo, qhi, c0, c1);
   float fqlo[3], fqhi[3];
@@ -606,10 +615,6 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
                               (iz > c0[2] ? iz : c0[2]) == z;
             if (!home) continue;
           }
-          // conservative float test first (no false rejections)
-          if (!(fqlo[0] <= en.hi[0] && en.lo[0] <= fqhi[0] && fqlo[1] <= en.hi[1] && en.lo[1] <= fqhi[1] &&
-                fqlo[2] <= en.hi[2] && en.lo[2] <= fqhi[2]))
-            continue;
           const ItemRec r = items[it];
           if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
           if (!overlap(qlo, qhi, r)) continue;
@@ -696,18 +701,151 @@ static void launch_query(int nq, const double *xs, const double *x1s, int n_vert
                                                        status);
 }
 
+// ---------------------------------------------------------------------------
+// Cell-parallel query (append mode): one thread per (query, cell of its
+// box), listed in query order so that neighbouring threads share the query
+// and its neighbourhood (mesh order is spatially coherent).  Queries
+// covering more than MAX_ITEM_CELLS cells run per query (k_query on a
+// list).
+// ---------------------------------------------------------------------------
+struct QEntry {
+  uint64_t cell;
+  int32_t q;
+  int32_t dlo;  // cell minus the query's lower cell, 6 bits per axis
+};
+
+template <int KIND>
+__global__ void k_qcells(int nq, const double *__restrict__ xs, const double *__restrict__ x1s, int n_vert, double h,
+                         QueryArgs qa_, int32_t *qcnt, int32_t *qlarge, int64_t *n_qlarge) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const GridDev g = *qa_.g;
+  double qlo[3], qhi[3];
+  int qa, qb, qsc;
+  bool qdof;
+  query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
+  int c0[3], c1[3];
+  cell_range(g, qlo, qhi, c0, c1);
+  const int64_t nc = (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+  if (nc > MAX_ITEM_CELLS) {
+    const int slot = (int)atomicAdd((unsigned long long *)n_qlarge, 1ull);
+    qlarge[slot] = q;
+    qcnt[q] = 0;
+  } else {
+    qcnt[q] = (int32_t)nc;
+  }
+}
+
+template <int KIND>
+__global__ void k_qlist(int nq, const double *__restrict__ xs, const double *__restrict__ x1s, int n_vert, double h,
+                        QueryArgs qa_, const int32_t *qcnt, const int64_t *qoff, QEntry *qent, int64_t qent_cap,
+                        uint32_t *status) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq || qcnt[q] == 0) return;
+  const GridDev g = *qa_.g;
+  double qlo[3], qhi[3];
+  int qa, qb, qsc;
+  bool qdof;
+  query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
+  int c0[3], c1[3];
+  cell_range(g, qlo, qhi, c0, c1);
+  int64_t slot = qoff[q];
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x, ++slot) {
+        if (slot < qent_cap)
+          qent[slot] = QEntry{cell_key(x, y, z, qsc), q, (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12)};
+        else
+          atomicOr(status, ST_PLAN_OVERFLOW);
+      }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(QT) void k_query_ent(const int64_t *__restrict__ n_qent, int64_t qent_cap,
+                                                  const QEntry *__restrict__ qent, const double *__restrict__ xs,
+                                                  const double *__restrict__ x1s, int n_vert, double h, QueryArgs qa_,
+                                                  int32_t *__restrict__ out, int64_t cap, unsigned long long *total) {
+  __shared__ int2 s_buf[QT * APPEND_BUF];
+  int2 *buf = s_buf + threadIdx.x * APPEND_BUF;
+  int nbuf = 0;
+  const ItemRec *items = qa_.items;
+  const int64_t n = *n_qent < qent_cap ? *n_qent : qent_cap;
+  for (int64_t base = (int64_t)blockIdx.x * QT; base < n; base += (int64_t)gridDim.x * QT) {
+    const int64_t t = base + threadIdx.x;
+    if (t < n) {
+      const QEntry qe = qent[t];
+      const int q = qe.q;
+      double qlo[3], qhi[3];
+      int qa, qb, qsc;
+      bool qdof;
+      query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
+      float fqlo[3], fqhi[3];
+      box_f32(qlo, qhi, fqlo, fqhi);
+      const int x = (int)(qe.cell & 0xffff), y = (int)((qe.cell >> 16) & 0xffff), z = (int)((qe.cell >> 32) & 0xffff);
+      const int qx = x - (qe.dlo & 63), qy = y - ((qe.dlo >> 6) & 63), qz = z - ((qe.dlo >> 12) & 63);
+      const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
+      const int64_t e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
+      for (int64_t e = qa_.bstart[b]; e < e1; ++e) {
+        const Entry en = qa_.ent[e];
+        if (en.cell != qe.cell) continue;
+        const int it = en.item;
+        if (KIND == 1 && it <= q) continue;
+        // report only in the cell holding the lower corner of the overlap
+        const int ix = x - (en.dlo & 63), iy = y - ((en.dlo >> 6) & 63), iz = z - ((en.dlo >> 12) & 63);
+        if ((ix > qx ? ix : qx) != x || (iy > qy ? iy : qy) != y || (iz > qz ? iz : qz) != z) continue;
+        const ItemRec r = items[it];
+        if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
+        if (!overlap(qlo, qhi, r)) continue;
+        stage_pair(buf, nbuf, q, it, total, out, cap);
+      }
+      if (qe.dlo == 0) {
+        // the query's lower cell also runs the items too large to hash
+        const int nl = (int)*qa_.n_large;
+        for (int j = 0; j < nl; ++j) {
+          const int it = qa_.large[j];
+          const ItemRec r = items[it];
+          if ((r.tag >> 1) != qsc) continue;
+          if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
+          if (!overlap(qlo, qhi, r)) continue;
+          stage_pair(buf, nbuf, q, it, total, out, cap);
+        }
+      }
+    }
+  }
+  // flush what is left: one atomic per wavefront
+  int64_t ex = nbuf;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t yv = __shfl_up(ex, o, 64);
+    if (lane >= o) ex += yv;
+  }
+  const int64_t wsum = __shfl(ex, 63, 64);
+  int64_t p0 = 0;
+  if (lane == 63 && wsum) p0 = (int64_t)atomicAdd(total, (unsigned long long)wsum);
+  p0 = __shfl(p0, 63, 64);
+  const int64_t p = p0 + ex - nbuf;
+  for (int j = 0; j < nbuf; ++j)
+    if (p + j < cap) {
+      out[2 * (p + j)] = buf[j].x;
+      out[2 * (p + j) + 1] = buf[j].y;
+    }
+}
+
 // Scratch of one broad phase (kind, swept) kept in the context's buffers.
 struct BPScratch {
   ItemRec *items;
-  int32_t *cnt, *large, *bcnt, *bfill, *qcnt;
-  int64_t *cell_off, *bstart, *qoff, *n_large;
+  int32_t *cnt, *large, *bcnt, *bfill, *qcnt, *qlarge;
+  int64_t *cell_off, *bstart, *qoff, *n_large, *n_qlarge;
   Entry *ent;
+  QEntry *qent;
   GridDev *g;
   uint64_t *st;
   unsigned long long *total;
 };
 
-static eipc_status bp_scratch(eipc_ctx *c, int nq, int ni, uint32_t nb, int64_t ent_cap, int slot, BPScratch &b) {
+static eipc_status bp_scratch(eipc_ctx *c, int nq, int ni, uint32_t nb, int64_t ent_cap, int slot, BPScratch &b,
+                              int64_t qent_cap = 1) {
   const int base = slot * BP_NBUF;
   EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 0), (size_t)ni, &b.items));
   EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 1), (size_t)ni, &b.cnt));
@@ -725,6 +863,9 @@ static eipc_status bp_scratch(eipc_ctx *c, int nq, int ni, uint32_t nb, int64_t 
   b.st = (uint64_t *)(small + 128);
   b.n_large = (int64_t *)(small + 256);
   b.total = (unsigned long long *)(small + 264);
+  b.n_qlarge = (int64_t *)(small + 272);
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 11), (size_t)nq, &b.qlarge));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 12), (size_t)std::max<int64_t>(qent_cap, 1), &b.qent));
   return EIPC_OK;
 }
 
@@ -737,7 +878,7 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   if (n_out) *n_out = 0;
   if (nq == 0 || ni == 0) {
     if (d_total) EIPC_TRY(launch_zero(c, d_total, 8, s));
-    if (!plan) c->last_plan[slot] = BPPlan{1024, 1, 0};
+    if (!plan) c->last_plan[slot] = BPPlan{1024, 1, 0, 1};
     return EIPC_OK;
   }
   const double h = 0.5 * dhat;
@@ -746,7 +887,7 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   BPScratch b;
   uint32_t nb = plan ? plan->nb : 1024;
   int64_t ent_cap = plan ? plan->ent_cap : 1;
-  EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b));
+  EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b, plan ? plan->qent_cap : 1));
   if (kind == 0)
     k_items<3><<<grid_for(ni, 256), 256, 0, s>>>(ni, sc->faces, xs, x1s, sc->n_vert, h, sc->W_rowptr, vsc, b.items);
   else
@@ -756,7 +897,7 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   k_box_stats<<<stat_blocks(ni), STAT_T, 0, s>>>(ni, b.items, nullptr, nullptr, 0, h, b.st, 1);
   if (kind == 0) k_box_stats<<<stat_blocks(nq), STAT_T, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, b.st, 0);
   k_grid_params<<<1, 64, 0, s>>>(b.st, ni, c->cell_scale, b.g, c->status);
-  EIPC_TRY(launch_zero(c, b.n_large, 16, s));
+  EIPC_TRY(launch_zero(c, b.n_large, 24, s));
   k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, b.cnt, b.large, b.n_large);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, b.cnt, ni, b.cell_off, s));
@@ -786,10 +927,40 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bstart, b.bfill, b.ent, ent_cap,
                                                  c->status);
   EIPC_HIP(c, hipGetLastError());
-  QueryArgs qa{b.g, bmask, b.bstart, b.ent, ent_cap, b.large, b.n_large, b.items, sc->W_rowptr, vsc};
+  QueryArgs qa{b.g, bmask, b.bstart, b.ent, ent_cap, b.large, b.n_large, b.items, sc->W_rowptr, vsc, nullptr,
+               nullptr};
   const int n_vert = sc->n_vert;
   if (!sort) {
-    // single pass, unsorted append
+    // single pass, unsorted append; per (query, cell) or per query
+    const bool cellpar = c->query_cells[kind];
+    int64_t qent_cap = plan ? plan->qent_cap : 1;
+    const int gq = grid_for(nq, 256);
+    if (!cellpar) {
+      if (!plan) c->last_plan[slot].qent_cap = 1;
+    } else {
+    if (kind == 0)
+      k_qcells<0><<<gq, 256, 0, s>>>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qlarge, b.n_qlarge);
+    else
+      k_qcells<1><<<gq, 256, 0, s>>>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qlarge, b.n_qlarge);
+    EIPC_HIP(c, hipGetLastError());
+    EIPC_TRY(exclusive_scan(c, b.qcnt, nq, b.qoff, s));
+    if (!plan) {
+      int64_t tq = 0;
+      EIPC_HIP(c, hipMemcpyAsync(&tq, b.qoff + nq, 8, hipMemcpyDeviceToHost, s));
+      EIPC_HIP(c, hipStreamSynchronize(s));
+      qent_cap = std::max<int64_t>(tq, 1);
+      c->last_plan[slot].qent_cap = qent_cap;
+      EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b, qent_cap));
+    }
+    if (kind == 0)
+      k_qlist<0><<<gq, 256, 0, s>>>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qoff, b.qent, qent_cap, c->status);
+    else
+      k_qlist<1><<<gq, 256, 0, s>>>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qoff, b.qent, qent_cap, c->status);
+    EIPC_HIP(c, hipGetLastError());
+    }
+    QueryArgs qlq = qa;  // queries too large to bin, run per query
+    qlq.qlist = b.qlarge;
+    qlq.n_qlist = b.n_qlarge;
     int64_t capa = cap;
     if (plan) {
       capa = plan->cand_cap;
@@ -802,10 +973,25 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
       EIPC_TRY(launch_zero(c, b.total, 8, s));
       {
         ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
+        const int ge = (int)std::min<int64_t>(grid_for(qent_cap, QT), 64 * (int64_t)c->num_cu);
+        if (!cellpar) {
+          if (kind == 0)
+            launch_query<0, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
+          else
+            launch_query<1, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
+        } else {
         if (kind == 0)
-          launch_query<0, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
+          k_query_ent<0><<<ge, QT, 0, s>>>(b.qoff + nq, qent_cap, b.qent, xs, x1s, n_vert, h, qa, out, capa,
+                                           b.total);
         else
-          launch_query<1, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
+          k_query_ent<1><<<ge, QT, 0, s>>>(b.qoff + nq, qent_cap, b.qent, xs, x1s, n_vert, h, qa, out, capa,
+                                           b.total);
+        EIPC_HIP(c, hipGetLastError());
+        if (kind == 0)
+          launch_query<0, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
+        else
+          launch_query<1, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
+        }
       }
       EIPC_HIP(c, hipGetLastError());
       if (plan) {

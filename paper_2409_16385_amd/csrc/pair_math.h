@@ -682,8 +682,15 @@ __device__ __forceinline__ double mollifier_eps(const V3 *r) {
 //   loop: x += tl p; d = dist(x); if t > 0 and d < g stop;
 //         t += tl; if t > t_c return t_c; tl = 0.9 d / l_p
 // ---------------------------------------------------------------------------
+struct AccdState {
+  double lp, g, t, tl;
+  int64_t it;
+};
+
+// Set-up of one pair (p is made relative to its mean).  Returns true when
+// the pair is already decided (no relative motion: the bound is t_c).
 template <int KIND>
-__device__ __forceinline__ double accd(V3 *x, V3 *p, double s, double t_c, int64_t max_iter, int64_t *iters) {
+__device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, AccdState &st) {
 #pragma clang fp contract(off)
   V3 mean;
   mean.x = (((p[0].x + p[1].x) + p[2].x) + p[3].x) * 0.25;
@@ -693,35 +700,52 @@ __device__ __forceinline__ double accd(V3 *x, V3 *p, double s, double t_c, int64
   for (int a = 0; a < 4; ++a) p[a] = xsub(p[a], mean);
   double n0 = sqrt(xdot(p[0], p[0])), n1 = sqrt(xdot(p[1], p[1]));
   double n2 = sqrt(xdot(p[2], p[2])), n3 = sqrt(xdot(p[3], p[3]));
-  double lp = KIND == 0 ? n0 + fmax(n1, fmax(n2, n3)) : fmax(n0, n1) + fmax(n2, n3);
-  *iters = 0;
-  if (lp == 0.0) return t_c;
-  int ty;
-  double d = sqrt(pair_dist2<KIND>(x, &ty));
-  const double g = s * d;
-  double t = 0.0;
-  double tl = (1.0 - s) * d / lp;
-  int64_t it = 0;
-  for (;;) {
-    if (it >= max_iter) break;
-    ++it;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      x[a].x = x[a].x + tl * p[a].x;
-      x[a].y = x[a].y + tl * p[a].y;
-      x[a].z = x[a].z + tl * p[a].z;
-    }
-    d = sqrt(pair_dist2<KIND>(x, &ty));
-    if (t > 0.0 && d < g) break;
-    t = t + tl;
-    if (t > t_c) {
-      t = t_c;
-      break;
-    }
-    tl = 0.9 * d / lp;
+  st.lp = KIND == 0 ? n0 + fmax(n1, fmax(n2, n3)) : fmax(n0, n1) + fmax(n2, n3);
+  st.it = 0;
+  st.t = 0.0;
+  if (st.lp == 0.0) {
+    st.t = t_c;
+    return true;
   }
-  *iters = it;
-  return t;
+  int ty;
+  const double d = sqrt(pair_dist2<KIND>(x, &ty));
+  st.g = s * d;
+  st.tl = (1.0 - s) * d / st.lp;
+  return false;
+}
+
+// One advancement step.  Returns true when the pair's bound st.t is final.
+template <int KIND>
+__device__ __forceinline__ bool accd_step(V3 *x, const V3 *p, double t_c, int64_t max_iter, AccdState &st) {
+#pragma clang fp contract(off)
+  if (st.it >= max_iter) return true;
+  ++st.it;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    x[a].x = x[a].x + st.tl * p[a].x;
+    x[a].y = x[a].y + st.tl * p[a].y;
+    x[a].z = x[a].z + st.tl * p[a].z;
+  }
+  int ty;
+  const double d = sqrt(pair_dist2<KIND>(x, &ty));
+  if (st.t > 0.0 && d < st.g) return true;
+  st.t = st.t + st.tl;
+  if (st.t > t_c) {
+    st.t = t_c;
+    return true;
+  }
+  st.tl = 0.9 * d / st.lp;
+  return false;
+}
+
+template <int KIND>
+__device__ __forceinline__ double accd(V3 *x, V3 *p, double s, double t_c, int64_t max_iter, int64_t *iters) {
+  AccdState st;
+  if (!accd_init<KIND>(x, p, s, t_c, st))
+    while (!accd_step<KIND>(x, p, t_c, max_iter, st)) {
+    }
+  *iters = st.it;
+  return st.t;
 }
 
 }  // namespace eipc

@@ -170,12 +170,13 @@ def test_plan_overflow_is_reported(batch):
 
 def test_autotune_keeps_results(ctx, scenes, seq):
     b = BT.Batch(ctx, BT.concat(scenes))
-    t = b.autotune(cell_scales=(1.0, 2.0), wg_values=(2, 8), reps=1)
+    t = b.autotune(cell_scales=(1.0, 2.0), query_modes=(0, 3), wg_values=(2, 8), reps=1)
     assert t["cell_scale"] in (1.0, 2.0) and all(v in (2, 8) for v in t["wg_per_cu"])
+    assert t["query_cells"] in (0, 3)
     b.step()
     assert b.status() == E.binding.OK
     _check_against_sequential(b, seq, scenes)
-    E.set_tuning(ctx, 2.0, [8, 2, 4, 4])
+    E.set_tuning(ctx, 2.0, [8, 2, 4, 4], 1)
 
 
 def test_bad_scene_id_is_an_argument_error(ctx, scenes):
@@ -186,3 +187,15 @@ def test_bad_scene_id_is_an_argument_error(ctx, scenes):
     with pytest.raises(E.EipcError):
         b.make_plan(1.5)
     ctx.sync_status()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_query_work_split_does_not_change_results(ctx, scenes, seq, mode):
+    """Per-query and per-(query, cell) broad-phase work splits give the same
+    candidate sets, so the same counts, energies and step bounds."""
+    b = BT.Batch(ctx, BT.concat(scenes))
+    E.set_tuning(b.ctx, 2.0, [0, 0, 0, 0], mode)
+    b.make_plan(1.5)
+    b.step()
+    assert b.status() == E.binding.OK
+    _check_against_sequential(b, seq, scenes)
