@@ -73,98 +73,75 @@ __global__ void k_ccd(int64_t cap, const int64_t *d_n, const int32_t *__restrict
   if (__any(capped) && (threadIdx.x & 63) == 0) atomicOr(status, ST_CCD_CAPPED);
 }
 
-// Step bound only (no per-pair output): persistent lanes with dynamic
-// work.  Each lane advances one pair per round; a lane whose pair is
-// decided takes the next pair from its wavefront's range of CCD_CHUNK
-// pairs, refilled from a global counter.  Pairs needing many steps then
-// no longer hold up the other lanes of their wavefront.  Each lane keeps
-// the minimum of its scene and publishes it when the scene changes and at
-// the end.
-constexpr int CCD_CHUNK = 256;
+// Step bound only (no per-pair output), in two passes so that the few
+// pairs needing many advancement steps do not hold up whole wavefronts:
+// pass 0 gives every pair up to CCD_SHORT steps and defers the pairs still
+// undecided to a compacted list; pass 1 runs those from the start with
+// the full iteration cap.  Each pair's bound is computed exactly as in
+// one uninterrupted run.
+constexpr int64_t CCD_SHORT = 16;
 
-template <int KIND>
-__global__ __launch_bounds__(256) void k_ccd_dyn(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
-                                                 const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
-                                                 const double *__restrict__ xs, const double *__restrict__ ps,
-                                                 int n_vert, double sfac, double t_max, int64_t max_iter,
-                                                 unsigned long long *alpha_bits, unsigned long long *next,
-                                                 const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
-  const int64_t n = d_n ? (*d_n < cap ? *d_n : cap) : cap;
+template <int KIND, int PASS>
+__global__ void k_ccd2(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
+                       const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
+                       const double *__restrict__ xs, const double *__restrict__ ps, int n_vert, double sfac,
+                       double t_max, int64_t max_iter, unsigned long long *alpha_bits, int32_t *__restrict__ longl,
+                       int64_t *n_long, const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
+  const int64_t n = PASS == 0 ? (d_n ? (*d_n < cap ? *d_n : cap) : cap) : (*n_long < cap ? *n_long : cap);
   const int lane = threadIdx.x & 63;
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
-  V3 x[4], p[4];
-  AccdState st;
-  bool busy = false, capped = false;
-  int scene = 0, cur = -1;
-  double tmin = INFINITY;
-  int64_t qb = 0, qe = 0;  // the wavefront's range of unclaimed pairs
-  bool exhausted = false;
-  auto record = [&](double t) {
-    if (scene != cur) {
-      if (cur >= 0) atomicMin(&alpha_bits[cur], (unsigned long long)__double_as_longlong(tmin));
-      cur = scene;
-      tmin = t;
-    } else {
-      tmin = fmin(tmin, t);
-    }
-  };
-  for (;;) {
-    const uint64_t want = __ballot(!busy);
-    if (want && qb >= qe && !exhausted) {
-      int64_t base = 0;
-      if (lane == 0) base = (int64_t)atomicAdd(next, (unsigned long long)CCD_CHUNK);
-      base = __shfl(base, 0, 64);
-      if (base >= n) {
-        exhausted = true;
+  bool capped = false;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool live = i < n;
+    double t = t_max;
+    int scene = 0;
+    bool decided = false, deferred = false;
+    if (live) {
+      const int64_t k = PASS == 0 ? i : (int64_t)longl[i];
+      const int a = pairs[2 * k], b = pairs[2 * k + 1];
+      int vid[4];
+      if (KIND == 0) {
+        vid[0] = a;
+        vid[1] = faces[3 * (int64_t)b];
+        vid[2] = faces[3 * (int64_t)b + 1];
+        vid[3] = faces[3 * (int64_t)b + 2];
       } else {
-        qb = base;
-        qe = base + CCD_CHUNK < n ? base + CCD_CHUNK : n;
+        vid[0] = edges[2 * (int64_t)a];
+        vid[1] = edges[2 * (int64_t)a + 1];
+        vid[2] = edges[2 * (int64_t)b];
+        vid[3] = edges[2 * (int64_t)b + 1];
       }
-    }
-    if (want && qb < qe) {
-      const int64_t avail = qe - qb;
-      const int rank = __popcll(want & lt_mask);
-      if (!busy && rank < avail) {
-        const int64_t k = qb + rank;
-        const int a = pairs[2 * k], b = pairs[2 * k + 1];
-        int vid[4];
-        if (KIND == 0) {
-          vid[0] = a;
-          vid[1] = faces[3 * (int64_t)b];
-          vid[2] = faces[3 * (int64_t)b + 1];
-          vid[3] = faces[3 * (int64_t)b + 2];
-        } else {
-          vid[0] = edges[2 * (int64_t)a];
-          vid[1] = edges[2 * (int64_t)a + 1];
-          vid[2] = edges[2 * (int64_t)b];
-          vid[3] = edges[2 * (int64_t)b + 1];
-        }
-        scene = vscene ? vscene[vid[0]] : 0;
-        if ((unsigned)scene >= (unsigned)n_scene) {
-          atomicOr(status, ST_BAD_SCENE);
-        } else {
+      if (vscene) scene = vscene[vid[0]];
+      V3 x[4], p[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            x[q] = V3{xs[vid[q]], xs[n_vert + vid[q]], xs[2 * (int64_t)n_vert + vid[q]]};
-            p[q] = V3{ps[vid[q]], ps[n_vert + vid[q]], ps[2 * (int64_t)n_vert + vid[q]]};
-          }
-          if (accd_init<KIND>(x, p, sfac, t_max, st))
-            record(st.t);
-          else
-            busy = true;
-        }
+      for (int q = 0; q < 4; ++q) {
+        x[q] = V3{xs[vid[q]], xs[n_vert + vid[q]], xs[2 * (int64_t)n_vert + vid[q]]};
+        p[q] = V3{ps[vid[q]], ps[n_vert + vid[q]], ps[2 * (int64_t)n_vert + vid[q]]};
       }
-      const int64_t taken = (int64_t)__popcll(want) < avail ? (int64_t)__popcll(want) : avail;
-      qb += taken;
+      AccdState st;
+      decided = accd_init<KIND>(x, p, sfac, t_max, st);
+      const int64_t lim = PASS == 0 ? (CCD_SHORT < max_iter ? CCD_SHORT : max_iter) : max_iter;
+      while (!decided && st.it < lim) decided = accd_step<KIND>(x, p, t_max, max_iter, st);
+      if (!decided && st.it >= max_iter) decided = accd_step<KIND>(x, p, t_max, max_iter, st);  // cap reached
+      if (decided) {
+        t = st.t;
+        capped = st.it >= max_iter;
+      } else {
+        deferred = true;  // pass 0 only: more than CCD_SHORT steps
+      }
     }
-    if (!__any(busy) && qb >= qe && exhausted) break;
-    if (busy && accd_step<KIND>(x, p, t_max, max_iter, st)) {
-      capped = capped || st.it >= max_iter;
-      record(st.t);
-      busy = false;
+    if (PASS == 0) {
+      const uint64_t dm = __ballot(deferred);
+      if (dm) {
+        int64_t p0 = 0;
+        if (lane == __ffsll((unsigned long long)dm) - 1)
+          p0 = (int64_t)atomicAdd((unsigned long long *)n_long, (unsigned long long)__popcll(dm));
+        p0 = __shfl(p0, __ffsll((unsigned long long)dm) - 1, 64);
+        if (deferred) longl[p0 + __popcll(dm & ((1ull << lane) - 1ull))] = (int32_t)i;
+      }
     }
+    agg_scene_min(alpha_bits, live && decided, scene, n_scene, t, status);
   }
-  if (cur >= 0) atomicMin(&alpha_bits[cur], (unsigned long long)__double_as_longlong(tmin));
   if (__any(capped) && lane == 0) atomicOr(status, ST_CCD_CAPPED);
 }
 
@@ -177,14 +154,22 @@ eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double
   const int32_t *vsc = vscene_of(sc);
   const int nsc = n_scene_of(sc);
   if (d_alpha_bits && !t_out && !it_out) {
-    unsigned long long *next = (unsigned long long *)(c->counters + 9 + kind);
-    EIPC_TRY(launch_zero(c, next, 8, s));
-    if (kind == 0)
-      k_ccd_dyn<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                          max_iter, (unsigned long long *)d_alpha_bits, next, vsc, nsc, c->status);
-    else
-      k_ccd_dyn<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                          max_iter, (unsigned long long *)d_alpha_bits, next, vsc, nsc, c->status);
+    int64_t *n_long = c->counters + 9 + kind;
+    int32_t *longl;
+    EIPC_TRY(ensure_t(c, kind == 0 ? B_CCD_LONG_PT : B_CCD_LONG_EE, (size_t)n, &longl));
+    EIPC_TRY(launch_zero(c, n_long, 8, s));
+    unsigned long long *ab = (unsigned long long *)d_alpha_bits;
+    if (kind == 0) {
+      k_ccd2<0, 0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+      k_ccd2<0, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+    } else {
+      k_ccd2<1, 0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+      k_ccd2<1, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+    }
   } else if (kind == 0)
     k_ccd<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max, max_iter,
                                      (unsigned long long *)d_alpha_bits, t_out, it_out, vsc, nsc, c->status);
