@@ -29,7 +29,7 @@ __device__ __forceinline__ void agg_scene_min(unsigned long long *bits, bool val
 }
 
 template <int KIND>
-__global__ void k_ccd(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
+__global__ __launch_bounds__(256) void k_ccd(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
                       const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
                       const double *__restrict__ xs, const double *__restrict__ ps, int n_vert, double sfac,
                       double t_max, int64_t max_iter, unsigned long long *alpha_bits, double *t_out, int64_t *it_out,
@@ -82,7 +82,7 @@ __global__ void k_ccd(int64_t cap, const int64_t *d_n, const int32_t *__restrict
 constexpr int64_t CCD_SHORT = 16;
 
 template <int KIND, int PASS>
-__global__ void k_ccd2(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
+__global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
                        const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
                        const double *__restrict__ xs, const double *__restrict__ ps, int n_vert, double sfac,
                        double t_max, int64_t max_iter, unsigned long long *alpha_bits, int32_t *__restrict__ longl,
