@@ -511,6 +511,46 @@ __device__ __forceinline__ bool pair_ok(int q, int qa, int qb, bool qdof, int it
   return qdof || (r.tag & 1);
 }
 
+// Scan the hash entries [e0, e1) of one bucket for the query's cell
+// (x, y, z) (key), with the query's lower cell (qx, qy, qz): entries are
+// read four at a time (independent loads), filtered on their own fields
+// (cell, EE order, lower-corner rule), then the surviving items' records
+// are read together and tested exactly; emit(item) for each candidate.
+template <int KIND, class Emit>
+__device__ __forceinline__ void scan_bucket(const Entry *__restrict__ ent, const ItemRec *__restrict__ items,
+                                            int64_t e0, int64_t e1, uint64_t key, int x, int y, int z, int qx,
+                                            int qy, int qz, int q, int qa, int qb, bool qdof, const double *qlo,
+                                            const double *qhi, Emit emit) {
+  for (int64_t e = e0; e < e1; e += 4) {
+    Entry en[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (e + u < e1) {
+        en[u] = ent[e + u];
+      } else {
+        en[u].cell = ~0ull;
+        en[u].item = 0;
+        en[u].dlo = 0;
+      }
+    }
+    bool pass[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int it = en[u].item;
+      const int ix = x - (en[u].dlo & 63), iy = y - ((en[u].dlo >> 6) & 63), iz = z - ((en[u].dlo >> 12) & 63);
+      pass[u] = en[u].cell == key && (KIND == 0 || it > q) && (ix > qx ? ix : qx) == x &&
+                (iy > qy ? iy : qy) == y && (iz > qz ? iz : qz) == z;
+    }
+    ItemRec r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (pass[u]) r[u] = items[en[u].item];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (pass[u] && pair_ok<KIND>(q, qa, qb, qdof, en[u].item, r[u]) && overlap(qlo, qhi, r[u])) emit(en[u].item);
+  }
+}
+
 constexpr int QT = 128;         // query threads per block
 constexpr int APPEND_BUF = 16;  // per-thread LDS staging for append mode
 
@@ -602,32 +642,20 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
         const uint64_t key = cell_key(x, y, z, qsc);
         const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
         const int64_t e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
-        for (int64_t e = qa_.bstart[b]; e < e1; ++e) {
-          const Entry en = qa_.ent[e];
-          if (en.cell != key) continue;
-          const int it = en.item;
-          if (KIND == 1 && it <= q) continue;
-          // report only in the cell holding the lower corner of the overlap:
-          // max(query low cell, item low cell) == this cell on every axis
-          {
-            const int ix = x - (en.dlo & 63), iy = y - ((en.dlo >> 6) & 63), iz = z - ((en.dlo >> 12) & 63);
-            const bool home = (ix > c0[0] ? ix : c0[0]) == x && (iy > c0[1] ? iy : c0[1]) == y &&
-                              (iz > c0[2] ? iz : c0[2]) == z;
-            if (!home) continue;
-          }
-          const ItemRec r = items[it];
-          if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
-          if (!overlap(qlo, qhi, r)) continue;
-          if (MODE == 1) {
-            if (base + k < cap) {
-              out[2 * (base + k)] = q;
-              out[2 * (base + k) + 1] = it;
-            }
-          } else if (MODE == 2) {
-            stage_pair(buf, nbuf, q, it, total, out, cap);
-          }
-          ++k;
-        }
+        // report only in the cell holding the lower corner of the overlap:
+        // max(query low cell, item low cell) == this cell on every axis
+        scan_bucket<KIND>(qa_.ent, items, qa_.bstart[b], e1, key, x, y, z, c0[0], c0[1], c0[2], q, qa, qb, qdof,
+                          qlo, qhi, [&](int it) {
+                            if (MODE == 1) {
+                              if (base + k < cap) {
+                                out[2 * (base + k)] = q;
+                                out[2 * (base + k) + 1] = it;
+                              }
+                            } else if (MODE == 2) {
+                              stage_pair(buf, nbuf, q, it, total, out, cap);
+                            }
+                            ++k;
+                          });
       }
   if (live) {
     const int nl = (int)*qa_.n_large;
@@ -785,19 +813,8 @@ __global__ __launch_bounds__(QT) void k_query_ent(const int64_t *__restrict__ n_
       const int qx = x - (qe.dlo & 63), qy = y - ((qe.dlo >> 6) & 63), qz = z - ((qe.dlo >> 12) & 63);
       const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
       const int64_t e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
-      for (int64_t e = qa_.bstart[b]; e < e1; ++e) {
-        const Entry en = qa_.ent[e];
-        if (en.cell != qe.cell) continue;
-        const int it = en.item;
-        if (KIND == 1 && it <= q) continue;
-        // report only in the cell holding the lower corner of the overlap
-        const int ix = x - (en.dlo & 63), iy = y - ((en.dlo >> 6) & 63), iz = z - ((en.dlo >> 12) & 63);
-        if ((ix > qx ? ix : qx) != x || (iy > qy ? iy : qy) != y || (iz > qz ? iz : qz) != z) continue;
-        const ItemRec r = items[it];
-        if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
-        if (!overlap(qlo, qhi, r)) continue;
-        stage_pair(buf, nbuf, q, it, total, out, cap);
-      }
+      scan_bucket<KIND>(qa_.ent, items, qa_.bstart[b], e1, qe.cell, x, y, z, qx, qy, qz, q, qa, qb, qdof, qlo, qhi,
+                        [&](int it) { stage_pair(buf, nbuf, q, it, total, out, cap); });
       if (qe.dlo == 0) {
         // the query's lower cell also runs the items too large to hash
         const int nl = (int)*qa_.n_large;

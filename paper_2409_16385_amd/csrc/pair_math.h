@@ -698,9 +698,10 @@ __device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, Ac
   mean.z = (((p[0].z + p[1].z) + p[2].z) + p[3].z) * 0.25;
 #pragma unroll
   for (int a = 0; a < 4; ++a) p[a] = xsub(p[a], mean);
-  double n0 = sqrt(xdot(p[0], p[0])), n1 = sqrt(xdot(p[1], p[1]));
-  double n2 = sqrt(xdot(p[2], p[2])), n3 = sqrt(xdot(p[3], p[3]));
-  st.lp = KIND == 0 ? n0 + fmax(n1, fmax(n2, n3)) : fmax(n0, n1) + fmax(n2, n3);
+  // |p_a| through squared norms: sqrt is monotone and correctly rounded,
+  // so sqrt(max(a, b)) == max(sqrt(a), sqrt(b)) exactly
+  const double q0 = xdot(p[0], p[0]), q1 = xdot(p[1], p[1]), q2 = xdot(p[2], p[2]), q3 = xdot(p[3], p[3]);
+  st.lp = KIND == 0 ? sqrt(q0) + sqrt(fmax(q1, fmax(q2, q3))) : sqrt(fmax(q0, q1)) + sqrt(fmax(q2, q3));
   st.it = 0;
   st.t = 0.0;
   if (st.lp == 0.0) {
@@ -720,6 +721,12 @@ __device__ __forceinline__ bool accd_step(V3 *x, const V3 *p, double t_c, int64_
 #pragma clang fp contract(off)
   if (st.it >= max_iter) return true;
   ++st.it;
+  // before the first advance (t == 0) the gap test cannot stop the pair,
+  // so a first step beyond t_c decides it without its distance
+  if (st.t == 0.0 && st.t + st.tl > t_c) {
+    st.t = t_c;
+    return true;
+  }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     x[a].x = x[a].x + st.tl * p[a].x;
