@@ -480,24 +480,50 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
 // of pairs touches few distinct node blocks (its LDS tables then absorb
 // most of the accumulation).
 // ---------------------------------------------------------------------------
+// Per-lane offsets from counters ctr[key], one atomic per distinct key in
+// the wavefront (lanes with equal keys are served together).  All lanes
+// of the wavefront must call.
+__device__ __forceinline__ int wave_key_add(int *ctr, int key, bool valid) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  int res = 0;
+  uint64_t pending = __ballot(valid);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int lk = __shfl(key, leader, 64);
+    const uint64_t m = __ballot(valid && key == lk) & pending;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[lk], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if ((m >> lane) & 1ull) res = base + __popcll(m & lt);
+    pending &= ~m;
+  }
+  return res;
+}
+
 template <int KIND>
 __global__ void k_pair_keys(const int32_t *__restrict__ pairs, const int32_t *__restrict__ act,
                             const int64_t *__restrict__ d_count, int64_t cap, const int32_t *__restrict__ faces,
                             const int32_t *__restrict__ edges, const int32_t *__restrict__ rowptr,
                             const int32_t *__restrict__ col, int n_node, int32_t *__restrict__ key, int32_t *hist) {
   const int64_t n = *d_count < cap ? *d_count : cap;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int vid[4];
-    pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
-    int k = -1;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool live = i < n;
+    int k = 0;
+    if (live) {
+      int vid[4];
+      pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
+      k = -1;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r0 = rowptr[vid[a]];
-      if (k < 0 && rowptr[vid[a] + 1] > r0) k = col[r0];
+      for (int a = 0; a < 4; ++a) {
+        const int r0 = rowptr[vid[a]];
+        if (k < 0 && rowptr[vid[a] + 1] > r0) k = col[r0];
+      }
+      if ((unsigned)k >= (unsigned)n_node) k = 0;
+      key[i] = k;
     }
-    if ((unsigned)k >= (unsigned)n_node) k = 0;
-    key[i] = k;
-    atomicAdd(&hist[k], 1);
+    wave_key_add(hist, k, live);
   }
 }
 
@@ -506,11 +532,16 @@ __global__ void k_pair_scatter(const int32_t *__restrict__ act, const int32_t *_
                                const int64_t *__restrict__ start, int32_t *fill, int32_t *__restrict__ act2,
                                int32_t *__restrict__ typ2) {
   const int64_t n = *d_count < cap ? *d_count : cap;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int k = key[i];
-    const int64_t pos = start[k] + atomicAdd(&fill[k], 1);
-    act2[pos] = act[i];
-    typ2[pos] = typ[i];
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool live = i < n;
+    const int k = live ? key[i] : 0;
+    const int off = wave_key_add(fill, k, live);
+    if (live) {
+      const int64_t pos = start[k] + off;
+      act2[pos] = act[i];
+      typ2[pos] = typ[i];
+    }
   }
 }
 
