@@ -236,9 +236,10 @@ eipc_status eipc_contact_step(eipc_ctx *ctx, const eipc_scene *sc, const eipc_pl
  * workgroups per compute unit of the grid-stride kernels (pair terms,
  * expansion, narrow phase, CCD; each 1..64, 0 keeps the current value; the
  * array may be NULL); and how the unsorted (planned-step and step-bound)
- * broad phases split their work: bit 0 for PT, bit 1 for EE, set = one
- * thread per (query, cell of its box), clear = one thread per query
- * (-1 keeps the current choice; default 1).  Used by the batch autotuner;
+ * broad phases split their work, query_cells = mode_PT + 4 * mode_EE with
+ * mode 0 = one thread per query, 1 = one thread per (query, cell of its
+ * box), 2 = one wavefront per (query, cell) (-1 keeps the current choice;
+ * default 1, i.e. PT mode 1 and EE mode 0).  Used by the batch autotuner;
  * results do not depend on them except for the order of unsorted
  * candidate lists and the rounding order of sums.  A plan must be made
  * again after changing them. */

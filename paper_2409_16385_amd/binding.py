@@ -443,8 +443,9 @@ def fp64_selftest(ctx: Context, a, b):
 def set_tuning(ctx: Context, cell_scale: float, wg_per_cu=(0, 0, 0, 0), query_cells: int = -1):
     """Broad-phase cell scale, workgroups per CU of the grid-stride kernels
     (pair terms, expansion, narrow phase, CCD; 0 keeps a value) and the
-    unsorted broad phase's work split (bit 0 PT, bit 1 EE: per query cell;
-    -1 keeps it)."""
+    unsorted broad phase's work split, mode_PT + 4 * mode_EE with modes 0
+    (thread per query), 1 (thread per query cell), 2 (wavefront per query
+    cell); -1 keeps it."""
     w = (_I32 * 4)(*[int(v) for v in wg_per_cu])
     ctx.check(_load().eipc_set_tuning(ctx.handle, float(cell_scale), w, int(query_cells)))
 

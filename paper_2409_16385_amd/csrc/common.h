@@ -84,7 +84,9 @@ struct eipc_ctx {
   int num_cu = 256;
   double cell_scale = 2.0;       // broad-phase cell edge / mean item extent
   int wg_per_cu[4] = {8, 2, 4, 4};  // grid sizes: pair terms, expansion, narrow, CCD
-  bool query_cells[2] = {true, false};  // append-mode query per (query, cell) [PT, EE], else per query
+  // append-mode broad phase work split [PT, EE]: 0 thread per query,
+  // 1 thread per (query, cell), 2 wavefront per (query, cell)
+  int query_mode[2] = {1, 0};
   eipc::BPPlan last_plan[4] = {};   // sizes seen by the last unplanned broad phases
   bool prof = false;                        // record per-kernel events
   std::vector<eipc::ProfRec> prof_pending;  // recorded, not yet read

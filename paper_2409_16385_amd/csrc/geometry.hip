@@ -849,6 +849,78 @@ __global__ __launch_bounds__(QT) void k_query_ent(const int64_t *__restrict__ n_
     }
 }
 
+// Wavefront per (query, cell): the 64 lanes read 64 consecutive entries of
+// the cell's bucket at once (coalesced), filter them in parallel and test
+// the survivors exactly; the query's data is the same for every lane.
+// Candidates are staged per lane in LDS as in k_query.  Query cells are
+// taken in query order, one per wavefront at a time.
+template <int KIND>
+__global__ __launch_bounds__(QT) void k_query_wave(const int64_t *__restrict__ n_qent, int64_t qent_cap,
+                                                   const QEntry *__restrict__ qent, const double *__restrict__ xs,
+                                                   const double *__restrict__ x1s, int n_vert, double h,
+                                                   QueryArgs qa_, int32_t *__restrict__ out, int64_t cap,
+                                                   unsigned long long *total) {
+  __shared__ int2 s_buf[QT * APPEND_BUF];
+  int2 *buf = s_buf + threadIdx.x * APPEND_BUF;
+  int nbuf = 0;
+  const ItemRec *items = qa_.items;
+  const int lane = threadIdx.x & 63;
+  const int64_t n = *n_qent < qent_cap ? *n_qent : qent_cap;
+  const int64_t wave = ((int64_t)blockIdx.x * QT + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * QT) >> 6;
+  for (int64_t t = wave; t < n; t += n_waves) {
+    const QEntry qe = qent[t];
+    const int q = qe.q;
+    double qlo[3], qhi[3];
+    int qa, qb, qsc;
+    bool qdof;
+    query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
+    const int x = (int)(qe.cell & 0xffff), y = (int)((qe.cell >> 16) & 0xffff), z = (int)((qe.cell >> 32) & 0xffff);
+    const int qx = x - (qe.dlo & 63), qy = y - ((qe.dlo >> 6) & 63), qz = z - ((qe.dlo >> 12) & 63);
+    const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
+    const int64_t e0 = qa_.bstart[b];
+    const int64_t e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+      const Entry en = qa_.ent[e];
+      const int it = en.item;
+      // report only in the cell holding the lower corner of the overlap
+      const int ix = x - (en.dlo & 63), iy = y - ((en.dlo >> 6) & 63), iz = z - ((en.dlo >> 12) & 63);
+      if (en.cell != qe.cell || (KIND == 1 && it <= q) || (ix > qx ? ix : qx) != x || (iy > qy ? iy : qy) != y ||
+          (iz > qz ? iz : qz) != z)
+        continue;
+      const ItemRec r = items[it];
+      if (pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r)) stage_pair(buf, nbuf, q, it, total, out, cap);
+    }
+    if (qe.dlo == 0) {
+      // the query's lower cell also runs the items too large to hash
+      const int nl = (int)*qa_.n_large;
+      for (int j = lane; j < nl; j += 64) {
+        const int it = qa_.large[j];
+        const ItemRec r = items[it];
+        if ((r.tag >> 1) != qsc) continue;
+        if (pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r)) stage_pair(buf, nbuf, q, it, total, out, cap);
+      }
+    }
+  }
+  // flush what is left: one atomic per wavefront
+  int64_t ex = nbuf;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t yv = __shfl_up(ex, o, 64);
+    if (lane >= o) ex += yv;
+  }
+  const int64_t wsum = __shfl(ex, 63, 64);
+  int64_t p0 = 0;
+  if (lane == 63 && wsum) p0 = (int64_t)atomicAdd(total, (unsigned long long)wsum);
+  p0 = __shfl(p0, 63, 64);
+  const int64_t p = p0 + ex - nbuf;
+  for (int j = 0; j < nbuf; ++j)
+    if (p + j < cap) {
+      out[2 * (p + j)] = buf[j].x;
+      out[2 * (p + j) + 1] = buf[j].y;
+    }
+}
+
 // Scratch of one broad phase (kind, swept) kept in the context's buffers.
 struct BPScratch {
   ItemRec *items;
@@ -949,7 +1021,7 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   const int n_vert = sc->n_vert;
   if (!sort) {
     // single pass, unsorted append; per (query, cell) or per query
-    const bool cellpar = c->query_cells[kind];
+    const bool cellpar = c->query_mode[kind] != 0;
     int64_t qent_cap = plan ? plan->qent_cap : 1;
     const int gq = grid_for(nq, 256);
     if (!cellpar) {
@@ -996,6 +1068,19 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
             launch_query<0, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
           else
             launch_query<1, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
+        } else if (c->query_mode[kind] == 2) {
+          const int gw = (int)std::min<int64_t>(grid_for(qent_cap * 64, QT), 32 * (int64_t)c->num_cu);
+          if (kind == 0)
+            k_query_wave<0><<<gw, QT, 0, s>>>(b.qoff + nq, qent_cap, b.qent, xs, x1s, n_vert, h, qa, out, capa,
+                                              b.total);
+          else
+            k_query_wave<1><<<gw, QT, 0, s>>>(b.qoff + nq, qent_cap, b.qent, xs, x1s, n_vert, h, qa, out, capa,
+                                              b.total);
+          EIPC_HIP(c, hipGetLastError());
+          if (kind == 0)
+            launch_query<0, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
+          else
+            launch_query<1, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
         } else {
         if (kind == 0)
           k_query_ent<0><<<ge, QT, 0, s>>>(b.qoff + nq, qent_cap, b.qent, xs, x1s, n_vert, h, qa, out, capa,

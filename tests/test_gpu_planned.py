@@ -89,7 +89,7 @@ def test_graph_replay_at_full_size(ctx):
         _compare(b, _plain(ctx, "config2"))
 
 
-@pytest.mark.parametrize("mode", [0, 3])
+@pytest.mark.parametrize("mode", [0, 5, 10])
 def test_tuning_does_not_change_results(ctx, mode):
     sc = _scene("config2")
     b = BT.Batch(ctx, BT.concat([sc]), flags=_flags(sc))
