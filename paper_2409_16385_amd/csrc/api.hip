@@ -276,7 +276,7 @@ eipc_status eipc_build_candidates(eipc_ctx *c, const eipc_scene *sc, const doubl
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   double *xs;
-  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_X, (size_t)PSTRIDE * sc->n_vert + 1, &xs));
   EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
   eipc_status s1 = broad_phase(c, sc, 0, xs, nullptr, dhat, pt, cap_pt, n_pt, 1, s);
   if (s1 != EIPC_OK && s1 != EIPC_ERR_CAPACITY) return s1;
@@ -306,7 +306,7 @@ eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double 
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   double *xs;
-  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_X, (size_t)PSTRIDE * sc->n_vert + 1, &xs));
   EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
   int32_t *act_pt, *typ_pt, *act_ee, *typ_ee;
   EIPC_TRY(narrow_both(c, sc, xs, pt, n_pt, ee, n_ee, dhat, &act_pt, &typ_pt, &act_ee, &typ_ee, s));
@@ -367,7 +367,7 @@ eipc_status eipc_ccd_max_step(eipc_ctx *c, const eipc_scene *sc, const double *q
     return set_err(c, EIPC_ERR_ARG, "bad CCD arguments");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
-  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  const int64_t n3 = (int64_t)PSTRIDE * sc->n_vert;
   double *xs, *ps, *x1s;
   EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
   EIPC_TRY(ensure_t(c, B_P, (size_t)n3 + 1, &ps));
@@ -403,7 +403,7 @@ eipc_status eipc_barrier_hvp(eipc_ctx *c, const eipc_scene *sc, const double *q,
     return set_err(c, EIPC_ERR_ARG, "bad HVP arguments");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
-  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  const int64_t n3 = (int64_t)PSTRIDE * sc->n_vert;
   double *xs, *xvs;
   EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
   EIPC_TRY(ensure_t(c, B_XV, (size_t)n3 + 1, &xvs));
@@ -412,7 +412,7 @@ eipc_status eipc_barrier_hvp(eipc_ctx *c, const eipc_scene *sc, const double *q,
   int32_t *act_pt, *typ_pt, *act_ee, *typ_ee;
   EIPC_TRY(narrow_both(c, sc, xs, pt, n_pt, ee, n_ee, dhat, &act_pt, &typ_pt, &act_ee, &typ_ee, s));
   EIPC_TRY(launch_zero(c, out, sizeof(double) * 3 * (size_t)sc->n_node, s));
-  if (out_off) EIPC_TRY(launch_zero(c, out_off, sizeof(double) * (size_t)n3, s));
+  if (out_off) EIPC_TRY(launch_zero(c, out_off, sizeof(double) * 3 * (size_t)sc->n_vert, s));
   EIPC_TRY(launch_hvp(c, sc, 0, xs, xvs, pt, act_pt, typ_pt, c->counters + 2, n_pt, dhat, kappa, flags, out, out_off,
                       s));
   EIPC_TRY(launch_hvp(c, sc, 1, xs, xvs, ee, act_ee, typ_ee, c->counters + 3, n_ee, dhat, kappa, flags, out, out_off,
@@ -432,7 +432,7 @@ eipc_status eipc_narrow_phase(eipc_ctx *c, const eipc_scene *sc, const double *q
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   double *xs;
-  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_X, (size_t)PSTRIDE * sc->n_vert + 1, &xs));
   EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
   EIPC_TRY(launch_zero(c, c->counters + 2, 2 * sizeof(int64_t), s));
   EIPC_TRY(launch_narrow(c, sc, 0, xs, pt, n_pt, dhat, act_pt, type_pt, c->counters + 2, s));
@@ -455,7 +455,7 @@ eipc_status eipc_pair_eval(eipc_ctx *c, const eipc_scene *sc, const double *q, i
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   double *xs;
-  EIPC_TRY(ensure_t(c, B_X, (size_t)3 * sc->n_vert + 1, &xs));
+  EIPC_TRY(ensure_t(c, B_X, (size_t)PSTRIDE * sc->n_vert + 1, &xs));
   EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
   return launch_pair_eval(c, sc, kind, xs, pairs, n, dhat, kappa, flags, type, sq, e, g, H, s);
 }
@@ -468,7 +468,7 @@ eipc_status eipc_ccd_candidates(eipc_ctx *c, const eipc_scene *sc, const double 
   if (!n_pt || !n_ee || (sc->n_node > 0 && (!q || !dq))) return set_err(c, EIPC_ERR_ARG, "bad CCD arguments");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
-  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  const int64_t n3 = (int64_t)PSTRIDE * sc->n_vert;
   double *xs, *ps, *x1s;
   EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
   EIPC_TRY(ensure_t(c, B_P, (size_t)n3 + 1, &ps));
@@ -496,7 +496,7 @@ eipc_status eipc_ccd_toi(eipc_ctx *c, const eipc_scene *sc, const double *q, con
     return set_err(c, EIPC_ERR_ARG, "bad CCD arguments");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
-  const int64_t n3 = 3 * (int64_t)sc->n_vert;
+  const int64_t n3 = (int64_t)PSTRIDE * sc->n_vert;
   double *xs, *ps;
   EIPC_TRY(ensure_t(c, B_X, (size_t)n3 + 1, &xs));
   EIPC_TRY(ensure_t(c, B_P, (size_t)n3 + 1, &ps));
@@ -580,7 +580,7 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     return set_err(c, EIPC_ERR_ARG, "the plan has no Hessian capacity");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
-  const int64_t n3v = 3 * (int64_t)sc->n_vert;
+  const int64_t n3v = (int64_t)PSTRIDE * sc->n_vert;
   int64_t *cn = c->counters;  // [2,3] active, [5,6] candidates, [7,8] swept candidates
   const BPPlan bp[4] = {{(uint32_t)plan->buckets[0], plan->ent[0], plan->cand_pt, plan->qent[0]},
                         {(uint32_t)plan->buckets[1], plan->ent[1], plan->cand_ee, plan->qent[1]},
@@ -665,7 +665,7 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
     return set_err(c, EIPC_ERR_ARG, "bad plan arguments");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
-  const int64_t n3v = 3 * (int64_t)sc->n_vert;
+  const int64_t n3v = (int64_t)PSTRIDE * sc->n_vert;
   auto grow = [margin](int64_t v) { return (int64_t)std::ceil(margin * (double)v) + 1024; };
   eipc_plan p{};
   // measure: unplanned broad phases (append mode, buffers grown to fit)

@@ -78,7 +78,9 @@ __device__ __forceinline__ void pair_vertices(const int32_t *pairs, int64_t k, c
 }
 
 __device__ __forceinline__ V3 load3(const double *xs, int n, int v) {
-  return V3{xs[v], xs[n + v], xs[2 * (int64_t)n + v]};
+  V3 r;
+  ld_pos(xs, v, r.x, r.y, r.z);
+  return r;
 }
 
 // global destination of a 3x3 block (I <= J)

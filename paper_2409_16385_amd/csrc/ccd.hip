@@ -22,9 +22,13 @@ __device__ __forceinline__ void agg_scene_min(unsigned long long *bits, bool val
     double m = ok ? t : INFINITY;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
-    if ((int)(threadIdx.x & 63) == first) atomicMin(&bits[s0], (unsigned long long)__double_as_longlong(m));
+    // the bound only decreases: skip the atomic when a plain read already
+    // holds a value no larger (a stale read only lets an atomic through)
+    const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+    if ((int)(threadIdx.x & 63) == first && mb < ((volatile unsigned long long *)bits)[s0]) atomicMin(&bits[s0], mb);
   } else if (ok) {
-    atomicMin(&bits[scene], (unsigned long long)__double_as_longlong(t));
+    const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
+    if (tb < ((volatile unsigned long long *)bits)[scene]) atomicMin(&bits[scene], tb);
   }
 }
 
@@ -59,8 +63,8 @@ __global__ __launch_bounds__(256) void k_ccd(int64_t cap, const int64_t *d_n, co
       V3 x[4], p[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        x[k] = V3{xs[vid[k]], xs[n_vert + vid[k]], xs[2 * (int64_t)n_vert + vid[k]]};
-        p[k] = V3{ps[vid[k]], ps[n_vert + vid[k]], ps[2 * (int64_t)n_vert + vid[k]]};
+        ld_pos(xs, vid[k], x[k].x, x[k].y, x[k].z);
+        ld_pos(ps, vid[k], p[k].x, p[k].y, p[k].z);
       }
       int64_t it = 0;
       t = accd<KIND>(x, p, sfac, t_max, max_iter, &it);
@@ -115,8 +119,8 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
       V3 x[4], p[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        x[q] = V3{xs[vid[q]], xs[n_vert + vid[q]], xs[2 * (int64_t)n_vert + vid[q]]};
-        p[q] = V3{ps[vid[q]], ps[n_vert + vid[q]], ps[2 * (int64_t)n_vert + vid[q]]};
+        ld_pos(xs, vid[q], x[q].x, x[q].y, x[q].z);
+        ld_pos(ps, vid[q], p[q].x, p[q].y, p[q].z);
       }
       AccdState st;
       decided = accd_init<KIND>(x, p, sfac, t_max, st);

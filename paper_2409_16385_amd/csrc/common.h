@@ -132,6 +132,16 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// Positions inside the library: one 32-byte record per vertex (x, y, z,
+// unused), so that gathering a vertex touches one cache line.
+constexpr int PSTRIDE = 4;
+__device__ __forceinline__ void ld_pos(const double *p, int v, double &x, double &y, double &z) {
+  const double2 a = *reinterpret_cast<const double2 *>(p + (int64_t)PSTRIDE * v);
+  x = a.x;
+  y = a.y;
+  z = p[(int64_t)PSTRIDE * v + 2];
+}
+
 inline int grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;
   return (int)(g < 1 ? 1 : g);

@@ -37,9 +37,9 @@ __global__ void k_embed(int n, const int32_t *__restrict__ rowptr, const int32_t
     a2 = a2 + off[3 * (int64_t)v + 2];
   }
   if (xs) {
-    xs[v] = a0;
-    xs[n + v] = a1;
-    xs[2 * (int64_t)n + v] = a2;
+    double2 *r = reinterpret_cast<double2 *>(xs + (int64_t)PSTRIDE * v);
+    r[0] = double2{a0, a1};
+    r[1] = double2{a2, 0.0};
   }
   if (x_aos) {
     x_aos[3 * (int64_t)v] = a0;
@@ -226,15 +226,14 @@ __device__ __forceinline__ void prim_box(const int *vid, const double *xs, const
 #pragma clang fp contract(off)
 #pragma unroll
   for (int cax = 0; cax < 3; ++cax) {
-    const double *xc = xs + (int64_t)cax * n_vert;
-    double mn = xc[vid[0]], mx = mn;
+    double mn = xs[(int64_t)PSTRIDE * vid[0] + cax], mx = mn;
 #pragma unroll
     for (int a = 0; a < NV; ++a) {
-      double v = xc[vid[a]];
+      double v = xs[(int64_t)PSTRIDE * vid[a] + cax];
       mn = fmin(mn, v);
       mx = fmax(mx, v);
       if (x1s) {
-        double w = x1s[(int64_t)cax * n_vert + vid[a]];
+        double w = x1s[(int64_t)PSTRIDE * vid[a] + cax];
         mn = fmin(mn, w);
         mx = fmax(mx, w);
       }
@@ -1230,7 +1229,7 @@ __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restr
       pair_vids<KIND>(pairs, i, faces, edges, vid);
       V3 x[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) x[a] = V3{xs[vid[a]], xs[n_vert + vid[a]], xs[2 * (int64_t)n_vert + vid[a]]};
+      for (int a = 0; a < 4; ++a) ld_pos(xs, vid[a], x[a].x, x[a].y, x[a].z);
       const bool cand = !FILTER || static_boxes_overlap<KIND>(x, h);
       if (cand) {
         ++n_cand;
