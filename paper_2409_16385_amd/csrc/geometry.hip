@@ -569,6 +569,30 @@ __device__ __forceinline__ void stage_pair(int2 *buf, int &nb, int q, int it, un
   }
 }
 
+// Flush every lane's staged pairs with one atomic for the wavefront (all
+// lanes of the wavefront must call).
+__device__ __forceinline__ void wave_flush(int2 *buf, int &nbuf, unsigned long long *total, int32_t *out,
+                                           int64_t cap) {
+  const int lane = threadIdx.x & 63;
+  int64_t ex = nbuf;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t yv = __shfl_up(ex, o, 64);
+    if (lane >= o) ex += yv;
+  }
+  const int64_t wsum = __shfl(ex, 63, 64);
+  int64_t p0 = 0;
+  if (lane == 63 && wsum) p0 = (int64_t)atomicAdd(total, (unsigned long long)wsum);
+  p0 = __shfl(p0, 63, 64);
+  const int64_t p = p0 + ex - nbuf;
+  for (int j = 0; j < nbuf; ++j)
+    if (p + j < cap) {
+      out[2 * (p + j)] = buf[j].x;
+      out[2 * (p + j) + 1] = buf[j].y;
+    }
+  nbuf = 0;
+}
+
 struct QueryArgs {
   const GridDev *g;
   uint32_t bmask;
@@ -675,26 +699,7 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
       ++k;
     }
   }
-  if (MODE == 2) {
-    // flush what is left: one atomic per wavefront
-    int64_t ex = nbuf;
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      int64_t y = __shfl_up(ex, o, 64);
-      if (lane >= o) ex += y;
-    }
-    const int64_t wsum = __shfl(ex, 63, 64);
-    int64_t p0 = 0;
-    if (lane == 63 && wsum) p0 = (int64_t)atomicAdd(total, (unsigned long long)wsum);
-    p0 = __shfl(p0, 63, 64);
-    const int64_t p = p0 + ex - nbuf;
-    for (int j = 0; j < nbuf; ++j)
-      if (p + j < cap) {
-        out[2 * (p + j)] = buf[j].x;
-        out[2 * (p + j) + 1] = buf[j].y;
-      }
-  }
+  if (MODE == 2) wave_flush(buf, nbuf, total, out, cap);
   if (MODE == 0 && live) cnt[q] = (int32_t)k;
   if (MODE == 1 && live) {
     if (base + k > cap) {
@@ -827,25 +832,9 @@ __global__ __launch_bounds__(QT) void k_query_ent(const int64_t *__restrict__ n_
         }
       }
     }
+    if (__any(nbuf >= APPEND_BUF / 2)) wave_flush(buf, nbuf, total, out, cap);
   }
-  // flush what is left: one atomic per wavefront
-  int64_t ex = nbuf;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int64_t yv = __shfl_up(ex, o, 64);
-    if (lane >= o) ex += yv;
-  }
-  const int64_t wsum = __shfl(ex, 63, 64);
-  int64_t p0 = 0;
-  if (lane == 63 && wsum) p0 = (int64_t)atomicAdd(total, (unsigned long long)wsum);
-  p0 = __shfl(p0, 63, 64);
-  const int64_t p = p0 + ex - nbuf;
-  for (int j = 0; j < nbuf; ++j)
-    if (p + j < cap) {
-      out[2 * (p + j)] = buf[j].x;
-      out[2 * (p + j) + 1] = buf[j].y;
-    }
+  wave_flush(buf, nbuf, total, out, cap);
 }
 
 // Wavefront per (query, cell): the 64 lanes read 64 consecutive entries of
@@ -879,45 +868,110 @@ __global__ __launch_bounds__(QT) void k_query_wave(const int64_t *__restrict__ n
     const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
     const int64_t e0 = qa_.bstart[b];
     const int64_t e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
-    for (int64_t e = e0 + lane; e < e1; e += 64) {
-      const Entry en = qa_.ent[e];
-      const int it = en.item;
-      // report only in the cell holding the lower corner of the overlap
-      const int ix = x - (en.dlo & 63), iy = y - ((en.dlo >> 6) & 63), iz = z - ((en.dlo >> 12) & 63);
-      if (en.cell != qe.cell || (KIND == 1 && it <= q) || (ix > qx ? ix : qx) != x || (iy > qy ? iy : qy) != y ||
-          (iz > qz ? iz : qz) != z)
-        continue;
-      const ItemRec r = items[it];
-      if (pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r)) stage_pair(buf, nbuf, q, it, total, out, cap);
+    for (int64_t base = e0; base < e1; base += 64) {
+      const int64_t e = base + lane;
+      if (e < e1) {
+        const Entry en = qa_.ent[e];
+        const int it = en.item;
+        // report only in the cell holding the lower corner of the overlap
+        const int ix = x - (en.dlo & 63), iy = y - ((en.dlo >> 6) & 63), iz = z - ((en.dlo >> 12) & 63);
+        if (en.cell == qe.cell && (KIND == 0 || it > q) && (ix > qx ? ix : qx) == x && (iy > qy ? iy : qy) == y &&
+            (iz > qz ? iz : qz) == z) {
+          const ItemRec r = items[it];
+          if (pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r)) buf[nbuf++] = make_int2(q, it);
+        }
+      }
+      if (__any(nbuf >= APPEND_BUF - 1)) wave_flush(buf, nbuf, total, out, cap);
     }
     if (qe.dlo == 0) {
       // the query's lower cell also runs the items too large to hash
       const int nl = (int)*qa_.n_large;
-      for (int j = lane; j < nl; j += 64) {
-        const int it = qa_.large[j];
-        const ItemRec r = items[it];
-        if ((r.tag >> 1) != qsc) continue;
-        if (pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r)) stage_pair(buf, nbuf, q, it, total, out, cap);
+      for (int jb = 0; jb < nl; jb += 64) {
+        const int j = jb + lane;
+        if (j < nl) {
+          const int it = qa_.large[j];
+          const ItemRec r = items[it];
+          if ((r.tag >> 1) == qsc && pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r))
+            buf[nbuf++] = make_int2(q, it);
+        }
+        if (__any(nbuf >= APPEND_BUF - 1)) wave_flush(buf, nbuf, total, out, cap);
       }
     }
   }
-  // flush what is left: one atomic per wavefront
-  int64_t ex = nbuf;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int64_t yv = __shfl_up(ex, o, 64);
-    if (lane >= o) ex += yv;
+  wave_flush(buf, nbuf, total, out, cap);
+}
+
+// Per-query append (work split 0) as rounds: in each round every lane
+// advances its own query by one group of up to four hash entries (or four
+// large items), so wavefront-uniform points come often enough to flush
+// all lanes' staged pairs with one atomic per wavefront.  Visits the same
+// cells, entries and large items in the same order as k_query.
+template <int KIND>
+__global__ __launch_bounds__(QT) void k_query_sm(int nq, const double *__restrict__ xs,
+                                                 const double *__restrict__ x1s, int n_vert, double h, QueryArgs qa_,
+                                                 int32_t *__restrict__ out, int64_t cap, unsigned long long *total) {
+  __shared__ int2 s_buf[QT * APPEND_BUF];
+  int2 *buf = s_buf + threadIdx.x * APPEND_BUF;
+  int nbuf = 0;
+  const ItemRec *items = qa_.items;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = qa_.qlist ? (t < *qa_.n_qlist ? qa_.qlist[t] : -1) : t;
+  const bool live = q >= 0 && q < nq;
+  int qa = 0, qb = -1, qsc = 0;
+  bool qdof = false;
+  double qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+  int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+  if (live) {
+    query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
+    cell_range(*qa_.g, qlo, qhi, c0, c1);
   }
-  const int64_t wsum = __shfl(ex, 63, 64);
-  int64_t p0 = 0;
-  if (lane == 63 && wsum) p0 = (int64_t)atomicAdd(total, (unsigned long long)wsum);
-  p0 = __shfl(p0, 63, 64);
-  const int64_t p = p0 + ex - nbuf;
-  for (int j = 0; j < nbuf; ++j)
-    if (p + j < cap) {
-      out[2 * (p + j)] = buf[j].x;
-      out[2 * (p + j) + 1] = buf[j].y;
+  const int nl = (int)*qa_.n_large;
+  int x = c0[0], y = c0[1], z = c0[2];
+  int64_t e = 0, e1 = 0;
+  uint64_t key = 0;
+  int lj = 0;
+  int phase = live ? 0 : 3;  // 0 open cell, 1 scan its bucket, 2 large items, 3 done
+  auto emit = [&](int it) { buf[nbuf++] = make_int2(q, it); };
+  while (__any(phase != 3)) {
+    if (phase == 0) {
+      key = cell_key(x, y, z, qsc);
+      const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
+      e = qa_.bstart[b];
+      e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
+      phase = 1;
     }
+    if (phase == 1) {
+      if (e < e1) {
+        const int64_t eg = e + 4 < e1 ? e + 4 : e1;
+        scan_bucket<KIND>(qa_.ent, items, e, eg, key, x, y, z, c0[0], c0[1], c0[2], q, qa, qb, qdof, qlo, qhi, emit);
+        e = eg;
+      }
+      if (e >= e1) {
+        if (++x > c1[0]) {
+          x = c0[0];
+          if (++y > c1[1]) {
+            y = c0[1];
+            if (++z > c1[2]) phase = 2;
+          }
+        }
+        if (phase == 1) phase = 0;
+      }
+    } else if (phase == 2) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = lj + u;
+        if (j < nl) {
+          const int it = qa_.large[j];
+          const ItemRec r = items[it];
+          if ((r.tag >> 1) == qsc && pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r)) emit(it);
+        }
+      }
+      lj += 4;
+      if (lj >= nl) phase = 3;
+    }
+    if (__any(nbuf > APPEND_BUF - 4)) wave_flush(buf, nbuf, total, out, cap);
+  }
+  wave_flush(buf, nbuf, total, out, cap);
 }
 
 // Scratch of one broad phase (kind, swept) kept in the context's buffers.
@@ -1064,9 +1118,9 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
         const int ge = (int)std::min<int64_t>(grid_for(qent_cap, QT), 64 * (int64_t)c->num_cu);
         if (!cellpar) {
           if (kind == 0)
-            launch_query<0, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
+            k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qa, out, capa, b.total);
           else
-            launch_query<1, 2>(nq, xs, x1s, n_vert, h, qa, nullptr, nullptr, out, capa, b.total, c->status, s);
+            k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qa, out, capa, b.total);
         } else if (c->query_mode[kind] == 2) {
           const int gw = (int)std::min<int64_t>(grid_for(qent_cap * 64, QT), 32 * (int64_t)c->num_cu);
           if (kind == 0)
@@ -1077,9 +1131,9 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
                                               b.total);
           EIPC_HIP(c, hipGetLastError());
           if (kind == 0)
-            launch_query<0, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
+            k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
           else
-            launch_query<1, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
+            k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
         } else {
         if (kind == 0)
           k_query_ent<0><<<ge, QT, 0, s>>>(b.qoff + nq, qent_cap, b.qent, xs, x1s, n_vert, h, qa, out, capa,
@@ -1089,9 +1143,9 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
                                            b.total);
         EIPC_HIP(c, hipGetLastError());
         if (kind == 0)
-          launch_query<0, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
+          k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
         else
-          launch_query<1, 2>(nq, xs, x1s, n_vert, h, qlq, nullptr, nullptr, out, capa, b.total, c->status, s);
+          k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
         }
       }
       EIPC_HIP(c, hipGetLastError());
