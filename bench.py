@@ -60,6 +60,7 @@ def _args():
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--no-graph", action="store_true", help="time eager planned steps instead of graph replays")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the per-call entry points")
     ap.add_argument("--tuning", default=None,
                     help="fixed tuning 'cell_scale,wg_terms,wg_expand,wg_narrow,wg_ccd,query_cells' "
                          "(skips the autotuner)")
@@ -385,7 +386,7 @@ def main():
         out["sequential_scenes_per_s"] = hb.n_scene / t_seq
         out["sequential_pairs_per_s"] = n_active / t_seq
         out["batch_speedup"] = (t_seq * 1e3) / ms_per_step
-    else:
+    elif not a.no_plain:
         sc = scenes_list[0]
         out["config"] = {"workload": f"{a.config} ({sc.name}): n_vert={sc.n_vert} n_face={sc.n_face} "
                                      f"n_edge={sc.n_edge} n_node={sc.n_node} dhat={sc.dhat:g}",
@@ -404,6 +405,12 @@ def main():
         out["plain_calls_ms_per_step"] = sum(ev.values())
         out["barrier_reduce_pairs_per_s"] = n_active / (ev["barrier_reduce"] / 1e3)
         out["ccd_pairs_per_s"] = swept / (ev["ccd"] / 1e3)
+    if "config" not in out:
+        sc = scenes_list[0]
+        out["config"] = {"workload": f"{a.config} ({sc.name}): n_vert={sc.n_vert} n_face={sc.n_face} "
+                                     f"n_edge={sc.n_edge} n_node={sc.n_node} dhat={sc.dhat:g}",
+                         "active_pairs": n_active, "candidates": cnt["cand_pt"] + cnt["cand_ee"],
+                         "ccd_candidates": swept, "seed": a.seed}
     out["timed"] = "graph replay of the planned step" if use_graph else "eager planned step"
     out["alpha_min"] = float(bt.out.alpha.min().item())
     out["tuning"] = None if tuning is None else {"cell_scale": tuning["cell_scale"],
