@@ -142,6 +142,21 @@ __device__ __forceinline__ void ld_pos(const double *p, int v, double &x, double
   z = p[(int64_t)PSTRIDE * v + 2];
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
+// b % 8), each XCD with its own L2.  This maps the physical workgroup to a
+// logical one so that each XCD takes runs of `chunk` consecutive logical
+// workgroups (XCD k takes runs k, k + 8, ...): neighbouring work in a
+// spatially ordered list then shares one L2, while the runs spread the
+// load over the XCDs.  A bijection on [0, gridDim.x) (the tail that does
+// not fill 8 runs keeps the identity).
+__device__ __forceinline__ int xcd_block(int chunk) {
+  const int b = blockIdx.x;
+  const int full = gridDim.x / (8 * chunk) * (8 * chunk);
+  if (b >= full) return b;
+  const int k = b & 7, j = b >> 3;
+  return ((j / chunk) * 8 + k) * chunk + j % chunk;
+}
+
 inline int grid_for(int64_t n, int threads) {
   int64_t g = (n + threads - 1) / threads;
   return (int)(g < 1 ? 1 : g);

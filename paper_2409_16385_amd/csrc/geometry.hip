@@ -551,6 +551,7 @@ __device__ __forceinline__ void scan_bucket(const Entry *__restrict__ ent, const
 }
 
 constexpr int QT = 128;         // query threads per block
+constexpr int XCD_CHUNK = 16;   // consecutive query workgroups kept on one XCD
 constexpr int APPEND_BUF = 16;  // per-thread LDS staging for append mode
 
 // append mode: stage a candidate in the thread's LDS slots; flush a full
@@ -914,7 +915,7 @@ __global__ __launch_bounds__(QT) void k_query_sm(int nq, const double *__restric
   int2 *buf = s_buf + threadIdx.x * APPEND_BUF;
   int nbuf = 0;
   const ItemRec *items = qa_.items;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block(XCD_CHUNK) * blockDim.x + threadIdx.x;
   const int q = qa_.qlist ? (t < *qa_.n_qlist ? qa_.qlist[t] : -1) : t;
   const bool live = q >= 0 && q < nq;
   int qa = 0, qb = -1, qsc = 0;
