@@ -238,8 +238,9 @@ eipc_status eipc_contact_step(eipc_ctx *ctx, const eipc_scene *sc, const eipc_pl
  * array may be NULL); and how the unsorted (planned-step and step-bound)
  * broad phases split their work, query_cells = mode_PT + 4 * mode_EE with
  * mode 0 = one thread per query, 1 = one thread per (query, cell of its
- * box), 2 = one wavefront per (query, cell) (-1 keeps the current choice;
- * default 1, i.e. PT mode 1 and EE mode 0).  Used by the batch autotuner;
+ * box), 2 = one wavefront per (query, cell), 3 = bucket join (the queries
+ * hashed like the items, each bucket's pairs tested from LDS) (-1 keeps
+ * the current choice; default 1, i.e. PT mode 1 and EE mode 0).  Used by the batch autotuner;
  * results do not depend on them except for the order of unsorted
  * candidate lists and the rounding order of sums.  A plan must be made
  * again after changing them. */

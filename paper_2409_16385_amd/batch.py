@@ -196,7 +196,7 @@ class Batch:
         ev1.synchronize()
         return ev0.elapsed_time(ev1) / reps
 
-    def autotune(self, cell_scales=(1.5, 2.0, 3.0, 4.0), query_modes=(0, 1, 5, 9, 10), wg_values=(1, 2, 4, 8, 16),
+    def autotune(self, cell_scales=(2.0, 3.0, 4.0, 6.0), query_modes=(0, 5, 12, 15), wg_values=(1, 2, 4, 8, 16),
                  reps: int = 3, margin: float = 1.5, verbose: bool = False) -> dict:
         """Pick the broad-phase cell scale and work split per query kind
         (whole-step time, re-planning for each pair of values), then for

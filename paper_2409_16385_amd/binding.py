@@ -445,7 +445,7 @@ def set_tuning(ctx: Context, cell_scale: float, wg_per_cu=(0, 0, 0, 0), query_ce
     (pair terms, expansion, narrow phase, CCD; 0 keeps a value) and the
     unsorted broad phase's work split, mode_PT + 4 * mode_EE with modes 0
     (thread per query), 1 (thread per query cell), 2 (wavefront per query
-    cell); -1 keeps it."""
+    cell), 3 (bucket join); -1 keeps it."""
     w = (_I32 * 4)(*[int(v) for v in wg_per_cu])
     ctx.check(_load().eipc_set_tuning(ctx.handle, float(cell_scale), w, int(query_cells)))
 

@@ -515,8 +515,8 @@ eipc_status eipc_fp64_selftest(eipc_ctx *c, const double *a, const double *b, do
 
 eipc_status eipc_set_tuning(eipc_ctx *c, double cell_scale, const int32_t wg_per_cu[4], int32_t query_cells) {
   if (!c) return EIPC_ERR_ARG;
-  if (query_cells < -1 || query_cells > 10 || (query_cells >= 0 && ((query_cells & 3) == 3 || (query_cells >> 2) == 3)))
-    return set_err(c, EIPC_ERR_ARG, "query_cells must be -1 or mode_pt + 4 * mode_ee with modes in [0, 2]");
+  if (query_cells < -1 || query_cells > 15)
+    return set_err(c, EIPC_ERR_ARG, "query_cells must be -1 or mode_pt + 4 * mode_ee with modes in [0, 3]");
   if (!(cell_scale > 0.0) || !std::isfinite(cell_scale)) return set_err(c, EIPC_ERR_ARG, "cell_scale must be > 0");
   if (wg_per_cu)
     for (int k = 0; k < 4; ++k)

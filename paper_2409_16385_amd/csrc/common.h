@@ -41,9 +41,9 @@ enum BufId {
   B_SKEY, B_SHIST, B_SFILL, B_SSTART, B_SACT, B_STYP,  // locality sort of active pairs
   B_CCD_LONG_PT, B_CCD_LONG_EE,                        // CCD pairs deferred to the second pass
   B_BP0,                               // broad-phase scratch: 4 slots (kind, swept) x BP_NBUF
-  B_NUM = B_BP0 + 4 * 13
+  B_NUM = B_BP0 + 4 * 17
 };
-constexpr int BP_NBUF = 13;
+constexpr int BP_NBUF = 17;
 
 // capacities of one broad phase in a planned (synchronization-free) call
 struct BPPlan {

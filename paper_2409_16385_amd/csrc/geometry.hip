@@ -356,6 +356,7 @@ struct GridDev {
 };
 
 constexpr int MAX_ITEM_CELLS = 64;
+constexpr int BIG_CELLS = 4096;
 constexpr int GRID_AXIS_MAX = 1 << 16;
 
 // cell edge: cell_scale times the mean item box extent (largest axis of the
@@ -421,20 +422,61 @@ __device__ __forceinline__ void cell_range(const GridDev &g, const double *lo, c
   }
 }
 
+// Items covering up to MAX_ITEM_CELLS cells are hashed one thread per
+// item; larger ones with at most 64 cells per axis (the reach of the 6-bit
+// offsets of an entry) and at most BIG_CELLS cells are hashed one wavefront
+// per item (the big list, n_big = {items, cells}); the rest (the large
+// list) are tested against every query instead.
 __global__ void k_item_cells(int n, const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, int32_t *cnt,
-                             int32_t *large, int64_t *n_large) {
+                             int32_t *large, int64_t *n_large, int32_t *big, int64_t *n_big) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const GridDev g = *gp;
   int c0[3], c1[3];
   cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
-  int64_t nc = (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
-  if (nc > MAX_ITEM_CELLS) {
-    int slot = (int)atomicAdd((unsigned long long *)n_large, 1ull);
-    large[slot] = i;
-    cnt[i] = 0;
-  } else {
+  const int sx = c1[0] - c0[0] + 1, sy = c1[1] - c0[1] + 1, sz = c1[2] - c0[2] + 1;
+  const int64_t nc = (int64_t)sx * sy * sz;
+  if (nc <= MAX_ITEM_CELLS) {
     cnt[i] = (int32_t)nc;
+    return;
+  }
+  cnt[i] = 0;
+  if (sx <= 64 && sy <= 64 && sz <= 64 && nc <= BIG_CELLS) {
+    const int slot = (int)atomicAdd((unsigned long long *)&n_big[0], 1ull);
+    big[slot] = i;
+    atomicAdd((unsigned long long *)&n_big[1], (unsigned long long)nc);
+  } else {
+    const int slot = (int)atomicAdd((unsigned long long *)n_large, 1ull);
+    large[slot] = i;
+  }
+}
+
+// the cells of a big item, one lane per cell
+__device__ __forceinline__ void big_cell(const int *c0, const int *c1, int c, int &x, int &y, int &z) {
+  const int sx = c1[0] - c0[0] + 1, sy = c1[1] - c0[1] + 1;
+  x = c0[0] + c % sx;
+  y = c0[1] + (c / sx) % sy;
+  z = c0[2] + c / (sx * sy);
+}
+
+__global__ void k_big_hist(const int32_t *__restrict__ big, const int64_t *__restrict__ n_big,
+                           const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, uint32_t bmask,
+                           int32_t *bcnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nbig = n_big[0];
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nbig; w += nw) {
+    const int i = big[w];
+    const GridDev g = *gp;
+    const int sc = rec[i].tag >> 1;
+    int c0[3], c1[3];
+    cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
+    const int nc = (c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+    for (int c = lane; c < nc; c += 64) {
+      int x, y, z;
+      big_cell(c0, c1, c, x, y, z);
+      atomicAdd(&bcnt[cell_hash(x, y, z, sc) & bmask], 1);
+    }
   }
 }
 
@@ -491,6 +533,41 @@ __global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, const GridDe
           atomicOr(status, ST_PLAN_OVERFLOW);
       }
 }
+
+__global__ void k_big_fill(const int32_t *__restrict__ big, const int64_t *__restrict__ n_big,
+                           const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, uint32_t bmask,
+                           const int64_t *bstart, int32_t *bfill, Entry *ent, int64_t ent_cap, uint32_t *status) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nbig = n_big[0];
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nbig; w += nw) {
+    const int i = big[w];
+    const GridDev g = *gp;
+    const int sc = rec[i].tag >> 1;
+    int c0[3], c1[3];
+    cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
+    const int nc = (c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+    for (int c = lane; c < nc; c += 64) {
+      int x, y, z;
+      big_cell(c0, c1, c, x, y, z);
+      const uint32_t b = cell_hash(x, y, z, sc) & bmask;
+      const int64_t slot = bstart[b] + atomicAdd(&bfill[b], 1);
+      if (slot < ent_cap) {
+        Entry en;
+        en.cell = cell_key(x, y, z, sc);
+        en.item = i;
+        en.dlo = (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12);
+        ent[slot] = en;
+      } else {
+        atomicOr(status, ST_PLAN_OVERFLOW);
+      }
+    }
+  }
+}
+
+// The hash of n records (count, histogram, scan, fill), small items one
+// thread each and big items one wavefront each.
+constexpr int BIG_BLOCKS = 256;
 
 __device__ __forceinline__ bool overlap(const double *qlo, const double *qhi, const ItemRec &r) {
 #pragma unroll
@@ -902,6 +979,32 @@ __global__ __launch_bounds__(QT) void k_query_wave(const int64_t *__restrict__ n
   wave_flush(buf, nbuf, total, out, cap);
 }
 
+// Wavefront-level candidate staging: every lane of the wavefront calls
+// push (ok false where it has nothing); positions come from the ballot, so
+// the count stays the same on every lane and needs no atomics.  A flush
+// reserves the whole staged run with one global atomic and writes it with
+// consecutive lanes on consecutive pairs.
+__device__ __forceinline__ void wave_push(bool ok, int2 pr, int2 *wout, int &wcnt) {
+  const unsigned long long m = __ballot(ok);
+  const int lane = threadIdx.x & 63;
+  if (ok) wout[wcnt + __popcll(m & ((1ull << lane) - 1ull))] = pr;
+  wcnt += __popcll(m);
+}
+__device__ __forceinline__ void wave_out_flush(int2 *wout, int &wcnt, unsigned long long *total,
+                                               int32_t *out, int64_t cap) {
+  if (wcnt == 0) return;
+  __builtin_amdgcn_wave_barrier();
+  const int lane = threadIdx.x & 63;
+  int64_t p0 = 0;
+  if (lane == 0) p0 = (int64_t)atomicAdd(total, (unsigned long long)wcnt);
+  p0 = __shfl(p0, 0, 64);
+  int2 *o2 = reinterpret_cast<int2 *>(out);
+  for (int k = lane; k < wcnt; k += 64)
+    if (p0 + k < cap) o2[p0 + k] = wout[k];
+  __builtin_amdgcn_wave_barrier();
+  wcnt = 0;
+}
+
 // Per-query append (work split 0) as rounds: in each round every lane
 // advances its own query by one group of up to four hash entries (or four
 // large items), so wavefront-uniform points come often enough to flush
@@ -975,6 +1078,201 @@ __global__ __launch_bounds__(QT) void k_query_sm(int nq, const double *__restric
   wave_flush(buf, nbuf, total, out, cap);
 }
 
+// ---------------------------------------------------------------------------
+// Bucket join (work split 3).  The queries are hashed like the items (PT:
+// vertex records in a second hash over the same grid and buckets; EE: the
+// edge hash itself), so every (query, item) pair that shares a cell lies in
+// one bucket of both hashes.  A workgroup takes JT consecutive query
+// entries (rows, in bucket order); the item entries of the buckets those
+// rows touch form one contiguous window of the item hash, staged in LDS in
+// chunks of JWIN entries together with their records.  Each row then tests
+// the items of its own bucket from LDS: same cell, lower-corner rule
+// (min of the two offsets from the lower cells is zero on every axis),
+// adjacency and DoF rule, exact box overlap.  EE joins the edge hash with
+// itself: row i pairs only with the entries after it in its bucket and
+// reports (min, max).  The row that is a query's lower cell also runs the
+// items too large to hash, as in the per-query splits; queries too large
+// to hash run per query (k_query_sm on a list).
+// ---------------------------------------------------------------------------
+constexpr int JT = 128;     // rows per workgroup
+constexpr int JWIN = 384;   // item entries staged in LDS per chunk
+constexpr int JOUT = 1024;  // candidates staged per wavefront
+
+struct JoinArgs {
+  const Entry *rows;        // query entries in bucket order
+  const int64_t *n_rows;    // number written (device), clamped to row_cap
+  int64_t row_cap;
+  const ItemRec *qrec;      // query records (PT: vertex records; EE: items)
+  const int64_t *pbstart;   // item-hash bucket offsets (nb + 1)
+  const Entry *pent;        // item entries
+  int64_t pent_cap;
+  const ItemRec *items;
+  const int32_t *large;
+  const int64_t *n_large;
+  uint32_t bmask;
+};
+
+__device__ __forceinline__ uint32_t key_bucket(uint64_t key, uint32_t bmask) {
+  return cell_hash((int)(key & 0xffff), (int)((key >> 16) & 0xffff), (int)((key >> 32) & 0xffff), (int)(key >> 48)) &
+         bmask;
+}
+
+// lower-corner rule from the two offsets (cell minus lower cell, 6 bits per
+// axis): the smaller offset is zero on every axis
+__device__ __forceinline__ int zero_axes(int d) {
+  return (int)((d & 63) == 0) | ((int)((d & (63 << 6)) == 0) << 1) | ((int)((d & (63 << 12)) == 0) << 2);
+}
+
+// adjacency, DoF rule and exact box overlap of a (query, item) pair, with
+// bitwise logic so that no part of it branches
+template <int KIND>
+__device__ __forceinline__ bool join_test(const ItemRec &r, int qa, int qb, bool qdof, const double *qlo,
+                                          const double *qhi) {
+  bool ok = (qa != r.v[0]) & (qa != r.v[1]);
+  if (KIND == 0)
+    ok &= qa != r.v[2];
+  else
+    ok &= (qb != r.v[0]) & (qb != r.v[1]);
+  ok &= qdof | ((r.tag & 1) != 0);
+  ok &= (qlo[0] <= r.hi[0]) & (r.lo[0] <= qhi[0]) & (qlo[1] <= r.hi[1]) & (r.lo[1] <= qhi[1]) &
+        (qlo[2] <= r.hi[2]) & (r.lo[2] <= qhi[2]);
+  return ok;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ out, int64_t cap,
+                                             unsigned long long *total) {
+  __shared__ Entry s_ent[JWIN];
+  __shared__ ItemRec s_rec[JWIN];
+  __shared__ int2 s_out[JT / 64][JOUT];
+  __shared__ int64_t s_win[2];
+  int2 *wout = s_out[threadIdx.x >> 6];
+  int wcnt = 0;
+  const int64_t nr0 = *ja.n_rows;
+  const int64_t n_rows = nr0 < ja.row_cap ? nr0 : ja.row_cap;
+  const int64_t r0 = (int64_t)blockIdx.x * JT;
+  if (r0 >= n_rows) return;  // uniform over the workgroup
+  const int64_t r1 = r0 + JT < n_rows ? r0 + JT : n_rows;
+  const int64_t i = r0 + threadIdx.x;
+  const bool live = i < r1;
+  // the row: its entry, bucket, record and partner range
+  Entry re{0, 0, 0};
+  int64_t p0 = 0, p1 = 0;
+  double qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+  int qa = 0, qb = -1, qsc = 0;
+  bool qdof = false;
+  if (live) {
+    re = ja.rows[i];
+    const uint32_t b = key_bucket(re.cell, ja.bmask);
+    const int64_t e1 = ja.pbstart[b + 1];
+    p1 = e1 < ja.pent_cap ? e1 : ja.pent_cap;
+    p0 = KIND == 1 ? i + 1 : ja.pbstart[b];
+    const ItemRec qr = ja.qrec[re.item];
+    qa = qr.v[0];
+    qb = qr.v[1];
+    qdof = qr.tag & 1;
+    qsc = qr.tag >> 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      qlo[a] = qr.lo[a];
+      qhi[a] = qr.hi[a];
+    }
+  }
+  // window of item entries for the whole tile: first row's range start to
+  // last row's range end (rows are in bucket order)
+  const int rz = zero_axes(re.dlo);
+  if (threadIdx.x == 0) s_win[0] = p0;
+  if (i == r1 - 1) s_win[1] = p1;
+  __syncthreads();
+  const int64_t w0 = s_win[0], w1 = s_win[1];
+  for (int64_t c0 = w0; c0 < w1; c0 += JWIN) {
+    const int nw = (int)(w1 - c0 < JWIN ? w1 - c0 : JWIN);
+    __syncthreads();  // previous chunk consumed
+    {
+      constexpr int U = (JWIN + JT - 1) / JT;
+      Entry e[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = u * JT + threadIdx.x;
+        if (k < nw) e[u] = ja.pent[c0 + k];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = u * JT + threadIdx.x;
+        if (k < nw) {
+          s_ent[k] = e[u];
+          s_rec[k] = ja.items[e[u].item];
+        }
+      }
+    }
+    __syncthreads();
+    int64_t j = p0 > c0 ? p0 : c0;
+    const int64_t je = p1 < c0 + nw ? p1 : c0 + nw;
+    while (__any(j < je)) {
+      // four partners per lane: entries first (one wait), then the
+      // records of those in the same cell under the lower-corner rule
+      Entry pe[4];
+      bool pass[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool in = j + u < je;
+        pe[u] = s_ent[in ? (int)(j + u - c0) : 0];
+        pass[u] = in & (pe[u].cell == re.cell) & ((rz | zero_axes(pe[u].dlo)) == 7);
+      }
+      ItemRec r[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (pass[u]) r[u] = s_rec[(int)(j + u - c0)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = pass[u] && join_test<KIND>(r[u], qa, qb, qdof, qlo, qhi);
+        const int it = pe[u].item;
+        const int2 pr = (KIND == 0 || re.item < it) ? make_int2(re.item, it) : make_int2(it, re.item);
+        wave_push(ok, pr, wout, wcnt);
+      }
+      j += 4;
+      if (wcnt > JOUT - 4 * 64) wave_out_flush(wout, wcnt, total, out, cap);
+    }
+  }
+  // the query's lower-cell row also runs the items too large to hash
+  const int nl = (int)*ja.n_large;
+  if (nl > 0) {
+    const bool lower = live && re.dlo == 0;
+    const int q = re.item;
+    for (int jb = 0; __any(lower && jb < nl); jb += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = jb + u;
+        bool ok = false;
+        int it = 0;
+        if (lower && jj < nl) {
+          it = ja.large[jj];
+          const ItemRec r = ja.items[it];
+          ok = (r.tag >> 1) == qsc && pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r);
+        }
+        wave_push(ok, make_int2(q, it), wout, wcnt);
+      }
+      if (wcnt > JOUT - 4 * 64) wave_out_flush(wout, wcnt, total, out, cap);
+    }
+  }
+  wave_out_flush(wout, wcnt, total, out, cap);
+}
+
+// vertex records for the PT query hash (box of the point, swept when x1s)
+__global__ void k_vert_items(int n, const double *__restrict__ xs, const double *__restrict__ x1s, int n_vert,
+                             double h, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ vscene,
+                             ItemRec *__restrict__ rec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ItemRec r;
+  prim_box<1>(&i, xs, x1s, n_vert, h, r.lo, r.hi);
+  r.v[0] = i;
+  r.v[1] = -1;
+  r.v[2] = -1;
+  r.tag = (int)has_dof(rowptr, i) | (scene_of(vscene, i) << 1);
+  rec[i] = r;
+}
+
 // Scratch of one broad phase (kind, swept) kept in the context's buffers.
 struct BPScratch {
   ItemRec *items;
@@ -982,6 +1280,10 @@ struct BPScratch {
   int64_t *cell_off, *bstart, *qoff, *n_large, *n_qlarge;
   Entry *ent;
   QEntry *qent;
+  int32_t *big, *qbig;
+  int64_t *n_big, *n_qbig;  // {items, cells}
+  ItemRec *vrec;     // bucket join, PT: vertex records
+  int64_t *vbstart;  // bucket join, PT: vertex-hash bucket offsets
   GridDev *g;
   uint64_t *st;
   unsigned long long *total;
@@ -1007,8 +1309,15 @@ static eipc_status bp_scratch(eipc_ctx *c, int nq, int ni, uint32_t nb, int64_t 
   b.n_large = (int64_t *)(small + 256);
   b.total = (unsigned long long *)(small + 264);
   b.n_qlarge = (int64_t *)(small + 272);
+  b.n_big = (int64_t *)(small + 280);
+  b.n_qbig = (int64_t *)(small + 296);
   EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 11), (size_t)nq, &b.qlarge));
   EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 12), (size_t)std::max<int64_t>(qent_cap, 1), &b.qent));
+  const bool vhash = (slot & 1) == 0 && c->query_mode[0] == 3;
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 13), vhash ? (size_t)nq : 1, &b.vrec));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 14), vhash ? (size_t)nb + 1 : 1, &b.vbstart));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 15), (size_t)ni, &b.big));
+  EIPC_TRY(ensure_t(c, (BufId)(B_BP0 + base + 16), vhash ? (size_t)nq : 1, &b.qbig));
   return EIPC_OK;
 }
 
@@ -1040,21 +1349,24 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   k_box_stats<<<stat_blocks(ni), STAT_T, 0, s>>>(ni, b.items, nullptr, nullptr, 0, h, b.st, 1);
   if (kind == 0) k_box_stats<<<stat_blocks(nq), STAT_T, 0, s>>>(nq, nullptr, xs, x1s, sc->n_vert, h, b.st, 0);
   k_grid_params<<<1, 64, 0, s>>>(b.st, ni, c->cell_scale, b.g, c->status);
-  EIPC_TRY(launch_zero(c, b.n_large, 24, s));
-  k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, b.cnt, b.large, b.n_large);
+  EIPC_TRY(launch_zero(c, b.n_large, 56, s));
+  k_item_cells<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, b.cnt, b.large, b.n_large, b.big, b.n_big);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, b.cnt, ni, b.cell_off, s));
   if (!plan) {
     // size the hash from the entry count (synchronizes)
     int64_t hv[2];
+    int64_t hbig[2];
     GridDev gh;
     EIPC_HIP(c, hipMemcpyAsync(&hv[0], b.cell_off + ni, 8, hipMemcpyDeviceToHost, s));
+    EIPC_HIP(c, hipMemcpyAsync(hbig, b.n_big, 16, hipMemcpyDeviceToHost, s));
     EIPC_HIP(c, hipMemcpyAsync(&gh, b.g, sizeof(GridDev), hipMemcpyDeviceToHost, s));
     EIPC_HIP(c, hipStreamSynchronize(s));
     if (gh.bad) {
       EIPC_TRY(launch_zero(c, c->status, 4, s));  // reported here instead
       return set_err(c, EIPC_ERR_NONFINITE, "non-finite primitive boxes");
     }
+    hv[0] += hbig[1];
     ent_cap = std::max<int64_t>(hv[0], 1);
     nb = next_pow2((uint64_t)std::max<int64_t>(2 * hv[0], 1024));
     EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b));
@@ -1065,20 +1377,55 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   EIPC_TRY(launch_zero(c, b.bcnt, sizeof(int32_t) * nb, s));
   EIPC_TRY(launch_zero(c, b.bfill, sizeof(int32_t) * nb, s));
   k_item_hist<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bcnt);
+  k_big_hist<<<BIG_BLOCKS, 256, 0, s>>>(b.big, b.n_big, b.items, b.g, bmask, b.bcnt);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, b.bcnt, nb, b.bstart, s));
   k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bstart, b.bfill, b.ent, ent_cap,
                                                  c->status);
+  k_big_fill<<<BIG_BLOCKS, 256, 0, s>>>(b.big, b.n_big, b.items, b.g, bmask, b.bstart, b.bfill, b.ent, ent_cap,
+                                        c->status);
   EIPC_HIP(c, hipGetLastError());
   QueryArgs qa{b.g, bmask, b.bstart, b.ent, ent_cap, b.large, b.n_large, b.items, sc->W_rowptr, vsc, nullptr,
                nullptr};
   const int n_vert = sc->n_vert;
   if (!sort) {
-    // single pass, unsorted append; per (query, cell) or per query
-    const bool cellpar = c->query_mode[kind] != 0;
+    // single pass, unsorted append; per query, per (query, cell) or as a
+    // bucket join
+    const int qmode = c->query_mode[kind];
+    const bool cellpar = qmode == 1 || qmode == 2;
     int64_t qent_cap = plan ? plan->qent_cap : 1;
     const int gq = grid_for(nq, 256);
-    if (!cellpar) {
+    if (qmode == 3) {
+      if (kind == 0) {
+        // vertex hash over the same grid and buckets as the faces
+        k_vert_items<<<gq, 256, 0, s>>>(nq, xs, x1s, n_vert, h, sc->W_rowptr, vsc, b.vrec);
+        k_item_cells<<<gq, 256, 0, s>>>(nq, b.vrec, b.g, b.qcnt, b.qlarge, b.n_qlarge, b.qbig, b.n_qbig);
+        EIPC_HIP(c, hipGetLastError());
+        if (!plan) {
+          EIPC_TRY(exclusive_scan(c, b.qcnt, nq, b.qoff, s));
+          int64_t tq = 0, tbig[2];
+          EIPC_HIP(c, hipMemcpyAsync(&tq, b.qoff + nq, 8, hipMemcpyDeviceToHost, s));
+          EIPC_HIP(c, hipMemcpyAsync(tbig, b.n_qbig, 16, hipMemcpyDeviceToHost, s));
+          EIPC_HIP(c, hipStreamSynchronize(s));
+          qent_cap = std::max<int64_t>(tq + tbig[1], 1);
+          c->last_plan[slot].qent_cap = qent_cap;
+          EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b, qent_cap));
+        }
+        EIPC_TRY(launch_zero(c, b.bcnt, sizeof(int32_t) * nb, s));
+        EIPC_TRY(launch_zero(c, b.bfill, sizeof(int32_t) * nb, s));
+        k_item_hist<<<gq, 256, 0, s>>>(nq, b.vrec, b.g, bmask, b.qcnt, b.bcnt);
+        k_big_hist<<<BIG_BLOCKS, 256, 0, s>>>(b.qbig, b.n_qbig, b.vrec, b.g, bmask, b.bcnt);
+        EIPC_HIP(c, hipGetLastError());
+        EIPC_TRY(exclusive_scan(c, b.bcnt, nb, b.vbstart, s));
+        k_item_fill<<<gq, 256, 0, s>>>(nq, b.vrec, b.g, bmask, b.qcnt, b.vbstart, b.bfill,
+                                       reinterpret_cast<Entry *>(b.qent), qent_cap, c->status);
+        k_big_fill<<<BIG_BLOCKS, 256, 0, s>>>(b.qbig, b.n_qbig, b.vrec, b.g, bmask, b.vbstart, b.bfill,
+                                              reinterpret_cast<Entry *>(b.qent), qent_cap, c->status);
+        EIPC_HIP(c, hipGetLastError());
+      } else if (!plan) {
+        c->last_plan[slot].qent_cap = 1;
+      }
+    } else if (!cellpar) {
       if (!plan) c->last_plan[slot].qent_cap = 1;
     } else {
     if (kind == 0)
@@ -1117,7 +1464,27 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
       {
         ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
         const int ge = (int)std::min<int64_t>(grid_for(qent_cap, QT), 64 * (int64_t)c->num_cu);
-        if (!cellpar) {
+        if (qmode == 3) {
+          QueryArgs qlj = qa;  // queries too large to hash, run per query
+          if (kind == 0) {
+            const JoinArgs ja{reinterpret_cast<const Entry *>(b.qent), b.vbstart + nb, qent_cap, b.vrec, b.bstart,
+                              b.ent, ent_cap, b.items, b.large, b.n_large, bmask};
+            k_join<0><<<grid_for(qent_cap, JT), JT, 0, s>>>(ja, out, capa, b.total);
+            qlj.qlist = b.qlarge;
+            qlj.n_qlist = b.n_qlarge;
+          } else {
+            const JoinArgs ja{b.ent, b.bstart + nb, ent_cap, b.items, b.bstart, b.ent, ent_cap, b.items, b.large,
+                              b.n_large, bmask};
+            k_join<1><<<grid_for(ent_cap, JT), JT, 0, s>>>(ja, out, capa, b.total);
+            qlj.qlist = b.large;
+            qlj.n_qlist = b.n_large;
+          }
+          EIPC_HIP(c, hipGetLastError());
+          if (kind == 0)
+            k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlj, out, capa, b.total);
+          else
+            k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlj, out, capa, b.total);
+        } else if (!cellpar) {
           if (kind == 0)
             k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qa, out, capa, b.total);
           else

@@ -13,6 +13,9 @@ the workloads the contact stage is measured on):
 * ``tiny_scene``: two small convex bodies separated by a plane, for exact
   comparisons on inputs small enough for brute force.
 * ``batch_scenes``: many grasp scenes of uneven size.
+* ``mixed_scale_scene``: a fine sheet over coarse static plates whose
+  triangles are tens to hundreds of times larger than the sheet's, so that
+  the broad phase meets primitives of very different sizes.
 """
 from __future__ import annotations
 
@@ -281,6 +284,41 @@ def full_space_scene(seed: int = 0) -> Scene:
 def single_tet_scene(seed: int = 0) -> Scene:
     """The paper's affine-body special case: body A in one tetrahedron."""
     return tiny_scene(seed, mode="tet")
+
+
+def _grid_sheet(n: int, lo: float, hi: float, z: float) -> tuple[np.ndarray, np.ndarray]:
+    """(n+1) x (n+1) vertices on [lo, hi]^2 at height z, two triangles per
+    quad (alternating diagonals)."""
+    t = np.linspace(lo, hi, n + 1)
+    gx, gy = np.meshgrid(t, t, indexing="ij")
+    v = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, z)], 1)
+    f = []
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = i * (n + 1) + j, (i + 1) * (n + 1) + j, (i + 1) * (n + 1) + j + 1, i * (n + 1) + j + 1
+            f += [(a, b, c), (a, c, d)] if (i + j) % 2 == 0 else [(a, b, d), (b, c, d)]
+    return v, np.array(f, dtype=np.int64)
+
+
+def mixed_scale_scene(seed: int = 0, n: int = 80, size: float = 0.1, dhat: float = 2e-4) -> Scene:
+    """A deformable n x n sheet (edge size/n, embedded in a 4x4x2 grid)
+    hovering 0.2-0.8 dhat above two static coplanar plates: a 2-triangle
+    plate twice the sheet's width (triangles spanning about a hundred broad-
+    phase cells per axis) and a 3x3-quad plate under the middle (tens of
+    cells per axis).  dq moves the sheet down by up to about 2 dhat."""
+    rng = rng_for(seed, 0)
+    sv, sf = _grid_sheet(n, 0.0, size, 0.5 * dhat)
+    sv[:, 2] += rng.uniform(-0.3, 0.3, len(sv)) * dhat
+    pv, pf = _grid_sheet(1, -0.5 * size, 1.5 * size, 0.0)
+    mv, mf = _grid_sheet(3, 0.2 * size, 0.8 * size, 0.0)
+    bodies = [Body(sv, sf, padded_grid(sv, (4, 4, 2))), Body(pv, pf, None), Body(mv, mf, None)]
+    asm = _assemble(bodies)
+    q = asm[5].copy()
+    dq = np.zeros_like(q).reshape(-1, 3)
+    dq[:, 2] = -rng.uniform(0.0, 2.0, len(dq)) * dhat
+    dq[:, :2] = rng.normal(0.0, 0.2 * dhat, (len(dq), 2))
+    return _make(f"mixed{seed}", bodies, q, dq.reshape(-1), dhat, 1e3, seed, assembled=asm,
+                 meta={"sheet_n": n, "size": size})
 
 
 # ---------------------------------------------------------------------------

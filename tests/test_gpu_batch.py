@@ -189,7 +189,7 @@ def test_bad_scene_id_is_an_argument_error(ctx, scenes):
     ctx.sync_status()
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 4, 5, 6, 8, 9, 10])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 15])
 def test_query_work_split_does_not_change_results(ctx, scenes, seq, mode):
     """Per-query and per-(query, cell) broad-phase work splits give the same
     candidate sets, so the same counts, energies and step bounds."""

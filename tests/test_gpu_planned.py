@@ -89,11 +89,13 @@ def test_graph_replay_at_full_size(ctx):
         _compare(b, _plain(ctx, "config2"))
 
 
-@pytest.mark.parametrize("mode", [0, 5, 10])
-def test_tuning_does_not_change_results(ctx, mode):
+@pytest.mark.parametrize("mode,cs", [(0, 1.5), (5, 3.0), (10, 3.0), (15, 3.0), (15, 1.0)])
+def test_tuning_does_not_change_results(ctx, mode, cs):
+    """Work splits and cell sizes (at cell_scale 1 several hundred edges and
+    faces span more than 64 cells and take the large-item path)."""
     sc = _scene("config2")
     b = BT.Batch(ctx, BT.concat([sc]), flags=_flags(sc))
-    E.set_tuning(b.ctx, 3.0 if mode else 1.5, [1, 16, 1, 16], mode)
+    E.set_tuning(b.ctx, cs, [1, 16, 1, 16], mode)
     b.make_plan(1.5)
     b.step()
     assert b.status() == E.binding.OK
