@@ -718,7 +718,7 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
     p.ent[2] = p.ent[3] = 1;
     p.qent[2] = p.qent[3] = 1;
   }
-  for (int k = 0; k < 4; ++k) p.buckets[k] = std::max<int64_t>(pow2_at_least(2 * p.ent[k]), 1024);
+  for (int k = 0; k < 4; ++k) p.buckets[k] = hash_buckets(p.ent[k]);
   {
     const eipc_status st0 = read_status(c, s);
     if (st0 != EIPC_OK && st0 != EIPC_WARN_CCD_CAPPED) return st0;

@@ -46,6 +46,15 @@ enum BufId {
 constexpr int BP_NBUF = 17;
 
 // capacities of one broad phase in a planned (synchronization-free) call
+// Buckets of a broad-phase hash of `entries` (item, cell) entries: a cell
+// holds tens of entries, so a quarter as many buckets as entries still
+// leaves most occupied cells a bucket of their own (power of 2, >= 1024).
+inline int64_t hash_buckets(int64_t entries) {
+  int64_t b = 1024;
+  while (b < entries / 4 && b < (1ll << 31)) b <<= 1;
+  return b;
+}
+
 struct BPPlan {
   uint32_t nb;        // hash buckets (power of 2)
   int64_t ent_cap;    // item hash entries

@@ -480,17 +480,67 @@ __global__ void k_big_hist(const int32_t *__restrict__ big, const int64_t *__res
   }
 }
 
-__global__ void k_item_hist(int n, const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, uint32_t bmask,
-                            const int32_t *cnt, int32_t *bcnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || cnt[i] == 0) return;
-  const GridDev g = *gp;
-  const int sc = rec[i].tag >> 1;
-  int c0[3], c1[3];
-  cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
-  for (int z = c0[2]; z <= c1[2]; ++z)
-    for (int y = c0[1]; y <= c1[1]; ++y)
-      for (int x = c0[0]; x <= c1[0]; ++x) atomicAdd(&bcnt[cell_hash(x, y, z, sc) & bmask], 1);
+// Workgroup-local bucket table: the items of a workgroup are neighbours
+// in mesh order, so their (item, cell) entries fall into few buckets.  Each
+// distinct bucket takes one LDS slot (linear probing on the bucket id), the
+// entries are counted there, and one global atomic per slot carries the
+// count (histogram) or reserves the bucket's range (fill).  An entry whose
+// probe finds neither its bucket nor a free slot within LT_PROBE steps goes
+// to the global counters directly; its bucket then never enters the table.
+constexpr int LT_T = 256;       // items per workgroup
+constexpr int LT_SLOTS = 2048;  // LDS table slots
+constexpr int LT_PROBE = 32;
+
+__device__ __forceinline__ int lt_insert(uint32_t *key, uint32_t b) {
+  uint32_t h = (b * 2654435761u) >> 21;  // 11 bits
+  for (int p = 0; p < LT_PROBE; ++p) {
+    const uint32_t old = atomicCAS(&key[h], 0u, b + 1u);
+    if (old == 0u || old == b + 1u) return (int)h;
+    h = (h + 1) & (LT_SLOTS - 1);
+  }
+  return -1;
+}
+__device__ __forceinline__ int lt_find(const uint32_t *key, uint32_t b) {
+  uint32_t h = (b * 2654435761u) >> 21;
+  for (int p = 0; p < LT_PROBE; ++p) {
+    const uint32_t k = key[h];
+    if (k == b + 1u) return (int)h;
+    if (k == 0u) return -1;
+    h = (h + 1) & (LT_SLOTS - 1);
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(LT_T) void k_item_hist(int n, const ItemRec *__restrict__ rec,
+                                                    const GridDev *__restrict__ gp, uint32_t bmask,
+                                                    const int32_t *cnt, int32_t *bcnt) {
+  __shared__ uint32_t s_key[LT_SLOTS];
+  __shared__ int32_t s_cnt[LT_SLOTS];
+  for (int k = threadIdx.x; k < LT_SLOTS; k += LT_T) {
+    s_key[k] = 0u;
+    s_cnt[k] = 0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * LT_T + threadIdx.x;
+  if (i < n && cnt[i] != 0) {
+    const GridDev g = *gp;
+    const int sc = rec[i].tag >> 1;
+    int c0[3], c1[3];
+    cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
+    for (int z = c0[2]; z <= c1[2]; ++z)
+      for (int y = c0[1]; y <= c1[1]; ++y)
+        for (int x = c0[0]; x <= c1[0]; ++x) {
+          const uint32_t b = cell_hash(x, y, z, sc) & bmask;
+          const int t = lt_insert(s_key, b);
+          if (t >= 0)
+            atomicAdd(&s_cnt[t], 1);
+          else
+            atomicAdd(&bcnt[b], 1);
+        }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < LT_SLOTS; k += LT_T)
+    if (s_key[k] != 0u) atomicAdd(&bcnt[s_key[k] - 1u], s_cnt[k]);
 }
 
 // Hash entry: the item's box rounded outward to float, so that most
@@ -509,28 +559,62 @@ __device__ __forceinline__ void box_f32(const double *lo, const double *hi, floa
   }
 }
 
-__global__ void k_item_fill(int n, const ItemRec *__restrict__ rec, const GridDev *__restrict__ gp, uint32_t bmask,
-                            const int32_t *cnt, const int64_t *bstart, int32_t *bfill, Entry *ent, int64_t ent_cap,
-                            uint32_t *status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || cnt[i] == 0) return;
-  const GridDev g = *gp;
-  const int sc = rec[i].tag >> 1;
-  int c0[3], c1[3];
-  cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
+__global__ __launch_bounds__(LT_T) void k_item_fill(int n, const ItemRec *__restrict__ rec,
+                                                    const GridDev *__restrict__ gp, uint32_t bmask,
+                                                    const int32_t *cnt, const int64_t *bstart, int32_t *bfill,
+                                                    Entry *ent, int64_t ent_cap, uint32_t *status) {
+  __shared__ uint32_t s_key[LT_SLOTS];
+  __shared__ int32_t s_cnt[LT_SLOTS];
+  __shared__ int32_t s_base[LT_SLOTS];
+  for (int k = threadIdx.x; k < LT_SLOTS; k += LT_T) {
+    s_key[k] = 0u;
+    s_cnt[k] = 0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * LT_T + threadIdx.x;
+  const bool live = i < n && cnt[i] != 0;
+  GridDev g;
+  int sc = 0, c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
+  if (live) {
+    g = *gp;
+    sc = rec[i].tag >> 1;
+    cell_range(g, rec[i].lo, rec[i].hi, c0, c1);
+  }
+  auto put = [&](int64_t slot, int x, int y, int z) {
+    if (slot < ent_cap) {
+      Entry en;
+      en.cell = cell_key(x, y, z, sc);
+      en.item = i;
+      en.dlo = (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12);
+      ent[slot] = en;
+    } else {
+      atomicOr(status, ST_PLAN_OVERFLOW);
+    }
+  };
+  // count per bucket in LDS (entries that find no slot take their global
+  // slot now)
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) {
-        uint32_t b = cell_hash(x, y, z, sc) & bmask;
-        int64_t slot = bstart[b] + atomicAdd(&bfill[b], 1);
-        if (slot < ent_cap) {
-          Entry en;
-          en.cell = cell_key(x, y, z, sc);
-          en.item = i;
-          en.dlo = (x - c0[0]) | ((y - c0[1]) << 6) | ((z - c0[2]) << 12);
-          ent[slot] = en;
-        } else
-          atomicOr(status, ST_PLAN_OVERFLOW);
+        const uint32_t b = cell_hash(x, y, z, sc) & bmask;
+        const int t = lt_insert(s_key, b);
+        if (t >= 0)
+          atomicAdd(&s_cnt[t], 1);
+        else
+          put(bstart[b] + atomicAdd(&bfill[b], 1), x, y, z);
+      }
+  __syncthreads();
+  // reserve each bucket's range once
+  for (int k = threadIdx.x; k < LT_SLOTS; k += LT_T)
+    if (s_key[k] != 0u) s_base[k] = atomicAdd(&bfill[s_key[k] - 1u], s_cnt[k]);
+  __syncthreads();
+  // place: rank within the workgroup's range from the LDS count
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) {
+        const uint32_t b = cell_hash(x, y, z, sc) & bmask;
+        const int t = lt_find(s_key, b);
+        if (t >= 0) put(bstart[b] + s_base[t] + atomicSub(&s_cnt[t], 1) - 1, x, y, z);
       }
 }
 
@@ -1368,7 +1452,7 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
     }
     hv[0] += hbig[1];
     ent_cap = std::max<int64_t>(hv[0], 1);
-    nb = next_pow2((uint64_t)std::max<int64_t>(2 * hv[0], 1024));
+    nb = (uint32_t)hash_buckets(hv[0]);
     EIPC_TRY(bp_scratch(c, nq, ni, nb, ent_cap, slot, b));
     c->last_plan[slot].nb = nb;
     c->last_plan[slot].ent_cap = ent_cap;
@@ -1376,11 +1460,11 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   const uint32_t bmask = nb - 1;
   EIPC_TRY(launch_zero(c, b.bcnt, sizeof(int32_t) * nb, s));
   EIPC_TRY(launch_zero(c, b.bfill, sizeof(int32_t) * nb, s));
-  k_item_hist<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bcnt);
+  k_item_hist<<<grid_for(ni, LT_T), LT_T, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bcnt);
   k_big_hist<<<BIG_BLOCKS, 256, 0, s>>>(b.big, b.n_big, b.items, b.g, bmask, b.bcnt);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, b.bcnt, nb, b.bstart, s));
-  k_item_fill<<<grid_for(ni, 256), 256, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bstart, b.bfill, b.ent, ent_cap,
+  k_item_fill<<<grid_for(ni, LT_T), LT_T, 0, s>>>(ni, b.items, b.g, bmask, b.cnt, b.bstart, b.bfill, b.ent, ent_cap,
                                                  c->status);
   k_big_fill<<<BIG_BLOCKS, 256, 0, s>>>(b.big, b.n_big, b.items, b.g, bmask, b.bstart, b.bfill, b.ent, ent_cap,
                                         c->status);
@@ -1413,11 +1497,11 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
         }
         EIPC_TRY(launch_zero(c, b.bcnt, sizeof(int32_t) * nb, s));
         EIPC_TRY(launch_zero(c, b.bfill, sizeof(int32_t) * nb, s));
-        k_item_hist<<<gq, 256, 0, s>>>(nq, b.vrec, b.g, bmask, b.qcnt, b.bcnt);
+        k_item_hist<<<grid_for(nq, LT_T), LT_T, 0, s>>>(nq, b.vrec, b.g, bmask, b.qcnt, b.bcnt);
         k_big_hist<<<BIG_BLOCKS, 256, 0, s>>>(b.qbig, b.n_qbig, b.vrec, b.g, bmask, b.bcnt);
         EIPC_HIP(c, hipGetLastError());
         EIPC_TRY(exclusive_scan(c, b.bcnt, nb, b.vbstart, s));
-        k_item_fill<<<gq, 256, 0, s>>>(nq, b.vrec, b.g, bmask, b.qcnt, b.vbstart, b.bfill,
+        k_item_fill<<<grid_for(nq, LT_T), LT_T, 0, s>>>(nq, b.vrec, b.g, bmask, b.qcnt, b.vbstart, b.bfill,
                                        reinterpret_cast<Entry *>(b.qent), qent_cap, c->status);
         k_big_fill<<<BIG_BLOCKS, 256, 0, s>>>(b.qbig, b.n_qbig, b.vrec, b.g, bmask, b.vbstart, b.bfill,
                                               reinterpret_cast<Entry *>(b.qent), qent_cap, c->status);
