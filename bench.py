@@ -60,7 +60,8 @@ def _args():
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--no-graph", action="store_true", help="time eager planned steps instead of graph replays")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip timing the per-call entry points")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip timing the per-call entry points (batch: the sequential single-scene calls)")
     ap.add_argument("--tuning", default=None,
                     help="fixed tuning 'cell_scale,wg_terms,wg_expand,wg_narrow,wg_ccd,query_cells' "
                          "(skips the autotuner)")
@@ -370,9 +371,11 @@ def main():
     }
     if a.config == "batch":
         # 256 sequential single-scene calls on the same scenes
-        dscs = [E.Scene.from_host(ctx, s) for s in scenes_list]
-        BT.sequential_reference(ctx, scenes_list[:4], dscs[:4])
-        _, t_seq = BT.sequential_reference(ctx, scenes_list, dscs)
+        t_seq = float("nan")
+        if not a.no_plain:
+            dscs = [E.Scene.from_host(ctx, s) for s in scenes_list]
+            BT.sequential_reference(ctx, scenes_list[:4], dscs[:4])
+            _, t_seq = BT.sequential_reference(ctx, scenes_list, dscs)
         nv = np.diff(hb.vert_off)
         out["config"] = {"workload": (f"batch of {hb.n_scene} ragged grasp scenes (objects 2e3-5e4 triangles, "
                                       f"100-2000 coarse nodes, fingers 2x5120 triangles, random SE(3)): "
@@ -382,10 +385,11 @@ def main():
                          "candidates": cnt["cand_pt"] + cnt["cand_ee"], "ccd_candidates": swept,
                          "verts_per_scene_min_max": [int(nv.min()), int(nv.max())], "seed0": a.seed}
         out["scenes_per_s"] = hb.n_scene / (ms_per_step / 1e3)
-        out["sequential_ms"] = 1e3 * t_seq
-        out["sequential_scenes_per_s"] = hb.n_scene / t_seq
-        out["sequential_pairs_per_s"] = n_active / t_seq
-        out["batch_speedup"] = (t_seq * 1e3) / ms_per_step
+        if not a.no_plain:
+            out["sequential_ms"] = 1e3 * t_seq
+            out["sequential_scenes_per_s"] = hb.n_scene / t_seq
+            out["sequential_pairs_per_s"] = n_active / t_seq
+            out["batch_speedup"] = (t_seq * 1e3) / ms_per_step
     elif not a.no_plain:
         sc = scenes_list[0]
         out["config"] = {"workload": f"{a.config} ({sc.name}): n_vert={sc.n_vert} n_face={sc.n_face} "

@@ -218,33 +218,6 @@ struct Acc {
   uint32_t *status;
 };
 
-__device__ __forceinline__ void lds_block_add_n(const Acc &A, long long key, const double *B) {
-  int slot = (int)table_slot64(A.T.bkey, LTBL - 1, key);
-  if (slot < 0) {
-    global_block_add(A.h, A.n_node, key / A.n_node, key % A.n_node, B, A.status);
-    return;
-  }
-#pragma unroll
-  for (int t = 0; t < 9; ++t) atomicAdd(&A.T.bval[9 * slot + t], B[t]);
-}
-
-// wavefront-aggregated add of a 3x3 block (all lanes must call)
-__device__ __forceinline__ void agg_block(const Acc &A, bool valid, long long key, const double *B) {
-  const uint64_t vm = __ballot(valid);
-  if (vm == 0) return;
-  const int first = __ffsll((unsigned long long)vm) - 1;
-  const long long k0 = __shfl(key, first, 64);
-  const bool uniform = __ballot(valid && key != k0) == 0;
-  if (uniform) {
-    double S[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) S[t] = wave_sum(valid ? B[t] : 0.0);
-    if ((int)(threadIdx.x & 63) == first) lds_block_add_n(A, key, S);
-  } else if (valid) {
-    lds_block_add_n(A, key, B);
-  }
-}
-
 __device__ __forceinline__ void agg_vec(const Acc &A, bool valid, int node, double g0, double g1, double g2) {
   const uint64_t vm = __ballot(valid);
   if (vm == 0) return;
@@ -360,10 +333,42 @@ __global__ __launch_bounds__(BR_THREADS) void k_pair_terms(
   }
 }
 
-// Phase 2: reduction through W of gamma and X (merged node sets, wavefront
-// aggregation, LDS tables flushed to the global target).
+// ---------------------------------------------------------------------------
+// Phase 2, reduction through W of gamma and X.  Cooperative expansion: sixteen lanes per pair, lane s holding slot s =
+// (vertex s / 4, weight s % 4) of the pair: its node and z_s = w_s Q[a]
+// (3 numbers).  The sixteen slots are sorted by node across the lanes
+// (bitonic exchange within the 16-lane group), runs of equal nodes summed
+// (segmented scan; the last lane of a run keeps the node), so each node of
+// the pair sits on one lane.  That lane forms Y_J = sum_beta z_J[beta]
+// X[.][beta] (27 numbers) and, for every node I <= J of the group (taken
+// by shuffle), the block sum_alpha z_I[alpha] Y_J[alpha], accumulated in
+// the workgroup's LDS table as in the per-pair form; the node's gradient
+// is sum_alpha z_J[alpha] gamma_alpha.
+// ---------------------------------------------------------------------------
+constexpr int EX_T = 512;  // threads per workgroup: 32 pairs per step
+
+__device__ __forceinline__ int64_t table_slot64_new(long long *keys, uint64_t mask, long long key, bool &fresh) {
+  uint64_t h = mix64((uint64_t)key) & mask;
+  fresh = false;
+  for (int p = 0; p < MAX_PROBE; ++p) {
+    long long k = ((volatile long long *)keys)[h];
+    if (k == key) return (int64_t)h;
+    if (k == -1) {
+      long long old = (long long)atomicCAS((unsigned long long *)&keys[h], (unsigned long long)-1ll,
+                                           (unsigned long long)key);
+      if (old == -1) {
+        fresh = true;
+        return (int64_t)h;
+      }
+      if (old == key) return (int64_t)h;
+    }
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
 template <int KIND>
-__global__ __launch_bounds__(BR_THREADS) void k_expand(
+__global__ __launch_bounds__(EX_T) void k_expand16(
     const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int64_t *__restrict__ d_count,
     const int32_t *__restrict__ faces, const int32_t *__restrict__ edges, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const double *__restrict__ val, int n_node, const double *__restrict__ gq,
@@ -373,86 +378,133 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
   __shared__ int s_gkey[LGT];
   __shared__ double s_gval[LGT * 3];
   __shared__ int s_used;
-  LdsTables T{s_bkey, s_bval, s_gkey, s_gval};
-  Acc A{T, h, n_node, grad, status};
   const bool want_g = gq != nullptr && grad != nullptr;
   const bool want_h = Xq != nullptr && h.kind != 0;
-  for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) s_bkey[t] = -1;
-  for (int t = threadIdx.x; t < LTBL * 9; t += BR_THREADS) s_bval[t] = 0.0;
-  for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = -1;
-  for (int t = threadIdx.x; t < LGT * 3; t += BR_THREADS) s_gval[t] = 0.0;
+  for (int t = threadIdx.x; t < LTBL; t += EX_T) s_bkey[t] = -1;
+  for (int t = threadIdx.x; t < LTBL * 9; t += EX_T) s_bval[t] = 0.0;
+  for (int t = threadIdx.x; t < LGT; t += EX_T) s_gkey[t] = -1;
+  for (int t = threadIdx.x; t < LGT * 3; t += EX_T) s_gval[t] = 0.0;
+  if (threadIdx.x == 0) s_used = 0;
   __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int s = lane & 15;
+  const int gbase = lane & ~15;
+  constexpr int PPS = EX_T / 16;  // pairs per step
   const int64_t n = *d_count < cap ? *d_count : cap;
-  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + BR_THREADS - 1) / BR_THREADS * BR_THREADS;
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + PPS - 1) / PPS * PPS;
   const int64_t r0 = (int64_t)blockIdx.x * per;
   const int64_t r1 = r0 + per < n ? r0 + per : n;
-  for (int64_t base = r0; base < r1; base += BR_THREADS) {
-    const int64_t i = base + threadIdx.x;
+  for (int64_t base = r0; base < r1; base += PPS) {
+    const int64_t i = base + (threadIdx.x >> 4);
     const bool active = i < r1;
-    int vid[4] = {0, 0, 0, 0};
-    NodeSet S;
-    int m = 0;
-    bool fast = true;
+    // this lane's slot
+    int node = NO_NODE;
+    double z[3] = {0.0, 0.0, 0.0};
     if (active) {
-      pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
-      fast = gather_nodes<KIND>(vid, rowptr, col, val, S, m);
+      const int a = s >> 2, k = s & 3;
+      const int pa = pairs[2 * act[i]], pb = pairs[2 * act[i] + 1];
+      int v;
+      if (KIND == 0)
+        v = a == 0 ? pa : faces[3 * (int64_t)pb + a - 1];
+      else
+        v = a < 2 ? edges[2 * (int64_t)pa + a] : edges[2 * (int64_t)pb + a - 2];
+      const int k0 = rowptr[v];
+      if (k < rowptr[v + 1] - k0) {
+        node = col[k0 + k];
+        const double w = val[k0 + k];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) z[al] = 0.5 * kS[a][al] * w;
+      }
     }
-    const bool use_fast = active && fast;
+    // sort the group's slots by node (bitonic, ascending; ties keep place)
+#pragma unroll
+    for (int k = 2; k <= 16; k <<= 1)
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int pn = __shfl_xor(node, j, 64);
+        double pz[3];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) pz[al] = __shfl_xor(z[al], j, 64);
+        const bool up = (s & k) == 0, low = (s & j) == 0;
+        const bool take = (low == up) ? (pn < node) : (pn > node);
+        if (take) {
+          node = pn;
+#pragma unroll
+          for (int al = 0; al < 3; ++al) z[al] = pz[al];
+        }
+      }
+    // sum runs of equal nodes; the run's last lane holds the total
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int pn = __shfl_up(node, off, 16);
+      double pz[3];
+#pragma unroll
+      for (int al = 0; al < 3; ++al) pz[al] = __shfl_up(z[al], off, 16);
+      if (s >= off && pn == node) {
+#pragma unroll
+        for (int al = 0; al < 3; ++al) z[al] += pz[al];
+      }
+    }
+    const int nn = __shfl_down(node, 1, 16);
+    const bool mine = node != NO_NODE && (s == 15 || nn != node);
     if (want_g) {
       double gam[9];
 #pragma unroll
       for (int e = 0; e < 9; ++e) gam[e] = active ? gq[e * cap + i] : 0.0;
+      double g[3];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const bool v = use_fast && s < m;
-        if (__any(v)) {
-          double g[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) g[c] = S.z[s][0] * gam[c] + S.z[s][1] * gam[3 + c] + S.z[s][2] * gam[6 + c];
-          agg_vec(A, v, v ? S.node[s] : -1, g[0], g[1], g[2]);
-        }
-      }
+      for (int c = 0; c < 3; ++c) g[c] = z[0] * gam[c] + z[1] * gam[3 + c] + z[2] * gam[6 + c];
+      LdsTables T{s_bkey, s_bval, s_gkey, s_gval};
+      Acc A{T, h, n_node, grad, status};
+      agg_vec(A, mine, mine ? node : -1, g[0], g[1], g[2]);
     }
     if (want_h) {
-      double X[45];
+      double Y[3][9];
+      {
+        double X[45];
 #pragma unroll
-      for (int e = 0; e < 45; ++e) X[e] = active ? Xq[e * cap + i] : 0.0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if (!__any(use_fast && j < m)) continue;
-        double Rt[3][9];
+        for (int e = 0; e < 45; ++e) X[e] = active ? Xq[e * cap + i] : 0.0;
 #pragma unroll
         for (int al = 0; al < 3; ++al)
 #pragma unroll
           for (int r = 0; r < 3; ++r)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-              Rt[al][3 * r + c] = S.z[j][0] * X[pidx(3 * al + r, c)] + S.z[j][1] * X[pidx(3 * al + r, 3 + c)] +
-                                  S.z[j][2] * X[pidx(3 * al + r, 6 + c)];
+              Y[al][3 * r + c] = z[0] * X[pidx(3 * al + r, c)] + z[1] * X[pidx(3 * al + r, 3 + c)] +
+                                 z[2] * X[pidx(3 * al + r, 6 + c)];
+      }
+#pragma unroll 2
+      for (int ii = 0; ii < 16; ++ii) {
+        const int src = gbase + ii;
+        const int nI = __shfl(node, src, 64);
+        const int nI1 = __shfl(node, (src & ~15) | ((ii + 1) & 15), 64);
+        const bool mI = nI != NO_NODE && (ii == 15 || nI1 != nI);
+        const bool v = mine && mI && nI <= node;
+        if (!__any(v)) continue;
+        double zI[3];
 #pragma unroll
-        for (int ii = 0; ii <= j; ++ii) {
-          const bool v = use_fast && j < m;
+        for (int al = 0; al < 3; ++al) zI[al] = __shfl(z[al], src, 64);
+        if (v) {
           double B[9];
 #pragma unroll
-          for (int t = 0; t < 9; ++t) B[t] = S.z[ii][0] * Rt[0][t] + S.z[ii][1] * Rt[1][t] + S.z[ii][2] * Rt[2][t];
-          const long long key = v ? (long long)S.node[ii] * n_node + S.node[j] : -1ll;
-          agg_block(A, v, key, B);
+          for (int t = 0; t < 9; ++t) B[t] = zI[0] * Y[0][t] + zI[1] * Y[1][t] + zI[2] * Y[2][t];
+          const long long key = (long long)nI * n_node + node;
+          bool fresh;
+          const int slot = (int)table_slot64_new(s_bkey, LTBL - 1, key, fresh);
+          if (slot < 0) {
+            global_block_add(h, n_node, nI, node, B, status);
+          } else {
+            if (fresh) atomicAdd(&s_used, 1);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) atomicAdd(&s_bval[9 * slot + t], B[t]);
+          }
         }
       }
     }
     __syncthreads();
-    const bool last = base + BR_THREADS >= r1;
-    if (!last) {
-      if (threadIdx.x == 0) s_used = 0;
-      __syncthreads();
-      int cnt = 0;
-      for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) cnt += s_bkey[t] != -1;
-      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) cnt += 2 * (s_gkey[t] != -1);
-      if (cnt) atomicAdd(&s_used, cnt);
-      __syncthreads();
-    }
+    const bool last = base + PPS >= r1;
     if (last || s_used > LTBL / 2) {
-      for (int t = threadIdx.x; t < LTBL; t += BR_THREADS) {
+      for (int t = threadIdx.x; t < LTBL; t += EX_T) {
         const long long key = s_bkey[t];
         if (key != -1) {
           global_block_add(h, n_node, key / n_node, key % n_node, &s_bval[9 * t], status);
@@ -461,7 +513,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
           for (int u = 0; u < 9; ++u) s_bval[9 * t + u] = 0.0;
         }
       }
-      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) {
+      for (int t = threadIdx.x; t < LGT; t += EX_T) {
         const int key = s_gkey[t];
         if (key != -1) {
           atomicAdd(&grad[3 * (int64_t)key], s_gval[3 * t]);
@@ -471,6 +523,8 @@ __global__ __launch_bounds__(BR_THREADS) void k_expand(
           s_gval[3 * t] = s_gval[3 * t + 1] = s_gval[3 * t + 2] = 0.0;
         }
       }
+      __syncthreads();
+      if (threadIdx.x == 0) s_used = 0;
     }
     __syncthreads();
   }
@@ -606,14 +660,14 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
   }
   if (!want_g && !want_h) return EIPC_OK;
   {
-    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), (int64_t)c->wg_per_cu[1] * c->num_cu);
+    int blocks = (int)std::min<int64_t>(grid_for(max_count, EX_T / 16), (int64_t)c->wg_per_cu[1] * c->num_cu);
     ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
     if (kind == 0)
-      k_expand<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                                 sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
+      k_expand16<0><<<blocks, EX_T, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                             sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
     else
-      k_expand<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                                 sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
+      k_expand16<1><<<blocks, EX_T, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
+                                             sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
     EIPC_HIP(c, hipGetLastError());
   }
   return EIPC_OK;
