@@ -225,8 +225,9 @@ def _rooflines(prof, n_steps, work, workload):
             nbytes = work["cand"][kind] * (8 + 4 * 24) + 8 * work["active"][kind]
             per_unit = "104 B per candidate + 8 B per active pair"
         elif dom == "ccd":
-            nbytes = work["swept"][kind] * (8 + 4 * 48)
-            per_unit = "200 B per swept candidate"
+            # planned step: narrow phase fused in (active pairs written)
+            nbytes = work["swept"][kind] * (8 + 4 * 48) + 8 * work["active"][kind]
+            per_unit = "200 B per swept candidate + 8 B per active pair"
         else:
             nbytes = work["n_vert"] * (24 + 24 + 16 * 4)
             per_unit = "112 B per vertex"

@@ -609,10 +609,14 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     EIPC_TRY(ensure_t(c, B_CAND_EE, (size_t)2 * std::max<int64_t>(plan->swept_ee, 1), &cee));
     EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, cpt, plan->swept_pt, nullptr, 0, s, -1, nullptr, &bp[2], cn + 7));
     EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, cee, plan->swept_ee, nullptr, 0, s, -1, nullptr, &bp[3], cn + 8));
-    EIPC_TRY(launch_narrow(c, sc, 0, xs, cpt, plan->swept_pt, dhat, act_pt, typ_pt, cn + 2, s, cn + 7, plan->act_pt,
-                           cn + 5));
-    EIPC_TRY(launch_narrow(c, sc, 1, xs, cee, plan->swept_ee, dhat, act_ee, typ_ee, cn + 3, s, cn + 8, plan->act_ee,
-                           cn + 6));
+    // narrow phase and step bound in one sweep over the swept candidates
+    uint64_t tb;
+    std::memcpy(&tb, &t_max, 8);
+    EIPC_TRY(fill_u64(c, (uint64_t *)alpha, n_scene_of(sc), tb, s));
+    EIPC_TRY(launch_narrow_ccd(c, sc, 0, xs, ps, cpt, plan->swept_pt, cn + 7, dhat, act_pt, typ_pt, plan->act_pt,
+                               cn + 2, cn + 5, sfac, t_max, max_iter, (uint64_t *)alpha, s));
+    EIPC_TRY(launch_narrow_ccd(c, sc, 1, xs, ps, cee, plan->swept_ee, cn + 8, dhat, act_ee, typ_ee, plan->act_ee,
+                               cn + 3, cn + 6, sfac, t_max, max_iter, (uint64_t *)alpha, s));
     pt = cpt;
     ee = cee;
   } else {
@@ -639,16 +643,6 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, cn + 3, plan->act_ee, dhat, kappa, f, energy, g, h, s));
   }
   if (want_h) EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s, plan->nnzb));
-  // step bound over the swept candidates
-  if (alpha) {
-    uint64_t tb;
-    std::memcpy(&tb, &t_max, 8);
-    EIPC_TRY(fill_u64(c, (uint64_t *)alpha, n_scene_of(sc), tb, s));
-    EIPC_TRY(launch_ccd(c, sc, 0, xs, ps, cpt, plan->swept_pt, sfac, t_max, max_iter, (uint64_t *)alpha, nullptr,
-                        nullptr, s, cn + 7));
-    EIPC_TRY(launch_ccd(c, sc, 1, xs, ps, cee, plan->swept_ee, sfac, t_max, max_iter, (uint64_t *)alpha, nullptr,
-                        nullptr, s, cn + 8));
-  }
   if (counts) {
     k_step_counts<<<1, 64, 0, s>>>(cn, counts);
     EIPC_HIP(c, hipGetLastError());

@@ -149,6 +149,143 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
   if (__any(capped) && lane == 0) atomicOr(status, ST_CCD_CAPPED);
 }
 
+// Narrow phase and step-bound pass 0 in one sweep over the swept
+// candidates (the planned step with a step bound): each pair's vertices are
+// loaded once; the candidate predicate at x and, for the pairs passing it,
+// the distance and activity test (active pairs appended to act/typ with one
+// atomic per wavefront) come first, then advancement as in k_ccd2 pass 0,
+// reusing the distance just computed.  The pass-1 list is the same.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_narrow_ccd(
+    int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
+    const int32_t *__restrict__ edges, const double *__restrict__ xs, const double *__restrict__ ps, double dhat2,
+    double h, int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t act_cap, int64_t *count,
+    int64_t *cand_count, double sfac, double t_max, int64_t max_iter, unsigned long long *alpha_bits,
+    int32_t *__restrict__ longl, int64_t *n_long, const int32_t *__restrict__ vscene, int n_scene,
+    uint32_t *status) {
+  const int64_t n = *d_n < cap ? *d_n : cap;
+  const int lane = threadIdx.x & 63;
+  bool capped = false;
+  int64_t n_cand = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool live = i < n;
+    double t = t_max;
+    int scene = 0, ty = 0;
+    bool decided = false, deferred = false, active = false;
+    if (live) {
+      const int a = pairs[2 * i], b = pairs[2 * i + 1];
+      int vid[4];
+      if (KIND == 0) {
+        vid[0] = a;
+        vid[1] = faces[3 * (int64_t)b];
+        vid[2] = faces[3 * (int64_t)b + 1];
+        vid[3] = faces[3 * (int64_t)b + 2];
+      } else {
+        vid[0] = edges[2 * (int64_t)a];
+        vid[1] = edges[2 * (int64_t)a + 1];
+        vid[2] = edges[2 * (int64_t)b];
+        vid[3] = edges[2 * (int64_t)b + 1];
+      }
+      if (vscene) scene = vscene[vid[0]];
+      V3 x[4], p[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ld_pos(xs, vid[q], x[q].x, x[q].y, x[q].z);
+        ld_pos(ps, vid[q], p[q].x, p[q].y, p[q].z);
+      }
+      double s2 = 0.0;
+      const bool cand = static_boxes_overlap<KIND>(x, h);
+      if (cand) {
+        ++n_cand;
+        s2 = pair_dist2<KIND>(x, &ty);
+        if (!isfinite(s2)) {
+          atomicOr(status, ST_NONFINITE);
+        } else if (s2 < dhat2) {
+          if (s2 <= 0.0)
+            atomicOr(status, ST_INTERSECTING);
+          else
+            active = true;
+        }
+      }
+      AccdState st;
+      decided = accd_init<KIND>(x, p, sfac, t_max, st, cand, s2);
+      const int64_t lim = CCD_SHORT < max_iter ? CCD_SHORT : max_iter;
+      while (!decided && st.it < lim) decided = accd_step<KIND>(x, p, t_max, max_iter, st);
+      if (!decided && st.it >= max_iter) decided = accd_step<KIND>(x, p, t_max, max_iter, st);  // cap reached
+      if (decided) {
+        t = st.t;
+        capped = st.it >= max_iter;
+      } else {
+        deferred = true;
+      }
+    }
+    {
+      const uint64_t mask = __ballot(active);
+      int64_t pos0 = 0;
+      if (lane == 0 && mask)
+        pos0 = (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(mask));
+      pos0 = __shfl(pos0, 0, 64);
+      if (active) {
+        const int64_t pos = pos0 + __popcll(mask & ((1ull << lane) - 1ull));
+        if (pos < act_cap) {
+          act[pos] = (int32_t)i;
+          typ[pos] = ty;
+        } else {
+          atomicOr(status, ST_PLAN_OVERFLOW);
+        }
+      }
+    }
+    {
+      const uint64_t dm = __ballot(deferred);
+      if (dm) {
+        int64_t p0 = 0;
+        if (lane == __ffsll((unsigned long long)dm) - 1)
+          p0 = (int64_t)atomicAdd((unsigned long long *)n_long, (unsigned long long)__popcll(dm));
+        p0 = __shfl(p0, __ffsll((unsigned long long)dm) - 1, 64);
+        if (deferred) longl[p0 + __popcll(dm & ((1ull << lane) - 1ull))] = (int32_t)i;
+      }
+    }
+    agg_scene_min(alpha_bits, live && decided, scene, n_scene, t, status);
+  }
+  if (__any(capped) && lane == 0) atomicOr(status, ST_CCD_CAPPED);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n_cand += __shfl_xor(n_cand, o, 64);
+  if (lane == 0 && n_cand) atomicAdd((unsigned long long *)cand_count, (unsigned long long)n_cand);
+}
+
+eipc_status launch_narrow_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
+                              const int32_t *pairs, int64_t n, const int64_t *d_n, double dhat, int32_t *act,
+                              int32_t *typ, int64_t act_cap, int64_t *d_count, int64_t *cand_count, double sfac,
+                              double t_max, int64_t max_iter, uint64_t *d_alpha_bits, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  ProfScope prof(c, kind == 0 ? K_CCD_PT : K_CCD_EE, s);
+  const int blocks = (int)std::min<int64_t>(grid_for(n, 256), (int64_t)c->wg_per_cu[3] * c->num_cu);
+  const int32_t *vsc = vscene_of(sc);
+  const int nsc = n_scene_of(sc);
+  int64_t *n_long = c->counters + 9 + kind;
+  int32_t *longl;
+  EIPC_TRY(ensure_t(c, kind == 0 ? B_CCD_LONG_PT : B_CCD_LONG_EE, (size_t)n, &longl));
+  EIPC_TRY(launch_zero(c, n_long, 8, s));
+  unsigned long long *ab = (unsigned long long *)d_alpha_bits;
+  const double d2 = dhat * dhat, h = 0.5 * dhat;
+  if (kind == 0) {
+    k_narrow_ccd<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ, act_cap,
+                                           d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long, vsc, nsc,
+                                           c->status);
+    k_ccd2<0, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                        max_iter, ab, longl, n_long, vsc, nsc, c->status);
+  } else {
+    k_narrow_ccd<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ, act_cap,
+                                           d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long, vsc, nsc,
+                                           c->status);
+    k_ccd2<1, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
+                                        max_iter, ab, longl, n_long, vsc, nsc, c->status);
+  }
+  EIPC_HIP(c, hipGetLastError());
+  return EIPC_OK;
+}
+
 eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
                        const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
                        uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s, const int64_t *d_n) {

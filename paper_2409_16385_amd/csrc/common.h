@@ -230,6 +230,13 @@ eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double
                        const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
                        uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s,
                        const int64_t *d_n = nullptr);
+// Planned step with a step bound: narrow phase of the swept candidates
+// (as launch_narrow with cand_count) and the step bound (as launch_ccd
+// into d_alpha_bits) in one sweep, plus the pass for long pairs.
+eipc_status launch_narrow_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
+                              const int32_t *pairs, int64_t n, const int64_t *d_n, double dhat, int32_t *act,
+                              int32_t *typ, int64_t act_cap, int64_t *d_count, int64_t *cand_count, double sfac,
+                              double t_max, int64_t max_iter, uint64_t *d_alpha_bits, hipStream_t s);
 eipc_status launch_fp64_selftest(eipc_ctx *c, const double *a, const double *b, double *sq, double *dv, int64_t n,
                                  hipStream_t s);
 

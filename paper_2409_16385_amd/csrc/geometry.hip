@@ -1683,40 +1683,6 @@ __device__ __forceinline__ void pair_vids(const int32_t *pairs, int64_t k, const
   }
 }
 
-// The candidate predicate on the pair's own vertices: the box of the
-// query primitive (PT: the vertex, EE: the first edge) against the box of
-// the item (the face, the second edge), each spanning its vertices widened
-// by h on every side, closed intervals -- the same arithmetic as the broad
-// phase's boxes.
-template <int KIND>
-__device__ __forceinline__ bool static_boxes_overlap(const V3 *x, double h) {
-#pragma clang fp contract(off)
-  const int nq = KIND == 0 ? 1 : 2;
-  bool ok = true;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double qmn = INFINITY, qmx = -INFINITY, imn = INFINITY, imx = -INFINITY;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const double v = c == 0 ? x[a].x : (c == 1 ? x[a].y : x[a].z);
-      if (a < nq) {
-        qmn = fmin(qmn, v);
-        qmx = fmax(qmx, v);
-      } else {
-        imn = fmin(imn, v);
-        imx = fmax(imx, v);
-      }
-    }
-    ok = ok && (qmn - h <= imx + h) && (imn - h <= qmx + h);
-  }
-  return ok;
-}
-
-// Narrow phase: distance type and d^2 per pair, active iff 0 < d^2 <
-// dhat^2, wavefront-ballot compaction into act/typ (capacity act_cap).
-// FILTER: the pairs are swept candidates; only those that pass the
-// candidate predicate at the start positions are considered, and their
-// number is added to *cand_count.
 template <int KIND, bool FILTER>
 __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
                          const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,

@@ -682,6 +682,40 @@ __device__ __forceinline__ double mollifier_eps(const V3 *r) {
 //   loop: x += tl p; d = dist(x); if t > 0 and d < g stop;
 //         t += tl; if t > t_c return t_c; tl = 0.9 d / l_p
 // ---------------------------------------------------------------------------
+// The candidate predicate on the pair's own vertices: the box of the
+// query primitive (PT: the vertex, EE: the first edge) against the box of
+// the item (the face, the second edge), each spanning its vertices widened
+// by h on every side, closed intervals -- the same arithmetic as the broad
+// phase's boxes.
+template <int KIND>
+__device__ __forceinline__ bool static_boxes_overlap(const V3 *x, double h) {
+#pragma clang fp contract(off)
+  const int nq = KIND == 0 ? 1 : 2;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double qmn = INFINITY, qmx = -INFINITY, imn = INFINITY, imx = -INFINITY;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double v = c == 0 ? x[a].x : (c == 1 ? x[a].y : x[a].z);
+      if (a < nq) {
+        qmn = fmin(qmn, v);
+        qmx = fmax(qmx, v);
+      } else {
+        imn = fmin(imn, v);
+        imx = fmax(imx, v);
+      }
+    }
+    ok = ok && (qmn - h <= imx + h) && (imn - h <= qmx + h);
+  }
+  return ok;
+}
+
+// Narrow phase: distance type and d^2 per pair, active iff 0 < d^2 <
+// dhat^2, wavefront-ballot compaction into act/typ (capacity act_cap).
+// FILTER: the pairs are swept candidates; only those that pass the
+// candidate predicate at the start positions are considered, and their
+// number is added to *cand_count.
 struct AccdState {
   double lp, g, t, tl;
   int64_t it;
@@ -689,8 +723,11 @@ struct AccdState {
 
 // Set-up of one pair (p is made relative to its mean).  Returns true when
 // the pair is already decided (no relative motion: the bound is t_c).
+// known: s2 holds the pair's squared distance at x, already computed (the
+// same function of the same x).
 template <int KIND>
-__device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, AccdState &st) {
+__device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, AccdState &st, bool known = false,
+                                          double s2 = 0.0) {
 #pragma clang fp contract(off)
   V3 mean;
   mean.x = (((p[0].x + p[1].x) + p[2].x) + p[3].x) * 0.25;
@@ -709,7 +746,7 @@ __device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, Ac
     return true;
   }
   int ty;
-  const double d = sqrt(pair_dist2<KIND>(x, &ty));
+  const double d = sqrt(known ? s2 : pair_dist2<KIND>(x, &ty));
   st.g = s * d;
   st.tl = (1.0 - s) * d / st.lp;
   return false;
