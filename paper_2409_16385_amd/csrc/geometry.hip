@@ -337,7 +337,8 @@ __global__ __launch_bounds__(STAT_T) void k_box_stats(int n, const ItemRec *__re
   }
 }
 
-static int stat_blocks(int n) { return std::max(1, std::min(grid_for(n, STAT_T), 512)); }
+// few workgroups: each ends with 9 atomics on the same 9 words
+static int stat_blocks(int n) { return std::max(1, std::min(grid_for(n, STAT_T), 64)); }
 
 __global__ void k_stats_init(uint64_t *st) {
   int t = threadIdx.x;
