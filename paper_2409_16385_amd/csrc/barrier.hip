@@ -261,7 +261,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_pair_terms(
     const int64_t *__restrict__ d_count, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
     const double *__restrict__ xs, const double *__restrict__ x_rest, int n_vert, double dhat, double kappa,
     uint32_t flags, double *energy, double *__restrict__ gq, double *__restrict__ Xq, int64_t cap,
-    const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
+    const int32_t *__restrict__ vscene, int n_scene, uint32_t *status, const int4 *__restrict__ vid4) {
   __shared__ double s_e[BR_THREADS / 64];
   const bool want_g = gq != nullptr;
   const bool want_h = Xq != nullptr;
@@ -275,10 +275,17 @@ __global__ __launch_bounds__(BR_THREADS) void k_pair_terms(
     double e_pair = 0.0;
     int scene = 0;
     if (live) {
-      const int64_t k = act[i];
       const int ty = typ[i];
       int vid[4];
-      pair_vertices<KIND>(pairs, k, faces, edges, vid);
+      if (vid4) {
+        const int4 v4 = vid4[i];
+        vid[0] = v4.x;
+        vid[1] = v4.y;
+        vid[2] = v4.z;
+        vid[3] = v4.w;
+      } else {
+        pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
+      }
       if (vscene) scene = vscene[vid[0]];
       V3 x[4];
 #pragma unroll
@@ -369,8 +376,7 @@ __device__ __forceinline__ int64_t table_slot64_new(long long *keys, uint64_t ma
 
 template <int KIND>
 __global__ __launch_bounds__(EX_T) void k_expand16(
-    const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int64_t *__restrict__ d_count,
-    const int32_t *__restrict__ faces, const int32_t *__restrict__ edges, const int32_t *__restrict__ rowptr,
+    const int4 *__restrict__ vid4, const int64_t *__restrict__ d_count, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const double *__restrict__ val, int n_node, const double *__restrict__ gq,
     const double *__restrict__ Xq, int64_t cap, double *grad, HessOut h, uint32_t *status) {
   __shared__ long long s_bkey[LTBL];
@@ -402,12 +408,8 @@ __global__ __launch_bounds__(EX_T) void k_expand16(
     double z[3] = {0.0, 0.0, 0.0};
     if (active) {
       const int a = s >> 2, k = s & 3;
-      const int pa = pairs[2 * act[i]], pb = pairs[2 * act[i] + 1];
-      int v;
-      if (KIND == 0)
-        v = a == 0 ? pa : faces[3 * (int64_t)pb + a - 1];
-      else
-        v = a < 2 ? edges[2 * (int64_t)pa + a] : edges[2 * (int64_t)pb + a - 2];
+      const int4 v4 = vid4[i];
+      const int v = a == 0 ? v4.x : (a == 1 ? v4.y : (a == 2 ? v4.z : v4.w));
       const int k0 = rowptr[v];
       if (k < rowptr[v + 1] - k0) {
         node = col[k0 + k];
@@ -561,7 +563,8 @@ template <int KIND>
 __global__ void k_pair_keys(const int32_t *__restrict__ pairs, const int32_t *__restrict__ act,
                             const int64_t *__restrict__ d_count, int64_t cap, const int32_t *__restrict__ faces,
                             const int32_t *__restrict__ edges, const int32_t *__restrict__ rowptr,
-                            const int32_t *__restrict__ col, int n_node, int32_t *__restrict__ key, int32_t *hist) {
+                            const int32_t *__restrict__ col, int n_node, int32_t *__restrict__ key, int32_t *hist,
+                            int4 *__restrict__ vidu) {
   const int64_t n = *d_count < cap ? *d_count : cap;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = base + threadIdx.x;
@@ -578,6 +581,7 @@ __global__ void k_pair_keys(const int32_t *__restrict__ pairs, const int32_t *__
       }
       if ((unsigned)k >= (unsigned)n_node) k = 0;
       key[i] = k;
+      vidu[i] = make_int4(vid[0], vid[1], vid[2], vid[3]);
     }
     wave_key_add(hist, k, live);
   }
@@ -586,7 +590,7 @@ __global__ void k_pair_keys(const int32_t *__restrict__ pairs, const int32_t *__
 __global__ void k_pair_scatter(const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
                                const int64_t *__restrict__ d_count, int64_t cap, const int32_t *__restrict__ key,
                                const int64_t *__restrict__ start, int32_t *fill, int32_t *__restrict__ act2,
-                               int32_t *__restrict__ typ2) {
+                               int32_t *__restrict__ typ2, const int4 *__restrict__ vidu, int4 *__restrict__ vid2) {
   const int64_t n = *d_count < cap ? *d_count : cap;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = base + threadIdx.x;
@@ -597,15 +601,17 @@ __global__ void k_pair_scatter(const int32_t *__restrict__ act, const int32_t *_
       const int64_t pos = start[k] + off;
       act2[pos] = act[i];
       typ2[pos] = typ[i];
+      vid2[pos] = vidu[i];
     }
   }
 }
 
 static eipc_status sort_active(eipc_ctx *c, const eipc_scene *sc, int kind, const int32_t *pairs, const int32_t *act,
                                const int32_t *typ, const int64_t *d_count, int64_t cap, const int32_t **act2,
-                               const int32_t **typ2, hipStream_t s) {
+                               const int32_t **typ2, const int4 **vid2, hipStream_t s) {
   const int nn = std::max(sc->n_node, 1);
   int32_t *key, *hist, *fill, *a2, *t2;
+  int4 *vu, *v2;
   int64_t *start;
   EIPC_TRY(ensure_t(c, B_SKEY, (size_t)cap, &key));
   EIPC_TRY(ensure_t(c, B_SHIST, (size_t)nn + 1, &hist));
@@ -613,21 +619,24 @@ static eipc_status sort_active(eipc_ctx *c, const eipc_scene *sc, int kind, cons
   EIPC_TRY(ensure_t(c, B_SSTART, (size_t)nn + 1, &start));
   EIPC_TRY(ensure_t(c, B_SACT, (size_t)cap, &a2));
   EIPC_TRY(ensure_t(c, B_STYP, (size_t)cap, &t2));
+  EIPC_TRY(ensure_t(c, B_SVIDU, (size_t)cap, &vu));
+  EIPC_TRY(ensure_t(c, B_SVID, (size_t)cap, &v2));
   EIPC_TRY(launch_zero(c, hist, sizeof(int32_t) * (nn + 1), s));
   EIPC_TRY(launch_zero(c, fill, sizeof(int32_t) * (nn + 1), s));
   const int blocks = (int)std::min<int64_t>(grid_for(cap, 256), 8 * (int64_t)c->num_cu);
   if (kind == 0)
     k_pair_keys<0><<<blocks, 256, 0, s>>>(pairs, act, d_count, cap, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                          nn, key, hist);
+                                          nn, key, hist, vu);
   else
     k_pair_keys<1><<<blocks, 256, 0, s>>>(pairs, act, d_count, cap, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                          nn, key, hist);
+                                          nn, key, hist, vu);
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, hist, nn, start, s));
-  k_pair_scatter<<<blocks, 256, 0, s>>>(act, typ, d_count, cap, key, start, fill, a2, t2);
+  k_pair_scatter<<<blocks, 256, 0, s>>>(act, typ, d_count, cap, key, start, fill, a2, t2, vu, v2);
   EIPC_HIP(c, hipGetLastError());
   *act2 = a2;
   *typ2 = t2;
+  if (vid2) *vid2 = v2;
   return EIPC_OK;
 }
 
@@ -642,7 +651,8 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
   const int64_t cap = max_count;
   if (want_g) EIPC_TRY(ensure_t(c, kind == 0 ? B_PG_PT : B_PG_EE, (size_t)9 * cap, &gq));
   if (want_h) EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)45 * cap, &Xq));
-  if (want_g || want_h) EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, cap, &act, &typ, s));
+  const int4 *vid4 = nullptr;  // vertex ids of the sorted pairs
+  if (want_g || want_h) EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, cap, &act, &typ, &vid4, s));
   {
     int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), (int64_t)c->wg_per_cu[0] * c->num_cu);
     ProfScope ps(c, kind == 0 ? K_BARRIER_PT : K_BARRIER_EE, s);
@@ -651,11 +661,11 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
     if (kind == 0)
       k_pair_terms<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
                                                      sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap, vsc, nsc,
-                                                     c->status);
+                                                     c->status, vid4);
     else
       k_pair_terms<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
                                                      sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap, vsc, nsc,
-                                                     c->status);
+                                                     c->status, vid4);
     EIPC_HIP(c, hipGetLastError());
   }
   if (!want_g && !want_h) return EIPC_OK;
@@ -663,11 +673,11 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
     int blocks = (int)std::min<int64_t>(grid_for(max_count, EX_T / 16), (int64_t)c->wg_per_cu[1] * c->num_cu);
     ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
     if (kind == 0)
-      k_expand16<0><<<blocks, EX_T, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                             sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
+      k_expand16<0><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
+                                             cap, grad, h, c->status);
     else
-      k_expand16<1><<<blocks, EX_T, 0, s>>>(pairs, act, d_count, sc->faces, sc->edges, sc->W_rowptr, sc->W_col,
-                                             sc->W_val, sc->n_node, gq, Xq, cap, grad, h, c->status);
+      k_expand16<1><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
+                                             cap, grad, h, c->status);
     EIPC_HIP(c, hipGetLastError());
   }
   return EIPC_OK;
@@ -1002,7 +1012,7 @@ eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double
                        int64_t max_count, double dhat, double kappa, uint32_t flags, double *out,
                        double *out_off, hipStream_t s) {
   if (max_count == 0) return EIPC_OK;
-  EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, max_count, &act, &typ, s));
+  EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, max_count, &act, &typ, nullptr, s));
   int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 4 * (int64_t)c->num_cu);
   ProfScope ps(c, kind == 0 ? K_HVP_PT : K_HVP_EE, s);
   if (kind == 0)

@@ -39,6 +39,7 @@ enum BufId {
   B_ALPHA,                             // per-scene step bound bits
   B_PLAN_OUT,                          // outputs of the reserving step of a plan
   B_SKEY, B_SHIST, B_SFILL, B_SSTART, B_SACT, B_STYP,  // locality sort of active pairs
+  B_SVIDU, B_SVID,                                   // their vertex ids (unsorted, sorted)
   B_CCD_LONG_PT, B_CCD_LONG_EE,                        // CCD pairs deferred to the second pass
   B_BP0,                               // broad-phase scratch: 4 slots (kind, swept) x BP_NBUF
   B_NUM = B_BP0 + 4 * 17
