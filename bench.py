@@ -42,7 +42,8 @@ EE_FN = ["PP", "PP", "PP", "PP", "PL", "PL", "PL", "PL", "TRI"]
 FAMILIES = {
     "query": ("query_count_pt", "query_count_ee", "query_write_pt", "query_write_ee"),
     "pair_terms": ("barrier_pt", "barrier_ee"), "expand": ("expand_pt", "expand_ee"),
-    "narrow": ("narrow_pt", "narrow_ee"), "ccd": ("ccd_pt", "ccd_ee"), "embed": ("embed",),
+    "narrow": ("narrow_pt", "narrow_ee"), "ccd": ("ccd_pt", "ccd_ee", "ccd_long_pt", "ccd_long_ee"),
+    "embed": ("embed",),
 }
 
 

@@ -273,8 +273,10 @@ eipc_status eipc_profile(eipc_ctx *ctx, int32_t enable);
 /* Synchronizes on the recorded events and returns, for the kernel `name`
  * ("embed", "query_count_pt", "query_count_ee", "query_write_pt",
  * "query_write_ee", "narrow_pt", "narrow_ee", "barrier_pt", "barrier_ee",
- * "expand_pt", "expand_ee", "ccd_pt", "ccd_ee", "hvp_pt", "hvp_ee"), the
- * summed milliseconds and the
+ * "expand_pt", "expand_ee", "ccd_pt", "ccd_ee", "ccd_long_pt", "ccd_long_ee",
+ * "hvp_pt", "hvp_ee"; in the planned step with a step bound "ccd_*" is the
+ * narrow phase fused with the bound's first pass and "ccd_long_*" the pass
+ * for pairs needing more advancement steps), the summed milliseconds and the
  * number of timed launches since the last reset.  reset != 0 clears all
  * totals after reading.  ms and launches are host pointers. */
 eipc_status eipc_profile_read(eipc_ctx *ctx, const char *name, double *ms, int64_t *launches, int32_t reset);

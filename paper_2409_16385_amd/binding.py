@@ -160,7 +160,7 @@ class Context:
 
     KERNELS = ("embed", "query_count_pt", "query_count_ee", "query_write_pt", "query_write_ee", "narrow_pt",
                "narrow_ee", "barrier_pt", "barrier_ee", "ccd_pt", "ccd_ee", "hvp_pt", "hvp_ee", "expand_pt",
-               "expand_ee")
+               "expand_ee", "ccd_long_pt", "ccd_long_ee")
 
     def profile(self, enable: bool = True):
         """Per-kernel HIP-event timing inside the library (on the launch stream)."""

@@ -21,7 +21,8 @@ eipc_status set_err(eipc_ctx *c, eipc_status st, const char *fmt, ...) {
 const char *const kKernelNames[K_NUM] = {"embed",        "query_count_pt", "query_count_ee", "query_write_pt",
                                          "query_write_ee", "narrow_pt",     "narrow_ee",      "barrier_pt",
                                          "barrier_ee",     "ccd_pt",        "ccd_ee",         "hvp_pt",
-                                         "hvp_ee",         "expand_pt",     "expand_ee"};
+                                         "hvp_ee",         "expand_pt",     "expand_ee",      "ccd_long_pt",
+                                         "ccd_long_ee"};
 
 static hipEvent_t take_event(eipc_ctx *c) {
   if (!c->prof_pool.empty()) {
@@ -205,6 +206,12 @@ eipc_status eipc_create(eipc_ctx **out, int32_t device) {
     eipc_destroy(c);
     return EIPC_ERR_HIP;
   }
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+    eipc_destroy(c);
+    return EIPC_ERR_HIP;
+  }
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->num_cu = ncu;
@@ -223,6 +230,9 @@ void eipc_destroy(eipc_ctx *c) {
   if (c->status) hipFree(c->status);
   if (c->stats) hipFree(c->stats);
   if (c->counters) hipFree(c->counters);
+  if (c->fork_ev) hipEventDestroy(c->fork_ev);
+  if (c->join_ev) hipEventDestroy(c->join_ev);
+  if (c->side) hipStreamDestroy(c->side);
   delete c;
 }
 
@@ -617,6 +627,15 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
                                cn + 2, cn + 5, sfac, t_max, max_iter, (uint64_t *)alpha, s));
     EIPC_TRY(launch_narrow_ccd(c, sc, 1, xs, ps, cee, plan->swept_ee, cn + 8, dhat, act_ee, typ_ee, plan->act_ee,
                                cn + 3, cn + 6, sfac, t_max, max_iter, (uint64_t *)alpha, s));
+    // the pairs needing more advancement steps run on the side stream,
+    // beside the barrier terms and their reduction
+    EIPC_HIP(c, hipEventRecord(c->fork_ev, s));
+    EIPC_HIP(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
+    EIPC_TRY(launch_ccd_long(c, sc, 0, xs, ps, cpt, plan->swept_pt, cn + 7, sfac, t_max, max_iter, (uint64_t *)alpha,
+                             c->side));
+    EIPC_TRY(launch_ccd_long(c, sc, 1, xs, ps, cee, plan->swept_ee, cn + 8, sfac, t_max, max_iter, (uint64_t *)alpha,
+                             c->side));
+    EIPC_HIP(c, hipEventRecord(c->join_ev, c->side));
     pt = cpt;
     ee = cee;
   } else {
@@ -643,6 +662,7 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, cn + 3, plan->act_ee, dhat, kappa, f, energy, g, h, s));
   }
   if (want_h) EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s, plan->nnzb));
+  if (alpha) EIPC_HIP(c, hipStreamWaitEvent(s, c->join_ev, 0));
   if (counts) {
     k_step_counts<<<1, 64, 0, s>>>(cn, counts);
     EIPC_HIP(c, hipGetLastError());

@@ -259,7 +259,6 @@ eipc_status launch_narrow_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const
                               int32_t *typ, int64_t act_cap, int64_t *d_count, int64_t *cand_count, double sfac,
                               double t_max, int64_t max_iter, uint64_t *d_alpha_bits, hipStream_t s) {
   if (n == 0) return EIPC_OK;
-  ProfScope prof(c, kind == 0 ? K_CCD_PT : K_CCD_EE, s);
   const int blocks = (int)std::min<int64_t>(grid_for(n, 256), (int64_t)c->wg_per_cu[3] * c->num_cu);
   const int32_t *vsc = vscene_of(sc);
   const int nsc = n_scene_of(sc);
@@ -269,19 +268,39 @@ eipc_status launch_narrow_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const
   EIPC_TRY(launch_zero(c, n_long, 8, s));
   unsigned long long *ab = (unsigned long long *)d_alpha_bits;
   const double d2 = dhat * dhat, h = 0.5 * dhat;
-  if (kind == 0) {
-    k_narrow_ccd<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ, act_cap,
-                                           d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long, vsc, nsc,
-                                           c->status);
+  {
+    ProfScope prof(c, kind == 0 ? K_CCD_PT : K_CCD_EE, s);
+    if (kind == 0)
+      k_narrow_ccd<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ,
+                                             act_cap, d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long,
+                                             vsc, nsc, c->status);
+    else
+      k_narrow_ccd<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ,
+                                             act_cap, d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long,
+                                             vsc, nsc, c->status);
+    EIPC_HIP(c, hipGetLastError());
+  }
+  return EIPC_OK;
+}
+
+eipc_status launch_ccd_long(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
+                            const int32_t *pairs, int64_t n, const int64_t *d_n, double sfac, double t_max,
+                            int64_t max_iter, uint64_t *d_alpha_bits, hipStream_t s) {
+  if (n == 0) return EIPC_OK;
+  const int blocks = (int)std::min<int64_t>(grid_for(n, 256), (int64_t)c->wg_per_cu[3] * c->num_cu);
+  const int32_t *vsc = vscene_of(sc);
+  const int nsc = n_scene_of(sc);
+  int64_t *n_long = c->counters + 9 + kind;
+  int32_t *longl;
+  EIPC_TRY(ensure_t(c, kind == 0 ? B_CCD_LONG_PT : B_CCD_LONG_EE, (size_t)n, &longl));
+  unsigned long long *ab = (unsigned long long *)d_alpha_bits;
+  ProfScope prof(c, kind == 0 ? K_CCD_LONG_PT : K_CCD_LONG_EE, s);
+  if (kind == 0)
     k_ccd2<0, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
                                         max_iter, ab, longl, n_long, vsc, nsc, c->status);
-  } else {
-    k_narrow_ccd<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ, act_cap,
-                                           d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long, vsc, nsc,
-                                           c->status);
+  else
     k_ccd2<1, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
                                         max_iter, ab, longl, n_long, vsc, nsc, c->status);
-  }
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }

@@ -71,7 +71,8 @@ struct DevBuf {
 // kernels timed by the optional event profiler
 enum KernelId {
   K_EMBED = 0, K_QUERY_COUNT_PT, K_QUERY_COUNT_EE, K_QUERY_WRITE_PT, K_QUERY_WRITE_EE, K_NARROW_PT, K_NARROW_EE,
-  K_BARRIER_PT, K_BARRIER_EE, K_CCD_PT, K_CCD_EE, K_HVP_PT, K_HVP_EE, K_EXPAND_PT, K_EXPAND_EE, K_NUM
+  K_BARRIER_PT, K_BARRIER_EE, K_CCD_PT, K_CCD_EE, K_HVP_PT, K_HVP_EE, K_EXPAND_PT, K_EXPAND_EE, K_CCD_LONG_PT,
+  K_CCD_LONG_EE, K_NUM
 };
 extern const char *const kKernelNames[K_NUM];
 
@@ -103,6 +104,10 @@ struct eipc_ctx {
   std::vector<hipEvent_t> prof_pool;        // reusable events
   double prof_ms[eipc::K_NUM] = {0};
   int64_t prof_n[eipc::K_NUM] = {0};
+  // second stream (default priority) for work that runs beside the step's
+  // main chain; joined back through events, also under graph capture
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace eipc {
@@ -232,12 +237,16 @@ eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double
                        uint64_t *d_alpha_bits, double *t_out, int64_t *it_out, hipStream_t s,
                        const int64_t *d_n = nullptr);
 // Planned step with a step bound: narrow phase of the swept candidates
-// (as launch_narrow with cand_count) and the step bound (as launch_ccd
-// into d_alpha_bits) in one sweep, plus the pass for long pairs.
+// (as launch_narrow with cand_count) and the step bound's first pass (as
+// launch_ccd into d_alpha_bits) in one sweep; launch_ccd_long then runs
+// the pairs that pass deferred (may go on another stream ordered after it).
 eipc_status launch_narrow_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
                               const int32_t *pairs, int64_t n, const int64_t *d_n, double dhat, int32_t *act,
                               int32_t *typ, int64_t act_cap, int64_t *d_count, int64_t *cand_count, double sfac,
                               double t_max, int64_t max_iter, uint64_t *d_alpha_bits, hipStream_t s);
+eipc_status launch_ccd_long(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,
+                            const int32_t *pairs, int64_t n, const int64_t *d_n, double sfac, double t_max,
+                            int64_t max_iter, uint64_t *d_alpha_bits, hipStream_t s);
 eipc_status launch_fp64_selftest(eipc_ctx *c, const double *a, const double *b, double *sq, double *dv, int64_t n,
                                  hipStream_t s);
 
