@@ -605,39 +605,52 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
   EIPC_TRY(ensure_t(c, B_TYP_PT, (size_t)std::max<int64_t>(plan->act_pt, 1), &typ_pt));
   EIPC_TRY(ensure_t(c, B_ACT_EE, (size_t)std::max<int64_t>(plan->act_ee, 1), &act_ee));
   EIPC_TRY(ensure_t(c, B_TYP_EE, (size_t)std::max<int64_t>(plan->act_ee, 1), &typ_ee));
-  const int32_t *pt, *ee;
-  double *ps = nullptr;
-  int32_t *cpt = nullptr, *cee = nullptr;
+  // barrier targets, cleared before any pair is added
+  const int64_t n3 = 3 * (int64_t)sc->n_node;
+  if (energy) EIPC_TRY(launch_zero(c, energy, sizeof(double) * n_scene_of(sc), s));
+  double *g = (flags & EIPC_GRAD) ? grad_q : nullptr;
+  if (g) EIPC_TRY(launch_zero(c, g, sizeof(double) * n3, s));
+  HessOut h{0, nullptr, nullptr, nullptr, 0};
+  if (want_h) EIPC_TRY(hess_table(c, plan->hess_blocks, h, s));
+  const uint32_t f = flags & (want_h ? ~0u : ~(uint32_t)EIPC_HESS);
+  const bool barrier = energy || g || want_h;
   if (alpha) {
-    // one swept broad phase; candidates at q filtered from it pair by pair
-    double *x1s;
+    // one swept broad phase per kind; candidates at q filtered from it pair
+    // by pair in the same sweep as the step bound's first pass.  The PT
+    // chain runs on the side stream beside the EE chain; they share only
+    // targets that are accumulated atomically (energy, gradient, Hessian
+    // table, step bounds, status).
+    double *ps, *x1s;
+    int32_t *cpt, *cee;
     EIPC_TRY(ensure_t(c, B_P, (size_t)n3v + 1, &ps));
     EIPC_TRY(ensure_t(c, B_X1, (size_t)n3v + 1, &x1s));
     EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
     EIPC_TRY(launch_add_soa(c, n3v, xs, ps, x1s, s));
     EIPC_TRY(ensure_t(c, B_CAND_PT, (size_t)2 * std::max<int64_t>(plan->swept_pt, 1), &cpt));
     EIPC_TRY(ensure_t(c, B_CAND_EE, (size_t)2 * std::max<int64_t>(plan->swept_ee, 1), &cee));
-    EIPC_TRY(broad_phase(c, sc, 0, xs, x1s, dhat, cpt, plan->swept_pt, nullptr, 0, s, -1, nullptr, &bp[2], cn + 7));
-    EIPC_TRY(broad_phase(c, sc, 1, xs, x1s, dhat, cee, plan->swept_ee, nullptr, 0, s, -1, nullptr, &bp[3], cn + 8));
-    // narrow phase and step bound in one sweep over the swept candidates
     uint64_t tb;
     std::memcpy(&tb, &t_max, 8);
     EIPC_TRY(fill_u64(c, (uint64_t *)alpha, n_scene_of(sc), tb, s));
-    EIPC_TRY(launch_narrow_ccd(c, sc, 0, xs, ps, cpt, plan->swept_pt, cn + 7, dhat, act_pt, typ_pt, plan->act_pt,
-                               cn + 2, cn + 5, sfac, t_max, max_iter, (uint64_t *)alpha, s));
-    EIPC_TRY(launch_narrow_ccd(c, sc, 1, xs, ps, cee, plan->swept_ee, cn + 8, dhat, act_ee, typ_ee, plan->act_ee,
-                               cn + 3, cn + 6, sfac, t_max, max_iter, (uint64_t *)alpha, s));
-    // the pairs needing more advancement steps run on the side stream,
-    // beside the barrier terms and their reduction
     EIPC_HIP(c, hipEventRecord(c->fork_ev, s));
     EIPC_HIP(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
-    EIPC_TRY(launch_ccd_long(c, sc, 0, xs, ps, cpt, plan->swept_pt, cn + 7, sfac, t_max, max_iter, (uint64_t *)alpha,
-                             c->side));
-    EIPC_TRY(launch_ccd_long(c, sc, 1, xs, ps, cee, plan->swept_ee, cn + 8, sfac, t_max, max_iter, (uint64_t *)alpha,
-                             c->side));
+    for (int kind = 0; kind < 2; ++kind) {
+      hipStream_t st = kind == 0 ? c->side : s;
+      int32_t *cand = kind == 0 ? cpt : cee;
+      int32_t *act = kind == 0 ? act_pt : act_ee, *typ = kind == 0 ? typ_pt : typ_ee;
+      const int64_t swept_cap = kind == 0 ? plan->swept_pt : plan->swept_ee;
+      const int64_t act_cap = kind == 0 ? plan->act_pt : plan->act_ee;
+      EIPC_TRY(broad_phase(c, sc, kind, xs, x1s, dhat, cand, swept_cap, nullptr, 0, st, -1, nullptr, &bp[2 + kind],
+                           cn + 7 + kind));
+      EIPC_TRY(launch_narrow_ccd(c, sc, kind, xs, ps, cand, swept_cap, cn + 7 + kind, dhat, act, typ, act_cap,
+                                 cn + 2 + kind, cn + 5 + kind, sfac, t_max, max_iter, (uint64_t *)alpha, st));
+      EIPC_TRY(launch_ccd_long(c, sc, kind, xs, ps, cand, swept_cap, cn + 7 + kind, sfac, t_max, max_iter,
+                               (uint64_t *)alpha, st));
+      if (barrier)
+        EIPC_TRY(launch_barrier(c, sc, kind, xs, cand, act, typ, cn + 2 + kind, act_cap, dhat, kappa, f, energy, g,
+                                h, st));
+    }
     EIPC_HIP(c, hipEventRecord(c->join_ev, c->side));
-    pt = cpt;
-    ee = cee;
+    EIPC_HIP(c, hipStreamWaitEvent(s, c->join_ev, 0));
   } else {
     int32_t *ppt, *pee;
     EIPC_TRY(ensure_t(c, B_STEP_PT, (size_t)2 * std::max<int64_t>(plan->cand_pt, 1), &ppt));
@@ -646,23 +659,14 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     EIPC_TRY(broad_phase(c, sc, 1, xs, nullptr, dhat, pee, plan->cand_ee, nullptr, 0, s, -1, nullptr, &bp[1], cn + 6));
     EIPC_TRY(launch_narrow(c, sc, 0, xs, ppt, plan->cand_pt, dhat, act_pt, typ_pt, cn + 2, s, cn + 5, plan->act_pt));
     EIPC_TRY(launch_narrow(c, sc, 1, xs, pee, plan->cand_ee, dhat, act_ee, typ_ee, cn + 3, s, cn + 6, plan->act_ee));
-    pt = ppt;
-    ee = pee;
-  }
-  // barrier terms and reduction
-  const int64_t n3 = 3 * (int64_t)sc->n_node;
-  if (energy) EIPC_TRY(launch_zero(c, energy, sizeof(double) * n_scene_of(sc), s));
-  double *g = (flags & EIPC_GRAD) ? grad_q : nullptr;
-  if (g) EIPC_TRY(launch_zero(c, g, sizeof(double) * n3, s));
-  HessOut h{0, nullptr, nullptr, nullptr, 0};
-  if (want_h) EIPC_TRY(hess_table(c, plan->hess_blocks, h, s));
-  const uint32_t f = flags & (want_h ? ~0u : ~(uint32_t)EIPC_HESS);
-  if (energy || g || want_h) {
-    EIPC_TRY(launch_barrier(c, sc, 0, xs, pt, act_pt, typ_pt, cn + 2, plan->act_pt, dhat, kappa, f, energy, g, h, s));
-    EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, cn + 3, plan->act_ee, dhat, kappa, f, energy, g, h, s));
+    if (barrier) {
+      EIPC_TRY(launch_barrier(c, sc, 0, xs, ppt, act_pt, typ_pt, cn + 2, plan->act_pt, dhat, kappa, f, energy, g, h,
+                              s));
+      EIPC_TRY(launch_barrier(c, sc, 1, xs, pee, act_ee, typ_ee, cn + 3, plan->act_ee, dhat, kappa, f, energy, g, h,
+                              s));
+    }
   }
   if (want_h) EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s, plan->nnzb));
-  if (alpha) EIPC_HIP(c, hipStreamWaitEvent(s, c->join_ev, 0));
   if (counts) {
     k_step_counts<<<1, 64, 0, s>>>(cn, counts);
     EIPC_HIP(c, hipGetLastError());

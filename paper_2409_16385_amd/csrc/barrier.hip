@@ -613,14 +613,16 @@ static eipc_status sort_active(eipc_ctx *c, const eipc_scene *sc, int kind, cons
   int32_t *key, *hist, *fill, *a2, *t2;
   int4 *vu, *v2;
   int64_t *start;
-  EIPC_TRY(ensure_t(c, B_SKEY, (size_t)cap, &key));
-  EIPC_TRY(ensure_t(c, B_SHIST, (size_t)nn + 1, &hist));
-  EIPC_TRY(ensure_t(c, B_SFILL, (size_t)nn + 1, &fill));
-  EIPC_TRY(ensure_t(c, B_SSTART, (size_t)nn + 1, &start));
-  EIPC_TRY(ensure_t(c, B_SACT, (size_t)cap, &a2));
-  EIPC_TRY(ensure_t(c, B_STYP, (size_t)cap, &t2));
-  EIPC_TRY(ensure_t(c, B_SVIDU, (size_t)cap, &vu));
-  EIPC_TRY(ensure_t(c, B_SVID, (size_t)cap, &v2));
+  // per kind, so that the two kinds can be sorted concurrently
+  const bool e = kind != 0;
+  EIPC_TRY(ensure_t(c, e ? B_SKEY_EE : B_SKEY, (size_t)cap, &key));
+  EIPC_TRY(ensure_t(c, e ? B_SHIST_EE : B_SHIST, (size_t)nn + 1, &hist));
+  EIPC_TRY(ensure_t(c, e ? B_SFILL_EE : B_SFILL, (size_t)nn + 1, &fill));
+  EIPC_TRY(ensure_t(c, e ? B_SSTART_EE : B_SSTART, (size_t)nn + 1, &start));
+  EIPC_TRY(ensure_t(c, e ? B_SACT_EE : B_SACT, (size_t)cap, &a2));
+  EIPC_TRY(ensure_t(c, e ? B_STYP_EE : B_STYP, (size_t)cap, &t2));
+  EIPC_TRY(ensure_t(c, e ? B_SVIDU_EE : B_SVIDU, (size_t)cap, &vu));
+  EIPC_TRY(ensure_t(c, e ? B_SVID_EE : B_SVID, (size_t)cap, &v2));
   EIPC_TRY(launch_zero(c, hist, sizeof(int32_t) * (nn + 1), s));
   EIPC_TRY(launch_zero(c, fill, sizeof(int32_t) * (nn + 1), s));
   const int blocks = (int)std::min<int64_t>(grid_for(cap, 256), 8 * (int64_t)c->num_cu);

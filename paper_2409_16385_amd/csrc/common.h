@@ -30,6 +30,7 @@ enum BufId {
   B_X1,          // CCD end positions, SoA
   B_XV,          // HVP input mapped to vertices, SoA
   B_SCANTMP,     // int64 block sums
+  B_SCANTMP_SIDE,  // the same, for scans on the side stream
   B_ACT_PT, B_TYP_PT, B_ACT_EE, B_TYP_EE,
   B_CAND_PT, B_CAND_EE,  // swept candidates (CCD)
   B_HKEY, B_HVAL,        // global block hash
@@ -40,6 +41,7 @@ enum BufId {
   B_PLAN_OUT,                          // outputs of the reserving step of a plan
   B_SKEY, B_SHIST, B_SFILL, B_SSTART, B_SACT, B_STYP,  // locality sort of active pairs
   B_SVIDU, B_SVID,                                   // their vertex ids (unsorted, sorted)
+  B_SKEY_EE, B_SHIST_EE, B_SFILL_EE, B_SSTART_EE, B_SACT_EE, B_STYP_EE, B_SVIDU_EE, B_SVID_EE,  // the same for EE
   B_CCD_LONG_PT, B_CCD_LONG_EE,                        // CCD pairs deferred to the second pass
   B_BP0,                               // broad-phase scratch: 4 slots (kind, swept) x BP_NBUF
   B_NUM = B_BP0 + 4 * 17

@@ -185,7 +185,7 @@ eipc_status exclusive_scan(eipc_ctx *c, const int32_t *in, int64_t n, int64_t *o
   int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (nb < 1) nb = 1;
   int64_t *bsum;
-  EIPC_TRY(ensure_t(c, B_SCANTMP, (size_t)nb + 1, &bsum));
+  EIPC_TRY(ensure_t(c, s == c->side ? B_SCANTMP_SIDE : B_SCANTMP, (size_t)nb + 1, &bsum));
   k_scan_partial<<<(unsigned)nb, SCAN_T, 0, s>>>(in, n, bsum);
   EIPC_HIP(c, hipGetLastError());
   k_scan_top<<<1, 1024, 0, s>>>(bsum, nb);
