@@ -200,9 +200,9 @@ class Batch:
                  reps: int = 3, margin: float = 1.5, verbose: bool = False) -> dict:
         """Pick the broad-phase cell scale and work split per query kind
         (whole-step time, re-planning for each pair of values), then for
-        each grid-stride kernel family the workgroups per CU with the
-        smallest kernel time (per-kernel event timing)."""
-        wg = list(self.tuning["wg_per_cu"])
+        each grid-stride kernel family in turn the workgroups per CU
+        (values from wg_values, whole-step time)."""
+        wg = [wg_values[len(wg_values) // 2]] * 4
         best = None
         trace = []
         for cs in cell_scales:
@@ -218,26 +218,23 @@ class Batch:
         cs, qm = best[0], best[1]
         B.set_tuning(self.ctx, cs, wg, qm)
         self.make_plan(margin)
-        families = (("barrier_pt", "barrier_ee"), ("expand_pt", "expand_ee"), ("narrow_pt", "narrow_ee"),
-                    ("ccd_pt", "ccd_ee"))
-        kbest = [None] * 4
-        for v in wg_values:
-            B.set_tuning(self.ctx, cs, [v] * 4, qm)
-            self.step()
-            torch.cuda.synchronize(self.ctx.torch_device)
-            self.ctx.profile(True)
-            self.ctx.profile_read(reset=True)
-            for _ in range(reps):
-                self.step()
-            prof = self.ctx.profile_read(reset=True)
-            self.ctx.profile(False)
-            for k, fam in enumerate(families):
-                t = sum(prof[n][0] for n in fam) / reps
-                trace.append((fam[0].split("_")[0], v, t))
-                if kbest[k] is None or t < kbest[k][1]:
-                    kbest[k] = (v, t)
-        wg = [kb[0] for kb in kbest]
-        B.set_tuning(self.ctx, cs, wg, qm)
+        # workgroups per CU of each grid-stride family (pair terms,
+        # expansion, narrow phase, CCD) by coordinate descent on the whole
+        # step time: the two kinds' chains run concurrently, so a kernel's
+        # own time is not the step's
+        best_ms = self._time_steps(reps)
+        for k in range(4):
+            for v in wg_values:
+                if v == wg[k]:
+                    continue
+                trial = list(wg)
+                trial[k] = v
+                B.set_tuning(self.ctx, cs, trial, qm)
+                ms = self._time_steps(reps)
+                trace.append((f"wg_per_cu[{k}]", v, ms))
+                if ms < best_ms:
+                    best_ms, wg = ms, trial
+            B.set_tuning(self.ctx, cs, wg, qm)
         self.tuning = {"cell_scale": cs, "wg_per_cu": wg, "query_cells": qm, "trace": trace}
         self.make_plan(margin)
         if verbose:
