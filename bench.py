@@ -105,9 +105,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, workload):
+def load_traffic(kernel, workload, tuning=None):
     """HBM bytes per launch from committed counter summaries, when taken
-    with the current sources."""
+    with the current sources and the same broad-phase tuning (cell scale
+    and work split; workgroups per CU barely move the bytes)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -116,6 +117,10 @@ def load_traffic(kernel, workload):
     e = t.get(f"{workload}:{kernel}")
     if not e or e.get("sources") != source_digest():
         return None
+    if tuning is not None and e.get("tuning"):
+        v = [float(x) for x in e["tuning"].split(",")]
+        if v[0] != float(tuning["cell_scale"]) or int(v[5]) != int(tuning["query_cells"]):
+            return None
     return e.get("bytes_per_launch")
 
 
@@ -191,7 +196,7 @@ def _timed(fn, reps, sync):
     return 1e3 * (time.perf_counter() - t0) / reps
 
 
-def _rooflines(prof, n_steps, work, workload):
+def _rooflines(prof, n_steps, work, workload, tuning=None):
     """Per-family averages and the roofline entry of the dominant family.
     work: active pairs per type, candidate and query counts of one step."""
     fam_ms = {f: sum(prof.get(k, (0.0, 0))[0] for k in ks) / n_steps for f, ks in FAMILIES.items()}
@@ -211,9 +216,10 @@ def _rooflines(prof, n_steps, work, workload):
                    per_unit=(f"{FLOPS_TERMS}+distance flop per active pair" if dom == "pair_terms"
                              else f"{FLOPS_EXPAND} flop per active pair"))
     else:
-        # compulsory bytes: query = query records + item table + pairs out;
-        # narrow = pair ids + 4 gathered vertices + type/index out;
-        # ccd = pair ids + 4 vertices x (x, p)
+        # algorithmic bytes: query = query records + item table + pairs out;
+        # narrow = pair ids + 4 gathered vertices + type/index out; ccd
+        # (fused with the narrow phase) = pair ids + vertex records once +
+        # active pairs out
         kind = 0 if kdom.endswith("_pt") else 1
         if dom == "query":
             swept = kdom.startswith("query_write") and work.get("swept_query", False)
@@ -226,18 +232,21 @@ def _rooflines(prof, n_steps, work, workload):
             nbytes = work["cand"][kind] * (8 + 4 * 24) + 8 * work["active"][kind]
             per_unit = "104 B per candidate + 8 B per active pair"
         elif dom == "ccd":
-            # planned step: narrow phase fused in (active pairs written)
-            nbytes = work["swept"][kind] * (8 + 4 * 48) + 8 * work["active"][kind]
-            per_unit = "200 B per swept candidate + 8 B per active pair"
+            # planned step, narrow phase fused in: the swept list read, the
+            # active pairs written, each vertex's position and displacement
+            # records (32 B each) read once (the per-pair gathers of them
+            # are cache traffic, not compulsory)
+            nbytes = work["swept"][kind] * 8 + 8 * work["active"][kind] + 64 * work["n_vert"]
+            per_unit = "8 B per swept candidate + 8 B per active pair + 64 B per vertex"
         else:
             nbytes = work["n_vert"] * (24 + 24 + 16 * 4)
             per_unit = "112 B per vertex"
         ach = nbytes / avg_s / 1e9
         ent.update(bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS,
                    per_unit=per_unit)
-        tb = load_traffic(kdom, workload)
-        if tb is not None:
-            ent["traffic"] = tb
+    tb = load_traffic(kdom, workload, tuning)
+    if tb is not None:
+        ent["traffic"] = tb
     ent["family_ms_per_step"] = {f: round(v, 4) for f, v in fam_ms.items()}
     ent["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1]}
     for k, kind in (("barrier_pt", 0), ("barrier_ee", 1)):
@@ -364,7 +373,7 @@ def main():
             if n:
                 log(f"kernel {k:16s} {ms / n * 1e3:10.1f} us/launch x {n}")
     workload = a.config
-    roofline = _rooflines(prof, max(3, min(a.steps, 10)), work, workload) if prof else None
+    roofline = _rooflines(prof, max(3, min(a.steps, 10)), work, workload, tuning) if prof else None
 
     out = {
         "metric": METRIC, "value": n_active / (ms_per_step / 1e3), "unit": "contact pairs/s", "n_gpus": 1,

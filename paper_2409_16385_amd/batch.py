@@ -201,7 +201,8 @@ class Batch:
         """Pick the broad-phase cell scale and work split per query kind
         (whole-step time, re-planning for each pair of values), then for
         each grid-stride kernel family in turn the workgroups per CU
-        (values from wg_values, whole-step time)."""
+        (values from wg_values, whole-step time; a change is kept when it
+        saves more than 2%)."""
         wg = [wg_values[len(wg_values) // 2]] * 4
         best = None
         trace = []
@@ -232,7 +233,7 @@ class Batch:
                 B.set_tuning(self.ctx, cs, trial, qm)
                 ms = self._time_steps(reps)
                 trace.append((f"wg_per_cu[{k}]", v, ms))
-                if ms < best_ms:
+                if ms < 0.98 * best_ms:  # a change must beat timing noise
                     best_ms, wg = ms, trial
             B.set_tuning(self.ctx, cs, wg, qm)
         self.tuning = {"cell_scale": cs, "wg_per_cu": wg, "query_cells": qm, "trace": trace}

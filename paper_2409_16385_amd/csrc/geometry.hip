@@ -337,8 +337,9 @@ __global__ __launch_bounds__(STAT_T) void k_box_stats(int n, const ItemRec *__re
   }
 }
 
-// few workgroups: each ends with 9 atomics on the same 9 words
-static int stat_blocks(int n) { return std::max(1, std::min(grid_for(n, STAT_T), 64)); }
+// a bounded number of workgroups: each ends with 9 atomics on the same 9
+// words, and too few leave each thread hundreds of items on large batches
+static int stat_blocks(int n) { return std::max(1, std::min(grid_for(n, STAT_T), 256)); }
 
 __global__ void k_stats_init(uint64_t *st) {
   int t = threadIdx.x;
