@@ -45,8 +45,11 @@ def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
 
 
-@pytest.mark.parametrize("cs", [1.0, 2.0, 4.0])
+@pytest.mark.parametrize("cs", [0.3, 1.0, 2.0, 4.0])
 def test_candidates_bit_exact(ctx, sc, ref, cs):
+    """At cell scale 0.3 each sheet primitive covers tens of cells, so a
+    workgroup's entries reach more distinct buckets than its LDS bucket
+    table holds and part of them take the global counters directly."""
     E.set_tuning(ctx, cs)
     dsc = E.Scene.from_host(ctx, sc)
     pt, ee = E.build_candidates(ctx, dsc, _dev(sc.q), sc.dhat)
@@ -55,7 +58,7 @@ def test_candidates_bit_exact(ctx, sc, ref, cs):
     E.set_tuning(ctx, 2.0)
 
 
-@pytest.mark.parametrize("cs", [1.0, 2.0])
+@pytest.mark.parametrize("cs", [0.3, 1.0, 2.0])
 @pytest.mark.parametrize("mode", SPLITS)
 def test_step_bound_every_split(ctx, sc, ref, mode, cs):
     E.set_tuning(ctx, cs, (0, 0, 0, 0), mode)
