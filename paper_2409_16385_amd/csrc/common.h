@@ -98,7 +98,7 @@ struct eipc_ctx {
   double cell_scale = 2.0;       // broad-phase cell edge / mean item extent
   int wg_per_cu[4] = {8, 2, 4, 4};  // grid sizes: pair terms, expansion, narrow, CCD
   // append-mode broad phase work split [PT, EE]: 0 thread per query,
-  // 1 thread per (query, cell), 2 wavefront per (query, cell)
+  // 1 thread per (query, cell), 2 wavefront per (query, cell), 3 bucket join
   int query_mode[2] = {1, 0};
   eipc::BPPlan last_plan[4] = {};   // sizes seen by the last unplanned broad phases
   bool prof = false;                        // record per-kernel events

@@ -545,21 +545,13 @@ __global__ __launch_bounds__(LT_T) void k_item_hist(int n, const ItemRec *__rest
     if (s_key[k] != 0u) atomicAdd(&bcnt[s_key[k] - 1u], s_cnt[k]);
 }
 
-// Hash entry: the item's box rounded outward to float, so that most
-// non-overlapping items are rejected without reading their record.
+// Hash entry: one (item, cell) pair.  The offset of the cell from the
+// item's lower cell decides the lower-corner rule without the item's record.
 struct Entry {
   uint64_t cell;
   int32_t item;
   int32_t dlo;  // cell minus the item's lower cell, 6 bits per axis
 };
-
-__device__ __forceinline__ void box_f32(const double *lo, const double *hi, float *flo, float *fhi) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    flo[a] = __double2float_rd(lo[a]);
-    fhi[a] = __double2float_ru(hi[a]);
-  }
-}
 
 __global__ __launch_bounds__(LT_T) void k_item_fill(int n, const ItemRec *__restrict__ rec,
                                                     const GridDev *__restrict__ gp, uint32_t bmask,
@@ -799,15 +791,12 @@ __device__ __forceinline__ void query_data(int q, const double *xs, const double
 }
 
 // modes: 0 count, 1 write (offset per query, sorted per query, capacity
-// guarded), 2 append (LDS-staged, unsorted; *total receives the count)
+// guarded)
 template <int KIND, int MODE>
 __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__ xs, const double *__restrict__ x1s,
                                               int n_vert, double h, QueryArgs qa_, int32_t *__restrict__ cnt,
                                               const int64_t *__restrict__ off, int32_t *__restrict__ out, int64_t cap,
                                               unsigned long long *total, uint32_t *status) {
-  __shared__ int2 s_buf[MODE == 2 ? QT * APPEND_BUF : 1];
-  int2 *buf = s_buf + (MODE == 2 ? threadIdx.x * APPEND_BUF : 0);
-  int nbuf = 0;
   const GridDev g = *qa_.g;
   const ItemRec *items = qa_.items;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -819,8 +808,6 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
   if (live) query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
   int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
   if (live) cell_range(g, qlo, qhi, c0, c1);
-  float fqlo[3], fqhi[3];
-  box_f32(qlo, qhi, fqlo, fqhi);
   const int64_t base = (MODE == 1 && live) ? off[q] : 0;
   int64_t k = 0;
   for (int z = c0[2]; z <= c1[2]; ++z)
@@ -833,13 +820,9 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
         // max(query low cell, item low cell) == this cell on every axis
         scan_bucket<KIND>(qa_.ent, items, qa_.bstart[b], e1, key, x, y, z, c0[0], c0[1], c0[2], q, qa, qb, qdof,
                           qlo, qhi, [&](int it) {
-                            if (MODE == 1) {
-                              if (base + k < cap) {
-                                out[2 * (base + k)] = q;
-                                out[2 * (base + k) + 1] = it;
-                              }
-                            } else if (MODE == 2) {
-                              stage_pair(buf, nbuf, q, it, total, out, cap);
+                            if (MODE == 1 && base + k < cap) {
+                              out[2 * (base + k)] = q;
+                              out[2 * (base + k) + 1] = it;
                             }
                             ++k;
                           });
@@ -852,18 +835,13 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
       if ((r.tag >> 1) != qsc) continue;
       if (!pair_ok<KIND>(q, qa, qb, qdof, it, r)) continue;
       if (!overlap(qlo, qhi, r)) continue;
-      if (MODE == 1) {
-        if (base + k < cap) {
-          out[2 * (base + k)] = q;
-          out[2 * (base + k) + 1] = it;
-        }
-      } else if (MODE == 2) {
-        stage_pair(buf, nbuf, q, it, total, out, cap);
+      if (MODE == 1 && base + k < cap) {
+        out[2 * (base + k)] = q;
+        out[2 * (base + k) + 1] = it;
       }
       ++k;
     }
   }
-  if (MODE == 2) wave_flush(buf, nbuf, total, out, cap);
   if (MODE == 0 && live) cnt[q] = (int32_t)k;
   if (MODE == 1 && live) {
     if (base + k > cap) {
@@ -975,8 +953,6 @@ __global__ __launch_bounds__(QT) void k_query_ent(const int64_t *__restrict__ n_
       int qa, qb, qsc;
       bool qdof;
       query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
-      float fqlo[3], fqhi[3];
-      box_f32(qlo, qhi, fqlo, fqhi);
       const int x = (int)(qe.cell & 0xffff), y = (int)((qe.cell >> 16) & 0xffff), z = (int)((qe.cell >> 32) & 0xffff);
       const int qx = x - (qe.dlo & 63), qy = y - ((qe.dlo >> 6) & 63), qz = z - ((qe.dlo >> 12) & 63);
       const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
