@@ -114,13 +114,11 @@ def load_traffic(kernel, workload, tuning=None):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    e = t.get(f"{workload}:{kernel}")
+    if tuning is None:
+        return None
+    e = t.get(f"{workload}:{kernel}@{float(tuning['cell_scale']):g},{int(tuning['query_cells'])}")
     if not e or e.get("sources") != source_digest():
         return None
-    if tuning is not None and e.get("tuning"):
-        v = [float(x) for x in e["tuning"].split(",")]
-        if v[0] != float(tuning["cell_scale"]) or int(v[5]) != int(tuning["query_cells"]):
-            return None
     return e.get("bytes_per_launch")
 
 

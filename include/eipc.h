@@ -215,7 +215,13 @@ eipc_status eipc_plan_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q,
  * pass the candidate predicate at q, tested pair by pair before the
  * distance.  Enqueues work only: no synchronization, no
  * allocation, no host-side reads of device data, so it can be captured in
- * a HIP graph and replayed with new contents of q and dq.
+ * a HIP graph and replayed with new contents of q and dq.  With alpha, the
+ * point-triangle part runs on a second stream owned by the context (default
+ * priority), forked from `stream` after the shared set-up and joined back
+ * into it by events before the call returns: all results are ordered on
+ * `stream`, and under capture the fork becomes a parallel branch of the
+ * graph.  Calls on one context must not overlap (they share that stream
+ * and the scratch). */
  *   energy   device double[n_scene] or NULL     grad_q  device double[3*n_node] or NULL
  *   hess_bsr host struct or NULL (needs EIPC_HESS and plan->hess_blocks > 0): context-owned
  *            BSR view with nnzb = -1 (the count is rowptr[n_rows] on the device)
