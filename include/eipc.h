@@ -221,7 +221,7 @@ eipc_status eipc_plan_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q,
  * into it by events before the call returns: all results are ordered on
  * `stream`, and under capture the fork becomes a parallel branch of the
  * graph.  Calls on one context must not overlap (they share that stream
- * and the scratch). */
+ * and the scratch).
  *   energy   device double[n_scene] or NULL     grad_q  device double[3*n_node] or NULL
  *   hess_bsr host struct or NULL (needs EIPC_HESS and plan->hess_blocks > 0): context-owned
  *            BSR view with nnzb = -1 (the count is rowptr[n_rows] on the device)
