@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_ccd(int64_t cap, const int64_t *d_n, co
 // undecided to a compacted list; pass 1 runs those from the start with
 // the full iteration cap.  Each pair's bound is computed exactly as in
 // one uninterrupted run.
-constexpr int64_t CCD_SHORT = 16;
+constexpr int64_t CCD_SHORT = 4;
 
 template <int KIND, int PASS>
 __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
