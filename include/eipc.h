@@ -162,7 +162,9 @@ eipc_status eipc_barrier_reduce(eipc_ctx *ctx, const eipc_scene *sc, const doubl
  * alpha (host double[n_scene]): the bound per scene; n_cand (host, or
  * NULL) receives the number of swept
  * candidates.  Returns EIPC_WARN_CCD_CAPPED if some pair reached max_iter
- * iterations (alpha is still safe).  Synchronizes. */
+ * iterations before its bound was shown to be no smaller than the scene's
+ * bound found so far (pairs shown so are not advanced further: the minimum
+ * is the same); alpha is still safe.  Synchronizes. */
 eipc_status eipc_ccd_max_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const double *dq,
                               const double *dx_off, double dhat, double s, double t_max, int64_t max_iter,
                               double *alpha, int64_t *n_cand, eipc_stream stream);

@@ -32,6 +32,37 @@ __device__ __forceinline__ void agg_scene_min(unsigned long long *bits, bool val
   }
 }
 
+// Cut-off for a pair of the given scene when only the per-scene minimum is
+// wanted: the scene's bound as published so far.  It starts at t_max and
+// only ever takes some pair's final bound, so a pair whose bound is shown
+// to be no smaller cannot lower the minimum.  A stale read returns an
+// earlier, larger value: a weaker cut-off, never a wrong one.  With no
+// step allowed (max_iter < 1) every bound is 0 and nothing is cut.
+__device__ __forceinline__ double scene_cut(const unsigned long long *bits, int scene, int n_scene, double t_max,
+                                            int64_t max_iter) {
+  if (max_iter < 1 || (unsigned)scene >= (unsigned)n_scene) return INFINITY;
+  return fmin(__longlong_as_double((long long)((const volatile unsigned long long *)bits)[scene]), t_max);
+}
+
+// Advancement of one pair after accd_init_cut, up to lim steps, dropping
+// the pair as soon as its bound reaches cut (it only grows from there).
+// Returns ACCD_OPEN when lim steps left it undecided.
+template <int KIND>
+__device__ __forceinline__ int accd_run_cut(V3 *x, const V3 *p, double t_c, int64_t max_iter, double cut,
+                                            int64_t lim, AccdState &st, int r) {
+  while (r == ACCD_OPEN && st.it < lim) {
+    if (accd_step<KIND>(x, p, t_c, max_iter, st))
+      r = ACCD_DONE;
+    else if (st.t >= cut)
+      r = ACCD_DROP;
+  }
+  if (r == ACCD_OPEN && st.it >= max_iter) {  // cap reached: the bound so far
+    accd_step<KIND>(x, p, t_c, max_iter, st);
+    r = ACCD_DONE;
+  }
+  return r;
+}
+
 template <int KIND>
 __global__ __launch_bounds__(256) void k_ccd(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
                       const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
@@ -82,7 +113,9 @@ __global__ __launch_bounds__(256) void k_ccd(int64_t cap, const int64_t *d_n, co
 // pass 0 gives every pair up to CCD_SHORT steps and defers the pairs still
 // undecided to a compacted list; pass 1 runs those from the start with
 // the full iteration cap.  Each pair's bound is computed exactly as in
-// one uninterrupted run.
+// one uninterrupted run, or the pair is dropped once its bound is shown to
+// be no smaller than its scene's bound published so far (scene_cut): the
+// minimum comes out the same, bit for bit.
 constexpr int64_t CCD_SHORT = 4;
 
 template <int KIND, int PASS>
@@ -123,16 +156,16 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
         ld_pos(ps, vid[q], p[q].x, p[q].y, p[q].z);
       }
       AccdState st;
-      decided = accd_init<KIND>(x, p, sfac, t_max, st);
+      const double cut = scene_cut(alpha_bits, scene, n_scene, t_max, max_iter);
       const int64_t lim = PASS == 0 ? (CCD_SHORT < max_iter ? CCD_SHORT : max_iter) : max_iter;
-      while (!decided && st.it < lim) decided = accd_step<KIND>(x, p, t_max, max_iter, st);
-      if (!decided && st.it >= max_iter) decided = accd_step<KIND>(x, p, t_max, max_iter, st);  // cap reached
-      if (decided) {
+      const int r = accd_run_cut<KIND>(x, p, t_max, max_iter, cut, lim, st,
+                                       accd_init_cut<KIND>(x, p, sfac, t_max, cut, st, false, 0.0));
+      if (r == ACCD_DONE) {
         t = st.t;
         capped = st.it >= max_iter;
-      } else {
-        deferred = true;  // pass 0 only: more than CCD_SHORT steps
       }
+      decided = r != ACCD_OPEN;  // a dropped pair keeps t = t_max
+      deferred = !decided;       // pass 0 only: more than CCD_SHORT steps
     }
     if (PASS == 0) {
       const uint64_t dm = __ballot(deferred);
@@ -155,8 +188,10 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
 // the distance and activity test (active pairs appended to act/typ with one
 // atomic per wavefront) come first, then advancement as in k_ccd2 pass 0,
 // reusing the distance just computed.  The pass-1 list is the same.
+// Held to three waves per SIMD (168 VGPRs; the EE form spills 44 bytes per
+// lane): measured faster than the two that its 186 unconstrained VGPRs allow.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_narrow_ccd(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_narrow_ccd(
     int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
     const int32_t *__restrict__ edges, const double *__restrict__ xs, const double *__restrict__ ps, double dhat2,
     double h, int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t act_cap, int64_t *count,
@@ -209,16 +244,16 @@ __global__ __launch_bounds__(256) void k_narrow_ccd(
         }
       }
       AccdState st;
-      decided = accd_init<KIND>(x, p, sfac, t_max, st, cand, s2);
+      const double cut = scene_cut(alpha_bits, scene, n_scene, t_max, max_iter);
       const int64_t lim = CCD_SHORT < max_iter ? CCD_SHORT : max_iter;
-      while (!decided && st.it < lim) decided = accd_step<KIND>(x, p, t_max, max_iter, st);
-      if (!decided && st.it >= max_iter) decided = accd_step<KIND>(x, p, t_max, max_iter, st);  // cap reached
-      if (decided) {
+      const int r = accd_run_cut<KIND>(x, p, t_max, max_iter, cut, lim, st,
+                                       accd_init_cut<KIND>(x, p, sfac, t_max, cut, st, cand, s2));
+      if (r == ACCD_DONE) {
         t = st.t;
         capped = st.it >= max_iter;
-      } else {
-        deferred = true;
       }
+      decided = r != ACCD_OPEN;  // a dropped pair keeps t = t_max
+      deferred = !decided;
     }
     {
       const uint64_t mask = __ballot(active);

@@ -721,13 +721,11 @@ struct AccdState {
   int64_t it;
 };
 
-// Set-up of one pair (p is made relative to its mean).  Returns true when
-// the pair is already decided (no relative motion: the bound is t_c).
-// known: s2 holds the pair's squared distance at x, already computed (the
-// same function of the same x).
+// p made relative to its mean; st.lp = the largest possible rate of
+// closing (the point's speed plus the triangle's fastest vertex, or the
+// fastest vertex of each edge); st.t = 0, no steps taken.
 template <int KIND>
-__device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, AccdState &st, bool known = false,
-                                          double s2 = 0.0) {
+__device__ __forceinline__ void accd_motion(V3 *p, AccdState &st) {
 #pragma clang fp contract(off)
   V3 mean;
   mean.x = (((p[0].x + p[1].x) + p[2].x) + p[3].x) * 0.25;
@@ -741,6 +739,17 @@ __device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, Ac
   st.lp = KIND == 0 ? sqrt(q0) + sqrt(fmax(q1, fmax(q2, q3))) : sqrt(fmax(q0, q1)) + sqrt(fmax(q2, q3));
   st.it = 0;
   st.t = 0.0;
+}
+
+// Set-up of one pair (p is made relative to its mean).  Returns true when
+// the pair is already decided (no relative motion: the bound is t_c).
+// known: s2 holds the pair's squared distance at x, already computed (the
+// same function of the same x).
+template <int KIND>
+__device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, AccdState &st, bool known = false,
+                                          double s2 = 0.0) {
+#pragma clang fp contract(off)
+  accd_motion<KIND>(p, st);
   if (st.lp == 0.0) {
     st.t = t_c;
     return true;
@@ -750,6 +759,67 @@ __device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, Ac
   st.g = s * d;
   st.tl = (1.0 - s) * d / st.lp;
   return false;
+}
+
+// Squared gap between the boxes of the pair's two primitives at x (zero
+// when they overlap): a lower bound on the pair's squared distance.
+template <int KIND>
+__device__ __forceinline__ double box_gap2(const V3 *x) {
+#pragma clang fp contract(off)
+  const int nq = KIND == 0 ? 1 : 2;
+  double g2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double qmn = INFINITY, qmx = -INFINITY, imn = INFINITY, imx = -INFINITY;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double v = c == 0 ? x[a].x : (c == 1 ? x[a].y : x[a].z);
+      if (a < nq) {
+        qmn = fmin(qmn, v);
+        qmx = fmax(qmx, v);
+      } else {
+        imn = fmin(imn, v);
+        imx = fmax(imx, v);
+      }
+    }
+    const double g = fmax(fmax(imn - qmx, qmn - imx), 0.0);
+    g2 = g2 + g * g;
+  }
+  return g2;
+}
+
+enum { ACCD_OPEN = 0, ACCD_DONE = 1, ACCD_DROP = 2 };
+
+// Set-up for the step bound alone (the minimum over pairs), given cut <=
+// t_c, a value that the minimum is already known not to exceed.  A pair's
+// bound never falls below min(first step, t_c): its first step skips the
+// gap test, and later steps only add to st.t.  So a pair whose first step
+// is at least cut cannot lower the minimum, and is dropped (ACCD_DROP)
+// without further steps.  For a pair whose distance is not yet known the
+// test is tried first with the box gap in place of the distance (shrunk by
+// a relative 1e-6, far above the rounding error of the gap or of the
+// computed distance; rounded products and quotients are monotone, so the
+// first step from the gap is no larger than the one from the distance),
+// which spares the distance for far pairs.  ACCD_DONE: decided with st.t
+// (no relative motion); ACCD_OPEN: advance with accd_step.
+template <int KIND>
+__device__ __forceinline__ int accd_init_cut(V3 *x, V3 *p, double s, double t_c, double cut, AccdState &st,
+                                             bool known, double s2) {
+#pragma clang fp contract(off)
+  accd_motion<KIND>(p, st);
+  if (st.lp == 0.0) {
+    st.t = t_c;
+    return ACCD_DONE;
+  }
+  if (!known) {
+    const double lb = sqrt(box_gap2<KIND>(x)) * (1.0 - 1e-6);
+    if ((1.0 - s) * lb / st.lp >= cut) return ACCD_DROP;
+  }
+  int ty;
+  const double d = sqrt(known ? s2 : pair_dist2<KIND>(x, &ty));
+  st.g = s * d;
+  st.tl = (1.0 - s) * d / st.lp;
+  return st.tl >= cut ? ACCD_DROP : ACCD_OPEN;
 }
 
 // One advancement step.  Returns true when the pair's bound st.t is final.

@@ -223,6 +223,21 @@ def test_ccd_candidates_and_toi_bit_exact(ctx, c1, seed, mode):
     assert a <= a_ref and a == a_ref
 
 
+@pytest.mark.parametrize("max_iter", [1, 2, 3, 5, 40])
+def test_ccd_max_step_at_small_iteration_caps(ctx, c1, max_iter):
+    # The step-bound kernels drop pairs whose bound is shown to be no smaller
+    # than their scene's bound so far; the minimum must come out exactly as
+    # the oracle's, which advances every pair to its end or its cap.
+    dsc = E.Scene.from_host(ctx, c1)
+    a, n, capped = E.ccd_max_step(ctx, dsc, _dev(c1.q), _dev(c1.dq), c1.dhat, max_iter=max_iter)
+    a_ref, n_ref, ncap_ref = O.ccd_max_step(c1, c1.q, c1.dq, c1.dhat, max_iter=max_iter)
+    assert n == n_ref
+    assert a == a_ref
+    # a warning names a capped pair that could still lower the bound; the
+    # oracle counts every capped pair
+    assert not capped or ncap_ref > 0
+
+
 def test_ccd_zero_motion_is_t_max(ctx, c1):
     dsc = E.Scene.from_host(ctx, c1)
     a, n, _ = E.ccd_max_step(ctx, dsc, _dev(c1.q), _dev(np.zeros_like(c1.dq)), c1.dhat)
