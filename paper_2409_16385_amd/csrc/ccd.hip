@@ -127,9 +127,15 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
   const int64_t n = PASS == 0 ? (d_n ? (*d_n < cap ? *d_n : cap) : cap) : (*n_long < cap ? *n_long : cap);
   const int lane = threadIdx.x & 63;
   bool capped = false;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+  // each workgroup walks a contiguous range of the list: a scene's pairs
+  // are adjacent in it, so the first pairs of a range publish their
+  // scene's bound early and the cut-off prunes the rest of the range
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  for (int64_t base = r0; base < r1; base += blockDim.x) {
     const int64_t i = base + threadIdx.x;
-    const bool live = i < n;
+    const bool live = i < r1;
     double t = t_max;
     int scene = 0;
     bool decided = false, deferred = false;
@@ -202,9 +208,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int lane = threadIdx.x & 63;
   bool capped = false;
   int64_t n_cand = 0;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+  // each workgroup walks a contiguous range of the list: a scene's pairs
+  // are adjacent in it, so the first pairs of a range publish their
+  // scene's bound early and the cut-off prunes the rest of the range
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  for (int64_t base = r0; base < r1; base += blockDim.x) {
     const int64_t i = base + threadIdx.x;
-    const bool live = i < n;
+    const bool live = i < r1;
     double t = t_max;
     int scene = 0, ty = 0;
     bool decided = false, deferred = false, active = false;
