@@ -205,7 +205,9 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
     kdom = max(kernels, key=lambda k: prof[k][0])
     ms, n = prof[kdom]
     avg_s = ms / n / 1e3
-    ent = {"kernel": kdom, "family": dom, "avg_launch_us": avg_s * 1e6, "traffic": None}
+    ent = {"kernel": kdom, "family": dom, "avg_launch_us": avg_s * 1e6, "traffic": None,
+           "timing": "HIP events on the launch stream over eager planned steps that run the PT and EE chains one "
+                     "after the other (each kernel alone on the device)"}
     if dom in ("pair_terms", "expand"):
         kind = 0 if kdom.endswith("_pt") else 1
         per = work["terms_flops"][kind] if dom == "pair_terms" else FLOPS_EXPAND * work["active"][kind]
@@ -360,7 +362,7 @@ def main():
     # per-kernel event profile of eager planned steps (same kernels)
     prof = {}
     if not a.no_profile:
-        bt.ctx.profile(True)
+        bt.ctx.profile(True, serial=True)  # each kernel timed alone on the device
         bt.ctx.profile_read(reset=True)
         n_prof = max(3, min(a.steps, 10))
         for _ in range(n_prof):

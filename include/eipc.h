@@ -217,8 +217,9 @@ eipc_status eipc_plan_step(eipc_ctx *ctx, const eipc_scene *sc, const double *q,
  * pass the candidate predicate at q, tested pair by pair before the
  * distance.  Enqueues work only: no synchronization, no
  * allocation, no host-side reads of device data, so it can be captured in
- * a HIP graph and replayed with new contents of q and dq.  With alpha, the
- * point-triangle part runs on a second stream owned by the context (default
+ * a HIP graph and replayed with new contents of q and dq.  With alpha
+ * (outside profiling mode 2), the point-triangle part runs on a second
+ * stream owned by the context (default
  * priority), forked from `stream` after the shared set-up and joined back
  * into it by events before the call returns: all results are ordered on
  * `stream`, and under capture the fork becomes a parallel branch of the
@@ -274,8 +275,12 @@ eipc_status eipc_cholesky_solve(eipc_ctx *ctx, const double *L, int64_t n, int64
 
 /* ---- optional kernel timing (benchmarks) ---- */
 
-/* Turn per-kernel timing on or off.  While on, the library brackets each
- * launch of its main kernels with HIP events on the launch stream. */
+/* Turn per-kernel timing on (1 or 2) or off (0).  While on, the library
+ * brackets each launch of its main kernels with HIP events on the launch
+ * stream.  With 2, the planned step also runs its PT chain on the caller's
+ * stream, before the EE chain instead of beside it, so that each timed kernel
+ * has the device to itself (its time then excludes waiting for the other
+ * chain's kernels); results are the same.  Any other value: EIPC_ERR_ARG. */
 eipc_status eipc_profile(eipc_ctx *ctx, int32_t enable);
 
 /* Synchronizes on the recorded events and returns, for the kernel `name`

@@ -196,16 +196,32 @@ class Batch:
         ev1.synchronize()
         return ev0.elapsed_time(ev1) / reps
 
+    def _device_ms(self, reps: int) -> float:
+        """Summed kernel time of one step, each kernel timed alone (the two
+        chains one after the other), averaged over reps eager steps."""
+        self.step()
+        torch.cuda.synchronize(self.ctx.torch_device)
+        self.ctx.profile(True, serial=True)
+        try:
+            self.ctx.profile_read(reset=True)
+            for _ in range(reps):
+                self.step()
+            prof = self.ctx.profile_read(reset=True)
+        finally:
+            self.ctx.profile(False)
+        return sum(ms for ms, _ in prof.values()) / reps
+
     def autotune(self, cell_scales=(2.0, 3.0, 4.0, 6.0), query_modes=(0, 5, 12, 15), wg_values=(1, 2, 4, 8, 16),
                  reps: int = 3, margin: float = 1.5, verbose: bool = False) -> dict:
         """Pick the broad-phase cell scale and work split per query kind
-        (whole-step time, re-planning for each pair of values), then for
-        each grid-stride kernel family in turn the workgroups per CU
-        (values from wg_values, whole-step time; a change is kept when it
-        saves more than 2%)."""
+        (whole-step time, re-planning for each pair of values; among pairs
+        within 1% of the fastest, the one with the least device time summed
+        over the step's kernels, each timed alone), then for each
+        grid-stride kernel family in turn the workgroups per CU (values
+        from wg_values, whole-step time; a change is kept when it saves
+        more than 2%)."""
         wg = [wg_values[len(wg_values) // 2]] * 4
-        best = None
-        trace = []
+        trace, timed = [], []
         for cs in cell_scales:
             for qm in query_modes:
                 B.set_tuning(self.ctx, cs, wg, qm)
@@ -214,9 +230,22 @@ class Batch:
                 if self.status() not in (B.OK, B.WARN_CCD_CAPPED):
                     continue
                 trace.append((f"cell_scale/query_cells {qm}", cs, ms))
-                if best is None or ms < best[2]:
-                    best = (cs, qm, ms)
-        cs, qm = best[0], best[1]
+                timed.append((ms, cs, qm))
+        fastest = min(timed)[0]
+        ties = [(cs, qm) for ms, cs, qm in timed if ms <= 1.01 * fastest]
+        if len(ties) > 1:
+            # the two chains run side by side, so pairs can tie on step time
+            # while one of them keeps the device busier
+            scored = []
+            for cs, qm in ties:
+                B.set_tuning(self.ctx, cs, wg, qm)
+                self.make_plan(margin)
+                dev_ms = self._device_ms(reps)
+                trace.append((f"device ms, query_cells {qm}", cs, dev_ms))
+                scored.append((dev_ms, cs, qm))
+            _, cs, qm = min(scored)
+        else:
+            cs, qm = ties[0]
         B.set_tuning(self.ctx, cs, wg, qm)
         self.make_plan(margin)
         # workgroups per CU of each grid-stride family (pair terms,

@@ -162,9 +162,11 @@ class Context:
                "narrow_ee", "barrier_pt", "barrier_ee", "ccd_pt", "ccd_ee", "hvp_pt", "hvp_ee", "expand_pt",
                "expand_ee", "ccd_long_pt", "ccd_long_ee")
 
-    def profile(self, enable: bool = True):
-        """Per-kernel HIP-event timing inside the library (on the launch stream)."""
-        self.check(_load().eipc_profile(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, serial: bool = False):
+        """Per-kernel HIP-event timing inside the library (on the launch stream);
+        serial: the planned step runs its two chains one after the other on
+        the caller's stream while timing, so each kernel is timed alone."""
+        self.check(_load().eipc_profile(self._h, (2 if serial else 1) if enable else 0))
 
     def profile_read(self, reset: bool = True) -> dict:
         """{kernel: (total_ms, launches)} since the last reset."""

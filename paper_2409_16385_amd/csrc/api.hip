@@ -240,7 +240,9 @@ const char *eipc_last_error(const eipc_ctx *c) { return c ? c->err : "no context
 
 eipc_status eipc_profile(eipc_ctx *c, int32_t enable) {
   if (!c) return EIPC_ERR_ARG;
+  if (enable < 0 || enable > 2) return set_err(c, EIPC_ERR_ARG, "profile mode must be 0, 1 or 2");
   c->prof = enable != 0;
+  c->prof_serial = enable == 2;
   return EIPC_OK;
 }
 
@@ -617,9 +619,10 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
   if (alpha) {
     // one swept broad phase per kind; candidates at q filtered from it pair
     // by pair in the same sweep as the step bound's first pass.  The PT
-    // chain runs on the side stream beside the EE chain; they share only
-    // targets that are accumulated atomically (energy, gradient, Hessian
-    // table, step bounds, status).
+    // chain runs on the side stream beside the EE chain (both on the
+    // caller's stream, PT first, when kernels are timed one at a time);
+    // they share only targets that are accumulated atomically (energy,
+    // gradient, Hessian table, step bounds, status).
     double *ps, *x1s;
     int32_t *cpt, *cee;
     EIPC_TRY(ensure_t(c, B_P, (size_t)n3v + 1, &ps));
@@ -634,7 +637,7 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     EIPC_HIP(c, hipEventRecord(c->fork_ev, s));
     EIPC_HIP(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
     for (int kind = 0; kind < 2; ++kind) {
-      hipStream_t st = kind == 0 ? c->side : s;
+      hipStream_t st = kind == 0 && !c->prof_serial ? c->side : s;
       int32_t *cand = kind == 0 ? cpt : cee;
       int32_t *act = kind == 0 ? act_pt : act_ee, *typ = kind == 0 ? typ_pt : typ_ee;
       const int64_t swept_cap = kind == 0 ? plan->swept_pt : plan->swept_ee;

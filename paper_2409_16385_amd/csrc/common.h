@@ -102,6 +102,7 @@ struct eipc_ctx {
   int query_mode[2] = {1, 0};
   eipc::BPPlan last_plan[4] = {};   // sizes seen by the last unplanned broad phases
   bool prof = false;                        // record per-kernel events
+  bool prof_serial = false;                 // planned step: both chains on the caller's stream
   std::vector<eipc::ProfRec> prof_pending;  // recorded, not yet read
   std::vector<hipEvent_t> prof_pool;        // reusable events
   double prof_ms[eipc::K_NUM] = {0};

@@ -179,6 +179,19 @@ def test_autotune_keeps_results(ctx, scenes, seq):
     E.set_tuning(ctx, 2.0, [8, 2, 4, 4], 1)
 
 
+def test_autotune_tie_break_by_device_time(ctx, scenes, seq):
+    # the same (cell scale, mode) twice: the two whole-step times fall within
+    # 1% of each other as a rule, which sends the pair to the device-time
+    # tie break; either way the tuning stays in range and results are kept
+    b = BT.Batch(ctx, BT.concat(scenes))
+    assert b._device_ms(1) > 0.0
+    t = b.autotune(cell_scales=(2.0, 2.0), query_modes=(15,), wg_values=(4,), reps=1)
+    assert t["cell_scale"] == 2.0 and t["query_cells"] == 15 and t["wg_per_cu"] == [4, 4, 4, 4]
+    b.step()
+    assert b.status() == E.binding.OK
+    _check_against_sequential(b, seq, scenes)
+
+
 def test_bad_scene_id_is_an_argument_error(ctx, scenes):
     hb = BT.concat(scenes[:2])
     hb.vert_scene = hb.vert_scene.copy()

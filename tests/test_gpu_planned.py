@@ -68,6 +68,24 @@ def _compare(b, ref):
     assert b.out.alpha[0].item() == ref["alpha"]
 
 
+def test_profiling_mode_2_gives_the_same_step(ctx):
+    # timing mode 2 runs the PT chain on the caller's stream before the EE
+    # chain (bench.py times kernels that way); results must not change
+    sc = _scene("config2")
+    b = BT.Batch(ctx, BT.concat([sc]), flags=_flags(sc))
+    b.make_plan(1.5)
+    b.ctx.profile(True, serial=True)  # the batch owns a context of its own
+    try:
+        b.step()
+        prof = b.ctx.profile_read(reset=True)
+    finally:
+        b.ctx.profile(False)
+    assert b.status() in (E.binding.OK, E.binding.WARN_CCD_CAPPED)
+    assert prof["ccd_pt"][1] == 1 and prof["ccd_ee"][1] == 1 and prof["expand_ee"][1] == 1
+    _compare(b, _plain(ctx, "config2"))
+    assert E.binding._load().eipc_profile(b.ctx._h, 3) == E.binding.ERR_ARG
+
+
 @pytest.mark.parametrize("name", ["config2", "config3"])
 def test_planned_step_matches_per_call_path(ctx, name):
     sc = _scene(name)
