@@ -540,6 +540,31 @@ __device__ __forceinline__ void to_q_basis(const double *H, double *M) {
 // Entries below thr (1e-20 of the matrix norm) are left alone: lanes keep
 // sweeping until the whole wavefront has converged, and rotating such
 // entries would square values that underflow.
+// 1/sqrt(x) and 1/x (x > 0, normal) from the hardware estimates refined by
+// two Newton steps (each roughly doubles the correct bits: y <- y (3 - x y^2)
+// / 2 and y <- y (2 - x y)), within a few ulp of the correctly rounded
+// values at a fraction of their cost.  The Jacobi rotation needs no more:
+// its (c, s) stay orthonormal to rounding, and its angle only has to
+// shrink the off-diagonal entry, which the sweep loop checks.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+  }
+  return y;
+}
+
 template <int P, int Q>
 __device__ __forceinline__ void jacobi_rot(double *a, double *v, double thr) {
   const double apq = a[pidx(P, Q)];
@@ -548,8 +573,8 @@ __device__ __forceinline__ void jacobi_rot(double *a, double *v, double thr) {
   const double h = 0.5 * (aqq - app);
   const double r = sqrt(h * h + apq * apq);
   const double den = h >= 0.0 ? h + r : h - r;
-  const double t = (fabs(apq) > thr && den != 0.0) ? apq / den : 0.0;
-  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double t = (fabs(apq) > thr && den != 0.0) ? apq * rcp_nr(den) : 0.0;
+  const double c = rsqrt_nr(1.0 + t * t);
   const double s = t * c;
   a[pidx(P, P)] = app - t * apq;
   a[pidx(Q, Q)] = aqq + t * apq;
