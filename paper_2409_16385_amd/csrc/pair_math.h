@@ -571,9 +571,12 @@ __device__ __forceinline__ void jacobi_rot(double *a, double *v, double thr) {
   const double app = a[pidx(P, P)];
   const double aqq = a[pidx(Q, Q)];
   const double h = 0.5 * (aqq - app);
-  const double r = sqrt(h * h + apq * apq);
+  const double ss = h * h + apq * apq;
+  // sqrt(ss) as ss / sqrt(ss); the smallest normal double keeps ss = 0 at 0
+  const double r = ss * rsqrt_nr(fmax(ss, 2.2250738585072014e-308));
   const double den = h >= 0.0 ? h + r : h - r;
-  const double t = (fabs(apq) > thr && den != 0.0) ? apq * rcp_nr(den) : 0.0;
+  // (an infinite den, from entries beyond 1e154, gives t = 0 as apq / den would)
+  const double t = (fabs(apq) > thr && den != 0.0 && fabs(den) < INFINITY) ? apq * rcp_nr(den) : 0.0;
   const double c = rsqrt_nr(1.0 + t * t);
   const double s = t * c;
   a[pidx(P, P)] = app - t * apq;
