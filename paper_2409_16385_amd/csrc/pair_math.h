@@ -818,8 +818,11 @@ __device__ __forceinline__ double box_gap2(const V3 *x) {
 
 enum { ACCD_OPEN = 0, ACCD_DONE = 1, ACCD_DROP = 2 };
 
-// Set-up for the step bound alone (the minimum over pairs), given cut <=
-// t_c, a value that the minimum is already known not to exceed.  A pair's
+// Set-up for the step bound alone (the minimum over pairs), given cut, a
+// value that the minimum is already known not to exceed (at most t_c; an
+// infinite cut turns the dropping off, up to an infinite first step, which
+// the plain set-up decides at t_c, so either way the pair contributes no
+// less than t_c).  A pair's
 // bound never falls below min(first step, t_c): its first step skips the
 // gap test, and later steps only add to st.t.  So a pair whose first step
 // is at least cut cannot lower the minimum, and is dropped (ACCD_DROP)
