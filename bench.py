@@ -52,7 +52,8 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "batch"])
+    ap.add_argument("--config", default="config2", choices=["config1", "config2", "config3", "batch", "resolution"],
+                    help="resolution: config 2's surface meshes with object grids from 250 to 32,000 nodes")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n-scene", type=int, default=256, help="scenes in the batch config")
     ap.add_argument("--cpu-queries", type=int, default=2000,
@@ -257,6 +258,68 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
     return ent
 
 
+RESOLUTION_NODES = (250, 1000, 2000, 8000, 32000)
+
+
+def resolution_sweep(a, log):
+    """Contact-stage throughput against the embedding's resolution: config
+    2's surface meshes (object frequency 71, fingers 32, seed a.seed) with
+    the object's coarse grid at each size of RESOLUTION_NODES (the fingers
+    keep their grids).  The contact work depends on the surface alone; only
+    the embedding and the reduction through W see the grid.  Each scene is
+    autotuned, then timed as in the single-scene bench (graph replays)."""
+    import torch
+    from scenes import scene as S
+    import paper_2409_16385_amd as E
+    from paper_2409_16385_amd import batch as BT
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    flags = E.ENERGY | E.GRAD | E.HESS | E.PROJECT
+    rows = []
+    for nodes in RESOLUTION_NODES:
+        t0 = time.perf_counter()
+        sc = S.grasp_scene(a.seed, 71, nodes, 32, name=f"config2_grid{nodes}")
+        bt = BT.Batch(ctx, BT.concat([sc]), flags=flags)
+        tuning = bt.autotune(reps=2)
+        bt.capture()
+        for _ in range(a.warmup):
+            bt.replay()
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        for _ in range(a.steps):
+            bt.replay()
+        torch.cuda.synchronize(dev)
+        ms = 1e3 * (time.perf_counter() - t1) / a.steps
+        st = bt.status()
+        if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):
+            raise RuntimeError(f"resolution {nodes}: status {st}")
+        cnt = bt.counts()
+        bt.ctx.profile(True, serial=True)
+        bt.ctx.profile_read(reset=True)
+        for _ in range(3):
+            bt.step()
+        prof = bt.ctx.profile_read(reset=True)
+        bt.ctx.profile(False)
+        fam = {f: round(sum(prof.get(k, (0.0, 0))[0] for k in ks) / 3, 4) for f, ks in FAMILIES.items()}
+        row = {"object_grid_nodes": nodes, "n_node": int(sc.n_node), "n_vert": int(sc.n_vert),
+               "active_pairs": cnt["active"], "swept": cnt["swept_pt"] + cnt["swept_ee"], "ms_per_step": ms,
+               "pairs_per_s": cnt["active"] / (ms * 1e-3), "family_ms_alone": fam,
+               "tuning": {k: v for k, v in tuning.items() if k != "trace"}}
+        log(f"resolution {nodes}: n_node={sc.n_node} active={cnt['active']} {ms:.3f} ms/step "
+            f"({time.perf_counter() - t0:.1f} s)")
+        rows.append(row)
+        del bt
+    ref = next(r for r in rows if r["object_grid_nodes"] == 2000)
+    out = {"metric": "contact pairs/s against embedding resolution", "value": ref["pairs_per_s"],
+           "unit": "contact pairs/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": ref["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "config 2 surfaces, object grid of 2,000 nodes (value); sweep over "
+                                  + ", ".join(str(n) for n in RESOLUTION_NODES) + " nodes", "seed": a.seed},
+           "sweep": rows, "sources": source_digest()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -268,6 +331,9 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if a.config == "resolution":
+        resolution_sweep(a, log)
+        return
     batch_scenes = make_batch(a.n_scene, a.seed, log) if a.config == "batch" else None
 
     import numpy as np
