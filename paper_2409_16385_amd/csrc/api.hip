@@ -636,24 +636,31 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     EIPC_TRY(fill_u64(c, (uint64_t *)alpha, n_scene_of(sc), tb, s));
     EIPC_HIP(c, hipEventRecord(c->fork_ev, s));
     EIPC_HIP(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
-    for (int kind = 0; kind < 2; ++kind) {
-      hipStream_t st = kind == 0 && !c->prof_serial ? c->side : s;
-      int32_t *cand = kind == 0 ? cpt : cee;
-      int32_t *act = kind == 0 ? act_pt : act_ee, *typ = kind == 0 ? typ_pt : typ_ee;
-      const int64_t swept_cap = kind == 0 ? plan->swept_pt : plan->swept_ee;
-      const int64_t act_cap = kind == 0 ? plan->act_pt : plan->act_ee;
-      EIPC_TRY(broad_phase(c, sc, kind, xs, x1s, dhat, cand, swept_cap, nullptr, 0, st, -1, nullptr, &bp[2 + kind],
-                           cn + 7 + kind));
-      EIPC_TRY(launch_narrow_ccd(c, sc, kind, xs, ps, cand, swept_cap, cn + 7 + kind, dhat, act, typ, act_cap,
-                                 cn + 2 + kind, cn + 5 + kind, sfac, t_max, max_iter, (uint64_t *)alpha, st));
-      EIPC_TRY(launch_ccd_long(c, sc, kind, xs, ps, cand, swept_cap, cn + 7 + kind, sfac, t_max, max_iter,
-                               (uint64_t *)alpha, st));
-      if (barrier)
-        EIPC_TRY(launch_barrier(c, sc, kind, xs, cand, act, typ, cn + 2 + kind, act_cap, dhat, kappa, f, energy, g,
-                                h, st));
-    }
+    auto chains = [&]() -> eipc_status {
+      for (int kind = 0; kind < 2; ++kind) {
+        hipStream_t st = kind == 0 && !c->prof_serial ? c->side : s;
+        int32_t *cand = kind == 0 ? cpt : cee;
+        int32_t *act = kind == 0 ? act_pt : act_ee, *typ = kind == 0 ? typ_pt : typ_ee;
+        const int64_t swept_cap = kind == 0 ? plan->swept_pt : plan->swept_ee;
+        const int64_t act_cap = kind == 0 ? plan->act_pt : plan->act_ee;
+        EIPC_TRY(broad_phase(c, sc, kind, xs, x1s, dhat, cand, swept_cap, nullptr, 0, st, -1, nullptr,
+                             &bp[2 + kind], cn + 7 + kind));
+        EIPC_TRY(launch_narrow_ccd(c, sc, kind, xs, ps, cand, swept_cap, cn + 7 + kind, dhat, act, typ, act_cap,
+                                   cn + 2 + kind, cn + 5 + kind, sfac, t_max, max_iter, (uint64_t *)alpha, st));
+        EIPC_TRY(launch_ccd_long(c, sc, kind, xs, ps, cand, swept_cap, cn + 7 + kind, sfac, t_max, max_iter,
+                                 (uint64_t *)alpha, st));
+        if (barrier)
+          EIPC_TRY(launch_barrier(c, sc, kind, xs, cand, act, typ, cn + 2 + kind, act_cap, dhat, kappa, f, energy,
+                                  g, h, st));
+      }
+      return EIPC_OK;
+    };
+    const eipc_status cst = chains();
+    // joined also when a chain failed part-way, so that nothing it enqueued
+    // on the side stream can overlap the caller's next use of the scratch
     EIPC_HIP(c, hipEventRecord(c->join_ev, c->side));
     EIPC_HIP(c, hipStreamWaitEvent(s, c->join_ev, 0));
+    if (cst != EIPC_OK) return cst;
   } else {
     int32_t *ppt, *pee;
     EIPC_TRY(ensure_t(c, B_STEP_PT, (size_t)2 * std::max<int64_t>(plan->cand_pt, 1), &ppt));
