@@ -62,6 +62,14 @@ def lib():
             "or_accd_pair": (_D, [C.c_int, _P, _P, _D, _D, _I64, _P]),
             "or_ccd_toi": (C.c_int, [_P, _P, _P, C.c_int, _P, _I64, _D, _D, _I64, _P, _P]),
             "or_ccd_max_step": (C.c_int, [_P, _P, _P, _P, _D, _D, _D, _I64, _P, _P, _P]),
+            "or_grid_build": (_P, [_P, _P, _P, _D, _D]),
+            "or_grid_pairs": (_I64, [_P, C.c_int, _I32, _I32, _P, _I64]),
+            "or_grid_cell": (_D, [_P]),
+            "or_grid_free": (None, [_P]),
+            "or_barrier_reduce_bsr": (_P, [_P, _P, _P, _I64, _P, _I64, _D, _D, C.c_uint32, _P, _P, _P, _P]),
+            "or_bsr_nnzb": (_I64, [_P]),
+            "or_bsr_copy": (None, [_P, _P, _P, _P]),
+            "or_bsr_free": (None, [_P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -259,3 +267,139 @@ def ccd_max_step(sc, q, dq, dhat, dx_off=None, s=0.1, t_max=1.0, max_iter=100000
     lib().or_ccd_max_step(sc_.ref, _ptr(q), _ptr(dq), _ptr(dx_off), dhat, s, t_max, max_iter,
                           _ptr(a), C.byref(nc), C.byref(ncap))
     return a[0], nc.value, ncap.value
+
+
+# ---------------------------------------------------------------------------
+# Workloads too large for the brute-force loops: the uniform-grid broad phase
+# and the block-sparse reduction, run over contiguous slices of the queries
+# or pairs on several host threads (ctypes releases the GIL during a call).
+# Slices are merged in order, so the lists come out exactly as from one call.
+# ---------------------------------------------------------------------------
+
+def threads() -> int:
+    """Host threads for the sliced oracle calls: the OMP_NUM_THREADS share
+    if set, else every core."""
+    n = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return max(1, n if n > 0 else (os.cpu_count() or 1))
+
+
+def _slices(n: int, parts: int):
+    parts = max(1, min(parts, n)) if n > 0 else 1
+    b = np.linspace(0, n, parts + 1).astype(np.int64)
+    return [(int(b[i]), int(b[i + 1])) for i in range(parts)]
+
+
+def _pmap(fn, items, nthreads):
+    if nthreads <= 1 or len(items) <= 1:
+        return [fn(it) for it in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(nthreads) as ex:
+        return list(ex.map(fn, items))
+
+
+def candidates_grid(sc, x, dhat, x1=None, cell=0.0, nthreads=None):
+    """The candidate set of candidates() (same pairs, same order), found
+    through a uniform grid of the given cell edge (<= 0: twice the mean
+    primitive box extent)."""
+    s = scene(sc)
+    x, x1 = _f64(x), _f64(x1)
+    L = lib()
+    g = L.or_grid_build(s.ref, _ptr(x), _ptr(x1), dhat, cell)
+    nthreads = nthreads or threads()
+    try:
+        out = []
+        for kind, nq in ((0, s.n_vert), (1, s.n_edge)):
+            def run(r, kind=kind):
+                a, b = r
+                n = L.or_grid_pairs(g, kind, a, b, None, 0)
+                buf = np.empty((max(n, 1), 2), dtype=np.int32)
+                m = L.or_grid_pairs(g, kind, a, b, _ptr(buf), n)
+                assert m == n
+                return buf[:n]
+            parts = _pmap(run, _slices(nq, 8 * nthreads), nthreads)
+            out.append(np.concatenate(parts).astype(np.int32) if parts else np.zeros((0, 2), np.int32))
+        return out[0], out[1]
+    finally:
+        L.or_grid_free(g)
+
+
+def barrier_reduce_bsr(sc, q, pt, ee, dhat, kappa, flags, nthreads=None):
+    """or_barrier_reduce with the reduced Hessian (flags HESS) as BSR.
+    Returns dict(status, energy, grad, n_active, rowptr, col, blocks[nnzb,3,3])
+    for one call; with several threads the pair lists are cut into slices,
+    each reduced by one call, and the slices' energies, gradients and
+    blocks are added in slice order."""
+    s = scene(sc)
+    q = _f64(q)
+    pt = _i32(pt).reshape(-1, 2) if pt is not None else np.zeros((0, 2), np.int32)
+    ee = _i32(ee).reshape(-1, 2) if ee is not None else np.zeros((0, 2), np.int32)
+    nthreads = nthreads or threads()
+    L = lib()
+    nd = 3 * s.n_node
+    if nthreads == 1:
+        jobs = [(-1, 0, 0)]  # one call over both lists: the oracle's own order
+    else:
+        jobs = [(0, a, b) for a, b in _slices(len(pt), 4 * nthreads)] + \
+               [(1, a, b) for a, b in _slices(len(ee), 4 * nthreads)]
+
+    def run(job):
+        kind, a, b = job
+        lp = pt if kind == -1 else (pt[a:b] if kind == 0 else np.zeros((0, 2), np.int32))
+        le = ee if kind == -1 else (ee[a:b] if kind == 1 else np.zeros((0, 2), np.int32))
+        e = np.zeros(1)
+        g = np.zeros(nd)
+        na = _I64()
+        st = C.c_int()
+        h = L.or_barrier_reduce_bsr(s.ref, _ptr(q), _ptr(lp), len(lp), _ptr(le), len(le), dhat, kappa,
+                                    int(flags), _ptr(e), _ptr(g), C.byref(na), C.byref(st))
+        try:
+            nnzb = L.or_bsr_nnzb(h)
+            rp = np.zeros(s.n_node + 1, dtype=np.int32)
+            col = np.zeros(max(nnzb, 1), dtype=np.int32)
+            blk = np.zeros((max(nnzb, 1), 3, 3))
+            L.or_bsr_copy(h, _ptr(rp), _ptr(col), _ptr(blk))
+        finally:
+            L.or_bsr_free(h)
+        return st.value, e[0], g, na.value, rp, col[:nnzb], blk[:nnzb]
+
+    parts = _pmap(run, jobs, nthreads)
+    status = next((p[0] for p in parts if p[0] != OK), OK)
+    energy = 0.0
+    grad = np.zeros(nd)
+    n_active = 0
+    for p in parts:
+        energy += p[1]
+        grad += p[2]
+        n_active += p[3]
+    rowptr, col, blocks = _bsr_sum(s.n_node, [(p[4], p[5], p[6]) for p in parts])
+    return {"status": status, "energy": energy, "grad": grad, "n_active": n_active,
+            "rowptr": rowptr, "col": col, "blocks": blocks}
+
+
+def _bsr_sum(n_rows, parts):
+    """Sum of block-sparse matrices with sorted columns (union pattern)."""
+    if len(parts) == 1:
+        return parts[0]
+    rows = np.concatenate([np.repeat(np.arange(n_rows), np.diff(rp)) for rp, _, _ in parts])
+    cols = np.concatenate([c for _, c, _ in parts])
+    blks = np.concatenate([b for _, _, b in parts]) if rows.size else np.zeros((0, 3, 3))
+    key = rows.astype(np.int64) * max(n_rows, 1) + cols
+    order = np.argsort(key, kind="stable")
+    key, blks = key[order], blks[order]
+    uk, start = np.unique(key, return_index=True)
+    out = np.add.reduceat(blks, start, axis=0) if uk.size else np.zeros((0, 3, 3))
+    ur = (uk // max(n_rows, 1)).astype(np.int64)
+    rowptr = np.zeros(n_rows + 1, dtype=np.int32)
+    np.add.at(rowptr, ur + 1, 1)
+    return np.cumsum(rowptr).astype(np.int32), (uk % max(n_rows, 1)).astype(np.int32), out
+
+
+def ccd_toi_threads(sc, x, p, kind, pairs, s=0.1, t_c=1.0, max_iter=100000, nthreads=None):
+    """ccd_toi over slices of the pairs on several threads (same values)."""
+    pairs = _i32(pairs).reshape(-1, 2)
+    nthreads = nthreads or threads()
+    parts = _pmap(lambda r: ccd_toi(sc, x, p, kind, pairs[r[0]:r[1]], s=s, t_c=t_c, max_iter=max_iter),
+                  _slices(len(pairs), 8 * nthreads), nthreads)
+    if not parts:
+        return np.zeros(0), np.zeros(0, dtype=np.int64)
+    return np.concatenate([a for a, _ in parts]), np.concatenate([b for _, b in parts])

@@ -913,3 +913,347 @@ int or_ccd_max_step(const or_scene *sc, const double *q, const double *dq, const
   free(x1);
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Candidate pairs through a uniform grid, for scenes too large for the */
+/* brute-force loops above.  The grid only filters: every item whose    */
+/* box shares a cell with the query's box is tested with the same       */
+/* closed-box predicate and the same exclusion rules as or_pt_query and */
+/* or_ee_query, and the pairs come out in the same (first, second)      */
+/* order, so the result is the brute-force result.  Two overlapping     */
+/* closed boxes both contain the lower corner of their overlap, and the */
+/* cell index floor((v - origin) / cell) is monotone in v, so that      */
+/* corner's cell lies in both boxes' cell ranges: no candidate is lost. */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int64_t key;
+  int32_t item;
+} or_cell_ent;
+
+struct or_grid {
+  const or_scene *sc;
+  double origin[3], cell;
+  int64_t dims[3];
+  double *vbox, *fbox, *ebox; /* [n][6]: lo xyz, hi xyz */
+  or_cell_ent *fent, *eent;
+  int64_t n_fent, n_eent;
+};
+
+static int cmp_ent(const void *a, const void *b) {
+  const or_cell_ent *x = (const or_cell_ent *)a, *y = (const or_cell_ent *)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return (x->item > y->item) - (x->item < y->item);
+}
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+static int64_t cell_index(double v, double o, double cell) { return (int64_t)floor((v - o) / cell); }
+
+static void cell_range(const or_grid *g, const double *box, int64_t *lo, int64_t *hi) {
+  for (int c = 0; c < 3; ++c) {
+    lo[c] = cell_index(box[c], g->origin[c], g->cell);
+    hi[c] = cell_index(box[3 + c], g->origin[c], g->cell);
+  }
+}
+
+static int64_t cell_key(const or_grid *g, int64_t i, int64_t j, int64_t k) {
+  return (i * g->dims[1] + j) * g->dims[2] + k;
+}
+
+static or_cell_ent *grid_entries(const or_grid *g, const double *boxes, int32_t n, int64_t *n_out) {
+  int64_t tot = 0, lo[3], hi[3];
+  for (int32_t i = 0; i < n; ++i) {
+    cell_range(g, boxes + 6 * (int64_t)i, lo, hi);
+    tot += (hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1);
+  }
+  or_cell_ent *e = (or_cell_ent *)malloc(sizeof(or_cell_ent) * (size_t)(tot + 1));
+  int64_t k = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    cell_range(g, boxes + 6 * (int64_t)i, lo, hi);
+    for (int64_t a = lo[0]; a <= hi[0]; ++a)
+      for (int64_t b = lo[1]; b <= hi[1]; ++b)
+        for (int64_t c = lo[2]; c <= hi[2]; ++c) {
+          e[k].key = cell_key(g, a, b, c);
+          e[k].item = i;
+          ++k;
+        }
+  }
+  qsort(e, (size_t)tot, sizeof(or_cell_ent), cmp_ent);
+  *n_out = tot;
+  return e;
+}
+
+/* cell <= 0: twice the mean largest box extent of the faces and edges */
+or_grid *or_grid_build(const or_scene *sc, const double *x, const double *x1, double dhat, double cell) {
+  or_grid *g = (or_grid *)calloc(1, sizeof(or_grid));
+  g->sc = sc;
+  double h = 0.5 * dhat;
+  g->vbox = (double *)malloc(sizeof(double) * 6 * (size_t)sc->n_vert + 8);
+  g->fbox = (double *)malloc(sizeof(double) * 6 * (size_t)sc->n_face + 8);
+  g->ebox = (double *)malloc(sizeof(double) * 6 * (size_t)sc->n_edge + 8);
+  for (int32_t v = 0; v < sc->n_vert; ++v) prim_box(x, x1, &v, 1, h, g->vbox + 6 * (int64_t)v, g->vbox + 6 * (int64_t)v + 3);
+  for (int32_t f = 0; f < sc->n_face; ++f)
+    prim_box(x, x1, sc->faces + 3 * (int64_t)f, 3, h, g->fbox + 6 * (int64_t)f, g->fbox + 6 * (int64_t)f + 3);
+  for (int32_t e = 0; e < sc->n_edge; ++e)
+    prim_box(x, x1, sc->edges + 2 * (int64_t)e, 2, h, g->ebox + 6 * (int64_t)e, g->ebox + 6 * (int64_t)e + 3);
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double ext = 0.0;
+  int64_t n_ext = 0;
+  const double *sets[3] = {g->vbox, g->fbox, g->ebox};
+  const int32_t counts[3] = {sc->n_vert, sc->n_face, sc->n_edge};
+  for (int s = 0; s < 3; ++s)
+    for (int32_t i = 0; i < counts[s]; ++i) {
+      const double *b = sets[s] + 6 * (int64_t)i;
+      double m = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        if (b[c] < lo[c]) lo[c] = b[c];
+        if (b[3 + c] > hi[c]) hi[c] = b[3 + c];
+        if (b[3 + c] - b[c] > m) m = b[3 + c] - b[c];
+      }
+      if (s > 0) {
+        ext += m;
+        ++n_ext;
+      }
+    }
+  if (cell <= 0.0) cell = n_ext > 0 ? 2.0 * ext / (double)n_ext : 1.0;
+  if (!(lo[0] <= hi[0])) lo[0] = lo[1] = lo[2] = hi[0] = hi[1] = hi[2] = 0.0;
+  /* keep the cell count within int64 keys */
+  for (;;) {
+    double tot = 1.0;
+    for (int c = 0; c < 3; ++c) tot *= floor((hi[c] - lo[c]) / cell) + 1.0;
+    if (tot < 1e15) break;
+    cell *= 2.0;
+  }
+  g->cell = cell;
+  for (int c = 0; c < 3; ++c) {
+    g->origin[c] = lo[c];
+    g->dims[c] = cell_index(hi[c], lo[c], cell) + 1;
+  }
+  g->fent = grid_entries(g, g->fbox, sc->n_face, &g->n_fent);
+  g->eent = grid_entries(g, g->ebox, sc->n_edge, &g->n_eent);
+  return g;
+}
+
+void or_grid_free(or_grid *g) {
+  if (!g) return;
+  free(g->vbox);
+  free(g->fbox);
+  free(g->ebox);
+  free(g->fent);
+  free(g->eent);
+  free(g);
+}
+
+double or_grid_cell(const or_grid *g) { return g->cell; }
+
+static int64_t lower_key(const or_cell_ent *e, int64_t n, int64_t key) {
+  int64_t a = 0, b = n;
+  while (a < b) {
+    int64_t m = a + (b - a) / 2;
+    if (e[m].key < key) a = m + 1; else b = m;
+  }
+  return a;
+}
+
+/* Candidates of queries q0 <= q < q1 of one kind (0: vertex against faces,
+ * 1: edge against later edges), in (query, item) order.  Returns the
+ * number of pairs; writes the first `cap` to out (2 int32 each). */
+int64_t or_grid_pairs(const or_grid *g, int kind, int32_t q0, int32_t q1, int32_t *out, int64_t cap) {
+  const or_scene *sc = g->sc;
+  const or_cell_ent *ent = kind == 0 ? g->fent : g->eent;
+  const int64_t n_ent = kind == 0 ? g->n_fent : g->n_eent;
+  const double *qbox = kind == 0 ? g->vbox : g->ebox;
+  const double *ibox = kind == 0 ? g->fbox : g->ebox;
+  int64_t bufcap = 1024, n = 0;
+  int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)bufcap);
+  for (int32_t qi = q0; qi < q1; ++qi) {
+    const double *qb = qbox + 6 * (int64_t)qi;
+    int64_t lo[3], hi[3], nb = 0;
+    cell_range(g, qb, lo, hi);
+    for (int64_t a = lo[0]; a <= hi[0]; ++a)
+      for (int64_t b = lo[1]; b <= hi[1]; ++b)
+        for (int64_t c = lo[2]; c <= hi[2]; ++c) {
+          if (a < 0 || b < 0 || c < 0 || a >= g->dims[0] || b >= g->dims[1] || c >= g->dims[2]) continue;
+          int64_t key = cell_key(g, a, b, c);
+          for (int64_t k = lower_key(ent, n_ent, key); k < n_ent && ent[k].key == key; ++k) {
+            if (nb == bufcap) {
+              bufcap *= 2;
+              buf = (int32_t *)realloc(buf, sizeof(int32_t) * (size_t)bufcap);
+            }
+            buf[nb++] = ent[k].item;
+          }
+        }
+    qsort(buf, (size_t)nb, sizeof(int32_t), cmp_i32);
+    for (int64_t k = 0; k < nb; ++k) {
+      int32_t it = buf[k];
+      if (k > 0 && buf[k - 1] == it) continue;
+      if (kind == 0) {
+        const int32_t *fv = sc->faces + 3 * (int64_t)it;
+        if (fv[0] == qi || fv[1] == qi || fv[2] == qi) continue;
+        if (!has_dof(sc, qi) && !has_dof(sc, fv[0]) && !has_dof(sc, fv[1]) && !has_dof(sc, fv[2])) continue;
+      } else {
+        if (it <= qi) continue;
+        const int32_t *ea = sc->edges + 2 * (int64_t)qi, *eb = sc->edges + 2 * (int64_t)it;
+        if (ea[0] == eb[0] || ea[0] == eb[1] || ea[1] == eb[0] || ea[1] == eb[1]) continue;
+        if (!has_dof(sc, ea[0]) && !has_dof(sc, ea[1]) && !has_dof(sc, eb[0]) && !has_dof(sc, eb[1])) continue;
+      }
+      const double *ib = ibox + 6 * (int64_t)it;
+      if (!boxes_overlap(qb, qb + 3, ib, ib + 3)) continue;
+      if (n < cap) {
+        out[2 * n] = qi;
+        out[2 * n + 1] = it;
+      }
+      ++n;
+    }
+  }
+  free(buf);
+  return n;
+}
+
+/* ------------------------------------------------------------------ */
+/* Reduction through the embedding (Eq. 17) into block-sparse rows: the */
+/* same pair loop, pair order and Neumaier-compensated sums as          */
+/* or_barrier_reduce, with the reduced Hessian kept as the 3x3 blocks   */
+/* (I, J) the pairs touch (both triangles) instead of a dense matrix.   */
+/* Row I holds its blocks sorted by column (binary search, insertion).  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t n, cap;
+  int32_t *col;
+  double *val, *comp; /* [cap][9] */
+} or_row;
+
+struct or_bsr {
+  int32_t n_rows;
+  or_row *rows;
+};
+
+static double *row_block(or_row *r, int32_t J, double **comp) {
+  int32_t a = 0, b = r->n;
+  while (a < b) {
+    int32_t m = a + (b - a) / 2;
+    if (r->col[m] < J) a = m + 1; else b = m;
+  }
+  if (a == r->n || r->col[a] != J) {
+    if (r->n == r->cap) {
+      r->cap = r->cap ? 2 * r->cap : 8;
+      r->col = (int32_t *)realloc(r->col, sizeof(int32_t) * (size_t)r->cap);
+      r->val = (double *)realloc(r->val, sizeof(double) * 9 * (size_t)r->cap);
+      r->comp = (double *)realloc(r->comp, sizeof(double) * 9 * (size_t)r->cap);
+    }
+    memmove(r->col + a + 1, r->col + a, sizeof(int32_t) * (size_t)(r->n - a));
+    memmove(r->val + 9 * (int64_t)(a + 1), r->val + 9 * (int64_t)a, sizeof(double) * 9 * (size_t)(r->n - a));
+    memmove(r->comp + 9 * (int64_t)(a + 1), r->comp + 9 * (int64_t)a, sizeof(double) * 9 * (size_t)(r->n - a));
+    r->col[a] = J;
+    memset(r->val + 9 * (int64_t)a, 0, sizeof(double) * 9);
+    memset(r->comp + 9 * (int64_t)a, 0, sizeof(double) * 9);
+    ++r->n;
+  }
+  *comp = r->comp + 9 * (int64_t)a;
+  return r->val + 9 * (int64_t)a;
+}
+
+or_bsr *or_barrier_reduce_bsr(const or_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
+                              const int32_t *ee, int64_t n_ee, double dhat, double kappa, uint32_t flags,
+                              double *energy, double *grad_q, int64_t *n_active, int *status_out) {
+  int64_t nd = 3 * (int64_t)sc->n_node;
+  double *x = (double *)malloc(sizeof(double) * 3 * (size_t)sc->n_vert + 8);
+  or_embed(sc, q, sc->x_off, x);
+  or_bsr *B = (or_bsr *)calloc(1, sizeof(or_bsr));
+  B->n_rows = sc->n_node;
+  B->rows = (or_row *)calloc((size_t)sc->n_node + 1, sizeof(or_row));
+  double es = 0.0, ec = 0.0;
+  double *gc = grad_q ? (double *)calloc((size_t)nd + 1, sizeof(double)) : NULL;
+  if (grad_q) memset(grad_q, 0, sizeof(double) * nd);
+  int64_t na = 0;
+  int status = OR_OK;
+  int moll = (flags & OR_MOLLIFY) && sc->x_rest;
+  for (int kind = 0; kind < 2; ++kind) {
+    const int32_t *list = kind == 0 ? pt : ee;
+    int64_t n = kind == 0 ? n_pt : n_ee;
+    for (int64_t k = 0; k < n; ++k) {
+      int32_t vid[4];
+      pair_vertices(sc, kind, list + 2 * k, vid);
+      double x12[12], r12[12];
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 3; ++c) {
+          x12[3 * a + c] = x[3 * vid[a] + c];
+          if (moll) r12[3 * a + c] = sc->x_rest[3 * vid[a] + c];
+        }
+      double e, g[12], H[144], P[144];
+      int st = or_pair_eval(kind, x12, moll ? r12 : NULL, dhat, kappa, NULL, NULL, &e, g, H);
+      if (st == OR_INACTIVE) continue;
+      if (st != OR_OK) {
+        status = st;
+        continue;
+      }
+      ++na;
+      nsum(&es, &ec, e);
+      const double *Hu = H;
+      if ((flags & OR_HESS) && (flags & OR_PROJECT)) {
+        or_project_psd(12, H, P);
+        Hu = P;
+      }
+      for (int a = 0; a < 4; ++a)
+        for (int32_t ka = sc->rowptr[vid[a]]; ka < sc->rowptr[vid[a] + 1]; ++ka) {
+          int32_t I = sc->col[ka];
+          double wa = sc->val[ka];
+          if (grad_q)
+            for (int i = 0; i < 3; ++i) nsum(&grad_q[3 * I + i], &gc[3 * I + i], wa * g[3 * a + i]);
+          if (!(flags & OR_HESS)) continue;
+          for (int b = 0; b < 4; ++b)
+            for (int32_t kb = sc->rowptr[vid[b]]; kb < sc->rowptr[vid[b] + 1]; ++kb) {
+              int32_t J = sc->col[kb];
+              double wab = wa * sc->val[kb];
+              double *cmp;
+              double *blk = row_block(&B->rows[I], J, &cmp);
+              for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) nsum(&blk[3 * i + j], &cmp[3 * i + j], wab * Hu[(3 * a + i) * 12 + 3 * b + j]);
+            }
+        }
+    }
+  }
+  if (grad_q)
+    for (int64_t i = 0; i < nd; ++i) grad_q[i] += gc[i];
+  for (int32_t I = 0; I < B->n_rows; ++I) {
+    or_row *r = &B->rows[I];
+    for (int64_t t = 0; t < 9 * (int64_t)r->n; ++t) r->val[t] += r->comp[t];
+  }
+  if (energy) *energy = es + ec;
+  if (n_active) *n_active = na;
+  if (status_out) *status_out = status;
+  free(gc);
+  free(x);
+  return B;
+}
+
+int64_t or_bsr_nnzb(const or_bsr *B) {
+  int64_t t = 0;
+  for (int32_t I = 0; I < B->n_rows; ++I) t += B->rows[I].n;
+  return t;
+}
+
+void or_bsr_copy(const or_bsr *B, int32_t *rowptr, int32_t *col, double *blocks) {
+  int64_t p = 0;
+  rowptr[0] = 0;
+  for (int32_t I = 0; I < B->n_rows; ++I) {
+    const or_row *r = &B->rows[I];
+    memcpy(col + p, r->col, sizeof(int32_t) * (size_t)r->n);
+    memcpy(blocks + 9 * p, r->val, sizeof(double) * 9 * (size_t)r->n);
+    p += r->n;
+    rowptr[I + 1] = (int32_t)p;
+  }
+}
+
+void or_bsr_free(or_bsr *B) {
+  if (!B) return;
+  for (int32_t I = 0; I < B->n_rows; ++I) {
+    free(B->rows[I].col);
+    free(B->rows[I].val);
+    free(B->rows[I].comp);
+  }
+  free(B->rows);
+  free(B);
+}

@@ -72,4 +72,20 @@ int or_ccd_toi(const or_scene *sc, const double *x, const double *p, int kind,
 int or_ccd_max_step(const or_scene *sc, const double *q, const double *dq, const double *dx_off,
                     double dhat, double s, double t_max, int64_t max_iter, double *alpha,
                     int64_t *n_cand, int64_t *n_capped);
+
+/* uniform-grid broad phase (same pairs and order as or_candidates) */
+typedef struct or_grid or_grid;
+or_grid *or_grid_build(const or_scene *sc, const double *x, const double *x1, double dhat, double cell);
+int64_t or_grid_pairs(const or_grid *g, int kind, int32_t q0, int32_t q1, int32_t *out, int64_t cap);
+double or_grid_cell(const or_grid *g);
+void or_grid_free(or_grid *g);
+
+/* reduction with the reduced Hessian as block-sparse rows */
+typedef struct or_bsr or_bsr;
+or_bsr *or_barrier_reduce_bsr(const or_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
+                              const int32_t *ee, int64_t n_ee, double dhat, double kappa, uint32_t flags,
+                              double *energy, double *grad_q, int64_t *n_active, int *status);
+int64_t or_bsr_nnzb(const or_bsr *B);
+void or_bsr_copy(const or_bsr *B, int32_t *rowptr, int32_t *col, double *blocks);
+void or_bsr_free(or_bsr *B);
 #endif
