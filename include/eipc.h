@@ -47,9 +47,10 @@ enum {
   EIPC_ERR_HIP = -6,          /* a HIP runtime call failed; see eipc_last_error */
   EIPC_WARN_CCD_CAPPED = 1    /* CCD hit its per-pair iteration cap (the bound is still safe) */
 };
-/* A planned call that exceeded a capacity of its plan reports
- * EIPC_ERR_CAPACITY through eipc_sync_status; its outputs are then not
- * valid and the caller plans again with a larger margin. */
+/* A planned call that exceeded a capacity of its plan, or whose
+ * reduced-Hessian block table filled up, reports EIPC_ERR_CAPACITY through
+ * eipc_sync_status; its outputs are then not valid and the caller plans
+ * again with a larger margin. */
 
 /* flags for eipc_barrier_reduce / eipc_barrier_hvp */
 enum {
@@ -57,7 +58,7 @@ enum {
   EIPC_GRAD = 2,    /* reduced gradient W^T g */
   EIPC_HESS = 4,    /* reduced Hessian W^T H W */
   EIPC_PROJECT = 8, /* use the per-pair PSD projection of H (projected Newton, Sec. III-C) */
-  EIPC_MOLLIFY = 16 /* EE mollifier for near-parallel edges (needs x_rest) */
+  EIPC_MOLLIFY = 16 /* EE mollifier for near-parallel edges (needs x_rest: EIPC_ERR_ARG without it) */
 };
 
 typedef struct eipc_ctx eipc_ctx;
@@ -104,9 +105,26 @@ typedef struct {
   const double *blocks;   /* [nnzb*9] row-major 3x3 */
 } eipc_bsr;
 
-/* Context on GPU `device`.  Owns scratch memory (grown on demand, kept
- * until eipc_destroy) and the device status word. */
-eipc_status eipc_create(eipc_ctx **ctx, int32_t device);
+/* Context on GPU `device`.  Owns the scratch memory of the calls and the
+ * device status word.
+ * reserve_bytes == 0 (grow mode): scratch buffers are allocated when a call
+ *   first needs them and replaced by larger ones when a later call needs
+ *   more.  A replaced buffer is kept, not freed, until the next
+ *   eipc_plan_step or eipc_destroy, so no call waits for the device because
+ *   of its scratch.
+ * reserve_bytes > 0 (arena mode): eipc_create allocates that many bytes
+ *   once and every later call carves its scratch from them; no call
+ *   allocates device memory after creation.  A call whose scratch does not
+ *   fit returns EIPC_ERR_CAPACITY (eipc_last_error names the size) before
+ *   it enqueues the kernel that needed it.  Size the reservation from
+ *   eipc_scratch_bytes of a grow-mode run of the same workload.
+ * Returns EIPC_ERR_ARG for a bad device, EIPC_ERR_HIP if an allocation
+ * fails. */
+eipc_status eipc_create(eipc_ctx **ctx, int32_t device, size_t reserve_bytes);
+/* reserved (host): the arena size, 0 in grow mode.  high_water (host): the
+ * most scratch one call has used (arena mode) or the bytes of all scratch
+ * buffers held (grow mode). */
+eipc_status eipc_scratch_bytes(const eipc_ctx *ctx, size_t *reserved, size_t *high_water);
 void eipc_destroy(eipc_ctx *ctx);
 const char *eipc_last_error(const eipc_ctx *ctx);
 const char *eipc_status_string(eipc_status s);
@@ -239,6 +257,18 @@ eipc_status eipc_contact_step(eipc_ctx *ctx, const eipc_scene *sc, const eipc_pl
                               const double *dq, const double *dx_off, double dhat, double kappa, uint32_t flags,
                               double s, double t_max, int64_t max_iter, double *energy, double *grad_q,
                               eipc_bsr *hess_bsr, double *alpha, int64_t *counts, eipc_stream stream);
+
+/* Pair lists of the last eipc_contact_step on this context (test and
+ * inspection use; valid until the next call that runs a planned step or
+ * carves scratch).  which = 0 / 1: the PT / EE pairs the step tested (its
+ * swept candidates when it computed alpha, else its candidates at q);
+ * which = 2 / 3: its active PT / EE pairs.  out (device int32[2*cap])
+ * receives the pairs as (first, second) rows in the step's unspecified
+ * order and *n (host) their number; when *n > cap the call returns
+ * EIPC_ERR_CAPACITY and writes nothing.  Lists cut short by a plan
+ * overflow are returned as cut.  Synchronizes. */
+eipc_status eipc_step_pairs(eipc_ctx *ctx, int32_t which, int32_t *out, int64_t cap, int64_t *n,
+                            eipc_stream stream);
 
 /* Launch shape of the library's kernels for this context: the broad-phase
  * cell edge as a multiple of the mean primitive box extent (> 0); the

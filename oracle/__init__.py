@@ -62,6 +62,7 @@ def lib():
             "or_accd_pair": (_D, [C.c_int, _P, _P, _D, _D, _I64, _P]),
             "or_ccd_toi": (C.c_int, [_P, _P, _P, C.c_int, _P, _I64, _D, _D, _I64, _P, _P]),
             "or_ccd_max_step": (C.c_int, [_P, _P, _P, _P, _D, _D, _D, _I64, _P, _P, _P]),
+            "or_narrow": (None, [_P, _P, C.c_int, _P, _I64, _D, _P, _P, _P]),
             "or_grid_build": (_P, [_P, _P, _P, _D, _D]),
             "or_grid_pairs": (_I64, [_P, C.c_int, _I32, _I32, _P, _I64]),
             "or_grid_cell": (_D, [_P]),
@@ -403,3 +404,22 @@ def ccd_toi_threads(sc, x, p, kind, pairs, s=0.1, t_c=1.0, max_iter=100000, nthr
     if not parts:
         return np.zeros(0), np.zeros(0, dtype=np.int64)
     return np.concatenate([a for a, _ in parts]), np.concatenate([b for _, b in parts])
+
+
+def narrow(sc, x, kind, pairs, dhat, nthreads=None):
+    """(type int32[n], d^2 f64[n], active bool[n]) of a pair list."""
+    s = scene(sc)
+    x = _f64(x)
+    pairs = _i32(pairs).reshape(-1, 2)
+    n = len(pairs)
+    ty = np.zeros(n, dtype=np.int32)
+    s2 = np.zeros(n)
+    act = np.zeros(n, dtype=np.uint8)
+    L = lib()
+
+    def run(r):
+        a, b = r
+        L.or_narrow(s.ref, _ptr(x), kind, _ptr(pairs[a:b]), b - a, dhat, _ptr(ty[a:]), _ptr(s2[a:]),
+                    _ptr(act[a:]))
+    _pmap(run, _slices(n, 8 * (nthreads or threads())), nthreads or threads())
+    return ty, s2, act.astype(bool)

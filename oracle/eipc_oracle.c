@@ -1257,3 +1257,22 @@ void or_bsr_free(or_bsr *B) {
   free(B->rows);
   free(B);
 }
+
+/* Narrow phase of a pair list (O3 and the indicator of Eq. 7): the
+ * distance type and squared distance of every pair, and whether it is
+ * active, 0 < d^2 < dhat^2 (d^2 < dhat^2 tested against dhat*dhat). */
+void or_narrow(const or_scene *sc, const double *x, int kind, const int32_t *pairs, int64_t n, double dhat,
+               int32_t *type, double *s2, uint8_t *active) {
+  for (int64_t k = 0; k < n; ++k) {
+    int32_t vid[4];
+    pair_vertices(sc, kind, pairs + 2 * k, vid);
+    double x12[12];
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 3; ++c) x12[3 * a + c] = x[3 * vid[a] + c];
+    int t = kind == 0 ? or_pt_type(x12, x12 + 3, x12 + 6, x12 + 9) : or_ee_type(x12, x12 + 3, x12 + 6, x12 + 9);
+    double s = or_pair_dist2(kind, t, x12);
+    if (type) type[k] = t;
+    if (s2) s2[k] = s;
+    if (active) active[k] = (uint8_t)(s > 0.0 && s < dhat * dhat);
+  }
+}

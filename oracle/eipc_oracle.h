@@ -73,6 +73,9 @@ int or_ccd_max_step(const or_scene *sc, const double *q, const double *dq, const
                     double dhat, double s, double t_max, int64_t max_iter, double *alpha,
                     int64_t *n_cand, int64_t *n_capped);
 
+void or_narrow(const or_scene *sc, const double *x, int kind, const int32_t *pairs, int64_t n, double dhat,
+               int32_t *type, double *s2, uint8_t *active);
+
 /* uniform-grid broad phase (same pairs and order as or_candidates) */
 typedef struct or_grid or_grid;
 or_grid *or_grid_build(const or_scene *sc, const double *x, const double *x1, double dhat, double cell);

@@ -68,7 +68,8 @@ def _load():
                           "or python paper_2409_16385_amd/_build.py")
     L = C.CDLL(_LIB_PATH)
     sig = {
-        "eipc_create": (_I32, [C.POINTER(_P), _I32]),
+        "eipc_create": (_I32, [C.POINTER(_P), _I32, C.c_size_t]),
+        "eipc_scratch_bytes": (_I32, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "eipc_destroy": (None, [_P]),
         "eipc_last_error": (C.c_char_p, [_P]),
         "eipc_status_string": (C.c_char_p, [_I32]),
@@ -90,6 +91,7 @@ def _load():
         "eipc_plan_step": (_I32, [_P, _P, _P, _P, _P, _D, _D, _I32, _P, _P]),
         "eipc_contact_step": (_I32, [_P, _P, _P, _P, _P, _P, _D, _D, _U32, _D, _D, _I64, _P, _P, _P, _P, _P, _P]),
         "eipc_set_tuning": (_I32, [_P, _D, _P, _I32]),
+        "eipc_step_pairs": (_I32, [_P, _I32, _P, _I64, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -113,9 +115,11 @@ def _ptr(t):
 
 
 class Context:
-    """One eipc context on one GPU (owns the library's scratch memory)."""
+    """One eipc context on one GPU (owns the library's scratch memory).
+    reserve_bytes > 0 reserves all scratch at creation (no allocation in
+    any later call; a call that needs more reports ERR_CAPACITY)."""
 
-    def __init__(self, device: int | torch.device | None = None):
+    def __init__(self, device: int | torch.device | None = None, reserve_bytes: int = 0):
         L = _load()
         if not torch.cuda.is_available():
             raise RuntimeError("the contact stage needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -126,7 +130,7 @@ class Context:
         self.device = int(device)
         self.torch_device = torch.device("cuda", self.device)
         h = _P()
-        st = L.eipc_create(C.byref(h), self.device)
+        st = L.eipc_create(C.byref(h), self.device, int(reserve_bytes))
         if st != OK:
             raise EipcError(st, "eipc_create failed")
         self._h = h
@@ -154,6 +158,13 @@ class Context:
             return st
         msg = _load().eipc_last_error(self._h).decode(errors="replace")
         raise EipcError(st, msg or _load().eipc_status_string(st).decode())
+
+    def scratch_bytes(self) -> tuple[int, int]:
+        """(reserved, high water): the arena size (0 in grow mode) and the
+        most scratch one call has used (grow mode: all buffers held)."""
+        r, h = C.c_size_t(), C.c_size_t()
+        self.check(_load().eipc_scratch_bytes(self._h, C.byref(r), C.byref(h)))
+        return r.value, h.value
 
     def sync_status(self) -> int:
         return _load().eipc_sync_status(self._h, self.stream())
@@ -502,3 +513,16 @@ def contact_step(ctx: Context, sc: Scene, plan: Plan, q, dhat: float, kappa: flo
                                    None if out.bsr is None else C.byref(out.bsr), _ptr(out.alpha),
                                    _ptr(out.counts), ctx.stream())
     ctx.check(st)
+
+
+def step_pairs(ctx: Context, which: int):
+    """Pair list of the last contact_step as an int32 [n, 2] device tensor:
+    which = 0 / 1 the PT / EE pairs it tested (swept candidates when it
+    computed alpha), 2 / 3 its active PT / EE pairs (synchronizes)."""
+    L = _load()
+    n = _I64()
+    ctx.check(L.eipc_step_pairs(ctx.handle, int(which), None, 0, C.byref(n), ctx.stream()),
+              allow=(OK, ERR_CAPACITY))
+    out = torch.empty((max(n.value, 1), 2), dtype=torch.int32, device=ctx.torch_device)
+    ctx.check(L.eipc_step_pairs(ctx.handle, int(which), _ptr(out), n.value, C.byref(n), ctx.stream()))
+    return out[:n.value]

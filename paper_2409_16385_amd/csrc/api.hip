@@ -8,6 +8,7 @@
 
 namespace eipc {
 
+
 eipc_status set_err(eipc_ctx *c, eipc_status st, const char *fmt, ...) {
   if (c) {
     va_list ap;
@@ -63,24 +64,49 @@ static void prof_collect(eipc_ctx *c) {
 
 eipc_status ensure(eipc_ctx *c, BufId id, size_t bytes, void **out) {
   DevBuf &b = c->buf[id];
-  if (b.bytes < bytes) {
-    if (b.p) {
-      EIPC_HIP(c, hipDeviceSynchronize());
-      EIPC_HIP(c, hipFree(b.p));
-      b.p = nullptr;
-      b.bytes = 0;
+  if (c->arena) {
+    // arena: carve at the top when the buffer is not yet part of this call
+    // or too small (its earlier space in this call is then left unused)
+    if (b.epoch != c->epoch || b.bytes < bytes) {
+      const size_t nb = (std::max(bytes, (size_t)256) + 255) & ~(size_t)255;
+      if (c->arena_top + nb > c->arena_bytes) {
+        c->scratch_short = true;
+        return set_err(c, EIPC_ERR_CAPACITY,
+                       "scratch reservation of %zu bytes exhausted: this call needs more than %zu bytes",
+                       c->arena_bytes, c->arena_top + nb);
+      }
+      b.p = c->arena + c->arena_top;
+      b.bytes = nb;
+      b.epoch = c->epoch;
+      c->arena_top += nb;
+      c->arena_high = std::max(c->arena_high, c->arena_top);
     }
-    size_t nb = std::max(bytes, (size_t)4096);
+    *out = b.p;
+    return EIPC_OK;
+  }
+  if (b.bytes < bytes) {
+    // grow by at least a quarter so that repeated growth stays rare; the
+    // old buffer may still be read by enqueued work, so it is retired, not
+    // freed (no device synchronization here)
+    size_t nb = std::max({bytes, (size_t)4096, b.bytes + b.bytes / 4});
     nb = (nb + 4095) & ~(size_t)4095;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, nb);
     if (e != hipSuccess)
       return set_err(c, EIPC_ERR_HIP, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
+    if (b.p) c->retired.push_back(b.p);
     b.p = p;
     b.bytes = nb;
   }
   *out = b.p;
   return EIPC_OK;
+}
+
+// frees retired scratch; the device must be idle on every stream that
+// used it (callers synchronize first)
+static void free_retired(eipc_ctx *c) {
+  for (void *p : c->retired) hipFree(p);
+  c->retired.clear();
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -121,6 +147,13 @@ static eipc_status fill_u64(eipc_ctx *c, uint64_t *p, int64_t n, uint64_t v, hip
   return EIPC_OK;
 }
 
+// the EE mollifier needs the rest positions it is defined by
+static eipc_status check_mollify(eipc_ctx *c, const eipc_scene *sc, uint32_t flags) {
+  if ((flags & EIPC_MOLLIFY) && !sc->x_rest && sc->n_edge > 0)
+    return set_err(c, EIPC_ERR_ARG, "EIPC_MOLLIFY needs the scene's rest positions (x_rest is NULL)");
+  return EIPC_OK;
+}
+
 static eipc_status check_dhat(eipc_ctx *c, double dhat) {
   if (!(dhat > 0.0) || !std::isfinite(dhat)) return set_err(c, EIPC_ERR_ARG, "dhat must be positive and finite");
   return EIPC_OK;
@@ -135,6 +168,8 @@ static eipc_status read_status(eipc_ctx *c, hipStream_t s, bool clear = true) {
   if (st & ST_BAD_W) return set_err(c, EIPC_ERR_ARG, "a row of W has more than 4 weights");
   if (st & ST_BAD_SCENE) return set_err(c, EIPC_ERR_ARG, "a vertex scene id is out of range");
   if (st & ST_PLAN_OVERFLOW) return set_err(c, EIPC_ERR_CAPACITY, "a capacity of the step plan was exceeded");
+  if (st & ST_HASH_OVERFLOW)
+    return set_err(c, EIPC_ERR_CAPACITY, "the reduced-Hessian block table is full (blocks were dropped)");
   if (st & ST_INTERSECTING) return set_err(c, EIPC_ERR_INTERSECTING, "a candidate pair has zero distance");
   if (st & ST_NONFINITE) return set_err(c, EIPC_ERR_NONFINITE, "non-finite position or pair quantity");
   if (st & ST_CCD_CAPPED) return EIPC_WARN_CCD_CAPPED;
@@ -191,7 +226,7 @@ const char *eipc_status_string(eipc_status s) {
   }
 }
 
-eipc_status eipc_create(eipc_ctx **out, int32_t device) {
+eipc_status eipc_create(eipc_ctx **out, int32_t device, size_t reserve_bytes) {
   if (!out) return EIPC_ERR_ARG;
   *out = nullptr;
   int ndev = 0;
@@ -212,6 +247,15 @@ eipc_status eipc_create(eipc_ctx **out, int32_t device) {
     eipc_destroy(c);
     return EIPC_ERR_HIP;
   }
+  if (reserve_bytes > 0) {
+    const size_t nb = (reserve_bytes + 4095) & ~(size_t)4095;
+    if (hipMalloc((void **)&c->arena, nb) != hipSuccess) {
+      c->arena = nullptr;
+      eipc_destroy(c);
+      return EIPC_ERR_HIP;
+    }
+    c->arena_bytes = nb;
+  }
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->num_cu = ncu;
@@ -225,8 +269,13 @@ void eipc_destroy(eipc_ctx *c) {
   hipDeviceSynchronize();
   prof_collect(c);
   for (auto e : c->prof_pool) hipEventDestroy(e);
-  for (auto &b : c->buf)
-    if (b.p) hipFree(b.p);
+  if (c->arena) {
+    hipFree(c->arena);
+  } else {
+    for (auto &b : c->buf)
+      if (b.p) hipFree(b.p);
+  }
+  free_retired(c);
   if (c->status) hipFree(c->status);
   if (c->stats) hipFree(c->stats);
   if (c->counters) hipFree(c->counters);
@@ -237,6 +286,19 @@ void eipc_destroy(eipc_ctx *c) {
 }
 
 const char *eipc_last_error(const eipc_ctx *c) { return c ? c->err : "no context"; }
+
+eipc_status eipc_scratch_bytes(const eipc_ctx *c, size_t *reserved, size_t *high_water) {
+  if (!c || !reserved || !high_water) return EIPC_ERR_ARG;
+  *reserved = c->arena_bytes;
+  if (c->arena) {
+    *high_water = c->arena_high;
+  } else {
+    size_t t = 0;
+    for (const auto &b : c->buf) t += b.bytes;
+    *high_water = t;
+  }
+  return EIPC_OK;
+}
 
 eipc_status eipc_profile(eipc_ctx *c, int32_t enable) {
   if (!c) return EIPC_ERR_ARG;
@@ -272,6 +334,7 @@ eipc_status eipc_sync_status(eipc_ctx *c, eipc_stream stream) {
 
 eipc_status eipc_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *off, double *x,
                        eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   if ((!q && sc->n_node > 0) || (!x && sc->n_vert > 0)) return set_err(c, EIPC_ERR_ARG, "q or x is NULL");
   EIPC_HIP(c, hipSetDevice(c->device));
@@ -281,6 +344,7 @@ eipc_status eipc_embed(eipc_ctx *c, const eipc_scene *sc, const double *q, const
 eipc_status eipc_build_candidates(eipc_ctx *c, const eipc_scene *sc, const double *q, double dhat, int32_t *pt,
                                   int64_t cap_pt, int32_t *ee, int64_t cap_ee, int64_t *n_pt, int64_t *n_ee,
                                   eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if (!n_pt || !n_ee || (!q && sc->n_node > 0) || cap_pt < 0 || cap_ee < 0)
@@ -291,9 +355,9 @@ eipc_status eipc_build_candidates(eipc_ctx *c, const eipc_scene *sc, const doubl
   EIPC_TRY(ensure_t(c, B_X, (size_t)PSTRIDE * sc->n_vert + 1, &xs));
   EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
   eipc_status s1 = broad_phase(c, sc, 0, xs, nullptr, dhat, pt, cap_pt, n_pt, 1, s);
-  if (s1 != EIPC_OK && s1 != EIPC_ERR_CAPACITY) return s1;
+  if ((s1 != EIPC_OK && s1 != EIPC_ERR_CAPACITY) || c->scratch_short) return s1;
   eipc_status s2 = broad_phase(c, sc, 1, xs, nullptr, dhat, ee, cap_ee, n_ee, 1, s);
-  if (s2 != EIPC_OK && s2 != EIPC_ERR_CAPACITY) return s2;
+  if ((s2 != EIPC_OK && s2 != EIPC_ERR_CAPACITY) || c->scratch_short) return s2;
   eipc_status st = read_status(c, s);
   if (st != EIPC_OK && st != EIPC_WARN_CCD_CAPPED) return st;
   if (s1 == EIPC_ERR_CAPACITY || s2 == EIPC_ERR_CAPACITY)
@@ -306,11 +370,13 @@ eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double 
                                 const int32_t *ee, int64_t n_ee, double dhat, double kappa, uint32_t flags,
                                 double *energy, double *grad_q, double *hess_dense, eipc_bsr *hess_bsr,
                                 int64_t *n_active, eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && !pt) || (n_ee > 0 && !ee) || (!q && sc->n_node > 0) ||
       !std::isfinite(kappa))
     return set_err(c, EIPC_ERR_ARG, "bad pair or parameter arguments");
+  EIPC_TRY(check_mollify(c, sc, flags));
   const bool want_h = (flags & EIPC_HESS) && (hess_dense || hess_bsr);
   if (want_h && 3 * (int64_t)sc->n_node >= (int64_t)INT32_MAX)
     return set_err(c, EIPC_ERR_ARG, "reduced Hessian output needs 3 * n_node < 2^31");
@@ -372,6 +438,7 @@ eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double 
 eipc_status eipc_ccd_max_step(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq,
                               const double *dx_off, double dhat, double sfac, double t_max, int64_t max_iter,
                               double *alpha, int64_t *n_cand, eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if (!alpha || (sc->n_node > 0 && (!q || !dq)) || !(sfac > 0.0 && sfac < 1.0) || !(t_max > 0.0) ||
@@ -409,10 +476,12 @@ eipc_status eipc_barrier_hvp(eipc_ctx *c, const eipc_scene *sc, const double *q,
                              const int32_t *ee, int64_t n_ee, double dhat, double kappa, uint32_t flags,
                              const double *v, const double *v_off, double *out, double *out_off,
                              eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && !pt) || (n_ee > 0 && !ee) || (sc->n_node > 0 && (!q || !v || !out)))
     return set_err(c, EIPC_ERR_ARG, "bad HVP arguments");
+  EIPC_TRY(check_mollify(c, sc, flags));
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   const int64_t n3 = (int64_t)PSTRIDE * sc->n_vert;
@@ -436,6 +505,7 @@ eipc_status eipc_narrow_phase(eipc_ctx *c, const eipc_scene *sc, const double *q
                               const int32_t *ee, int64_t n_ee, double dhat, int32_t *act_pt, int32_t *type_pt,
                               int64_t *n_act_pt, int32_t *act_ee, int32_t *type_ee, int64_t *n_act_ee,
                               eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && (!pt || !act_pt || !type_pt)) || (n_ee > 0 && (!ee || !act_ee || !type_ee)) ||
@@ -461,9 +531,11 @@ eipc_status eipc_narrow_phase(eipc_ctx *c, const eipc_scene *sc, const double *q
 eipc_status eipc_pair_eval(eipc_ctx *c, const eipc_scene *sc, const double *q, int32_t kind, const int32_t *pairs,
                            int64_t n, double dhat, double kappa, uint32_t flags, int32_t *type, double *sq, double *e,
                            double *g, double *H, eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if ((kind != 0 && kind != 1) || n < 0 || (n > 0 && !pairs)) return set_err(c, EIPC_ERR_ARG, "bad pair arguments");
+  EIPC_TRY(check_mollify(c, sc, flags));
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   double *xs;
@@ -475,6 +547,7 @@ eipc_status eipc_pair_eval(eipc_ctx *c, const eipc_scene *sc, const double *q, i
 eipc_status eipc_ccd_candidates(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq,
                                 const double *dx_off, double dhat, int32_t *pt, int64_t cap_pt, int32_t *ee,
                                 int64_t cap_ee, int64_t *n_pt, int64_t *n_ee, eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if (!n_pt || !n_ee || (sc->n_node > 0 && (!q || !dq))) return set_err(c, EIPC_ERR_ARG, "bad CCD arguments");
@@ -489,9 +562,9 @@ eipc_status eipc_ccd_candidates(eipc_ctx *c, const eipc_scene *sc, const double 
   EIPC_TRY(launch_embed(c, sc, dq, dx_off, ps, nullptr, s));
   EIPC_TRY(launch_add_soa(c, n3, xs, ps, x1s, s));
   eipc_status s1 = broad_phase(c, sc, 0, xs, x1s, dhat, pt, cap_pt, n_pt, 1, s);
-  if (s1 != EIPC_OK && s1 != EIPC_ERR_CAPACITY) return s1;
+  if ((s1 != EIPC_OK && s1 != EIPC_ERR_CAPACITY) || c->scratch_short) return s1;
   eipc_status s2 = broad_phase(c, sc, 1, xs, x1s, dhat, ee, cap_ee, n_ee, 1, s);
-  if (s2 != EIPC_OK && s2 != EIPC_ERR_CAPACITY) return s2;
+  if ((s2 != EIPC_OK && s2 != EIPC_ERR_CAPACITY) || c->scratch_short) return s2;
   EIPC_HIP(c, hipStreamSynchronize(s));
   if (s1 == EIPC_ERR_CAPACITY || s2 == EIPC_ERR_CAPACITY)
     return set_err(c, EIPC_ERR_CAPACITY, "swept candidates need %lld PT / %lld EE slots", (long long)*n_pt,
@@ -502,6 +575,7 @@ eipc_status eipc_ccd_candidates(eipc_ctx *c, const eipc_scene *sc, const double 
 eipc_status eipc_ccd_toi(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq, const double *dx_off,
                          int32_t kind, const int32_t *pairs, int64_t n, double sfac, double t_max, int64_t max_iter,
                          double *t, int64_t *iters, eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   if ((kind != 0 && kind != 1) || n < 0 || (n > 0 && (!pairs || !t)) || !(sfac > 0.0 && sfac < 1.0) ||
       !(t_max > 0.0) || max_iter < 1)
@@ -558,6 +632,15 @@ __global__ void k_step_counts(const int64_t *cn, int64_t *out) {
   }
 }
 
+// out[k] = pairs[act[k]] (two int32 per pair)
+__global__ void k_gather_pairs(const int32_t *pairs, const int32_t *act, int64_t n, int32_t *out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = act[i];
+    out[2 * i] = pairs[2 * k];
+    out[2 * i + 1] = pairs[2 * k + 1];
+  }
+}
+
 static eipc_status check_plan(eipc_ctx *c, const eipc_plan *p) {
   if (!p) return set_err(c, EIPC_ERR_ARG, "plan is NULL");
   if (p->cand_pt < 0 || p->cand_ee < 0 || p->swept_pt < 0 || p->swept_ee < 0 || p->act_pt < 0 || p->act_ee < 0 ||
@@ -569,6 +652,9 @@ static eipc_status check_plan(eipc_ctx *c, const eipc_plan *p) {
       return set_err(c, EIPC_ERR_ARG, "plan buckets must be powers of 2 and entries >= 1");
   }
   if (p->hess_blocks & (p->hess_blocks - 1)) return set_err(c, EIPC_ERR_ARG, "plan hess_blocks must be a power of 2");
+  // the block table holds the upper blocks (at most nnzb); at most half full
+  if (p->hess_blocks > 0 && p->hess_blocks < 2 * p->nnzb)
+    return set_err(c, EIPC_ERR_ARG, "plan hess_blocks must be at least 2 * nnzb");
   return EIPC_OK;
 }
 
@@ -580,6 +666,7 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
                               const double *dq, const double *dx_off, double dhat, double kappa, uint32_t flags,
                               double sfac, double t_max, int64_t max_iter, double *energy, double *grad_q,
                               eipc_bsr *hess_bsr, double *alpha, int64_t *counts, eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   EIPC_TRY(check_plan(c, plan));
@@ -587,6 +674,7 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
   if (alpha && ((!dq && sc->n_node > 0) || !(sfac > 0.0 && sfac < 1.0) || !(t_max > 0.0) || !std::isfinite(t_max) ||
                 max_iter < 1))
     return set_err(c, EIPC_ERR_ARG, "bad step-bound arguments");
+  EIPC_TRY(check_mollify(c, sc, flags));
   const bool want_h = (flags & EIPC_HESS) && hess_bsr;
   if (want_h && (plan->hess_blocks == 0 || 3 * (int64_t)sc->n_node >= (int64_t)INT32_MAX))
     return set_err(c, EIPC_ERR_ARG, "the plan has no Hessian capacity");
@@ -655,6 +743,12 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
       }
       return EIPC_OK;
     };
+    c->step_pairs[0] = cpt;
+    c->step_pairs[1] = cee;
+    c->step_pair_ctr[0] = 7;
+    c->step_pair_ctr[1] = 8;
+    c->step_pair_cap[0] = plan->swept_pt;
+    c->step_pair_cap[1] = plan->swept_ee;
     const eipc_status cst = chains();
     // joined also when a chain failed part-way, so that nothing it enqueued
     // on the side stream can overlap the caller's next use of the scratch
@@ -665,6 +759,12 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     int32_t *ppt, *pee;
     EIPC_TRY(ensure_t(c, B_STEP_PT, (size_t)2 * std::max<int64_t>(plan->cand_pt, 1), &ppt));
     EIPC_TRY(ensure_t(c, B_STEP_EE, (size_t)2 * std::max<int64_t>(plan->cand_ee, 1), &pee));
+    c->step_pairs[0] = ppt;
+    c->step_pairs[1] = pee;
+    c->step_pair_ctr[0] = 5;
+    c->step_pair_ctr[1] = 6;
+    c->step_pair_cap[0] = plan->cand_pt;
+    c->step_pair_cap[1] = plan->cand_ee;
     EIPC_TRY(broad_phase(c, sc, 0, xs, nullptr, dhat, ppt, plan->cand_pt, nullptr, 0, s, -1, nullptr, &bp[0], cn + 5));
     EIPC_TRY(broad_phase(c, sc, 1, xs, nullptr, dhat, pee, plan->cand_ee, nullptr, 0, s, -1, nullptr, &bp[1], cn + 6));
     EIPC_TRY(launch_narrow(c, sc, 0, xs, ppt, plan->cand_pt, dhat, act_pt, typ_pt, cn + 2, s, cn + 5, plan->act_pt));
@@ -677,6 +777,10 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
     }
   }
   if (want_h) EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s, plan->nnzb));
+  for (int kind = 0; kind < 2; ++kind) {
+    c->step_act[kind] = kind == 0 ? act_pt : act_ee;
+    c->step_act_cap[kind] = kind == 0 ? plan->act_pt : plan->act_ee;
+  }
   if (counts) {
     k_step_counts<<<1, 64, 0, s>>>(cn, counts);
     EIPC_HIP(c, hipGetLastError());
@@ -684,9 +788,40 @@ eipc_status eipc_contact_step(eipc_ctx *c, const eipc_scene *sc, const eipc_plan
   return EIPC_OK;
 }
 
+eipc_status eipc_step_pairs(eipc_ctx *c, int32_t which, int32_t *out, int64_t cap, int64_t *n,
+                            eipc_stream stream) {
+  if (!c) return EIPC_ERR_ARG;
+  if (which < 0 || which > 3 || !n || cap < 0 || (cap > 0 && !out))
+    return set_err(c, EIPC_ERR_ARG, "bad step_pairs arguments");
+  const int kind = which & 1;
+  if (!c->step_pairs[kind]) return set_err(c, EIPC_ERR_ARG, "no planned step has run on this context");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  int64_t cnt[9];
+  EIPC_HIP(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  const bool active = which >= 2;
+  const int64_t total = active ? std::min(cnt[2 + kind], c->step_act_cap[kind])
+                               : std::min(cnt[c->step_pair_ctr[kind]], c->step_pair_cap[kind]);
+  *n = total;
+  if (total > cap) return set_err(c, EIPC_ERR_CAPACITY, "the list has %lld pairs", (long long)total);
+  if (total == 0) return EIPC_OK;
+  if (active) {
+    k_gather_pairs<<<std::min(grid_for(total, 256), 4096), 256, 0, s>>>(c->step_pairs[kind], c->step_act[kind],
+                                                                       total, out);
+    EIPC_HIP(c, hipGetLastError());
+  } else {
+    EIPC_HIP(c, hipMemcpyAsync(out, c->step_pairs[kind], sizeof(int32_t) * 2 * (size_t)total,
+                               hipMemcpyDeviceToDevice, s));
+  }
+  EIPC_HIP(c, hipStreamSynchronize(s));
+  return EIPC_OK;
+}
+
 eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, const double *dq,
                            const double *dx_off, double dhat, double margin, int32_t with_hess, eipc_plan *plan,
                            eipc_stream stream) {
+  CallScope call(c);
   EIPC_TRY(check_scene(c, sc));
   EIPC_TRY(check_dhat(c, dhat));
   if (!plan || (!q && sc->n_node > 0) || !(margin >= 1.0) || !std::isfinite(margin))
@@ -769,6 +904,9 @@ eipc_status eipc_plan_step(eipc_ctx *c, const eipc_scene *sc, const double *q, c
                                p.hess_blocks ? &hb : nullptr, a1, cnt, stream));
   eipc_status st = read_status(c, s);
   if (st != EIPC_OK && st != EIPC_WARN_CCD_CAPPED) return st;
+  // scratch replaced while measuring is no longer used by any stream
+  EIPC_HIP(c, hipStreamSynchronize(c->side));
+  free_retired(c);
   *plan = p;
   return EIPC_OK;
 }

@@ -11,7 +11,8 @@ namespace eipc {
 constexpr int BR_THREADS = 256;
 constexpr int LTBL = 1024;  // LDS 3x3-block table entries (76 KiB)
 constexpr int LGT = 512;    // LDS node-vector table entries (14 KiB)
-constexpr int MAX_PROBE = 32;
+constexpr int MAX_PROBE = 32;       // LDS tables (a miss falls back to the global table)
+constexpr int GLOBAL_PROBE = 4096;  // global block table (at most half full; a miss is reported)
 
 __device__ __forceinline__ uint32_t mix32(uint32_t k) {
   k ^= k >> 16;
@@ -30,9 +31,9 @@ __device__ __forceinline__ uint32_t mix64(uint64_t k) {
 }
 
 // find-or-insert in an open-addressing table of 64-bit keys (-1 = empty)
-__device__ __forceinline__ int64_t table_slot64(long long *keys, uint64_t mask, long long key) {
+__device__ __forceinline__ int64_t table_slot64(long long *keys, uint64_t mask, long long key, int max_probe) {
   uint64_t h = mix64((uint64_t)key) & mask;
-  for (int p = 0; p < MAX_PROBE; ++p) {
+  for (int p = 0; p < max_probe; ++p) {
     long long k = ((volatile long long *)keys)[h];
     if (k == key) return (int64_t)h;
     if (k == -1) {
@@ -93,7 +94,7 @@ __device__ __forceinline__ void global_block_add(const HessOut &h, int n_node, i
 #pragma unroll
       for (int j = 0; j < 3; ++j) atomicAdd(&h.dense[(3 * (int64_t)I + i) * n3 + 3 * J + j], B[3 * i + j]);
   } else if (h.kind == 2) {
-    const int64_t slot = table_slot64((long long *)h.hkey, h.hmask, (long long)(I * n_node + J));
+    const int64_t slot = table_slot64((long long *)h.hkey, h.hmask, (long long)(I * n_node + J), GLOBAL_PROBE);
     if (slot < 0) {
       atomicOr(status, ST_HASH_OVERFLOW);
       return;
@@ -741,13 +742,15 @@ __global__ void k_hash_rowfill(int64_t cap, const int64_t *hkey, int n_node, con
   }
 }
 
-// Sort each BSR row by column: one wavefront per row, by rank (columns of
-// a row are distinct); rows longer than 64 x ROW_PER_LANE blocks by
-// insertion.
-constexpr int ROW_PER_LANE = 16;
+// Sort each BSR row by column, out of place (bcol, bsrc -> bcol2, bsrc2):
+// one wavefront per row.  Columns of a row are distinct, so an entry's
+// position is its rank, the number of entries of the row with a smaller
+// column.  Rows of up to 64 entries rank by shuffles; longer rows are
+// taken 64 entries at a time, each ranked against the whole row by
+// wavefront-uniform reads (any length; time grows as len^2 / 64).
 // Rows that end beyond the capacity are left alone (overflow is raised).
-__global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int64_t *bsrc, int32_t *rowptr32,
-                           int64_t nnzb_cap, uint32_t *status) {
+__global__ void k_row_sort(int n_node, const int64_t *rowptr, const int32_t *bcol, const int64_t *bsrc,
+                           int32_t *bcol2, int64_t *bsrc2, int32_t *rowptr32, int64_t nnzb_cap, uint32_t *status) {
   const int lane = threadIdx.x & 63;
   const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (r > n_node) return;
@@ -766,50 +769,23 @@ __global__ void k_row_sort(int n_node, const int64_t *rowptr, int32_t *bcol, int
   if (len <= 64) {
     const bool v = lane < len;
     const int32_t cv = v ? bcol[b + lane] : 0x7fffffff;
-    const int64_t sv = v ? bsrc[b + lane] : 0;
     int rank = 0;
     for (int j = 0; j < len; ++j) rank += __shfl(cv, j, 64) < cv;
     if (v) {
-      bcol[b + rank] = cv;
-      bsrc[b + rank] = sv;
+      bcol2[b + rank] = cv;
+      bsrc2[b + rank] = bsrc[b + lane];
     }
-  } else if (len <= 64 * ROW_PER_LANE) {
-    // rank sort: each lane ranks up to ROW_PER_LANE entries against the
-    // whole row (broadcast reads), then scatters them; every read of the
-    // row happens before the first write in the wavefront's stream
-    int32_t cv[ROW_PER_LANE];
-    int64_t sv[ROW_PER_LANE];
-    int rk[ROW_PER_LANE];
-#pragma unroll
-    for (int u = 0; u < ROW_PER_LANE; ++u) {
-      const int64_t idx = lane + 64 * u;
-      cv[u] = idx < len ? bcol[b + idx] : 0x7fffffff;
-      sv[u] = idx < len ? bsrc[b + idx] : 0;
-      rk[u] = 0;
-    }
-    for (int64_t j = 0; j < len; ++j) {
-      const int32_t cj = bcol[b + j];
-#pragma unroll
-      for (int u = 0; u < ROW_PER_LANE; ++u) rk[u] += cj < cv[u];
-    }
-#pragma unroll
-    for (int u = 0; u < ROW_PER_LANE; ++u)
-      if (lane + 64 * u < len) {
-        bcol[b + rk[u]] = cv[u];
-        bsrc[b + rk[u]] = sv[u];
-      }
-  } else if (lane == 0) {
-    for (int64_t i = b + 1; i < e; ++i) {
-      const int32_t cv = bcol[i];
-      const int64_t sv = bsrc[i];
-      int64_t j = i - 1;
-      while (j >= b && bcol[j] > cv) {
-        bcol[j + 1] = bcol[j];
-        bsrc[j + 1] = bsrc[j];
-        --j;
-      }
-      bcol[j + 1] = cv;
-      bsrc[j + 1] = sv;
+    return;
+  }
+  for (int64_t c0 = 0; c0 < len; c0 += 64) {
+    const int64_t idx = c0 + lane;
+    const bool v = idx < len;
+    const int32_t cv = v ? bcol[b + idx] : 0x7fffffff;
+    int64_t rank = 0;
+    for (int64_t j = 0; j < len; ++j) rank += bcol[b + j] < cv;
+    if (v) {
+      bcol2[b + rank] = cv;
+      bsrc2[b + rank] = bsrc[b + idx];
     }
   }
 }
@@ -857,21 +833,25 @@ eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out
   EIPC_TRY(ensure_t(c, B_BCOL, (size_t)std::max<int64_t>(nnzb_cap, 1), &bcol));
   EIPC_TRY(ensure_t(c, B_BSRC, (size_t)std::max<int64_t>(nnzb_cap, 1), &bsrc));
   EIPC_TRY(ensure_t(c, B_BBLK, (size_t)std::max<int64_t>(nnzb_cap, 1) * 9, &blocks));
+  int32_t *bcol2;
+  int64_t *bsrc2;
+  EIPC_TRY(ensure_t(c, B_BCOL2, (size_t)std::max<int64_t>(nnzb_cap, 1), &bcol2));
+  EIPC_TRY(ensure_t(c, B_BSRC2, (size_t)std::max<int64_t>(nnzb_cap, 1), &bsrc2));
   rowptr32 = rowcnt;  // counts are no longer needed once scanned
   k_hash_rowfill<<<grid_for(cap, 256), 256, 0, s>>>(cap, h.hkey, n_node, rowptr, rowfill, bcol, bsrc, nnzb_cap);
   EIPC_HIP(c, hipGetLastError());
-  k_row_sort<<<grid_for((int64_t)(n_node + 1) * 64, 256), 256, 0, s>>>(n_node, rowptr, bcol, bsrc, rowptr32,
-                                                                        nnzb_cap, c->status);
+  k_row_sort<<<grid_for((int64_t)(n_node + 1) * 64, 256), 256, 0, s>>>(n_node, rowptr, bcol, bsrc, bcol2, bsrc2,
+                                                                        rowptr32, nnzb_cap, c->status);
   EIPC_HIP(c, hipGetLastError());
   if (nnzb_cap > 0) {
-    k_bsr_gather<<<std::min(grid_for(nnzb_cap, 256), 16 * c->num_cu), 256, 0, s>>>(nnzb_cap, rowptr32, n_node, bsrc,
+    k_bsr_gather<<<std::min(grid_for(nnzb_cap, 256), 16 * c->num_cu), 256, 0, s>>>(nnzb_cap, rowptr32, n_node, bsrc2,
                                                                                    h.hval, blocks);
     EIPC_HIP(c, hipGetLastError());
   }
   out->n_rows = n_node;
   out->nnzb = planned ? -1 : nnzb;
   out->rowptr = rowptr32;
-  out->col = bcol;
+  out->col = bcol2;
   out->blocks = blocks;
   return EIPC_OK;
 }
@@ -1016,9 +996,10 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
 eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *xvs,
                        const int32_t *pairs, const int32_t *act, const int32_t *typ, const int64_t *d_count,
                        int64_t max_count, double dhat, double kappa, uint32_t flags, double *out,
-                       double *out_off, hipStream_t s) {
+                       double *out_off, hipStream_t s, bool locality_sort) {
   if (max_count == 0) return EIPC_OK;
-  EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, max_count, &act, &typ, nullptr, s));
+  // the locality order only cuts the flushes of the LDS tables
+  if (locality_sort) EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, max_count, &act, &typ, nullptr, s));
   int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), 4 * (int64_t)c->num_cu);
   ProfScope ps(c, kind == 0 ? K_HVP_PT : K_HVP_EE, s);
   if (kind == 0)

@@ -34,7 +34,7 @@ enum BufId {
   B_ACT_PT, B_TYP_PT, B_ACT_EE, B_TYP_EE,
   B_CAND_PT, B_CAND_EE,  // swept candidates (CCD)
   B_HKEY, B_HVAL,        // global block hash
-  B_ROWCNT, B_ROWFILL, B_ROWPTR, B_BCOL, B_BSRC, B_BBLK,
+  B_ROWCNT, B_ROWFILL, B_ROWPTR, B_BCOL, B_BSRC, B_BBLK, B_BCOL2, B_BSRC2,
   B_PG_PT, B_PG_EE, B_PX_PT, B_PX_EE,  // per-pair gradient / Hessian in the Q basis
   B_STEP_PT, B_STEP_EE,                // candidates of a planned step
   B_ALPHA,                             // per-scene step bound bits
@@ -68,6 +68,7 @@ struct BPPlan {
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  uint32_t epoch = 0;  // arena mode: the call that carved it
 };
 
 // kernels timed by the optional event profiler
@@ -92,7 +93,28 @@ struct eipc_ctx {
   uint32_t *status = nullptr;   // device status word
   double *stats = nullptr;      // device [32] reduction scratch
   int64_t *counters = nullptr;  // device [16] counters
-  int64_t *host = nullptr;      // pinned host staging [64]
+  // Scratch.  Grow mode (no reservation): each buffer is allocated on
+  // first need and replaced by a larger one when a call needs more; the
+  // replaced buffer is kept (work already enqueued may still use it) until
+  // the next synchronizing plan or eipc_destroy, so growth never waits for
+  // the device.  Arena mode (reserve_bytes > 0 at creation): one
+  // allocation made by eipc_create, carved afresh by every top-level call
+  // (nothing in scratch outlives the call that wrote it, except outputs
+  // that are valid until the next call); a call that does not fit returns
+  // EIPC_ERR_CAPACITY and nothing is ever allocated after creation.
+  std::vector<void *> retired;
+  char *arena = nullptr;
+  size_t arena_bytes = 0, arena_top = 0, arena_high = 0;
+  uint32_t epoch = 1;
+  int depth = 0;               // nesting of entry points (plan_step calls others)
+  bool scratch_short = false;  // this call ran out of its reservation
+  // pair lists of the last planned step, for eipc_step_pairs: the pairs
+  // it tested per kind, their count word and capacity, and its active
+  // lists (indices into them)
+  const int32_t *step_pairs[2] = {nullptr, nullptr};
+  const int32_t *step_act[2] = {nullptr, nullptr};
+  int step_pair_ctr[2] = {0, 0};
+  int64_t step_pair_cap[2] = {0, 0}, step_act_cap[2] = {0, 0};
   int64_t hash_cap = 1 << 16;   // global block hash capacity (power of 2, grows)
   int num_cu = 256;
   double cell_scale = 2.0;       // broad-phase cell edge / mean item extent
@@ -130,8 +152,25 @@ eipc_status set_err(eipc_ctx *c, eipc_status st, const char *fmt, ...);
     if (s_ != EIPC_OK) return s_; \
   } while (0)
 
-// grow-only scratch allocation
+// scratch allocation (grow mode or arena mode, see eipc_ctx)
 eipc_status ensure(eipc_ctx *c, BufId id, size_t bytes, void **out);
+// Marks one entry-point call: the outermost call on a context starts a
+// fresh carving of the arena.
+struct CallScope {
+  eipc_ctx *c;
+  explicit CallScope(eipc_ctx *c_) : c(c_) {
+    if (c && c->depth++ == 0) {
+      c->scratch_short = false;
+      if (c->arena) {
+        c->arena_top = 0;
+        ++c->epoch;
+      }
+    }
+  }
+  ~CallScope() {
+    if (c) --c->depth;
+  }
+};
 template <class T>
 inline eipc_status ensure_t(eipc_ctx *c, BufId id, size_t count, T **out) {
   void *p = nullptr;
@@ -227,7 +266,7 @@ eipc_status bsr_compact(eipc_ctx *c, int n_node, const HessOut &h, eipc_bsr *out
 eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *xvs,
                        const int32_t *pairs, const int32_t *act, const int32_t *typ, const int64_t *d_count,
                        int64_t max_count, double dhat, double kappa, uint32_t flags, double *out,
-                       double *out_off, hipStream_t s);
+                       double *out_off, hipStream_t s, bool locality_sort = true);
 eipc_status launch_pair_eval(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                              int64_t n, double dhat, double kappa, uint32_t flags, int32_t *type, double *sq,
                              double *e, double *g, double *H, hipStream_t s);

@@ -321,6 +321,24 @@ def mixed_scale_scene(seed: int = 0, n: int = 80, size: float = 0.1, dhat: float
                  meta={"sheet_n": n, "size": size})
 
 
+def long_row_scene(seed: int = 0, n: int = 80, size: float = 0.1, dhat: float = 2e-4) -> Scene:
+    """The mixed-scale sheet with other embeddings: the n x n sheet is
+    full-space (W = I, one node per vertex) over the 3x3-quad middle plate
+    alone, now a dynamic affine body (one enclosing tetrahedron, 4 nodes).
+    Every sheet vertex over the plate couples with its 4 nodes, so those
+    reduced-Hessian rows hold thousands of blocks."""
+    rng = rng_for(seed, 0)
+    sv, sf = _grid_sheet(n, 0.0, size, 0.5 * dhat)
+    sv[:, 2] += rng.uniform(-0.3, 0.3, len(sv)) * dhat
+    mv, mf = _grid_sheet(3, 0.2 * size, 0.8 * size, 0.0)
+    bodies = [Body(sv, sf, None, full_space=True), Body(mv, mf, SingleTet(mv))]
+    asm = _assemble(bodies)
+    q = asm[5].copy()
+    dq = rng.normal(0.0, 0.2 * dhat, q.shape)
+    return _make(f"longrow{seed}", bodies, q, dq, dhat, 1e3, seed, assembled=asm,
+                 meta={"sheet_n": n, "size": size})
+
+
 # ---------------------------------------------------------------------------
 # Config 3: plate over a rack of cylinders
 # ---------------------------------------------------------------------------

@@ -79,6 +79,12 @@ def _scene_hess(bsr, hb, i):
     return H
 
 
+def _sorted_rows(t):
+    a = t.cpu().numpy() if hasattr(t, "cpu") else np.asarray(t)
+    a = a.reshape(-1, 2).astype(np.int64)
+    return a[np.lexsort((a[:, 1], a[:, 0]))]
+
+
 def _check_against_sequential(b, seq, scenes):
     cnt = b.counts()
     assert cnt["cand_pt"] == sum(r["n_pt"] for r in seq)
@@ -155,17 +161,27 @@ def test_graph_replays_match_eager(batch, scenes):
 
 
 def test_plan_overflow_is_reported(batch):
-    """A plan with too few candidate slots reports a capacity error (the
-    kernels stay within the planned buffers) and the next good step is
-    clean."""
-    for field in ("swept_pt", "swept_ee", "act_pt", "act_ee", "nnzb"):
+    """A plan with too few candidate, active-pair, BSR or block-table slots
+    reports a capacity error (the kernels stay within the planned buffers,
+    and a full block table is reported, never dropped silently) and the
+    next good step is clean.  A block table under twice the BSR capacity is
+    an argument error."""
+    for field in ("swept_pt", "swept_ee", "act_pt", "act_ee", "nnzb", "hess_blocks"):
         small = E.Plan.from_buffer_copy(batch.plan)
         setattr(small, field, 16)
+        if field == "hess_blocks":
+            small.nnzb = 8  # a table of 16 blocks holds at most 8 (half full)
         E.contact_step(batch.ctx, batch.scene, small, batch.q, batch.hb.dhat, batch.hb.kappa, batch.out, batch.dq,
                        None, BT.DEFAULT_FLAGS)
         assert batch.status() == E.binding.ERR_CAPACITY, field
         batch.step()
         assert batch.status() == E.binding.OK
+    small = E.Plan.from_buffer_copy(batch.plan)
+    small.hess_blocks = 16
+    with pytest.raises(E.EipcError) as ei:
+        E.contact_step(batch.ctx, batch.scene, small, batch.q, batch.hb.dhat, batch.hb.kappa, batch.out, batch.dq,
+                       None, BT.DEFAULT_FLAGS)
+    assert ei.value.status == E.binding.ERR_ARG
 
 
 def test_autotune_keeps_results(ctx, scenes, seq):
@@ -212,3 +228,58 @@ def test_query_work_split_does_not_change_results(ctx, scenes, seq, mode):
     b.step()
     assert b.status() == E.binding.OK
     _check_against_sequential(b, seq, scenes)
+
+
+@pytest.fixture(scope="module")
+def slice32():
+    """The first 32 scenes of the 256-scene benchmark batch (same seeds)."""
+    return S.batch_scenes(32)
+
+
+def test_batch_slice_against_oracle(ctx, slice32):
+    """One planned step over 32 scenes of the benchmark batch against the
+    oracle scene by scene: candidate, swept and active sets (the step's own
+    unsorted lists, sorted, in batch numbering), energy, reduced gradient
+    and Hessian within 1e-10, step bound equal."""
+    scenes = slice32
+    b = BT.Batch(ctx, BT.concat(scenes))
+    b.make_plan(1.5)
+    b.step()
+    assert b.status() == E.binding.OK
+    hb = b.hb
+    energy = b.out.energy.cpu().numpy()
+    alpha = b.out.alpha.cpu().numpy()
+    rp, col, blk = (t.cpu().numpy() for t in b.out.hess(b.ctx))
+    lists = {w: _sorted_rows(E.step_pairs(b.ctx, w)) for w in range(4)}
+    want = {w: [] for w in range(4)}
+    n_act = 0
+    for i, sc in enumerate(scenes):
+        x = O.embed(sc, sc.q)
+        p = O.embed(sc, sc.dq, off=sc.dx_off)
+        pt, ee = O.candidates_grid(sc, x, sc.dhat)
+        spt, see = O.candidates_grid(sc, x, sc.dhat, x1=x + p)
+        red = O.barrier_reduce_bsr(sc, sc.q, pt, ee, sc.dhat, sc.kappa, BT.DEFAULT_FLAGS)
+        n_act += red["n_active"]
+        tp, _ = O.ccd_toi_threads(sc, x, p, 0, spt)
+        te, _ = O.ccd_toi_threads(sc, x, p, 1, see)
+        assert alpha[i] == min(1.0, tp.min(initial=1.0), te.min(initial=1.0)), i
+        if red["n_active"]:
+            assert abs(energy[i] - red["energy"]) <= TOL * abs(red["energy"]), i
+            assert _rel(b.per_scene_grad(i).cpu().numpy(), red["grad"]) <= TOL, i
+        else:
+            assert energy[i] == 0.0
+        # this scene's rows of the batch Hessian, in scene numbering
+        n0, n1 = hb.node_off[i], hb.node_off[i + 1]
+        srp = rp[n0:n1 + 1] - rp[n0]
+        assert np.array_equal(srp, red["rowptr"]), i
+        assert np.array_equal(col[rp[n0]:rp[n1]] - n0, red["col"]), i
+        if len(red["col"]):
+            assert _rel(blk[rp[n0]:rp[n1]], red["blocks"]) <= TOL, i
+        vo, fo, eo = hb.vert_off[i], hb.face_off[i], hb.edge_off[i]
+        want[0].append(spt.astype(np.int64) + [vo, fo])
+        want[1].append(see.astype(np.int64) + [eo, eo])
+        want[2].append(pt[O.narrow(sc, x, 0, pt, sc.dhat)[2]].astype(np.int64) + [vo, fo])
+        want[3].append(ee[O.narrow(sc, x, 1, ee, sc.dhat)[2]].astype(np.int64) + [eo, eo])
+    assert b.counts()["active"] == n_act
+    for w in range(4):
+        assert np.array_equal(lists[w], _sorted_rows(np.concatenate(want[w]))), w

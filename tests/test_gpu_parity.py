@@ -299,3 +299,93 @@ def test_argument_errors_enqueue_nothing(ctx, c1):
     assert ei.value.status == -1
     with pytest.raises(E.EipcError):
         E.ccd_max_step(ctx, dsc, _dev(c1.q), _dev(c1.dq), c1.dhat, s=1.5)
+
+
+def test_mollifier_without_rest_positions_is_an_argument_error(ctx):
+    """EIPC_MOLLIFY is defined by the rest edge lengths: a scene without
+    them is rejected (never silently unmollified)."""
+    import copy
+    sc = copy.copy(tiny_scene(2, mode="grid"))
+    sc.x_rest = None
+    dsc = E.Scene.from_host(ctx, sc)
+    x = O.embed(sc, sc.q)
+    pt, ee = O.candidates(sc, x, sc.dhat)
+    q = _dev(sc.q)
+    with pytest.raises(E.EipcError) as ei:
+        E.barrier_reduce(ctx, dsc, q, _dev(pt), _dev(ee), sc.dhat, sc.kappa, FLAGS | E.MOLLIFY, hess="dense")
+    assert ei.value.status == -1
+    with pytest.raises(E.EipcError) as ei:
+        E.barrier_hvp(ctx, dsc, q, _dev(pt), _dev(ee), sc.dhat, sc.kappa, E.MOLLIFY, _dev(np.ones_like(sc.q)))
+    assert ei.value.status == -1
+    with pytest.raises(E.EipcError) as ei:
+        E.pair_eval(ctx, dsc, q, 1, _dev(ee), sc.dhat, sc.kappa, E.MOLLIFY)
+    assert ei.value.status == -1
+    # without the flag the same call runs
+    r = E.barrier_reduce(ctx, dsc, q, _dev(pt), _dev(ee), sc.dhat, sc.kappa, FLAGS, hess="dense")
+    assert r["n_active"] > 0
+
+
+def test_arena_mode_matches_grow_mode(ctx, c1):
+    """A context created with a scratch reservation carves every call from
+    it (no allocation after creation) and gives the grow-mode results; a
+    reservation too small for a call is a capacity error, and the context
+    stays usable for calls that fit."""
+    dsc = E.Scene.from_host(ctx, c1)
+    q, dq = _dev(c1.q), _dev(c1.dq)
+    g = E.Context(0)
+    dg = E.Scene.from_host(g, c1)
+
+    def run(cx, ds):
+        pt, ee = E.build_candidates(cx, ds, q, c1.dhat)
+        r = E.barrier_reduce(cx, ds, q, pt, ee, c1.dhat, c1.kappa, FLAGS, hess="bsr")
+        a, n, _ = E.ccd_max_step(cx, ds, q, dq, c1.dhat)
+        hv = E.barrier_hvp(cx, ds, q, pt, ee, c1.dhat, c1.kappa, E.PROJECT, dq)
+        return pt, ee, r, a, n, hv
+
+    ref = run(g, dg)
+    reserved, high = g.scratch_bytes()
+    assert reserved == 0 and high > 0
+    a_ctx = E.Context(0, reserve_bytes=2 * high)
+    da = E.Scene.from_host(a_ctx, c1)
+    for _ in range(2):  # the second round reuses the same carving
+        got = run(a_ctx, da)
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+        assert got[2]["n_active"] == ref[2]["n_active"]
+        assert _rel(got[2]["grad"].cpu().numpy(), ref[2]["grad"].cpu().numpy()) <= 1e-12
+        for u, v in zip(got[2]["hess"][:2], ref[2]["hess"][:2]):
+            assert torch.equal(u, v)
+        assert _rel(got[2]["hess"][2].cpu().numpy(), ref[2]["hess"][2].cpu().numpy()) <= 1e-12
+        assert got[3] == ref[3] and got[4] == ref[4]
+        assert _rel(got[5].cpu().numpy(), ref[5].cpu().numpy()) <= 1e-12
+    r2, h2 = a_ctx.scratch_bytes()
+    assert r2 >= 2 * high and 0 < h2 <= r2
+    tiny_ctx = E.Context(0, reserve_bytes=1 << 20)
+    dt = E.Scene.from_host(tiny_ctx, c1)
+    with pytest.raises(E.EipcError) as ei:
+        E.ccd_max_step(tiny_ctx, dt, q, dq, c1.dhat)
+    assert ei.value.status == -2
+    sc = tiny_scene(0)
+    ds = E.Scene.from_host(tiny_ctx, sc)
+    pt, ee = E.build_candidates(tiny_ctx, ds, _dev(sc.q), sc.dhat)
+    opt, oee = O.candidates(sc, O.embed(sc, sc.q), sc.dhat)
+    assert np.array_equal(pt.cpu().numpy(), opt) and np.array_equal(ee.cpu().numpy(), oee)
+
+
+def test_long_bsr_rows_against_oracle(ctx):
+    """A full-space sheet over an affine-body plate: the plate's 4 node rows
+    hold about 2,600 blocks each (rows beyond 64 blocks are sorted 64 at a
+    time against the whole row).  Blocks, pattern and products match the
+    oracle."""
+    from scenes.scene import long_row_scene
+    sc = long_row_scene()
+    dsc = E.Scene.from_host(ctx, sc)
+    x = O.embed(sc, sc.q)
+    pt, ee = O.candidates_grid(sc, x, sc.dhat)
+    ref = O.barrier_reduce_bsr(sc, sc.q, pt, ee, sc.dhat, sc.kappa, FLAGS)
+    assert ref["status"] == O.OK and np.diff(ref["rowptr"]).max() > 1024
+    q = _dev(sc.q)
+    r = E.barrier_reduce(ctx, dsc, q, _dev(pt), _dev(ee), sc.dhat, sc.kappa, FLAGS, hess="bsr")
+    rp, col, blk = (t.cpu().numpy() for t in r["hess"])
+    assert np.array_equal(rp, ref["rowptr"]) and np.array_equal(col, ref["col"])
+    assert _rel(blk.reshape(-1, 3, 3), ref["blocks"]) <= TOL
+    assert _rel(r["grad"].cpu().numpy(), ref["grad"]) <= TOL

@@ -35,9 +35,11 @@ def test_status_strings_and_argument_errors_without_gpu():
     L = B._load()
     assert L.eipc_status_string(0) == b"ok"
     assert L.eipc_status_string(-3).startswith(b"intersecting")
-    assert L.eipc_create(None, 0) == B.ERR_ARG
+    assert L.eipc_create(None, 0, 0) == B.ERR_ARG
     h = C.c_void_p()
-    assert L.eipc_create(C.byref(h), -1) == B.ERR_ARG
+    assert L.eipc_create(C.byref(h), -1, 0) == B.ERR_ARG
+    r, hw = C.c_size_t(), C.c_size_t()
+    assert L.eipc_scratch_bytes(None, C.byref(r), C.byref(hw)) == B.ERR_ARG
     # NULL context is rejected before any device work
     assert L.eipc_build_candidates(None, None, None, 1e-3, None, 0, None, 0, None, None, None) == B.ERR_ARG
     assert L.eipc_barrier_reduce(None, None, None, None, 0, None, 0, 1e-3, 1.0, 0, None, None, None, None,
