@@ -330,6 +330,27 @@ eipc_status eipc_profile_read(eipc_ctx *ctx, const char *name, double *ms, int64
  * (device int32[n_pt] / [n_ee]) receive indices into pt / ee, type_pt /
  * type_ee (device int32, same sizes) the distance type, in unspecified
  * order; counts go to the host.  Synchronizes. */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * product of eipc_barrier_hvp (same arguments, same result up to the
+ * rounding order of its sums) with all scratch in a fixed array of
+ * EIPC_NOALLOC_SCRATCH_BYTES that the library holds on each GPU from
+ * module load until the process ends (its address is looked up once per
+ * device by eipc_create).  The call allocates nothing, does not
+ * synchronize, and records no memset.  It needs
+ *   256 + 2 * (32 * n_vert + 64) + 8 * (n_pt + n_ee)  bytes
+ * (each term rounded up to 256; n_pt, n_ee at least 1); larger inputs
+ * return EIPC_ERR_CAPACITY with nothing enqueued.  Every call on one GPU,
+ * from any context, uses that GPU's one array: calls that overlap in time
+ * on one GPU (two streams, two host threads) race and give wrong results,
+ * so callers order them on one stream.  Data-dependent errors go to the
+ * context's status word as for eipc_barrier_hvp. */
+#define EIPC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+eipc_status eipc_barrier_hvp_noalloc(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
+                                     int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
+                                     uint32_t flags, const double *v, const double *v_off, double *out,
+                                     double *out_off, eipc_stream stream);
+
 eipc_status eipc_narrow_phase(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
                               int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, int32_t *act_pt,
                               int32_t *type_pt, int64_t *n_act_pt, int32_t *act_ee, int32_t *type_ee,

@@ -92,6 +92,7 @@ def _load():
         "eipc_contact_step": (_I32, [_P, _P, _P, _P, _P, _P, _D, _D, _U32, _D, _D, _I64, _P, _P, _P, _P, _P, _P]),
         "eipc_set_tuning": (_I32, [_P, _D, _P, _I32]),
         "eipc_step_pairs": (_I32, [_P, _I32, _P, _I64, _P, _P]),
+        "eipc_barrier_hvp_noalloc": (_I32, [_P, _P, _P, _P, _I64, _P, _I64, _D, _D, _U32, _P, _P, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -341,14 +342,17 @@ def ccd_max_step(ctx: Context, sc: Scene, q, dq, dhat: float, dx_off=None, s: fl
 
 
 def barrier_hvp(ctx: Context, sc: Scene, q, pt, ee, dhat: float, kappa: float, flags: int, v, v_off=None,
-                want_off: bool = False):
+                want_off: bool = False, noalloc: bool = False):
+    """Hessian-vector product; noalloc: the library's no-allocation entry
+    point (fixed scratch array; inputs and outputs still come from torch)."""
     dev = ctx.torch_device
     q, v, v_off = _f64(q, dev), _f64(v, dev), _f64(v_off, dev)
     pt = _i32(pt, dev).reshape(-1, 2)
     ee = _i32(ee, dev).reshape(-1, 2)
     out = torch.empty(3 * sc.n_node, dtype=torch.float64, device=dev)
     out_off = torch.empty((sc.n_vert, 3), dtype=torch.float64, device=dev) if want_off else None
-    st = _load().eipc_barrier_hvp(ctx.handle, sc.ref, _ptr(q), _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0],
+    fn = _load().eipc_barrier_hvp_noalloc if noalloc else _load().eipc_barrier_hvp
+    st = fn(ctx.handle, sc.ref, _ptr(q), _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0],
                                   float(dhat), float(kappa), int(flags), _ptr(v), _ptr(v_off), _ptr(out),
                                   _ptr(out_off), ctx.stream())
     ctx.check(st)

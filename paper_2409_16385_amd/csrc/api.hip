@@ -4,10 +4,31 @@
 #include <cstring>
 #include <new>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace eipc {
 
+// Fixed scratch of eipc_barrier_hvp_noalloc: one copy per GPU, held from
+// module load until the process ends.  Host code uses its per-device
+// address (noalloc_scratch_of), never this name.
+static __device__ __align__(256) unsigned char scratch[EIPC_NOALLOC_SCRATCH_BYTES];
+
+// Device address of this GPU's copy of `scratch` (the device must be
+// current); looked up once per device.  nullptr when the lookup fails.
+static void *noalloc_scratch_of(int device) {
+  static std::mutex mu;
+  static void *addr[64] = {nullptr};
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    addr[device] = p;
+  }
+  return addr[device];
+}
 
 eipc_status set_err(eipc_ctx *c, eipc_status st, const char *fmt, ...) {
   if (c) {
@@ -256,6 +277,11 @@ eipc_status eipc_create(eipc_ctx **out, int32_t device, size_t reserve_bytes) {
     }
     c->arena_bytes = nb;
   }
+  c->noalloc_scratch = noalloc_scratch_of(device);
+  if (!c->noalloc_scratch) {
+    eipc_destroy(c);
+    return EIPC_ERR_HIP;
+  }
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->num_cu = ncu;
@@ -498,6 +524,48 @@ eipc_status eipc_barrier_hvp(eipc_ctx *c, const eipc_scene *sc, const double *q,
                       s));
   EIPC_TRY(launch_hvp(c, sc, 1, xs, xvs, ee, act_ee, typ_ee, c->counters + 3, n_ee, dhat, kappa, flags, out, out_off,
                       s));
+  return EIPC_OK;
+}
+
+eipc_status eipc_barrier_hvp_noalloc(eipc_ctx *c, const eipc_scene *sc, const double *q, const int32_t *pt,
+                                     int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
+                                     uint32_t flags, const double *v, const double *v_off, double *out,
+                                     double *out_off, eipc_stream stream) {
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && !pt) || (n_ee > 0 && !ee) || (sc->n_node > 0 && (!q || !v || !out)))
+    return set_err(c, EIPC_ERR_ARG, "bad HVP arguments");
+  EIPC_TRY(check_mollify(c, sc, flags));
+  // carve the fixed array: counters, positions of q and of v, active lists
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t pos = up(sizeof(double) * PSTRIDE * (size_t)sc->n_vert + 64);
+  const size_t lpt = up(sizeof(int32_t) * (size_t)std::max<int64_t>(n_pt, 1));
+  const size_t lee = up(sizeof(int32_t) * (size_t)std::max<int64_t>(n_ee, 1));
+  const size_t need = 256 + 2 * pos + 2 * lpt + 2 * lee;
+  if (need > EIPC_NOALLOC_SCRATCH_BYTES)
+    return set_err(c, EIPC_ERR_CAPACITY, "this product needs %zu bytes of scratch; the fixed array holds %zu", need,
+                   (size_t)EIPC_NOALLOC_SCRATCH_BYTES);
+  if (!c->noalloc_scratch) return set_err(c, EIPC_ERR_HIP, "no address for the fixed scratch array");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  char *base = (char *)c->noalloc_scratch;
+  int64_t *cnt = (int64_t *)base;
+  double *xs = (double *)(base + 256);
+  double *xvs = (double *)(base + 256 + pos);
+  int32_t *act_pt = (int32_t *)(base + 256 + 2 * pos);
+  int32_t *typ_pt = (int32_t *)(base + 256 + 2 * pos + lpt);
+  int32_t *act_ee = (int32_t *)(base + 256 + 2 * pos + 2 * lpt);
+  int32_t *typ_ee = (int32_t *)(base + 256 + 2 * pos + 2 * lpt + lee);
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_embed(c, sc, v, v_off, xvs, nullptr, s));
+  EIPC_TRY(launch_zero(c, cnt, 2 * sizeof(int64_t), s));  // the array keeps the last call's counts
+  EIPC_TRY(launch_narrow(c, sc, 0, xs, pt, n_pt, dhat, act_pt, typ_pt, cnt, s));
+  EIPC_TRY(launch_narrow(c, sc, 1, xs, ee, n_ee, dhat, act_ee, typ_ee, cnt + 1, s));
+  EIPC_TRY(launch_zero(c, out, sizeof(double) * 3 * (size_t)sc->n_node, s));
+  if (out_off) EIPC_TRY(launch_zero(c, out_off, sizeof(double) * 3 * (size_t)sc->n_vert, s));
+  EIPC_TRY(launch_hvp(c, sc, 0, xs, xvs, pt, act_pt, typ_pt, cnt, n_pt, dhat, kappa, flags, out, out_off, s, false));
+  EIPC_TRY(launch_hvp(c, sc, 1, xs, xvs, ee, act_ee, typ_ee, cnt + 1, n_ee, dhat, kappa, flags, out, out_off, s,
+                      false));
   return EIPC_OK;
 }
 

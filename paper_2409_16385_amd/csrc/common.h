@@ -133,6 +133,9 @@ struct eipc_ctx {
   // main chain; joined back through events, also under graph capture
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // device address of this GPU's copy of the library's fixed no-allocation
+  // scratch array (looked up once per device at creation)
+  void *noalloc_scratch = nullptr;
 };
 
 namespace eipc {
