@@ -27,18 +27,18 @@ METRIC = "contact pairs/s (barrier+reduce) & CCD pairs/s, FP64, % HBM roofline"
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops per active pair, split by kernel.  Pair terms
-# (distance type fixed): derivatives of the feature function in the
-# 9-dimensional translation-free basis (point-point / point-line /
-# triple-product) + barrier chain rule + basis change + 9x9 Jacobi
-# eigen-projection (9 n^3) + reconstruction (2 n^2 (n+1) / 2).  Expansion:
-# blocks z_I^T X z_J over the merged nodes of the pair (16 weights, 136
-# block pairs) and the gradient expansion.
-FLOPS_TERMS = 220 + 200 + 6561 + 810
-FLOPS_DIST = {"PP": 30, "PL": 350, "TRI": 700}
-FLOPS_EXPAND = 810 + 2584 + 132
-PT_FN = ["PP", "PP", "PP", "PL", "PL", "PL", "TRI"]
-EE_FN = ["PP", "PP", "PP", "PP", "PL", "PL", "PL", "PL", "TRI"]
+# Algorithmic FP64 flops per active pair, split by kernel (counts of the
+# operations the method needs, not of what a kernel executes).  Pair terms:
+# distance, its gradient and Hessian ~1e3, barrier chain rule and assembly
+# ~0.3e3, the symmetric eigendecomposition of the 9x9 translation-free
+# Hessian 9 n^3 = 6,561 and the reconstruction V max(L, 0) V^T ~2e3.
+# Expansion through W (16 weights, merged nodes, blocks and gradient):
+# ~4.6e3.  Algorithmic bytes per active pair for the whole barrier +
+# reduction: the pair record, its share of the gathered geometry and of
+# the outputs, ~85 B at config 2's reuse.
+FLOPS_TERMS = 1000 + 300 + 6561 + 2000
+FLOPS_EXPAND = 4600
+BYTES_BARRIER_PAIR = 85
 FAMILIES = {
     "query": ("query_count_pt", "query_count_ee", "query_write_pt", "query_write_ee"),
     "pair_terms": ("barrier_pt", "barrier_ee"), "expand": ("expand_pt", "expand_ee"),
@@ -56,8 +56,8 @@ def _args():
                     help="resolution: config 2's surface meshes with object grids from 250 to 32,000 nodes")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n-scene", type=int, default=256, help="scenes in the batch config")
-    ap.add_argument("--cpu-queries", type=int, default=2000,
-                    help="oracle CPU baseline: number of sampled query primitives per kind")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the main workload (skip configs 1, 3, 4 and the batch beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--no-graph", action="store_true", help="time eager planned steps instead of graph replays")
@@ -123,66 +123,49 @@ def load_traffic(kernel, workload, tuning=None):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(sc, n_queries, log):
-    """Oracle (single thread) on a bounded sample: brute-force candidate
-    queries for a sample of vertices and edges (untimed), then the oracle's
-    barrier + reduction timed on the pairs they produce."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sc, log, slice_frac=1.0 / 16):
+    """The oracle on the host cores: its uniform-grid candidates of the
+    whole scene (untimed), then its barrier + reduction (energy, gradient,
+    PSD-projected block-sparse Hessian) over all candidates, timed on every
+    host thread (the pair lists cut into slices, one oracle call per slice),
+    and on one thread over the first slice_frac of each list."""
     import numpy as np
 
     import oracle as O
-    dof = np.diff(sc.W_rowptr) > 0
     x = O.embed(sc, sc.q)
-    rng = np.random.default_rng(sc.seed + 99)
-    from scipy.sparse import coo_matrix
-    from scipy.sparse.csgraph import connected_components
-    e = sc.edges.astype(np.int64)
-    adj = coo_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(sc.n_vert, sc.n_vert))
-    _, body = connected_components(adj, directed=False)
-    # vertices within 2 dhat (grid cells) of a vertex of another body
-    h = 2 * sc.dhat
-    keys = np.floor(x / h).astype(np.int64)
-    keys -= keys.min(axis=0)
-    span = keys.max(axis=0) + 3
-    near = np.zeros(sc.n_vert, dtype=bool)
-    code = lambda k: (k[:, 0] * span[1] + k[:, 1]) * span[2] + k[:, 2]
-    base = code(keys + 1)
-    order = np.argsort(base)
-    sb = base[order]
-    bl = body[order]
-    for dx in (-1, 0, 1):
-        for dy in (-1, 0, 1):
-            for dz in (-1, 0, 1):
-                c = code(keys + 1 + np.array([dx, dy, dz]))
-                lo = np.searchsorted(sb, c, side="left")
-                hi = np.searchsorted(sb, c, side="right")
-                idx = np.nonzero(hi > lo)[0]
-                if len(idx) == 0:
-                    continue
-                mn = np.minimum.reduceat(bl, lo[idx])
-                mx = np.maximum.reduceat(bl, lo[idx])
-                other = (mn != body[idx]) | (mx != body[idx])
-                near[idx[other]] = True
-    vq = np.nonzero(near & dof)[0]
-    eq = np.nonzero(near[sc.edges[:, 0]] & near[sc.edges[:, 1]])[0]
-    vq = rng.choice(vq, size=min(n_queries, len(vq)), replace=False) if len(vq) else vq
-    eq = rng.choice(eq, size=min(n_queries, len(eq)), replace=False) if len(eq) else eq
     t0 = time.perf_counter()
-    pt = [(v, f) for v in sorted(vq) for f in O.pt_query(sc, x, sc.dhat, v)]
-    ee = [(a, b) for a in sorted(eq) for b in O.ee_query(sc, x, sc.dhat, a)]
-    t_query = time.perf_counter() - t0
-    pt = np.array(pt, dtype=np.int32).reshape(-1, 2)
-    ee = np.array(ee, dtype=np.int32).reshape(-1, 2)
+    pt, ee = O.candidates_grid(sc, x, sc.dhat)
+    t_cand = time.perf_counter() - t0
     flags = O.ENERGY | O.GRAD | O.HESS | O.PROJECT | (O.MOLLIFY if sc.name == "config3" else 0)
+    nth = O.threads()
     t0 = time.perf_counter()
-    r = O.barrier_reduce(sc, sc.q, pt, ee, sc.dhat, sc.kappa, flags)
-    t_red = time.perf_counter() - t0
-    log(f"cpu baseline: {len(vq)} PT + {len(eq)} EE queries ({t_query:.1f} s untimed) -> "
-        f"{len(pt)} + {len(ee)} candidates, {r['n_active']} active, barrier+reduce {t_red:.2f} s")
-    return {"value": r["n_active"] / t_red if t_red > 0 else None, "unit": "contact pairs/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"{sc.name}: oracle brute-force candidates of {len(vq)} vertices and {len(eq)} edges "
-                       f"sampled near contact ({len(pt) + len(ee)} candidates, {r['n_active']} active); timed: "
-                       f"or_barrier_reduce energy+grad+projected dense Hessian, 1 thread, {t_red:.2f} s")}
+    r = O.barrier_reduce_bsr(sc, sc.q, pt, ee, sc.dhat, sc.kappa, flags, nthreads=nth)
+    t_all = time.perf_counter() - t0
+    k_pt, k_ee = max(1, int(len(pt) * slice_frac)), max(1, int(len(ee) * slice_frac))
+    t0 = time.perf_counter()
+    r1 = O.barrier_reduce_bsr(sc, sc.q, pt[:k_pt], ee[:k_ee], sc.dhat, sc.kappa, flags, nthreads=1)
+    t_one = time.perf_counter() - t0
+    log(f"cpu baseline: {len(pt)} + {len(ee)} candidates ({t_cand:.1f} s untimed), {r['n_active']} active, "
+        f"barrier+reduce {t_all:.2f} s on {nth} threads; one thread {r1['n_active']} active in {t_one:.2f} s")
+    return {"value": r["n_active"] / t_all if t_all > 0 else None, "unit": "contact pairs/s", "cores": nth,
+            "kind": "oracle", "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "single_thread_value": r1["n_active"] / t_one if t_one > 0 else None,
+            "sample": (f"{sc.name}, whole workload: oracle uniform-grid candidates ({len(pt) + len(ee)}, untimed), "
+                       f"then or_barrier_reduce_bsr (energy, gradient, projected block-sparse Hessian) over all "
+                       f"{r['n_active']} active pairs on {nth} threads, slices merged in order ({t_all:.2f} s); "
+                       f"single_thread_value: the first {slice_frac:g} of each list on one thread "
+                       f"({r1['n_active']} active, {t_one:.2f} s)")}
 
 
 def _timed(fn, reps, sync):
@@ -210,12 +193,15 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
            "timing": "HIP events on the launch stream over eager planned steps that run the PT and EE chains one "
                      "after the other (each kernel alone on the device)"}
     if dom in ("pair_terms", "expand"):
+        # FP64-bound: ~1.5e4 algorithmic flop against ~85 B per pair is far
+        # above the ridge (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B)
         kind = 0 if kdom.endswith("_pt") else 1
-        per = work["terms_flops"][kind] if dom == "pair_terms" else FLOPS_EXPAND * work["active"][kind]
+        per_pair = FLOPS_TERMS if dom == "pair_terms" else FLOPS_EXPAND
+        per = per_pair * work["active"][kind]
         ach = per / avg_s / 1e12
-        ent.update(bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s", frac=ach / PEAK_FP64_TFLOPS,
-                   per_unit=(f"{FLOPS_TERMS}+distance flop per active pair" if dom == "pair_terms"
-                             else f"{FLOPS_EXPAND} flop per active pair"))
+        ent.update(bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                   frac=ach / PEAK_FP64_TFLOPS, per_unit=f"{per_pair} flop per active pair",
+                   hbm_algorithmic_GBs=BYTES_BARRIER_PAIR * work["active"][kind] / avg_s / 1e9)
     else:
         # algorithmic bytes: query = query records + item table + pairs out;
         # narrow = pair ids + 4 gathered vertices + type/index out; ccd
@@ -248,14 +234,182 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
     tb = load_traffic(kdom, workload, tuning)
     if tb is not None:
         ent["traffic"] = tb
+        ent["hbm_measured_GBs"] = tb / avg_s / 1e9
+        ent["hbm_measured_frac"] = tb / avg_s / 1e9 / PEAK_HBM_GBS
     ent["family_ms_per_step"] = {f: round(v, 4) for f, v in fam_ms.items()}
     ent["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1]}
     for k, kind in (("barrier_pt", 0), ("barrier_ee", 1)):
         if prof.get(k, (0, 0))[1]:
             s_ = prof[k][0] / prof[k][1] / 1e3
-            ent[f"{k}_tflops"] = work["terms_flops"][kind] / s_ / 1e12
+            ent[f"{k}_tflops"] = FLOPS_TERMS * work["active"][kind] / s_ / 1e12
+    for k, kind in (("expand_pt", 0), ("expand_ee", 1)):
+        if prof.get(k, (0, 0))[1]:
+            s_ = prof[k][0] / prof[k][1] / 1e3
+            ent[f"{k}_tflops"] = FLOPS_EXPAND * work["active"][kind] / s_ / 1e12
     ent["launches"] = launches
     return ent
+
+
+def _median_us(fn, reps, sync, warm=5):
+    """Median wall time of fn() in microseconds, each call synchronized."""
+    import statistics
+    for _ in range(warm):
+        fn()
+    sync()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        ts.append(1e6 * (time.perf_counter() - t0))
+    return statistics.median(ts)
+
+
+def _replay_ms(bt, steps, warmup, sync):
+    bt.capture()
+    for _ in range(warmup):
+        bt.replay()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bt.replay()
+    sync()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def extra_config1(sc, log):
+    """Config 1 is latency-bound: microseconds per call of each entry point
+    (median of 200 synchronized calls) and per planned step (graph
+    replay)."""
+    import torch
+    import paper_2409_16385_amd as E
+    from paper_2409_16385_amd import batch as BT
+    dev = torch.device("cuda", 0)
+    sync = lambda: torch.cuda.synchronize(dev)  # noqa: E731
+    ctx = E.Context(0)
+    dsc = E.Scene.from_host(ctx, sc)
+    q, dq = torch.as_tensor(sc.q, device=dev), torch.as_tensor(sc.dq, device=dev)
+    v = torch.as_tensor(sc.dq, device=dev)
+    flags = E.ENERGY | E.GRAD | E.HESS | E.PROJECT
+    pt, ee = E.build_candidates(ctx, dsc, q, sc.dhat)
+    r = E.barrier_reduce(ctx, dsc, q, pt, ee, sc.dhat, sc.kappa, flags, hess="bsr")
+    a, n_swept, _ = E.ccd_max_step(ctx, dsc, q, dq, sc.dhat)
+    us = {"build_candidates": _median_us(lambda: E.build_candidates(ctx, dsc, q, sc.dhat), 200, sync),
+          "barrier_reduce": _median_us(lambda: E.barrier_reduce(ctx, dsc, q, pt, ee, sc.dhat, sc.kappa, flags,
+                                                                hess="bsr", count=False), 200, sync),
+          "ccd_max_step": _median_us(lambda: E.ccd_max_step(ctx, dsc, q, dq, sc.dhat), 200, sync),
+          "barrier_hvp": _median_us(lambda: E.barrier_hvp(ctx, dsc, q, pt, ee, sc.dhat, sc.kappa, E.PROJECT, v),
+                                    200, sync)}
+    bt = BT.Batch(ctx, BT.concat([sc]), flags=flags)
+    bt.make_plan(1.5)
+    step_ms = _replay_ms(bt, 200, 10, sync)
+    log(f"config1: per call {us}, planned step {1e3 * step_ms:.1f} us")
+    return {"workload": f"config1 ({sc.name}): n_vert={sc.n_vert} n_node={sc.n_node} dhat={sc.dhat:g}",
+            "active_pairs": int(r["n_active"]), "candidates": int(pt.shape[0] + ee.shape[0]),
+            "ccd_candidates": int(n_swept), "call_us": us, "planned_step_us": 1e3 * step_ms,
+            "timing": "median of 200 synchronized calls; planned step: graph replays"}
+
+
+def extra_single(sc, log, flags_extra=0, steps=20):
+    """A single-scene workload timed like the main one (autotuned planned
+    step, graph replays) plus its per-call barrier + reduction and CCD."""
+    import torch
+    import paper_2409_16385_amd as E
+    from paper_2409_16385_amd import batch as BT
+    dev = torch.device("cuda", 0)
+    sync = lambda: torch.cuda.synchronize(dev)  # noqa: E731
+    ctx = E.Context(0)
+    flags = E.ENERGY | E.GRAD | E.HESS | E.PROJECT | flags_extra
+    bt = BT.Batch(ctx, BT.concat([sc]), flags=flags)
+    tuning = bt.autotune(reps=2)
+    ms = _replay_ms(bt, steps, 3, sync)
+    st = bt.status()
+    if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):
+        raise RuntimeError(f"{sc.name}: status {st}")
+    cnt = bt.counts()
+    dsc = E.Scene.from_host(ctx, sc)
+    q, dq = torch.as_tensor(sc.q, device=dev), torch.as_tensor(sc.dq, device=dev)
+    pt, ee = E.build_candidates(ctx, dsc, q, sc.dhat)
+    t_red = _median_us(lambda: E.barrier_reduce(ctx, dsc, q, pt, ee, sc.dhat, sc.kappa, flags, hess="bsr",
+                                                count=False), 10, sync, warm=2)
+    t_ccd = _median_us(lambda: E.ccd_max_step(ctx, dsc, q, dq, sc.dhat), 10, sync, warm=2)
+    swept = cnt["swept_pt"] + cnt["swept_ee"]
+    log(f"{sc.name}: {ms:.3f} ms/step, {cnt['active']} active, barrier+reduce {t_red:.0f} us, ccd {t_ccd:.0f} us")
+    return {"workload": f"{sc.name}: n_vert={sc.n_vert} n_face={sc.n_face} n_node={sc.n_node} dhat={sc.dhat:g}",
+            "ms_per_step": ms, "pairs_per_s": cnt["active"] / (ms * 1e-3), "active_pairs": cnt["active"],
+            "candidates": cnt["cand_pt"] + cnt["cand_ee"], "ccd_candidates": swept,
+            "barrier_reduce_ms": t_red / 1e3, "barrier_reduce_pairs_per_s": cnt["active"] / (t_red * 1e-6),
+            "ccd_ms": t_ccd / 1e3, "ccd_pairs_per_s": swept / (t_ccd * 1e-6),
+            "tuning": {k: v for k, v in tuning.items() if k != "trace"}}
+
+
+def extra_config4(sc, log):
+    """Differentiable form on config 1: the autograd barrier energy, its
+    backward (the reduced gradient) and double backward (HVP with the true
+    pair Hessians, recomputed), backward / forward time ratio."""
+    import statistics
+    import torch
+    import paper_2409_16385_amd as E
+    dev = torch.device("cuda", 0)
+    sync = lambda: torch.cuda.synchronize(dev)  # noqa: E731
+    ctx = E.Context(0)
+    dsc = E.Scene.from_host(ctx, sc)
+    q0 = torch.as_tensor(sc.q, device=dev)
+    pt, ee = E.build_candidates(ctx, dsc, q0, sc.dhat)
+    state = E.BarrierState(ctx, dsc, pt, ee, sc.dhat, sc.kappa)
+    q = q0.clone().requires_grad_(True)
+    v = torch.as_tensor(sc.dq, device=dev)
+
+    def fwd():
+        return E.barrier_energy(q, state)
+
+    def fwd_bwd():
+        torch.autograd.grad(E.barrier_energy(q, state), q)
+
+    def hvp():
+        (g,) = torch.autograd.grad(E.barrier_energy(q, state), q, create_graph=True)
+        torch.autograd.grad(g, q, grad_outputs=v)
+
+    t_f = _median_us(fwd, 100, sync)
+    t_fb = _median_us(fwd_bwd, 100, sync)
+    t_h = _median_us(hvp, 100, sync)
+    log(f"config4: forward {t_f:.1f} us, forward+backward {t_fb:.1f} us, with HVP {t_h:.1f} us")
+    return {"workload": f"differentiable form on config1 ({pt.shape[0] + ee.shape[0]} candidate pairs)",
+            "forward_us": t_f, "forward_backward_us": t_fb, "backward_over_forward": (t_fb - t_f) / t_f,
+            "energy_grad_hvp_us": t_h, "timing": "median of 100 synchronized calls"}
+
+
+def extra_batch(scenes_list, log, steps=10):
+    """The batched form: one planned step over the ragged batch, graph
+    replays, against the same scenes as sequential single-scene steps."""
+    import numpy as np
+    import torch
+    import paper_2409_16385_amd as E
+    from paper_2409_16385_amd import batch as BT
+    dev = torch.device("cuda", 0)
+    sync = lambda: torch.cuda.synchronize(dev)  # noqa: E731
+    ctx = E.Context(0)
+    hb = BT.concat(scenes_list)
+    bt = BT.Batch(ctx, hb)
+    tuning = bt.autotune(reps=1)
+    ms = _replay_ms(bt, steps, 2, sync)
+    st = bt.status()
+    if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):
+        raise RuntimeError(f"batch: status {st}")
+    cnt = bt.counts()
+    dscs = [E.Scene.from_host(ctx, s) for s in scenes_list]
+    BT.sequential_reference(ctx, scenes_list[:4], dscs[:4])
+    _, t_seq = BT.sequential_reference(ctx, scenes_list, dscs)
+    nv = np.diff(hb.vert_off)
+    log(f"batch: {ms:.2f} ms/step ({hb.n_scene / (ms * 1e-3):.0f} scenes/s), sequential {1e3 * t_seq:.1f} ms")
+    return {"workload": (f"batch of {hb.n_scene} ragged grasp scenes: n_vert={int(hb.vert_off[-1])} "
+                         f"n_face={hb.faces.shape[0]} n_node={hb.n_node}"),
+            "ms_per_step": ms, "scenes_per_s": hb.n_scene / (ms * 1e-3),
+            "pairs_per_s": cnt["active"] / (ms * 1e-3), "active_pairs": cnt["active"],
+            "ccd_candidates": cnt["swept_pt"] + cnt["swept_ee"],
+            "sequential_ms": 1e3 * t_seq, "sequential_scenes_per_s": hb.n_scene / t_seq,
+            "batch_speedup": 1e3 * t_seq / ms, "verts_per_scene_min_max": [int(nv.min()), int(nv.max())],
+            "tuning": {k: v for k, v in tuning.items() if k != "trace"}}
 
 
 RESOLUTION_NODES = (250, 1000, 2000, 8000, 32000)
@@ -334,7 +488,12 @@ def main():
     if a.config == "resolution":
         resolution_sweep(a, log)
         return
-    batch_scenes = make_batch(a.n_scene, a.seed, log) if a.config == "batch" else None
+    extras = a.config == "config2" and not a.no_extras
+    batch_scenes = make_batch(a.n_scene, a.seed, log) if (a.config == "batch" or extras) else None
+    extra_scenes = {}
+    if extras:
+        extra_scenes = {"config1": make_scene("config1", a.seed), "config3": make_scene("config3", a.seed)}
+        extra_batch_scenes, batch_scenes = batch_scenes, None
 
     import numpy as np
     import torch
@@ -397,10 +556,8 @@ def main():
     tpc += np.bincount(tp.cpu().numpy(), minlength=7)
     tec += np.bincount(te.cpu().numpy(), minlength=9)
     assert int(ap.numel() + ae.numel()) == n_active and pt.shape[0] == cnt["cand_pt"] and ee.shape[0] == cnt["cand_ee"]
-    terms_pt = sum(int(tpc[i]) * (FLOPS_TERMS + FLOPS_DIST[PT_FN[i]]) for i in range(7))
-    terms_ee = sum(int(tec[i]) * (FLOPS_TERMS + FLOPS_DIST[EE_FN[i]]) for i in range(9))
     work = {"active": (int(ap.numel()), int(ae.numel())), "cand": (cnt["cand_pt"], cnt["cand_ee"]),
-            "swept": (cnt["swept_pt"], cnt["swept_ee"]), "terms_flops": (terms_pt, terms_ee),
+            "swept": (cnt["swept_pt"], cnt["swept_ee"]),
             "n_query": (hb.W_rowptr.size - 1, hb.edges.shape[0]), "n_item": (hb.faces.shape[0], hb.edges.shape[0]),
             "n_vert": hb.W_rowptr.size - 1}
     log(f"candidates pt={cnt['cand_pt']} ee={cnt['cand_ee']} active pt={work['active'][0]} "
@@ -500,8 +657,20 @@ def main():
     out["roofline"] = roofline
     out["cpu_baseline"] = None
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scenes_list[0] if a.config != "batch" else _largest(scenes_list),
-                                           a.cpu_queries, log)
+        out["cpu_baseline"] = cpu_baseline(scenes_list[0] if a.config != "batch" else _largest(scenes_list), log)
+    if extras:
+        import paper_2409_16385_amd as E
+        jobs = (("config1", lambda: extra_config1(extra_scenes["config1"], log)),
+                ("config3", lambda: extra_single(extra_scenes["config3"], log, E.MOLLIFY)),
+                ("config4", lambda: extra_config4(extra_scenes["config1"], log)),
+                ("batch", lambda: extra_batch(extra_batch_scenes, log)))
+        for key, job in jobs:
+            t0 = time.perf_counter()
+            try:
+                out[key] = job()
+            except Exception as e:  # recorded, never fatal to the main line
+                out[key] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"extra {key}: {time.perf_counter() - t0:.1f} s")
     out["sources"] = source_digest()
     print(json.dumps(out), flush=True)
 
