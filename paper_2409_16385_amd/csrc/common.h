@@ -43,6 +43,7 @@ enum BufId {
   B_SVIDU, B_SVID,                                   // their vertex ids (unsorted, sorted)
   B_SKEY_EE, B_SHIST_EE, B_SFILL_EE, B_SSTART_EE, B_SACT_EE, B_STYP_EE, B_SVIDU_EE, B_SVID_EE,  // the same for EE
   B_CCD_LONG_PT, B_CCD_LONG_EE,                        // CCD pairs deferred to the second pass
+  B_LQTMP,                                             // unsorted candidates of large queries (sorted lists)
   B_BP0,                               // broad-phase scratch: 4 slots (kind, swept) x BP_NBUF
   B_NUM = B_BP0 + 4 * 17
 };

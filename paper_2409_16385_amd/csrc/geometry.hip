@@ -762,7 +762,17 @@ struct QueryArgs {
   const int32_t *vscene;
   const int32_t *qlist;    // when set: the queries to run, *n_qlist of them
   const int64_t *n_qlist;
+  int32_t *defer;          // when set: queries spanning more than LQ_CELLS cells are
+  int64_t *n_defer;        // listed here and skipped (k_query_lq runs them)
 };
+
+// Queries whose boxes span more than this many cells run one wavefront
+// each (k_query_lq) instead of one thread each.
+constexpr int LQ_CELLS = 64;
+
+__device__ __forceinline__ int64_t n_cells(const int *c0, const int *c1) {
+  return (int64_t)(c1[0] - c0[0] + 1) * (c1[1] - c0[1] + 1) * (c1[2] - c0[2] + 1);
+}
 
 // box, vertices, DoF flag and scene of query q (a vertex for PT, an edge
 // record for EE)
@@ -808,6 +818,11 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
   if (live) query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
   int c0[3] = {0, 0, 0}, c1[3] = {-1, -1, -1};
   if (live) cell_range(g, qlo, qhi, c0, c1);
+  if (live && qa_.defer && n_cells(c0, c1) > LQ_CELLS) {
+    // a wavefront counts and writes this query (k_query_lq)
+    if (MODE == 0) qa_.defer[atomicAdd((unsigned long long *)qa_.n_defer, 1ull)] = q;
+    return;
+  }
   const int64_t base = (MODE == 1 && live) ? off[q] : 0;
   int64_t k = 0;
   for (int z = c0[2]; z <= c1[2]; ++z)
@@ -856,6 +871,116 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
           --j;
         }
         seg[2 * (j + 1) + 1] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Queries whose boxes span more than LQ_CELLS cells (listed by the
+// per-query kernels, or too large to bin or hash): one wavefront per query,
+// its cells and the items too large to hash spread over the 64 lanes, so
+// that one huge box does not keep a single thread scanning thousands of
+// cells.  MODE 0 counts each query's candidates into cnt[q]; MODE 1 writes
+// them, unsorted, to tmp at the query's offset (k_seg_rank then puts them
+// in order into out); MODE 2 appends them to out (staged per lane).
+// ---------------------------------------------------------------------------
+template <int KIND, int MODE>
+__global__ __launch_bounds__(QT) void k_query_lq(const int32_t *__restrict__ qlist, const int64_t *__restrict__ n_qlist,
+                                                 const double *__restrict__ xs, const double *__restrict__ x1s,
+                                                 int n_vert, double h, QueryArgs qa_, int32_t *__restrict__ cnt,
+                                                 const int64_t *__restrict__ off, int32_t *__restrict__ tmp,
+                                                 int32_t *__restrict__ out, int64_t cap, unsigned long long *total) {
+  __shared__ int2 s_buf[QT * APPEND_BUF];
+  int2 *buf = s_buf + threadIdx.x * APPEND_BUF;
+  int nbuf = 0;
+  const int lane = threadIdx.x & 63;
+  const ItemRec *items = qa_.items;
+  const GridDev g = *qa_.g;
+  const int n_large = (int)*qa_.n_large;
+  const int64_t nl = *n_qlist;
+  const int64_t nw = ((int64_t)gridDim.x * QT) >> 6;
+  for (int64_t w = ((int64_t)blockIdx.x * QT + threadIdx.x) >> 6; w < nl; w += nw) {
+    const int q = qlist[w];
+    double qlo[3], qhi[3];
+    int qa, qb, qsc;
+    bool qdof;
+    query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
+    int c0[3], c1[3];
+    cell_range(g, qlo, qhi, c0, c1);
+    const int64_t nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1;
+    const int64_t nc = n_cells(c0, c1);
+    // this lane's share: cells lane, lane + 64, ..., then large items alike
+    auto each = [&](auto emit) {
+      for (int64_t ci = lane; ci < nc; ci += 64) {
+        const int x = c0[0] + (int)(ci % nx), y = c0[1] + (int)((ci / nx) % ny), z = c0[2] + (int)(ci / (nx * ny));
+        const uint64_t key = cell_key(x, y, z, qsc);
+        const uint32_t b = cell_hash(x, y, z, qsc) & qa_.bmask;
+        const int64_t e1 = qa_.bstart[b + 1] < qa_.ent_cap ? qa_.bstart[b + 1] : qa_.ent_cap;
+        scan_bucket<KIND>(qa_.ent, items, qa_.bstart[b], e1, key, x, y, z, c0[0], c0[1], c0[2], q, qa, qb, qdof,
+                          qlo, qhi, emit);
+      }
+      for (int j = lane; j < n_large; j += 64) {
+        const int it = qa_.large[j];
+        const ItemRec r = items[it];
+        if ((r.tag >> 1) == qsc && pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r)) emit(it);
+      }
+    };
+    if constexpr (MODE == 2) {
+      each([&](int it) { stage_pair(buf, nbuf, q, it, total, out, cap); });
+      wave_flush(buf, nbuf, total, out, cap);
+    } else {
+      int64_t k = 0;
+      each([&](int) { ++k; });
+      int64_t ex = k;  // inclusive scan over the lanes
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int64_t yv = __shfl_up(ex, o, 64);
+        if (lane >= o) ex += yv;
+      }
+      if constexpr (MODE == 0) {
+        if (lane == 63) cnt[q] = (int32_t)ex;
+      } else {
+        int64_t p = off[q] + ex - k;
+        each([&](int it) {
+          if (p < cap) tmp[p] = it;
+          ++p;
+        });
+      }
+    }
+  }
+}
+
+// Sorts the candidates of each listed query (tmp, unsorted, at off[q]) into
+// out by rank: the items of one query are distinct, so an item's position
+// is the number of smaller items, counted against the query's list staged
+// through LDS in tiles.  One workgroup per query.
+constexpr int RANK_T = 256, RANK_TILE = 2048;
+__global__ __launch_bounds__(RANK_T) void k_seg_rank(const int32_t *__restrict__ qlist,
+                                                     const int64_t *__restrict__ n_qlist,
+                                                     const int32_t *__restrict__ cnt, const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ tmp, int32_t *__restrict__ out,
+                                                     int64_t cap) {
+  __shared__ int32_t tile[RANK_TILE];
+  const int64_t nl = *n_qlist;
+  for (int64_t w = blockIdx.x; w < nl; w += gridDim.x) {
+    const int q = qlist[w];
+    const int64_t o = off[q], L = cnt[q];
+    if (o + L > cap) continue;  // the host checked the total against the capacity
+    for (int64_t c0 = 0; c0 < L; c0 += RANK_T) {
+      const int64_t i = c0 + threadIdx.x;
+      const int32_t v = i < L ? tmp[o + i] : 0x7fffffff;
+      int64_t rank = 0;
+      for (int64_t t0 = 0; t0 < L; t0 += RANK_TILE) {
+        const int tn = (int)(L - t0 < RANK_TILE ? L - t0 : RANK_TILE);
+        __syncthreads();
+        for (int j = threadIdx.x; j < tn; j += RANK_T) tile[j] = tmp[o + t0 + j];
+        __syncthreads();
+        for (int j = 0; j < tn; ++j) rank += tile[j] < v;
+      }
+      if (i < L) {
+        out[2 * (o + rank)] = q;
+        out[2 * (o + rank) + 1] = v;
       }
     }
   }
@@ -1087,16 +1212,21 @@ __global__ __launch_bounds__(QT) void k_query_sm(int nq, const double *__restric
   bool qdof = false;
   double qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
   int c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0};
+  bool deferred = false;
   if (live) {
     query_data<KIND>(q, xs, x1s, n_vert, h, qa_, qlo, qhi, qa, qb, qdof, qsc);
     cell_range(*qa_.g, qlo, qhi, c0, c1);
+    if (qa_.defer && n_cells(c0, c1) > LQ_CELLS) {
+      qa_.defer[atomicAdd((unsigned long long *)qa_.n_defer, 1ull)] = q;  // run by k_query_lq
+      deferred = true;
+    }
   }
   const int nl = (int)*qa_.n_large;
   int x = c0[0], y = c0[1], z = c0[2];
   int64_t e = 0, e1 = 0;
   uint64_t key = 0;
   int lj = 0;
-  int phase = live ? 0 : 3;  // 0 open cell, 1 scan its bucket, 2 large items, 3 done
+  int phase = live && !deferred ? 0 : 3;  // 0 open cell, 1 scan its bucket, 2 large items, 3 done
   auto emit = [&](int it) { buf[nbuf++] = make_int2(q, it); };
   while (__any(phase != 3)) {
     if (phase == 0) {
@@ -1448,7 +1578,11 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
                                         c->status);
   EIPC_HIP(c, hipGetLastError());
   QueryArgs qa{b.g, bmask, b.bstart, b.ent, ent_cap, b.large, b.n_large, b.items, sc->W_rowptr, vsc, nullptr,
-               nullptr};
+               nullptr, nullptr, nullptr};
+  QueryArgs qdef = qa;  // per-query kernels hand queries of many cells to k_query_lq
+  qdef.defer = b.qlarge;
+  qdef.n_defer = b.n_qlarge;
+  const int glq = 2 * c->num_cu;
   const int n_vert = sc->n_vert;
   if (!sort) {
     // single pass, unsorted append; per query, per (query, cell) or as a
@@ -1543,14 +1677,25 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
           }
           EIPC_HIP(c, hipGetLastError());
           if (kind == 0)
-            k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlj, out, capa, b.total);
+            k_query_lq<0, 2><<<glq, QT, 0, s>>>(qlj.qlist, qlj.n_qlist, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                                nullptr, out, capa, b.total);
           else
-            k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlj, out, capa, b.total);
+            k_query_lq<1, 2><<<glq, QT, 0, s>>>(qlj.qlist, qlj.n_qlist, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                                nullptr, out, capa, b.total);
         } else if (!cellpar) {
+          // the deferred list is rebuilt by every attempt
+          EIPC_TRY(launch_zero(c, b.n_qlarge, 8, s));
           if (kind == 0)
-            k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qa, out, capa, b.total);
+            k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qdef, out, capa, b.total);
           else
-            k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qa, out, capa, b.total);
+            k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qdef, out, capa, b.total);
+          EIPC_HIP(c, hipGetLastError());
+          if (kind == 0)
+            k_query_lq<0, 2><<<glq, QT, 0, s>>>(b.qlarge, b.n_qlarge, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                                nullptr, out, capa, b.total);
+          else
+            k_query_lq<1, 2><<<glq, QT, 0, s>>>(b.qlarge, b.n_qlarge, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                                nullptr, out, capa, b.total);
         } else if (c->query_mode[kind] == 2) {
           const int gw = (int)std::min<int64_t>(grid_for(qent_cap * 64, QT), 32 * (int64_t)c->num_cu);
           if (kind == 0)
@@ -1561,9 +1706,11 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
                                               b.total);
           EIPC_HIP(c, hipGetLastError());
           if (kind == 0)
-            k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
+            k_query_lq<0, 2><<<glq, QT, 0, s>>>(qlq.qlist, qlq.n_qlist, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                                nullptr, out, capa, b.total);
           else
-            k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
+            k_query_lq<1, 2><<<glq, QT, 0, s>>>(qlq.qlist, qlq.n_qlist, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                                nullptr, out, capa, b.total);
         } else {
         if (kind == 0)
           k_query_ent<0><<<ge, QT, 0, s>>>(b.qoff + nq, qent_cap, b.qent, xs, x1s, n_vert, h, qa, out, capa,
@@ -1573,9 +1720,11 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
                                            b.total);
         EIPC_HIP(c, hipGetLastError());
         if (kind == 0)
-          k_query_sm<0><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
+          k_query_lq<0, 2><<<glq, QT, 0, s>>>(qlq.qlist, qlq.n_qlist, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                              nullptr, out, capa, b.total);
         else
-          k_query_sm<1><<<grid_for(nq, QT), QT, 0, s>>>(nq, xs, x1s, n_vert, h, qlq, out, capa, b.total);
+          k_query_lq<1, 2><<<glq, QT, 0, s>>>(qlq.qlist, qlq.n_qlist, xs, x1s, n_vert, h, qa, nullptr, nullptr,
+                                              nullptr, out, capa, b.total);
         }
       }
       EIPC_HIP(c, hipGetLastError());
@@ -1602,10 +1751,15 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
   }
   {
     ProfScope ps(c, kind == 0 ? K_QUERY_COUNT_PT : K_QUERY_COUNT_EE, s);
-    if (kind == 0)
-      launch_query<0, 0>(nq, xs, x1s, n_vert, h, qa, b.qcnt, nullptr, nullptr, 0, nullptr, c->status, s);
-    else
-      launch_query<1, 0>(nq, xs, x1s, n_vert, h, qa, b.qcnt, nullptr, nullptr, 0, nullptr, c->status, s);
+    if (kind == 0) {
+      launch_query<0, 0>(nq, xs, x1s, n_vert, h, qdef, b.qcnt, nullptr, nullptr, 0, nullptr, c->status, s);
+      k_query_lq<0, 0><<<glq, QT, 0, s>>>(b.qlarge, b.n_qlarge, xs, x1s, n_vert, h, qa, b.qcnt, nullptr, nullptr,
+                                          nullptr, 0, nullptr);
+    } else {
+      launch_query<1, 0>(nq, xs, x1s, n_vert, h, qdef, b.qcnt, nullptr, nullptr, 0, nullptr, c->status, s);
+      k_query_lq<1, 0><<<glq, QT, 0, s>>>(b.qlarge, b.n_qlarge, xs, x1s, n_vert, h, qa, b.qcnt, nullptr, nullptr,
+                                          nullptr, 0, nullptr);
+    }
   }
   EIPC_HIP(c, hipGetLastError());
   EIPC_TRY(exclusive_scan(c, b.qcnt, nq, b.qoff, s));
@@ -1626,11 +1780,19 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
     if (total == 0) return EIPC_OK;
   }
   {
+    int32_t *tmp;
+    EIPC_TRY(ensure_t(c, B_LQTMP, (size_t)std::max<int64_t>(cap, 1), &tmp));
     ProfScope ps(c, kind == 0 ? K_QUERY_WRITE_PT : K_QUERY_WRITE_EE, s);
-    if (kind == 0)
-      launch_query<0, 1>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qoff, out, cap, nullptr, c->status, s);
-    else
-      launch_query<1, 1>(nq, xs, x1s, n_vert, h, qa, b.qcnt, b.qoff, out, cap, nullptr, c->status, s);
+    if (kind == 0) {
+      launch_query<0, 1>(nq, xs, x1s, n_vert, h, qdef, b.qcnt, b.qoff, out, cap, nullptr, c->status, s);
+      k_query_lq<0, 1><<<glq, QT, 0, s>>>(b.qlarge, b.n_qlarge, xs, x1s, n_vert, h, qa, nullptr, b.qoff, tmp,
+                                          nullptr, cap, nullptr);
+    } else {
+      launch_query<1, 1>(nq, xs, x1s, n_vert, h, qdef, b.qcnt, b.qoff, out, cap, nullptr, c->status, s);
+      k_query_lq<1, 1><<<glq, QT, 0, s>>>(b.qlarge, b.n_qlarge, xs, x1s, n_vert, h, qa, nullptr, b.qoff, tmp,
+                                          nullptr, cap, nullptr);
+    }
+    k_seg_rank<<<glq, RANK_T, 0, s>>>(b.qlarge, b.n_qlarge, b.qcnt, b.qoff, tmp, out, cap);
   }
   EIPC_HIP(c, hipGetLastError());
   if (plan) {

@@ -300,24 +300,31 @@ def _grid_sheet(n: int, lo: float, hi: float, z: float) -> tuple[np.ndarray, np.
     return v, np.array(f, dtype=np.int64)
 
 
-def mixed_scale_scene(seed: int = 0, n: int = 80, size: float = 0.1, dhat: float = 2e-4) -> Scene:
+def mixed_scale_scene(seed: int = 0, n: int = 80, size: float = 0.1, dhat: float = 2e-4,
+                      plates_first: bool = False) -> Scene:
     """A deformable n x n sheet (edge size/n, embedded in a 4x4x2 grid)
     hovering 0.2-0.8 dhat above two static coplanar plates: a 2-triangle
     plate twice the sheet's width (triangles spanning about a hundred broad-
     phase cells per axis) and a 3x3-quad plate under the middle (tens of
-    cells per axis).  dq moves the sheet down by up to about 2 dhat."""
+    cells per axis).  dq moves the sheet down by up to about 2 dhat.
+    ``plates_first`` numbers the plates' vertices (and so their edges)
+    before the sheet's: every plate edge is then the lower index of its
+    edge-edge pairs, so one plate edge queries thousands of sheet edges."""
     rng = rng_for(seed, 0)
     sv, sf = _grid_sheet(n, 0.0, size, 0.5 * dhat)
     sv[:, 2] += rng.uniform(-0.3, 0.3, len(sv)) * dhat
     pv, pf = _grid_sheet(1, -0.5 * size, 1.5 * size, 0.0)
     mv, mf = _grid_sheet(3, 0.2 * size, 0.8 * size, 0.0)
     bodies = [Body(sv, sf, padded_grid(sv, (4, 4, 2))), Body(pv, pf, None), Body(mv, mf, None)]
+    if plates_first:
+        bodies = bodies[1:] + bodies[:1]
     asm = _assemble(bodies)
     q = asm[5].copy()
     dq = np.zeros_like(q).reshape(-1, 3)
     dq[:, 2] = -rng.uniform(0.0, 2.0, len(dq)) * dhat
     dq[:, :2] = rng.normal(0.0, 0.2 * dhat, (len(dq), 2))
-    return _make(f"mixed{seed}", bodies, q, dq.reshape(-1), dhat, 1e3, seed, assembled=asm,
+    return _make(f"mixed{seed}" + ("_pf" if plates_first else ""), bodies, q, dq.reshape(-1), dhat, 1e3, seed,
+                 assembled=asm,
                  meta={"sheet_n": n, "size": size})
 
 

@@ -3,7 +3,10 @@ that the broad-phase hash holds one-thread, one-wavefront and unhashed
 primitives): sorted candidates bit-exact against the oracle at several cell
 sizes; the step bound and swept-candidate count of every broad-phase work
 split equal the oracle's; the planned step (every split) reproduces the
-oracle's counts, energy and step bound."""
+oracle's counts, energy and step bound.  With the plates numbered first, a
+plate edge is the lower index of some 19,000 edge-edge candidates: queries
+spanning many cells run one wavefront each, and that query's sorted list is
+put in order by rank through LDS tiles."""
 import numpy as np
 import pytest
 
@@ -20,9 +23,9 @@ SPLITS = [0, 5, 10, 15]
 FLAGS = E.ENERGY | E.GRAD | E.HESS | E.PROJECT
 
 
-@pytest.fixture(scope="module")
-def sc():
-    return mixed_scale_scene()
+@pytest.fixture(scope="module", params=[False, True], ids=["sheet_first", "plates_first"])
+def sc(request):
+    return mixed_scale_scene(plates_first=request.param)
 
 
 @pytest.fixture(scope="module")
@@ -32,8 +35,8 @@ def ref(sc):
     spt, see = O.candidates(sc, x, sc.dhat, x1=O.embed(sc, sc.q + sc.dq))
     alpha, _, _ = O.ccd_max_step(sc, sc.q, sc.dq, sc.dhat)
     r = O.barrier_reduce(sc, sc.q, pt, ee, sc.dhat, sc.kappa, O.ENERGY)
-    return {"pt": pt, "ee": ee, "n_swept": len(spt) + len(see), "alpha": alpha, "energy": r["energy"],
-            "n_active": r["n_active"]}
+    return {"pt": pt, "ee": ee, "spt": spt, "see": see, "n_swept": len(spt) + len(see), "alpha": alpha,
+            "energy": r["energy"], "n_active": r["n_active"]}
 
 
 @pytest.fixture(scope="module")
@@ -83,3 +86,16 @@ def test_planned_step_every_split(ctx, sc, ref, mode, cs):
     assert cnt["active"] == ref["n_active"]
     assert b.out.energy[0].item() == pytest.approx(ref["energy"], rel=1e-10)
     assert b.out.alpha[0].item() == ref["alpha"]
+    for which, key in ((0, "spt"), (1, "see")):
+        got = E.step_pairs(b.ctx, which).cpu().numpy().astype(np.int64)
+        got = got[np.lexsort((got[:, 1], got[:, 0]))]
+        assert np.array_equal(got, ref[key]), which
+
+
+@pytest.mark.parametrize("mode", SPLITS)
+def test_swept_candidates_sorted_every_split(ctx, sc, ref, mode):
+    E.set_tuning(ctx, 2.0, (0, 0, 0, 0), mode)
+    dsc = E.Scene.from_host(ctx, sc)
+    spt, see = E.ccd_candidates(ctx, dsc, _dev(sc.q), _dev(sc.dq), sc.dhat)
+    E.set_tuning(ctx, 2.0, (0, 0, 0, 0), 1)
+    assert np.array_equal(spt.cpu().numpy(), ref["spt"]) and np.array_equal(see.cpu().numpy(), ref["see"])
