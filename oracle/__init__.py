@@ -63,6 +63,11 @@ def lib():
             "or_ccd_toi": (C.c_int, [_P, _P, _P, C.c_int, _P, _I64, _D, _D, _I64, _P, _P]),
             "or_ccd_max_step": (C.c_int, [_P, _P, _P, _P, _D, _D, _D, _I64, _P, _P, _P]),
             "or_narrow": (None, [_P, _P, C.c_int, _P, _I64, _D, _P, _P, _P]),
+            "or_friction_f": (None, [_D, _D, _P, _P, _P]),
+            "or_friction_lag": (C.c_int, [C.c_int, _P, _P, _D, _D, _P]),
+            "or_friction_pair": (None, [_P, _P, _D, _D, _P, _P, _P]),
+            "or_friction_lag_list": (C.c_int, [_P, _P, C.c_int, _P, _I64, _D, _D, C.c_uint32, _P]),
+            "or_friction_reduce": (C.c_int, [_P, _P, _P, _I64, _P, _P, _I64, _P, _D, _D, _P, _P, _P]),
             "or_grid_build": (_P, [_P, _P, _P, _D, _D]),
             "or_grid_pairs": (_I64, [_P, C.c_int, _I32, _I32, _P, _I64]),
             "or_grid_cell": (_D, [_P]),
@@ -423,3 +428,62 @@ def narrow(sc, x, kind, pairs, dhat, nthreads=None):
                     _ptr(act[a:]))
     _pmap(run, _slices(n, 8 * (nthreads or threads())), nthreads or threads())
     return ty, s2, act.astype(bool)
+
+
+# ---------------------------------------------------------------------------
+# Lagged friction (lag record: lambda, beta[4], normal[3], G x^n[3])
+# ---------------------------------------------------------------------------
+LAG = 11
+
+
+def friction_f(y, epsvh):
+    """(f0, f1, f1') at y."""
+    out = np.zeros(3)
+    lib().or_friction_f(float(y), float(epsvh), _ptr(out[0:]), _ptr(out[1:]), _ptr(out[2:]))
+    return out[0], out[1], out[2]
+
+
+def friction_lag(kind, x12, dhat, kappa, rest12=None):
+    x12 = _f64(x12).reshape(12)
+    r12 = None if rest12 is None else _f64(rest12).reshape(12)
+    lag = np.zeros(LAG)
+    st = lib().or_friction_lag(kind, _ptr(x12), _ptr(r12), dhat, kappa, _ptr(lag))
+    return st, lag
+
+
+def friction_pair(x12, lag, mu, epsvh):
+    """(energy, g[12], H[12, 12]) of one lagged pair."""
+    x12 = _f64(x12).reshape(12)
+    lag = _f64(lag).reshape(LAG)
+    e = np.zeros(1)
+    g = np.zeros(12)
+    H = np.zeros((12, 12))
+    lib().or_friction_pair(_ptr(x12), _ptr(lag), mu, epsvh, _ptr(e), _ptr(g), _ptr(H))
+    return e[0], g, H
+
+
+def friction_lag_list(sc, q_n, kind, pairs, dhat, kappa, flags=0):
+    s = scene(sc)
+    q_n = _f64(q_n)
+    pairs = _i32(pairs).reshape(-1, 2)
+    lag = np.zeros((len(pairs), LAG))
+    st = lib().or_friction_lag_list(s.ref, _ptr(q_n), kind, _ptr(pairs), len(pairs), dhat, kappa, int(flags),
+                                    _ptr(lag))
+    return st, lag
+
+
+def friction_reduce(sc, q, pt, lag_pt, ee, lag_ee, mu, epsvh, hess=True):
+    """dict(energy, grad, hess (dense or None)) of the lagged friction."""
+    s = scene(sc)
+    q = _f64(q)
+    pt = _i32(pt).reshape(-1, 2)
+    ee = _i32(ee).reshape(-1, 2)
+    lag_pt = _f64(lag_pt).reshape(-1, LAG)
+    lag_ee = _f64(lag_ee).reshape(-1, LAG)
+    nd = 3 * s.n_node
+    e = np.zeros(1)
+    g = np.zeros(nd)
+    H = np.zeros((nd, nd)) if hess else None
+    lib().or_friction_reduce(s.ref, _ptr(q), _ptr(pt), len(pt), _ptr(lag_pt), _ptr(ee), len(ee), _ptr(lag_ee),
+                             mu, epsvh, _ptr(e), _ptr(g), _ptr(H))
+    return {"energy": e[0], "grad": g, "hess": H}

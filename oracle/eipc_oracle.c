@@ -1276,3 +1276,259 @@ void or_narrow(const or_scene *sc, const double *x, int kind, const int32_t *pai
     if (active) active[k] = (uint8_t)(s > 0.0 && s < dhat * dhat);
   }
 }
+
+/* ------------------------------------------------------------------ */
+/* Lagged friction (Sec. III-B): D_k(x, x^n) = mu lambda_k^n f0(|u_k|),  */
+/*   f1(y) = -y^2/(eps_v h)^2 + 2y/(eps_v h) on (0, eps_v h), 1 above;   */
+/*   f0(x) = integral of f1 from eps_v h to x, plus eps_v h.            */
+/* Readings (the paper defers to IPC):                                  */
+/*  - lambda_k^n = kappa |b'(d^n)| (times m(c^n) for a mollified EE     */
+/*    pair), the magnitude of the barrier's normal force at x^n;        */
+/*  - the closest points at x^n define signed weights beta over the     */
+/*    pair's four vertices (point minus closest triangle point for PT,  */
+/*    closest point of edge a minus that of edge b for EE), so the      */
+/*    relative position is G x = sum_a beta_a x_a, and the contact      */
+/*    normal is n = G x^n / |G x^n|;                                    */
+/*  - u_k is the part of G (x - x^n) orthogonal to n (its length is     */
+/*    the same in any orthonormal tangent frame).                      */
+/* Lag record (11 doubles): lambda, beta[4], n[3], G x^n[3].            */
+/* ------------------------------------------------------------------ */
+void or_friction_f(double y, double epsvh, double *f0, double *f1, double *f1p) {
+  if (y < epsvh) {
+    double r = y / epsvh;
+    *f0 = -(y * y * y) / (3.0 * epsvh * epsvh) + (y * y) / epsvh + epsvh / 3.0;
+    *f1 = -(r * r) + 2.0 * r;
+    *f1p = -2.0 * y / (epsvh * epsvh) + 2.0 / epsvh;
+  } else {
+    *f0 = y;
+    *f1 = 1.0;
+    *f1p = 0.0;
+  }
+}
+
+/* closest-point weights of a classified pair: G x = sum_a beta_a x_a */
+static void closest_weights(int kind, int type, const double *x12, double *beta) {
+  const double *p0 = x12, *p1 = x12 + 3, *p2 = x12 + 6, *p3 = x12 + 9;
+  for (int a = 0; a < 4; ++a) beta[a] = 0.0;
+  if (kind == 0) {
+    double w[3] = {0.0, 0.0, 0.0};
+    if (type <= PT_T2) {
+      w[type] = 1.0;
+    } else if (type <= PT_E2) {
+      int i = type - PT_E0, j = (i + 1) % 3; /* edges t0t1, t1t2, t2t0 */
+      const double *ti = x12 + 3 * (1 + i), *tj = x12 + 3 * (1 + j);
+      double e[3], r[3];
+      sub3(tj, ti, e);
+      sub3(p0, ti, r);
+      double s = dot3(r, e) / dot3(e, e);
+      w[i] = 1.0 - s;
+      w[j] = s;
+    } else {
+      double e0[3], e1[3], r[3];
+      sub3(p2, p1, e0);
+      sub3(p3, p1, e1);
+      sub3(p0, p1, r);
+      double a = dot3(e0, e0), b = dot3(e0, e1), c = dot3(e1, e1);
+      double d0 = dot3(e0, r), d1 = dot3(e1, r);
+      double det = a * c - b * b;
+      double u = (c * d0 - b * d1) / det, v = (a * d1 - b * d0) / det;
+      w[0] = 1.0 - u - v;
+      w[1] = u;
+      w[2] = v;
+    }
+    beta[0] = 1.0;
+    beta[1] = -w[0];
+    beta[2] = -w[1];
+    beta[3] = -w[2];
+  } else {
+    double s = 0.0, t = 0.0; /* closest points a0 + s (a1 - a0), b0 + t (b1 - b0) */
+    double u[3], v[3];
+    sub3(p1, p0, u);
+    sub3(p3, p2, v);
+    switch (type) {
+      case EE_A0B0: s = 0.0; t = 0.0; break;
+      case EE_A0B1: s = 0.0; t = 1.0; break;
+      case EE_A1B0: s = 1.0; t = 0.0; break;
+      case EE_A1B1: s = 1.0; t = 1.0; break;
+      case EE_AB0: { double r[3]; sub3(p2, p0, r); s = dot3(r, u) / dot3(u, u); t = 0.0; break; }
+      case EE_AB1: { double r[3]; sub3(p3, p0, r); s = dot3(r, u) / dot3(u, u); t = 1.0; break; }
+      case EE_A0B: { double r[3]; sub3(p0, p2, r); t = dot3(r, v) / dot3(v, v); s = 0.0; break; }
+      case EE_A1B: { double r[3]; sub3(p1, p2, r); t = dot3(r, v) / dot3(v, v); s = 1.0; break; }
+      default: {
+        double w[3];
+        sub3(p0, p2, w);
+        double a = dot3(u, u), b = dot3(u, v), c = dot3(v, v), d = dot3(u, w), e = dot3(v, w);
+        double D = a * c - b * b;
+        s = (b * e - c * d) / D;
+        t = (a * e - b * d) / D;
+      }
+    }
+    beta[0] = 1.0 - s;
+    beta[1] = s;
+    beta[2] = -(1.0 - t);
+    beta[3] = -t;
+  }
+}
+
+/* Lag record of one pair at x^n (see above); returns OR_OK, OR_INACTIVE
+ * (lambda = 0: the pair adds no friction) or an error. */
+int or_friction_lag(int kind, const double *x12, const double *rest12, double dhat, double kappa, double *lag) {
+  for (int i = 0; i < 11; ++i) lag[i] = 0.0;
+  int type = kind == 0 ? or_pt_type(x12, x12 + 3, x12 + 6, x12 + 9) : or_ee_type(x12, x12 + 3, x12 + 6, x12 + 9);
+  double s = or_pair_dist2(kind, type, x12);
+  if (!isfinite(s)) return OR_ERR_NONFINITE;
+  if (!(s < dhat * dhat)) return OR_INACTIVE;
+  if (s <= 0.0) return OR_ERR_INTERSECTING;
+  double d = sqrt(s), b, b1, b2;
+  or_barrier(d, dhat, &b, &b1, &b2);
+  double m = 1.0;
+  if (kind == 1 && rest12) {
+    double ur[3], vr[3], u[3], v[3], n[3], m1, m2;
+    sub3(rest12 + 3, rest12, ur);
+    sub3(rest12 + 9, rest12 + 6, vr);
+    sub3(x12 + 3, x12, u);
+    sub3(x12 + 9, x12 + 6, v);
+    cross3(u, v, n);
+    or_mollifier(dot3(n, n), 1e-3 * dot3(ur, ur) * dot3(vr, vr), &m, &m1, &m2);
+  }
+  double beta[4], gx[3] = {0.0, 0.0, 0.0};
+  closest_weights(kind, type, x12, beta);
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) gx[c] += beta[a] * x12[3 * a + c];
+  double gn = sqrt(dot3(gx, gx));
+  lag[0] = kappa * m * fabs(b1);
+  for (int a = 0; a < 4; ++a) lag[1 + a] = beta[a];
+  for (int c = 0; c < 3; ++c) {
+    lag[5 + c] = gx[c] / gn;
+    lag[8 + c] = gx[c];
+  }
+  return OR_OK;
+}
+
+/* Friction energy of one lagged pair at x, its 12-gradient and 12x12
+ * Hessian (exact; positive semidefinite by construction, no projection):
+ *   w = G x - G x^n, u = P w with P = I - n n^T, y = |u|,
+ *   D = mu lambda f0(y), grad_a = beta_a mu lambda f1(y)/y u,
+ *   H_ab = beta_a beta_b mu lambda P [f1(y)/y I + (f1'(y) y - f1(y))/y^3 u u^T] P
+ * (at y = 0 the bracket tends to 2/(eps_v h) I). */
+void or_friction_pair(const double *x12, const double *lag, double mu, double epsvh, double *e, double *g12,
+                      double *H144) {
+  double lam = lag[0];
+  const double *beta = lag + 1, *n = lag + 5, *c0 = lag + 8;
+  double w[3] = {0.0, 0.0, 0.0}, P[9], u[3];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) w[c] += beta[a] * x12[3 * a + c];
+  for (int c = 0; c < 3; ++c) w[c] = w[c] - c0[c];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P[3 * i + j] = (i == j ? 1.0 : 0.0) - n[i] * n[j];
+  for (int i = 0; i < 3; ++i) u[i] = P[3 * i] * w[0] + P[3 * i + 1] * w[1] + P[3 * i + 2] * w[2];
+  double y = sqrt(dot3(u, u)), f0, f1, f1p;
+  or_friction_f(y, epsvh, &f0, &f1, &f1p);
+  double s1 = y > 0.0 ? f1 / y : 2.0 / epsvh;           /* f1(y)/y */
+  double s2 = y > 0.0 ? (f1p * y - f1) / (y * y * y) : 0.0; /* (f1' y - f1)/y^3 */
+  if (y > 0.0 && y < epsvh) s2 = -1.0 / (epsvh * epsvh * y); /* the same, without cancellation */
+  double ml = mu * lam;
+  if (e) *e = ml * f0;
+  if (g12)
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 3; ++c) g12[3 * a + c] = beta[a] * (ml * s1 * u[c]);
+  if (H144) {
+    double M[9], K[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M[3 * i + j] = s1 * (i == j ? 1.0 : 0.0) + s2 * u[i] * u[j];
+    /* K = P M P */
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) acc += P[3 * i + k] * M[3 * k + l] * P[3 * l + j];
+        K[3 * i + j] = ml * acc;
+      }
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) H144[(3 * a + i) * 12 + 3 * b + j] = beta[a] * beta[b] * K[3 * i + j];
+  }
+}
+
+/* Lag records of pair lists at positions W q_n + x_off (inactive pairs get
+ * lambda = 0). */
+int or_friction_lag_list(const or_scene *sc, const double *q_n, int kind, const int32_t *pairs, int64_t n,
+                         double dhat, double kappa, uint32_t flags, double *lag) {
+  double *x = (double *)malloc(sizeof(double) * 3 * (size_t)sc->n_vert + 8);
+  or_embed(sc, q_n, sc->x_off, x);
+  int moll = (flags & OR_MOLLIFY) && sc->x_rest, status = OR_OK;
+  for (int64_t k = 0; k < n; ++k) {
+    int32_t vid[4];
+    pair_vertices(sc, kind, pairs + 2 * k, vid);
+    double x12[12], r12[12];
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 3; ++c) {
+        x12[3 * a + c] = x[3 * vid[a] + c];
+        if (moll) r12[3 * a + c] = sc->x_rest[3 * vid[a] + c];
+      }
+    int st = or_friction_lag(kind, x12, moll ? r12 : NULL, dhat, kappa, lag + 11 * k);
+    if (st != OR_OK && st != OR_INACTIVE) status = st;
+  }
+  free(x);
+  return status;
+}
+
+/* Friction energy, reduced gradient and dense reduced Hessian (Eq. 17)
+ * over lagged pair lists at positions W q + x_off, summed in list order
+ * with Neumaier compensation. */
+int or_friction_reduce(const or_scene *sc, const double *q, const int32_t *pt, int64_t n_pt, const double *lag_pt,
+                       const int32_t *ee, int64_t n_ee, const double *lag_ee, double mu, double epsvh,
+                       double *energy, double *grad_q, double *hess_q) {
+  int64_t nd = 3 * (int64_t)sc->n_node;
+  double *x = (double *)malloc(sizeof(double) * 3 * (size_t)sc->n_vert + 8);
+  or_embed(sc, q, sc->x_off, x);
+  double es = 0.0, ec = 0.0;
+  double *gc = grad_q ? (double *)calloc((size_t)nd + 1, sizeof(double)) : NULL;
+  double *hc = hess_q ? (double *)calloc((size_t)(nd * nd) + 1, sizeof(double)) : NULL;
+  if (grad_q) memset(grad_q, 0, sizeof(double) * nd);
+  if (hess_q) memset(hess_q, 0, sizeof(double) * nd * nd);
+  for (int kind = 0; kind < 2; ++kind) {
+    const int32_t *list = kind == 0 ? pt : ee;
+    const double *lags = kind == 0 ? lag_pt : lag_ee;
+    int64_t n = kind == 0 ? n_pt : n_ee;
+    for (int64_t k = 0; k < n; ++k) {
+      const double *lag = lags + 11 * k;
+      if (lag[0] == 0.0) continue;
+      int32_t vid[4];
+      pair_vertices(sc, kind, list + 2 * k, vid);
+      double x12[12], e, g[12], H[144];
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 3; ++c) x12[3 * a + c] = x[3 * vid[a] + c];
+      or_friction_pair(x12, lag, mu, epsvh, &e, g, H);
+      nsum(&es, &ec, e);
+      for (int a = 0; a < 4; ++a)
+        for (int32_t ka = sc->rowptr[vid[a]]; ka < sc->rowptr[vid[a] + 1]; ++ka) {
+          int32_t I = sc->col[ka];
+          double wa = sc->val[ka];
+          if (grad_q)
+            for (int i = 0; i < 3; ++i) nsum(&grad_q[3 * I + i], &gc[3 * I + i], wa * g[3 * a + i]);
+          if (!hess_q) continue;
+          for (int b = 0; b < 4; ++b)
+            for (int32_t kb = sc->rowptr[vid[b]]; kb < sc->rowptr[vid[b] + 1]; ++kb) {
+              int32_t J = sc->col[kb];
+              double wab = wa * sc->val[kb];
+              for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                  int64_t idx = (3 * (int64_t)I + i) * nd + 3 * J + j;
+                  nsum(&hess_q[idx], &hc[idx], wab * H[(3 * a + i) * 12 + 3 * b + j]);
+                }
+            }
+        }
+    }
+  }
+  if (grad_q)
+    for (int64_t i = 0; i < nd; ++i) grad_q[i] += gc[i];
+  if (hess_q)
+    for (int64_t i = 0; i < nd * nd; ++i) hess_q[i] += hc[i];
+  if (energy) *energy = es + ec;
+  free(gc);
+  free(hc);
+  free(x);
+  return OR_OK;
+}

@@ -91,4 +91,15 @@ or_bsr *or_barrier_reduce_bsr(const or_scene *sc, const double *q, const int32_t
 int64_t or_bsr_nnzb(const or_bsr *B);
 void or_bsr_copy(const or_bsr *B, int32_t *rowptr, int32_t *col, double *blocks);
 void or_bsr_free(or_bsr *B);
+
+/* lagged friction (Sec. III-B); lag record: lambda, beta[4], n[3], G x^n[3] */
+void or_friction_f(double y, double epsvh, double *f0, double *f1, double *f1p);
+int or_friction_lag(int kind, const double *x12, const double *rest12, double dhat, double kappa, double *lag);
+void or_friction_pair(const double *x12, const double *lag, double mu, double epsvh, double *e, double *g12,
+                      double *H144);
+int or_friction_lag_list(const or_scene *sc, const double *q_n, int kind, const int32_t *pairs, int64_t n,
+                         double dhat, double kappa, uint32_t flags, double *lag);
+int or_friction_reduce(const or_scene *sc, const double *q, const int32_t *pt, int64_t n_pt, const double *lag_pt,
+                       const int32_t *ee, int64_t n_ee, const double *lag_ee, double mu, double epsvh,
+                       double *energy, double *grad_q, double *hess_q);
 #endif
