@@ -200,6 +200,48 @@ eipc_status eipc_barrier_hvp(eipc_ctx *ctx, const eipc_scene *sc, const double *
                              uint32_t flags, const double *v, const double *v_off, double *out, double *out_off,
                              eipc_stream stream);
 
+/* ---- lagged friction (Sec. III-B) ---- */
+
+/* Doubles per lag record: lambda, beta[4], normal[3], G x^n[3]. */
+#define EIPC_FRICTION_LAG 11
+
+/* Lag records of the friction potential D_k = mu lambda_k^n f0(|u_k|)
+ * (Sec. III-B) at the previous time step's positions x^n = W q_n + x_off,
+ * one per given pair (typically the active pairs at x^n), written to
+ * lag_pt / lag_ee (device double[n][EIPC_FRICTION_LAG]):
+ *   lambda   kappa |b'(d^n)|, the magnitude of the barrier's normal force
+ *            (times the mollifier m(c^n) for EE pairs with EIPC_MOLLIFY);
+ *            0 for a pair that is not active at x^n (it adds no friction);
+ *   beta[4]  signed closest-point weights over the pair's vertices (point
+ *            minus closest triangle point for PT; closest point on edge a
+ *            minus closest point on edge b for EE), G x = sum_a beta_a x_a;
+ *   normal   G x^n / |G x^n|, the contact normal at x^n;
+ *   G x^n    the relative position at x^n.
+ * Single scenes only (n_scene <= 1).  Asynchronous; a pair at zero
+ * distance raises EIPC_ERR_INTERSECTING in the status word. */
+eipc_status eipc_friction_lag(eipc_ctx *ctx, const eipc_scene *sc, const double *q_n, const int32_t *pt,
+                              int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
+                              uint32_t flags, double *lag_pt, double *lag_ee, eipc_stream stream);
+
+/* Lagged friction at x = W q + x_off over the pairs and lag records of
+ * eipc_friction_lag (Sec. III-B, reduced through the embedding as Eq. 17):
+ * u_k = P (G x - G x^n) with P = I - n n^T the tangential part of the
+ * relative displacement, D = sum_k mu lambda_k f0(|u_k|) with
+ *   f1(y) = 2 y/eps_h - y^2/eps_h^2 for y < eps_h, 1 otherwise,
+ *   f0(y) = integral of f1 from eps_h to y, plus eps_h,
+ * eps_h = eps_v h (the velocity threshold times the time step).  Pass
+ * mu h^2 for the h^2-scaled term of E_IPC.  The pair Hessians are positive
+ * semidefinite by construction (no projection).  Flags: EIPC_ENERGY,
+ * EIPC_GRAD, EIPC_HESS.
+ *   energy     device double[1] or NULL     grad_q  device double[3*n_node] or NULL
+ *   hess_dense device double[(3*n_node)^2] or NULL (row-major)
+ *   hess_bsr   host struct or NULL: context-owned BSR view (synchronizes)
+ * Single scenes only. */
+eipc_status eipc_friction_reduce(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
+                                 int64_t n_pt, const double *lag_pt, const int32_t *ee, int64_t n_ee,
+                                 const double *lag_ee, double mu, double eps_h, uint32_t flags, double *energy,
+                                 double *grad_q, double *hess_dense, eipc_bsr *hess_bsr, eipc_stream stream);
+
 /* ---- planned contact step: one Newton iteration's contact stage with no
  * host synchronization and no allocation (capturable in a HIP graph) ---- */
 

@@ -12,5 +12,6 @@ from .binding import (  # noqa: F401
     embed, build_candidates, barrier_reduce, ccd_max_step, barrier_hvp,
     narrow_phase, pair_eval, ccd_candidates, ccd_toi, fp64_selftest, bsr_to_dense,
     cholesky, cholesky_solve, Plan, StepOut, set_tuning, plan_step, contact_step, step_pairs,
+    friction_lag, friction_reduce,
 )
 from .autograd import BarrierState, barrier_energy, barrier_grad  # noqa: F401

@@ -92,6 +92,8 @@ def _load():
         "eipc_contact_step": (_I32, [_P, _P, _P, _P, _P, _P, _D, _D, _U32, _D, _D, _I64, _P, _P, _P, _P, _P, _P]),
         "eipc_set_tuning": (_I32, [_P, _D, _P, _I32]),
         "eipc_step_pairs": (_I32, [_P, _I32, _P, _I64, _P, _P]),
+        "eipc_friction_lag": (_I32, [_P, _P, _P, _P, _I64, _P, _I64, _D, _D, _U32, _P, _P, _P]),
+        "eipc_friction_reduce": (_I32, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _D, _D, _U32, _P, _P, _P, _P, _P]),
         "eipc_barrier_hvp_noalloc": (_I32, [_P, _P, _P, _P, _I64, _P, _I64, _D, _D, _U32, _P, _P, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
@@ -530,3 +532,46 @@ def step_pairs(ctx: Context, which: int):
     out = torch.empty((max(n.value, 1), 2), dtype=torch.int32, device=ctx.torch_device)
     ctx.check(L.eipc_step_pairs(ctx.handle, int(which), _ptr(out), n.value, C.byref(n), ctx.stream()))
     return out[:n.value]
+
+
+FRICTION_LAG = 11
+
+
+def friction_lag(ctx: Context, sc: Scene, q_n, pt, ee, dhat: float, kappa: float, flags: int = 0):
+    """Lag records (device [n, 11] tensors for the PT and EE pairs) of the
+    friction potential at the previous step's q_n (asynchronous)."""
+    dev = ctx.torch_device
+    q_n = _f64(q_n, dev)
+    pt = _i32(pt, dev).reshape(-1, 2)
+    ee = _i32(ee, dev).reshape(-1, 2)
+    lpt = torch.empty((pt.shape[0], FRICTION_LAG), dtype=torch.float64, device=dev)
+    lee = torch.empty((ee.shape[0], FRICTION_LAG), dtype=torch.float64, device=dev)
+    ctx.check(_load().eipc_friction_lag(ctx.handle, sc.ref, _ptr(q_n), _ptr(pt), pt.shape[0], _ptr(ee), ee.shape[0],
+                                        float(dhat), float(kappa), int(flags), _ptr(lpt), _ptr(lee), ctx.stream()))
+    return lpt, lee
+
+
+def friction_reduce(ctx: Context, sc: Scene, q, pt, lag_pt, ee, lag_ee, mu: float, eps_h: float,
+                    flags: int = ENERGY | GRAD | HESS, hess: str | None = "bsr"):
+    """Lagged friction energy, reduced gradient and reduced Hessian ('bsr',
+    'dense' or None) at q; returns dict(energy, grad, hess)."""
+    dev = ctx.torch_device
+    q = _f64(q, dev)
+    pt = _i32(pt, dev).reshape(-1, 2)
+    ee = _i32(ee, dev).reshape(-1, 2)
+    energy = torch.empty(1, dtype=torch.float64, device=dev) if flags & ENERGY else None
+    grad = torch.empty(3 * sc.n_node, dtype=torch.float64, device=dev) if flags & GRAD else None
+    dense = None
+    bsr = None
+    if flags & HESS and hess == "dense":
+        dense = torch.empty((3 * sc.n_node, 3 * sc.n_node), dtype=torch.float64, device=dev)
+    elif flags & HESS and hess == "bsr":
+        bsr = _Bsr()
+    st = _load().eipc_friction_reduce(ctx.handle, sc.ref, _ptr(q), _ptr(pt), pt.shape[0], _ptr(lag_pt), _ptr(ee),
+                                      ee.shape[0], _ptr(lag_ee), float(mu), float(eps_h), int(flags), _ptr(energy),
+                                      _ptr(grad), _ptr(dense), None if bsr is None else C.byref(bsr), ctx.stream())
+    ctx.check(st)
+    H = dense
+    if bsr is not None:
+        H = _copy_bsr(ctx, bsr)
+    return {"energy": energy, "grad": grad, "hess": H}

@@ -569,6 +569,85 @@ eipc_status eipc_barrier_hvp_noalloc(eipc_ctx *c, const eipc_scene *sc, const do
   return EIPC_OK;
 }
 
+eipc_status eipc_friction_lag(eipc_ctx *c, const eipc_scene *sc, const double *q_n, const int32_t *pt, int64_t n_pt,
+                              const int32_t *ee, int64_t n_ee, double dhat, double kappa, uint32_t flags,
+                              double *lag_pt, double *lag_ee, eipc_stream stream) {
+  CallScope call(c);
+  EIPC_TRY(check_scene(c, sc));
+  EIPC_TRY(check_dhat(c, dhat));
+  if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && (!pt || !lag_pt)) || (n_ee > 0 && (!ee || !lag_ee)) ||
+      (!q_n && sc->n_node > 0) || !(kappa >= 0.0) || !std::isfinite(kappa))
+    return set_err(c, EIPC_ERR_ARG, "bad friction-lag arguments");
+  if (sc->n_scene > 1) return set_err(c, EIPC_ERR_ARG, "friction takes one scene");
+  EIPC_TRY(check_mollify(c, sc, flags));
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)PSTRIDE * sc->n_vert + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q_n, sc->x_off, xs, nullptr, s));
+  EIPC_TRY(launch_friction_lag(c, sc, 0, xs, pt, n_pt, dhat, kappa, flags, lag_pt, s));
+  EIPC_TRY(launch_friction_lag(c, sc, 1, xs, ee, n_ee, dhat, kappa, flags, lag_ee, s));
+  return EIPC_OK;
+}
+
+eipc_status eipc_friction_reduce(eipc_ctx *c, const eipc_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
+                                 const double *lag_pt, const int32_t *ee, int64_t n_ee, const double *lag_ee,
+                                 double mu, double eps_h, uint32_t flags, double *energy, double *grad_q,
+                                 double *hess_dense, eipc_bsr *hess_bsr, eipc_stream stream) {
+  CallScope call(c);
+  EIPC_TRY(check_scene(c, sc));
+  if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && (!pt || !lag_pt)) || (n_ee > 0 && (!ee || !lag_ee)) ||
+      (!q && sc->n_node > 0) || !(mu >= 0.0) || !std::isfinite(mu) || !(eps_h > 0.0) || !std::isfinite(eps_h))
+    return set_err(c, EIPC_ERR_ARG, "bad friction arguments");
+  if (sc->n_scene > 1) return set_err(c, EIPC_ERR_ARG, "friction takes one scene");
+  const bool want_h = (flags & EIPC_HESS) && (hess_dense || hess_bsr);
+  if (want_h && 3 * (int64_t)sc->n_node >= (int64_t)INT32_MAX)
+    return set_err(c, EIPC_ERR_ARG, "reduced Hessian output needs 3 * n_node < 2^31");
+  if (hess_dense && hess_bsr) return set_err(c, EIPC_ERR_ARG, "ask for one Hessian layout");
+  hipStream_t s = (hipStream_t)stream;
+  EIPC_HIP(c, hipSetDevice(c->device));
+  double *xs;
+  EIPC_TRY(ensure_t(c, B_X, (size_t)PSTRIDE * sc->n_vert + 1, &xs));
+  EIPC_TRY(launch_embed(c, sc, q, sc->x_off, xs, nullptr, s));
+  const int64_t n3 = 3 * (int64_t)sc->n_node;
+  double *e = (flags & EIPC_ENERGY) ? energy : nullptr;
+  double *g = (flags & EIPC_GRAD) ? grad_q : nullptr;
+  for (int attempt = 0;; ++attempt) {
+    if (e) EIPC_TRY(launch_zero(c, e, sizeof(double), s));
+    if (g) EIPC_TRY(launch_zero(c, g, sizeof(double) * n3, s));
+    HessOut h{0, nullptr, nullptr, nullptr, 0};
+    if (want_h && hess_dense) {
+      EIPC_TRY(launch_zero(c, hess_dense, sizeof(double) * n3 * n3, s));
+      h.kind = 1;
+      h.dense = hess_dense;
+    } else if (want_h) {
+      int64_t cap = std::max<int64_t>(c->hash_cap, pow2_at_least(16 * (int64_t)sc->n_node));
+      c->hash_cap = cap;
+      EIPC_TRY(hess_table(c, cap, h, s));
+    }
+    EIPC_TRY(launch_friction(c, sc, 0, xs, pt, n_pt, lag_pt, mu, eps_h, e, g, h, s));
+    EIPC_TRY(launch_friction(c, sc, 1, xs, ee, n_ee, lag_ee, mu, eps_h, e, g, h, s));
+    if (h.kind == 1) EIPC_TRY(launch_dense_mirror(c, sc->n_node, hess_dense, s));
+    if (h.kind == 2) {
+      uint32_t st = 0;
+      EIPC_HIP(c, hipMemcpyAsync(&st, c->status, 4, hipMemcpyDeviceToHost, s));
+      EIPC_HIP(c, hipStreamSynchronize(s));
+      if ((st & ST_HASH_OVERFLOW) && attempt < 8) {
+        st &= ~ST_HASH_OVERFLOW;
+        EIPC_HIP(c, hipMemcpyAsync(c->status, &st, 4, hipMemcpyHostToDevice, s));
+        c->hash_cap *= 4;
+        continue;
+      }
+      if (st & ST_HASH_OVERFLOW) return set_err(c, EIPC_ERR_CAPACITY, "reduced Hessian hash overflow");
+      EIPC_TRY(bsr_compact(c, sc->n_node, h, hess_bsr, s));
+      eipc_status st2 = read_status(c, s);
+      if (st2 != EIPC_OK && st2 != EIPC_WARN_CCD_CAPPED) return st2;
+    }
+    break;
+  }
+  return EIPC_OK;
+}
+
 eipc_status eipc_narrow_phase(eipc_ctx *c, const eipc_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
                               const int32_t *ee, int64_t n_ee, double dhat, int32_t *act_pt, int32_t *type_pt,
                               int64_t *n_act_pt, int32_t *act_ee, int32_t *type_ee, int64_t *n_act_ee,

@@ -676,17 +676,22 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
     EIPC_HIP(c, hipGetLastError());
   }
   if (!want_g && !want_h) return EIPC_OK;
-  {
-    int blocks = (int)std::min<int64_t>(grid_for(max_count, EX_T / 16), (int64_t)c->wg_per_cu[1] * c->num_cu);
-    ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
-    if (kind == 0)
-      k_expand16<0><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
-                                             cap, grad, h, c->status);
-    else
-      k_expand16<1><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
-                                             cap, grad, h, c->status);
-    EIPC_HIP(c, hipGetLastError());
-  }
+  return launch_expand(c, sc, kind, vid4, d_count, cap, gq, Xq, want_g ? grad : nullptr, want_h ? h : HessOut{},
+                       s);
+}
+
+eipc_status launch_expand(eipc_ctx *c, const eipc_scene *sc, int kind, const int4 *vid4, const int64_t *d_count,
+                          int64_t cap, const double *gq, const double *Xq, double *grad, const HessOut &h,
+                          hipStream_t s) {
+  int blocks = (int)std::min<int64_t>(grid_for(cap, EX_T / 16), (int64_t)c->wg_per_cu[1] * c->num_cu);
+  ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
+  if (kind == 0)
+    k_expand16<0><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
+                                           cap, grad, h, c->status);
+  else
+    k_expand16<1><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
+                                           cap, grad, h, c->status);
+  EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }
 

@@ -262,6 +262,12 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
                            double dhat, double kappa, uint32_t flags, double *energy, double *grad,
                            const HessOut &h, hipStream_t s);
 eipc_status launch_dense_mirror(eipc_ctx *c, int n_node, double *dense, hipStream_t s);
+// Reduction through W of per-pair gradients and Hessians in the Q basis
+// (SoA [9][cap] and [45][cap]) of min(*d_count, cap) pairs with vertex ids
+// vid4; grad or h.kind == 0 skip a part.
+eipc_status launch_expand(eipc_ctx *c, const eipc_scene *sc, int kind, const int4 *vid4, const int64_t *d_count,
+                          int64_t cap, const double *gq, const double *Xq, double *grad, const HessOut &h,
+                          hipStream_t s);
 // BSR view of the hashed blocks.  nnzb_cap < 0: sized on the host
 // (synchronizes); else fixed capacity, the count only on the device
 // (rowptr[n_node]) and out->nnzb = -1.
@@ -274,6 +280,15 @@ eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double
 eipc_status launch_pair_eval(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                              int64_t n, double dhat, double kappa, uint32_t flags, int32_t *type, double *sq,
                              double *e, double *g, double *H, hipStream_t s);
+
+// ---- friction.hip ----
+// Lag records (EIPC_FRICTION_LAG doubles per pair) at positions xs, and the
+// friction energy / reduced gradient / reduced Hessian at xs from them.
+eipc_status launch_friction_lag(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                                int64_t n, double dhat, double kappa, uint32_t flags, double *lag, hipStream_t s);
+eipc_status launch_friction(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
+                            int64_t n, const double *lag, double mu, double epsvh, double *energy, double *grad,
+                            const HessOut &h, hipStream_t s);
 
 // ---- ccd.hip ----
 // Per-pair bound; min into d_alpha_bits[scene] when given.  n pairs at

@@ -1,0 +1,128 @@
+"""Lagged friction (Sec. III-B) on the GPU against the oracle: lag records
+(lagged normal force, closest-point weights, contact normal, relative
+position; activity decided bit for bit) and the friction energy, reduced
+gradient and reduced Hessian at a later position, in the static and the
+sliding regime, within 1e-10 (relative, global norms)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+import paper_2409_16385_amd as E  # noqa: E402
+from scenes import config1, config2, tiny_scene  # noqa: E402
+
+TOL = 1e-10
+TINY = [(s, m) for s in range(4) for m in ("grid", "static", "full", "full_both", "tet")]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return E.Context(0)
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+
+
+def _rel(a, b):
+    n = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (n if n > 0 else 1.0)
+
+
+def _check_lags(got, ref):
+    got = got.cpu().numpy()
+    act = ref[:, 0] > 0
+    assert np.array_equal(got[:, 0] > 0, act)
+    if act.any():
+        assert _rel(got[act, 0], ref[act, 0]) <= TOL
+        assert _rel(got[act, 1:], ref[act, 1:]) <= TOL
+    assert not got[~act].any()
+
+
+def _case(ctx, sc, moll=False):
+    dsc = E.Scene.from_host(ctx, sc)
+    xn = O.embed(sc, sc.q)
+    pt, ee = O.candidates_grid(sc, xn, sc.dhat)
+    fl = O.MOLLIFY if moll else 0
+    st1, rpt = O.friction_lag_list(sc, sc.q, 0, pt, sc.dhat, sc.kappa, fl)
+    st2, ree = O.friction_lag_list(sc, sc.q, 1, ee, sc.dhat, sc.kappa, fl)
+    assert st1 == O.OK and st2 == O.OK
+    lpt, lee = E.friction_lag(ctx, dsc, _dev(sc.q), _dev(pt), _dev(ee), sc.dhat, sc.kappa,
+                              E.MOLLIFY if moll else 0)
+    return dsc, pt, ee, rpt, ree, lpt, lee
+
+
+@pytest.mark.parametrize("seed,mode", TINY)
+def test_friction_tiny_against_oracle(ctx, seed, mode):
+    sc = tiny_scene(seed, mode=mode)
+    dsc, pt, ee, rpt, ree, lpt, lee = _case(ctx, sc)
+    _check_lags(lpt, rpt)
+    _check_lags(lee, ree)
+    if (rpt[:, 0] > 0).sum() + (ree[:, 0] > 0).sum() == 0:
+        pytest.skip("no active pair")
+    epsvh = 0.05 * sc.dhat
+    rng = np.random.default_rng(seed)
+    for scale in (0.3, 5.0):  # static and sliding
+        q = sc.q + rng.normal(size=sc.q.shape) * scale * epsvh
+        ref = O.friction_reduce(sc, q, pt, rpt, ee, ree, 0.8, epsvh)
+        r = E.friction_reduce(ctx, dsc, _dev(q), _dev(pt), lpt, _dev(ee), lee, 0.8, epsvh, hess="dense")
+        assert abs(r["energy"].item() - ref["energy"]) <= TOL * abs(ref["energy"])
+        assert _rel(r["grad"].cpu().numpy(), ref["grad"]) <= TOL
+        H = r["hess"].cpu().numpy()
+        assert _rel(H, ref["hess"]) <= TOL
+        rb = E.friction_reduce(ctx, dsc, _dev(q), _dev(pt), lpt, _dev(ee), lee, 0.8, epsvh, hess="bsr")
+        assert _rel(E.bsr_to_dense(*rb["hess"], sc.n_node), ref["hess"]) <= TOL
+
+
+def test_friction_config1_against_oracle(ctx):
+    sc = config1()
+    dsc, pt, ee, rpt, ree, lpt, lee = _case(ctx, sc)
+    _check_lags(lpt, rpt)
+    _check_lags(lee, ree)
+    assert (rpt[:, 0] > 0).sum() > 100
+    epsvh = 1e-3 * 0.01  # eps_v = 1e-3 m/s, h = 0.01 s
+    rng = np.random.default_rng(5)
+    for scale in (0.3, 5.0):
+        q = sc.q + rng.normal(size=sc.q.shape) * scale * epsvh
+        ref = O.friction_reduce(sc, q, pt, rpt, ee, ree, 1.0, epsvh)
+        r = E.friction_reduce(ctx, dsc, _dev(q), _dev(pt), lpt, _dev(ee), lee, 1.0, epsvh, hess="bsr")
+        assert abs(r["energy"].item() - ref["energy"]) <= TOL * abs(ref["energy"])
+        assert _rel(r["grad"].cpu().numpy(), ref["grad"]) <= TOL
+        H = E.bsr_to_dense(*r["hess"], sc.n_node)
+        assert _rel(H, ref["hess"]) <= TOL
+        assert np.linalg.eigvalsh(H).min() >= -1e-10 * np.linalg.norm(H)  # PSD by construction
+
+
+def test_friction_config2_energy_and_gradient(ctx):
+    """Full size (520,384 lagged active pairs), sliding and static mixed."""
+    sc = config2()
+    dsc = E.Scene.from_host(ctx, sc)
+    xn = O.embed(sc, sc.q)
+    pt, ee = O.candidates_grid(sc, xn, sc.dhat)
+    apt = pt[O.narrow(sc, xn, 0, pt, sc.dhat)[2]]
+    aee = ee[O.narrow(sc, xn, 1, ee, sc.dhat)[2]]
+    _, rpt = O.friction_lag_list(sc, sc.q, 0, apt, sc.dhat, sc.kappa)
+    _, ree = O.friction_lag_list(sc, sc.q, 1, aee, sc.dhat, sc.kappa)
+    lpt, lee = E.friction_lag(ctx, dsc, _dev(sc.q), _dev(apt), _dev(aee), sc.dhat, sc.kappa)
+    _check_lags(lpt, rpt)
+    _check_lags(lee, ree)
+    epsvh = 1e-5
+    q = sc.q + np.random.default_rng(9).normal(size=sc.q.shape) * epsvh
+    ref = O.friction_reduce(sc, q, apt, rpt, aee, ree, 1.0, epsvh, hess=False)
+    r = E.friction_reduce(ctx, dsc, _dev(q), _dev(apt), lpt, _dev(aee), lee, 1.0, epsvh, flags=E.ENERGY | E.GRAD,
+                          hess=None)
+    assert abs(r["energy"].item() - ref["energy"]) <= TOL * abs(ref["energy"])
+    assert _rel(r["grad"].cpu().numpy(), ref["grad"]) <= TOL
+
+
+def test_friction_lag_config3_mollified(ctx):
+    """Near-parallel edges: the lagged normal force carries the mollifier."""
+    from scenes import config3
+    sc = config3()
+    dsc, pt, ee, rpt, ree, lpt, lee = _case(ctx, sc, moll=True)
+    _check_lags(lpt, rpt)
+    _check_lags(lee, ree)
+    assert (ree[:, 0] > 0).sum() > 1000
