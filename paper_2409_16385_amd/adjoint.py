@@ -104,33 +104,23 @@ class StepProblem:
         return torch.as_tensor(T, device=self.ctx.torch_device)
 
 
-def build_config1_step(ctx: B.Context, grid_dims=(5, 5, 5), seed: int = 0, n_samples: int = 20000,
-                       h: float = 0.01, E: float = 5e4, nu: float = 0.45, rho: float = 1e3, g: float = 9.81,
-                       target_sigma: float = 1e-3) -> tuple[StepProblem, torch.Tensor]:
-    """The step problem on the sphere-on-ground scene (body = the sphere,
-    kinematic body = the ground).  Returns the problem and a seeded target
-    for the loss L = 1/2 |q* - q_target|^2."""
-    from scenes import config1
-    from scenes.meshes import geodesic_sphere, padded_grid
-    sc = config1(seed, grid_dims=grid_dims)
+def build_step(ctx: B.Context, si) -> tuple[StepProblem, torch.Tensor]:
+    """The step problem of the given inputs (scenes.step_inputs): reduced
+    mass M = sum_s rho V_s (w_s w_s^T) (x) I3 over the interior samples,
+    linear elasticity on each coarse tet with the aggregated volume V_T of
+    its samples (Eq. 15), gravity f = J^T f_ext (Eq. 16).  Returns the
+    problem and the loss target."""
+    sc = si.scene
     dev = ctx.torch_device
-    v_unit, _ = geodesic_sphere(16)
-    r = 0.05
-    grid = padded_grid(r * v_unit, grid_dims)
-    n_node = grid.n_node
-    rng = np.random.Generator(np.random.PCG64([seed, 11]))
-    # uniform interior samples of the rest body (a ball of radius r)
-    u = rng.normal(size=(n_samples, 3))
-    u /= np.linalg.norm(u, axis=1, keepdims=True)
-    pts = u * (r * rng.uniform(size=(n_samples, 1)) ** (1.0 / 3.0))
-    vol = 4.0 / 3.0 * math.pi * r ** 3
-    Vs = vol / n_samples
-    tet_nodes, w = grid.embed(pts)
-    # reduced mass M = sum_s rho V_s (w_s w_s^T) (x) I3
+    nodes, tets = si.grid_nodes, si.tets
+    n_node = len(nodes)
+    tet_nodes = tets[si.sample_tet]
+    w = si.sample_w
+    Vs = si.sample_vol
     Mn = np.zeros((n_node, n_node))
     for a in range(4):
         for b in range(4):
-            np.add.at(Mn, (tet_nodes[:, a], tet_nodes[:, b]), rho * Vs * w[:, a] * w[:, b])
+            np.add.at(Mn, (tet_nodes[:, a], tet_nodes[:, b]), si.rho * Vs * w[:, a] * w[:, b])
     # nodes no interior sample reaches carry no mass and no stiffness; give
     # them a small lumped mass so the step's Newton matrix stays definite
     d = np.diag(Mn).copy()
@@ -138,31 +128,33 @@ def build_config1_step(ctx: B.Context, grid_dims=(5, 5, 5), seed: int = 0, n_sam
     if empty.any():
         Mn[empty, empty] = 1e-3 * d[~empty].mean()
     M = np.kron(Mn, np.eye(3))
-    # aggregated tet volumes (Eq. 15) and linear elasticity
-    # tet index of each sample: the grid's embed picked it; recover it by matching
-    tet_of = {tuple(t): i for i, t in enumerate(grid.tets.tolist())}
-    tid = np.array([tet_of[tuple(t)] for t in tet_nodes.tolist()])
-    VT = np.bincount(tid, minlength=len(grid.tets)) * Vs
-    lam = E * nu / ((1 + nu) * (1 - 2 * nu))
-    mu = E / (2 * (1 + nu))
+    VT = np.bincount(si.sample_tet, minlength=len(tets)) * Vs
+    lam = si.young * si.poisson / ((1 + si.poisson) * (1 - 2 * si.poisson))
+    mu = si.young / (2 * (1 + si.poisson))
     Kd = np.zeros((3 * n_node, 3 * n_node))
     for t in np.nonzero(VT)[0]:
-        nodes = grid.tets[t]
-        Ke = _tet_stiffness(grid.nodes[nodes], VT[t], lam, mu)
-        idx = np.concatenate([[3 * i, 3 * i + 1, 3 * i + 2] for i in nodes])
+        tn = tets[t]
+        Ke = _tet_stiffness(nodes[tn], VT[t], lam, mu)
+        idx = np.concatenate([[3 * i, 3 * i + 1, 3 * i + 2] for i in tn])
         Kd[np.ix_(idx, idx)] += Ke
-    # gravity, reduced: f = J^T f_ext
     fn = np.zeros((n_node, 3))
     for a in range(4):
-        np.add.at(fn[:, 2], tet_nodes[:, a], -rho * Vs * g * w[:, a])
+        np.add.at(fn[:, 2], tet_nodes[:, a], -si.rho * Vs * si.g * w[:, a])
     scene = B.Scene.from_host(ctx, sc)
-    kin = np.nonzero(np.diff(sc.W_rowptr) == 0)[0]
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    prob = StepProblem(ctx=ctx, scene=scene, host=sc, M=T(M), K=T(Kd), q_rest=T(grid.nodes.reshape(-1)),
-                       f=T(fn.reshape(-1)), q_n=T(sc.q), v_n=T(np.zeros_like(sc.q)), h=h, kappa=sc.kappa,
-                       dhat=sc.dhat, kin_rows=kin, kin_rest=sc.x_off[kin].copy(), theta=np.zeros(6))
-    q_target = prob.q_n + T(np.random.Generator(np.random.PCG64([seed, 12])).normal(0, target_sigma, sc.q.shape))
-    return prob, q_target
+    prob = StepProblem(ctx=ctx, scene=scene, host=sc, M=T(M), K=T(Kd), q_rest=T(nodes.reshape(-1)),
+                       f=T(fn.reshape(-1)), q_n=T(si.q_n), v_n=T(si.v_n), h=si.h, kappa=sc.kappa,
+                       dhat=sc.dhat, kin_rows=si.kin_rows, kin_rest=si.kin_rest.copy(), theta=np.zeros(6))
+    return prob, T(si.q_target)
+
+
+def build_config1_step(ctx: B.Context, grid_dims=(5, 5, 5), seed: int = 0, n_samples: int = 20000,
+                       **kw) -> tuple[StepProblem, torch.Tensor]:
+    """The step problem on the sphere-on-ground scene (body = the sphere,
+    kinematic body = the ground) and the seeded target of the loss
+    L = 1/2 |q* - q_target|^2."""
+    from scenes.scene import step_inputs
+    return build_step(ctx, step_inputs(seed, grid_dims=grid_dims, n_samples=n_samples, **kw))
 
 
 def _contact(prob: StepProblem, q, flags, hess):

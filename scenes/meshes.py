@@ -258,14 +258,15 @@ class CoarseGrid:
         c = np.floor((x - self.lo) / self.h).astype(np.int64)
         return np.clip(c, 0, np.array(self.dims) - 2)
 
-    def embed(self, x: np.ndarray, node_pos: np.ndarray | None = None):
+    def embed(self, x: np.ndarray, node_pos: np.ndarray | None = None, with_tet: bool = False):
         """Barycentric weights of points x in the grid's tets.
 
         Reading of the 'unique containing tetrahedron' rule: the point is
         assigned to the cell that contains it (floor of the grid coordinate,
         clamped), and within that cell to the first of its 6 Kuhn tets (in
         the fixed order above) whose smallest barycentric coordinate is
-        >= -1e-12.  Returns (tet_nodes int32[n,4], weights f64[n,4])."""
+        >= -1e-12.  Returns (tet_nodes int32[n,4], weights f64[n,4]) and,
+        with with_tet, the tet indices int64[n] too."""
         if node_pos is None:
             node_pos = self.nodes
         nx, ny, nz = self.dims
@@ -287,6 +288,8 @@ class CoarseGrid:
             best_w[ok] = w[ok]
         if (best_tet < 0).any():
             raise ValueError("some points lie outside the embedding grid")
+        if with_tet:
+            return self.tets[best_tet].astype(np.int32), best_w, best_tet
         return self.tets[best_tet].astype(np.int32), best_w
 
 

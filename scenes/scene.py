@@ -612,3 +612,58 @@ def batch_scenes(n: int = 256, seed0: int = 0) -> list[Scene]:
         out.append(grasp_scene(seed0 + i, nu, nodes, 16, frac=frac, rotate=True,
                                name=f"batch{seed0 + i}"))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Inputs of one implicit step on config 1 (the differentiable form)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class StepInputs:
+    """Inputs of one implicit time step of the sphere-on-ground scene: the
+    contact scene, the coarse grid (rest nodes, tets), seeded interior
+    samples of the body with their tet and barycentric weights (each sample
+    carries volume V / n_samples: the aggregation of Eq. 15), material and
+    time-step parameters, the previous state and a seeded target for the
+    loss 1/2 |q* - q_target|^2.  The ground is the kinematic body (empty W
+    rows); its rest positions define the pose theta = 0."""
+    scene: Scene
+    grid_nodes: np.ndarray   # [n_node, 3] rest positions of the coarse nodes
+    tets: np.ndarray         # [n_tet, 4] node indices
+    sample_tet: np.ndarray   # [n_s] tet of each interior sample
+    sample_w: np.ndarray     # [n_s, 4] barycentric weights in that tet
+    sample_vol: float        # volume carried by one sample
+    young: float
+    poisson: float
+    rho: float
+    g: float
+    h: float
+    q_n: np.ndarray
+    v_n: np.ndarray
+    kin_rows: np.ndarray     # vertex indices of the kinematic body
+    kin_rest: np.ndarray     # [k, 3]
+    q_target: np.ndarray
+
+
+def step_inputs(seed: int = 0, grid_dims=(5, 5, 5), n_samples: int = 20000, h: float = 0.01,
+                young: float = 5e4, poisson: float = 0.45, rho: float = 1e3, g: float = 9.81,
+                target_sigma: float = 1e-3) -> StepInputs:
+    """Config 1's sphere (r = 0.05 m) in a grid of grid_dims nodes over the
+    ground, E = 5e4 Pa, nu = 0.45, rho = 1e3 kg/m^3 (the paper's teddy
+    material, Sec. IV-A), h = 0.01 s, gravity along -z, at rest (v_n = 0)."""
+    sc = config1(seed, grid_dims=grid_dims)
+    v_unit, _ = geodesic_sphere(16)
+    r = 0.05
+    grid = padded_grid(r * v_unit, grid_dims)
+    rng = np.random.Generator(np.random.PCG64([seed, 11]))
+    u = rng.normal(size=(n_samples, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    pts = u * (r * rng.uniform(size=(n_samples, 1)) ** (1.0 / 3.0))
+    _, w, tet = grid.embed(pts, with_tet=True)
+    vol = 4.0 / 3.0 * math.pi * r ** 3
+    kin = np.nonzero(np.diff(sc.W_rowptr) == 0)[0]
+    q_target = sc.q + np.random.Generator(np.random.PCG64([seed, 12])).normal(0, target_sigma, sc.q.shape)
+    return StepInputs(scene=sc, grid_nodes=grid.nodes.copy(), tets=grid.tets.copy(), sample_tet=tet, sample_w=w,
+                      sample_vol=vol / n_samples, young=young, poisson=poisson, rho=rho, g=g, h=h,
+                      q_n=sc.q.copy(), v_n=np.zeros_like(sc.q), kin_rows=kin, kin_rest=sc.x_off[kin].copy(),
+                      q_target=q_target)

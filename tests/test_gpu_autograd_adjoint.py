@@ -171,9 +171,29 @@ def test_adjoint_against_central_differences(step):
         assert fd == pytest.approx(dth[k], rel=2e-4, abs=1e-9)
 
 
+def test_step_and_adjoint_match_the_oracle(step):
+    """The oracle's own step (numpy Newton around the contact oracle, its
+    own mass, stiffness and gravity assembly, CPU Cholesky) and adjoint at
+    375 reduced DoF: the converged q, dL/dq_n, dL/dv_n and dL/dtheta."""
+    from oracle import step as OS
+    from scenes.scene import step_inputs
+    prob, target, q_star, info = step
+    st = OS.Step(step_inputs())
+    q_ref, _ = st.solve()
+    q = q_star.cpu().numpy()
+    assert np.linalg.norm(q - q_ref) <= 1e-9 * np.linalg.norm(q_ref - st.q_n)
+    dq_n, dv_n, dth, used_true = A.adjoint(prob, q_star, q_star - target)
+    r_qn, r_vn, r_th, res = st.adjoint(q_ref, q_ref - st.si.q_target)
+    assert used_true and res <= 1e-12
+    assert np.linalg.norm(dq_n.cpu().numpy() - r_qn) <= 1e-6 * np.linalg.norm(r_qn)
+    assert np.linalg.norm(dv_n.cpu().numpy() - r_vn) <= 1e-6 * np.linalg.norm(r_vn)
+    assert np.linalg.norm(dth - r_th) <= 1e-6 * np.linalg.norm(r_th)
+
+
 def test_large_reduced_system_step_and_adjoint(ctx):
     """About 7.6k reduced DoF (14x14x13 grid): one converged step and its
-    adjoint through the dense Cholesky."""
+    adjoint through the library's dense Cholesky, whose solve has a
+    residual |H lambda - dL/dq| / |dL/dq| <= 1e-12."""
     prob, target = A.build_config1_step(ctx, grid_dims=(14, 14, 13), n_samples=60000)
     assert prob.n == 3 * 14 * 14 * 13
     t0 = time.perf_counter()
@@ -185,3 +205,13 @@ def test_large_reduced_system_step_and_adjoint(ctx):
     t2 = time.perf_counter()
     print(f"\n{prob.n} DoF: step {info['iters']} Newton iterations in {t1 - t0:.2f} s, adjoint {t2 - t1:.3f} s")
     assert np.isfinite(dq_n.cpu().numpy()).all() and np.isfinite(dth).all()
+    # residual of the adjoint solve: lambda = M^-1 dL/dq_n (dL/dq_n = M lambda)
+    g, H, _ = A.gradient_hessian(prob, q_star, project=not used_true)
+    b = q_star - target
+    L = H.clone()
+    assert E.cholesky(ctx, L) == 0
+    lam = b.clone()
+    E.cholesky_solve(ctx, L, lam)
+    res = float(torch.linalg.vector_norm(H @ lam - b) / torch.linalg.vector_norm(b))
+    assert res <= 1e-12, res
+    assert torch.allclose(prob.M @ lam, dq_n, rtol=1e-12, atol=1e-12 * float(dq_n.abs().max()))

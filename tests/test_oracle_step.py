@@ -1,0 +1,107 @@
+"""Pins for the oracle of one implicit step and its adjoint (Sec. III-A
+Eq. 5-6, III-B Eq. 10-12, III-C): the assembled mass, stiffness and
+gravity against their definitions (total mass, partition of unity, rigid
+null space of the elastic energy, the energy of a constant strain), the
+converged step, and the adjoint gradients against central differences of
+the loss with the step solved again."""
+import numpy as np
+import pytest
+
+from oracle import step as OS
+from scenes.scene import step_inputs
+
+
+@pytest.fixture(scope="module")
+def st():
+    return OS.Step(step_inputs())
+
+
+def test_mass_and_gravity(st):
+    si = st.si
+    n = len(si.grid_nodes)
+    Mn = st.M[0::3, 0::3]
+    assert np.allclose(st.M, st.M.T, rtol=0, atol=1e-18)
+    assert np.linalg.eigvalsh(st.M).min() > 0
+    vol = si.sample_vol * len(si.sample_tet)
+    reached = np.zeros(n, dtype=bool)
+    reached[np.unique(si.tets[si.sample_tet])] = True
+    # partition of unity: the sampled mass sums to rho V (lumped masses of
+    # unreached nodes aside)
+    assert Mn[np.ix_(reached, reached)].sum() == pytest.approx(si.rho * vol, rel=1e-12)
+    assert st.f.reshape(-1, 3)[:, 2].sum() == pytest.approx(-si.rho * vol * si.g, rel=1e-12)
+    assert not st.f.reshape(-1, 3)[:, :2].any()
+
+
+def test_stiffness_null_space_and_constant_strain(st):
+    si = st.si
+    X = si.grid_nodes
+    K = st.K
+    assert np.allclose(K, K.T, rtol=0, atol=1e-9 * np.abs(K).max())
+    scale = np.abs(K).max()
+    for k in range(3):
+        t = np.zeros_like(X)
+        t[:, k] = 1.0
+        assert np.abs(K @ t.reshape(-1)).max() <= 1e-10 * scale
+        e = np.zeros(3)
+        e[k] = 1.0
+        assert np.abs(K @ np.cross(e, X).reshape(-1)).max() <= 1e-10 * scale * np.abs(X).max()
+    # a constant strain eps = sym(A): energy V_sampled (mu eps:eps + lam/2 tr(eps)^2)
+    rng = np.random.default_rng(2)
+    A = rng.normal(size=(3, 3)) * 1e-3
+    u = X @ A.T
+    eps = 0.5 * (A + A.T)
+    lam = si.young * si.poisson / ((1 + si.poisson) * (1 - 2 * si.poisson))
+    mu = si.young / (2 * (1 + si.poisson))
+    vol = si.sample_vol * len(si.sample_tet)
+    psi = mu * np.sum(eps * eps) + 0.5 * lam * np.trace(eps) ** 2
+    assert 0.5 * u.reshape(-1) @ (K @ u.reshape(-1)) == pytest.approx(vol * psi, rel=1e-10)
+
+
+@pytest.fixture(scope="module")
+def solved(st):
+    q, it = st.solve()
+    return q, it
+
+
+def test_step_converges(st, solved):
+    q, it = solved
+    assert it < 60
+    g, H, _ = st.grad_hess(q, project=False)
+    qt = st.q_n + st.h * st.v_n
+    assert np.linalg.norm(g) <= 1e-9 * np.linalg.norm(st.M @ qt)
+    assert np.linalg.eigvalsh(H).min() > 0  # a strict minimum
+
+
+def test_adjoint_against_central_differences(st, solved):
+    """Perturb q_n and the ground's pose, solve the step again each time."""
+    q, _ = solved
+    target = st.si.q_target
+    dq_n, dv_n, dth, res = st.adjoint(q, q - target)
+    assert res <= 1e-12
+    assert np.array_equal(dv_n, st.h * dq_n)
+
+    def loss():
+        qs, _ = st.solve()
+        return 0.5 * np.sum((qs - target) ** 2)
+
+    rng = np.random.default_rng(4)
+    q_n0 = st.q_n.copy()
+    eps = 1e-6
+    d = rng.normal(size=q_n0.shape)
+    d /= np.abs(d).max()
+    st.q_n = q_n0 + eps * d
+    lp = loss()
+    st.q_n = q_n0 - eps * d
+    lm = loss()
+    st.q_n = q_n0
+    assert (lp - lm) / (2 * eps) == pytest.approx(dq_n @ d, rel=2e-4, abs=1e-9)
+    for k in (2, 3):
+        th = np.zeros(6)
+        th[k] = eps
+        st.set_pose(th)
+        lp = loss()
+        th[k] = -eps
+        st.set_pose(th)
+        lm = loss()
+        st.set_pose(np.zeros(6))
+        assert (lp - lm) / (2 * eps) == pytest.approx(dth[k], rel=2e-4, abs=1e-9)
