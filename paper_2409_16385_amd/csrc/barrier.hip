@@ -303,7 +303,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_pair_terms(
       V3 Y[3];
       y_basis<KIND>(x, Y);
       double gE[9], HE[45];
-      e_pair = energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, want_h);
+      e_pair = energy_derivs<KIND>(ty, x, Y, s2, dhat, kappa, eps, gE, HE, want_h);
       if (want_g) {
 #pragma unroll
         for (int al = 0; al < 3; ++al)
@@ -914,7 +914,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
       V3 Y[3];
       y_basis<KIND>(x, Y);
       double gE[9], HE[45], M[45];
-      energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, true);
+      energy_derivs<KIND>(ty, x, Y, s2, dhat, kappa, eps, gE, HE, true);
       to_q_basis<KIND>(HE, M);
       if (flags & EIPC_PROJECT) project_psd9(M);
       // zeta = Q^T z, eta = X zeta
@@ -1052,7 +1052,7 @@ __global__ void k_pair_eval(int64_t n, const int32_t *__restrict__ pairs, const 
   if (active) {
     V3 Y[3];
     y_basis<KIND>(x, Y);
-    ev = energy_derivs<KIND>(ty, Y, s2, dhat, kappa, eps, gE, HE, true);
+    ev = energy_derivs<KIND>(ty, x, Y, s2, dhat, kappa, eps, gE, HE, true);
     to_q_basis<KIND>(HE, M);
     if (flags & EIPC_PROJECT) project_psd9(M);
   }

@@ -261,13 +261,6 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
   return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 __device__ __forceinline__ double comp(V3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
-__device__ __forceinline__ V3 lin(int c0, V3 a, int c1, V3 b, int c2, V3 c) {
-  V3 r{0.0, 0.0, 0.0};
-  if (c0) { r.x += c0 * a.x; r.y += c0 * a.y; r.z += c0 * a.z; }
-  if (c1) { r.x += c1 * b.x; r.y += c1 * b.y; r.z += c1 * b.z; }
-  if (c2) { r.x += c2 * c.x; r.y += c2 * c.y; r.z += c2 * c.z; }
-  return r;
-}
 
 // Local derivatives of s for a type in its own local vectors y_0..y_{m-1}:
 // gl[3m], Hl[3m][3m] (full, row-major, stride 9).
@@ -292,8 +285,12 @@ __device__ __forceinline__ void skew_into(double *H, int r0, int c0, V3 a, doubl
 }
 
 // |y1 x y2|^2: gradient into g[o1..], g[o2..] and Hessian blocks into H.
+// The cross product and its norm are formed without contraction, as in the
+// squared-distance values: when y1 and y2 are nearly parallel n is far
+// smaller than its products, and only the same rounding keeps the
+// derivatives consistent with the value (and with the oracle's).
 __device__ __forceinline__ double crossnorm2(V3 y1, V3 y2, int o1, int o2, double *g, double *H) {
-  V3 n = cross(y1, y2);
+  V3 n = xcross(y1, y2);
   V3 t1 = cross(y2, n), t2 = cross(n, y1);
   g[o1 + 0] = 2.0 * t1.x; g[o1 + 1] = 2.0 * t1.y; g[o1 + 2] = 2.0 * t1.z;
   g[o2 + 0] = 2.0 * t2.x; g[o2 + 1] = 2.0 * t2.y; g[o2 + 2] = 2.0 * t2.z;
@@ -309,7 +306,7 @@ __device__ __forceinline__ double crossnorm2(V3 y1, V3 y2, int o1, int o2, doubl
       H[(o1 + i) * 9 + o2 + j] = c;
       H[(o2 + j) * 9 + o1 + i] = c;
     }
-  return dot(n, n);
+  return xdot(n, n);
 }
 
 template <int FN>
@@ -328,7 +325,7 @@ __device__ __forceinline__ void local_derivs(const V3 *y, Local &L) {
     double N, D, fN, fD, fNN, fND, fDD;
     if constexpr (FN == FN_PL) {
       N = crossnorm2(y[0], y[1], 0, 3, gN, HN);
-      D = dot(y[1], y[1]);
+      D = xdot(y[1], y[1]);
       gD[3] = 2.0 * y[1].x; gD[4] = 2.0 * y[1].y; gD[5] = 2.0 * y[1].z;
       HD[3 * 9 + 3] = 2.0; HD[4 * 9 + 4] = 2.0; HD[5 * 9 + 5] = 2.0;
       double iD = 1.0 / D;
@@ -338,9 +335,11 @@ __device__ __forceinline__ void local_derivs(const V3 *y, Local &L) {
       fND = -iD * iD;
       fDD = 2.0 * N * iD * iD * iD;
     } else {
-      V3 n = cross(y[1], y[2]);
+      // the triple product N is small against its terms near the plane:
+      // formed as in the value, without contraction
+      V3 n = xcross(y[1], y[2]);
       V3 c20 = cross(y[2], y[0]), c01 = cross(y[0], y[1]);
-      N = dot(y[0], n);
+      N = xdot(y[0], n);
       gN[0] = n.x; gN[1] = n.y; gN[2] = n.z;
       gN[3] = c20.x; gN[4] = c20.y; gN[5] = c20.z;
       gN[6] = c01.x; gN[7] = c01.y; gN[8] = c01.z;
@@ -371,12 +370,14 @@ __device__ __forceinline__ void local_derivs(const V3 *y, Local &L) {
 }
 
 // s-derivatives of one type mapped to the Y basis: gY[9], HY packed[45].
+// The local vectors are the value's own differences of the four positions
+// x (not combinations of Y), so s and its derivatives see the same inputs.
 template <int KIND, int TYPE>
-__device__ __forceinline__ void s_derivs_typed(const V3 *Y, double *gY, double *HY) {
+__device__ __forceinline__ void s_derivs_typed(const V3 *x, double *gY, double *HY) {
   constexpr TypeDef t = type_def<KIND, TYPE>();
   V3 y[3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) y[j] = (j < t.m) ? lin(t.c[j][0], Y[0], t.c[j][1], Y[1], t.c[j][2], Y[2]) : V3{0, 0, 0};
+  for (int j = 0; j < 3; ++j) y[j] = (j < t.m) ? xsub(x[t.plus[j]], x[t.minus[j]]) : V3{0, 0, 0};
   Local L;
   local_derivs<t.fn>(y, L);
 #pragma unroll
@@ -408,29 +409,30 @@ __device__ __forceinline__ void s_derivs_typed(const V3 *Y, double *gY, double *
         }
 }
 
+// type-dispatched s_derivs_typed over the four positions x
 template <int KIND>
-__device__ __forceinline__ void s_derivs(int type, const V3 *Y, double *gY, double *HY) {
+__device__ __forceinline__ void s_derivs(int type, const V3 *x, double *gY, double *HY) {
   if constexpr (KIND == 0) {
     switch (type) {
-      case 0: s_derivs_typed<0, 0>(Y, gY, HY); break;
-      case 1: s_derivs_typed<0, 1>(Y, gY, HY); break;
-      case 2: s_derivs_typed<0, 2>(Y, gY, HY); break;
-      case 3: s_derivs_typed<0, 3>(Y, gY, HY); break;
-      case 4: s_derivs_typed<0, 4>(Y, gY, HY); break;
-      case 5: s_derivs_typed<0, 5>(Y, gY, HY); break;
-      default: s_derivs_typed<0, 6>(Y, gY, HY); break;
+      case 0: s_derivs_typed<0, 0>(x, gY, HY); break;
+      case 1: s_derivs_typed<0, 1>(x, gY, HY); break;
+      case 2: s_derivs_typed<0, 2>(x, gY, HY); break;
+      case 3: s_derivs_typed<0, 3>(x, gY, HY); break;
+      case 4: s_derivs_typed<0, 4>(x, gY, HY); break;
+      case 5: s_derivs_typed<0, 5>(x, gY, HY); break;
+      default: s_derivs_typed<0, 6>(x, gY, HY); break;
     }
   } else {
     switch (type) {
-      case 0: s_derivs_typed<1, 0>(Y, gY, HY); break;
-      case 1: s_derivs_typed<1, 1>(Y, gY, HY); break;
-      case 2: s_derivs_typed<1, 2>(Y, gY, HY); break;
-      case 3: s_derivs_typed<1, 3>(Y, gY, HY); break;
-      case 4: s_derivs_typed<1, 4>(Y, gY, HY); break;
-      case 5: s_derivs_typed<1, 5>(Y, gY, HY); break;
-      case 6: s_derivs_typed<1, 6>(Y, gY, HY); break;
-      case 7: s_derivs_typed<1, 7>(Y, gY, HY); break;
-      default: s_derivs_typed<1, 8>(Y, gY, HY); break;
+      case 0: s_derivs_typed<1, 0>(x, gY, HY); break;
+      case 1: s_derivs_typed<1, 1>(x, gY, HY); break;
+      case 2: s_derivs_typed<1, 2>(x, gY, HY); break;
+      case 3: s_derivs_typed<1, 3>(x, gY, HY); break;
+      case 4: s_derivs_typed<1, 4>(x, gY, HY); break;
+      case 5: s_derivs_typed<1, 5>(x, gY, HY); break;
+      case 6: s_derivs_typed<1, 6>(x, gY, HY); break;
+      case 7: s_derivs_typed<1, 7>(x, gY, HY); break;
+      default: s_derivs_typed<1, 8>(x, gY, HY); break;
     }
   }
 }
@@ -464,10 +466,10 @@ __device__ __forceinline__ Barrier barrier_s(double s, double dhat) {
 // mollifier).  gE[9], HE packed [45].  eps_x <= 0 disables the mollifier.
 // Returns the energy.
 template <int KIND>
-__device__ __forceinline__ double energy_derivs(int type, const V3 *Y, double s, double dhat, double kappa,
-                                                double eps_x, double *gE, double *HE, bool want_h) {
+__device__ __forceinline__ double energy_derivs(int type, const V3 *x, const V3 *Y, double s, double dhat,
+                                                double kappa, double eps_x, double *gE, double *HE, bool want_h) {
   double gs[9], Hs[45];
-  s_derivs<KIND>(type, Y, gs, Hs);
+  s_derivs<KIND>(type, x, gs, Hs);
   Barrier br = barrier_s(s, dhat);
   double m = 1.0, m1 = 0.0, m2 = 0.0;
   double gc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -475,8 +477,8 @@ __device__ __forceinline__ double energy_derivs(int type, const V3 *Y, double s,
   bool moll = false;
   if constexpr (KIND == 1) {
     if (eps_x > 0.0) {
-      V3 n = cross(Y[1], Y[2]);
-      double c = dot(n, n);
+      V3 n = xcross(Y[1], Y[2]);
+      double c = xdot(n, n);
       if (c < eps_x) {
         moll = true;
         double r = c / eps_x;
