@@ -27,21 +27,24 @@ METRIC = "contact pairs/s (barrier+reduce) & CCD pairs/s, FP64, % HBM roofline"
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops per active pair, split by kernel (counts of the
-# operations the method needs, not of what a kernel executes).  Pair terms:
-# distance, its gradient and Hessian ~1e3, barrier chain rule and assembly
-# ~0.3e3, the symmetric eigendecomposition of the 9x9 translation-free
-# Hessian 9 n^3 = 6,561 and the reconstruction V max(L, 0) V^T ~2e3.
-# Expansion through W (16 weights, merged nodes, blocks and gradient):
-# ~4.6e3.  Algorithmic bytes per active pair for the whole barrier +
-# reduction: the pair record, its share of the gathered geometry and of
-# the outputs, ~85 B at config 2's reuse.
+# Algorithmic FP64 flops per active pair (counts of the operations the
+# method needs, not of what a kernel executes).  Pair terms: distance, its
+# gradient and Hessian ~1e3, barrier chain rule and assembly ~0.3e3, the
+# symmetric eigendecomposition of the 9x9 translation-free Hessian
+# 9 n^3 = 6,561 and the reconstruction V max(L, 0) V^T ~2e3.  Expansion
+# through W (16 weights, merged nodes, blocks and gradient): ~4.6e3.  The
+# barrier kernel does both for every active pair (the class-specialised
+# projections execute fewer flops than the nominal 9x9 count for
+# point-point and point-line pairs).  Algorithmic bytes per active pair
+# for the whole barrier + reduction: the pair record, its share of the
+# gathered geometry and of the outputs, ~85 B at config 2's reuse.
 FLOPS_TERMS = 1000 + 300 + 6561 + 2000
 FLOPS_EXPAND = 4600
+FLOPS_BARRIER = FLOPS_TERMS + FLOPS_EXPAND
 BYTES_BARRIER_PAIR = 85
 FAMILIES = {
     "query": ("query_count_pt", "query_count_ee", "query_write_pt", "query_write_ee"),
-    "pair_terms": ("barrier_pt", "barrier_ee"), "expand": ("expand_pt", "expand_ee"),
+    "barrier": ("barrier_pt", "barrier_ee"), "expand": ("expand_pt", "expand_ee"),
     "narrow": ("narrow_pt", "narrow_ee"), "ccd": ("ccd_pt", "ccd_ee", "ccd_long_pt", "ccd_long_ee"),
     "embed": ("embed",),
 }
@@ -192,11 +195,11 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
     ent = {"kernel": kdom, "family": dom, "avg_launch_us": avg_s * 1e6, "traffic": None,
            "timing": "HIP events on the launch stream over eager planned steps that run the PT and EE chains one "
                      "after the other (each kernel alone on the device)"}
-    if dom in ("pair_terms", "expand"):
+    if dom in ("barrier", "expand"):
         # FP64-bound: ~1.5e4 algorithmic flop against ~85 B per pair is far
         # above the ridge (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B)
         kind = 0 if kdom.endswith("_pt") else 1
-        per_pair = FLOPS_TERMS if dom == "pair_terms" else FLOPS_EXPAND
+        per_pair = FLOPS_BARRIER if dom == "barrier" else FLOPS_EXPAND
         per = per_pair * work["active"][kind]
         ach = per / avg_s / 1e12
         ent.update(bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
@@ -241,7 +244,7 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
     for k, kind in (("barrier_pt", 0), ("barrier_ee", 1)):
         if prof.get(k, (0, 0))[1]:
             s_ = prof[k][0] / prof[k][1] / 1e3
-            ent[f"{k}_tflops"] = FLOPS_TERMS * work["active"][kind] / s_ / 1e12
+            ent[f"{k}_tflops"] = FLOPS_BARRIER * work["active"][kind] / s_ / 1e12
     for k, kind in (("expand_pt", 0), ("expand_ee", 1)):
         if prof.get(k, (0, 0))[1]:
             s_ = prof[k][0] / prof[k][1] / 1e3

@@ -165,7 +165,9 @@ eipc_status eipc_build_candidates(eipc_ctx *ctx, const eipc_scene *sc, const dou
  * pair Hessian.  n_active (host) or NULL receives the number of active
  * pairs.  Synchronizes when n_active or hess_bsr is requested.
  * An active pair with d == 0 raises EIPC_ERR_INTERSECTING.  The reduced
- * Hessian needs n_node < 2^31 / 3 rows. */
+ * Hessian needs n_node < 2^31 / 3 rows; a reduced gradient or Hessian
+ * needs n_node < 2^27 (node ids are packed with a 4-bit slot in the
+ * reduction), else EIPC_ERR_ARG. */
 eipc_status eipc_barrier_reduce(eipc_ctx *ctx, const eipc_scene *sc, const double *q, const int32_t *pt,
                                 int64_t n_pt, const int32_t *ee, int64_t n_ee, double dhat, double kappa,
                                 uint32_t flags, double *energy, double *grad_q, double *hess_dense,

@@ -9,7 +9,6 @@
 namespace eipc {
 
 constexpr int BR_THREADS = 256;
-constexpr int LTBL = 1024;  // LDS 3x3-block table entries (76 KiB)
 constexpr int LGT = 512;    // LDS node-vector table entries (14 KiB)
 constexpr int MAX_PROBE = 32;       // LDS tables (a miss falls back to the global table)
 constexpr int GLOBAL_PROBE = 4096;  // global block table (at most half full; a miss is reported)
@@ -34,7 +33,7 @@ __device__ __forceinline__ uint32_t mix64(uint64_t k) {
 __device__ __forceinline__ int64_t table_slot64(long long *keys, uint64_t mask, long long key, int max_probe) {
   uint64_t h = mix64((uint64_t)key) & mask;
   for (int p = 0; p < max_probe; ++p) {
-    long long k = ((volatile long long *)keys)[h];
+    long long k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (k == key) return (int64_t)h;
     if (k == -1) {
       long long old = (long long)atomicCAS((unsigned long long *)&keys[h], (unsigned long long)-1ll,
@@ -46,19 +45,38 @@ __device__ __forceinline__ int64_t table_slot64(long long *keys, uint64_t mask, 
   return -1;
 }
 
-// find-or-insert in an open-addressing table of int keys (-1 = empty)
-__device__ __forceinline__ int table_slot(int *keys, uint32_t mask, int key) {
-  uint32_t h = mix32((uint32_t)key) & mask;
+// find-or-insert of key in an LDS open-addressing table of `size` entries
+// (all bits set = empty): linear probing from a multiplicative range
+// reduction of the key's hash.  All lanes of the wavefront call, `valid`
+// marking the lanes that look up; a lane that finds no slot within
+// MAX_PROBE probes gets -1.  fresh: this lane inserted the key.
+template <typename K>
+__device__ __forceinline__ int lds_slot(K *keys, int size, K key, bool valid, bool &fresh) {
+  const uint32_t hv = sizeof(K) == 8 ? mix64((uint64_t)key) : mix32((uint32_t)key);
+  int h = (int)(((uint64_t)hv * (uint32_t)size) >> 32);
+  int slot = -1;
+  fresh = false;
+  bool pending = valid;
   for (int p = 0; p < MAX_PROBE; ++p) {
-    int k = ((volatile int *)keys)[h];
-    if (k == key) return (int)h;
-    if (k == -1) {
-      int old = atomicCAS(&keys[h], -1, key);
-      if (old == -1 || old == key) return (int)h;
+    if (!__any(pending)) break;
+    if (pending) {
+      K k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (k == (K)~(K)0) {
+        k = atomicCAS(&keys[h], (K)~(K)0, key);
+        if (k == (K)~(K)0) {
+          fresh = true;
+          k = key;
+        }
+      }
+      if (k == key) {
+        slot = h;
+        pending = false;
+      } else {
+        h = h + 1 == size ? 0 : h + 1;
+      }
     }
-    h = (h + 1) & mask;
   }
-  return -1;
+  return slot;
 }
 
 template <int KIND>
@@ -104,36 +122,17 @@ __device__ __forceinline__ void global_block_add(const HessOut &h, int n_node, i
   }
 }
 
+// A workgroup's LDS table of node 3-vectors keyed by node.
 struct LdsTables {
-  long long *bkey;
-  double *bval;
-  int *gkey;
+  uint32_t *gkey;
   double *gval;
 };
 
-__device__ __forceinline__ void lds_vec_add(const LdsTables &T, double *grad, int I, double g0, double g1,
-                                            double g2) {
-  int slot = table_slot(T.gkey, LGT - 1, I);
-  if (slot < 0) {
-    atomicAdd(&grad[3 * (int64_t)I], g0);
-    atomicAdd(&grad[3 * (int64_t)I + 1], g1);
-    atomicAdd(&grad[3 * (int64_t)I + 2], g2);
-    return;
-  }
-  atomicAdd(&T.gval[3 * slot], g0);
-  atomicAdd(&T.gval[3 * slot + 1], g1);
-  atomicAdd(&T.gval[3 * slot + 2], g2);
-}
-
 // ---------------------------------------------------------------------------
-// Merged expansion.  The 16 (node, weight) slots of a pair (4 vertices x up
-// to 4 weights) are taken to the Q basis, z_s = w_s Q[a(s)] (3 numbers),
-// sorted by node with a bitonic network, equal nodes merged, and sorted
-// again to compact.  Then, for distinct nodes I <= J,
-//   block(I, J) = sum_{alpha, beta} z_I[alpha] z_J[beta] X[alpha][beta]
-// and the gradient of node I is sum_alpha z_I[alpha] gamma_alpha with
-// gamma = G^T gY.  Each block is summed across the wavefront when every
-// lane holding one targets the same block, else added per lane.
+// A pair's merged node set in one lane (the Hessian-vector product).  The
+// 16 (node, weight) slots of a pair (4 vertices x up to 4 weights) are
+// taken to the Q basis, z_s = w_s Q[a(s)] (3 numbers), sorted by node with
+// a bitonic network, equal nodes merged, and sorted again to compact.
 // ---------------------------------------------------------------------------
 constexpr int NO_NODE = 0x7fffffff;
 
@@ -219,20 +218,33 @@ struct Acc {
   uint32_t *status;
 };
 
+// Add a lane's node 3-vector into the LDS node table (all lanes of the
+// wavefront call): summed across the wavefront first when every valid lane
+// holds the same node; a table miss goes to the output directly.
 __device__ __forceinline__ void agg_vec(const Acc &A, bool valid, int node, double g0, double g1, double g2) {
   const uint64_t vm = __ballot(valid);
   if (vm == 0) return;
   const int first = __ffsll((unsigned long long)vm) - 1;
   const int k0 = __shfl(node, first, 64);
-  const bool uniform = __ballot(valid && node != k0) == 0;
-  if (uniform) {
+  bool ins = valid;
+  if (__ballot(valid && node != k0) == 0) {
     g0 = wave_sum(valid ? g0 : 0.0);
     g1 = wave_sum(valid ? g1 : 0.0);
     g2 = wave_sum(valid ? g2 : 0.0);
-    if ((int)(threadIdx.x & 63) == first) lds_vec_add(A.T, A.grad, node, g0, g1, g2);
-  } else if (valid) {
-    lds_vec_add(A.T, A.grad, node, g0, g1, g2);
+    ins = (int)(threadIdx.x & 63) == first;
   }
+  bool fresh;
+  const int slot = lds_slot<uint32_t>(A.T.gkey, LGT, (uint32_t)node, ins, fresh);
+  if (!ins) return;
+  if (slot < 0) {
+    atomicAdd(&A.grad[3 * (int64_t)node], g0);
+    atomicAdd(&A.grad[3 * (int64_t)node + 1], g1);
+    atomicAdd(&A.grad[3 * (int64_t)node + 2], g2);
+    return;
+  }
+  atomicAdd(&A.T.gval[3 * slot], g0);
+  atomicAdd(&A.T.gval[3 * slot + 1], g1);
+  atomicAdd(&A.T.gval[3 * slot + 2], g2);
 }
 
 // Add a per-lane value into out[scene] (all lanes of the wavefront call):
@@ -253,193 +265,244 @@ __device__ __forceinline__ void agg_scene_add(double *out, bool valid, int scene
   }
 }
 
-// Phase 1: per active pair, energy (reduced per scene), the gradient in
-// the Q basis gamma = G^T gY (9) and the Hessian X in the Q basis (45,
-// PSD-projected with EIPC_PROJECT), stored SoA: out[e*cap + i].
-template <int KIND>
-__global__ __launch_bounds__(BR_THREADS) void k_pair_terms(
-    const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
-    const int64_t *__restrict__ d_count, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
-    const double *__restrict__ xs, const double *__restrict__ x_rest, int n_vert, double dhat, double kappa,
-    uint32_t flags, double *energy, double *__restrict__ gq, double *__restrict__ Xq, int64_t cap,
-    const int32_t *__restrict__ vscene, int n_scene, uint32_t *status, const int4 *__restrict__ vid4) {
-  __shared__ double s_e[BR_THREADS / 64];
-  const bool want_g = gq != nullptr;
-  const bool want_h = Xq != nullptr;
-  const bool project = flags & EIPC_PROJECT;
-  const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
-  const int64_t n = *d_count < cap ? *d_count : cap;
-  double e_acc = 0.0;
-  for (int64_t base = (int64_t)blockIdx.x * BR_THREADS; base < n; base += (int64_t)gridDim.x * BR_THREADS) {
-    const int64_t i = base + threadIdx.x;
-    const bool live = i < n;
-    double e_pair = 0.0;
-    int scene = 0;
-    if (live) {
-      const int ty = typ[i];
-      int vid[4];
-      if (vid4) {
-        const int4 v4 = vid4[i];
-        vid[0] = v4.x;
-        vid[1] = v4.y;
-        vid[2] = v4.z;
-        vid[3] = v4.w;
+// ---------------------------------------------------------------------------
+// Reduction through W (Eq. 17) of per-pair term records (gamma, X in the Q
+// basis; TERM_REC doubles per pair).
+//
+// A workgroup accumulates into LDS over a contiguous range of pairs in
+// locality order.  Nodes, not blocks, are looked up: a node's local index
+// is its slot in a small open-addressing table of LN slots (installed by
+// compare-and-swap), and the blocks of local nodes a <= b live in a dense
+// packed upper triangle of LN x LN 3x3 FP64 blocks addressed
+// arithmetically, the gradient in LN 3-vectors.  A node that finds no slot
+// (the table is full) goes straight to the outputs.  Between steps the
+// accumulator is flushed into the outputs once it holds more than LN / 4
+// nodes (each touched block once).
+// ---------------------------------------------------------------------------
+constexpr int EX_T = 512;                // eight wavefronts, two per SIMD
+constexpr int EX_PPG = 8;                // pairs per 16-lane group and step
+constexpr int EX_STEP = EX_T / 16 * EX_PPG;  // pairs per step (256)
+constexpr int LN = 60;                   // local node slots
+constexpr int LNB = LN * (LN + 1) / 2;   // their upper 3x3 blocks (129 KiB)
+constexpr int LN_PROBE = 16;
+
+struct LocalAcc {
+  int *nkey;               // LN: node of the slot, -1 = empty
+  double *bval;            // LNB * 9 (rows of the lower slot)
+  unsigned char *touched;  // LNB
+  double *gval;            // LN * 3
+  int *count;              // nodes installed
+};
+
+__device__ __forceinline__ int ltri(int a, int b) { return a * LN - (a * (a - 1)) / 2 + (b - a); }  // a <= b
+
+// local slot of node (all lanes of the wavefront call; valid marks the
+// lookups); -1 when none is found within LN_PROBE probes
+__device__ __forceinline__ int local_index(const LocalAcc &L, int node, bool valid) {
+  int h = (int)(((uint64_t)mix32((uint32_t)node) * (uint32_t)LN) >> 32);
+  int li = -1;
+  bool pending = valid;
+  for (int p = 0; p < LN_PROBE; ++p) {
+    if (!__any(pending)) break;
+    if (pending) {
+      int k = __hip_atomic_load(&L.nkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (k == -1) {
+        k = atomicCAS(&L.nkey[h], -1, node);
+        if (k == -1) {
+          atomicAdd(L.count, 1);
+          k = node;
+        }
+      }
+      if (k == node) {
+        li = h;
+        pending = false;
       } else {
-        pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
-      }
-      if (vscene) scene = vscene[vid[0]];
-      V3 x[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) x[a] = load3(xs, n_vert, vid[a]);
-      const double s2 = type_value<KIND>(ty, x);
-      double eps = 0.0;
-      if (moll) {
-        V3 r[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-          r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
-        eps = mollifier_eps(r);
-      }
-      V3 Y[3];
-      y_basis<KIND>(x, Y);
-      double gE[9], HE[45];
-      e_pair = energy_derivs<KIND>(ty, x, Y, s2, dhat, kappa, eps, gE, HE, want_h);
-      if (want_g) {
-#pragma unroll
-        for (int al = 0; al < 3; ++al)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            double acc = 0.0;
-#pragma unroll
-            for (int J = 0; J < 3; ++J) {
-              const int g = gcoef(KIND, J, al);
-              if (g != 0) acc += g * gE[3 * J + c];
-            }
-            gq[(3 * al + c) * cap + i] = acc;
-          }
-      }
-      if (want_h) {
-        double M[45];
-        to_q_basis<KIND>(HE, M);
-        if (project) project_psd9(M);
-#pragma unroll
-        for (int e = 0; e < 45; ++e) Xq[e * cap + i] = M[e];
+        h = h + 1 == LN ? 0 : h + 1;
       }
     }
-    if (energy && vscene) agg_scene_add(energy, live, scene, n_scene, e_pair, status);
-    e_acc += e_pair;
   }
-  if (energy && !vscene) {
-    e_acc = wave_sum(e_acc);
-    if ((threadIdx.x & 63) == 0) s_e[threadIdx.x >> 6] = e_acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < BR_THREADS / 64; ++w) t += s_e[w];
-      if (t != 0.0) atomicAdd(energy, t);
-    }
-  }
+  return li;
 }
 
-// ---------------------------------------------------------------------------
-// Phase 2, reduction through W of gamma and X.  Cooperative expansion: sixteen lanes per pair, lane s holding slot s =
-// (vertex s / 4, weight s % 4) of the pair: its node and z_s = w_s Q[a]
-// (3 numbers).  The sixteen slots are sorted by node across the lanes
-// (bitonic exchange within the 16-lane group), runs of equal nodes summed
-// (segmented scan; the last lane of a run keeps the node), so each node of
-// the pair sits on one lane.  That lane forms Y_J = sum_beta z_J[beta]
-// X[.][beta] (27 numbers) and, for every node I <= J of the group (taken
-// by shuffle), the block sum_alpha z_I[alpha] Y_J[alpha], accumulated in
-// the workgroup's LDS table as in the per-pair form; the node's gradient
-// is sum_alpha z_J[alpha] gamma_alpha.
-// ---------------------------------------------------------------------------
-// threads per workgroup: 64 pairs per step.  The LDS tables allow one
-// workgroup per CU, so its size sets the waves a CU runs: 1,024 threads
-// (four per SIMD; the kernel is then held to 128 VGPRs and spills 68 bytes
-// per lane) measured faster than 768 (three) and 512 (two)
-constexpr int EX_T = 1024;
-
-__device__ __forceinline__ int64_t table_slot64_new(long long *keys, uint64_t mask, long long key, bool &fresh) {
-  uint64_t h = mix64((uint64_t)key) & mask;
-  fresh = false;
-  for (int p = 0; p < MAX_PROBE; ++p) {
-    long long k = ((volatile long long *)keys)[h];
-    if (k == key) return (int64_t)h;
-    if (k == -1) {
-      long long old = (long long)atomicCAS((unsigned long long *)&keys[h], (unsigned long long)-1ll,
-                                           (unsigned long long)key);
-      if (old == -1) {
-        fresh = true;
-        return (int64_t)h;
-      }
-      if (old == key) return (int64_t)h;
-    }
-    h = (h + 1) & mask;
-  }
-  return -1;
+__device__ __forceinline__ void local_init(const LocalAcc &L) {
+  for (int t = threadIdx.x; t < LN; t += blockDim.x) L.nkey[t] = -1;
+  for (int t = threadIdx.x; t < LNB * 9; t += blockDim.x) L.bval[t] = 0.0;
+  for (int t = threadIdx.x; t < LNB; t += blockDim.x) L.touched[t] = 0;
+  for (int t = threadIdx.x; t < LN * 3; t += blockDim.x) L.gval[t] = 0.0;
+  if (threadIdx.x == 0) *L.count = 0;
 }
 
-template <int KIND>
-__global__ __launch_bounds__(EX_T) void k_expand16(
-    const int4 *__restrict__ vid4, const int64_t *__restrict__ d_count, const int32_t *__restrict__ rowptr,
-    const int32_t *__restrict__ col, const double *__restrict__ val, int n_node, const double *__restrict__ gq,
-    const double *__restrict__ Xq, int64_t cap, double *grad, HessOut h, uint32_t *status) {
-  __shared__ long long s_bkey[LTBL];
-  __shared__ double s_bval[LTBL * 9];
-  __shared__ int s_gkey[LGT];
-  __shared__ double s_gval[LGT * 3];
-  __shared__ int s_used;
-  const bool want_g = gq != nullptr && grad != nullptr;
-  const bool want_h = Xq != nullptr && h.kind != 0;
-  for (int t = threadIdx.x; t < LTBL; t += EX_T) s_bkey[t] = -1;
-  for (int t = threadIdx.x; t < LTBL * 9; t += EX_T) s_bval[t] = 0.0;
-  for (int t = threadIdx.x; t < LGT; t += EX_T) s_gkey[t] = -1;
-  for (int t = threadIdx.x; t < LGT * 3; t += EX_T) s_gval[t] = 0.0;
-  if (threadIdx.x == 0) s_used = 0;
+// All threads of the workgroup call (between barriers).
+__device__ __forceinline__ void local_flush(const LocalAcc &L, const HessOut &h, int n_node, double *grad,
+                                            uint32_t *status) {
+  for (int idx = threadIdx.x; idx < LNB; idx += blockDim.x) {
+    if (!L.touched[idx]) continue;
+    // row a of the packed triangle: start(a) = a (2 LN - a + 1) / 2 <= idx
+    int a = (int)((2.0 * LN + 1.0 - sqrt((2.0 * LN + 1.0) * (2.0 * LN + 1.0) - 8.0 * idx)) * 0.5);
+    if (a < 0) a = 0;
+    while (a + 1 < LN && ltri(a + 1, a + 1) <= idx) ++a;
+    while (a > 0 && ltri(a, a) > idx) --a;
+    const int b = a + (idx - ltri(a, a));
+    const int na = L.nkey[a], nb = L.nkey[b];
+    double M[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+      M[u] = L.bval[9 * idx + u];
+      L.bval[9 * idx + u] = 0.0;
+    }
+    L.touched[idx] = 0;
+    if (na <= nb) {
+      global_block_add(h, n_node, na, nb, M, status);
+    } else {
+      double Mt[9];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Mt[3 * r + c] = M[3 * c + r];
+      global_block_add(h, n_node, nb, na, Mt, status);
+    }
+  }
+  __syncthreads();  // nkey is read above and reset below
+  for (int li = threadIdx.x; li < LN; li += blockDim.x) {
+    const int node = L.nkey[li];
+    if (node >= 0 && grad) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) atomicAdd(&grad[3 * (int64_t)node + c], L.gval[3 * li + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) L.gval[3 * li + c] = 0.0;
+    L.nkey[li] = -1;
+  }
   __syncthreads();
+  if (threadIdx.x == 0) *L.count = 0;
+}
+
+__device__ __forceinline__ int permute_lane(int v, int dst) { return __builtin_amdgcn_ds_permute(dst << 2, v); }
+__device__ __forceinline__ double permute_lane(double v, int dst) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_permute(dst << 2, (int)(unsigned)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_permute(dst << 2, (int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// J with J(J+1)/2 <= t < (J+1)(J+2)/2, for 0 <= t < 256
+__device__ __forceinline__ int tri_root(int t) {
+  int J = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  if (((J + 1) * (J + 2)) / 2 <= t) ++J;
+  if ((J * (J + 1)) / 2 > t) --J;
+  return J;
+}
+
+// The wavefront's pairs are held by lanes 16g + p, p < EX_PPG (pair i0 +
+// g EX_PPG + p, `own` when it exists) and taken in EX_PPG passes: in pass p
+// the sixteen lanes of group g (lanes 16g .. 16g+15) serve the pair of lane
+// 16g + p, lane s holding slot s = (vertex s / 4, weight s % 4): its node
+// and z_s = w_s Q[a] (3 numbers).
+// The slots are sorted by node (bitonic on the packed key node * 16 + s),
+// runs of equal nodes summed (the run's last lane keeps the total), and the
+// m distinct nodes packed in order onto lanes 0 .. m-1 of the group, which
+// look up their local indices.  Node I's gradient is sum_alpha z_I[alpha]
+// gamma_alpha; the m(m+1)/2 blocks I <= J are dealt to the group's lanes
+// (block t on lane t mod 16),
+//   B(I, J) = sum_{alpha, beta} z_I[alpha] z_J[beta] X[alpha][beta].
+// All 64 lanes call, in wavefront-uniform control flow.
+__device__ __forceinline__ void expand_wave(const LocalAcc &L, const HessOut &h, int n_node, double *grad,
+                                            uint32_t *status, const int32_t *__restrict__ rowptr,
+                                            const int32_t *__restrict__ col, const double *__restrict__ val,
+                                            bool own, const int *vid, const double *__restrict__ rec, int64_t i0,
+                                            bool want_g, bool want_h) {
   const int lane = threadIdx.x & 63;
   const int s = lane & 15;
   const int gbase = lane & ~15;
-  constexpr int PPS = EX_T / 16;  // pairs per step
-  const int64_t n = *d_count < cap ? *d_count : cap;
-  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + PPS - 1) / PPS * PPS;
-  const int64_t r0 = (int64_t)blockIdx.x * per;
-  const int64_t r1 = r0 + per < n ? r0 + per : n;
-  for (int64_t base = r0; base < r1; base += PPS) {
-    const int64_t i = base + (threadIdx.x >> 4);
-    const bool active = i < r1;
-    // this lane's slot
-    int node = NO_NODE;
-    double z[3] = {0.0, 0.0, 0.0};
-    if (active) {
-      const int a = s >> 2, k = s & 3;
-      const int4 v4 = vid4[i];
-      const int v = a == 0 ? v4.x : (a == 1 ? v4.y : (a == 2 ? v4.z : v4.w));
-      const int k0 = rowptr[v];
-      if (k < rowptr[v + 1] - k0) {
-        node = col[k0 + k];
-        const double w = val[k0 + k];
+  const int a = s >> 2, k = s & 3;
+  const uint64_t own_mask = __ballot(own);
+  // The slot data of pass p (row of the slot's vertex, then its node and
+  // weight) is loaded one and two passes ahead, so its latency hides behind
+  // the previous pass.
+  auto slot_vertex = [&](int p) {
+    const int owner = gbase + p;
+    const int v0 = __shfl(vid[0], owner, 64), v1 = __shfl(vid[1], owner, 64);
+    const int v2 = __shfl(vid[2], owner, 64), v3 = __shfl(vid[3], owner, 64);
+    return a == 0 ? v0 : (a == 1 ? v1 : (a == 2 ? v2 : v3));
+  };
+  int row_k0, row_n;  // row of pass p + 1
+  int cur_node = NO_NODE;
+  double cur_w = 0.0;  // slot of pass p
+  {
+    const int v = slot_vertex(0);
+    const int k0 = rowptr[v];
+    const int cnt = rowptr[v + 1] - k0;
+    if ((own_mask >> gbase) & 1ull && k < cnt) {
+      cur_node = col[k0 + k];
+      cur_w = val[k0 + k];
+    }
+    const int v1 = slot_vertex(1 < EX_PPG ? 1 : 0);
+    row_k0 = rowptr[v1];
+    row_n = rowptr[v1 + 1] - row_k0;
+  }
+  for (int p = 0; p < EX_PPG; ++p) {
+    // pairs fill the owner lanes in order: an empty pass ends the wavefront's work
+    if (((own_mask >> p) & 0x0001000100010001ull) == 0) break;
+    const int owner = gbase + p;
+    const bool active = (own_mask >> owner) & 1ull;
+    // the owner's terms (the sixteen lanes read the same record; a group
+    // without a pair reads the wavefront's first and ignores it)
+    const double2 *r2 =
+        (const double2 *)(rec + (i0 + (active ? (gbase >> 4) * EX_PPG + p : 0)) * TERM_REC);
+    double tv[54];
 #pragma unroll
-        for (int al = 0; al < 3; ++al) z[al] = 0.5 * kS[a][al] * w;
+    for (int q = 0; q < 5; ++q) {
+      const double2 t2 = r2[q];
+      tv[2 * q] = t2.x;
+      tv[2 * q + 1] = t2.y;
+    }
+    if (want_h) {
+#pragma unroll
+      for (int q = 5; q < 27; ++q) {
+        const double2 t2 = r2[q];
+        tv[2 * q] = t2.x;
+        tv[2 * q + 1] = t2.y;
       }
     }
-    // sort the group's slots by node (bitonic, ascending; ties keep place)
-#pragma unroll
-    for (int k = 2; k <= 16; k <<= 1)
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        const int pn = __shfl_xor(node, j, 64);
-        double pz[3];
-#pragma unroll
-        for (int al = 0; al < 3; ++al) pz[al] = __shfl_xor(z[al], j, 64);
-        const bool up = (s & k) == 0, low = (s & j) == 0;
-        const bool take = (low == up) ? (pn < node) : (pn > node);
-        if (take) {
-          node = pn;
-#pragma unroll
-          for (int al = 0; al < 3; ++al) z[al] = pz[al];
-        }
+    // prefetch: the slot of pass p + 1, the row of pass p + 2
+    int nxt_node = NO_NODE;
+    double nxt_w = 0.0;
+    if (p + 1 < EX_PPG) {
+      if ((own_mask >> (owner + 1)) & 1ull && k < row_n) {
+        nxt_node = col[row_k0 + k];
+        nxt_w = val[row_k0 + k];
       }
+      if (p + 2 < EX_PPG) {
+        const int v2 = slot_vertex(p + 2);
+        row_k0 = rowptr[v2];
+        row_n = rowptr[v2 + 1] - row_k0;
+      }
+    }
+    int node = cur_node;
+    double z[3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) z[al] = 0.5 * (double)qsign(a, al) * cur_w;
+    cur_node = nxt_node;
+    cur_w = nxt_w;
+    // sort the group's slots by node: bitonic on the packed key node * 16 +
+    // slot (unique in the group, empty slots last), then each position
+    // takes its slot's z
+    uint32_t pk = node == NO_NODE ? (0xfffffff0u | (uint32_t)s) : (((uint32_t)node << 4) | (uint32_t)s);
+#pragma unroll
+    for (int kk = 2; kk <= 16; kk <<= 1)
+#pragma unroll
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        const uint32_t po = (uint32_t)__shfl_xor((int)pk, j, 64);
+        const bool up = (s & kk) == 0, low = (s & j) == 0;
+        const bool take = (low == up) ? (po < pk) : (po > pk);
+        pk = take ? po : pk;
+      }
+    node = (pk >> 4) == 0x0fffffffu ? NO_NODE : (int)(pk >> 4);
+    {
+      const int src = gbase + (int)(pk & 15u);
+#pragma unroll
+      for (int al = 0; al < 3; ++al) z[al] = __shfl(z[al], src, 64);
+    }
     // sum runs of equal nodes; the run's last lane holds the total
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) {
@@ -454,85 +517,127 @@ __global__ __launch_bounds__(EX_T) void k_expand16(
     }
     const int nn = __shfl_down(node, 1, 16);
     const bool mine = node != NO_NODE && (s == 15 || nn != node);
-    if (want_g) {
-      double gam[9];
+    // pack the distinct nodes onto lanes 0..m-1 of the group, in order (a
+    // permutation of the group's lanes)
+    const uint32_t gm = (uint32_t)(__ballot(mine) >> gbase) & 0xffffu;
+    const int m = __popc(gm);
+    const int below = __popc(gm & ((1u << s) - 1u));
+    const int dst = gbase + (mine ? below : m + (s - below));
+    const int pnode = permute_lane(node, dst);
+    double cz[3];
 #pragma unroll
-      for (int e = 0; e < 9; ++e) gam[e] = active ? gq[e * cap + i] : 0.0;
+    for (int al = 0; al < 3; ++al) cz[al] = permute_lane(z[al], dst);
+    const bool has = s < m;
+    const int cnode = has ? pnode : NO_NODE;
+    const int cli = local_index(L, cnode, has);
+    if (want_g && has) {
       double g[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) g[c] = z[0] * gam[c] + z[1] * gam[3 + c] + z[2] * gam[6 + c];
-      LdsTables T{s_bkey, s_bval, s_gkey, s_gval};
-      Acc A{T, h, n_node, grad, status};
-      agg_vec(A, mine, mine ? node : -1, g[0], g[1], g[2]);
+      for (int c = 0; c < 3; ++c) g[c] = cz[0] * tv[c] + cz[1] * tv[3 + c] + cz[2] * tv[6 + c];
+      if (cli >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(&L.gval[3 * cli + c], g[c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(&grad[3 * (int64_t)cnode + c], g[c]);
+      }
     }
     if (want_h) {
-      double Y[3][9];
-      {
-        double X[45];
+      const double *Xo = tv + 9;
+      const int nb = (m * (m + 1)) >> 1;
+      for (int t0 = 0;; t0 += 16) {
+        const int t = t0 + s;
+        const bool vb = t < nb;
+        if (!__any(vb)) break;
+        int I = 0, J = 0;
+        if (vb) {
+          J = tri_root(t);
+          I = t - ((J * (J + 1)) >> 1);
+        }
+        const int nI = __shfl(cnode, gbase + I, 64), nJ = __shfl(cnode, gbase + J, 64);
+        const int lI = __shfl(cli, gbase + I, 64), lJ = __shfl(cli, gbase + J, 64);
+        double zI[3], zJ[3];
 #pragma unroll
-        for (int e = 0; e < 45; ++e) X[e] = active ? Xq[e * cap + i] : 0.0;
+        for (int al = 0; al < 3; ++al) {
+          zI[al] = __shfl(cz[al], gbase + I, 64);
+          zJ[al] = __shfl(cz[al], gbase + J, 64);
+        }
+        if (vb) {
+          double w[9];
 #pragma unroll
-        for (int al = 0; al < 3; ++al)
+          for (int al = 0; al < 3; ++al)
+#pragma unroll
+            for (int be = 0; be < 3; ++be) w[3 * al + be] = zI[al] * zJ[be];
+          double B[9];
 #pragma unroll
           for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-              Y[al][3 * r + c] = z[0] * X[pidx(3 * al + r, c)] + z[1] * X[pidx(3 * al + r, 3 + c)] +
-                                 z[2] * X[pidx(3 * al + r, 6 + c)];
-      }
-#pragma unroll 2
-      for (int ii = 0; ii < 16; ++ii) {
-        const int src = gbase + ii;
-        const int nI = __shfl(node, src, 64);
-        const int nI1 = __shfl(node, (src & ~15) | ((ii + 1) & 15), 64);
-        const bool mI = nI != NO_NODE && (ii == 15 || nI1 != nI);
-        const bool v = mine && mI && nI <= node;
-        if (!__any(v)) continue;
-        double zI[3];
+            for (int c = 0; c < 3; ++c) {
+              double acc = 0.0;
 #pragma unroll
-        for (int al = 0; al < 3; ++al) zI[al] = __shfl(z[al], src, 64);
-        if (v) {
-          double B[9];
+              for (int al = 0; al < 3; ++al)
 #pragma unroll
-          for (int t = 0; t < 9; ++t) B[t] = zI[0] * Y[0][t] + zI[1] * Y[1][t] + zI[2] * Y[2][t];
-          const long long key = (long long)nI * n_node + node;
-          bool fresh;
-          const int slot = (int)table_slot64_new(s_bkey, LTBL - 1, key, fresh);
-          if (slot < 0) {
-            global_block_add(h, n_node, nI, node, B, status);
+                for (int be = 0; be < 3; ++be) acc += w[3 * al + be] * Xo[pidx(3 * al + r, 3 * be + c)];
+              B[3 * r + c] = acc;
+            }
+          if (lI >= 0 && lJ >= 0) {
+            // rows of the lower local index
+            const bool tr = lI > lJ;
+            const int slot = tr ? ltri(lJ, lI) : ltri(lI, lJ);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) atomicAdd(&L.bval[9 * slot + 3 * r + c], tr ? B[3 * c + r] : B[3 * r + c]);
+            L.touched[slot] = 1;
           } else {
-            if (fresh) atomicAdd(&s_used, 1);
-#pragma unroll
-            for (int t = 0; t < 9; ++t) atomicAdd(&s_bval[9 * slot + t], B[t]);
+            global_block_add(h, n_node, nI, nJ, B, status);
           }
         }
       }
     }
-    __syncthreads();
-    const bool last = base + PPS >= r1;
-    if (last || s_used > LTBL / 2) {
-      for (int t = threadIdx.x; t < LTBL; t += EX_T) {
-        const long long key = s_bkey[t];
-        if (key != -1) {
-          global_block_add(h, n_node, key / n_node, key % n_node, &s_bval[9 * t], status);
-          s_bkey[t] = -1;
-#pragma unroll
-          for (int u = 0; u < 9; ++u) s_bval[9 * t + u] = 0.0;
-        }
+  }
+}
+
+// Reduction of per-pair term records (pairs in locality order with their
+// vertex ids): a workgroup takes a contiguous range, 64 pairs per
+// wavefront step.
+__global__ __launch_bounds__(EX_T) void k_expand(
+    const int4 *__restrict__ vid4, const int64_t *__restrict__ d_count, const int32_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const double *__restrict__ val, int n_node, const double *__restrict__ rec,
+    int64_t cap, bool want_g, bool want_h, double *grad, HessOut h, uint32_t *status) {
+  __shared__ int s_nkey[LN];
+  __shared__ double s_bval[LNB * 9];
+  __shared__ double s_gval[LN * 3];
+  __shared__ unsigned char s_touched[LNB];
+  __shared__ int s_count;
+  LocalAcc L{s_nkey, s_bval, s_touched, s_gval, &s_count};
+  local_init(L);
+  __syncthreads();
+  // consecutive ranges on one XCD (workgroups are dealt to the 8 XCDs in turn)
+  int rid = blockIdx.x;
+  if ((gridDim.x & 7) == 0) rid = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int64_t n = *d_count < cap ? *d_count : cap;
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 63) / 64 * 64;
+  const int64_t r0 = (int64_t)rid * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t base = r0; base < r1; base += EX_STEP) {
+    const int64_t wb = base + 4 * EX_PPG * wave;
+    if (wb < r1) {
+      const int64_t i = wb + (lane >> 4) * EX_PPG + (lane & 15);
+      const bool live = (lane & 15) < EX_PPG && i < r1;
+      int vid[4] = {0, 0, 0, 0};
+      if (live) {
+        const int4 v4 = vid4[i];
+        vid[0] = v4.x;
+        vid[1] = v4.y;
+        vid[2] = v4.z;
+        vid[3] = v4.w;
       }
-      for (int t = threadIdx.x; t < LGT; t += EX_T) {
-        const int key = s_gkey[t];
-        if (key != -1) {
-          atomicAdd(&grad[3 * (int64_t)key], s_gval[3 * t]);
-          atomicAdd(&grad[3 * (int64_t)key + 1], s_gval[3 * t + 1]);
-          atomicAdd(&grad[3 * (int64_t)key + 2], s_gval[3 * t + 2]);
-          s_gkey[t] = -1;
-          s_gval[3 * t] = s_gval[3 * t + 1] = s_gval[3 * t + 2] = 0.0;
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) s_used = 0;
+      expand_wave(L, h, n_node, grad, status, rowptr, col, val, live, vid, rec, wb, want_g, want_h);
     }
+    __syncthreads();
+    if (base + EX_STEP >= r1 || s_count > LN / 4) local_flush(L, h, n_node, want_g ? grad : nullptr, status);
     __syncthreads();
   }
 }
@@ -647,50 +752,203 @@ static eipc_status sort_active(eipc_ctx *c, const eipc_scene *sc, int kind, cons
   return EIPC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Per active pair: the energy (Eq. 7, summed per scene), its Q-basis
+// gradient and (projected) Hessian, stored as a term record in the pair's
+// (locality-order) position for k_expand.
+//
+// A workgroup takes a contiguous range of the active pairs in tiles of up
+// to TERMS_TILE pairs.  Each tile is put in order of pair class (point-point,
+// point-line, interior, mollified) by a counting sort in LDS, so that the
+// lanes of a wavefront nearly always share one derivative path; each
+// wavefront then takes 64 pairs of the tile at a time, one per lane.
+// ---------------------------------------------------------------------------
+constexpr int TERMS_T = 256;      // four wavefronts, one per SIMD (the 9x9 projection's registers)
+constexpr int TERMS_TILE = 2048;  // pairs per class-sorted tile
+
+template <int KIND>
+__global__ __launch_bounds__(TERMS_T) void k_pair_terms(
+    const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
+    const int4 *__restrict__ vid4, const int64_t *__restrict__ d_count, int64_t cap,
+    const int32_t *__restrict__ faces, const int32_t *__restrict__ edges, const double *__restrict__ xs,
+    const double *__restrict__ x_rest, int n_vert, double dhat, double kappa, uint32_t flags, bool want_g,
+    bool want_h, double *energy, double *__restrict__ rec, const int32_t *__restrict__ vscene, int n_scene,
+    uint32_t *status) {
+  __shared__ int s_tile[TERMS_TILE];
+  __shared__ int s_cnt[4];
+  __shared__ double s_e[TERMS_T / 64];
+  const bool expand = want_g || want_h;
+  const bool project = flags & EIPC_PROJECT;
+  const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  constexpr int NW = TERMS_T / 64;
+  const int64_t n = *d_count < cap ? *d_count : cap;
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + 63) / 64 * 64;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  double e_acc = 0.0;
+  for (int64_t tb = r0; tb < r1; tb += TERMS_TILE) {
+    const int tn = (int)(r1 - tb < TERMS_TILE ? r1 - tb : TERMS_TILE);
+    if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    // class of each pair of the tile and its rank within the class
+    constexpr int PER_T = TERMS_TILE / TERMS_T;
+    int cls_of[PER_T], rank_of[PER_T];
+#pragma unroll
+    for (int u = 0; u < PER_T; ++u) {
+      const int li = u * TERMS_T + threadIdx.x;
+      const bool v = li < tn;
+      int cls = 0;
+      if (v && expand) {
+        const int64_t i = tb + li;
+        const int ty = typ[i];
+        if (moll) {
+          int vid[4];
+          if (vid4) {
+            const int4 v4 = vid4[i];
+            vid[0] = v4.x;
+            vid[1] = v4.y;
+            vid[2] = v4.z;
+            vid[3] = v4.w;
+          } else {
+            pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
+          }
+          V3 x[4], r[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            x[q] = load3(xs, n_vert, vid[q]);
+            r[q] = V3{x_rest[3 * (int64_t)vid[q]], x_rest[3 * (int64_t)vid[q] + 1], x_rest[3 * (int64_t)vid[q] + 2]};
+          }
+          cls = pair_class<KIND>(ty, x, mollifier_eps(r));
+        } else {
+          cls = type_fn<KIND>(ty);
+        }
+      }
+      cls_of[u] = cls;
+      rank_of[u] = wave_key_add(s_cnt, cls, v);
+    }
+    __syncthreads();
+    {
+      const int c0 = s_cnt[0], c1 = s_cnt[1], c2 = s_cnt[2];
+#pragma unroll
+      for (int u = 0; u < PER_T; ++u) {
+        const int li = u * TERMS_T + threadIdx.x;
+        if (li < tn) {
+          const int cls = cls_of[u];
+          const int base = cls == 0 ? 0 : (cls == 1 ? c0 : (cls == 2 ? c0 + c1 : c0 + c1 + c2));
+          s_tile[base + rank_of[u]] = li | (cls << 16);
+        }
+      }
+    }
+    __syncthreads();
+    const int nc = (tn + 63) / 64;
+    for (int ch = wave; ch < nc; ch += NW) {
+      const int pos = ch * 64 + lane;
+      const bool live = pos < tn;
+      double e_pair = 0.0;
+      int scene = 0;
+      if (live) {
+        const int code = s_tile[pos];
+        const int64_t i = tb + (code & 0xffff);
+        const int cls = code >> 16;
+        const int ty = typ[i];
+        int vid[4];
+        if (vid4) {
+          const int4 v4 = vid4[i];
+          vid[0] = v4.x;
+          vid[1] = v4.y;
+          vid[2] = v4.z;
+          vid[3] = v4.w;
+        } else {
+          pair_vertices<KIND>(pairs, act[i], faces, edges, vid);
+        }
+        if (vscene) scene = vscene[vid[0]];
+        V3 x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = load3(xs, n_vert, vid[q]);
+        double eps = 0.0;
+        if (moll && (cls == CLS_GEN || !expand)) {
+          V3 r[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            r[q] = V3{x_rest[3 * (int64_t)vid[q]], x_rest[3 * (int64_t)vid[q] + 1], x_rest[3 * (int64_t)vid[q] + 2]};
+          eps = mollifier_eps(r);
+        }
+        if (expand) {
+          double tv[54];
+          e_pair = pair_qterms<KIND>(cls, ty, x, eps, dhat, kappa, want_g, want_h, project, tv, tv + 9);
+          double2 *r2 = (double2 *)(rec + i * TERM_REC);
+          const int nst = want_h ? 27 : 5;
+#pragma unroll
+          for (int q = 0; q < 27; ++q)
+            if (q < nst) r2[q] = make_double2(tv[2 * q], tv[2 * q + 1]);
+        } else {
+          e_pair = pair_energy<KIND>(ty, x, eps, dhat, kappa);
+        }
+      }
+      if (energy && vscene) agg_scene_add(energy, live, scene, n_scene, e_pair, status);
+      e_acc += e_pair;
+    }
+  }
+  if (energy && !vscene) {
+    e_acc = wave_sum(e_acc);
+    if (lane == 0) s_e[wave] = e_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < NW; ++w) t += s_e[w];
+      if (t != 0.0) atomicAdd(energy, t);
+    }
+  }
+}
+
 eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const int32_t *pairs,
                            const int32_t *act, const int32_t *typ, const int64_t *d_count, int64_t max_count,
                            double dhat, double kappa, uint32_t flags, double *energy, double *grad,
                            const HessOut &h, hipStream_t s) {
   if (max_count == 0) return EIPC_OK;
+  // node ids are packed with 4 bits of slot in the expansion's sort
+  if (sc->n_node >= (1 << 27)) return set_err(c, EIPC_ERR_ARG, "n_node must be below 2^27");
   const bool want_g = (flags & EIPC_GRAD) && grad;
   const bool want_h = (flags & EIPC_HESS) && h.kind != 0;
-  double *gq = nullptr, *Xq = nullptr;
   const int64_t cap = max_count;
-  if (want_g) EIPC_TRY(ensure_t(c, kind == 0 ? B_PG_PT : B_PG_EE, (size_t)9 * cap, &gq));
-  if (want_h) EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)45 * cap, &Xq));
   const int4 *vid4 = nullptr;  // vertex ids of the sorted pairs
-  if (want_g || want_h) EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, cap, &act, &typ, &vid4, s));
+  double *rec = nullptr;
+  if (want_g || want_h) {
+    EIPC_TRY(sort_active(c, sc, kind, pairs, act, typ, d_count, cap, &act, &typ, &vid4, s));
+    EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)TERM_REC * cap, &rec));
+  }
+  const int blocks =
+      (int)std::max<int64_t>(1, std::min<int64_t>(grid_for(max_count, 64), (int64_t)c->wg_per_cu[0] * c->num_cu));
+  const int32_t *vsc = vscene_of(sc);
+  const int nsc = n_scene_of(sc);
   {
-    int blocks = (int)std::min<int64_t>(grid_for(max_count, BR_THREADS), (int64_t)c->wg_per_cu[0] * c->num_cu);
     ProfScope ps(c, kind == 0 ? K_BARRIER_PT : K_BARRIER_EE, s);
-    const int32_t *vsc = vscene_of(sc);
-    const int nsc = n_scene_of(sc);
     if (kind == 0)
-      k_pair_terms<0><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
-                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap, vsc, nsc,
-                                                     c->status, vid4);
+      k_pair_terms<0><<<blocks, TERMS_T, 0, s>>>(pairs, act, typ, vid4, d_count, cap, sc->faces, sc->edges, xs,
+                                              sc->x_rest, sc->n_vert, dhat, kappa, flags, want_g, want_h, energy,
+                                              rec, vsc, nsc, c->status);
     else
-      k_pair_terms<1><<<blocks, BR_THREADS, 0, s>>>(pairs, act, typ, d_count, sc->faces, sc->edges, xs, sc->x_rest,
-                                                     sc->n_vert, dhat, kappa, flags, energy, gq, Xq, cap, vsc, nsc,
-                                                     c->status, vid4);
+      k_pair_terms<1><<<blocks, TERMS_T, 0, s>>>(pairs, act, typ, vid4, d_count, cap, sc->faces, sc->edges, xs,
+                                              sc->x_rest, sc->n_vert, dhat, kappa, flags, want_g, want_h, energy,
+                                              rec, vsc, nsc, c->status);
     EIPC_HIP(c, hipGetLastError());
   }
   if (!want_g && !want_h) return EIPC_OK;
-  return launch_expand(c, sc, kind, vid4, d_count, cap, gq, Xq, want_g ? grad : nullptr, want_h ? h : HessOut{},
-                       s);
+  return launch_expand(c, sc, kind, vid4, d_count, cap, rec, want_g, want_h, want_g ? grad : nullptr,
+                       want_h ? h : HessOut{}, s);
 }
 
 eipc_status launch_expand(eipc_ctx *c, const eipc_scene *sc, int kind, const int4 *vid4, const int64_t *d_count,
-                          int64_t cap, const double *gq, const double *Xq, double *grad, const HessOut &h,
+                          int64_t cap, const double *rec, bool want_g, bool want_h, double *grad, const HessOut &h,
                           hipStream_t s) {
-  int blocks = (int)std::min<int64_t>(grid_for(cap, EX_T / 16), (int64_t)c->wg_per_cu[1] * c->num_cu);
+  if (sc->n_node >= (1 << 27)) return set_err(c, EIPC_ERR_ARG, "n_node must be below 2^27");
+  const int blocks =
+      (int)std::max<int64_t>(1, std::min<int64_t>(grid_for(cap, 64), (int64_t)c->wg_per_cu[1] * c->num_cu));
   ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
-  if (kind == 0)
-    k_expand16<0><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
-                                           cap, grad, h, c->status);
-  else
-    k_expand16<1><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, gq, Xq,
-                                           cap, grad, h, c->status);
+  k_expand<<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, rec, cap, want_g,
+                                   want_h, grad, h, c->status);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }
@@ -873,14 +1131,14 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, const double *__restrict__ val,
     const double *__restrict__ xs, const double *__restrict__ xvs, const double *__restrict__ x_rest, int n_vert,
     int n_node, double dhat, double kappa, uint32_t flags, double *out, double *out_off, uint32_t *status) {
-  __shared__ int s_gkey[LGT];
+  __shared__ uint32_t s_gkey[LGT];
   __shared__ double s_gval[LGT * 3];
   __shared__ int s_used;
-  LdsTables T{nullptr, nullptr, s_gkey, s_gval};
+  LdsTables T{s_gkey, s_gval};
   HessOut none{0, nullptr, nullptr, nullptr, 0};
   Acc A{T, none, n_node, out, status};
   const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
-  for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = -1;
+  for (int t = threadIdx.x; t < LGT; t += BR_THREADS) s_gkey[t] = 0xffffffffu;
   for (int t = threadIdx.x; t < LGT * 3; t += BR_THREADS) s_gval[t] = 0.0;
   __syncthreads();
   const int64_t n = *d_count;
@@ -902,7 +1160,6 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
         x[a] = load3(xs, n_vert, vid[a]);
         z[a] = load3(xvs, n_vert, vid[a]);
       }
-      const double s2 = type_value<KIND>(ty, x);
       double eps = 0.0;
       if (moll) {
         V3 r[4];
@@ -911,12 +1168,10 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
           r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
         eps = mollifier_eps(r);
       }
-      V3 Y[3];
-      y_basis<KIND>(x, Y);
-      double gE[9], HE[45], M[45];
-      energy_derivs<KIND>(ty, x, Y, s2, dhat, kappa, eps, gE, HE, true);
-      to_q_basis<KIND>(HE, M);
-      if (flags & EIPC_PROJECT) project_psd9(M);
+      // the Hessian of the barrier stage's per-class path
+      double gam[9], M[45];
+      pair_qterms<KIND>(pair_class<KIND>(ty, x, eps), ty, x, eps, dhat, kappa, false, true,
+                        (flags & EIPC_PROJECT) != 0, gam, M);
       // zeta = Q^T z, eta = X zeta
       double zeta[9];
 #pragma unroll
@@ -978,18 +1233,18 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
       if (threadIdx.x == 0) s_used = 0;
       __syncthreads();
       int cnt = 0;
-      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) cnt += s_gkey[t] != -1;
+      for (int t = threadIdx.x; t < LGT; t += BR_THREADS) cnt += s_gkey[t] != 0xffffffffu;
       if (cnt) atomicAdd(&s_used, cnt);
       __syncthreads();
     }
     if (last || s_used > LGT / 2) {
       for (int t = threadIdx.x; t < LGT; t += BR_THREADS) {
-        const int key = s_gkey[t];
+        const int key = (int)s_gkey[t];
         if (key != -1) {
           atomicAdd(&out[3 * (int64_t)key], s_gval[3 * t]);
           atomicAdd(&out[3 * (int64_t)key + 1], s_gval[3 * t + 1]);
           atomicAdd(&out[3 * (int64_t)key + 2], s_gval[3 * t + 2]);
-          s_gkey[t] = -1;
+          s_gkey[t] = 0xffffffffu;
           s_gval[3 * t] = s_gval[3 * t + 1] = s_gval[3 * t + 2] = 0.0;
         }
       }
@@ -1023,7 +1278,7 @@ eipc_status launch_hvp(eipc_ctx *c, const eipc_scene *sc, int kind, const double
 // per-pair inspection: type, s, e, g (12), H (12x12)
 // ---------------------------------------------------------------------------
 template <int KIND>
-__global__ void k_pair_eval(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
+__global__ __launch_bounds__(64) void k_pair_eval(int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
                             const int32_t *__restrict__ edges, const double *__restrict__ xs,
                             const double *__restrict__ x_rest, int n_vert, double dhat, double kappa,
                             uint32_t flags, int32_t *type, double *sq, double *e, double *g, double *H) {
@@ -1047,23 +1302,22 @@ __global__ void k_pair_eval(int64_t n, const int32_t *__restrict__ pairs, const 
       r[a] = V3{x_rest[3 * (int64_t)vid[a]], x_rest[3 * (int64_t)vid[a] + 1], x_rest[3 * (int64_t)vid[a] + 2]};
     eps = mollifier_eps(r);
   }
-  double gE[9], HE[45], M[45];
+  // the barrier stage's own per-class path; x-space gradient g_x = Q gamma
+  double gam[9], M[45];
   double ev = 0.0;
   if (active) {
-    V3 Y[3];
-    y_basis<KIND>(x, Y);
-    ev = energy_derivs<KIND>(ty, x, Y, s2, dhat, kappa, eps, gE, HE, true);
-    to_q_basis<KIND>(HE, M);
-    if (flags & EIPC_PROJECT) project_psd9(M);
+    const int cls = pair_class<KIND>(ty, x, eps);
+    ev = pair_qterms<KIND>(cls, ty, x, eps, dhat, kappa, true, true, (flags & EIPC_PROJECT) != 0, gam, M);
   }
   if (e) e[i] = ev;
   if (g) {
-    double gx[12];
-    if (active)
-      slot_grad<KIND>(gE, gx);
-    else
-      for (int t = 0; t < 12; ++t) gx[t] = 0.0;
-    for (int t = 0; t < 12; ++t) g[12 * i + t] = gx[t];
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+        if (active)
+          for (int al = 0; al < 3; ++al) acc += (0.5 * kS[a][al]) * gam[3 * al + c];
+        g[12 * i + 3 * a + c] = acc;
+      }
   }
   if (H) {
     for (int a = 0; a < 4; ++a)

@@ -119,7 +119,7 @@ struct eipc_ctx {
   int64_t hash_cap = 1 << 16;   // global block hash capacity (power of 2, grows)
   int num_cu = 256;
   double cell_scale = 2.0;       // broad-phase cell edge / mean item extent
-  int wg_per_cu[4] = {8, 2, 4, 4};  // grid sizes: pair terms, expansion, narrow, CCD
+  int wg_per_cu[4] = {1, 2, 4, 4};  // grid sizes: barrier stage, stored-terms expansion, narrow, CCD
   // append-mode broad phase work split [PT, EE]: 0 thread per query,
   // 1 thread per (query, cell), 2 wavefront per (query, cell), 3 bucket join
   int query_mode[2] = {1, 0};
@@ -265,8 +265,12 @@ eipc_status launch_dense_mirror(eipc_ctx *c, int n_node, double *dense, hipStrea
 // Reduction through W of per-pair gradients and Hessians in the Q basis
 // (SoA [9][cap] and [45][cap]) of min(*d_count, cap) pairs with vertex ids
 // vid4; grad or h.kind == 0 skip a part.
+// Per-pair terms record (doubles, 16-byte aligned): the Q-basis gradient
+// gamma [0, 9), the packed Q-basis Hessian X [9, 54), 2 unused.
+constexpr int TERM_REC = 56;
+// Reduction through W of per-pair term records (rec[i * TERM_REC + e]).
 eipc_status launch_expand(eipc_ctx *c, const eipc_scene *sc, int kind, const int4 *vid4, const int64_t *d_count,
-                          int64_t cap, const double *gq, const double *Xq, double *grad, const HessOut &h,
+                          int64_t cap, const double *rec, bool want_g, bool want_h, double *grad, const HessOut &h,
                           hipStream_t s);
 // BSR view of the hashed blocks.  nnzb_cap < 0: sized on the host
 // (synchronizes); else fixed capacity, the count only on the device

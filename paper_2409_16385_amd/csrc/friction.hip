@@ -153,7 +153,7 @@ template <int KIND>
 __global__ __launch_bounds__(FR_T) void k_friction_terms(
     int64_t n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
     const double *__restrict__ xs, const double *__restrict__ lag, double mu, double epsvh, double *energy,
-    double *__restrict__ gq, double *__restrict__ Xq, int4 *__restrict__ vid4, uint32_t *status) {
+    double *__restrict__ rec, bool want_g, bool want_h, int4 *__restrict__ vid4, uint32_t *status) {
   __shared__ double s_e[FR_T / 64];
   double e_acc = 0.0;
   for (int64_t base = (int64_t)blockIdx.x * FR_T; base < n; base += (int64_t)gridDim.x * FR_T) {
@@ -202,13 +202,14 @@ __global__ __launch_bounds__(FR_T) void k_friction_terms(
         for (int al = 0; al < 3; ++al)
           b[al] = 0.5 * (kS[0][al] * L[1] + kS[1][al] * L[2] + kS[2][al] * L[3] + kS[3][al] * L[4]);
       }
-      if (gq) {
+      double *rp = rec + (int64_t)TERM_REC * i;
+      if (want_g) {
 #pragma unroll
         for (int al = 0; al < 3; ++al)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) gq[(int64_t)(3 * al + c) * n + i] = b[al] * g3[c];
+          for (int c = 0; c < 3; ++c) rp[3 * al + c] = b[al] * g3[c];
       }
-      if (Xq) {
+      if (want_h) {
 #pragma unroll
         for (int al = 0; al < 3; ++al)
 #pragma unroll
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(FR_T) void k_friction_terms(
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
                 if (al == be && c < r) continue;
-                Xq[(int64_t)pidx(3 * al + r, 3 * be + c) * n + i] = b[al] * b[be] * K[3 * r + c];
+                rp[9 + pidx(3 * al + r, 3 * be + c)] = b[al] * b[be] * K[3 * r + c];
               }
       }
       if (!isfinite(e_acc)) atomicOr(status, ST_NONFINITE);
@@ -261,24 +262,23 @@ eipc_status launch_friction(eipc_ctx *c, const eipc_scene *sc, int kind, const d
                             const HessOut &h, hipStream_t s) {
   if (n == 0) return EIPC_OK;
   const bool want_g = grad != nullptr, want_h = h.kind != 0;
-  double *gq = nullptr, *Xq = nullptr;
+  double *rec = nullptr;
   int4 *vid4;
-  if (want_g) EIPC_TRY(ensure_t(c, kind == 0 ? B_PG_PT : B_PG_EE, (size_t)9 * n, &gq));
-  if (want_h) EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)45 * n, &Xq));
+  if (want_g || want_h) EIPC_TRY(ensure_t(c, kind == 0 ? B_PX_PT : B_PX_EE, (size_t)TERM_REC * n, &rec));
   EIPC_TRY(ensure_t(c, kind == 0 ? B_SVID : B_SVID_EE, (size_t)n, &vid4));
   const int blocks = (int)std::min<int64_t>(grid_for(n, FR_T), 8 * (int64_t)c->num_cu);
   if (kind == 0)
-    k_friction_terms<0><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, lag, mu, epsvh, energy, gq, Xq,
-                                                vid4, c->status);
+    k_friction_terms<0><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, lag, mu, epsvh, energy, rec,
+                                                want_g, want_h, vid4, c->status);
   else
-    k_friction_terms<1><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, lag, mu, epsvh, energy, gq, Xq,
-                                                vid4, c->status);
+    k_friction_terms<1><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, lag, mu, epsvh, energy, rec,
+                                                want_g, want_h, vid4, c->status);
   EIPC_HIP(c, hipGetLastError());
   if (!want_g && !want_h) return EIPC_OK;
   int64_t *cnt = c->counters + 12 + kind;
   k_set_count<<<1, 64, 0, s>>>(cnt, n);
   EIPC_HIP(c, hipGetLastError());
-  return launch_expand(c, sc, kind, vid4, cnt, n, gq, Xq, grad, h, s);
+  return launch_expand(c, sc, kind, vid4, cnt, n, rec, want_g, want_h, grad, h, s);
 }
 
 }  // namespace eipc

@@ -465,11 +465,11 @@ __device__ __forceinline__ Barrier barrier_s(double s, double dhat) {
 // Energy derivatives in the Y basis: e = kappa m(c) bt(s) (m = 1 without
 // mollifier).  gE[9], HE packed [45].  eps_x <= 0 disables the mollifier.
 // Returns the energy.
+// (gs, Hs: the s-derivatives in the Y basis)
 template <int KIND>
-__device__ __forceinline__ double energy_derivs(int type, const V3 *x, const V3 *Y, double s, double dhat,
-                                                double kappa, double eps_x, double *gE, double *HE, bool want_h) {
-  double gs[9], Hs[45];
-  s_derivs<KIND>(type, x, gs, Hs);
+__device__ __forceinline__ double energy_derivs_gs(const double *gs, const double *Hs, const V3 *Y, double s,
+                                                   double dhat, double kappa, double eps_x, double *gE, double *HE,
+                                                   bool want_h) {
   Barrier br = barrier_s(s, dhat);
   double m = 1.0, m1 = 0.0, m2 = 0.0;
   double gc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -512,6 +512,14 @@ __device__ __forceinline__ double energy_derivs(int type, const V3 *x, const V3 
       }
   }
   return e;
+}
+
+template <int KIND>
+__device__ __forceinline__ double energy_derivs(int type, const V3 *x, const V3 *Y, double s, double dhat,
+                                                double kappa, double eps_x, double *gE, double *HE, bool want_h) {
+  double gs[9], Hs[45];
+  s_derivs<KIND>(type, x, gs, Hs);
+  return energy_derivs_gs<KIND>(gs, Hs, Y, s, dhat, kappa, eps_x, gE, HE, want_h);
 }
 
 // M = G^T H G (packed), G = (T Q) (x) I3 with integer entries gcoef.
@@ -567,11 +575,17 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y;
 }
 
-template <int P, int Q>
+// packed index of the upper triangle of an N x N symmetric matrix
+template <int N>
+__host__ __device__ constexpr int pidxn(int i, int j) {
+  return i <= j ? i * N - (i * (i - 1)) / 2 + (j - i) : j * N - (j * (j - 1)) / 2 + (i - j);
+}
+
+template <int N, int P, int Q>
 __device__ __forceinline__ void jacobi_rot(double *a, double *v, double thr) {
-  const double apq = a[pidx(P, Q)];
-  const double app = a[pidx(P, P)];
-  const double aqq = a[pidx(Q, Q)];
+  const double apq = a[pidxn<N>(P, Q)];
+  const double app = a[pidxn<N>(P, P)];
+  const double aqq = a[pidxn<N>(Q, Q)];
   const double h = 0.5 * (aqq - app);
   const double ss = h * h + apq * apq;
   // sqrt(ss) as ss / sqrt(ss); the smallest normal double keeps ss = 0 at 0
@@ -581,73 +595,77 @@ __device__ __forceinline__ void jacobi_rot(double *a, double *v, double thr) {
   const double t = (fabs(apq) > thr && den != 0.0 && fabs(den) < INFINITY) ? apq * rcp_nr(den) : 0.0;
   const double c = rsqrt_nr(1.0 + t * t);
   const double s = t * c;
-  a[pidx(P, P)] = app - t * apq;
-  a[pidx(Q, Q)] = aqq + t * apq;
-  a[pidx(P, Q)] = 0.0;
+  a[pidxn<N>(P, P)] = app - t * apq;
+  a[pidxn<N>(Q, Q)] = aqq + t * apq;
+  a[pidxn<N>(P, Q)] = 0.0;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
+  for (int k = 0; k < N; ++k) {
     if (k == P || k == Q) continue;
-    const double akp = a[pidx(k, P)], akq = a[pidx(k, Q)];
-    a[pidx(k, P)] = c * akp - s * akq;
-    a[pidx(k, Q)] = s * akp + c * akq;
+    const double akp = a[pidxn<N>(k, P)], akq = a[pidxn<N>(k, Q)];
+    a[pidxn<N>(k, P)] = c * akp - s * akq;
+    a[pidxn<N>(k, Q)] = s * akp + c * akq;
   }
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const double vkp = v[k * 9 + P], vkq = v[k * 9 + Q];
-    v[k * 9 + P] = c * vkp - s * vkq;
-    v[k * 9 + Q] = s * vkp + c * vkq;
+  for (int k = 0; k < N; ++k) {
+    const double vkp = v[k * N + P], vkq = v[k * N + Q];
+    v[k * N + P] = c * vkp - s * vkq;
+    v[k * N + Q] = s * vkp + c * vkq;
   }
 }
 
-template <int P, int Q>
+template <int N, int P, int Q>
 __device__ __forceinline__ void jacobi_sweep_from(double *a, double *v, double thr) {
-  if constexpr (P < 8) {
-    jacobi_rot<P, Q>(a, v, thr);
-    if constexpr (Q + 1 < 9)
-      jacobi_sweep_from<P, Q + 1>(a, v, thr);
-    else if constexpr (P + 2 < 9)
-      jacobi_sweep_from<P + 1, P + 2>(a, v, thr);
+  if constexpr (P < N - 1) {
+    jacobi_rot<N, P, Q>(a, v, thr);
+    if constexpr (Q + 1 < N)
+      jacobi_sweep_from<N, P, Q + 1>(a, v, thr);
+    else if constexpr (P + 2 < N)
+      jacobi_sweep_from<N, P + 1, P + 2>(a, v, thr);
   }
 }
 
-// In place: a <- V max(L, 0) V^T, cyclic Jacobi until the off-diagonal mass
-// is below 1e-30 of the total (relative off-norm 1e-15), at most 16 sweeps.
-// The loop count is uniform over the wavefront.
-__device__ __forceinline__ void project_psd9(double *a) {
-  double v[81];
+// In place on a packed N x N symmetric matrix: a <- V max(L, 0) V^T,
+// cyclic Jacobi until the off-diagonal mass is below 1e-30 of the total
+// (relative off-norm 1e-15), at most 16 sweeps.  The loop count is uniform
+// over the wavefront.
+template <int N>
+__device__ __forceinline__ void project_psd(double *a) {
+  double v[N * N];
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < 9; ++j) v[i * 9 + j] = (i == j) ? 1.0 : 0.0;
+    for (int j = 0; j < N; ++j) v[i * N + j] = (i == j) ? 1.0 : 0.0;
   double fro2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = i; j < 9; ++j) fro2 += (i == j ? 1.0 : 2.0) * a[pidx(i, j)] * a[pidx(i, j)];
+    for (int j = i; j < N; ++j) fro2 += (i == j ? 1.0 : 2.0) * a[pidxn<N>(i, j)] * a[pidxn<N>(i, j)];
   const double thr = 1e-20 * sqrt(fro2);
   for (int sweep = 0; sweep < 16; ++sweep) {
     double off = 0.0;
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < N; ++i)
 #pragma unroll
-      for (int j = i + 1; j < 9; ++j) off += a[pidx(i, j)] * a[pidx(i, j)];
+      for (int j = i + 1; j < N; ++j) off += a[pidxn<N>(i, j)] * a[pidxn<N>(i, j)];
     const bool done = !(off > 1e-30 * fro2);
     if (__all(done)) break;
-    jacobi_sweep_from<0, 1>(a, v, thr);
+    jacobi_sweep_from<N, 0, 1>(a, v, thr);
   }
-  double lam[9];
+  double lam[N];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) lam[k] = fmax(a[pidx(k, k)], 0.0);
+  for (int k = 0; k < N; ++k) lam[k] = fmax(a[pidxn<N>(k, k)], 0.0);
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = i; j < 9; ++j) {
+    for (int j = i; j < N; ++j) {
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc += v[i * 9 + k] * lam[k] * v[j * 9 + k];
-      a[pidx(i, j)] = acc;
+      for (int k = 0; k < N; ++k) acc += v[i * N + k] * lam[k] * v[j * N + k];
+      a[pidxn<N>(i, j)] = acc;
     }
 }
+
+__device__ __forceinline__ void project_psd9(double *a) { project_psd<9>(a); }
 
 // 3x3 block (a, b) of H_x = Q X Q^T from X packed in the Q basis.
 __device__ __forceinline__ void x_block(const double *X, int a, int b, double *B) {
@@ -701,6 +719,313 @@ __device__ __forceinline__ double mollifier_eps(const V3 *r) {
   V3 u = xsub(r[1], r[0]);
   V3 v = xsub(r[3], r[2]);
   return 1e-3 * xdot(u, u) * xdot(v, v);
+}
+
+// ---------------------------------------------------------------------------
+// Pair terms in the Q basis by class of distance type.
+//
+// With xi the Q-basis coordinates of the pair (x_a = sum_alpha Q[a][alpha]
+// xi_alpha + a translation), a type's local vectors are
+//   y_j = x[plus_j] - x[minus_j] = sum_alpha E[j][alpha] xi_alpha,
+//   E[j][alpha] = (S[plus_j][alpha] - S[minus_j][alpha]) / 2 in {-1, 0, 1},
+// so the Q-basis gradient is gamma = (E^T x I3) g_l and the Hessian
+// X = (E^T x I3) H_l (E x I3), with g_l, H_l the energy's derivatives in
+// the local vectors.  E E^T is the Gram matrix of the types' difference
+// rows over the four slots, the same for every type of a class ([2] for
+// point-point, [[2,1],[1,2]] for point-line).  With E E^T = L L^T the rows
+// of F = L^{-1} E are orthonormal, so F^T x I3 is an isometry and
+//   X = (F^T x I3) P (F x I3),  P = (L^T x I3) H_l (L x I3),
+//   proj(X) = (F^T x I3) proj(P) (F x I3).
+// A point-point pair's H_l = a y y^T + b I is projected in closed form
+// (eigenvalues a s + b along y, b across), a point-line pair's 6x6 P by
+// Jacobi, and an interior pair's 9x9 X by Jacobi.  Mollified edge-edge
+// pairs (whose mollifier involves all four slots) take the general path.
+// ---------------------------------------------------------------------------
+enum { CLS_PP = 0, CLS_PL = 1, CLS_TRI = 2, CLS_GEN = 3 };
+
+template <int KIND>
+__host__ __device__ constexpr int type_fn(int type) {
+  return KIND == 0 ? (type < 3 ? FN_PP : (type < 6 ? FN_PL : FN_TRI))
+                   : (type < 4 ? FN_PP : (type < 8 ? FN_PL : FN_TRI));
+}
+
+// plus/minus slots of the first two local vectors of each point-point and
+// point-line type, 2 bits each, 8 bits per type
+template <int KIND>
+__host__ __device__ constexpr uint64_t slot_codes() {
+  uint64_t r = 0;
+  const int nt = KIND == 0 ? 6 : 8;
+  for (int t = 0; t < nt; ++t) {
+    const TypeDef d = KIND == 0 ? kPT[t] : kEE[t];
+    const uint64_t c = (uint64_t)d.plus[0] | ((uint64_t)d.minus[0] << 2) | ((uint64_t)d.plus[1] << 4) |
+                       ((uint64_t)d.minus[1] << 6);
+    r |= c << (8 * t);
+  }
+  return r;
+}
+
+template <int KIND>
+__host__ __device__ constexpr bool type_fn_matches_tables() {
+  const int nt = KIND == 0 ? 7 : 9;
+  for (int t = 0; t < nt; ++t)
+    if ((KIND == 0 ? kPT[t].fn : kEE[t].fn) != type_fn<KIND>(t)) return false;
+  return true;
+}
+static_assert(type_fn_matches_tables<0>() && type_fn_matches_tables<1>(), "type classes");
+
+// S[a][alpha] (Hadamard signs) for a runtime slot a
+__host__ __device__ constexpr int qsign(int a, int al) {
+  return al == 0 ? ((a & 2) ? -1 : 1) : (al == 1 ? ((a & 1) ? -1 : 1) : ((a & 2) ? -1 : 1) * ((a & 1) ? -1 : 1));
+}
+__host__ __device__ constexpr bool qsign_matches() {
+  for (int a = 0; a < 4; ++a)
+    for (int al = 0; al < 3; ++al)
+      if (qsign(a, al) != kS[a][al]) return false;
+  return true;
+}
+static_assert(qsign_matches(), "Hadamard signs");
+
+__device__ __forceinline__ V3 pick4(const V3 *x, int i) {
+  const V3 a = (i & 1) ? x[1] : x[0];
+  const V3 b = (i & 1) ? x[3] : x[2];
+  return (i & 2) ? b : a;
+}
+
+__device__ __forceinline__ void e_row(int p, int m, double *E) {
+#pragma unroll
+  for (int al = 0; al < 3; ++al) E[al] = 0.5 * (double)(qsign(p, al) - qsign(m, al));
+}
+
+// class of a pair: its type's function, or the general path when the
+// edge-edge mollifier is active (the same test as in energy_derivs_gs)
+template <int KIND>
+__device__ __forceinline__ int pair_class(int type, const V3 *x, double eps_x) {
+  if constexpr (KIND == 1) {
+    if (eps_x > 0.0) {
+      V3 Y[3];
+      y_basis<1>(x, Y);
+      const V3 n = xcross(Y[1], Y[2]);
+      if (xdot(n, n) < eps_x) return CLS_GEN;
+    }
+  }
+  return type_fn<KIND>(type);
+}
+
+template <int KIND>
+__device__ __forceinline__ void grad_to_q(const double *gE, double *gam) {
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) {
+        const int g = gcoef(KIND, J, al);
+        if (g != 0) acc += g * gE[3 * J + c];
+      }
+      gam[3 * al + c] = acc;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ double terms_pp(int type, const V3 *x, double dhat, double kappa, bool want_g,
+                                           bool want_h, bool project, double *gam, double *X) {
+  const uint32_t code = (uint32_t)(slot_codes<KIND>() >> (8 * type)) & 0xffu;
+  const int p0 = code & 3, m0 = (code >> 2) & 3;
+  const V3 y = xsub(pick4(x, p0), pick4(x, m0));
+  const double s = xdot(y, y);
+  const Barrier br = barrier_s(s, dhat);
+  double E[3];
+  e_row(p0, m0, E);
+  if (want_g) {
+    const double g[3] = {kappa * (br.bs1 * (2.0 * y.x)), kappa * (br.bs1 * (2.0 * y.y)),
+                         kappa * (br.bs1 * (2.0 * y.z))};
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gam[3 * al + c] = E[al] * g[c];
+  }
+  if (want_h) {
+    // H_l = c1 y y^T + c0 I
+    const double a = kappa * (4.0 * br.bs2), b = kappa * (2.0 * br.bs1);
+    double c0 = b, c1 = a;
+    if (project) {
+      const double l1 = fmax(a * s + b, 0.0), l2 = fmax(b, 0.0);
+      c0 = l2;
+      c1 = (l1 - l2) / s;
+    }
+    const double yv[3] = {y.x, y.y, y.z};
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int be = al; be < 3; ++be)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (al == be && c < r) continue;
+            const double hl = c1 * yv[r] * yv[c] + (r == c ? c0 : 0.0);
+            X[pidx(3 * al + r, 3 * be + c)] = (E[al] * E[be]) * hl;
+          }
+  }
+  return kappa * br.b;
+}
+
+template <int KIND>
+__device__ __forceinline__ double terms_pl(int type, const V3 *x, double dhat, double kappa, bool want_g,
+                                           bool want_h, bool project, double *gam, double *X) {
+  const uint32_t code = (uint32_t)(slot_codes<KIND>() >> (8 * type)) & 0xffu;
+  const int p0 = code & 3, m0 = (code >> 2) & 3, p1 = (code >> 4) & 3, m1 = (code >> 6) & 3;
+  V3 y[3];
+  y[0] = xsub(pick4(x, p0), pick4(x, m0));
+  y[1] = xsub(pick4(x, p1), pick4(x, m1));
+  y[2] = V3{0.0, 0.0, 0.0};
+  double s;
+  {
+#pragma clang fp contract(off)
+    const V3 cr = xcross(y[0], y[1]);
+    s = xdot(cr, cr) / xdot(y[1], y[1]);
+  }
+  const Barrier br = barrier_s(s, dhat);
+  if (!want_g && !want_h) return kappa * br.b;
+  Local L;
+  local_derivs<FN_PL>(y, L);
+  double E[2][3];
+  e_row(p0, m0, E[0]);
+  e_row(p1, m1, E[1]);
+  if (want_g) {
+    double gl[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) gl[i] = kappa * (br.bs1 * L.g[i]);
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gam[3 * al + c] = E[0][al] * gl[c] + E[1][al] * gl[3 + c];
+  }
+  if (want_h) {
+    double H6[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i; j < 6; ++j) H6[pidxn<6>(i, j)] = kappa * (br.bs2 * L.g[i] * L.g[j] + br.bs1 * L.H[i * 9 + j]);
+    double W[2][3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      W[0][al] = E[0][al];
+      W[1][al] = E[1][al];
+    }
+    if (project) {
+      // Gram [[2,1],[1,2]] = L L^T, L = [[l00, 0], [l10, l11]]
+      constexpr double l00 = 1.4142135623730951, l10 = 0.7071067811865476, l11 = 1.2247448713915890;
+      double P[21];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double h00 = H6[pidxn<6>(r, c)], h11 = H6[pidxn<6>(3 + r, 3 + c)];
+          const double h01 = H6[pidxn<6>(r, 3 + c)], h10 = H6[pidxn<6>(3 + r, c)];
+          if (c >= r) {
+            P[pidxn<6>(r, c)] = l00 * l00 * h00 + l00 * l10 * (h01 + h10) + l10 * l10 * h11;
+            P[pidxn<6>(3 + r, 3 + c)] = l11 * l11 * h11;
+          }
+          P[pidxn<6>(r, 3 + c)] = l00 * l11 * h01 + l10 * l11 * h11;
+        }
+      project_psd<6>(P);
+#pragma unroll
+      for (int i = 0; i < 21; ++i) H6[i] = P[i];
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        W[0][al] = E[0][al] * (1.0 / l00);
+        W[1][al] = (E[1][al] - l10 * W[0][al]) * (1.0 / l11);
+      }
+    }
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+      for (int be = al; be < 3; ++be)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (al == be && c < r) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+              for (int k = 0; k < 2; ++k) acc += (W[j][al] * W[k][be]) * H6[pidxn<6>(3 * j + r, 3 * k + c)];
+            X[pidx(3 * al + r, 3 * be + c)] = acc;
+          }
+  }
+  return kappa * br.b;
+}
+
+template <int KIND>
+__device__ __forceinline__ double terms_tri(const V3 *x, double dhat, double kappa, bool want_g, bool want_h,
+                                            bool project, double *gam, double *X) {
+  constexpr int TT = KIND == 0 ? (int)PT_T : (int)EE_AB;
+  const double s = type_value_t<KIND, TT>(x);
+  if (!want_g && !want_h) return kappa * barrier_s(s, dhat).b;
+  double gs[9], Hs[45], gE[9], HE[45];
+  s_derivs_typed<KIND, TT>(x, gs, Hs);
+  V3 Y[3];
+  y_basis<KIND>(x, Y);
+  const double e = energy_derivs_gs<KIND>(gs, Hs, Y, s, dhat, kappa, 0.0, gE, HE, want_h);
+  if (want_g) grad_to_q<KIND>(gE, gam);
+  if (want_h) {
+    to_q_basis<KIND>(HE, X);
+    if (project) project_psd<9>(X);
+  }
+  return e;
+}
+
+// any type, with the mollifier when eps_x > 0
+template <int KIND>
+__device__ __forceinline__ double terms_gen(int type, const V3 *x, double eps_x, double dhat, double kappa,
+                                            bool want_g, bool want_h, bool project, double *gam, double *X) {
+  const double s = type_value<KIND>(type, x);
+  V3 Y[3];
+  y_basis<KIND>(x, Y);
+  double gE[9], HE[45];
+  const double e = energy_derivs<KIND>(type, x, Y, s, dhat, kappa, eps_x, gE, HE, want_h);
+  if (want_g) grad_to_q<KIND>(gE, gam);
+  if (want_h) {
+    to_q_basis<KIND>(HE, X);
+    if (project) project_psd<9>(X);
+  }
+  return e;
+}
+
+// energy only
+template <int KIND>
+__device__ __forceinline__ double pair_energy(int type, const V3 *x, double eps_x, double dhat, double kappa) {
+  const double s = type_value<KIND>(type, x);
+  const Barrier br = barrier_s(s, dhat);
+  double m = 1.0;
+  if constexpr (KIND == 1) {
+    if (eps_x > 0.0) {
+      V3 Y[3];
+      y_basis<1>(x, Y);
+      const V3 n = xcross(Y[1], Y[2]);
+      const double c = xdot(n, n);
+      if (c < eps_x) {
+        const double r = c / eps_x;
+        m = (2.0 - r) * r;
+      }
+    }
+  }
+  return kappa * (m * br.b);
+}
+
+// Energy, Q-basis gradient gamma[9] and Hessian X (packed, 45) of one pair
+// of class cls.  Lanes of a wavefront that share the class share the path.
+template <int KIND>
+__device__ __forceinline__ double pair_qterms(int cls, int type, const V3 *x, double eps_x, double dhat,
+                                              double kappa, bool want_g, bool want_h, bool project, double *gam,
+                                              double *X) {
+  if (cls == CLS_PP) return terms_pp<KIND>(type, x, dhat, kappa, want_g, want_h, project, gam, X);
+  if (cls == CLS_PL) return terms_pl<KIND>(type, x, dhat, kappa, want_g, want_h, project, gam, X);
+  if (cls == CLS_TRI) return terms_tri<KIND>(x, dhat, kappa, want_g, want_h, project, gam, X);
+  return terms_gen<KIND>(type, x, eps_x, dhat, kappa, want_g, want_h, project, gam, X);
 }
 
 // ---------------------------------------------------------------------------

@@ -81,7 +81,7 @@ def test_profiling_mode_2_gives_the_same_step(ctx):
     finally:
         b.ctx.profile(False)
     assert b.status() in (E.binding.OK, E.binding.WARN_CCD_CAPPED)
-    assert prof["ccd_pt"][1] == 1 and prof["ccd_ee"][1] == 1 and prof["expand_ee"][1] == 1
+    assert prof["ccd_pt"][1] == 1 and prof["ccd_ee"][1] == 1 and prof["barrier_ee"][1] == 1
     _compare(b, _plain(ctx, "config2"))
     assert E.binding._load().eipc_profile(b.ctx._h, 3) == E.binding.ERR_ARG
 
