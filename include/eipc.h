@@ -58,7 +58,12 @@ enum {
   EIPC_GRAD = 2,    /* reduced gradient W^T g */
   EIPC_HESS = 4,    /* reduced Hessian W^T H W */
   EIPC_PROJECT = 8, /* use the per-pair PSD projection of H (projected Newton, Sec. III-C) */
-  EIPC_MOLLIFY = 16 /* EE mollifier for near-parallel edges (needs x_rest: EIPC_ERR_ARG without it) */
+  EIPC_MOLLIFY = 16, /* EE mollifier for near-parallel edges (needs x_rest: EIPC_ERR_ARG without it) */
+  /* Alternative formulation: the log barrier of Eq. 7 written in the
+   * squared distance, b(s) = -(s - dhat^2)^2 ln(s / dhat^2) with s = d^2
+   * (the same active set; the friction normal force becomes
+   * kappa m |db/dd| = kappa m 2 d |db/ds|). */
+  EIPC_SQDIST = 32
 };
 
 typedef struct eipc_ctx eipc_ctx;
@@ -328,6 +333,27 @@ eipc_status eipc_step_pairs(eipc_ctx *ctx, int32_t which, int32_t *out, int64_t 
  * candidate lists and the rounding order of sums.  A plan must be made
  * again after changing them. */
 eipc_status eipc_set_tuning(eipc_ctx *ctx, double cell_scale, const int32_t wg_per_cu[4], int32_t query_cells);
+
+/* Per-pair step bound of the CCD (Sec. III-C; the paper names a conservative
+ * advancement CCD and cites C2A for it) used by every call of this context
+ * that computes one (eipc_ccd_max_step, eipc_ccd_toi, eipc_contact_step;
+ * a plan keeps working):
+ *   EIPC_CCD_ADDITIVE (default): additive CCD, each step (0.9 of) the
+ *     distance over lp, the largest possible closing speed (the point's
+ *     speed plus the fastest triangle vertex, or the fastest vertex of each
+ *     edge, after removing the mean motion).
+ *   EIPC_CCD_CLOSEST_DIRECTION: the same steps with lp replaced, at every
+ *     iterate, by the closing speed along the closest direction n (from the
+ *     second primitive's closest point to the first's),
+ *     mu = max_{second} n.p - min_{first} n.p <= lp: both primitives stay on
+ *     their sides of the separating planes through the closest points, so
+ *     the distance cannot fall faster than mu.  mu <= 0 bounds the pair by
+ *     t_max.  Fewer, longer steps where the motion is mostly tangential.
+ * Both bounds are conservative; their values differ.  EIPC_ERR_ARG for
+ * another method. */
+#define EIPC_CCD_ADDITIVE 0
+#define EIPC_CCD_CLOSEST_DIRECTION 1
+eipc_status eipc_set_ccd_method(eipc_ctx *ctx, int32_t method);
 
 /* ---- dense reduced Newton system (adjoint of a converged step) ---- */
 

@@ -15,7 +15,7 @@ import numpy as np
 
 from . import build as _build
 
-ENERGY, GRAD, HESS, PROJECT, MOLLIFY = 1, 2, 4, 8, 16
+ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST = 1, 2, 4, 8, 16, 32
 OK, INACTIVE, ERR_CAPACITY, ERR_INTERSECTING, ERR_NONFINITE = 0, 1, -2, -3, -5
 PT_TYPES = ["P-T0", "P-T1", "P-T2", "P-E0", "P-E1", "P-E2", "P-T"]
 EE_TYPES = ["EA0-EB0", "EA0-EB1", "EA1-EB0", "EA1-EB1", "EA-EB0", "EA-EB1",
@@ -54,6 +54,8 @@ def lib():
             "or_barrier": (None, [_D, _D, _P, _P, _P]),
             "or_mollifier": (None, [_D, _D, _P, _P, _P]),
             "or_pair_eval": (C.c_int, [C.c_int, _P, _P, _D, _D, _P, _P, _P, _P, _P]),
+            "or_pair_eval_f": (C.c_int, [C.c_int, _P, _P, _D, _D, C.c_uint32, _P, _P, _P, _P, _P]),
+            "or_barrier_sq": (None, [_D, _D, _P, _P, _P]),
             "or_project_psd": (C.c_int, [C.c_int, _P, _P]),
             "or_barrier_reduce": (C.c_int, [_P, _P, _P, _I64, _P, _I64, _D, _D, C.c_uint32,
                                             _P, _P, _P, _P]),
@@ -61,10 +63,13 @@ def lib():
                                          _P, _P, _P, _P]),
             "or_accd_pair": (_D, [C.c_int, _P, _P, _D, _D, _I64, _P]),
             "or_ccd_toi": (C.c_int, [_P, _P, _P, C.c_int, _P, _I64, _D, _D, _I64, _P, _P]),
+            "or_ccd_toi_m": (C.c_int, [_P, _P, _P, C.c_int, _P, _I64, _D, _D, _I64, C.c_int, _P, _P]),
+            "or_c2a_pair": (_D, [C.c_int, _P, _P, _D, _D, _I64, _P]),
             "or_ccd_max_step": (C.c_int, [_P, _P, _P, _P, _D, _D, _D, _I64, _P, _P, _P]),
             "or_narrow": (None, [_P, _P, C.c_int, _P, _I64, _D, _P, _P, _P]),
             "or_friction_f": (None, [_D, _D, _P, _P, _P]),
             "or_friction_lag": (C.c_int, [C.c_int, _P, _P, _D, _D, _P]),
+            "or_friction_lag_f": (C.c_int, [C.c_int, _P, _P, _D, _D, C.c_uint32, _P]),
             "or_friction_pair": (None, [_P, _P, _D, _D, _P, _P, _P]),
             "or_friction_lag_list": (C.c_int, [_P, _P, C.c_int, _P, _I64, _D, _D, C.c_uint32, _P]),
             "or_friction_reduce": (C.c_int, [_P, _P, _P, _I64, _P, _P, _I64, _P, _D, _D, _P, _P, _P]),
@@ -196,8 +201,16 @@ def mollifier(c, eps):
     return out[0], out[1], out[2]
 
 
-def pair_eval(kind, x12, dhat, kappa, rest12=None):
-    """Returns (status, type, s, e, g[12], H[12,12]) with the true Hessian."""
+def barrier_sq(s, shat):
+    """(b, db/ds, d2b/ds2) of the squared-distance barrier at s."""
+    out = np.zeros(3)
+    lib().or_barrier_sq(float(s), float(shat), _ptr(out[0:]), _ptr(out[1:]), _ptr(out[2:]))
+    return out[0], out[1], out[2]
+
+
+def pair_eval(kind, x12, dhat, kappa, rest12=None, flags=0):
+    """Returns (status, type, s, e, g[12], H[12,12]) with the true Hessian
+    (flags: SQDIST for the squared-distance barrier)."""
     x12 = _f64(x12).reshape(12)
     r12 = None if rest12 is None else _f64(rest12).reshape(12)
     t = C.c_int()
@@ -205,8 +218,8 @@ def pair_eval(kind, x12, dhat, kappa, rest12=None):
     e = np.zeros(1)
     g = np.zeros(12)
     H = np.zeros((12, 12))
-    st = lib().or_pair_eval(kind, _ptr(x12), _ptr(r12), dhat, kappa, C.byref(t), _ptr(s),
-                            _ptr(e), _ptr(g), _ptr(H))
+    st = lib().or_pair_eval_f(kind, _ptr(x12), _ptr(r12), dhat, kappa, flags, C.byref(t), _ptr(s),
+                              _ptr(e), _ptr(g), _ptr(H))
     return st, t.value, s[0], e[0], g, H
 
 
@@ -254,14 +267,24 @@ def accd_pair(kind, x12, p12, s=0.1, t_c=1.0, max_iter=100000):
     return t, it.value
 
 
-def ccd_toi(sc, x, p, kind, pairs, s=0.1, t_c=1.0, max_iter=100000):
+def c2a_pair(kind, x12, p12, s=0.1, t_c=1.0, max_iter=100000):
+    """Conservative advancement along the closest direction (method 1)."""
+    x12 = _f64(x12).reshape(12)
+    p12 = _f64(p12).reshape(12)
+    it = _I64()
+    t = lib().or_c2a_pair(kind, _ptr(x12), _ptr(p12), s, t_c, max_iter, C.byref(it))
+    return t, it.value
+
+
+def ccd_toi(sc, x, p, kind, pairs, s=0.1, t_c=1.0, max_iter=100000, method=0):
+    """Per-pair step bounds; method 0 additive CCD, 1 closest-direction advancement."""
     sc_ = scene(sc)
     x, p = _f64(x), _f64(p)
     pairs = _i32(pairs).reshape(-1, 2)
     t = np.zeros(len(pairs))
     it = np.zeros(len(pairs), dtype=np.int64)
-    lib().or_ccd_toi(sc_.ref, _ptr(x), _ptr(p), kind, _ptr(pairs), len(pairs), s, t_c, max_iter,
-                     _ptr(t), _ptr(it))
+    lib().or_ccd_toi_m(sc_.ref, _ptr(x), _ptr(p), kind, _ptr(pairs), len(pairs), s, t_c, max_iter, int(method),
+                       _ptr(t), _ptr(it))
     return t, it
 
 
@@ -400,11 +423,12 @@ def _bsr_sum(n_rows, parts):
     return np.cumsum(rowptr).astype(np.int32), (uk % max(n_rows, 1)).astype(np.int32), out
 
 
-def ccd_toi_threads(sc, x, p, kind, pairs, s=0.1, t_c=1.0, max_iter=100000, nthreads=None):
+def ccd_toi_threads(sc, x, p, kind, pairs, s=0.1, t_c=1.0, max_iter=100000, nthreads=None, method=0):
     """ccd_toi over slices of the pairs on several threads (same values)."""
     pairs = _i32(pairs).reshape(-1, 2)
     nthreads = nthreads or threads()
-    parts = _pmap(lambda r: ccd_toi(sc, x, p, kind, pairs[r[0]:r[1]], s=s, t_c=t_c, max_iter=max_iter),
+    parts = _pmap(lambda r: ccd_toi(sc, x, p, kind, pairs[r[0]:r[1]], s=s, t_c=t_c, max_iter=max_iter,
+                                    method=method),
                   _slices(len(pairs), 8 * nthreads), nthreads)
     if not parts:
         return np.zeros(0), np.zeros(0, dtype=np.int64)
@@ -443,11 +467,11 @@ def friction_f(y, epsvh):
     return out[0], out[1], out[2]
 
 
-def friction_lag(kind, x12, dhat, kappa, rest12=None):
+def friction_lag(kind, x12, dhat, kappa, rest12=None, flags=0):
     x12 = _f64(x12).reshape(12)
     r12 = None if rest12 is None else _f64(rest12).reshape(12)
     lag = np.zeros(LAG)
-    st = lib().or_friction_lag(kind, _ptr(x12), _ptr(r12), dhat, kappa, _ptr(lag))
+    st = lib().or_friction_lag_f(kind, _ptr(x12), _ptr(r12), dhat, kappa, flags, _ptr(lag))
     return st, lag
 
 

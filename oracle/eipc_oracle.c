@@ -494,6 +494,22 @@ void or_barrier(double d, double dhat, double *b, double *b1, double *b2) {
   *b2 = -2.0 * lr - 4.0 * dm / d + (dm * dm) / (d * d);
 }
 
+/* Alternative formulation: the same log barrier written in the squared
+ * distance, b(s) = -(s - shat)^2 ln(s / shat) with s = d^2, shat = dhat^2
+ * (the form IPC implementations evaluate; Eq. 7 states it in d).  The
+ * active set is the same (s < shat); b1, b2 are db/ds and d2b/ds2. */
+void or_barrier_sq(double s, double shat, double *b, double *b1, double *b2) {
+  if (!(s > 0.0 && s < shat)) {
+    *b = *b1 = *b2 = 0.0;
+    return;
+  }
+  double lr = log(s / shat);
+  double sm = s - shat;
+  *b = -(sm * sm) * lr;
+  *b1 = -2.0 * sm * lr - (sm * sm) / s;
+  *b2 = -2.0 * lr - 4.0 * sm / s + (sm * sm) / (s * s);
+}
+
 /* EE mollifier (IPC, which the paper defers to for its contact model):
  * m(c) = (2 - c/eps) c/eps for c < eps, else 1, with c = |ea x eb|^2. */
 void or_mollifier(double c, double eps_x, double *m, double *m1, double *m2) {
@@ -515,6 +531,11 @@ void or_mollifier(double c, double eps_x, double *m, double *m1, double *m2) {
  * (d == 0) or OR_ERR_NONFINITE. */
 int or_pair_eval(int kind, const double *x12, const double *rest12, double dhat, double kappa, int *type_out,
                  double *s_out, double *e, double *g12, double *H144) {
+  return or_pair_eval_f(kind, x12, rest12, dhat, kappa, 0, type_out, s_out, e, g12, H144);
+}
+
+int or_pair_eval_f(int kind, const double *x12, const double *rest12, double dhat, double kappa, uint32_t flags,
+                   int *type_out, double *s_out, double *e, double *g12, double *H144) {
   int type = kind == 0 ? or_pt_type(x12, x12 + 3, x12 + 6, x12 + 9) : or_ee_type(x12, x12 + 3, x12 + 6, x12 + 9);
   double s = or_pair_dist2(kind, type, x12);
   if (type_out) *type_out = type;
@@ -524,12 +545,16 @@ int or_pair_eval(int kind, const double *x12, const double *rest12, double dhat,
   if (s <= 0.0) return OR_ERR_INTERSECTING;
   double gs[12], Hs[144], s2;
   or_pair_dist2_derivs(kind, type, x12, &s2, gs, Hs);
-  double d = sqrt(s);
-  double b, b1, b2;
-  or_barrier(d, dhat, &b, &b1, &b2);
-  /* b as a function of s = d^2 */
-  double bs1 = b1 / (2.0 * d);
-  double bs2 = (b2 - b1 / d) / (4.0 * s);
+  double b, bs1, bs2;
+  if (flags & OR_SQDIST) {
+    or_barrier_sq(s, dhat * dhat, &b, &bs1, &bs2);
+  } else {
+    double d = sqrt(s), b1, b2;
+    or_barrier(d, dhat, &b, &b1, &b2);
+    /* b as a function of s = d^2 */
+    bs1 = b1 / (2.0 * d);
+    bs2 = (b2 - b1 / d) / (4.0 * s);
+  }
   double m = 1.0, m1 = 0.0, m2 = 0.0, c = 0.0, gc[12] = {0}, Hc[144] = {0};
   int moll = (kind == 1 && rest12 != NULL);
   if (moll) {
@@ -684,7 +709,7 @@ int or_barrier_reduce(const or_scene *sc, const double *q, const int32_t *pt, in
           if (moll) r12[3 * a + c] = sc->x_rest[3 * vid[a] + c];
         }
       double e, g[12], H[144], P[144];
-      int st = or_pair_eval(kind, x12, moll ? r12 : NULL, dhat, kappa, NULL, NULL, &e, g, H);
+      int st = or_pair_eval_f(kind, x12, moll ? r12 : NULL, dhat, kappa, flags, NULL, NULL, &e, g, H);
       if (st == OR_INACTIVE) continue;
       if (st != OR_OK) {
         status = st;
@@ -761,7 +786,7 @@ int or_barrier_hvp(const or_scene *sc, const double *q, const int32_t *pt, int64
           if (moll) r12[3 * a + c] = sc->x_rest[3 * vid[a] + c];
         }
       double H[144], P[144];
-      int st = or_pair_eval(kind, x12, moll ? r12 : NULL, dhat, kappa, NULL, NULL, NULL, NULL, H);
+      int st = or_pair_eval_f(kind, x12, moll ? r12 : NULL, dhat, kappa, flags, NULL, NULL, NULL, NULL, H);
       if (st == OR_INACTIVE) continue;
       if (st != OR_OK) {
         status = st;
@@ -855,8 +880,93 @@ double or_accd_pair(int kind, const double *x12, const double *p12, double s, do
   return t;
 }
 
+/* Alternative CCD (f4): conservative advancement along the closest
+ * direction, after C2A (the CCD reference the paper cites).  At positions
+ * x with distance d, let n be the unit vector from the second primitive's
+ * closest point to the first's (the triangle or edge b, to the point or
+ * edge a).  The two closest points span separating planes with normal n:
+ * every point of the first primitive lies at or beyond n.c_first and every
+ * point of the second at or before n.c_second.  Under linear motion each
+ * point of a primitive stays a convex combination of its moving vertices,
+ * so for any later time t' the distance is at least
+ *   d - mu (t' - t),   mu = max_{b in second} n.p_b - min_{a in first} n.p_a.
+ * The steps are those of additive CCD (or_accd_pair) with the motion bound
+ * lp replaced by mu at each iterate; mu <= 0 (the gap along n does not
+ * close) bounds the pair by t_c.  mu <= lp, so no step is shorter than the
+ * additive one from the same iterate. */
+static void closest_weights(int kind, int type, const double *x12, double *beta);
+
+static double closing_rate(int kind, const double *x12, const double *p12) {
+  int type = kind == 0 ? or_pt_type(x12, x12 + 3, x12 + 6, x12 + 9) : or_ee_type(x12, x12 + 3, x12 + 6, x12 + 9);
+  double beta[4], r[3] = {0.0, 0.0, 0.0};
+  closest_weights(kind, type, x12, beta);
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) r[c] += beta[a] * x12[3 * a + c];
+  double rn = sqrt(dot3(r, r));
+  double nv[3] = {r[0] / rn, r[1] / rn, r[2] / rn};
+  int nfirst = kind == 0 ? 1 : 2;
+  double amin = INFINITY, bmax = -INFINITY;
+  for (int a = 0; a < 4; ++a) {
+    double v = dot3(nv, p12 + 3 * a);
+    if (a < nfirst)
+      amin = fmin(amin, v);
+    else
+      bmax = fmax(bmax, v);
+  }
+  return bmax - amin;
+}
+
+double or_c2a_pair(int kind, const double *x12, const double *p12, double s, double t_c, int64_t max_iter,
+                   int64_t *iters) {
+  double x[12], p[12], mean[3];
+  memcpy(x, x12, sizeof x);
+  for (int c = 0; c < 3; ++c) mean[c] = (((p12[c] + p12[3 + c]) + p12[6 + c]) + p12[9 + c]) * 0.25;
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) p[3 * a + c] = p12[3 * a + c] - mean[c];
+  if (iters) *iters = 0;
+  int moving = 0;
+  for (int i = 0; i < 12; ++i) moving |= p[i] != 0.0;
+  if (!moving) return t_c;
+  double d = pair_dist(kind, x);
+  double mu = closing_rate(kind, x, p);
+  if (!(mu > 0.0)) return t_c;
+  double g = s * d;
+  double t = 0.0;
+  double tl = (1.0 - s) * d / mu;
+  int64_t it = 0;
+  for (;;) {
+    if (it >= max_iter) break;
+    ++it;
+    if (t == 0.0 && t + tl > t_c) {
+      t = t_c;
+      break;
+    }
+    for (int i = 0; i < 12; ++i) x[i] = x[i] + tl * p[i];
+    d = pair_dist(kind, x);
+    if (t > 0.0 && d < g) break;
+    t = t + tl;
+    if (t > t_c) {
+      t = t_c;
+      break;
+    }
+    mu = closing_rate(kind, x, p);
+    if (!(mu > 0.0)) {
+      t = t_c;
+      break;
+    }
+    tl = 0.9 * d / mu;
+  }
+  if (iters) *iters = it;
+  return t;
+}
+
 int or_ccd_toi(const or_scene *sc, const double *x, const double *p, int kind, const int32_t *pairs, int64_t n,
                double s, double t_c, int64_t max_iter, double *t_out, int64_t *iters_out) {
+  return or_ccd_toi_m(sc, x, p, kind, pairs, n, s, t_c, max_iter, 0, t_out, iters_out);
+}
+
+int or_ccd_toi_m(const or_scene *sc, const double *x, const double *p, int kind, const int32_t *pairs, int64_t n,
+                 double s, double t_c, int64_t max_iter, int method, double *t_out, int64_t *iters_out) {
   for (int64_t k = 0; k < n; ++k) {
     int32_t vid[4];
     pair_vertices(sc, kind, pairs + 2 * k, vid);
@@ -867,7 +977,8 @@ int or_ccd_toi(const or_scene *sc, const double *x, const double *p, int kind, c
         p12[3 * a + c] = p[3 * vid[a] + c];
       }
     int64_t it;
-    t_out[k] = or_accd_pair(kind, x12, p12, s, t_c, max_iter, &it);
+    t_out[k] = method == 1 ? or_c2a_pair(kind, x12, p12, s, t_c, max_iter, &it)
+                           : or_accd_pair(kind, x12, p12, s, t_c, max_iter, &it);
     if (iters_out) iters_out[k] = it;
   }
   return OR_OK;
@@ -1183,7 +1294,7 @@ or_bsr *or_barrier_reduce_bsr(const or_scene *sc, const double *q, const int32_t
           if (moll) r12[3 * a + c] = sc->x_rest[3 * vid[a] + c];
         }
       double e, g[12], H[144], P[144];
-      int st = or_pair_eval(kind, x12, moll ? r12 : NULL, dhat, kappa, NULL, NULL, &e, g, H);
+      int st = or_pair_eval_f(kind, x12, moll ? r12 : NULL, dhat, kappa, flags, NULL, NULL, &e, g, H);
       if (st == OR_INACTIVE) continue;
       if (st != OR_OK) {
         status = st;
@@ -1373,6 +1484,13 @@ static void closest_weights(int kind, int type, const double *x12, double *beta)
 /* Lag record of one pair at x^n (see above); returns OR_OK, OR_INACTIVE
  * (lambda = 0: the pair adds no friction) or an error. */
 int or_friction_lag(int kind, const double *x12, const double *rest12, double dhat, double kappa, double *lag) {
+  return or_friction_lag_f(kind, x12, rest12, dhat, kappa, 0, lag);
+}
+
+/* OR_SQDIST: the normal force is kappa m |db/dd| of the squared-distance
+ * barrier, 2 d |db/ds| */
+int or_friction_lag_f(int kind, const double *x12, const double *rest12, double dhat, double kappa, uint32_t flags,
+                      double *lag) {
   for (int i = 0; i < 11; ++i) lag[i] = 0.0;
   int type = kind == 0 ? or_pt_type(x12, x12 + 3, x12 + 6, x12 + 9) : or_ee_type(x12, x12 + 3, x12 + 6, x12 + 9);
   double s = or_pair_dist2(kind, type, x12);
@@ -1380,7 +1498,12 @@ int or_friction_lag(int kind, const double *x12, const double *rest12, double dh
   if (!(s < dhat * dhat)) return OR_INACTIVE;
   if (s <= 0.0) return OR_ERR_INTERSECTING;
   double d = sqrt(s), b, b1, b2;
-  or_barrier(d, dhat, &b, &b1, &b2);
+  if (flags & OR_SQDIST) {
+    or_barrier_sq(s, dhat * dhat, &b, &b1, &b2);
+    b1 = 2.0 * d * b1;
+  } else {
+    or_barrier(d, dhat, &b, &b1, &b2);
+  }
   double m = 1.0;
   if (kind == 1 && rest12) {
     double ur[3], vr[3], u[3], v[3], n[3], m1, m2;
@@ -1467,7 +1590,7 @@ int or_friction_lag_list(const or_scene *sc, const double *q_n, int kind, const 
         x12[3 * a + c] = x[3 * vid[a] + c];
         if (moll) r12[3 * a + c] = sc->x_rest[3 * vid[a] + c];
       }
-    int st = or_friction_lag(kind, x12, moll ? r12 : NULL, dhat, kappa, lag + 11 * k);
+    int st = or_friction_lag_f(kind, x12, moll ? r12 : NULL, dhat, kappa, flags, lag + 11 * k);
     if (st != OR_OK && st != OR_INACTIVE) status = st;
   }
   free(x);

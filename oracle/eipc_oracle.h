@@ -25,7 +25,7 @@ typedef struct {
   const double *x_rest;    /* [n_vert*3] rest positions (EE mollifier) or NULL */
 } or_scene;
 
-enum { OR_ENERGY = 1, OR_GRAD = 2, OR_HESS = 4, OR_PROJECT = 8, OR_MOLLIFY = 16 };
+enum { OR_ENERGY = 1, OR_GRAD = 2, OR_HESS = 4, OR_PROJECT = 8, OR_MOLLIFY = 16, OR_SQDIST = 32 };
 enum { OR_OK = 0, OR_INACTIVE = 1, OR_ERR_INTERSECTING = -3, OR_ERR_NONFINITE = -5,
        OR_ERR_CAPACITY = -2 };
 
@@ -54,6 +54,11 @@ void or_mollifier(double c, double eps_x, double *m, double *m1, double *m2);
 
 int or_pair_eval(int kind, const double *x12, const double *rest12, double dhat, double kappa,
                  int *type, double *s, double *e, double *g12, double *H144);
+/* or_pair_eval with flags (OR_SQDIST: the barrier in s = d^2, see or_barrier_sq) */
+int or_pair_eval_f(int kind, const double *x12, const double *rest12, double dhat, double kappa, uint32_t flags,
+                   int *type_out, double *s_out, double *e, double *g12, double *H144);
+/* squared-distance barrier b(s) = -(s - shat)^2 ln(s / shat) and its s-derivatives */
+void or_barrier_sq(double s, double shat, double *b, double *b1, double *b2);
 int or_project_psd(int n, const double *A, double *P);
 
 int or_barrier_reduce(const or_scene *sc, const double *q, const int32_t *pt, int64_t n_pt,
@@ -69,6 +74,12 @@ double or_accd_pair(int kind, const double *x12, const double *p12, double s, do
 int or_ccd_toi(const or_scene *sc, const double *x, const double *p, int kind,
                const int32_t *pairs, int64_t n, double s, double t_c, int64_t max_iter,
                double *t_out, int64_t *iters_out);
+/* method 0: additive CCD (or_accd_pair); 1: conservative advancement along
+ * the closest direction (or_c2a_pair) */
+int or_ccd_toi_m(const or_scene *sc, const double *x, const double *p, int kind, const int32_t *pairs, int64_t n,
+                 double s, double t_c, int64_t max_iter, int method, double *t_out, int64_t *iters_out);
+double or_c2a_pair(int kind, const double *x12, const double *p12, double s, double t_c, int64_t max_iter,
+                   int64_t *iters);
 int or_ccd_max_step(const or_scene *sc, const double *q, const double *dq, const double *dx_off,
                     double dhat, double s, double t_max, int64_t max_iter, double *alpha,
                     int64_t *n_cand, int64_t *n_capped);
@@ -95,6 +106,8 @@ void or_bsr_free(or_bsr *B);
 /* lagged friction (Sec. III-B); lag record: lambda, beta[4], n[3], G x^n[3] */
 void or_friction_f(double y, double epsvh, double *f0, double *f1, double *f1p);
 int or_friction_lag(int kind, const double *x12, const double *rest12, double dhat, double kappa, double *lag);
+int or_friction_lag_f(int kind, const double *x12, const double *rest12, double dhat, double kappa,
+                      uint32_t flags, double *lag);
 void or_friction_pair(const double *x12, const double *lag, double mu, double epsvh, double *e, double *g12,
                       double *H144);
 int or_friction_lag_list(const or_scene *sc, const double *q_n, int kind, const int32_t *pairs, int64_t n,

@@ -12,7 +12,7 @@ import os
 import numpy as np
 import torch
 
-ENERGY, GRAD, HESS, PROJECT, MOLLIFY = 1, 2, 4, 8, 16
+ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST = 1, 2, 4, 8, 16, 32
 OK, ERR_ARG, ERR_CAPACITY, ERR_INTERSECTING, ERR_DEGENERATE, ERR_NONFINITE, ERR_HIP = 0, -1, -2, -3, -4, -5, -6
 WARN_CCD_CAPPED = 1
 
@@ -91,6 +91,7 @@ def _load():
         "eipc_plan_step": (_I32, [_P, _P, _P, _P, _P, _D, _D, _I32, _P, _P]),
         "eipc_contact_step": (_I32, [_P, _P, _P, _P, _P, _P, _D, _D, _U32, _D, _D, _I64, _P, _P, _P, _P, _P, _P]),
         "eipc_set_tuning": (_I32, [_P, _D, _P, _I32]),
+        "eipc_set_ccd_method": (_I32, [_P, _I32]),
         "eipc_step_pairs": (_I32, [_P, _I32, _P, _I64, _P, _P]),
         "eipc_friction_lag": (_I32, [_P, _P, _P, _P, _I64, _P, _I64, _D, _D, _U32, _P, _P, _P]),
         "eipc_friction_reduce": (_I32, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _D, _D, _U32, _P, _P, _P, _P, _P]),
@@ -467,6 +468,15 @@ def set_tuning(ctx: Context, cell_scale: float, wg_per_cu=(0, 0, 0, 0), query_ce
     cell), 3 (bucket join); -1 keeps it."""
     w = (_I32 * 4)(*[int(v) for v in wg_per_cu])
     ctx.check(_load().eipc_set_tuning(ctx.handle, float(cell_scale), w, int(query_cells)))
+
+
+CCD_ADDITIVE, CCD_CLOSEST_DIRECTION = 0, 1
+
+
+def set_ccd_method(ctx: Context, method: int):
+    """The context's per-pair CCD step bound: CCD_ADDITIVE (default) or
+    CCD_CLOSEST_DIRECTION (advancement along the closest direction)."""
+    ctx.check(_load().eipc_set_ccd_method(ctx.handle, int(method)))
 
 
 def plan_step(ctx: Context, sc: Scene, q, dhat: float, dq=None, dx_off=None, margin: float = 1.5,

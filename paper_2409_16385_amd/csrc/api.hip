@@ -765,6 +765,14 @@ eipc_status eipc_set_tuning(eipc_ctx *c, double cell_scale, const int32_t wg_per
   return EIPC_OK;
 }
 
+eipc_status eipc_set_ccd_method(eipc_ctx *c, int32_t method) {
+  if (!c) return EIPC_ERR_ARG;
+  if (method != EIPC_CCD_ADDITIVE && method != EIPC_CCD_CLOSEST_DIRECTION)
+    return set_err(c, EIPC_ERR_ARG, "method must be EIPC_CCD_ADDITIVE or EIPC_CCD_CLOSEST_DIRECTION");
+  c->ccd_method = method;
+  return EIPC_OK;
+}
+
 }  // extern "C"
 
 namespace eipc {

@@ -779,6 +779,7 @@ __global__ __launch_bounds__(TERMS_T) void k_pair_terms(
   __shared__ double s_e[TERMS_T / 64];
   const bool expand = want_g || want_h;
   const bool project = flags & EIPC_PROJECT;
+  const bool sq = flags & EIPC_SQDIST;
   const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -877,14 +878,14 @@ __global__ __launch_bounds__(TERMS_T) void k_pair_terms(
         }
         if (expand) {
           double tv[54];
-          e_pair = pair_qterms<KIND>(cls, ty, x, eps, dhat, kappa, want_g, want_h, project, tv, tv + 9);
+          e_pair = pair_qterms<KIND>(cls, ty, x, eps, dhat, kappa, want_g, want_h, project, sq, tv, tv + 9);
           double2 *r2 = (double2 *)(rec + i * TERM_REC);
           const int nst = want_h ? 27 : 5;
 #pragma unroll
           for (int q = 0; q < 27; ++q)
             if (q < nst) r2[q] = make_double2(tv[2 * q], tv[2 * q + 1]);
         } else {
-          e_pair = pair_energy<KIND>(ty, x, eps, dhat, kappa);
+          e_pair = pair_energy<KIND>(ty, x, eps, dhat, kappa, sq);
         }
       }
       if (energy && vscene) agg_scene_add(energy, live, scene, n_scene, e_pair, status);
@@ -1171,7 +1172,7 @@ __global__ __launch_bounds__(BR_THREADS) void k_hvp(
       // the Hessian of the barrier stage's per-class path
       double gam[9], M[45];
       pair_qterms<KIND>(pair_class<KIND>(ty, x, eps), ty, x, eps, dhat, kappa, false, true,
-                        (flags & EIPC_PROJECT) != 0, gam, M);
+                        (flags & EIPC_PROJECT) != 0, (flags & EIPC_SQDIST) != 0, gam, M);
       // zeta = Q^T z, eta = X zeta
       double zeta[9];
 #pragma unroll
@@ -1307,7 +1308,8 @@ __global__ __launch_bounds__(64) void k_pair_eval(int64_t n, const int32_t *__re
   double ev = 0.0;
   if (active) {
     const int cls = pair_class<KIND>(ty, x, eps);
-    ev = pair_qterms<KIND>(cls, ty, x, eps, dhat, kappa, true, true, (flags & EIPC_PROJECT) != 0, gam, M);
+    ev = pair_qterms<KIND>(cls, ty, x, eps, dhat, kappa, true, true, (flags & EIPC_PROJECT) != 0,
+                           (flags & EIPC_SQDIST) != 0, gam, M);
   }
   if (e) e[i] = ev;
   if (g) {

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_ccd(int64_t cap, const int64_t *d_n, co
                       const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
                       const double *__restrict__ xs, const double *__restrict__ ps, int n_vert, double sfac,
                       double t_max, int64_t max_iter, unsigned long long *alpha_bits, double *t_out, int64_t *it_out,
-                      const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
+                      const int32_t *__restrict__ vscene, int n_scene, uint32_t *status, bool dir) {
   const int64_t n = d_n ? (*d_n < cap ? *d_n : cap) : cap;
   bool capped = false;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_ccd(int64_t cap, const int64_t *d_n, co
         ld_pos(ps, vid[k], p[k].x, p[k].y, p[k].z);
       }
       int64_t it = 0;
-      t = accd<KIND>(x, p, sfac, t_max, max_iter, &it);
+      t = accd<KIND>(x, p, sfac, t_max, max_iter, &it, dir);
       capped = capped || it >= max_iter;
       if (t_out) t_out[i] = t;
       if (it_out) it_out[i] = it;
@@ -123,7 +123,8 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
                        const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
                        const double *__restrict__ xs, const double *__restrict__ ps, int n_vert, double sfac,
                        double t_max, int64_t max_iter, unsigned long long *alpha_bits, int32_t *__restrict__ longl,
-                       int64_t *n_long, const int32_t *__restrict__ vscene, int n_scene, uint32_t *status) {
+                       int64_t *n_long, const int32_t *__restrict__ vscene, int n_scene, uint32_t *status,
+                       bool dir) {
   const int64_t n = PASS == 0 ? (d_n ? (*d_n < cap ? *d_n : cap) : cap) : (*n_long < cap ? *n_long : cap);
   const int lane = threadIdx.x & 63;
   bool capped = false;
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
         ld_pos(ps, vid[q], p[q].x, p[q].y, p[q].z);
       }
       AccdState st;
+      st.dir = dir;
       const double cut = scene_cut(alpha_bits, scene, n_scene, t_max, max_iter);
       const int64_t lim = PASS == 0 ? (CCD_SHORT < max_iter ? CCD_SHORT : max_iter) : max_iter;
       const int r = accd_run_cut<KIND>(x, p, t_max, max_iter, cut, lim, st,
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     double h, int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t act_cap, int64_t *count,
     int64_t *cand_count, double sfac, double t_max, int64_t max_iter, unsigned long long *alpha_bits,
     int32_t *__restrict__ longl, int64_t *n_long, const int32_t *__restrict__ vscene, int n_scene,
-    uint32_t *status) {
+    uint32_t *status, bool dir) {
   const int64_t n = *d_n < cap ? *d_n : cap;
   const int lane = threadIdx.x & 63;
   bool capped = false;
@@ -256,6 +258,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         }
       }
       AccdState st;
+      st.dir = dir;
       const double cut = scene_cut(alpha_bits, scene, n_scene, t_max, max_iter);
       const int64_t lim = CCD_SHORT < max_iter ? CCD_SHORT : max_iter;
       const int r = accd_run_cut<KIND>(x, p, t_max, max_iter, cut, lim, st,
@@ -320,11 +323,11 @@ eipc_status launch_narrow_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const
     if (kind == 0)
       k_narrow_ccd<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ,
                                              act_cap, d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long,
-                                             vsc, nsc, c->status);
+                                             vsc, nsc, c->status, c->ccd_method == 1);
     else
       k_narrow_ccd<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, d2, h, act, typ,
                                              act_cap, d_count, cand_count, sfac, t_max, max_iter, ab, longl, n_long,
-                                             vsc, nsc, c->status);
+                                             vsc, nsc, c->status, c->ccd_method == 1);
     EIPC_HIP(c, hipGetLastError());
   }
   return EIPC_OK;
@@ -344,10 +347,10 @@ eipc_status launch_ccd_long(eipc_ctx *c, const eipc_scene *sc, int kind, const d
   ProfScope prof(c, kind == 0 ? K_CCD_LONG_PT : K_CCD_LONG_EE, s);
   if (kind == 0)
     k_ccd2<0, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                        max_iter, ab, longl, n_long, vsc, nsc, c->status);
+                                        max_iter, ab, longl, n_long, vsc, nsc, c->status, c->ccd_method == 1);
   else
     k_ccd2<1, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                        max_iter, ab, longl, n_long, vsc, nsc, c->status);
+                                        max_iter, ab, longl, n_long, vsc, nsc, c->status, c->ccd_method == 1);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }
@@ -368,21 +371,23 @@ eipc_status launch_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double
     unsigned long long *ab = (unsigned long long *)d_alpha_bits;
     if (kind == 0) {
       k_ccd2<0, 0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status, c->ccd_method == 1);
       k_ccd2<0, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status, c->ccd_method == 1);
     } else {
       k_ccd2<1, 0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status, c->ccd_method == 1);
       k_ccd2<1, 1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max,
-                                          max_iter, ab, longl, n_long, vsc, nsc, c->status);
+                                          max_iter, ab, longl, n_long, vsc, nsc, c->status, c->ccd_method == 1);
     }
   } else if (kind == 0)
     k_ccd<0><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max, max_iter,
-                                     (unsigned long long *)d_alpha_bits, t_out, it_out, vsc, nsc, c->status);
+                                     (unsigned long long *)d_alpha_bits, t_out, it_out, vsc, nsc, c->status,
+                                     c->ccd_method == 1);
   else
     k_ccd<1><<<blocks, 256, 0, s>>>(n, d_n, pairs, sc->faces, sc->edges, xs, ps, sc->n_vert, sfac, t_max, max_iter,
-                                     (unsigned long long *)d_alpha_bits, t_out, it_out, vsc, nsc, c->status);
+                                     (unsigned long long *)d_alpha_bits, t_out, it_out, vsc, nsc, c->status,
+                                     c->ccd_method == 1);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }

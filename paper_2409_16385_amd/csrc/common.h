@@ -120,6 +120,7 @@ struct eipc_ctx {
   int num_cu = 256;
   double cell_scale = 2.0;       // broad-phase cell edge / mean item extent
   int wg_per_cu[4] = {1, 2, 4, 4};  // grid sizes: barrier stage, stored-terms expansion, narrow, CCD
+  int ccd_method = 0;                // 0: additive CCD, 1: advancement along the closest direction
   // append-mode broad phase work split [PT, EE]: 0 thread per query,
   // 1 thread per (query, cell), 2 wavefront per (query, cell), 3 bucket join
   int query_mode[2] = {1, 0};

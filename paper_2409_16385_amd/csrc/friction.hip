@@ -26,48 +26,6 @@ namespace eipc {
 
 constexpr int FR_T = 256;
 
-// signed closest-point weights of a classified pair at positions x
-template <int KIND>
-__device__ __forceinline__ void closest_beta(int type, const V3 *x, double *beta) {
-  constexpr const TypeDef *defs = KIND == 0 ? kPT : kEE;
-  beta[0] = beta[1] = beta[2] = beta[3] = 0.0;
-  const TypeDef t = defs[type];
-  if (t.fn == FN_PP) {
-    beta[t.plus[0]] = 1.0;
-    beta[t.minus[0]] = -1.0;
-  } else if (t.fn == FN_PL) {
-    // point P = plus[0] against the segment from A = minus[1] to B = plus[1]
-    const V3 y0 = xsub(x[t.plus[0]], x[t.minus[1]]);
-    const V3 y1 = xsub(x[t.plus[1]], x[t.minus[1]]);
-    const double s = xdot(y0, y1) / xdot(y1, y1);
-    const double sg = (KIND == 0 || t.plus[0] < 2) ? 1.0 : -1.0;  // the point's side
-    beta[t.plus[0]] = sg;
-    beta[t.minus[1]] = -sg * (1.0 - s);
-    beta[t.plus[1]] = -sg * s;
-  } else if (KIND == 0) {
-    // closest triangle point t0 + u (t1 - t0) + v (t2 - t0)
-    const V3 r = xsub(x[0], x[1]), e0 = xsub(x[2], x[1]), e1 = xsub(x[3], x[1]);
-    const double a = xdot(e0, e0), b = xdot(e0, e1), c = xdot(e1, e1);
-    const double d0 = xdot(e0, r), d1 = xdot(e1, r);
-    const double det = a * c - b * b;
-    const double u = (c * d0 - b * d1) / det, v = (a * d1 - b * d0) / det;
-    beta[0] = 1.0;
-    beta[1] = -(1.0 - u - v);
-    beta[2] = -u;
-    beta[3] = -v;
-  } else {
-    // closest points a0 + s (a1 - a0) and b0 + t (b1 - b0)
-    const V3 u = xsub(x[1], x[0]), v = xsub(x[3], x[2]), w = xsub(x[0], x[2]);
-    const double a = xdot(u, u), b = xdot(u, v), c = xdot(v, v), d = xdot(u, w), e = xdot(v, w);
-    const double D = a * c - b * b;
-    const double s = (b * e - c * d) / D, tt = (a * e - b * d) / D;
-    beta[0] = 1.0 - s;
-    beta[1] = s;
-    beta[2] = -(1.0 - tt);
-    beta[3] = -tt;
-  }
-}
-
 template <int KIND>
 __device__ __forceinline__ void pair_vid(const int32_t *pairs, int64_t k, const int32_t *faces, const int32_t *edges,
                                          int *vid) {
@@ -90,7 +48,8 @@ __global__ __launch_bounds__(FR_T) void k_friction_lag(int64_t n, const int32_t 
                                                        const int32_t *__restrict__ faces,
                                                        const int32_t *__restrict__ edges, const double *__restrict__ xs,
                                                        const double *__restrict__ x_rest, double dhat, double kappa,
-                                                       bool moll, double *__restrict__ lag, uint32_t *status) {
+                                                       bool moll, bool sq, double *__restrict__ lag,
+                                                       uint32_t *status) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     int vid[4];
     pair_vid<KIND>(pairs, k, faces, edges, vid);
@@ -108,8 +67,10 @@ __global__ __launch_bounds__(FR_T) void k_friction_lag(int64_t n, const int32_t 
       if (!(s2 > 0.0)) {
         atomicOr(status, ST_INTERSECTING);
       } else {
-        const double d = sqrt(s2), dm = d - dhat;
-        const double b1 = -2.0 * dm * log(d / dhat) - dm * dm / d;
+        const double d = sqrt(s2);
+        // db/dd; of the squared-distance barrier 2 d db/ds
+        const double b1 = sq ? 2.0 * d * barrier_s(s2, dhat, true).bs1
+                             : -2.0 * (d - dhat) * log(d / dhat) - (d - dhat) * (d - dhat) / d;
         double m = 1.0;
         if (KIND == 1 && moll) {
           V3 r[4];
@@ -247,12 +208,13 @@ eipc_status launch_friction_lag(eipc_ctx *c, const eipc_scene *sc, int kind, con
   if (n == 0) return EIPC_OK;
   const int blocks = (int)std::min<int64_t>(grid_for(n, FR_T), 8 * (int64_t)c->num_cu);
   const bool moll = (flags & EIPC_MOLLIFY) && sc->x_rest;
+  const bool sq = flags & EIPC_SQDIST;
   if (kind == 0)
-    k_friction_lag<0><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->x_rest, dhat, kappa, moll, lag,
-                                              c->status);
+    k_friction_lag<0><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->x_rest, dhat, kappa, moll, sq,
+                                              lag, c->status);
   else
-    k_friction_lag<1><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->x_rest, dhat, kappa, moll, lag,
-                                              c->status);
+    k_friction_lag<1><<<blocks, FR_T, 0, s>>>(n, pairs, sc->faces, sc->edges, xs, sc->x_rest, dhat, kappa, moll, sq,
+                                              lag, c->status);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }

@@ -447,7 +447,20 @@ __device__ __forceinline__ void s_derivs(int type, const V3 *x, double *gY, doub
 struct Barrier {
   double b, bs1, bs2;
 };
-__device__ __forceinline__ Barrier barrier_s(double s, double dhat) {
+// sq (alternative formulation): the barrier written in s itself,
+//   bt(s) = -(s - shat)^2 ln(s / shat),  shat = dhat^2
+__device__ __forceinline__ Barrier barrier_s(double s, double dhat, bool sq) {
+  if (sq) {
+    const double shat = dhat * dhat;
+    const double lr = log(s / shat);
+    const double sm = s - shat;
+    const double is = 1.0 / s;
+    Barrier r;
+    r.b = -(sm * sm) * lr;
+    r.bs1 = -2.0 * sm * lr - (sm * sm) * is;
+    r.bs2 = -2.0 * lr - 4.0 * sm * is + (sm * sm) * is * is;
+    return r;
+  }
   double d = sqrt(s);
   double lr = log(d / dhat);
   double dm = d - dhat;
@@ -469,8 +482,8 @@ __device__ __forceinline__ Barrier barrier_s(double s, double dhat) {
 template <int KIND>
 __device__ __forceinline__ double energy_derivs_gs(const double *gs, const double *Hs, const V3 *Y, double s,
                                                    double dhat, double kappa, double eps_x, double *gE, double *HE,
-                                                   bool want_h) {
-  Barrier br = barrier_s(s, dhat);
+                                                   bool want_h, bool sq) {
+  Barrier br = barrier_s(s, dhat, sq);
   double m = 1.0, m1 = 0.0, m2 = 0.0;
   double gc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   double Hc[81];
@@ -516,10 +529,11 @@ __device__ __forceinline__ double energy_derivs_gs(const double *gs, const doubl
 
 template <int KIND>
 __device__ __forceinline__ double energy_derivs(int type, const V3 *x, const V3 *Y, double s, double dhat,
-                                                double kappa, double eps_x, double *gE, double *HE, bool want_h) {
+                                                double kappa, double eps_x, double *gE, double *HE, bool want_h,
+                                                bool sq) {
   double gs[9], Hs[45];
   s_derivs<KIND>(type, x, gs, Hs);
-  return energy_derivs_gs<KIND>(gs, Hs, Y, s, dhat, kappa, eps_x, gE, HE, want_h);
+  return energy_derivs_gs<KIND>(gs, Hs, Y, s, dhat, kappa, eps_x, gE, HE, want_h, sq);
 }
 
 // M = G^T H G (packed), G = (T Q) (x) I3 with integer entries gcoef.
@@ -829,12 +843,12 @@ __device__ __forceinline__ void grad_to_q(const double *gE, double *gam) {
 
 template <int KIND>
 __device__ __forceinline__ double terms_pp(int type, const V3 *x, double dhat, double kappa, bool want_g,
-                                           bool want_h, bool project, double *gam, double *X) {
+                                           bool want_h, bool project, bool sq, double *gam, double *X) {
   const uint32_t code = (uint32_t)(slot_codes<KIND>() >> (8 * type)) & 0xffu;
   const int p0 = code & 3, m0 = (code >> 2) & 3;
   const V3 y = xsub(pick4(x, p0), pick4(x, m0));
   const double s = xdot(y, y);
-  const Barrier br = barrier_s(s, dhat);
+  const Barrier br = barrier_s(s, dhat, sq);
   double E[3];
   e_row(p0, m0, E);
   if (want_g) {
@@ -873,7 +887,7 @@ __device__ __forceinline__ double terms_pp(int type, const V3 *x, double dhat, d
 
 template <int KIND>
 __device__ __forceinline__ double terms_pl(int type, const V3 *x, double dhat, double kappa, bool want_g,
-                                           bool want_h, bool project, double *gam, double *X) {
+                                           bool want_h, bool project, bool sq, double *gam, double *X) {
   const uint32_t code = (uint32_t)(slot_codes<KIND>() >> (8 * type)) & 0xffu;
   const int p0 = code & 3, m0 = (code >> 2) & 3, p1 = (code >> 4) & 3, m1 = (code >> 6) & 3;
   V3 y[3];
@@ -886,7 +900,7 @@ __device__ __forceinline__ double terms_pl(int type, const V3 *x, double dhat, d
     const V3 cr = xcross(y[0], y[1]);
     s = xdot(cr, cr) / xdot(y[1], y[1]);
   }
-  const Barrier br = barrier_s(s, dhat);
+  const Barrier br = barrier_s(s, dhat, sq);
   if (!want_g && !want_h) return kappa * br.b;
   Local L;
   local_derivs<FN_PL>(y, L);
@@ -961,15 +975,15 @@ __device__ __forceinline__ double terms_pl(int type, const V3 *x, double dhat, d
 
 template <int KIND>
 __device__ __forceinline__ double terms_tri(const V3 *x, double dhat, double kappa, bool want_g, bool want_h,
-                                            bool project, double *gam, double *X) {
+                                            bool project, bool sq, double *gam, double *X) {
   constexpr int TT = KIND == 0 ? (int)PT_T : (int)EE_AB;
   const double s = type_value_t<KIND, TT>(x);
-  if (!want_g && !want_h) return kappa * barrier_s(s, dhat).b;
+  if (!want_g && !want_h) return kappa * barrier_s(s, dhat, sq).b;
   double gs[9], Hs[45], gE[9], HE[45];
   s_derivs_typed<KIND, TT>(x, gs, Hs);
   V3 Y[3];
   y_basis<KIND>(x, Y);
-  const double e = energy_derivs_gs<KIND>(gs, Hs, Y, s, dhat, kappa, 0.0, gE, HE, want_h);
+  const double e = energy_derivs_gs<KIND>(gs, Hs, Y, s, dhat, kappa, 0.0, gE, HE, want_h, sq);
   if (want_g) grad_to_q<KIND>(gE, gam);
   if (want_h) {
     to_q_basis<KIND>(HE, X);
@@ -981,12 +995,13 @@ __device__ __forceinline__ double terms_tri(const V3 *x, double dhat, double kap
 // any type, with the mollifier when eps_x > 0
 template <int KIND>
 __device__ __forceinline__ double terms_gen(int type, const V3 *x, double eps_x, double dhat, double kappa,
-                                            bool want_g, bool want_h, bool project, double *gam, double *X) {
+                                            bool want_g, bool want_h, bool project, bool sq, double *gam,
+                                            double *X) {
   const double s = type_value<KIND>(type, x);
   V3 Y[3];
   y_basis<KIND>(x, Y);
   double gE[9], HE[45];
-  const double e = energy_derivs<KIND>(type, x, Y, s, dhat, kappa, eps_x, gE, HE, want_h);
+  const double e = energy_derivs<KIND>(type, x, Y, s, dhat, kappa, eps_x, gE, HE, want_h, sq);
   if (want_g) grad_to_q<KIND>(gE, gam);
   if (want_h) {
     to_q_basis<KIND>(HE, X);
@@ -997,9 +1012,10 @@ __device__ __forceinline__ double terms_gen(int type, const V3 *x, double eps_x,
 
 // energy only
 template <int KIND>
-__device__ __forceinline__ double pair_energy(int type, const V3 *x, double eps_x, double dhat, double kappa) {
+__device__ __forceinline__ double pair_energy(int type, const V3 *x, double eps_x, double dhat, double kappa,
+                                              bool sq) {
   const double s = type_value<KIND>(type, x);
-  const Barrier br = barrier_s(s, dhat);
+  const Barrier br = barrier_s(s, dhat, sq);
   double m = 1.0;
   if constexpr (KIND == 1) {
     if (eps_x > 0.0) {
@@ -1020,12 +1036,12 @@ __device__ __forceinline__ double pair_energy(int type, const V3 *x, double eps_
 // of class cls.  Lanes of a wavefront that share the class share the path.
 template <int KIND>
 __device__ __forceinline__ double pair_qterms(int cls, int type, const V3 *x, double eps_x, double dhat,
-                                              double kappa, bool want_g, bool want_h, bool project, double *gam,
-                                              double *X) {
-  if (cls == CLS_PP) return terms_pp<KIND>(type, x, dhat, kappa, want_g, want_h, project, gam, X);
-  if (cls == CLS_PL) return terms_pl<KIND>(type, x, dhat, kappa, want_g, want_h, project, gam, X);
-  if (cls == CLS_TRI) return terms_tri<KIND>(x, dhat, kappa, want_g, want_h, project, gam, X);
-  return terms_gen<KIND>(type, x, eps_x, dhat, kappa, want_g, want_h, project, gam, X);
+                                              double kappa, bool want_g, bool want_h, bool project, bool sq,
+                                              double *gam, double *X) {
+  if (cls == CLS_PP) return terms_pp<KIND>(type, x, dhat, kappa, want_g, want_h, project, sq, gam, X);
+  if (cls == CLS_PL) return terms_pl<KIND>(type, x, dhat, kappa, want_g, want_h, project, sq, gam, X);
+  if (cls == CLS_TRI) return terms_tri<KIND>(x, dhat, kappa, want_g, want_h, project, sq, gam, X);
+  return terms_gen<KIND>(type, x, eps_x, dhat, kappa, want_g, want_h, project, sq, gam, X);
 }
 
 // ---------------------------------------------------------------------------
@@ -1071,9 +1087,93 @@ __device__ __forceinline__ bool static_boxes_overlap(const V3 *x, double h) {
 // FILTER: the pairs are swept candidates; only those that pass the
 // candidate predicate at the start positions are considered, and their
 // number is added to *cand_count.
+// signed closest-point weights of a classified pair at positions x (the
+// point minus the closest triangle point for PT, the closest point of edge
+// a minus that of edge b for EE: G x = sum_a beta_a x_a), each product and
+// sum rounded on its own
+template <int KIND>
+__device__ __forceinline__ void closest_beta(int type, const V3 *x, double *beta) {
+#pragma clang fp contract(off)
+  constexpr const TypeDef *defs = KIND == 0 ? kPT : kEE;
+  beta[0] = beta[1] = beta[2] = beta[3] = 0.0;
+  const TypeDef t = defs[type];
+  if (t.fn == FN_PP) {
+    beta[t.plus[0]] = 1.0;
+    beta[t.minus[0]] = -1.0;
+  } else if (t.fn == FN_PL) {
+    // point P = plus[0] against the segment from A = minus[1] to B = plus[1]
+    const V3 y0 = xsub(x[t.plus[0]], x[t.minus[1]]);
+    const V3 y1 = xsub(x[t.plus[1]], x[t.minus[1]]);
+    const double s = xdot(y0, y1) / xdot(y1, y1);
+    const double sg = (KIND == 0 || t.plus[0] < 2) ? 1.0 : -1.0;  // the point's side
+    beta[t.plus[0]] = sg;
+    beta[t.minus[1]] = -sg * (1.0 - s);
+    beta[t.plus[1]] = -sg * s;
+  } else if (KIND == 0) {
+    // closest triangle point t0 + u (t1 - t0) + v (t2 - t0)
+    const V3 r = xsub(x[0], x[1]), e0 = xsub(x[2], x[1]), e1 = xsub(x[3], x[1]);
+    const double a = xdot(e0, e0), b = xdot(e0, e1), c = xdot(e1, e1);
+    const double d0 = xdot(e0, r), d1 = xdot(e1, r);
+    const double det = a * c - b * b;
+    const double u = (c * d0 - b * d1) / det, v = (a * d1 - b * d0) / det;
+    beta[0] = 1.0;
+    beta[1] = -(1.0 - u - v);
+    beta[2] = -u;
+    beta[3] = -v;
+  } else {
+    // closest points a0 + s (a1 - a0) and b0 + t (b1 - b0)
+    const V3 u = xsub(x[1], x[0]), v = xsub(x[3], x[2]), w = xsub(x[0], x[2]);
+    const double a = xdot(u, u), b = xdot(u, v), c = xdot(v, v), d = xdot(u, w), e = xdot(v, w);
+    const double D = a * c - b * b;
+    const double s = (b * e - c * d) / D, tt = (a * e - b * d) / D;
+    beta[0] = 1.0 - s;
+    beta[1] = s;
+    beta[2] = -(1.0 - tt);
+    beta[3] = -tt;
+  }
+}
+
+// Rate at which the gap along the pair's current closest direction can
+// close under the motion p (conservative advancement after C2A): with n
+// the unit vector from the second primitive's closest point to the
+// first's, both primitives stay on their sides of the separating planes
+// through the closest points, and each point of a primitive is a convex
+// combination of its linearly moving vertices, so the distance at any
+// later time t' is at least d - mu (t' - t) with
+//   mu = max_{b in second} n.p_b - min_{a in first} n.p_a  (<= lp).
+template <int KIND>
+__device__ __forceinline__ double closing_rate(int type, const V3 *x, const V3 *p) {
+#pragma clang fp contract(off)
+  double beta[4];
+  closest_beta<KIND>(type, x, beta);
+  V3 r{0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    r.x += beta[a] * x[a].x;
+    r.y += beta[a] * x[a].y;
+    r.z += beta[a] * x[a].z;
+  }
+  const double rn = sqrt(xdot(r, r));
+  const V3 n{r.x / rn, r.y / rn, r.z / rn};
+  constexpr int nfirst = KIND == 0 ? 1 : 2;
+  double amin = INFINITY, bmax = -INFINITY;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const double v = n.x * p[a].x + n.y * p[a].y + n.z * p[a].z;
+    if (a < nfirst)
+      amin = fmin(amin, v);
+    else
+      bmax = fmax(bmax, v);
+  }
+  return bmax - amin;
+}
+
+// dir: advance with the closing rate along the closest direction (an
+// alternative CCD) instead of lp
 struct AccdState {
   double lp, g, t, tl;
   int64_t it;
+  bool dir;
 };
 
 // p made relative to its mean; st.lp = the largest possible rate of
@@ -1109,10 +1209,19 @@ __device__ __forceinline__ bool accd_init(V3 *x, V3 *p, double s, double t_c, Ac
     st.t = t_c;
     return true;
   }
-  int ty;
+  int ty = 0;
   const double d = sqrt(known ? s2 : pair_dist2<KIND>(x, &ty));
   st.g = s * d;
-  st.tl = (1.0 - s) * d / st.lp;
+  double rate = st.lp;
+  if (st.dir) {
+    if (known) ty = classify<KIND>(x);
+    rate = closing_rate<KIND>(ty, x, p);
+    if (!(rate > 0.0)) {  // the gap along the closest direction never closes
+      st.t = t_c;
+      return true;
+    }
+  }
+  st.tl = (1.0 - s) * d / rate;
   return false;
 }
 
@@ -1173,10 +1282,21 @@ __device__ __forceinline__ int accd_init_cut(V3 *x, V3 *p, double s, double t_c,
     const double lb = sqrt(box_gap2<KIND>(x)) * (1.0 - 1e-6);
     if ((1.0 - s) * lb / st.lp >= cut) return ACCD_DROP;
   }
-  int ty;
+  int ty = 0;
   const double d = sqrt(known ? s2 : pair_dist2<KIND>(x, &ty));
   st.g = s * d;
-  st.tl = (1.0 - s) * d / st.lp;
+  double rate = st.lp;
+  if (st.dir) {
+    // (the box-gap test above used lp >= the closing rate: a first step it
+    // drops is no shorter here)
+    if (known) ty = classify<KIND>(x);
+    rate = closing_rate<KIND>(ty, x, p);
+    if (!(rate > 0.0)) {
+      st.t = t_c;
+      return ACCD_DONE;
+    }
+  }
+  st.tl = (1.0 - s) * d / rate;
   return st.tl >= cut ? ACCD_DROP : ACCD_OPEN;
 }
 
@@ -1206,13 +1326,23 @@ __device__ __forceinline__ bool accd_step(V3 *x, const V3 *p, double t_c, int64_
     st.t = t_c;
     return true;
   }
-  st.tl = 0.9 * d / st.lp;
+  double rate = st.lp;
+  if (st.dir) {
+    rate = closing_rate<KIND>(ty, x, p);
+    if (!(rate > 0.0)) {
+      st.t = t_c;
+      return true;
+    }
+  }
+  st.tl = 0.9 * d / rate;
   return false;
 }
 
 template <int KIND>
-__device__ __forceinline__ double accd(V3 *x, V3 *p, double s, double t_c, int64_t max_iter, int64_t *iters) {
+__device__ __forceinline__ double accd(V3 *x, V3 *p, double s, double t_c, int64_t max_iter, int64_t *iters,
+                                       bool dir) {
   AccdState st;
+  st.dir = dir;
   if (!accd_init<KIND>(x, p, s, t_c, st))
     while (!accd_step<KIND>(x, p, t_c, max_iter, st)) {
     }
