@@ -63,7 +63,14 @@ enum {
    * squared distance, b(s) = -(s - dhat^2)^2 ln(s / dhat^2) with s = d^2
    * (the same active set; the friction normal force becomes
    * kappa m |db/dd| = kappa m 2 d |db/ds|). */
-  EIPC_SQDIST = 32
+  EIPC_SQDIST = 32,
+  /* Alternative projection (barrier_reduce, contact_step): the PSD
+   * projection of each pair's reduced local block W_k^T H_k W_k (over the
+   * pair's distinct nodes) in place of EIPC_PROJECT's projection of the
+   * 12x12 H_k.  The same for point-point pairs (and for W = I); another
+   * matrix for point-line and interior pairs under a coarse embedding.
+   * EIPC_ERR_ARG with barrier_hvp and pair_eval (per-pair outputs). */
+  EIPC_PROJECT_REDUCED = 64
 };
 
 typedef struct eipc_ctx eipc_ctx;

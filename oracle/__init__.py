@@ -15,7 +15,7 @@ import numpy as np
 
 from . import build as _build
 
-ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST = 1, 2, 4, 8, 16, 32
+ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST, PROJECT_REDUCED = 1, 2, 4, 8, 16, 32, 64
 OK, INACTIVE, ERR_CAPACITY, ERR_INTERSECTING, ERR_NONFINITE = 0, 1, -2, -3, -5
 PT_TYPES = ["P-T0", "P-T1", "P-T2", "P-E0", "P-E1", "P-E2", "P-T"]
 EE_TYPES = ["EA0-EB0", "EA0-EB1", "EA1-EB0", "EA1-EB1", "EA-EB0", "EA-EB1",

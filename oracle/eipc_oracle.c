@@ -606,7 +606,8 @@ int or_pair_eval_f(int kind, const double *x12, const double *rest12, double dha
 /* eigensolver gives the same P.  Returns the number of sweeps.         */
 /* ------------------------------------------------------------------ */
 int or_project_psd(int n, const double *A, double *P) {
-  double a[144], v[144];
+  static _Thread_local double a[48 * 48], v[48 * 48];
+  if (n < 1 || n > 48) return -1;
   memcpy(a, A, sizeof(double) * n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
@@ -717,6 +718,48 @@ int or_barrier_reduce(const or_scene *sc, const double *q, const int32_t *pt, in
       }
       ++na;
       nsum(&es, &ec, e);
+      if (hess_q && (flags & OR_PROJECT_REDUCED)) {
+        /* the pair's reduced local block over its distinct nodes, then its
+         * PSD projection */
+        int32_t nodes[16];
+        int m = 0;
+        for (int a = 0; a < 4; ++a)
+          for (int32_t ka = sc->rowptr[vid[a]]; ka < sc->rowptr[vid[a] + 1]; ++ka) {
+            int f = 0;
+            for (int t = 0; t < m; ++t) f |= nodes[t] == sc->col[ka];
+            if (!f) nodes[m++] = sc->col[ka];
+          }
+        static _Thread_local double K[48 * 48], PK[48 * 48];
+        int n3 = 3 * m;
+        memset(K, 0, sizeof(double) * n3 * n3);
+        for (int a = 0; a < 4; ++a)
+          for (int32_t ka = sc->rowptr[vid[a]]; ka < sc->rowptr[vid[a] + 1]; ++ka) {
+            int I = 0;
+            while (nodes[I] != sc->col[ka]) ++I;
+            for (int b = 0; b < 4; ++b)
+              for (int32_t kb = sc->rowptr[vid[b]]; kb < sc->rowptr[vid[b] + 1]; ++kb) {
+                int J = 0;
+                while (nodes[J] != sc->col[kb]) ++J;
+                double wab = sc->val[ka] * sc->val[kb];
+                for (int i = 0; i < 3; ++i)
+                  for (int j = 0; j < 3; ++j) K[(3 * I + i) * n3 + 3 * J + j] += wab * H[(3 * a + i) * 12 + 3 * b + j];
+              }
+          }
+        if (m > 0) or_project_psd(n3, K, PK);
+        for (int I = 0; I < m; ++I)
+          for (int J = 0; J < m; ++J)
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j) {
+                int64_t idx = (3 * (int64_t)nodes[I] + i) * nd + 3 * nodes[J] + j;
+                nsum(&hess_q[idx], &hc[idx], PK[(3 * I + i) * n3 + 3 * J + j]);
+              }
+        if (grad_q)
+          for (int a = 0; a < 4; ++a)
+            for (int32_t ka = sc->rowptr[vid[a]]; ka < sc->rowptr[vid[a] + 1]; ++ka)
+              for (int i = 0; i < 3; ++i)
+                nsum(&grad_q[3 * sc->col[ka] + i], &gc[3 * sc->col[ka] + i], sc->val[ka] * g[3 * a + i]);
+        continue;
+      }
       const double *Hu = H;
       if (hess_q && (flags & OR_PROJECT)) {
         or_project_psd(12, H, P);

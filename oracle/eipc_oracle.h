@@ -25,7 +25,8 @@ typedef struct {
   const double *x_rest;    /* [n_vert*3] rest positions (EE mollifier) or NULL */
 } or_scene;
 
-enum { OR_ENERGY = 1, OR_GRAD = 2, OR_HESS = 4, OR_PROJECT = 8, OR_MOLLIFY = 16, OR_SQDIST = 32 };
+enum { OR_ENERGY = 1, OR_GRAD = 2, OR_HESS = 4, OR_PROJECT = 8, OR_MOLLIFY = 16, OR_SQDIST = 32,
+       OR_PROJECT_REDUCED = 64 /* or_barrier_reduce: project each pair's reduced local block W^T H W */ };
 enum { OR_OK = 0, OR_INACTIVE = 1, OR_ERR_INTERSECTING = -3, OR_ERR_NONFINITE = -5,
        OR_ERR_CAPACITY = -2 };
 

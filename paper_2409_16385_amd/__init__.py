@@ -8,7 +8,7 @@ every compute call needs the built library and a ROCm device and raises
 otherwise.
 """
 from .binding import (  # noqa: F401
-    ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST, EipcError, Context, Scene, lib_path,
+    ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST, PROJECT_REDUCED, EipcError, Context, Scene, lib_path,
     embed, build_candidates, barrier_reduce, ccd_max_step, barrier_hvp,
     narrow_phase, pair_eval, ccd_candidates, ccd_toi, fp64_selftest, bsr_to_dense,
     cholesky, cholesky_solve, Plan, StepOut, set_tuning, set_ccd_method, CCD_ADDITIVE, CCD_CLOSEST_DIRECTION,

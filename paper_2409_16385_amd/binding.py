@@ -12,7 +12,7 @@ import os
 import numpy as np
 import torch
 
-ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST = 1, 2, 4, 8, 16, 32
+ENERGY, GRAD, HESS, PROJECT, MOLLIFY, SQDIST, PROJECT_REDUCED = 1, 2, 4, 8, 16, 32, 64
 OK, ERR_ARG, ERR_CAPACITY, ERR_INTERSECTING, ERR_DEGENERATE, ERR_NONFINITE, ERR_HIP = 0, -1, -2, -3, -4, -5, -6
 WARN_CCD_CAPPED = 1
 

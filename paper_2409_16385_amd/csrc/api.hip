@@ -508,6 +508,8 @@ eipc_status eipc_barrier_hvp(eipc_ctx *c, const eipc_scene *sc, const double *q,
   if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && !pt) || (n_ee > 0 && !ee) || (sc->n_node > 0 && (!q || !v || !out)))
     return set_err(c, EIPC_ERR_ARG, "bad HVP arguments");
   EIPC_TRY(check_mollify(c, sc, flags));
+  if (flags & EIPC_PROJECT_REDUCED)
+    return set_err(c, EIPC_ERR_ARG, "EIPC_PROJECT_REDUCED projects reduced blocks: not for per-pair outputs");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   const int64_t n3 = (int64_t)PSTRIDE * sc->n_vert;
@@ -536,6 +538,8 @@ eipc_status eipc_barrier_hvp_noalloc(eipc_ctx *c, const eipc_scene *sc, const do
   if (n_pt < 0 || n_ee < 0 || (n_pt > 0 && !pt) || (n_ee > 0 && !ee) || (sc->n_node > 0 && (!q || !v || !out)))
     return set_err(c, EIPC_ERR_ARG, "bad HVP arguments");
   EIPC_TRY(check_mollify(c, sc, flags));
+  if (flags & EIPC_PROJECT_REDUCED)
+    return set_err(c, EIPC_ERR_ARG, "EIPC_PROJECT_REDUCED projects reduced blocks: not for per-pair outputs");
   // carve the fixed array: counters, positions of q and of v, active lists
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t pos = up(sizeof(double) * PSTRIDE * (size_t)sc->n_vert + 64);
@@ -683,6 +687,8 @@ eipc_status eipc_pair_eval(eipc_ctx *c, const eipc_scene *sc, const double *q, i
   EIPC_TRY(check_dhat(c, dhat));
   if ((kind != 0 && kind != 1) || n < 0 || (n > 0 && !pairs)) return set_err(c, EIPC_ERR_ARG, "bad pair arguments");
   EIPC_TRY(check_mollify(c, sc, flags));
+  if (flags & EIPC_PROJECT_REDUCED)
+    return set_err(c, EIPC_ERR_ARG, "EIPC_PROJECT_REDUCED projects reduced blocks: not for per-pair outputs");
   hipStream_t s = (hipStream_t)stream;
   EIPC_HIP(c, hipSetDevice(c->device));
   double *xs;

@@ -766,19 +766,22 @@ static eipc_status sort_active(eipc_ctx *c, const eipc_scene *sc, int kind, cons
 constexpr int TERMS_T = 256;      // four wavefronts, one per SIMD (the 9x9 projection's registers)
 constexpr int TERMS_TILE = 2048;  // pairs per class-sorted tile
 
-template <int KIND>
+template <int KIND, bool REDUCED>
 __global__ __launch_bounds__(TERMS_T) void k_pair_terms(
     const int32_t *__restrict__ pairs, const int32_t *__restrict__ act, const int32_t *__restrict__ typ,
     const int4 *__restrict__ vid4, const int64_t *__restrict__ d_count, int64_t cap,
     const int32_t *__restrict__ faces, const int32_t *__restrict__ edges, const double *__restrict__ xs,
     const double *__restrict__ x_rest, int n_vert, double dhat, double kappa, uint32_t flags, bool want_g,
     bool want_h, double *energy, double *__restrict__ rec, const int32_t *__restrict__ vscene, int n_scene,
-    uint32_t *status) {
+    uint32_t *status, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+    const double *__restrict__ val) {
   __shared__ int s_tile[TERMS_TILE];
   __shared__ int s_cnt[4];
   __shared__ double s_e[TERMS_T / 64];
   const bool expand = want_g || want_h;
-  const bool project = flags & EIPC_PROJECT;
+  // the reduced-block projection takes the true X and projects after the transform
+  const bool reduced = REDUCED && want_h;
+  const bool project = (flags & EIPC_PROJECT) && !reduced;
   const bool sq = flags & EIPC_SQDIST;
   const bool moll = (KIND == 1) && (flags & EIPC_MOLLIFY) && x_rest;
   const int lane = threadIdx.x & 63;
@@ -879,6 +882,36 @@ __global__ __launch_bounds__(TERMS_T) void k_pair_terms(
         if (expand) {
           double tv[54];
           e_pair = pair_qterms<KIND>(cls, ty, x, eps, dhat, kappa, want_g, want_h, project, sq, tv, tv + 9);
+          if (reduced) {
+            // dot products of the four vertices' rows of W
+            int cc[4][4];
+            double ww[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int k0 = rowptr[vid[a]];
+              const int n = rowptr[vid[a] + 1] - k0;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const bool v = k < n;
+                cc[a][k] = v ? col[k0 + k] : -1 - (4 * a + k);
+                ww[a][k] = v ? val[k0 + k] : 0.0;
+              }
+            }
+            double M4[16];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = a; b < 4; ++b) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                  for (int l = 0; l < 4; ++l) acc += cc[a][k] == cc[b][l] ? ww[a][k] * ww[b][l] : 0.0;
+                M4[a * 4 + b] = acc;
+                M4[b * 4 + a] = acc;
+              }
+            reduced_block_projection(M4, tv + 9);
+          }
           double2 *r2 = (double2 *)(rec + i * TERM_REC);
           const int nst = want_h ? 27 : 5;
 #pragma unroll
@@ -926,14 +959,23 @@ eipc_status launch_barrier(eipc_ctx *c, const eipc_scene *sc, int kind, const do
   const int nsc = n_scene_of(sc);
   {
     ProfScope ps(c, kind == 0 ? K_BARRIER_PT : K_BARRIER_EE, s);
-    if (kind == 0)
-      k_pair_terms<0><<<blocks, TERMS_T, 0, s>>>(pairs, act, typ, vid4, d_count, cap, sc->faces, sc->edges, xs,
-                                              sc->x_rest, sc->n_vert, dhat, kappa, flags, want_g, want_h, energy,
-                                              rec, vsc, nsc, c->status);
-    else
-      k_pair_terms<1><<<blocks, TERMS_T, 0, s>>>(pairs, act, typ, vid4, d_count, cap, sc->faces, sc->edges, xs,
-                                              sc->x_rest, sc->n_vert, dhat, kappa, flags, want_g, want_h, energy,
-                                              rec, vsc, nsc, c->status);
+#define EIPC_TERMS_LAUNCH(K, R)                                                                                    \
+  k_pair_terms<K, R><<<blocks, TERMS_T, 0, s>>>(pairs, act, typ, vid4, d_count, cap, sc->faces, sc->edges, xs,        \
+                                                sc->x_rest, sc->n_vert, dhat, kappa, flags, want_g, want_h, energy, \
+                                                rec, vsc, nsc, c->status, sc->W_rowptr, sc->W_col, sc->W_val)
+    const bool reduced = want_h && (flags & EIPC_PROJECT_REDUCED);
+    if (kind == 0) {
+      if (reduced)
+        EIPC_TERMS_LAUNCH(0, true);
+      else
+        EIPC_TERMS_LAUNCH(0, false);
+    } else {
+      if (reduced)
+        EIPC_TERMS_LAUNCH(1, true);
+      else
+        EIPC_TERMS_LAUNCH(1, false);
+    }
+#undef EIPC_TERMS_LAUNCH
     EIPC_HIP(c, hipGetLastError());
   }
   if (!want_g && !want_h) return EIPC_OK;

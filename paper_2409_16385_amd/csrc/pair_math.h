@@ -681,6 +681,32 @@ __device__ __forceinline__ void project_psd(double *a) {
 
 __device__ __forceinline__ void project_psd9(double *a) { project_psd<9>(a); }
 
+// Symmetric eigendecomposition of a packed N x N matrix by the same cyclic
+// Jacobi sweeps: on return the diagonal of a holds the eigenvalues and the
+// columns of v (row-major N x N) the eigenvectors.
+template <int N>
+__device__ __forceinline__ void jacobi_eig(double *a, double *v) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[i * N + j] = (i == j) ? 1.0 : 0.0;
+  double fro2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) fro2 += (i == j ? 1.0 : 2.0) * a[pidxn<N>(i, j)] * a[pidxn<N>(i, j)];
+  const double thr = 1e-20 * sqrt(fro2);
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    double off = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i + 1; j < N; ++j) off += a[pidxn<N>(i, j)] * a[pidxn<N>(i, j)];
+    if (__all(!(off > 1e-30 * fro2))) break;
+    jacobi_sweep_from<N, 0, 1>(a, v, thr);
+  }
+}
+
 // 3x3 block (a, b) of H_x = Q X Q^T from X packed in the Q basis.
 __device__ __forceinline__ void x_block(const double *X, int a, int b, double *B) {
 #pragma unroll
@@ -1087,6 +1113,85 @@ __device__ __forceinline__ bool static_boxes_overlap(const V3 *x, double h) {
 // FILTER: the pairs are swept candidates; only those that pass the
 // candidate predicate at the start positions are considered, and their
 // number is added to *cand_count.
+// Alternative projection: the PSD projection of the pair's reduced local
+// block K = Z^T X Z (Z: the 9 x 3m map from the pair's m merged nodes, node
+// I's block z_I (x) I3 with z_I = sum_{slots of I} w Q[a]) instead of X.
+// With G3 = sum_I z_I z_I^T = V L V^T and R = V L^{1/2}, U = R^+ Z has
+// orthonormal rows and Z = (R (x) I3) U, so
+//   proj(K) = U^T proj((R^T (x) I3) X (R (x) I3)) U,
+// and X is replaced by X_eff = (R^+T (x) I3) proj(X') (R^+ (x) I3) with
+// X' = (R^T (x) I3) X (R (x) I3): the reduction B(I, J) = z_I^T X z_J then
+// gives proj(K)'s blocks.  G3 = Q^T M Q with M_ab = w_a . w_b, the dot
+// products of the four vertices' rows of W; directions of G3 below 1e-12
+// of its largest eigenvalue (the z_I have no component there) are dropped.
+__device__ __forceinline__ void reduced_block_projection(const double *M4, double *X) {
+  // G3 (packed 3x3)
+  double G[6];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int be = al; be < 3; ++be) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc += (0.25 * (double)(qsign(a, al) * qsign(b, be))) * M4[a * 4 + b];
+      G[pidxn<3>(al, be)] = acc;
+    }
+  double V[9];
+  jacobi_eig<3>(G, V);
+  double lmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) lmax = fmax(lmax, G[pidxn<3>(k, k)]);
+  double R[9], Rp[9];  // R[al][k], Rp[k][al]
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double lam = G[pidxn<3>(k, k)];
+    const bool keep = lam > 1e-12 * lmax;
+    const double sq = keep ? sqrt(lam) : 0.0, isq = keep ? 1.0 / sqrt(lam) : 0.0;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      R[al * 3 + k] = V[al * 3 + k] * sq;
+      Rp[k * 3 + al] = V[al * 3 + k] * isq;
+    }
+  }
+  double Xp[45];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = k; l < 3; ++l)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (k == l && c < r) continue;
+          double acc = 0.0;
+#pragma unroll
+          for (int al = 0; al < 3; ++al)
+#pragma unroll
+            for (int be = 0; be < 3; ++be) acc += (R[al * 3 + k] * R[be * 3 + l]) * X[pidx(3 * al + r, 3 * be + c)];
+          Xp[pidx(3 * k + r, 3 * l + c)] = acc;
+        }
+  project_psd<9>(Xp);
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int be = al; be < 3; ++be)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (al == be && c < r) continue;
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = 0; l < 3; ++l) acc += (Rp[k * 3 + al] * Rp[l * 3 + be]) * Xp[pidx(3 * k + r, 3 * l + c)];
+          X[pidx(3 * al + r, 3 * be + c)] = acc;
+        }
+}
+
 // signed closest-point weights of a classified pair at positions x (the
 // point minus the closest triangle point for PT, the closest point of edge
 // a minus that of edge b for EE: G x = sum_a beta_a x_a), each product and
