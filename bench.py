@@ -382,6 +382,50 @@ def extra_config4(sc, log):
             "energy_grad_hvp_us": t_h, "timing": "median of 100 synchronized calls"}
 
 
+def extra_formulations(log):
+    """The alternative formulations on one implicit step of config 1's
+    step problem (projected Newton with CCD-clamped backtracking): Newton
+    iterations, the CCD step bounds along the way and the converged
+    position, per barrier form, projection and CCD."""
+    import time
+    import torch
+    import paper_2409_16385_amd as E
+    from paper_2409_16385_amd import adjoint as A
+    dev = torch.device("cuda", 0)
+    ctx = E.Context(0)
+    prob, _ = A.build_config1_step(ctx)
+    variants = [("distance barrier, per-pair projection, additive CCD", 0, False, E.CCD_ADDITIVE),
+                ("squared-distance barrier", E.SQDIST, False, E.CCD_ADDITIVE),
+                ("reduced-block projection", 0, True, E.CCD_ADDITIVE),
+                ("closest-direction CCD", 0, False, E.CCD_CLOSEST_DIRECTION)]
+    out, q_base = [], None
+    kappa0 = prob.kappa
+    for name, bf, red, ccd in variants:
+        prob.barrier_flags, prob.reduced_projection = bf, red
+        # the squared-distance barrier is about dhat^2 smaller at equal
+        # kappa: its stiffness is rescaled so that both forms give the same
+        # energy at d = dhat / sqrt(2)
+        prob.kappa = kappa0 * (A.SQDIST_KAPPA_FACTOR / prob.dhat ** 2 if bf & E.SQDIST else 1.0)
+        E.set_ccd_method(ctx, ccd)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        q, info = A.solve_step(prob)
+        torch.cuda.synchronize(dev)
+        ms = (time.perf_counter() - t0) * 1e3
+        if q_base is None:
+            q_base = q
+        dn = float(torch.linalg.vector_norm(q_base - prob.q_n))
+        ent = {"formulation": name, "kappa": prob.kappa, "converged": info["converged"],
+               "newton_iters": info["iters"], "true_hessian_steps": info["true_hessian_steps"],
+               "alpha_ccd": [round(a, 6) for a in info["alpha_ccd"]], "alpha_taken": [round(a, 6) for a in info["alpha"]],
+               "solve_ms": ms, "q_vs_first_rel": float(torch.linalg.vector_norm(q - q_base)) / dn if dn > 0 else 0.0}
+        log(f"formulation {name}: {info['iters']} Newton iterations, CCD alphas {ent['alpha_ccd'][:4]}, {ms:.1f} ms")
+        out.append(ent)
+    E.set_ccd_method(ctx, E.CCD_ADDITIVE)
+    prob.kappa = kappa0
+    return {"workload": f"one implicit step of config 1's step problem ({prob.n} reduced DoF)", "variants": out}
+
+
 def extra_batch(scenes_list, log, steps=10):
     """The batched form: one planned step over the ragged batch, graph
     replays, against the same scenes as sequential single-scene steps."""
@@ -666,6 +710,7 @@ def main():
         jobs = (("config1", lambda: extra_config1(extra_scenes["config1"], log)),
                 ("config3", lambda: extra_single(extra_scenes["config3"], log, E.MOLLIFY)),
                 ("config4", lambda: extra_config4(extra_scenes["config1"], log)),
+                ("formulations", lambda: extra_formulations(log)),
                 ("batch", lambda: extra_batch(extra_batch_scenes, log)))
         for key, job in jobs:
             t0 = time.perf_counter()

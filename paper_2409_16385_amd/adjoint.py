@@ -78,6 +78,11 @@ class StepProblem:
     kin_rows: np.ndarray     # vertex indices of the kinematic body
     kin_rest: np.ndarray     # their rest positions [k, 3]
     theta: np.ndarray        # pose (tx, ty, tz, rx, ry, rz)
+    # barrier formulation: B.SQDIST for the squared-distance form, and
+    # reduced_projection for the projection of each pair's reduced block
+    # (B.PROJECT_REDUCED) in place of the per-pair B.PROJECT
+    barrier_flags: int = 0
+    reduced_projection: bool = False
 
     @property
     def n(self) -> int:
@@ -157,10 +162,16 @@ def build_config1_step(ctx: B.Context, grid_dims=(5, 5, 5), seed: int = 0, n_sam
     return build_step(ctx, step_inputs(seed, grid_dims=grid_dims, n_samples=n_samples, **kw))
 
 
+# kappa for the squared-distance barrier with the distance form's energy at
+# d = dhat / sqrt(2): kappa_sq = kappa * SQDIST_KAPPA_FACTOR / dhat^2
+# (b(d) = dhat^2 (1 - 1/sqrt2)^2 ln2 / 2 there, b(s) = dhat^4 ln2 / 4)
+SQDIST_KAPPA_FACTOR = 2.0 * (1.0 - 0.5 ** 0.5) ** 2
+
+
 def _contact(prob: StepProblem, q, flags, hess):
     pt, ee = B.build_candidates(prob.ctx, prob.scene, q, prob.dhat)
-    r = B.barrier_reduce(prob.ctx, prob.scene, q, pt, ee, prob.dhat, prob.h ** 2 * prob.kappa, flags, hess=hess,
-                         count=False)
+    r = B.barrier_reduce(prob.ctx, prob.scene, q, pt, ee, prob.dhat, prob.h ** 2 * prob.kappa,
+                         flags | prob.barrier_flags, hess=hess, count=False)
     return r, pt, ee
 
 
@@ -176,7 +187,8 @@ def energy(prob: StepProblem, q) -> float:
 
 def gradient_hessian(prob: StepProblem, q, project: bool):
     qt = prob.q_n + prob.h * prob.v_n
-    flags = B.ENERGY | B.GRAD | B.HESS | (B.PROJECT if project else 0)
+    proj = B.PROJECT_REDUCED if prob.reduced_projection else B.PROJECT
+    flags = B.ENERGY | B.GRAD | B.HESS | (proj if project else 0)
     r, pt, ee = _contact(prob, q, flags, "dense")
     g = prob.M @ (q - qt) + prob.h ** 2 * (prob.K @ (q - prob.q_rest) - prob.f) + r["grad"]
     H = prob.M + prob.h ** 2 * prob.K + r["hess"]
@@ -192,13 +204,14 @@ def solve_step(prob: StepProblem, tol: float = 1e-12, max_iter: int = 100, verbo
     qt = prob.q_n + prob.h * prob.v_n
     scale = float(torch.linalg.vector_norm(prob.M @ qt))
     it = 0
-    info = {"iters": 0, "true_hessian_steps": 0}
+    info = {"iters": 0, "true_hessian_steps": 0, "alpha_ccd": [], "alpha": [], "converged": False}
     for it in range(max_iter):
         g, H, _ = gradient_hessian(prob, q, project=False)
         gn = float(torch.linalg.vector_norm(g))
         if verbose:
             print(f"newton {it}: |g| = {gn:.3e} (rel {gn / scale:.3e})")
         if gn <= tol * scale:
+            info["converged"] = True
             break
         L = H.clone()
         used_true = B.cholesky(prob.ctx, L) == 0
@@ -214,15 +227,19 @@ def solve_step(prob: StepProblem, tol: float = 1e-12, max_iter: int = 100, verbo
         # the predicted decrease (half the Newton decrement) is below the
         # rounding level of the energy: nothing left to gain
         if -0.5 * slope <= 1e-15 * abs(e0):
+            info["converged"] = True
             break
         alpha, _, _ = B.ccd_max_step(prob.ctx, prob.scene, q, dq, prob.dhat)
         alpha = min(1.0, alpha)
+        info["alpha_ccd"].append(alpha)
         while True:
             q1 = q + alpha * dq
             if energy(prob, q1) <= e0 + 1e-4 * alpha * slope or alpha < 1e-12:
                 break
             alpha *= 0.5
+        info["alpha"].append(alpha)
         if float(torch.linalg.vector_norm(q1 - q)) == 0.0:
+            info["converged"] = True
             break
         q = q1
     info["iters"] = it
@@ -248,7 +265,7 @@ def adjoint(prob: StepProblem, q_star, dLdq):
     zero = torch.zeros(prob.n, dtype=torch.float64, device=prob.ctx.torch_device)
     dth = np.zeros(6)
     for k in range(6):
-        cross = B.barrier_hvp(prob.ctx, prob.scene, q_star, pt, ee, prob.dhat, prob.h ** 2 * prob.kappa, 0, zero,
-                              T[k].contiguous())
+        cross = B.barrier_hvp(prob.ctx, prob.scene, q_star, pt, ee, prob.dhat, prob.h ** 2 * prob.kappa,
+                              prob.barrier_flags & B.SQDIST, zero, T[k].contiguous())
         dth[k] = -float(lam @ cross)
     return dq_n, dv_n, dth, used_true

@@ -215,3 +215,30 @@ def test_large_reduced_system_step_and_adjoint(ctx):
     res = float(torch.linalg.vector_norm(H @ lam - b) / torch.linalg.vector_norm(b))
     assert res <= 1e-12, res
     assert torch.allclose(prob.M @ lam, dq_n, rtol=1e-12, atol=1e-12 * float(dq_n.abs().max()))
+
+
+@pytest.mark.parametrize("variant", ["sqdist", "reduced", "closest_direction"])
+def test_step_converges_under_each_formulation(ctx, variant):
+    """The implicit step under the alternative formulations converges to a
+    position near the distance-barrier step's (the same problem up to the
+    barrier's form inside dhat)."""
+    prob, _ = A.build_config1_step(ctx)
+    q0, info0 = A.solve_step(prob)
+    if variant == "sqdist":
+        prob.barrier_flags = E.SQDIST
+        prob.kappa *= A.SQDIST_KAPPA_FACTOR / prob.dhat ** 2
+    elif variant == "reduced":
+        prob.reduced_projection = True
+    else:
+        E.set_ccd_method(ctx, E.CCD_CLOSEST_DIRECTION)
+    try:
+        q1, info1 = A.solve_step(prob)
+    finally:
+        E.set_ccd_method(ctx, E.CCD_ADDITIVE)
+    assert info0["converged"] and info1["converged"] and len(info1["alpha_ccd"]) > 0
+    dn = float(torch.linalg.vector_norm(q0 - prob.q_n))
+    rel = float(torch.linalg.vector_norm(q1 - q0)) / dn
+    if variant == "sqdist":
+        assert rel < 0.5  # another barrier: close, not equal
+    else:
+        assert rel < 1e-6  # the same minimizer
