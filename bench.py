@@ -33,14 +33,14 @@ PEAK_HBM_GBS = 8000.0
 # symmetric eigendecomposition of the 9x9 translation-free Hessian
 # 9 n^3 = 6,561 and the reconstruction V max(L, 0) V^T ~2e3.  Expansion
 # through W (16 weights, merged nodes, blocks and gradient): ~4.6e3.  The
-# barrier kernel does both for every active pair (the class-specialised
-# projections execute fewer flops than the nominal 9x9 count for
-# point-point and point-line pairs).  Algorithmic bytes per active pair
-# for the whole barrier + reduction: the pair record, its share of the
-# gathered geometry and of the outputs, ~85 B at config 2's reuse.
+# pair-terms kernel ("barrier" scope) does the first for every active pair
+# (its class-specialised projections execute fewer flops than the nominal
+# 9x9 count for point-point and point-line pairs), the expansion kernel the
+# second.  Algorithmic bytes per active pair for the whole barrier +
+# reduction: the pair record, its share of the gathered geometry and of the
+# outputs, ~85 B at config 2's reuse.
 FLOPS_TERMS = 1000 + 300 + 6561 + 2000
 FLOPS_EXPAND = 4600
-FLOPS_BARRIER = FLOPS_TERMS + FLOPS_EXPAND
 BYTES_BARRIER_PAIR = 85
 FAMILIES = {
     "query": ("query_count_pt", "query_count_ee", "query_write_pt", "query_write_ee"),
@@ -199,7 +199,7 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
         # FP64-bound: ~1.5e4 algorithmic flop against ~85 B per pair is far
         # above the ridge (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B)
         kind = 0 if kdom.endswith("_pt") else 1
-        per_pair = FLOPS_BARRIER if dom == "barrier" else FLOPS_EXPAND
+        per_pair = FLOPS_TERMS if dom == "barrier" else FLOPS_EXPAND
         per = per_pair * work["active"][kind]
         ach = per / avg_s / 1e12
         ent.update(bound="alu", achieved=ach, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
@@ -244,7 +244,7 @@ def _rooflines(prof, n_steps, work, workload, tuning=None):
     for k, kind in (("barrier_pt", 0), ("barrier_ee", 1)):
         if prof.get(k, (0, 0))[1]:
             s_ = prof[k][0] / prof[k][1] / 1e3
-            ent[f"{k}_tflops"] = FLOPS_BARRIER * work["active"][kind] / s_ / 1e12
+            ent[f"{k}_tflops"] = FLOPS_TERMS * work["active"][kind] / s_ / 1e12
     for k, kind in (("expand_pt", 0), ("expand_ee", 1)):
         if prof.get(k, (0, 0))[1]:
             s_ = prof[k][0] / prof[k][1] / 1e3

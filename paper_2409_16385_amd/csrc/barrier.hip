@@ -276,7 +276,7 @@ __device__ __forceinline__ void agg_scene_add(double *out, bool valid, int scene
 // packed upper triangle of LN x LN 3x3 FP64 blocks addressed
 // arithmetically, the gradient in LN 3-vectors.  A node that finds no slot
 // (the table is full) goes straight to the outputs.  Between steps the
-// accumulator is flushed into the outputs once it holds more than LN / 4
+// accumulator is flushed into the outputs once it holds more than LN / 2
 // nodes (each touched block once).
 // ---------------------------------------------------------------------------
 constexpr int EX_T = 512;                // eight wavefronts, two per SIMD
@@ -285,6 +285,7 @@ constexpr int EX_STEP = EX_T / 16 * EX_PPG;  // pairs per step (256)
 constexpr int LN = 60;                   // local node slots
 constexpr int LNB = LN * (LN + 1) / 2;   // their upper 3x3 blocks (129 KiB)
 constexpr int LN_PROBE = 16;
+constexpr int EX_TRI = 16 * 17 / 2;      // blocks of a pair's (at most 16) merged nodes
 
 struct LocalAcc {
   int *nkey;               // LN: node of the slot, -1 = empty
@@ -402,15 +403,60 @@ __device__ __forceinline__ int tri_root(int t) {
 // runs of equal nodes summed (the run's last lane keeps the total), and the
 // m distinct nodes packed in order onto lanes 0 .. m-1 of the group, which
 // look up their local indices.  Node I's gradient is sum_alpha z_I[alpha]
-// gamma_alpha; the m(m+1)/2 blocks I <= J are dealt to the group's lanes
-// (block t on lane t mod 16),
+// gamma_alpha; the merged nodes are staged in LDS and the m(m+1)/2 blocks
+// I <= J dealt to the group's lanes (block t on lane t mod 16, its (I, J)
+// from a table),
 //   B(I, J) = sum_{alpha, beta} z_I[alpha] z_J[beta] X[alpha][beta].
 // All 64 lanes call, in wavefront-uniform control flow.
+// A merged node of a pass, staged in LDS for the group's block lanes.
+struct NodeRec {
+  double z[3];
+  int node;  // NO_NODE past the group's m nodes
+  int li;    // local index, -1 = none
+};
+
+// One block of the pass: B(I, J) = sum_{alpha, beta} z_I[alpha] z_J[beta]
+// X[alpha][beta] into the accumulator.  A local block holds the rows of the
+// lower local index: when that is J's, B(J, I) = B(I, J)^T is formed
+// directly by exchanging the two nodes' roles (X is symmetric), so no
+// element is picked by a run-time index.
+__device__ __forceinline__ void expand_block(const LocalAcc &L, const HessOut &h, int n_node, uint32_t *status,
+                                             const double *Xo, const NodeRec &RI, const NodeRec &RJ) {
+  const bool both = RI.li >= 0 && RJ.li >= 0;
+  const bool tr = both && RI.li > RJ.li;
+  double w[9];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int be = 0; be < 3; ++be) w[3 * al + be] = (tr ? RJ.z[al] : RI.z[al]) * (tr ? RI.z[be] : RJ.z[be]);
+  double B[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int be = 0; be < 3; ++be) acc += w[3 * al + be] * Xo[pidx(3 * al + r, 3 * be + c)];
+      B[3 * r + c] = acc;
+    }
+  if (both) {
+    const int slot = tr ? ltri(RJ.li, RI.li) : ltri(RI.li, RJ.li);
+#pragma unroll
+    for (int u = 0; u < 9; ++u) atomicAdd(&L.bval[9 * slot + u], B[u]);
+    L.touched[slot] = 1;
+  } else {
+    global_block_add(h, n_node, RI.node, RJ.node, B, status);
+  }
+}
+
 __device__ __forceinline__ void expand_wave(const LocalAcc &L, const HessOut &h, int n_node, double *grad,
                                             uint32_t *status, const int32_t *__restrict__ rowptr,
                                             const int32_t *__restrict__ col, const double *__restrict__ val,
                                             bool own, const int *vid, const double *__restrict__ rec, int64_t i0,
-                                            bool want_g, bool want_h) {
+                                            bool want_g, bool want_h, NodeRec *nstage,
+                                            const uint16_t *__restrict__ tri_ij) {
   const int lane = threadIdx.x & 63;
   const int s = lane & 15;
   const int gbase = lane & ~15;
@@ -543,55 +589,30 @@ __device__ __forceinline__ void expand_wave(const LocalAcc &L, const HessOut &h,
       }
     }
     if (want_h) {
+      // the group's merged nodes go to its LDS stage (the previous pass's
+      // reads of it come first in the wavefront's program order)
+      NodeRec *ns = nstage + gbase;
+      if (has) {
+        NodeRec r;
+        r.z[0] = cz[0];
+        r.z[1] = cz[1];
+        r.z[2] = cz[2];
+        r.node = cnode;
+        r.li = cli;
+        ns[s] = r;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const double *Xo = tv + 9;
       const int nb = (m * (m + 1)) >> 1;
       for (int t0 = 0;; t0 += 16) {
         const int t = t0 + s;
         const bool vb = t < nb;
         if (!__any(vb)) break;
-        int I = 0, J = 0;
         if (vb) {
-          J = tri_root(t);
-          I = t - ((J * (J + 1)) >> 1);
-        }
-        const int nI = __shfl(cnode, gbase + I, 64), nJ = __shfl(cnode, gbase + J, 64);
-        const int lI = __shfl(cli, gbase + I, 64), lJ = __shfl(cli, gbase + J, 64);
-        double zI[3], zJ[3];
-#pragma unroll
-        for (int al = 0; al < 3; ++al) {
-          zI[al] = __shfl(cz[al], gbase + I, 64);
-          zJ[al] = __shfl(cz[al], gbase + J, 64);
-        }
-        if (vb) {
-          double w[9];
-#pragma unroll
-          for (int al = 0; al < 3; ++al)
-#pragma unroll
-            for (int be = 0; be < 3; ++be) w[3 * al + be] = zI[al] * zJ[be];
-          double B[9];
-#pragma unroll
-          for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              double acc = 0.0;
-#pragma unroll
-              for (int al = 0; al < 3; ++al)
-#pragma unroll
-                for (int be = 0; be < 3; ++be) acc += w[3 * al + be] * Xo[pidx(3 * al + r, 3 * be + c)];
-              B[3 * r + c] = acc;
-            }
-          if (lI >= 0 && lJ >= 0) {
-            // rows of the lower local index
-            const bool tr = lI > lJ;
-            const int slot = tr ? ltri(lJ, lI) : ltri(lI, lJ);
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-              for (int c = 0; c < 3; ++c) atomicAdd(&L.bval[9 * slot + 3 * r + c], tr ? B[3 * c + r] : B[3 * r + c]);
-            L.touched[slot] = 1;
-          } else {
-            global_block_add(h, n_node, nI, nJ, B, status);
-          }
+          const uint32_t ij = tri_ij[t];
+          expand_block(L, h, n_node, status, Xo, ns[ij & 15u], ns[ij >> 8]);
         }
       }
     }
@@ -610,7 +631,13 @@ __global__ __launch_bounds__(EX_T) void k_expand(
   __shared__ double s_gval[LN * 3];
   __shared__ unsigned char s_touched[LNB];
   __shared__ int s_count;
+  __shared__ NodeRec s_nodes[EX_T];       // per wavefront: 4 groups x 16
+  __shared__ uint16_t s_tri[EX_TRI];      // block t -> I | J << 8, I <= J < 16
   LocalAcc L{s_nkey, s_bval, s_touched, s_gval, &s_count};
+  for (int t = threadIdx.x; t < EX_TRI; t += blockDim.x) {
+    const int J = tri_root(t);
+    s_tri[t] = (uint16_t)((t - ((J * (J + 1)) >> 1)) | (J << 8));
+  }
   local_init(L);
   __syncthreads();
   // consecutive ranges on one XCD (workgroups are dealt to the 8 XCDs in turn)
@@ -634,10 +661,11 @@ __global__ __launch_bounds__(EX_T) void k_expand(
         vid[2] = v4.z;
         vid[3] = v4.w;
       }
-      expand_wave(L, h, n_node, grad, status, rowptr, col, val, live, vid, rec, wb, want_g, want_h);
+      expand_wave(L, h, n_node, grad, status, rowptr, col, val, live, vid, rec, wb, want_g, want_h,
+                  s_nodes + 64 * wave, s_tri);
     }
     __syncthreads();
-    if (base + EX_STEP >= r1 || s_count > LN / 4) local_flush(L, h, n_node, want_g ? grad : nullptr, status);
+    if (base + EX_STEP >= r1 || s_count > LN / 2) local_flush(L, h, n_node, want_g ? grad : nullptr, status);
     __syncthreads();
   }
 }

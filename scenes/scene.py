@@ -586,13 +586,15 @@ def grasp_scene(seed: int, obj_nu: int, obj_nodes: int, finger_nu: int,
                        "obj_grid": og.dims, "finger_grid": finger_dims})
 
 
-def config2(seed: int = 0, frac: float = 0.8) -> Scene:
+def config2(seed: int = 0, frac: float = 0.75) -> Scene:
     """Bubble-gripper grasp: blob of frequency 71 (100,820 f, r0 = 0.04 m,
     SH order 8, 10 % amplitude) in a ~2,000-node grid, two ellipsoidal
     membranes (semi-axes 0.015 x 0.04 x 0.06 m, x the grasp axis, frequency
     32, 20,480 f each) in 5x10x10-node grids, pressed onto the object over
     ``frac`` of their semi-axes with gaps dhat U(0.1, 0.9).  dhat = 5e-4 m,
-    kappa = 1e3, dq ~ N(0, 1e-3 m)."""
+    kappa = 1e3, dq ~ N(0, 1e-3 m).  The default closure puts 483,655 pairs
+    within dhat at seed 0 (2,453,031 candidates), inside the 1e5 - 5e5 band
+    the workload asks for; 0.8 would give 520,384."""
     return grasp_scene(seed, 71, 2000, 32, frac=frac, name="config2")
 
 

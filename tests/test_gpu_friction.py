@@ -97,7 +97,7 @@ def test_friction_config1_against_oracle(ctx):
 
 
 def test_friction_config2_energy_and_gradient(ctx):
-    """Full size (520,384 lagged active pairs), sliding and static mixed."""
+    """Full size (483,655 lagged active pairs), sliding and static mixed."""
     sc = config2()
     dsc = E.Scene.from_host(ctx, sc)
     xn = O.embed(sc, sc.q)
