@@ -620,8 +620,11 @@ __device__ __forceinline__ void expand_wave(const LocalAcc &L, const HessOut &h,
 }
 
 // Reduction of per-pair term records (pairs in locality order with their
-// vertex ids): a workgroup takes a contiguous range, 64 pairs per
-// wavefront step.
+// vertex ids): a workgroup takes a contiguous range, 32 pairs per
+// wavefront and step.  Instantiated per pair kind (the code is the same)
+// so that the two launches of a step carry their own names in kernel
+// traces.
+template <int KIND>
 __global__ __launch_bounds__(EX_T) void k_expand(
     const int4 *__restrict__ vid4, const int64_t *__restrict__ d_count, const int32_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const double *__restrict__ val, int n_node, const double *__restrict__ rec,
@@ -1018,8 +1021,12 @@ eipc_status launch_expand(eipc_ctx *c, const eipc_scene *sc, int kind, const int
   const int blocks =
       (int)std::max<int64_t>(1, std::min<int64_t>(grid_for(cap, 64), (int64_t)c->wg_per_cu[1] * c->num_cu));
   ProfScope ps(c, kind == 0 ? K_EXPAND_PT : K_EXPAND_EE, s);
-  k_expand<<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, rec, cap, want_g,
-                                   want_h, grad, h, c->status);
+  if (kind == 0)
+    k_expand<0><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, rec, cap,
+                                        want_g, want_h, grad, h, c->status);
+  else
+    k_expand<1><<<blocks, EX_T, 0, s>>>(vid4, d_count, sc->W_rowptr, sc->W_col, sc->W_val, sc->n_node, rec, cap,
+                                        want_g, want_h, grad, h, c->status);
   EIPC_HIP(c, hipGetLastError());
   return EIPC_OK;
 }
