@@ -196,10 +196,11 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
 // the distance and activity test (active pairs appended to act/typ with one
 // atomic per wavefront) come first, then advancement as in k_ccd2 pass 0,
 // reusing the distance just computed.  The pass-1 list is the same.
-// Held to three waves per SIMD (168 VGPRs; the EE form spills 44 bytes per
-// lane): measured faster than the two that its 186 unconstrained VGPRs allow.
+// The PT form is held to three waves per SIMD (168 VGPRs, no spill); the EE
+// form runs at two, where its 189 VGPRs fit without spilling (at three it
+// spilled 68 bytes per lane and was 8 % slower).
 template <int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_narrow_ccd(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 0 ? 3 : 2))) void k_narrow_ccd(
     int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
     const int32_t *__restrict__ edges, const double *__restrict__ xs, const double *__restrict__ ps, double dhat2,
     double h, int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t act_cap, int64_t *count,

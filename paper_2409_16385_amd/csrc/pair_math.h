@@ -1200,20 +1200,23 @@ template <int KIND>
 __device__ __forceinline__ void closest_beta(int type, const V3 *x, double *beta) {
 #pragma clang fp contract(off)
   constexpr const TypeDef *defs = KIND == 0 ? kPT : kEE;
-  beta[0] = beta[1] = beta[2] = beta[3] = 0.0;
   const TypeDef t = defs[type];
+  // vertices are picked and weights placed by selects, never by a run-time
+  // index into x or beta (which would put both in scratch memory)
   if (t.fn == FN_PP) {
-    beta[t.plus[0]] = 1.0;
-    beta[t.minus[0]] = -1.0;
+    const int p0 = t.plus[0], m0 = t.minus[0];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) beta[a] = a == p0 ? 1.0 : (a == m0 ? -1.0 : 0.0);
   } else if (t.fn == FN_PL) {
     // point P = plus[0] against the segment from A = minus[1] to B = plus[1]
-    const V3 y0 = xsub(x[t.plus[0]], x[t.minus[1]]);
-    const V3 y1 = xsub(x[t.plus[1]], x[t.minus[1]]);
+    const int p0 = t.plus[0], m1 = t.minus[1], p1 = t.plus[1];
+    const V3 y0 = xsub(pick4(x, p0), pick4(x, m1));
+    const V3 y1 = xsub(pick4(x, p1), pick4(x, m1));
     const double s = xdot(y0, y1) / xdot(y1, y1);
-    const double sg = (KIND == 0 || t.plus[0] < 2) ? 1.0 : -1.0;  // the point's side
-    beta[t.plus[0]] = sg;
-    beta[t.minus[1]] = -sg * (1.0 - s);
-    beta[t.plus[1]] = -sg * s;
+    const double sg = (KIND == 0 || p0 < 2) ? 1.0 : -1.0;  // the point's side
+    const double bp0 = sg, bm1 = -sg * (1.0 - s), bp1 = -sg * s;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) beta[a] = a == p0 ? bp0 : (a == m1 ? bm1 : (a == p1 ? bp1 : 0.0));
   } else if (KIND == 0) {
     // closest triangle point t0 + u (t1 - t0) + v (t2 - t0)
     const V3 r = xsub(x[0], x[1]), e0 = xsub(x[2], x[1]), e1 = xsub(x[3], x[1]);
