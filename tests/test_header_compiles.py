@@ -1,6 +1,6 @@
 """The C ABI header compiles on its own, as C and as C++ (it is what a
 caller includes; declarations in it are checked against the library's
-exports in test_abi_exports.py)."""
+exports in test_lib_abi.py)."""
 import os
 import shutil
 import subprocess
