@@ -1401,20 +1401,24 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
     int64_t j = p0 > c0 ? p0 : c0;
     const int64_t je = p1 < c0 + nw ? p1 : c0 + nw;
     while (__any(j < je)) {
-      // four partners per lane: entries first (one wait), then the
-      // records of those in the same cell under the lower-corner rule
+      // four partners per lane: their entries and records read from LDS
+      // without conditions (a conditional read kept the previous records
+      // live in registers: ~45 copies per step and 200 VGPRs), then the
+      // same-cell and lower-corner rule and the pair test
       Entry pe[4];
       bool pass[4];
+      int idx[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const bool in = j + u < je;
-        pe[u] = s_ent[in ? (int)(j + u - c0) : 0];
-        pass[u] = in & (pe[u].cell == re.cell) & ((rz | zero_axes(pe[u].dlo)) == 7);
+        idx[u] = j + u < je ? (int)(j + u - c0) : 0;
+        pe[u] = s_ent[idx[u]];
       }
       ItemRec r[4];
 #pragma unroll
+      for (int u = 0; u < 4; ++u) r[u] = s_rec[idx[u]];
+#pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (pass[u]) r[u] = s_rec[(int)(j + u - c0)];
+        pass[u] = (j + u < je) & (pe[u].cell == re.cell) & ((rz | zero_axes(pe[u].dlo)) == 7);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool ok = pass[u] && join_test<KIND>(r[u], qa, qb, qdof, qlo, qhi);
