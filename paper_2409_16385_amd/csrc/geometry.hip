@@ -1287,7 +1287,7 @@ __global__ __launch_bounds__(QT) void k_query_sm(int nq, const double *__restric
 // to hash run per query (k_query_sm on a list).
 // ---------------------------------------------------------------------------
 constexpr int JT = 128;     // rows per workgroup
-constexpr int JWIN = 384;   // item entries staged in LDS per chunk
+constexpr int JWIN = 192;   // item entries staged in LDS per chunk (five workgroups per CU)
 constexpr int JOUT = 1024;  // candidates staged per wavefront
 
 struct JoinArgs {
