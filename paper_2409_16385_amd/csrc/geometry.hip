@@ -1281,8 +1281,9 @@ __global__ __launch_bounds__(QT) void k_query_sm(int nq, const double *__restric
 // the items of its own bucket from LDS: same cell, lower-corner rule
 // (min of the two offsets from the lower cells is zero on every axis),
 // adjacency and DoF rule, exact box overlap.  EE joins the edge hash with
-// itself: row i pairs only with the entries after it in its bucket and
-// reports (min, max).  The row that is a query's lower cell also runs the
+// itself: each row pairs with about half of its bucket (the entries after
+// it, wrapping to the bucket's start), so that every unordered pair of the
+// bucket is tested once, and reports (min, max).  The row that is a query's lower cell also runs the
 // items too large to hash, as in the per-query splits; queries too large
 // to hash run per query (k_query_sm on a list).
 // ---------------------------------------------------------------------------
@@ -1349,16 +1350,34 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
   const bool live = i < r1;
   // the row: its entry, bucket, record and partner range
   Entry re{0, 0, 0};
-  int64_t p0 = 0, p1 = 0;
+  // partners: the entries [pa0, pa1) and then [pb0, pb1) of the row's
+  // bucket [bs, be).  PT: the whole bucket.  EE: the next h entries after
+  // the row, cyclically (wrapping to the bucket's start), with h = (n - 1)
+  // / 2 for a bucket of n entries, plus one for the first half of an even
+  // bucket (its partner n / 2 ahead): every unordered pair of the bucket
+  // once, and every row about half the bucket, where scanning all later
+  // entries left the first rows of a bucket with all of it.
+  int64_t pa0 = 0, pa1 = 0, pb0 = 0, pb1 = 0, bs = 0, be = 0;
   double qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
   int qa = 0, qb = -1, qsc = 0;
   bool qdof = false;
   if (live) {
     re = ja.rows[i];
     const uint32_t b = key_bucket(re.cell, ja.bmask);
-    const int64_t e1 = ja.pbstart[b + 1];
-    p1 = e1 < ja.pent_cap ? e1 : ja.pent_cap;
-    p0 = KIND == 1 ? i + 1 : ja.pbstart[b];
+    const int64_t e0 = ja.pbstart[b], e1 = ja.pbstart[b + 1];
+    be = e1 < ja.pent_cap ? e1 : ja.pent_cap;
+    bs = e0 < be ? e0 : be;
+    if (KIND == 0) {
+      pa0 = bs;
+      pa1 = be;
+    } else {
+      const int64_t n = be - bs, pos = i - bs;
+      const int64_t h = (n - 1) / 2 + ((n % 2 == 0 && pos < n / 2) ? 1 : 0);
+      pa0 = i + 1;
+      pa1 = i + 1 + h < be ? i + 1 + h : be;
+      pb0 = bs;
+      pb1 = bs + (i + 1 + h - be > 0 ? i + 1 + h - be : 0);
+    }
     const ItemRec qr = ja.qrec[re.item];
     qa = qr.v[0];
     qb = qr.v[1];
@@ -1370,11 +1389,11 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
       qhi[a] = qr.hi[a];
     }
   }
-  // window of item entries for the whole tile: first row's range start to
-  // last row's range end (rows are in bucket order)
+  // window of item entries for the whole tile: first row's bucket start to
+  // last row's bucket end (rows are in bucket order)
   const int rz = zero_axes(re.dlo);
-  if (threadIdx.x == 0) s_win[0] = p0;
-  if (i == r1 - 1) s_win[1] = p1;
+  if (threadIdx.x == 0) s_win[0] = bs;
+  if (i == r1 - 1) s_win[1] = be;
   __syncthreads();
   const int64_t w0 = s_win[0], w1 = s_win[1];
   for (int64_t c0 = w0; c0 < w1; c0 += JWIN) {
@@ -1398,9 +1417,13 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
       }
     }
     __syncthreads();
-    int64_t j = p0 > c0 ? p0 : c0;
-    const int64_t je = p1 < c0 + nw ? p1 : c0 + nw;
-    while (__any(j < je)) {
+    // this chunk's part of the two partner ranges, taken as one list
+    const int64_t cend = c0 + nw;
+    const int64_t a0 = pa0 > c0 ? pa0 : c0, a1 = pa1 < cend ? pa1 : cend;
+    const int64_t b0 = pb0 > c0 ? pb0 : c0, b1 = pb1 < cend ? pb1 : cend;
+    const int64_t na = a1 > a0 ? a1 - a0 : 0, ntot = na + (b1 > b0 ? b1 - b0 : 0);
+    int64_t t = 0;
+    while (__any(t < ntot)) {
       // four partners per lane: their entries and records read from LDS
       // without conditions (a conditional read kept the previous records
       // live in registers: ~45 copies per step and 200 VGPRs), then the
@@ -1410,7 +1433,8 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
       int idx[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        idx[u] = j + u < je ? (int)(j + u - c0) : 0;
+        const int64_t tu = t + u;
+        idx[u] = tu < ntot ? (int)((tu < na ? a0 + tu : b0 + (tu - na)) - c0) : 0;
         pe[u] = s_ent[idx[u]];
       }
       ItemRec r[4];
@@ -1418,7 +1442,7 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
       for (int u = 0; u < 4; ++u) r[u] = s_rec[idx[u]];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        pass[u] = (j + u < je) & (pe[u].cell == re.cell) & ((rz | zero_axes(pe[u].dlo)) == 7);
+        pass[u] = (t + u < ntot) & (pe[u].cell == re.cell) & ((rz | zero_axes(pe[u].dlo)) == 7);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool ok = pass[u] && join_test<KIND>(r[u], qa, qb, qdof, qlo, qhi);
@@ -1426,7 +1450,7 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
         const int2 pr = (KIND == 0 || re.item < it) ? make_int2(re.item, it) : make_int2(it, re.item);
         wave_push(ok, pr, wout, wcnt);
       }
-      j += 4;
+      t += 4;
       if (wcnt > JOUT - 4 * 64) wave_out_flush(wout, wcnt, total, out, cap);
     }
   }
