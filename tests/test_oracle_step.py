@@ -57,6 +57,58 @@ def test_stiffness_null_space_and_constant_strain(st):
     assert 0.5 * u.reshape(-1) @ (K @ u.reshape(-1)) == pytest.approx(vol * psi, rel=1e-10)
 
 
+def _corotational_energy(si, x):
+    """Linear corotational elastic energy of the coarse tets at node
+    positions x (Sec. IV-A's model): sum_T V_T (mu |F - R|^2 + lam/2
+    tr(R^T F - I)^2), F = Ds Dm^-1, R the rotation of F's polar
+    decomposition, V_T the aggregated sample volumes (Eq. 15)."""
+    lam = si.young * si.poisson / ((1 + si.poisson) * (1 - 2 * si.poisson))
+    mu = si.young / (2 * (1 + si.poisson))
+    VT = np.zeros(len(si.tets))
+    np.add.at(VT, si.sample_tet, si.sample_vol)
+    X = si.grid_nodes
+    e = 0.0
+    for t in np.nonzero(VT)[0]:
+        a, b, c, d = si.tets[t]
+        Dm = np.column_stack([X[b] - X[a], X[c] - X[a], X[d] - X[a]])
+        Ds = np.column_stack([x[b] - x[a], x[c] - x[a], x[d] - x[a]])
+        F = Ds @ np.linalg.inv(Dm)
+        U, _, Vt = np.linalg.svd(F)
+        R = U @ Vt
+        if np.linalg.det(R) < 0:
+            U[:, -1] *= -1
+            R = U @ Vt
+        S = R.T @ F - np.eye(3)
+        e += VT[t] * (mu * np.sum((F - R) ** 2) + 0.5 * lam * np.trace(S) ** 2)
+    return e
+
+
+def test_linear_model_is_the_rest_linearization_of_corotational(st):
+    """The step's elastic model (small-strain linear elasticity) stands in
+    for the paper's linear corotational model: the two agree to second
+    order about the rest shape (equal energy, gradient and Hessian there),
+    so for a displacement of scale s their energies differ by O(s^3); a
+    finite rotation shows they are different models (corotational energy
+    zero, linear energy not)."""
+    si = st.si
+    X = si.grid_nodes
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=X.shape) * np.ptp(X, axis=0).max()
+    rel = []
+    for s in (1e-3, 1e-4):
+        us = s * u
+        e_lin = 0.5 * us.reshape(-1) @ (st.K @ us.reshape(-1))
+        e_cor = _corotational_energy(si, X + us)
+        rel.append(abs(e_cor - e_lin) / e_lin)
+    assert rel[0] < 1e-2 and rel[1] < 0.2 * rel[0]
+    th = 0.3
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    xr = (X - X.mean(0)) @ Rz.T + X.mean(0)
+    ur = (xr - X).reshape(-1)
+    assert _corotational_energy(si, xr) <= 1e-20 * (0.5 * ur @ (st.K @ ur))
+    assert 0.5 * ur @ (st.K @ ur) > 0
+
+
 @pytest.fixture(scope="module")
 def solved(st):
     q, it = st.solve()
