@@ -17,6 +17,12 @@ elasticity matrix C, K_T = V_T B^T C B (the rest-pose linearization of the
 paper's corotational model: the two share energy, gradient and Hessian at
 the rest shape); gravity f = J^T f_ext (Eq. 16).
 
+The paper's linear corotational model is available as the elastic term
+of the step (Step(si, "corotational"), function corotational): the same
+energy with the rotation of each tet's deformation gradient factored out,
+its Newton matrix taking the warped stiffness R K0 R^T; the adjoint is
+taken with the linear model, whose Hessian is exact.
+
 Solved by projected Newton (Sec. III-C): the true Hessian when Cholesky
 accepts it, else the per-pair PSD-projected one; the step length clamped
 by the oracle's conservative CCD bound over the swept candidates, then
@@ -98,13 +104,76 @@ def assemble(si):
     return np.kron(M, np.eye(3)), K, f.reshape(-1)
 
 
+def elastic_tets(si):
+    """(node indices [4], rest shape-function gradients g_a as rows [4, 3],
+    aggregated volume V_T) of each coarse tet that holds samples."""
+    VT = np.zeros(len(si.tets))
+    np.add.at(VT, si.sample_tet, si.sample_vol)
+    out = []
+    for t in np.nonzero(VT)[0]:
+        tn = si.tets[t]
+        X = si.grid_nodes[tn]
+        Dinv = np.linalg.inv(np.column_stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]]))
+        out.append((tn, np.vstack([-Dinv.sum(axis=0), Dinv]), VT[t]))
+    return out
+
+
+def corotational(si, q, tets=None, want_hess=True):
+    """Linear corotational elasticity on the coarse tets (the paper's model,
+    Sec. IV-A), per tet with deformation gradient F = sum_a x_a g_a^T and R
+    the rotation of its polar decomposition (from the SVD, F = U S V^T,
+    R = U V^T):
+
+        energy   V (mu |F - R|^2 + lam/2 tr(R^T F - I)^2),
+        gradient V P g_a at node a, P = 2 mu (F - R) + lam tr(R^T F - I) R,
+        Hessian  the warped stiffness R K0 R^T: K0 the tet's linear
+                 stiffness, its (a, b) block V (mu (g_b g_a^T + (g_a.g_b) I)
+                 + lam g_a g_b^T), each block rotated by R on both sides
+                 (positive semidefinite; at the rest shape it is the linear
+                 stiffness).
+
+    Returns (energy, gradient [3 n], Hessian [3 n, 3 n] or None)."""
+    lam = si.young * si.poisson / ((1 + si.poisson) * (1 - 2 * si.poisson))
+    mu = si.young / (2 * (1 + si.poisson))
+    tets = elastic_tets(si) if tets is None else tets
+    n = len(si.grid_nodes)
+    x = np.asarray(q).reshape(-1, 3)
+    e = 0.0
+    g = np.zeros(3 * n)
+    H = np.zeros((3 * n, 3 * n)) if want_hess else None
+    I3 = np.eye(3)
+    for tn, G, V in tets:
+        F = sum(np.outer(x[tn[a]], G[a]) for a in range(4))
+        U, _, Vt = np.linalg.svd(F)
+        R = U @ Vt
+        if np.linalg.det(R) < 0:
+            U[:, -1] *= -1
+            R = U @ Vt
+        tr = np.trace(R.T @ F) - 3.0
+        e += V * (mu * np.sum((F - R) ** 2) + 0.5 * lam * tr * tr)
+        P = 2 * mu * (F - R) + lam * tr * R
+        for a in range(4):
+            g[3 * tn[a]:3 * tn[a] + 3] += V * (P @ G[a])
+        if want_hess:
+            for a in range(4):
+                for b in range(4):
+                    ga, gb = G[a], G[b]
+                    blk = V * (mu * (np.outer(gb, ga) + (ga @ gb) * I3) + lam * np.outer(ga, gb))
+                    H[3 * tn[a]:3 * tn[a] + 3, 3 * tn[b]:3 * tn[b] + 3] += R @ blk @ R.T
+    return e, g, H
+
+
 class Step:
     """The oracle step of the given inputs; pose theta (tx, ty, tz, rx, ry,
-    rz) places the kinematic body, rotated about its rest centroid."""
+    rz) places the kinematic body, rotated about its rest centroid.
+    elastic: "linear" (the constant stiffness K) or "corotational" (the
+    paper's model, Newton matrix with the warped stiffness)."""
 
-    def __init__(self, si):
+    def __init__(self, si, elastic="linear"):
         self.si = si
         self.sc = si.scene
+        self.elastic = elastic
+        self._tets = elastic_tets(si)
         self.M, self.K, self.f = assemble(si)
         self.q_rest = si.grid_nodes.reshape(-1).copy()
         self.q_n = si.q_n.copy()
@@ -149,18 +218,26 @@ class Step:
             raise RuntimeError(f"contact oracle status {r['status']}")
         return r, pt, ee
 
+    def _elastic(self, q, want_hess):
+        if self.elastic == "corotational":
+            return corotational(self.si, q, self._tets, want_hess)
+        dr = q - self.q_rest
+        Kd = self.K @ dr
+        return 0.5 * dr @ Kd, Kd, self.K
+
     def energy(self, q):
         qt = self.q_n + self.h * self.v_n
         d = q - qt
-        dr = q - self.q_rest
         r, _, _ = self._contact(q, ENERGY, False)
-        return 0.5 * d @ (self.M @ d) + self.h ** 2 * (0.5 * dr @ (self.K @ dr) - self.f @ q) + r["energy"]
+        e_el, _, _ = self._elastic(q, False)
+        return 0.5 * d @ (self.M @ d) + self.h ** 2 * (e_el - self.f @ q) + r["energy"]
 
     def grad_hess(self, q, project):
         qt = self.q_n + self.h * self.v_n
         r, pt, ee = self._contact(q, ENERGY | GRAD | HESS | (PROJECT if project else 0), True)
-        g = self.M @ (q - qt) + self.h ** 2 * (self.K @ (q - self.q_rest) - self.f) + r["grad"]
-        H = self.M + self.h ** 2 * self.K + r["hess"]
+        _, g_el, K_el = self._elastic(q, True)
+        g = self.M @ (q - qt) + self.h ** 2 * (g_el - self.f) + r["grad"]
+        H = self.M + self.h ** 2 * K_el + r["hess"]
         return g, H, (pt, ee)
 
     def step_bound(self, q, dq):

@@ -2,8 +2,10 @@
 Eq. 5-6, III-B Eq. 10-12, III-C): the assembled mass, stiffness and
 gravity against their definitions (total mass, partition of unity, rigid
 null space of the elastic energy, the energy of a constant strain), the
-converged step, and the adjoint gradients against central differences of
-the loss with the step solved again."""
+linear model as the rest linearization of the paper's corotational one,
+the corotational term (rigid invariance, differences, warped stiffness),
+the converged step under either model, and the adjoint gradients against
+central differences of the loss with the step solved again."""
 import numpy as np
 import pytest
 
@@ -107,6 +109,57 @@ def test_linear_model_is_the_rest_linearization_of_corotational(st):
     ur = (xr - X).reshape(-1)
     assert _corotational_energy(si, xr) <= 1e-20 * (0.5 * ur @ (st.K @ ur))
     assert 0.5 * ur @ (st.K @ ur) > 0
+
+
+def _rigid(X, th, t):
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(0.7 * th), -np.sin(0.7 * th)], [0, np.sin(0.7 * th), np.cos(0.7 * th)]])
+    return (X - X.mean(0)) @ (Rz @ Rx).T + X.mean(0) + t
+
+
+def test_corotational_oracle_definition(st):
+    """The oracle's corotational term: its energy equals the definition
+    evaluated separately above; rigid motions (finite rotations) give zero
+    energy and zero gradient; the gradient matches central differences of
+    the energy; the warped stiffness equals the linear stiffness at the rest
+    shape and stays positive semidefinite when deformed."""
+    from oracle.step import corotational
+    si = st.si
+    X = si.grid_nodes
+    rng = np.random.default_rng(8)
+    xd = X + 0.02 * np.ptp(X, axis=0).max() * rng.normal(size=X.shape)
+    e, g, H = corotational(si, xd.reshape(-1))
+    assert e == pytest.approx(_corotational_energy(si, xd), rel=1e-12)
+    xr = _rigid(X, 0.9, np.array([0.01, -0.02, 0.03]))
+    er, gr, _ = corotational(si, xr.reshape(-1), want_hess=False)
+    assert abs(er) <= 1e-20 * e and np.abs(gr).max() <= 1e-10 * np.abs(g).max()
+    for _ in range(3):
+        v = rng.normal(size=g.shape)
+        eps = 1e-6 * np.ptp(X, axis=0).max()
+        ep, _, _ = corotational(si, xd.reshape(-1) + eps * v, want_hess=False)
+        em, _, _ = corotational(si, xd.reshape(-1) - eps * v, want_hess=False)
+        assert (ep - em) / (2 * eps) == pytest.approx(g @ v, rel=1e-6)
+    _, g0, H0 = corotational(si, X.reshape(-1))
+    assert np.abs(g0).max() <= 1e-10 * np.abs(g).max()
+    assert np.allclose(H0, st.K, rtol=0, atol=1e-12 * np.abs(st.K).max())
+    lam = np.linalg.eigvalsh(0.5 * (H + H.T))
+    assert lam.min() >= -1e-10 * lam.max()
+
+
+def test_corotational_step_converges(st):
+    """One step under the corotational model converges (its Newton matrix
+    carries the warped stiffness, not the exact Hessian, so it stops on the
+    energy's rounding level with a gradient a little above the linear
+    model's) and lands near the linear model's step."""
+    stc = OS.Step(st.si, elastic="corotational")
+    q, it = stc.solve()
+    assert it < 60
+    g, _, _ = stc.grad_hess(q, project=False)
+    qt = stc.q_n + stc.h * stc.v_n
+    assert np.linalg.norm(g) <= 1e-7 * np.linalg.norm(stc.M @ qt)
+    ql, _ = st.solve()
+    rel = np.linalg.norm(q - ql) / np.linalg.norm(ql - st.q_n)
+    assert 0 < rel < 0.1
 
 
 @pytest.fixture(scope="module")
