@@ -42,7 +42,7 @@ enum {
   EIPC_ERR_ARG = -1,          /* invalid argument (nothing enqueued) */
   EIPC_ERR_CAPACITY = -2,     /* an output buffer is too small; the required size is returned */
   EIPC_ERR_INTERSECTING = -3, /* a candidate pair has distance 0: the input is not intersection-free */
-  EIPC_ERR_DEGENERATE = -4,   /* reserved */
+  EIPC_ERR_DEGENERATE = -4,   /* a degenerate or inverted element of the elastic mesh (eipc_elastic) */
   EIPC_ERR_NONFINITE = -5,    /* NaN or Inf in positions or pair quantities */
   EIPC_ERR_HIP = -6,          /* a HIP runtime call failed; see eipc_last_error */
   EIPC_WARN_CCD_CAPPED = 1    /* CCD hit its per-pair iteration cap (the bound is still safe) */
@@ -379,6 +379,55 @@ eipc_status eipc_cholesky(eipc_ctx *ctx, double *A, int64_t n, int64_t lda, int6
  * [n][nrhs] device memory and is overwritten by X. */
 eipc_status eipc_cholesky_solve(eipc_ctx *ctx, const double *L, int64_t n, int64_t lda, double *B, int64_t nrhs,
                                 eipc_stream stream);
+
+/* Reduced mass and gravity of one implicit step on a coarse tetrahedral
+ * mesh, from interior samples of the body (M = J^T M_x J, Sec. III-A Eq. 1,
+ * with the volume aggregation of Eq. 15; f = J^T f_ext, Eq. 16).  Sample s
+ * has mass sample_mass (rho times its volume) and barycentric weights
+ * sample_w[4 s .. 4 s + 3] in the coarse tet whose nodes are
+ * sample_nodes[4 s .. 4 s + 3]; it adds sample_mass w_a w_b to the diagonal
+ * of the 3x3 block (a, b) of M and -sample_mass gravity w_a to the z
+ * component of node a in f.  Nodes that no sample reaches then get 1e-3 of
+ * the mean mass of the reached nodes on their diagonal, so that the Newton
+ * matrix stays definite (this reads M: clear M before the call).
+ * M: dense [3 n_node x 3 n_node] row-major, leading dimension lda >=
+ * 3 n_node; f: [3 n_node] node-major xyz, or NULL.  Both are added to.
+ * Device memory, caller owned.  Enqueued on stream.  EIPC_ERR_ARG for bad
+ * sizes or pointers. */
+eipc_status eipc_reduced_mass(eipc_ctx *ctx, int32_t n_node, int64_t n_sample, const int32_t *sample_nodes,
+                              const double *sample_w, double sample_mass, double gravity, double *M, int64_t lda,
+                              double *f, eipc_stream stream);
+
+/* elastic models for eipc_elastic */
+enum {
+  EIPC_ELASTIC_LINEAR = 0,       /* small-strain linear elasticity: psi = mu eps:eps + lam/2 tr(eps)^2 */
+  EIPC_ELASTIC_COROTATIONAL = 1  /* linear corotational (Sec. IV-A): psi = mu |F - R|^2 + lam/2 tr(R^T F - I)^2 */
+};
+
+/* Elastic energy Phi of the coarse tetrahedra of one implicit step (Sec.
+ * III-A; each tet's volume aggregated from samples as in Eq. 15; the
+ * paper's bodies are linear corotational, Sec. IV-A) and its derivatives
+ * in the reduced coordinates q (the coarse node positions, [3 n_node]).
+ * Tet t has nodes tets[4 t .. 4 t + 3], rest node positions rest
+ * ([3 n_node]) and volume vol[t] (tets with volume 0 are skipped);
+ * F = sum_a x_a g_a^T with g_a the rest shape-function gradients.
+ * EIPC_ELASTIC_LINEAR: eps = sym(F) - I, gradient and Hessian exact (the
+ * Hessian is the constant stiffness K0).  EIPC_ELASTIC_COROTATIONAL: R the
+ * rotation of F's polar decomposition, first Piola stress
+ * P = 2 mu (F - R) + lam tr(R^T F - I) R (the exact gradient), Newton
+ * matrix the warped stiffness R K0 R^T (positive semidefinite; K0 at the
+ * rest shape).  young > 0 and -1 < poisson < 0.5 give the Lame parameters.
+ * Adds scale * energy to energy[0], scale * gradient to grad ([3 n_node])
+ * and scale * Newton matrix to hess (dense [3 n_node x 3 n_node] row-major,
+ * leading dimension lda >= 3 n_node); each may be NULL.  Device memory,
+ * caller owned.  Enqueued on stream.  EIPC_ERR_ARG for bad arguments; a
+ * degenerate rest tet, or an inverted one (det F <= 0) in the corotational
+ * model, adds nothing and raises EIPC_ERR_DEGENERATE through
+ * eipc_sync_status. */
+eipc_status eipc_elastic(eipc_ctx *ctx, int32_t n_node, int32_t n_tet, const int32_t *tets, const double *rest,
+                         const double *vol, double young, double poisson, int32_t model, const double *q,
+                         double scale, double *energy, double *grad, double *hess, int64_t lda,
+                         eipc_stream stream);
 
 /* ---- optional kernel timing (benchmarks) ---- */
 

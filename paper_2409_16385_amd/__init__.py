@@ -14,5 +14,6 @@ from .binding import (  # noqa: F401
     cholesky, cholesky_solve, Plan, StepOut, set_tuning, set_ccd_method, CCD_ADDITIVE, CCD_CLOSEST_DIRECTION,
     plan_step, contact_step, step_pairs,
     friction_lag, friction_reduce,
+    reduced_mass, elastic, ELASTIC_LINEAR, ELASTIC_COROTATIONAL,
 )
 from .autograd import BarrierState, barrier_energy, barrier_grad  # noqa: F401

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_obj")
 LIB = os.path.join(PKG, "libeipc.so")
-SOURCES = ["api.hip", "geometry.hip", "barrier.hip", "ccd.hip", "linalg.hip", "friction.hip"]
+SOURCES = ["api.hip", "geometry.hip", "barrier.hip", "ccd.hip", "linalg.hip", "friction.hip", "elastic.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EIPC_OFFLOAD_ARCH", "gfx950")
 

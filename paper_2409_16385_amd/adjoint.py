@@ -13,15 +13,19 @@ Newton (Sec. III-C) with a CCD-clamped backtracking line search solves it;
 the adjoint of the converged step gives dL/dq_n, dL/dv_n and dL/dtheta for
 the pose theta of a kinematic body (its vertices' x_off).
 
-Elastic model: linear (small-strain) isotropic elasticity, whose Hessian
-is exact and constant; the paper's experiments use linear corotational
-elasticity.  Volumes and masses come from seeded uniform samples of the
-body's interior, each carrying V/N, assigned to their coarse tetrahedron
-(the aggregation of Eq. 15).  Grid nodes that no sample reaches get a
-lumped mass of 1e-3 of the mean node mass.
+Elastic model (StepProblem.elastic_model): linear (small-strain) isotropic
+elasticity, whose Hessian is exact and constant, or the paper's linear
+corotational elasticity (Sec. IV-A), whose Newton matrix takes the warped
+stiffness R K0 R^T; the adjoint needs the exact Hessian and is taken with
+the linear model.  Volumes and masses come from seeded uniform samples of
+the body's interior, each carrying V/N, assigned to their coarse
+tetrahedron (the aggregation of Eq. 15).  Grid nodes that no sample
+reaches get a lumped mass of 1e-3 of the mean node mass.
 
-Dense linear algebra runs in the library (eipc_cholesky / _solve); the
-contact terms come from the library's contact stage.
+The mass, gravity and elastic terms (eipc_reduced_mass, eipc_elastic), the
+dense Cholesky factorization and solves (eipc_cholesky / _solve) and the
+contact terms run in the library; the Newton loop and the dense
+matrix-vector products with M are driven from here.
 """
 from __future__ import annotations
 
@@ -43,24 +47,6 @@ def _rodrigues(r):
     return np.eye(3) + math.sin(th) * K + (1 - math.cos(th)) * K @ K
 
 
-def _tet_stiffness(X: np.ndarray, V: float, lam: float, mu: float) -> np.ndarray:
-    """12x12 linear-elastic stiffness of one tetrahedron with rest corners X
-    (4x3) and volume weight V:  Psi = mu |eps|^2 + lam/2 tr(eps)^2."""
-    Dm = np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]], axis=1)
-    Bm = np.linalg.inv(Dm)
-    # gradients of the 4 barycentric shape functions
-    G = np.zeros((4, 3))
-    G[1:] = Bm
-    G[0] = -Bm.sum(axis=0)
-    K = np.zeros((12, 12))
-    for a in range(4):
-        for b in range(4):
-            ga, gb = G[a], G[b]
-            blk = mu * (np.outer(gb, ga) + (ga @ gb) * np.eye(3)) + lam * np.outer(ga, gb)
-            K[3 * a:3 * a + 3, 3 * b:3 * b + 3] = V * blk
-    return K
-
-
 @dataclasses.dataclass
 class StepProblem:
     ctx: B.Context
@@ -78,6 +64,12 @@ class StepProblem:
     kin_rows: np.ndarray     # vertex indices of the kinematic body
     kin_rest: np.ndarray     # their rest positions [k, 3]
     theta: np.ndarray        # pose (tx, ty, tz, rx, ry, rz)
+    tets: torch.Tensor       # coarse tets (int32 [n_tet, 4])
+    vol: torch.Tensor        # their aggregated volumes V_T (Eq. 15)
+    young: float
+    poisson: float
+    # B.ELASTIC_LINEAR or B.ELASTIC_COROTATIONAL
+    elastic_model: int = B.ELASTIC_LINEAR
     # barrier formulation: B.SQDIST for the squared-distance form, and
     # reduced_projection for the projection of each pair's reduced block
     # (B.PROJECT_REDUCED) in place of the per-pair B.PROJECT
@@ -119,37 +111,23 @@ def build_step(ctx: B.Context, si) -> tuple[StepProblem, torch.Tensor]:
     dev = ctx.torch_device
     nodes, tets = si.grid_nodes, si.tets
     n_node = len(nodes)
-    tet_nodes = tets[si.sample_tet]
-    w = si.sample_w
-    Vs = si.sample_vol
-    Mn = np.zeros((n_node, n_node))
-    for a in range(4):
-        for b in range(4):
-            np.add.at(Mn, (tet_nodes[:, a], tet_nodes[:, b]), si.rho * Vs * w[:, a] * w[:, b])
-    # nodes no interior sample reaches carry no mass and no stiffness; give
-    # them a small lumped mass so the step's Newton matrix stays definite
-    d = np.diag(Mn).copy()
-    empty = d <= 0.0
-    if empty.any():
-        Mn[empty, empty] = 1e-3 * d[~empty].mean()
-    M = np.kron(Mn, np.eye(3))
-    VT = np.bincount(si.sample_tet, minlength=len(tets)) * Vs
-    lam = si.young * si.poisson / ((1 + si.poisson) * (1 - 2 * si.poisson))
-    mu = si.young / (2 * (1 + si.poisson))
-    Kd = np.zeros((3 * n_node, 3 * n_node))
-    for t in np.nonzero(VT)[0]:
-        tn = tets[t]
-        Ke = _tet_stiffness(nodes[tn], VT[t], lam, mu)
-        idx = np.concatenate([[3 * i, 3 * i + 1, 3 * i + 2] for i in tn])
-        Kd[np.ix_(idx, idx)] += Ke
-    fn = np.zeros((n_node, 3))
-    for a in range(4):
-        np.add.at(fn[:, 2], tet_nodes[:, a], -si.rho * Vs * si.g * w[:, a])
-    scene = B.Scene.from_host(ctx, sc)
     T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    prob = StepProblem(ctx=ctx, scene=scene, host=sc, M=T(M), K=T(Kd), q_rest=T(nodes.reshape(-1)),
-                       f=T(fn.reshape(-1)), q_n=T(si.q_n), v_n=T(si.v_n), h=si.h, kappa=sc.kappa,
-                       dhat=sc.dhat, kin_rows=si.kin_rows, kin_rest=si.kin_rest.copy(), theta=np.zeros(6))
+    # mass and gravity from the samples, in the library (with the lumped
+    # mass of nodes that no sample reaches)
+    M, f = B.reduced_mass(ctx, n_node, torch.as_tensor(tets[si.sample_tet], dtype=torch.int32),
+                          torch.as_tensor(si.sample_w), si.rho * si.sample_vol, si.g)
+    VT = np.bincount(si.sample_tet, minlength=len(tets)) * si.sample_vol
+    tets_d = torch.as_tensor(np.ascontiguousarray(tets, dtype=np.int32), device=dev)
+    vol_d = T(VT)
+    q_rest = T(nodes.reshape(-1))
+    # the linear model's constant stiffness: its Newton matrix at rest
+    K = torch.zeros((3 * n_node, 3 * n_node), dtype=torch.float64, device=dev)
+    B.elastic(ctx, n_node, tets_d, q_rest, vol_d, si.young, si.poisson, B.ELASTIC_LINEAR, q_rest, hess=K)
+    scene = B.Scene.from_host(ctx, sc)
+    prob = StepProblem(ctx=ctx, scene=scene, host=sc, M=M, K=K, q_rest=q_rest, f=f, q_n=T(si.q_n),
+                       v_n=T(si.v_n), h=si.h, kappa=sc.kappa, dhat=sc.dhat, kin_rows=si.kin_rows,
+                       kin_rest=si.kin_rest.copy(), theta=np.zeros(6), tets=tets_d, vol=vol_d, young=si.young,
+                       poisson=si.poisson)
     return prob, T(si.q_target)
 
 
@@ -175,12 +153,17 @@ def _contact(prob: StepProblem, q, flags, hess):
     return r, pt, ee
 
 
+def _elastic(prob: StepProblem, q, scale, energy=None, grad=None, hess=None):
+    B.elastic(prob.ctx, prob.n // 3, prob.tets, prob.q_rest, prob.vol, prob.young, prob.poisson,
+              prob.elastic_model, q, scale, energy=energy, grad=grad, hess=hess)
+
+
 def energy(prob: StepProblem, q) -> float:
     qt = prob.q_n + prob.h * prob.v_n
     d = q - qt
-    e = 0.5 * d @ (prob.M @ d)
-    dr = q - prob.q_rest
-    e = e + prob.h ** 2 * (0.5 * dr @ (prob.K @ dr) - prob.f @ q)
+    e_el = torch.zeros(1, dtype=torch.float64, device=q.device)
+    _elastic(prob, q.contiguous(), 1.0, energy=e_el)
+    e = 0.5 * d @ (prob.M @ d) + prob.h ** 2 * (e_el[0] - prob.f @ q)
     r, _, _ = _contact(prob, q, B.ENERGY, None)
     return float(e + r["energy"][0])
 
@@ -190,8 +173,10 @@ def gradient_hessian(prob: StepProblem, q, project: bool):
     proj = B.PROJECT_REDUCED if prob.reduced_projection else B.PROJECT
     flags = B.ENERGY | B.GRAD | B.HESS | (proj if project else 0)
     r, pt, ee = _contact(prob, q, flags, "dense")
-    g = prob.M @ (q - qt) + prob.h ** 2 * (prob.K @ (q - prob.q_rest) - prob.f) + r["grad"]
-    H = prob.M + prob.h ** 2 * prob.K + r["hess"]
+    g = prob.M @ (q - qt) - prob.h ** 2 * prob.f + r["grad"]
+    H = prob.M + r["hess"]
+    # elastic terms (times h^2) added in the library
+    _elastic(prob, q.contiguous(), prob.h ** 2, grad=g, hess=H)
     return g, H, (pt, ee)
 
 
@@ -248,7 +233,11 @@ def solve_step(prob: StepProblem, tol: float = 1e-12, max_iter: int = 100, verbo
 
 def adjoint(prob: StepProblem, q_star, dLdq):
     """Adjoint of the converged step.  Returns (dL/dq_n, dL/dv_n,
-    dL/dtheta[6], used_true_hessian)."""
+    dL/dtheta[6], used_true_hessian).  Needs the exact Hessian: linear
+    elastic model only (the corotational Newton matrix is the warped
+    stiffness)."""
+    if prob.elastic_model != B.ELASTIC_LINEAR:
+        raise NotImplementedError("the adjoint takes the exact Hessian: use the linear elastic model")
     g, H, (pt, ee) = gradient_hessian(prob, q_star, project=False)
     L = H.clone()
     used_true = B.cholesky(prob.ctx, L) == 0

@@ -96,6 +96,8 @@ def _load():
         "eipc_friction_lag": (_I32, [_P, _P, _P, _P, _I64, _P, _I64, _D, _D, _U32, _P, _P, _P]),
         "eipc_friction_reduce": (_I32, [_P, _P, _P, _P, _I64, _P, _P, _I64, _P, _D, _D, _U32, _P, _P, _P, _P, _P]),
         "eipc_barrier_hvp_noalloc": (_I32, [_P, _P, _P, _P, _I64, _P, _I64, _D, _D, _U32, _P, _P, _P, _P, _P]),
+        "eipc_reduced_mass": (_I32, [_P, _I32, _I64, _P, _P, _D, _D, _P, _I64, _P, _P]),
+        "eipc_elastic": (_I32, [_P, _I32, _I32, _P, _P, _P, _D, _D, _I32, _P, _D, _P, _P, _P, _I64, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -449,6 +451,41 @@ def cholesky_solve(ctx: Context, L: torch.Tensor, B: torch.Tensor):
         raise ValueError("B must be contiguous")
     ctx.check(_load().eipc_cholesky_solve(ctx.handle, _ptr(L), n, L.shape[1], _ptr(Bm), Bm.shape[1], ctx.stream()))
     return B
+
+
+ELASTIC_LINEAR = 0
+ELASTIC_COROTATIONAL = 1
+
+
+def reduced_mass(ctx: Context, n_node: int, sample_nodes: torch.Tensor, sample_w: torch.Tensor,
+                 sample_mass: float, gravity: float):
+    """Reduced mass M [3 n_node, 3 n_node] and gravity f [3 n_node] from
+    interior samples (int32 [n_s, 4] tet nodes, float64 [n_s, 4] weights)."""
+    dev = ctx.torch_device
+    n3 = 3 * n_node
+    M = torch.zeros((n3, n3), dtype=torch.float64, device=dev)
+    f = torch.zeros(n3, dtype=torch.float64, device=dev)
+    sn = sample_nodes.to(device=dev, dtype=torch.int32).contiguous()
+    sw = sample_w.to(device=dev, dtype=torch.float64).contiguous()
+    ctx.check(_load().eipc_reduced_mass(ctx.handle, n_node, sn.shape[0], _ptr(sn), _ptr(sw), float(sample_mass),
+                                        float(gravity), _ptr(M), n3, _ptr(f), ctx.stream()))
+    return M, f
+
+
+def elastic(ctx: Context, n_node: int, tets: torch.Tensor, rest: torch.Tensor, vol: torch.Tensor, young: float,
+            poisson: float, model: int, q: torch.Tensor, scale: float = 1.0, energy: torch.Tensor | None = None,
+            grad: torch.Tensor | None = None, hess: torch.Tensor | None = None):
+    """Adds scale * (elastic energy, gradient, Newton matrix) of the coarse
+    tets at q into the given float64 device tensors (each optional)."""
+    lda = hess.shape[1] if hess is not None else 3 * n_node
+    for t in (energy, grad, hess):
+        if t is not None and (t.dtype != torch.float64 or not t.is_contiguous()):
+            raise ValueError("outputs must be contiguous float64 tensors")
+    ctx.check(_load().eipc_elastic(ctx.handle, n_node, tets.shape[0], _ptr(tets), _ptr(rest), _ptr(vol),
+                                   float(young), float(poisson), int(model), _ptr(q), float(scale),
+                                   _ptr(energy) if energy is not None else None,
+                                   _ptr(grad) if grad is not None else None,
+                                   _ptr(hess) if hess is not None else None, lda, ctx.stream()))
 
 
 def fp64_selftest(ctx: Context, a, b):

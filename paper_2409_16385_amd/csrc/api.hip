@@ -191,6 +191,8 @@ static eipc_status read_status(eipc_ctx *c, hipStream_t s, bool clear = true) {
   if (st & ST_PLAN_OVERFLOW) return set_err(c, EIPC_ERR_CAPACITY, "a capacity of the step plan was exceeded");
   if (st & ST_HASH_OVERFLOW)
     return set_err(c, EIPC_ERR_CAPACITY, "the reduced-Hessian block table is full (blocks were dropped)");
+  if (st & ST_DEGENERATE)
+    return set_err(c, EIPC_ERR_DEGENERATE, "an element of the elastic mesh is degenerate or inverted");
   if (st & ST_INTERSECTING) return set_err(c, EIPC_ERR_INTERSECTING, "a candidate pair has zero distance");
   if (st & ST_NONFINITE) return set_err(c, EIPC_ERR_NONFINITE, "non-finite position or pair quantity");
   if (st & ST_CCD_CAPPED) return EIPC_WARN_CCD_CAPPED;

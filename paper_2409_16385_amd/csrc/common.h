@@ -20,7 +20,8 @@ enum : uint32_t {
   ST_HASH_OVERFLOW = 8u,
   ST_BAD_W = 16u,         // a W row with more than 4 weights
   ST_PLAN_OVERFLOW = 32u,  // a planned capacity was exceeded
-  ST_BAD_SCENE = 64u       // a vertex scene id out of range
+  ST_BAD_SCENE = 64u,      // a vertex scene id out of range
+  ST_DEGENERATE = 128u     // a degenerate or inverted element of the elastic mesh
 };
 
 // scratch buffers owned by the context
