@@ -386,7 +386,7 @@ def extra_formulations(log):
     """The alternative formulations on one implicit step of config 1's
     step problem (projected Newton with CCD-clamped backtracking): Newton
     iterations, the CCD step bounds along the way and the converged
-    position, per barrier form, projection and CCD."""
+    position, per barrier form, projection, CCD and elastic model."""
     import time
     import torch
     import paper_2409_16385_amd as E
@@ -394,14 +394,16 @@ def extra_formulations(log):
     dev = torch.device("cuda", 0)
     ctx = E.Context(0)
     prob, _ = A.build_config1_step(ctx)
-    variants = [("distance barrier, per-pair projection, additive CCD", 0, False, E.CCD_ADDITIVE),
-                ("squared-distance barrier", E.SQDIST, False, E.CCD_ADDITIVE),
-                ("reduced-block projection", 0, True, E.CCD_ADDITIVE),
-                ("closest-direction CCD", 0, False, E.CCD_CLOSEST_DIRECTION)]
+    lin, cor = E.ELASTIC_LINEAR, E.ELASTIC_COROTATIONAL
+    variants = [("distance barrier, per-pair projection, additive CCD", 0, False, E.CCD_ADDITIVE, lin),
+                ("squared-distance barrier", E.SQDIST, False, E.CCD_ADDITIVE, lin),
+                ("reduced-block projection", 0, True, E.CCD_ADDITIVE, lin),
+                ("closest-direction CCD", 0, False, E.CCD_CLOSEST_DIRECTION, lin),
+                ("linear corotational elasticity", 0, False, E.CCD_ADDITIVE, cor)]
     out, q_base = [], None
     kappa0 = prob.kappa
-    for name, bf, red, ccd in variants:
-        prob.barrier_flags, prob.reduced_projection = bf, red
+    for name, bf, red, ccd, model in variants:
+        prob.barrier_flags, prob.reduced_projection, prob.elastic_model = bf, red, model
         # the squared-distance barrier is about dhat^2 smaller at equal
         # kappa: its stiffness is rescaled so that both forms give the same
         # energy at d = dhat / sqrt(2)
@@ -422,7 +424,7 @@ def extra_formulations(log):
         log(f"formulation {name}: {info['iters']} Newton iterations, CCD alphas {ent['alpha_ccd'][:4]}, {ms:.1f} ms")
         out.append(ent)
     E.set_ccd_method(ctx, E.CCD_ADDITIVE)
-    prob.kappa = kappa0
+    prob.kappa, prob.elastic_model = kappa0, lin
     return {"workload": f"one implicit step of config 1's step problem ({prob.n} reduced DoF)", "variants": out}
 
 
