@@ -199,6 +199,8 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
 // The PT form is held to three waves per SIMD (168 VGPRs, no spill); the EE
 // form runs at two, where its 189 VGPRs fit without spilling (at three it
 // spilled 68 bytes per lane and was 8 % slower).
+constexpr int NCCD_BUF = 1024;  // staged active pairs per workgroup
+
 template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 0 ? 3 : 2))) void k_narrow_ccd(
     int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs, const int32_t *__restrict__ faces,
@@ -207,10 +209,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 0 ?
     int64_t *cand_count, double sfac, double t_max, int64_t max_iter, unsigned long long *alpha_bits,
     int32_t *__restrict__ longl, int64_t *n_long, const int32_t *__restrict__ vscene, int n_scene,
     uint32_t *status, bool dir) {
+  // active pairs are staged in LDS and appended with one atomic per
+  // workgroup flush: one atomic per wavefront on the shared counter
+  // serialised at the memory side (about a third of a pass's time)
+  __shared__ int2 s_act[NCCD_BUF];
+  __shared__ int s_nact;
+  __shared__ int64_t s_abase;
   const int64_t n = *d_n < cap ? *d_n : cap;
   const int lane = threadIdx.x & 63;
   bool capped = false;
   int64_t n_cand = 0;
+  if (threadIdx.x == 0) s_nact = 0;
+  __syncthreads();
   // each workgroup walks a contiguous range of the list: a scene's pairs
   // are adjacent in it, so the first pairs of a range publish their
   // scene's bound early and the cut-off prunes the rest of the range
@@ -273,18 +283,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 0 ?
     }
     {
       const uint64_t mask = __ballot(active);
-      int64_t pos0 = 0;
-      if (lane == 0 && mask)
-        pos0 = (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(mask));
-      pos0 = __shfl(pos0, 0, 64);
-      if (active) {
-        const int64_t pos = pos0 + __popcll(mask & ((1ull << lane) - 1ull));
-        if (pos < act_cap) {
-          act[pos] = (int32_t)i;
-          typ[pos] = ty;
-        } else {
-          atomicOr(status, ST_PLAN_OVERFLOW);
+      int p0 = 0;
+      if (lane == 0 && mask) p0 = atomicAdd(&s_nact, (int)__popcll(mask));
+      p0 = __shfl(p0, 0, 64);
+      if (active) s_act[p0 + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2((int)i, ty);
+      __syncthreads();
+      const int na = s_nact;
+      __syncthreads();  // every thread has read the count before it changes
+      // flush when another round could overfill the stage, and at the end
+      if (na > NCCD_BUF - (int)blockDim.x || base + (int64_t)blockDim.x >= r1) {
+        if (threadIdx.x == 0) s_abase = na ? (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)na) : 0;
+        __syncthreads();
+        const int64_t ab = s_abase;
+        for (int k = threadIdx.x; k < na; k += blockDim.x) {
+          const int64_t pos = ab + k;
+          if (pos < act_cap) {
+            act[pos] = s_act[k].x;
+            typ[pos] = s_act[k].y;
+          } else {
+            atomicOr(status, ST_PLAN_OVERFLOW);
+          }
         }
+        __syncthreads();
+        if (threadIdx.x == 0) s_nact = 0;
+        __syncthreads();
       }
     }
     {
