@@ -1851,16 +1851,26 @@ __device__ __forceinline__ void pair_vids(const int32_t *pairs, int64_t k, const
   }
 }
 
+constexpr int NARROW_BUF = 1024;  // staged active pairs per workgroup (256 threads)
+
 template <int KIND, bool FILTER>
 __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restrict__ pairs,
                          const int32_t *__restrict__ faces, const int32_t *__restrict__ edges,
                          const double *__restrict__ xs, int n_vert, double dhat2, double h,
                          int32_t *__restrict__ act, int32_t *__restrict__ typ, int64_t act_cap, int64_t *count,
                          int64_t *cand_count, uint32_t *status) {
+  // active pairs staged in LDS and appended with one atomic per workgroup
+  // flush (one atomic per wavefront on the shared counter serialises)
+  __shared__ int2 s_act[NARROW_BUF];
+  __shared__ int s_nact;
+  __shared__ int64_t s_abase;
   const int64_t n = d_n ? (*d_n < cap ? *d_n : cap) : cap;
   const int lane = threadIdx.x & 63;
   int64_t n_cand = 0;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+  if (threadIdx.x == 0) s_nact = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
     const int64_t i = base + threadIdx.x;
     bool active = false;
     int ty = 0;
@@ -1885,17 +1895,30 @@ __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restr
       }
     }
     const uint64_t mask = __ballot(active);
-    int64_t pos0 = 0;
-    if (lane == 0 && mask) pos0 = (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(mask));
-    pos0 = __shfl(pos0, 0, 64);
-    if (active) {
-      const int64_t pos = pos0 + __popcll(mask & ((1ull << lane) - 1ull));
-      if (pos < act_cap) {
-        act[pos] = (int32_t)i;
-        typ[pos] = ty;
-      } else {
-        atomicOr(status, ST_PLAN_OVERFLOW);
+    int p0 = 0;
+    if (lane == 0 && mask) p0 = atomicAdd(&s_nact, (int)__popcll(mask));
+    p0 = __shfl(p0, 0, 64);
+    if (active) s_act[p0 + __popcll(mask & ((1ull << lane) - 1ull))] = make_int2((int)i, ty);
+    __syncthreads();
+    const int na = s_nact;
+    __syncthreads();  // every thread has read the count before it changes
+    // flush when another round could overfill the stage, and at the end
+    if (na > NARROW_BUF - (int)blockDim.x || base + stride >= n) {
+      if (threadIdx.x == 0) s_abase = na ? (int64_t)atomicAdd((unsigned long long *)count, (unsigned long long)na) : 0;
+      __syncthreads();
+      const int64_t ab = s_abase;
+      for (int k = threadIdx.x; k < na; k += blockDim.x) {
+        const int64_t pos = ab + k;
+        if (pos < act_cap) {
+          act[pos] = s_act[k].x;
+          typ[pos] = s_act[k].y;
+        } else {
+          atomicOr(status, ST_PLAN_OVERFLOW);
+        }
       }
+      __syncthreads();
+      if (threadIdx.x == 0) s_nact = 0;
+      __syncthreads();
     }
   }
   if (FILTER) {
