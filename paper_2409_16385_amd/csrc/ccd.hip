@@ -322,9 +322,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == 0 ?
     agg_scene_min(alpha_bits, live && decided, scene, n_scene, t, status);
   }
   if (__any(capped) && lane == 0) atomicOr(status, ST_CCD_CAPPED);
+  // the candidate count: one atomic per workgroup
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) n_cand += __shfl_xor(n_cand, o, 64);
-  if (lane == 0 && n_cand) atomicAdd((unsigned long long *)cand_count, (unsigned long long)n_cand);
+  __shared__ int64_t s_cand[4];
+  if (lane == 0) s_cand[threadIdx.x >> 6] = n_cand;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t tot = s_cand[0] + s_cand[1] + s_cand[2] + s_cand[3];
+    if (tot) atomicAdd((unsigned long long *)cand_count, (unsigned long long)tot);
+  }
 }
 
 eipc_status launch_narrow_ccd(eipc_ctx *c, const eipc_scene *sc, int kind, const double *xs, const double *ps,

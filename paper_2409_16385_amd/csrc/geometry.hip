@@ -1922,9 +1922,16 @@ __global__ void k_narrow(int64_t cap, const int64_t *d_n, const int32_t *__restr
     }
   }
   if (FILTER) {
+    // the candidate count: one atomic per workgroup
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) n_cand += __shfl_xor(n_cand, o, 64);
-    if (lane == 0 && n_cand) atomicAdd((unsigned long long *)cand_count, (unsigned long long)n_cand);
+    __shared__ int64_t s_cand[4];
+    if (lane == 0) s_cand[threadIdx.x >> 6] = n_cand;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int64_t tot = s_cand[0] + s_cand[1] + s_cand[2] + s_cand[3];
+      if (tot) atomicAdd((unsigned long long *)cand_count, (unsigned long long)tot);
+    }
   }
 }
 
