@@ -193,8 +193,9 @@ __global__ __launch_bounds__(256) void k_ccd2(int64_t cap, const int64_t *d_n, c
 // Narrow phase and step-bound pass 0 in one sweep over the swept
 // candidates (the planned step with a step bound): each pair's vertices are
 // loaded once; the candidate predicate at x and, for the pairs passing it,
-// the distance and activity test (active pairs appended to act/typ with one
-// atomic per wavefront) come first, then advancement as in k_ccd2 pass 0,
+// the distance and activity test (active pairs staged per workgroup and
+// appended to act/typ with one atomic per flush) come first, then
+// advancement as in k_ccd2 pass 0,
 // reusing the distance just computed.  The pass-1 list is the same.
 // The PT form is held to three waves per SIMD (168 VGPRs, no spill); the EE
 // form runs at two, where its 189 VGPRs fit without spilling (at three it

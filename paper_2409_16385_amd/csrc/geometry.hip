@@ -1832,7 +1832,8 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
 
 // ---------------------------------------------------------------------------
 // narrow phase: distance type and d^2 per candidate; active (0 < d < dhat)
-// pairs compacted with a wavefront ballot and one atomic per wavefront.
+// pairs compacted by wavefront ballots into a workgroup stage in LDS and
+// appended with one atomic per stage flush.
 // ---------------------------------------------------------------------------
 template <int KIND>
 __device__ __forceinline__ void pair_vids(const int32_t *pairs, int64_t k, const int32_t *faces,
