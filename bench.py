@@ -481,7 +481,7 @@ def resolution_sweep(a, log):
     rows = []
     for nodes in RESOLUTION_NODES:
         t0 = time.perf_counter()
-        sc = S.grasp_scene(a.seed, 71, nodes, 32, name=f"config2_grid{nodes}")
+        sc = S.grasp_scene(a.seed, 71, nodes, 32, frac=0.75, name=f"config2_grid{nodes}")
         bt = BT.Batch(ctx, BT.concat([sc]), flags=flags)
         tuning = bt.autotune(reps=2)
         bt.capture()
