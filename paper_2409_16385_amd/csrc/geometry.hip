@@ -764,6 +764,7 @@ struct QueryArgs {
   const int64_t *n_qlist;
   int32_t *defer;          // when set: queries spanning more than LQ_CELLS cells are
   int64_t *n_defer;        // listed here and skipped (k_query_lq runs them)
+  int n_items;             // items in the hash (k_query_lq: a query of more cells tests them all)
 };
 
 // Queries whose boxes span more than this many cells run one wavefront
@@ -910,8 +911,32 @@ __global__ __launch_bounds__(QT) void k_query_lq(const int32_t *__restrict__ qli
     cell_range(g, qlo, qhi, c0, c1);
     const int64_t nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1;
     const int64_t nc = n_cells(c0, c1);
+    // a query whose cells outnumber the items by a sixteenth tests every
+    // item instead, four independent record loads per lane at a time (the
+    // same set: the cell scan reports each overlapping item once, the
+    // unhashed ones from their list; a cell costs a chain of dependent
+    // loads, an item one coalesced load)
+    const bool all_items = qa_.n_items > 0 && 16 * nc > (int64_t)qa_.n_items;
     // this lane's share: cells lane, lane + 64, ..., then large items alike
     auto each = [&](auto emit) {
+      if (all_items) {
+        for (int i0 = 0; i0 < qa_.n_items; i0 += 256) {
+          ItemRec r[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int it = i0 + 64 * u + lane;
+            r[u] = items[it < qa_.n_items ? it : 0];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int it = i0 + 64 * u + lane;
+            if (it < qa_.n_items && (r[u].tag >> 1) == qsc && pair_ok<KIND>(q, qa, qb, qdof, it, r[u]) &&
+                overlap(qlo, qhi, r[u]))
+              emit(it);
+          }
+        }
+        return;
+      }
       for (int64_t ci = lane; ci < nc; ci += 64) {
         const int x = c0[0] + (int)(ci % nx), y = c0[1] + (int)((ci / nx) % ny), z = c0[2] + (int)(ci / (nx * ny));
         const uint64_t key = cell_key(x, y, z, qsc);
@@ -1606,7 +1631,7 @@ eipc_status broad_phase(eipc_ctx *c, const eipc_scene *sc, int kind, const doubl
                                         c->status);
   EIPC_HIP(c, hipGetLastError());
   QueryArgs qa{b.g, bmask, b.bstart, b.ent, ent_cap, b.large, b.n_large, b.items, sc->W_rowptr, vsc, nullptr,
-               nullptr, nullptr, nullptr};
+               nullptr, nullptr, nullptr, ni};
   QueryArgs qdef = qa;  // per-query kernels hand queries of many cells to k_query_lq
   qdef.defer = b.qlarge;
   qdef.n_defer = b.n_qlarge;
