@@ -810,7 +810,9 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
                                               unsigned long long *total, uint32_t *status) {
   const GridDev g = *qa_.g;
   const ItemRec *items = qa_.items;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  // workgroups of consecutive queries in runs on one XCD (its L2 then holds
+  // their hash entries)
+  const int t = xcd_block(XCD_CHUNK) * blockDim.x + threadIdx.x;
   const int q = qa_.qlist ? (t < *qa_.n_qlist ? qa_.qlist[t] : -1) : t;
   const bool live = q >= 0 && q < nq;
   int qa = 0, qb = -1, qsc = 0;
