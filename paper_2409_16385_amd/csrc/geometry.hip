@@ -1338,9 +1338,11 @@ __device__ __forceinline__ uint32_t key_bucket(uint64_t key, uint32_t bmask) {
 }
 
 // lower-corner rule from the two offsets (cell minus lower cell, 6 bits per
-// axis): the smaller offset is zero on every axis
-__device__ __forceinline__ int zero_axes(int d) {
-  return (int)((d & 63) == 0) | ((int)((d & (63 << 6)) == 0) << 1) | ((int)((d & (63 << 12)) == 0) << 2);
+// axis): on every axis one of the two offsets is zero.  With the row's
+// nonzero fields as a mask (all ones in each such field) it is one AND per
+// partner: (partner offsets & mask) == 0
+__device__ __forceinline__ int nonzero_fields(int d) {
+  return ((d & 63) != 0 ? 63 : 0) | ((d & (63 << 6)) != 0 ? 63 << 6 : 0) | ((d & (63 << 12)) != 0 ? 63 << 12 : 0);
 }
 
 // adjacency, DoF rule and exact box overlap of a (query, item) pair, with
@@ -1418,7 +1420,7 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
   }
   // window of item entries for the whole tile: first row's bucket start to
   // last row's bucket end (rows are in bucket order)
-  const int rz = zero_axes(re.dlo);
+  const int rmask = nonzero_fields(re.dlo);
   if (threadIdx.x == 0) s_win[0] = bs;
   if (i == r1 - 1) s_win[1] = be;
   __syncthreads();
@@ -1448,8 +1450,11 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
     const int64_t cend = c0 + nw;
     const int64_t a0 = pa0 > c0 ? pa0 : c0, a1 = pa1 < cend ? pa1 : cend;
     const int64_t b0 = pb0 > c0 ? pb0 : c0, b1 = pb1 < cend ? pb1 : cend;
-    const int64_t na = a1 > a0 ? a1 - a0 : 0, ntot = na + (b1 > b0 ? b1 - b0 : 0);
-    int64_t t = 0;
+    // chunk-relative: the list's entry tu is ra + tu below na, else rb + tu
+    const int na = a1 > a0 ? (int)(a1 - a0) : 0;
+    const int ntot = na + (b1 > b0 ? (int)(b1 - b0) : 0);
+    const int ra = (int)(a0 - c0), rb = (int)(b0 - c0) - na;
+    int t = 0;
     while (__any(t < ntot)) {
       // four partners per lane: their entries and records read from LDS
       // without conditions (a conditional read kept the previous records
@@ -1460,8 +1465,8 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
       int idx[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t tu = t + u;
-        idx[u] = tu < ntot ? (int)((tu < na ? a0 + tu : b0 + (tu - na)) - c0) : 0;
+        const int tu = t + u;
+        idx[u] = tu < ntot ? (tu < na ? ra : rb) + tu : 0;
         pe[u] = s_ent[idx[u]];
       }
       ItemRec r[4];
@@ -1469,7 +1474,7 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
       for (int u = 0; u < 4; ++u) r[u] = s_rec[idx[u]];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        pass[u] = (t + u < ntot) & (pe[u].cell == re.cell) & ((rz | zero_axes(pe[u].dlo)) == 7);
+        pass[u] = (t + u < ntot) & (pe[u].cell == re.cell) & ((pe[u].dlo & rmask) == 0);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const bool ok = pass[u] && join_test<KIND>(r[u], qa, qb, qdof, qlo, qhi);
