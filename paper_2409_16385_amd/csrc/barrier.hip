@@ -336,31 +336,63 @@ __device__ __forceinline__ void local_init(const LocalAcc &L) {
 // All threads of the workgroup call (between barriers).
 __device__ __forceinline__ void local_flush(const LocalAcc &L, const HessOut &h, int n_node, double *grad,
                                             uint32_t *status) {
-  for (int idx = threadIdx.x; idx < LNB; idx += blockDim.x) {
-    if (!L.touched[idx]) continue;
-    // row a of the packed triangle: start(a) = a (2 LN - a + 1) / 2 <= idx
-    int a = (int)((2.0 * LN + 1.0 - sqrt((2.0 * LN + 1.0) * (2.0 * LN + 1.0) - 8.0 * idx)) * 0.5);
-    if (a < 0) a = 0;
-    while (a + 1 < LN && ltri(a + 1, a + 1) <= idx) ++a;
-    while (a > 0 && ltri(a, a) > idx) --a;
-    const int b = a + (idx - ltri(a, a));
-    const int na = L.nkey[a], nb = L.nkey[b];
-    double M[9];
+  // per thread up to FU blocks at a time: first their global slots (table
+  // reads), then their adds.  A table read issued after adds would wait
+  // for all of them: vector memory operations retire in order.
+  constexpr int FU = 4;
+  for (int base = 0; base < LNB; base += FU * (int)blockDim.x) {
+    int64_t dst[FU];  // kind 2: table slot; kind 1: I * n_node + J; -1: none
+    bool tr[FU];
 #pragma unroll
-    for (int u = 0; u < 9; ++u) {
-      M[u] = L.bval[9 * idx + u];
-      L.bval[9 * idx + u] = 0.0;
+    for (int u = 0; u < FU; ++u) {
+      const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+      dst[u] = -1;
+      tr[u] = false;
+      if (idx < LNB && L.touched[idx]) {
+        // row a of the packed triangle: start(a) = a (2 LN - a + 1) / 2 <= idx
+        int a = (int)((2.0 * LN + 1.0 - sqrt((2.0 * LN + 1.0) * (2.0 * LN + 1.0) - 8.0 * idx)) * 0.5);
+        if (a < 0) a = 0;
+        while (a + 1 < LN && ltri(a + 1, a + 1) <= idx) ++a;
+        while (a > 0 && ltri(a, a) > idx) --a;
+        const int b = a + (idx - ltri(a, a));
+        const int na = L.nkey[a], nb = L.nkey[b];
+        tr[u] = na > nb;
+        const int64_t I = tr[u] ? nb : na, J = tr[u] ? na : nb;
+        if (h.kind == 1) {
+          dst[u] = I * n_node + J;
+        } else if (h.kind == 2) {
+          dst[u] = table_slot64((long long *)h.hkey, h.hmask, (long long)(I * n_node + J), GLOBAL_PROBE);
+          if (dst[u] < 0) atomicOr(status, ST_HASH_OVERFLOW);
+        }
+        if (dst[u] < 0) {
+#pragma unroll
+          for (int t = 0; t < 9; ++t) L.bval[9 * idx + t] = 0.0;
+          L.touched[idx] = 0;
+        }
+      }
     }
-    L.touched[idx] = 0;
-    if (na <= nb) {
-      global_block_add(h, n_node, na, nb, M, status);
-    } else {
-      double Mt[9];
+#pragma unroll
+    for (int u = 0; u < FU; ++u) {
+      const int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+      if (dst[u] < 0) continue;
+      double B[9];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Mt[3 * r + c] = M[3 * c + r];
-      global_block_add(h, n_node, nb, na, Mt, status);
+        for (int c = 0; c < 3; ++c) B[3 * r + c] = tr[u] ? L.bval[9 * idx + 3 * c + r] : L.bval[9 * idx + 3 * r + c];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) L.bval[9 * idx + t] = 0.0;
+      L.touched[idx] = 0;
+      if (h.kind == 1) {
+        const int64_t n3 = 3 * (int64_t)n_node, I = dst[u] / n_node, J = dst[u] % n_node;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) atomicAdd(&h.dense[(3 * I + i) * n3 + 3 * J + j], B[3 * i + j]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) atomicAdd(&h.hval[9 * dst[u] + t], B[t]);
+      }
     }
   }
   __syncthreads();  // nkey is read above and reset below

@@ -810,6 +810,7 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
                                               unsigned long long *total, uint32_t *status) {
   const GridDev g = *qa_.g;
   const ItemRec *items = qa_.items;
+  const int nl = (int)*qa_.n_large;  // read before any store: a later load would wait for the stores
   // workgroups of consecutive queries in runs on one XCD (its L2 then holds
   // their hash entries)
   const int t = xcd_block(XCD_CHUNK) * blockDim.x + threadIdx.x;
@@ -846,7 +847,6 @@ __global__ __launch_bounds__(QT) void k_query(int nq, const double *__restrict__
                           });
       }
   if (live) {
-    const int nl = (int)*qa_.n_large;
     for (int j = 0; j < nl; ++j) {
       const int it = qa_.large[j];
       const ItemRec r = items[it];
@@ -1095,6 +1095,7 @@ __global__ __launch_bounds__(QT) void k_query_ent(const int64_t *__restrict__ n_
   int2 *buf = s_buf + threadIdx.x * APPEND_BUF;
   int nbuf = 0;
   const ItemRec *items = qa_.items;
+  const int nl = (int)*qa_.n_large;  // read before any store: a later load would wait for the stores
   const int64_t n = *n_qent < qent_cap ? *n_qent : qent_cap;
   for (int64_t base = (int64_t)blockIdx.x * QT; base < n; base += (int64_t)gridDim.x * QT) {
     const int64_t t = base + threadIdx.x;
@@ -1113,7 +1114,6 @@ __global__ __launch_bounds__(QT) void k_query_ent(const int64_t *__restrict__ n_
                         [&](int it) { stage_pair(buf, nbuf, q, it, total, out, cap); });
       if (qe.dlo == 0) {
         // the query's lower cell also runs the items too large to hash
-        const int nl = (int)*qa_.n_large;
         for (int j = 0; j < nl; ++j) {
           const int it = qa_.large[j];
           const ItemRec r = items[it];
@@ -1145,6 +1145,7 @@ __global__ __launch_bounds__(QT) void k_query_wave(const int64_t *__restrict__ n
   int nbuf = 0;
   const ItemRec *items = qa_.items;
   const int lane = threadIdx.x & 63;
+  const int nl = (int)*qa_.n_large;  // read before any store: a later load would wait for the stores
   const int64_t n = *n_qent < qent_cap ? *n_qent : qent_cap;
   const int64_t wave = ((int64_t)blockIdx.x * QT + threadIdx.x) >> 6;
   const int64_t n_waves = ((int64_t)gridDim.x * QT) >> 6;
@@ -1177,7 +1178,6 @@ __global__ __launch_bounds__(QT) void k_query_wave(const int64_t *__restrict__ n
     }
     if (qe.dlo == 0) {
       // the query's lower cell also runs the items too large to hash
-      const int nl = (int)*qa_.n_large;
       for (int jb = 0; jb < nl; jb += 64) {
         const int j = jb + lane;
         if (j < nl) {
@@ -1371,6 +1371,9 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
   int2 *wout = s_out[threadIdx.x >> 6];
   int wcnt = 0;
   const int64_t nr0 = *ja.n_rows;
+  // read here, not after the scan: a late load of it waited for all of the
+  // wavefront's stores, which kept finished wavefronts resident
+  const int nl = (int)*ja.n_large;
   const int64_t n_rows = nr0 < ja.row_cap ? nr0 : ja.row_cap;
   const int64_t r0 = (int64_t)blockIdx.x * JT;
   if (r0 >= n_rows) return;  // uniform over the workgroup
@@ -1487,7 +1490,6 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
     }
   }
   // the query's lower-cell row also runs the items too large to hash
-  const int nl = (int)*ja.n_large;
   if (nl > 0) {
     const bool lower = live && re.dlo == 0;
     const int q = re.item;
