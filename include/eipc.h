@@ -335,7 +335,7 @@ eipc_status eipc_step_pairs(eipc_ctx *ctx, int32_t which, int32_t *out, int64_t 
  * mode 0 = one thread per query, 1 = one thread per (query, cell of its
  * box), 2 = one wavefront per (query, cell), 3 = bucket join (the queries
  * hashed like the items, each bucket's pairs tested from LDS) (-1 keeps
- * the current choice; default 1, i.e. PT mode 1 and EE mode 0).  Used by the batch autotuner;
+ * the current choice; default 15, the bucket join for both).  Used by the batch autotuner;
  * results do not depend on them except for the order of unsorted
  * candidate lists and the rounding order of sums.  A plan must be made
  * again after changing them. */

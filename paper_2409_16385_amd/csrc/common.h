@@ -124,7 +124,8 @@ struct eipc_ctx {
   int ccd_method = 0;                // 0: additive CCD, 1: advancement along the closest direction
   // append-mode broad phase work split [PT, EE]: 0 thread per query,
   // 1 thread per (query, cell), 2 wavefront per (query, cell), 3 bucket join
-  int query_mode[2] = {1, 0};
+  // (the default: the fastest on every workload measured, small to batch)
+  int query_mode[2] = {3, 3};
   eipc::BPPlan last_plan[4] = {};   // sizes seen by the last unplanned broad phases
   bool prof = false;                        // record per-kernel events
   bool prof_serial = false;                 // planned step: both chains on the caller's stream

@@ -192,7 +192,7 @@ def test_autotune_keeps_results(ctx, scenes, seq):
     b.step()
     assert b.status() == E.binding.OK
     _check_against_sequential(b, seq, scenes)
-    E.set_tuning(ctx, 2.0, [8, 2, 4, 4], 1)
+    E.set_tuning(ctx, 2.0, [1, 2, 4, 4], 15)  # the context's defaults
 
 
 def test_autotune_tie_break_by_device_time(ctx, scenes, seq):

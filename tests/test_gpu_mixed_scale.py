@@ -67,7 +67,7 @@ def test_step_bound_every_split(ctx, sc, ref, mode, cs):
     E.set_tuning(ctx, cs, (0, 0, 0, 0), mode)
     dsc = E.Scene.from_host(ctx, sc)
     a, n, _ = E.ccd_max_step(ctx, dsc, _dev(sc.q), _dev(sc.dq), sc.dhat)
-    E.set_tuning(ctx, 2.0, (0, 0, 0, 0), 1)
+    E.set_tuning(ctx, 2.0, (0, 0, 0, 0), 15)
     assert n == ref["n_swept"]
     assert a == ref["alpha"]
 
@@ -97,5 +97,5 @@ def test_swept_candidates_sorted_every_split(ctx, sc, ref, mode):
     E.set_tuning(ctx, 2.0, (0, 0, 0, 0), mode)
     dsc = E.Scene.from_host(ctx, sc)
     spt, see = E.ccd_candidates(ctx, dsc, _dev(sc.q), _dev(sc.dq), sc.dhat)
-    E.set_tuning(ctx, 2.0, (0, 0, 0, 0), 1)
+    E.set_tuning(ctx, 2.0, (0, 0, 0, 0), 15)
     assert np.array_equal(spt.cpu().numpy(), ref["spt"]) and np.array_equal(see.cpu().numpy(), ref["see"])
