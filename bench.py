@@ -324,7 +324,7 @@ def extra_single(sc, log, flags_extra=0, steps=20):
     ctx = E.Context(0)
     flags = E.ENERGY | E.GRAD | E.HESS | E.PROJECT | flags_extra
     bt = BT.Batch(ctx, BT.concat([sc]), flags=flags)
-    tuning = bt.autotune(reps=2)
+    tuning = bt.autotune(reps=3)
     ms = _replay_ms(bt, steps, 3, sync)
     st = bt.status()
     if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):
@@ -440,7 +440,7 @@ def extra_batch(scenes_list, log, steps=10):
     ctx = E.Context(0)
     hb = BT.concat(scenes_list)
     bt = BT.Batch(ctx, hb)
-    tuning = bt.autotune(reps=1)
+    tuning = bt.autotune(reps=2)
     ms = _replay_ms(bt, steps, 2, sync)
     st = bt.status()
     if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):
@@ -579,7 +579,7 @@ def main():
         bt.make_plan(1.5)
     elif not a.no_autotune:
         t1 = time.perf_counter()
-        tuning = bt.autotune(reps=2)
+        tuning = bt.autotune(reps=5)  # timed over eager steps: with fewer, timing noise decides the pick
         log(f"autotune: cell_scale={tuning['cell_scale']} wg_per_cu={tuning['wg_per_cu']} "
             f"({time.perf_counter() - t1:.1f} s)")
         log("autotune trace (what, value, ms): " + " ".join(f"{w}={v}:{t:.3f}" for w, v, t in tuning["trace"]))
