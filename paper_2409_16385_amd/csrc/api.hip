@@ -432,8 +432,27 @@ eipc_status eipc_barrier_reduce(eipc_ctx *c, const eipc_scene *sc, const double 
     }
     const uint32_t f = flags & (want_h ? ~0u : ~(uint32_t)EIPC_HESS);
     double *g = (flags & EIPC_GRAD) ? grad_q : nullptr;
-    EIPC_TRY(launch_barrier(c, sc, 0, xs, pt, act_pt, typ_pt, c->counters + 2, n_pt, dhat, kappa, f, energy, g, h, s));
-    EIPC_TRY(launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, c->counters + 3, n_ee, dhat, kappa, f, energy, g, h, s));
+    // with enough pairs of both kinds, the PT chain runs on the side stream
+    // beside the EE chain, as in the planned step (their outputs meet in
+    // atomics; their scratch is per kind); small calls stay on one stream,
+    // where the fork and join would cost more than the overlap gains
+    const bool fork = !c->prof_serial && n_pt > 0 && n_ee > 0 && n_pt + n_ee >= (int64_t)1 << 16;
+    if (fork) {
+      EIPC_HIP(c, hipEventRecord(c->fork_ev, s));
+      EIPC_HIP(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
+    }
+    const eipc_status b0 = launch_barrier(c, sc, 0, xs, pt, act_pt, typ_pt, c->counters + 2, n_pt, dhat, kappa, f,
+                                          energy, g, h, fork ? c->side : s);
+    const eipc_status b1 = b0 != EIPC_OK ? b0
+                                         : launch_barrier(c, sc, 1, xs, ee, act_ee, typ_ee, c->counters + 3, n_ee,
+                                                          dhat, kappa, f, energy, g, h, s);
+    if (fork) {
+      // joined also after a failure, so that nothing enqueued on the side
+      // stream can overlap the caller's next use of the scratch
+      EIPC_HIP(c, hipEventRecord(c->join_ev, c->side));
+      EIPC_HIP(c, hipStreamWaitEvent(s, c->join_ev, 0));
+    }
+    EIPC_TRY(b1);
     if (h.kind == 1) EIPC_TRY(launch_dense_mirror(c, sc->n_node, hess_dense, s));
     if (h.kind == 2) {
       uint32_t st = 0;
