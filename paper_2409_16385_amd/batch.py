@@ -93,6 +93,9 @@ def concat(scenes) -> HostBatch:
 
 
 DEFAULT_FLAGS = B.ENERGY | B.GRAD | B.HESS | B.PROJECT
+# workgroups per CU of the pair-terms, expansion, narrow and CCD kernels: the
+# library context's defaults
+DEFAULT_WG_PER_CU = (1, 2, 4, 4)
 
 
 class Batch:
@@ -218,9 +221,12 @@ class Batch:
         within 1% of the fastest, the one with the least device time summed
         over the step's kernels, each timed alone), then for each
         grid-stride kernel family in turn the workgroups per CU (values
-        from wg_values, whole-step time; a change is kept when it saves
-        more than 2%)."""
-        wg = [wg_values[len(wg_values) // 2]] * 4
+        from wg_values, starting from the library's defaults; whole-step
+        time; a change is kept when it saves more than 2%)."""
+        # start from the library's defaults (where offered): a family keeps
+        # its start unless a value beats it by the noise margin below, and
+        # the expansion (one workgroup per CU by its LDS) is slow at 4
+        wg = [v if v in wg_values else wg_values[len(wg_values) // 2] for v in DEFAULT_WG_PER_CU]
         trace, timed = [], []
         for cs in cell_scales:
             for qm in query_modes:

@@ -1480,7 +1480,8 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
         pass[u] = (t + u < ntot) & (pe[u].cell == re.cell) & ((pe[u].dlo & rmask) == 0);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const bool ok = pass[u] && join_test<KIND>(r[u], qa, qb, qdof, qlo, qhi);
+        // & rather than &&: the test is branch-free, a short circuit would branch
+        const bool ok = pass[u] & join_test<KIND>(r[u], qa, qb, qdof, qlo, qhi);
         const int it = pe[u].item;
         const int2 pr = (KIND == 0 || re.item < it) ? make_int2(re.item, it) : make_int2(it, re.item);
         wave_push(ok, pr, wout, wcnt);
