@@ -692,8 +692,9 @@ __device__ __forceinline__ void scan_bucket(const Entry *__restrict__ ent, const
     for (int u = 0; u < 4; ++u) {
       const int it = en[u].item;
       const int ix = x - (en[u].dlo & 63), iy = y - ((en[u].dlo >> 6) & 63), iz = z - ((en[u].dlo >> 12) & 63);
-      pass[u] = en[u].cell == key && (KIND == 0 || it > q) && (ix > qx ? ix : qx) == x &&
-                (iy > qy ? iy : qy) == y && (iz > qz ? iz : qz) == z;
+      // & rather than &&: no branches between the fields' tests
+      pass[u] = (en[u].cell == key) & (KIND == 0 || it > q) & ((ix > qx ? ix : qx) == x) &
+                ((iy > qy ? iy : qy) == y) & ((iz > qz ? iz : qz) == z);
     }
     ItemRec r[4];
 #pragma unroll
@@ -701,7 +702,7 @@ __device__ __forceinline__ void scan_bucket(const Entry *__restrict__ ent, const
       if (pass[u]) r[u] = items[en[u].item];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (pass[u] && pair_ok<KIND>(q, qa, qb, qdof, en[u].item, r[u]) && overlap(qlo, qhi, r[u])) emit(en[u].item);
+      if (pass[u] && (pair_ok<KIND>(q, qa, qb, qdof, en[u].item, r[u]) & overlap(qlo, qhi, r[u]))) emit(en[u].item);
   }
 }
 
