@@ -440,7 +440,7 @@ def extra_batch(scenes_list, log, steps=10):
     ctx = E.Context(0)
     hb = BT.concat(scenes_list)
     bt = BT.Batch(ctx, hb)
-    tuning = bt.autotune(reps=2)
+    tuning = bt.autotune(reps=4)
     ms = _replay_ms(bt, steps, 2, sync)
     st = bt.status()
     if st not in (E.binding.OK, E.binding.WARN_CCD_CAPPED):

@@ -933,7 +933,8 @@ __global__ __launch_bounds__(QT) void k_query_lq(const int32_t *__restrict__ qli
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int it = i0 + 64 * u + lane;
-            if (it < qa_.n_items && (r[u].tag >> 1) == qsc && pair_ok<KIND>(q, qa, qb, qdof, it, r[u]) &&
+            // & rather than &&: every record was read, so nothing needs a branch
+            if ((it < qa_.n_items) & ((r[u].tag >> 1) == qsc) & pair_ok<KIND>(q, qa, qb, qdof, it, r[u]) &
                 overlap(qlo, qhi, r[u]))
               emit(it);
           }
@@ -1504,7 +1505,7 @@ __global__ __launch_bounds__(JT) void k_join(JoinArgs ja, int32_t *__restrict__ 
         if (lower && jj < nl) {
           it = ja.large[jj];
           const ItemRec r = ja.items[it];
-          ok = (r.tag >> 1) == qsc && pair_ok<KIND>(q, qa, qb, qdof, it, r) && overlap(qlo, qhi, r);
+          ok = ((r.tag >> 1) == qsc) & pair_ok<KIND>(q, qa, qb, qdof, it, r) & overlap(qlo, qhi, r);
         }
         wave_push(ok, make_int2(q, it), wout, wcnt);
       }
