@@ -1103,7 +1103,7 @@ __device__ __forceinline__ bool static_boxes_overlap(const V3 *x, double h) {
         imx = fmax(imx, v);
       }
     }
-    ok = ok && (qmn - h <= imx + h) && (imn - h <= qmx + h);
+    ok = ok & (qmn - h <= imx + h) & (imn - h <= qmx + h);  // & rather than &&: no branch
   }
   return ok;
 }
